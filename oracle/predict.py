@@ -1,0 +1,49 @@
+"""Oracle: posterior (kriging) mean at test points (float64).
+
+Test infrastructure only.
+
+Sec. 3.2 gives m_{y|z} = W_P beta + C_{y,z} C_z^{-1} (z - W beta).  With the
+residual y = z - W beta passed in and a zero prior mean at the test points
+(the mean term is the caller's), this is
+
+    m(x*) = sum_q C_y(x*, x_q) alpha_q,   alpha = C_z^{-1} y,
+
+where C_y is C_sparse with a unit core kernel and carries no nugget (the
+nugget belongs to the observations z, Eq. Zcov).  At the training inputs
+m(X) = (C_z - sigma^2 I) alpha = y - sigma^2 alpha.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import kernel
+
+
+def mean(xs, x, th, alpha, block: int = 256):
+    """m(x*) for every row of xs, by brute force over all training points."""
+    xs = np.asarray(xs, np.float64)
+    x = np.asarray(x, np.float64)
+    alpha = np.asarray(alpha, np.float64)
+    M, F = kernel.features(x, th)
+    Ms, Fs = kernel.features(xs, th)
+    out = np.empty(xs.shape[0])
+    for s in range(0, xs.shape[0], block):
+        e = min(xs.shape[0], s + block)
+        xp = xs[s:e, None, :]
+        xq = x[None, :, :]
+        same = np.zeros((e - s, x.shape[0]), bool)
+        P = kernel.pattern_pred(xp, xq, Ms[s:e, None, :], M[None, :, :], same, th)
+        v = kernel.entries(xp, xq, Ms[s:e, None, :], M[None, :, :], Fs[s:e, None, :], F[None, :, :],
+                           same, th)
+        out[s:e] = np.where(P, v, 0.0) @ alpha
+    return out
+
+
+def mean_rows(xs, x, th, alpha):
+    """Same as ``mean`` but through the sparse cross-covariance rows."""
+    rp, cols, vals = kernel.cross_entries(xs, x, th)
+    alpha = np.asarray(alpha, np.float64)
+    out = np.empty(xs.shape[0])
+    for s in range(xs.shape[0]):
+        out[s] = vals[rp[s]:rp[s + 1]] @ alpha[cols[rp[s]:rp[s + 1]]]
+    return out

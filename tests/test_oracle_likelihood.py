@@ -1,0 +1,143 @@
+"""Pins of the oracle's log-likelihood, SLQ log-det and kriging mean:
+independent algorithms, closed forms on diagonal matrices, a library
+density routine, the SplitMix64 published sequence, and the predictor's
+identity at the training inputs (Sec. 3.1 Eq. Zmarg, Sec. 3.2, Sec. 3.3)."""
+import math
+import os
+
+import numpy as np
+import scipy.stats
+
+from oracle import kernel, likelihood, predict, slq
+from workloads import Theta, uniform_problem, config1
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _y_from_z(K, z):
+    return np.linalg.cholesky(K) @ z
+
+
+def test_three_routes_agree_config1():
+    p = config1()
+    K, _ = kernel.dense(p.x, p.theta)
+    y = _y_from_z(K, p.z_std)
+    d = likelihood.dense_cholesky(K, y)
+    ip, ci, vals, (M, F) = kernel.sparse(p.x, p.theta, return_features=True)
+    A = kernel.to_scipy(ip, ci, vals, p.n)
+    s = likelihood.sparse_lu(A, y)
+    th0 = p.theta.copy()
+    th0.a[:] = 0.0
+    ipl, cil, vl = kernel.sparse(p.x, th0)
+    Al = kernel.to_scipy(ipl, cil, vl, p.n)
+    w = likelihood.split_woodbury(Al, F, y)
+    for r in (s, w):
+        assert abs(r["logdet"] - d["logdet"]) <= 1e-10 * abs(d["logdet"])
+        assert abs(r["quad"] - d["quad"]) <= 1e-10 * abs(d["quad"])
+        assert np.allclose(r["alpha"], d["alpha"], rtol=1e-8, atol=1e-10 * np.abs(d["alpha"]).max())
+    # library density (scipy's multivariate normal, eigen-decomposition route)
+    ref = scipy.stats.multivariate_normal(mean=np.zeros(p.n), cov=K).logpdf(y)
+    assert abs(d["loglik"] - ref) <= 1e-9 * abs(ref)
+
+
+def test_diagonal_closed_form_no_bumps():
+    # r0 below the minimum pair distance and all a = 0: K = (s0 + sigma^2) I.
+    p = uniform_problem(500, 2, 3, r0=1e-6, n1=2, n2=2)
+    p.theta.a[:] = 0.0
+    p.theta.s0 = 1.7
+    K, P = kernel.dense(p.x, p.theta)
+    assert P.sum() == p.n
+    y = p.z_std
+    c = p.theta.s0 + p.theta.nugget
+    expect = -0.5 * p.n * math.log(c) - 0.5 * float(y @ y) / c - 0.5 * p.n * math.log(2 * math.pi)
+    assert abs(likelihood.dense_cholesky(K, y)["loglik"] - expect) <= 1e-12 * abs(expect)
+
+
+def test_diagonal_closed_form_isolated_bumps():
+    # n2 = 1 and each bump holds exactly one point: K diagonal with
+    # k_p = s0 + sum_i f_i(p)^2 + sigma^2.
+    x = np.array([[0.1, 0.1], [0.5, 0.5], [0.9, 0.2], [0.3, 0.8]])
+    h = x[:3, None, :].copy()
+    r = np.full((3, 1, 2), 0.05)
+    a = np.array([[0.9], [0.6], [0.75]])
+    th = Theta(1.0, np.array([1e-3, 1e-3]), h, r, a, np.ones((3, 1)), 0.01, 0)
+    K, P = kernel.dense(x, th)
+    assert np.count_nonzero(K - np.diag(np.diag(K))) == 0
+    kp = np.array([1.0 + 0.81 + 0.01, 1.0 + 0.36 + 0.01, 1.0 + 0.5625 + 0.01, 1.01])
+    assert np.allclose(np.diag(K), kp, rtol=1e-15)
+    y = np.array([0.3, -1.2, 0.7, 2.0])
+    expect = -0.5 * np.log(kp).sum() - 0.5 * (y * y / kp).sum() - 2 * math.log(2 * math.pi)
+    assert abs(likelihood.dense_cholesky(K, y)["loglik"] - expect) < 1e-13
+
+
+def test_splitmix64_published_sequence():
+    with open(os.path.join(GOLD, "splitmix64_seed1234567.txt")) as f:
+        ref = [int(l) for l in f if l.strip() and not l.startswith("#")]
+    out = slq.splitmix64_sequence(1234567, 5)
+    assert [int(v) for v in out] == ref
+
+
+def test_rademacher_probe_is_counter_indexed_splitmix():
+    # probe entry == sign of the SplitMix64 output at counter (l << 40 | i) + 1
+    seq = slq.splitmix64_sequence(99, 64)
+    z = slq.rademacher(99, 0, np.arange(64))
+    assert np.array_equal(z, np.where((seq >> np.uint64(63)) != 0, -1.0, 1.0))
+    big = slq.rademacher(7, 3, np.arange(200_000))
+    assert abs(big.mean()) < 5 / math.sqrt(big.size)
+
+
+def test_slq_exact_on_diagonal():
+    # Hutchinson with Rademacher probes is exact on diagonal matrices and the
+    # Jacobi-scaled matrix is I, so SLQ returns sum log d_p exactly.
+    d = np.random.default_rng(1).uniform(0.5, 3.0, 400)
+    r = slq.slq_logdet(np.diag(d), seed=5, n_probes=4, n_steps=10)
+    assert abs(r["logdet"] - np.log(d).sum()) <= 1e-12 * abs(np.log(d).sum())
+    assert np.all(r["steps"] == 1)
+
+
+def test_slq_quadrature_exact_with_few_distinct_eigenvalues():
+    # With at most k distinct eigenvalues, k-step Lanczos Gauss quadrature equals
+    # z^T log(Ahat) z; compare per probe with a dense eigen-decomposition.
+    rng = np.random.default_rng(2)
+    n = 60
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    lam = np.repeat([0.5, 1.0, 2.0, 4.0, 8.0], n // 5)
+    A = (Q * lam) @ Q.T
+    A = 0.5 * (A + A.T)
+    r = slq.slq_logdet(A, seed=11, n_probes=6, n_steps=20)
+    s = 1.0 / np.sqrt(np.diag(A))
+    Ah = s[:, None] * A * s[None, :]
+    w, V = np.linalg.eigh(Ah)
+    logAh = (V * np.log(w)) @ V.T
+    for l in range(6):
+        z = slq.rademacher(11, l, np.arange(n))
+        assert abs(r["gammas"][l] - z @ logAh @ z) <= 1e-8 * abs(z @ logAh @ z) + 1e-9
+
+
+def test_slq_within_three_se_of_exact_config1():
+    p = config1()
+    K, _ = kernel.dense(p.x, p.theta)
+    exact = likelihood.dense_cholesky(K, p.z_std)["logdet"]
+    r = slq.slq_logdet(K, seed=2024, n_probes=30, n_steps=50)
+    assert abs(r["logdet"] - exact) <= 3 * r["se"]
+    assert abs(r["logdet"] - exact) <= 0.01 * abs(exact)
+
+
+def test_predict_identity_at_training_inputs():
+    p = uniform_problem(300, 2, 8, r0=0.12, n1=2, n2=2, bump_radius=0.25)
+    K, _ = kernel.dense(p.x, p.theta)
+    y = _y_from_z(K, p.z_std)
+    alpha = likelihood.dense_cholesky(K, y)["alpha"]
+    m = predict.mean(p.x, p.x, p.theta, alpha)
+    assert np.allclose(m, y - p.theta.nugget * alpha, rtol=0, atol=1e-10 * np.abs(y).max())
+    xs = np.random.default_rng(3).random((50, 2))
+    assert np.allclose(predict.mean(xs, p.x, p.theta, alpha), predict.mean_rows(xs, p.x, p.theta, alpha),
+                       rtol=1e-12, atol=1e-12)
+
+
+def test_predict_closed_form_single_point():
+    # one training point, no bumps, test point at u = 1/2: m = s0 f0(1/2) alpha
+    th = Theta(1.5, np.array([1.0]), np.zeros((1, 1, 1)), np.ones((1, 1, 1)), np.zeros((1, 1)),
+               np.ones((1, 1)), 0.2, 0)
+    m = predict.mean(np.array([[0.5], [2.0]]), np.array([[0.0]]), th, np.array([3.0]))
+    assert m[0] == 1.5 * 0.06103515625 * 3.0 and m[1] == 0.0

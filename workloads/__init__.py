@@ -1,0 +1,265 @@
+"""Seeded synthetic inputs for the sparse-covariance GP hot path.
+
+This module only draws random numbers and lays them out: points, kernel
+hyper-parameters, observations, request streams.  It holds none of the
+method's arithmetic (no kernel, predicate, solve or log-det), so both the
+HIP path and the CPU oracle may take their inputs from it.
+
+Every generator uses ``numpy.random.default_rng(seed)`` with a fixed draw
+order, so a (config, seed) pair always yields bitwise-identical arrays.
+
+Where a workload needs a quantity that only the method can produce (the
+Wendland radius of the 100k-point mixture, chosen so that rows hold about
+50 nonzeros), the value is read from ``calibration.json``, which the
+committed script ``workloads/calibrate.py`` writes by calling the oracle.
+
+The workloads stand in for the paper's data sets (Sec. 3.3 runtime study:
+N = 50k-200k scattered 2-D points; Sec. 5.2: about 1.04M daily space-time
+observations on a station grid, d = 3, with bump functions); the real
+station records are not used.
+"""
+from __future__ import annotations
+
+import dataclasses
+import json
+import math
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+@dataclasses.dataclass
+class Theta:
+    """Hyper-parameters of C_sparse plus the nugget (Sec. 2.1, Eq. C_sparse).
+
+    Shapes: r0 (d,), h (n1, n2, d), r (n1, n2, d), a (n1, n2), b (n1, n2).
+    ``r`` may hold +inf to make a bump ignore a coordinate.
+    ``wendland_variant`` 0 is the polynomial as printed (35 u^3), 1 is the
+    textbook Wendland phi_{3,3} (32 u^3).
+    """
+
+    s0: float
+    r0: np.ndarray
+    h: np.ndarray
+    r: np.ndarray
+    a: np.ndarray
+    b: np.ndarray
+    nugget: float
+    wendland_variant: int = 0
+
+    @property
+    def d(self) -> int:
+        return int(self.r0.shape[0])
+
+    @property
+    def n1(self) -> int:
+        return int(self.a.shape[0])
+
+    @property
+    def n2(self) -> int:
+        return int(self.a.shape[1])
+
+    def copy(self) -> "Theta":
+        return Theta(float(self.s0), self.r0.copy(), self.h.copy(), self.r.copy(),
+                     self.a.copy(), self.b.copy(), float(self.nugget),
+                     int(self.wendland_variant))
+
+
+@dataclasses.dataclass
+class Problem:
+    """One data set with its hyper-parameters and observations."""
+
+    name: str
+    x: np.ndarray                    # (n, d) float64, original order
+    theta: Theta
+    y: Optional[np.ndarray] = None   # (n,) residual z - W beta, or None
+    z_std: Optional[np.ndarray] = None  # (n,) N(0,1) draws to be coloured by a caller
+    cell: Optional[np.ndarray] = None   # suggested binning cell size per coordinate
+
+    @property
+    def n(self) -> int:
+        return int(self.x.shape[0])
+
+    @property
+    def d(self) -> int:
+        return int(self.x.shape[1])
+
+
+def _calibration() -> dict:
+    path = os.path.join(_HERE, "calibration.json")
+    with open(path) as f:
+        return json.load(f)
+
+
+def _bumps(rng, n1, n2, lo, hi, radius, amp_lo=0.5, amp_hi=1.0):
+    """Centres uniform on the box [lo, hi), radii fixed, amplitudes U[amp_lo, amp_hi], b = 1."""
+    lo = np.asarray(lo, np.float64)
+    hi = np.asarray(hi, np.float64)
+    d = lo.shape[0]
+    h = lo + (hi - lo) * rng.random((n1, n2, d))
+    r = np.broadcast_to(np.asarray(radius, np.float64), (n1, n2, d)).copy()
+    a = rng.uniform(amp_lo, amp_hi, (n1, n2))
+    b = np.ones((n1, n2))
+    return h, r, a, b
+
+
+def uniform_problem(n: int, d: int, seed: int, *, r0=0.05, n1=2, n2=2, bump_radius=0.2,
+                    s0=1.0, nugget=1e-2, amp=(0.5, 1.0), wendland_variant=0,
+                    name: str = "uniform") -> Problem:
+    """n points uniform on [0,1]^d with n1 x n2 bumps; y is left to the caller.
+
+    Draw order: points, bump centres, amplitudes, then n standard normals.
+    """
+    rng = np.random.default_rng(seed)
+    x = rng.random((n, d))
+    h, r, a, b = _bumps(rng, n1, n2, np.zeros(d), np.ones(d), bump_radius, *amp)
+    z = rng.standard_normal(n)
+    r0v = np.broadcast_to(np.asarray(r0, np.float64), (d,)).copy()
+    th = Theta(s0, r0v, h, r, a, b, nugget, wendland_variant)
+    return Problem(name, x, th, y=None, z_std=z, cell=r0v * 1.15)
+
+
+def config1() -> Problem:
+    """Plain method at n = 2000: uniform points on [0,1]^2, Wendland radius 0.05,
+    2 x 2 bumps (radius 0.2), nugget 1e-2.  y ~ N(0, K) is formed by the caller
+    from ``z_std`` (a Cholesky colouring needs the covariance itself)."""
+    p = uniform_problem(2000, 2, 1, r0=0.05, n1=2, n2=2, bump_radius=0.2, name="cfg1-n2000-2d")
+    return p
+
+
+def gmm_points(rng, n: int, n_comp: int = 20):
+    means = rng.random((n_comp, 2))
+    sds = rng.uniform(0.02, 0.1, n_comp)
+    comp = rng.integers(0, n_comp, n)
+    x = means[comp] + sds[comp, None] * rng.standard_normal((n, 2))
+    return x
+
+
+def smooth_field_2d(x):
+    return np.sin(2 * np.pi * x[:, 0]) * np.cos(2 * np.pi * x[:, 1])
+
+
+def gmm_problem(n: int, seed: int, r0: float, bump_radius: float, *, n1=4, n2=4,
+                nugget=1e-2, name="gmm") -> Problem:
+    """n points from a 20-component isotropic Gaussian mixture (means U[0,1]^2,
+    sd U[0.02, 0.1], equal weights, no clipping); 4 x 4 bumps with centres on
+    the unit square; y = sin(2 pi x1) cos(2 pi x2) + N(0, 0.1^2).
+
+    Draw order: mixture, bumps, noise."""
+    rng = np.random.default_rng(seed)
+    x = gmm_points(rng, n)
+    h, r, a, b = _bumps(rng, n1, n2, np.zeros(2), np.ones(2), bump_radius)
+    y = smooth_field_2d(x) + 0.1 * rng.standard_normal(n)
+    r0v = np.array([r0, r0])
+    th = Theta(1.0, r0v, h, r, a, b, nugget, 0)
+    return Problem(name, x, th, y=y, cell=r0v * 1.15)
+
+
+def config2() -> Problem:
+    """n = 100,000 points from the mixture, 16 bumps (4 x 4, radius 0.02); the
+    Wendland radius comes from the calibration file (mean row length ~50)."""
+    cal = _calibration()
+    return gmm_problem(100_000, 2, cal["cfg2_r0"], 0.02, name="cfg2-n100k-gmm")
+
+
+def spacetime_points(rng, n_stations: int, n_days: int):
+    st = rng.random((n_stations, 2))
+    days = np.arange(n_days, dtype=np.float64)
+    x = np.empty((n_stations * n_days, 3))
+    x[:, 0] = np.repeat(st[:, 0], n_days)   # station-major order
+    x[:, 1] = np.repeat(st[:, 1], n_days)
+    x[:, 2] = np.tile(days, n_stations)
+    return x
+
+
+def config3(n_stations: int = 3000, n_days: int = 365, seed: int = 3) -> Problem:
+    """Space-time: stations uniform on [0,1]^2 times integer days 0..364 in
+    station-major order (n = 1,095,000, d = 3).  Anisotropic Wendland radii
+    (0.03, 0.03, 3 days); 16 x 4 space-time bumps with radii (0.05, 0.05, 14
+    days); y = sin(2 pi s1) cos(2 pi s2) + 0.5 sin(2 pi t / 365) + N(0, 0.1^2).
+
+    Draw order: stations, bumps, noise."""
+    rng = np.random.default_rng(seed)
+    x = spacetime_points(rng, n_stations, n_days)
+    h, r, a, b = _bumps(rng, 16, 4, np.zeros(3), np.array([1.0, 1.0, 365.0]),
+                        np.array([0.05, 0.05, 14.0]))
+    y = (np.sin(2 * np.pi * x[:, 0]) * np.cos(2 * np.pi * x[:, 1])
+         + 0.5 * np.sin(2 * np.pi * x[:, 2] / 365.0)
+         + 0.1 * rng.standard_normal(x.shape[0]))
+    r0v = np.array([0.03, 0.03, 3.0])
+    th = Theta(1.0, r0v, h, r, a, b, 1e-2, 0)
+    # cell: radius in space; one day in time (integer days, three rings reach |dt| <= 2)
+    cell = np.array([0.03 * 1.0001, 0.03 * 1.0001, 1.0001])
+    return Problem(f"cfg3-spacetime-{n_stations}x{n_days}", x, th, y=y, cell=cell)
+
+
+# ---------------------------------------------------------------- serving ---
+
+def config4_pool(n_datasets: int = 16, base_seed: int = 4000):
+    """Pool of mixture data sets with n log-uniform in [5k, 300k]; every radius
+    is scaled by sqrt(1e5 / n) so rows keep about 50 nonzeros."""
+    cal = _calibration()
+    pool = []
+    for k in range(n_datasets):
+        rng = np.random.default_rng(base_seed + k)
+        n = int(round(math.exp(rng.uniform(math.log(5e3), math.log(3e5)))))
+        scale = math.sqrt(1e5 / n)
+        p = gmm_problem(n, base_seed + k, cal["cfg2_r0"] * scale, 0.02 * scale,
+                        name=f"cfg4-pool{k}-n{n}")
+        pool.append(p)
+    return pool
+
+
+def perturb_theta(rng, th: Theta, sd: float = 0.05) -> Theta:
+    """MCMC-style proposal: independent log-normal multipliers exp(N(0, sd^2))
+    on r0 (one per coordinate), every bump radius, every amplitude and the
+    nugget."""
+    t = th.copy()
+    t.r0 = t.r0 * np.exp(sd * rng.standard_normal(t.r0.shape))
+    t.r = t.r * np.exp(sd * rng.standard_normal(t.r.shape))
+    t.a = t.a * np.exp(sd * rng.standard_normal(t.a.shape))
+    t.nugget = float(t.nugget * math.exp(sd * rng.standard_normal()))
+    return t
+
+
+def config4_requests(n_requests: int = 512, rate: float = 50.0, seed: int = 4,
+                     n_datasets: int = 16):
+    """Poisson stream of log-likelihood requests: (arrival_s, dataset_index, theta)."""
+    rng = np.random.default_rng(seed)
+    pool_meta = config4_pool(n_datasets)
+    t = 0.0
+    reqs = []
+    for _ in range(n_requests):
+        t += rng.exponential(1.0 / rate)
+        k = int(rng.integers(0, n_datasets))
+        reqs.append((t, k, perturb_theta(rng, pool_meta[k].theta)))
+    return pool_meta, reqs
+
+
+def config5_requests(n_requests: int = 1000, seed: int = 5, m_lo: int = 1000,
+                     m_hi: int = 50000, n_days: int = 365):
+    """Prediction requests on the space-time training set: m ~ U{m_lo..m_hi}
+    test points, uniform on the unit square times a uniform integer day."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n_requests):
+        m = int(rng.integers(m_lo, m_hi + 1))
+        xs = np.empty((m, 3))
+        xs[:, :2] = rng.random((m, 2))
+        xs[:, 2] = rng.integers(0, n_days, m).astype(np.float64)
+        out.append(xs)
+    return out
+
+
+def rademacher_counter_doc() -> str:
+    """The probe generator shared in definition (not in code) by both sides.
+
+    Probe l, original point index i, seed s: the counter k = (l << 40 | i) + 1
+    indexes the SplitMix64 sequence started at state s, i.e. the value is the
+    SplitMix64 output function applied to s + k * 0x9E3779B97F4A7C15 (mod 2^64);
+    the entry is -1 if bit 63 of that output is set, else +1.
+    """
+    return rademacher_counter_doc.__doc__
