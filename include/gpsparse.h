@@ -1,0 +1,227 @@
+/*
+ * gpsparse.h - C ABI of the MI355X (gfx950) sparse-covariance exact-GP library.
+ *
+ * The library assembles the covariance of the compactly supported,
+ * nonstationary kernel of "Compactly-supported nonstationary kernels for
+ * computing exact Gaussian processes on big data" (arXiv 2411.05869),
+ *
+ *     K_pq = s0 f0(x_p, x_q; r0) + sum_{i=1..n1} f_i(x_p) f_i(x_q) + sigma^2 [p = q]
+ *
+ * (Sec. 2.1, Eq. C_sparse with the Wendland part of Eq. compSupp, the bump
+ * sums of Eq. sumOfBumps / bumpFcn; Sec. 3.1 Eq. Zcov for the nugget; unit
+ * core kernel), evaluates the Gaussian log-likelihood of Sec. 3.1 Eq. Zmarg
+ * (log det K and y^T K^-1 y, the three tasks of Sec. 3.3) and the kriging
+ * mean of Sec. 3.2.  All numerical work runs in HIP kernels on one GPU.
+ *
+ * Conventions shared by every entry point:
+ *   - Pointers named *_dev are device pointers on the context's device; all
+ *     other pointers are host pointers.  Caller-owned buffers are never
+ *     retained past the call.
+ *   - All work is issued on the context's HIP stream.  A call returns after
+ *     its results are complete unless stated otherwise.
+ *   - Every call returns gp_status; no C++ exception crosses the ABI.  On an
+ *     error the message is available from gp_last_error(ctx).  Input errors
+ *     (GP_EINVAL) are detected on the host before any device work.
+ *   - Objects (gp_dataset, gp_matrix, gp_predictor) belong to the context
+ *     that created them and are freed through its allocator.  A context is
+ *     not thread-safe: use one context per host thread / serving slot.
+ *   - Point coordinates are n x d row-major float64 with 1 <= d <= 3.
+ */
+#ifndef GPSPARSE_H
+#define GPSPARSE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#if defined(__GNUC__) || defined(__clang__)
+#define GP_API __attribute__((visibility("default")))
+#else
+#define GP_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum gp_status {
+  GP_OK = 0,
+  GP_EINVAL = 1,    /* invalid argument (shape, hyper-parameter, non-finite input) */
+  GP_ENOMEM = 2,    /* the allocator failed or a size limit was exceeded */
+  GP_ENOTCONV = 3,  /* iteration limit reached; outputs hold the last iterate */
+  GP_ENOTPD = 4,    /* non-positive curvature met: matrix not positive definite */
+  GP_EDEVICE = 5    /* HIP runtime error or an internal consistency check failed */
+} gp_status;
+
+typedef enum gp_precision {
+  GP_FP64 = 0,      /* float64 values, vectors and accumulation */
+  GP_MIXED = 1      /* float32 values and SpMV/SpMM, float64 residuals and reductions */
+} gp_precision;
+
+typedef enum gp_logdet_mode {
+  GP_LOGDET_SLQ = 0,    /* stochastic Lanczos quadrature (Sec. 3.3 Lanczos log-det) */
+  GP_LOGDET_EXACT = 1,  /* Lanczos to dimension n with full re-orthogonalisation (n <= 8192) */
+  GP_LOGDET_NONE = 2    /* skip the log-determinant (quadratic form only) */
+} gp_logdet_mode;
+
+typedef struct gp_ctx gp_ctx;
+typedef struct gp_dataset gp_dataset;
+typedef struct gp_matrix gp_matrix;
+typedef struct gp_predictor gp_predictor;
+
+/* Device-memory allocator supplied by the caller (e.g. a framework's caching
+ * allocator).  alloc returns a device pointer or NULL; free receives the
+ * pointer and the size that was requested. */
+typedef void* (*gp_alloc_fn)(size_t bytes, void* user);
+typedef void (*gp_free_fn)(void* ptr, size_t bytes, void* user);
+
+/* ------------------------------------------------------------------ context
+ * gp_ctx_create: binds a context to `device` and the HIP stream `stream`
+ * (a hipStream_t; NULL = the null stream).  alloc/free may both be NULL, in
+ * which case the library uses the device's stream-ordered memory pool.
+ * Errors: GP_EINVAL (bad device, only one of alloc/free given), GP_EDEVICE. */
+GP_API gp_status gp_ctx_create(int device, void* stream, gp_alloc_fn alloc, gp_free_fn free_fn,
+                        void* user, gp_ctx** out);
+/* Releases the context's workspace.  Objects it created must be destroyed first. */
+GP_API gp_status gp_ctx_destroy(gp_ctx* ctx);
+/* Re-targets later work of the context to another stream. */
+GP_API gp_status gp_ctx_set_stream(gp_ctx* ctx, void* stream);
+/* Last error message of the context ("" if none).  Valid until the next call. */
+GP_API const char* gp_last_error(const gp_ctx* ctx);
+/* Bytes currently held by the context's workspace and live objects. */
+GP_API gp_status gp_ctx_memory(const gp_ctx* ctx, size_t* bytes_in_use, size_t* peak_bytes);
+
+/* ------------------------------------------------------------------ dataset
+ * gp_dataset_create: copies and spatially bins n points (x_dev, n x d
+ * row-major float64, caller-owned, read during the call).  The points are
+ * sorted by a cell key on a regular grid with cell edge cell[k] per
+ * coordinate (host array of d positive values; NULL picks about eight
+ * points per cell).  Cells never decide membership in the covariance pattern;
+ * they only bound the candidate search.  The binned copy stays resident on
+ * the device until gp_dataset_destroy.
+ * Errors: GP_EINVAL (n < 1, d not in 1..3, non-finite coordinate, cell <= 0),
+ * GP_ENOMEM, GP_EDEVICE. */
+GP_API gp_status gp_dataset_create(gp_ctx* ctx, int64_t n, int32_t d, const double* x_dev,
+                            const double* cell, gp_dataset** out);
+GP_API gp_status gp_dataset_destroy(gp_ctx* ctx, gp_dataset* ds);
+/* n, d, number of grid cells, and the cell edges used (cell_out: d doubles or NULL). */
+GP_API gp_status gp_dataset_info(const gp_dataset* ds, int64_t* n, int32_t* d, int64_t* n_cells,
+                          double* cell_out);
+/* Binned position -> original index (perm_dev: n int32, caller-owned). */
+GP_API gp_status gp_dataset_permutation(gp_ctx* ctx, const gp_dataset* ds, int32_t* perm_dev);
+
+/* ------------------------------------------------------- hyper-parameters
+ * theta_sparse of Sec. 2.1 (s0, r0, {h_ij, a_ij, b_ij, r_ij}) plus the
+ * nugget sigma^2 of Eq. Zcov, all in host memory, copied by each call.
+ *   r0[k]  coordinate-specific Wendland radii (> 0; Appendix E uses
+ *          per-coordinate truncation radii); u = |((x - x') / r0)|.
+ *   h      n1*n2*d bump centres, bump (i, j) at h[(i*n2 + j)*d + k]
+ *   r      n1*n2*d bump radii per coordinate (> 0; +INF drops the coordinate)
+ *   a      n1*n2 amplitudes (>= 0; a = 0 removes the bump)
+ *   b      n1*n2 shapes (> 0)
+ * Support tests use the float64 expression sum_k ((x_k - c_k) * (1 / r_k))^2
+ * < 1 evaluated left to right without fused multiply-add.
+ * Limits: 1 <= n1 <= 64, n1*n2 <= 4096, s0 > 0, nugget >= 0. */
+typedef struct gp_theta {
+  int32_t d;
+  int32_t n1;
+  int32_t n2;
+  int32_t wendland_variant;  /* 0: cubic coefficient 35 as printed in Eq. compSupp; 1: 32 */
+  double s0;
+  double r0[3];
+  const double* h;
+  const double* r;
+  const double* a;
+  const double* b;
+  double nugget;
+} gp_theta;
+
+/* ------------------------------------------------------------------ matrix
+ * gp_assemble: builds K(theta) + sigma^2 I for the dataset as a CSR matrix
+ * owned by the library, rows and columns in binned order, ascending column
+ * indices, full symmetric storage.  The pattern is exactly the set of pairs
+ * that pass a support test (local Wendland support, a shared bump group, or
+ * the diagonal); entries whose value underflows stay stored.  Values are
+ * float64 (GP_FP64) or float32 rounded from float64 (GP_MIXED).
+ * Errors: GP_EINVAL (theta), GP_ENOMEM, GP_EDEVICE (device error or the
+ * count and fill passes disagree). */
+GP_API gp_status gp_assemble(gp_ctx* ctx, const gp_dataset* ds, const gp_theta* theta,
+                      gp_precision prec, gp_matrix** out);
+GP_API gp_status gp_matrix_destroy(gp_ctx* ctx, gp_matrix* m);
+/* n, nnz, bytes of the CSR arrays, precision, longest row. */
+GP_API gp_status gp_matrix_info(const gp_matrix* m, int64_t* n, int64_t* nnz, size_t* bytes,
+                         int32_t* prec, int64_t* max_row);
+/* Writes the matrix in ORIGINAL point order with ascending columns into
+ * caller device buffers: row_ptr_dev (n+1 int64), col_dev (nnz int32),
+ * val_dev (nnz float64; float32 values are widened).  Debug/parity path. */
+GP_API gp_status gp_matrix_export_csr(gp_ctx* ctx, const gp_matrix* m, int64_t* row_ptr_dev,
+                               int32_t* col_dev, double* val_dev);
+/* Y = K X for nrhs right-hand sides, X and Y n x nrhs row-major float64 in
+ * ORIGINAL point order (device).  Uses the matrix's value precision with
+ * float64 accumulation. */
+GP_API gp_status gp_matvec(gp_ctx* ctx, const gp_matrix* m, int32_t nrhs, const double* x_dev,
+                    double* y_dev);
+
+/* ------------------------------------------------------------ likelihood */
+typedef struct gp_solve_opts {
+  double rtol;          /* stop when |y - K alpha|_2 <= rtol |y|_2 (default 1e-10) */
+  int32_t max_iter;     /* conjugate-gradient iteration cap (default 10000) */
+  int32_t n_probes;     /* SLQ probes (default 30, at most 64) */
+  int32_t n_lanczos;    /* SLQ Lanczos steps (default 50, at most 128) */
+  int32_t logdet_mode;  /* gp_logdet_mode */
+  uint64_t seed;        /* probe seed */
+} gp_solve_opts;
+
+/* Fills opts with the defaults listed above. */
+GP_API void gp_solve_opts_default(gp_solve_opts* opts);
+
+typedef struct gp_loglik_result {
+  double loglik;        /* -1/2 logdet - 1/2 quad - (n/2) log(2 pi) */
+  double logdet;        /* log det K */
+  double quad;          /* y^T K^-1 y */
+  double logdet_se;     /* standard error of the SLQ estimate (0 in exact mode) */
+  double relres;        /* final |y - K alpha| / |y| (float64 true residual) */
+  int32_t cg_iters;     /* conjugate-gradient iterations */
+  int32_t refreshes;    /* float64 true-residual recomputations */
+  int32_t lanczos_steps;/* Lanczos steps taken (max over probes; n in exact mode) */
+  int32_t status;       /* gp_status of the solve */
+} gp_loglik_result;
+
+/* gp_loglik: log p(y | theta) for the residual y = z - W beta (y_dev: n
+ * float64 in ORIGINAL point order).  Quadratic form by Jacobi-preconditioned
+ * conjugate gradients on K; log det by stochastic Lanczos quadrature on the
+ * Jacobi-scaled matrix (or exact Lanczos, see gp_logdet_mode).  With a
+ * GP_MIXED matrix the products run in float32 and the residual
+ * recomputation, Lanczos coefficients, quadrature and quadratic form in
+ * float64.  alpha_dev (n float64, original order, may be NULL) receives
+ * K^-1 y.  opts may be NULL (defaults).
+ * Errors: GP_EINVAL, GP_ENOMEM, GP_ENOTCONV (result and alpha hold the last
+ * iterate), GP_ENOTPD, GP_EDEVICE. */
+GP_API gp_status gp_loglik(gp_ctx* ctx, const gp_matrix* m, const double* y_dev,
+                    const gp_solve_opts* opts, double* alpha_dev, gp_loglik_result* out);
+
+/* gp_solve: alpha = K^-1 y only (the quadratic-form task of Sec. 3.3). */
+GP_API gp_status gp_solve(gp_ctx* ctx, const gp_matrix* m, const double* y_dev,
+                   const gp_solve_opts* opts, double* alpha_dev, gp_loglik_result* out);
+
+/* ------------------------------------------------------------- prediction
+ * gp_predictor_create: caches what the kriging mean of Sec. 3.2 needs for a
+ * fixed theta and alpha = K^-1 y (alpha_dev: n float64 in ORIGINAL order of
+ * the training dataset): alpha in binned order and, per bump group i, the
+ * coefficient c_i = sum_q f_i(x_q) alpha_q.  The training dataset must
+ * outlive the predictor. */
+GP_API gp_status gp_predictor_create(gp_ctx* ctx, const gp_dataset* train, const gp_theta* theta,
+                              const double* alpha_dev, gp_predictor** out);
+GP_API gp_status gp_predictor_destroy(gp_ctx* ctx, gp_predictor* p);
+
+/* gp_predict: posterior mean m(x*) = sum_q C_y(x*, x_q) alpha_q (no nugget)
+ * for m test points (xstar_dev: m x d row-major float64) into mean_dev (m
+ * float64).  The cross-covariance is evaluated and applied in one pass and
+ * never stored.  GP_MIXED evaluates the cross-covariance in float32.
+ * Errors: GP_EINVAL (m < 0, non-finite), GP_EDEVICE. */
+GP_API gp_status gp_predict(gp_ctx* ctx, const gp_predictor* p, int64_t m, const double* xstar_dev,
+                     gp_precision prec, double* mean_dev);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GPSPARSE_H */

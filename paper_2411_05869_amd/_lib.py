@@ -1,0 +1,368 @@
+"""ctypes binding of libgpsparse.so with PyTorch memory and streams."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libgpsparse.so")
+_lib = None
+
+FP64, MIXED = 0, 1
+LOGDET_SLQ, LOGDET_EXACT, LOGDET_NONE = 0, 1, 2
+_STATUS = {0: "GP_OK", 1: "GP_EINVAL", 2: "GP_ENOMEM", 3: "GP_ENOTCONV", 4: "GP_ENOTPD", 5: "GP_EDEVICE"}
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_size_t, C.c_void_p)
+
+
+class GPError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+        self.name = _STATUS.get(status, str(status))
+
+
+class CTheta(C.Structure):
+    _fields_ = [("d", C.c_int32), ("n1", C.c_int32), ("n2", C.c_int32), ("wendland_variant", C.c_int32),
+                ("s0", C.c_double), ("r0", C.c_double * 3), ("h", C.POINTER(C.c_double)),
+                ("r", C.POINTER(C.c_double)), ("a", C.POINTER(C.c_double)), ("b", C.POINTER(C.c_double)),
+                ("nugget", C.c_double)]
+
+
+class CSolveOpts(C.Structure):
+    _fields_ = [("rtol", C.c_double), ("max_iter", C.c_int32), ("n_probes", C.c_int32),
+                ("n_lanczos", C.c_int32), ("logdet_mode", C.c_int32), ("seed", C.c_uint64)]
+
+
+class CLoglikResult(C.Structure):
+    _fields_ = [("loglik", C.c_double), ("logdet", C.c_double), ("quad", C.c_double),
+                ("logdet_se", C.c_double), ("relres", C.c_double), ("cg_iters", C.c_int32),
+                ("refreshes", C.c_int32), ("lanczos_steps", C.c_int32), ("status", C.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+EXPORTS = [
+    "gp_ctx_create", "gp_ctx_destroy", "gp_ctx_set_stream", "gp_last_error", "gp_ctx_memory",
+    "gp_dataset_create", "gp_dataset_destroy", "gp_dataset_info", "gp_dataset_permutation",
+    "gp_assemble", "gp_matrix_destroy", "gp_matrix_info", "gp_matrix_export_csr", "gp_matvec",
+    "gp_solve_opts_default", "gp_loglik", "gp_solve", "gp_predictor_create", "gp_predictor_destroy",
+    "gp_predict",
+]
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def lib():
+    """Loads libgpsparse.so once; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise RuntimeError(f"{_LIB_PATH} is missing: build it with `python -m paper_2411_05869_amd.build`")
+    L = C.CDLL(_LIB_PATH)
+    P, I32, I64, D = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+    st = C.c_int
+    L.gp_ctx_create.argtypes = [C.c_int, P, ALLOC_FN, FREE_FN, P, C.POINTER(P)]
+    L.gp_ctx_destroy.argtypes = [P]
+    L.gp_ctx_set_stream.argtypes = [P, P]
+    L.gp_last_error.argtypes = [P]
+    L.gp_last_error.restype = C.c_char_p
+    L.gp_ctx_memory.argtypes = [P, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]
+    L.gp_dataset_create.argtypes = [P, I64, I32, P, C.POINTER(D), C.POINTER(P)]
+    L.gp_dataset_destroy.argtypes = [P, P]
+    L.gp_dataset_info.argtypes = [P, C.POINTER(I64), C.POINTER(I32), C.POINTER(I64), C.POINTER(D)]
+    L.gp_dataset_permutation.argtypes = [P, P, P]
+    L.gp_assemble.argtypes = [P, P, C.POINTER(CTheta), C.c_int, C.POINTER(P)]
+    L.gp_matrix_destroy.argtypes = [P, P]
+    L.gp_matrix_info.argtypes = [P, C.POINTER(I64), C.POINTER(I64), C.POINTER(C.c_size_t), C.POINTER(I32),
+                                 C.POINTER(I64)]
+    L.gp_matrix_export_csr.argtypes = [P, P, P, P, P]
+    L.gp_matvec.argtypes = [P, P, I32, P, P]
+    L.gp_solve_opts_default.argtypes = [C.POINTER(CSolveOpts)]
+    L.gp_solve_opts_default.restype = None
+    L.gp_loglik.argtypes = [P, P, P, C.POINTER(CSolveOpts), P, C.POINTER(CLoglikResult)]
+    L.gp_solve.argtypes = [P, P, P, C.POINTER(CSolveOpts), P, C.POINTER(CLoglikResult)]
+    L.gp_predictor_create.argtypes = [P, P, C.POINTER(CTheta), P, C.POINTER(P)]
+    L.gp_predictor_destroy.argtypes = [P, P]
+    L.gp_predict.argtypes = [P, P, I64, P, C.c_int, P]
+    for name in EXPORTS:
+        getattr(L, name).restype = st
+    L.gp_last_error.restype = C.c_char_p
+    L.gp_solve_opts_default.restype = None
+    _lib = L
+    return L
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _ptr(t) -> int:
+    return t.data_ptr()
+
+
+def _check_dev_tensor(t, dtype, shape=None, name="tensor"):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {shape}, got {tuple(t.shape)}")
+
+
+def theta_struct(th):
+    """C struct for an object with fields s0, r0, h, r, a, b, nugget (numpy) and
+    wendland_variant; the numpy buffers are kept alive on the struct."""
+    r0 = np.ascontiguousarray(np.asarray(th.r0, np.float64))
+    d = int(r0.shape[0])
+    a = np.ascontiguousarray(np.asarray(th.a, np.float64))
+    n1, n2 = (int(a.shape[0]), int(a.shape[1])) if a.ndim == 2 else (1 if a.size else 0, int(a.size))
+    h = np.ascontiguousarray(np.asarray(th.h, np.float64).reshape(-1))
+    r = np.ascontiguousarray(np.asarray(th.r, np.float64).reshape(-1))
+    a = a.reshape(-1)
+    b = np.ascontiguousarray(np.asarray(th.b, np.float64).reshape(-1))
+    cs = CTheta()
+    cs.d, cs.n1, cs.n2 = d, n1, n2
+    cs.wendland_variant = int(getattr(th, "wendland_variant", 0))
+    cs.s0 = float(th.s0)
+    for k in range(3):
+        cs.r0[k] = float(r0[k]) if k < d else 0.0
+    dp = C.POINTER(C.c_double)
+    cs.h = h.ctypes.data_as(dp)
+    cs.r = r.ctypes.data_as(dp)
+    cs.a = a.ctypes.data_as(dp)
+    cs.b = b.ctypes.data_as(dp)
+    cs.nugget = float(th.nugget)
+    cs._keep = (h, r, a, b)
+    return cs
+
+
+class Context:
+    """A library context bound to one device and one HIP stream.
+
+    ``stream``: a ``torch.cuda.Stream`` (default: the current stream).
+    ``torch_allocator``: hand PyTorch's caching allocator to the library
+    (default); otherwise the library uses the device's stream-ordered pool.
+    """
+
+    def __init__(self, device: int = 0, stream=None, torch_allocator: bool = True):
+        torch = _torch()
+        self._L = lib()
+        self.device = device
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        self._alloc_bytes = 0
+        self._peak = 0
+        if torch_allocator:
+            dev, strm = device, self.stream
+
+            def _alloc(nbytes, user):
+                try:
+                    p = torch.cuda.caching_allocator_alloc(int(nbytes), dev, strm)
+                    self._alloc_bytes += int(nbytes)
+                    self._peak = max(self._peak, self._alloc_bytes)
+                    return p
+                except Exception:  # out of memory -> NULL -> GP_ENOMEM
+                    return None
+
+            def _free(ptr, nbytes, user):
+                try:
+                    torch.cuda.caching_allocator_delete(ptr)
+                    self._alloc_bytes -= int(nbytes)
+                except Exception:
+                    pass
+
+            self._cb = (ALLOC_FN(_alloc), FREE_FN(_free))
+        else:
+            self._cb = (ALLOC_FN(0), FREE_FN(0))
+        h = C.c_void_p()
+        st = self._L.gp_ctx_create(device, C.c_void_p(self.stream.cuda_stream), self._cb[0], self._cb[1], None,
+                                   C.byref(h))
+        if st != 0:
+            raise GPError(st, "gp_ctx_create failed")
+        self._h = h
+
+    # ------------------------------------------------------------------ util
+    def _check(self, st: int, what: str):
+        if st != 0:
+            msg = self._L.gp_last_error(self._h)
+            raise GPError(st, f"{what}: {msg.decode() if msg else ''}")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.gp_ctx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def memory(self):
+        a, b = C.c_size_t(), C.c_size_t()
+        self._L.gp_ctx_memory(self._h, C.byref(a), C.byref(b))
+        return a.value, b.value
+
+    # --------------------------------------------------------------- objects
+    def dataset(self, x, cell=None) -> "Dataset":
+        torch = _torch()
+        _check_dev_tensor(x, torch.float64, name="x")
+        if x.dim() != 2:
+            raise ValueError("x must be (n, d)")
+        n, d = x.shape
+        cp = None
+        if cell is not None:
+            cell = np.ascontiguousarray(np.asarray(cell, np.float64).reshape(-1))
+            cp = cell.ctypes.data_as(C.POINTER(C.c_double))
+        h = C.c_void_p()
+        self._check(self._L.gp_dataset_create(self._h, n, d, C.c_void_p(_ptr(x)), cp, C.byref(h)),
+                    "gp_dataset_create")
+        return Dataset(self, h, n, d)
+
+    def assemble(self, ds: "Dataset", theta, precision: int = FP64) -> "Matrix":
+        cs = theta_struct(theta)
+        h = C.c_void_p()
+        self._check(self._L.gp_assemble(self._h, ds._h, C.byref(cs), int(precision), C.byref(h)), "gp_assemble")
+        return Matrix(self, h, ds)
+
+    def opts(self, **kw) -> CSolveOpts:
+        o = CSolveOpts()
+        self._L.gp_solve_opts_default(C.byref(o))
+        for k, v in kw.items():
+            if v is not None:
+                setattr(o, k, v)
+        return o
+
+    def loglik(self, K: "Matrix", y, alpha_out=None, raise_on_error: bool = True, **opts) -> dict:
+        torch = _torch()
+        _check_dev_tensor(y, torch.float64, (K.n,), "y")
+        if alpha_out is not None:
+            _check_dev_tensor(alpha_out, torch.float64, (K.n,), "alpha_out")
+        o = self.opts(**opts)
+        res = CLoglikResult()
+        st = self._L.gp_loglik(self._h, K._h, C.c_void_p(_ptr(y)), C.byref(o),
+                               C.c_void_p(_ptr(alpha_out)) if alpha_out is not None else None, C.byref(res))
+        if st != 0 and raise_on_error:
+            self._check(st, "gp_loglik")
+        return res.as_dict()
+
+    def solve(self, K: "Matrix", y, alpha_out, raise_on_error: bool = True, **opts) -> dict:
+        torch = _torch()
+        _check_dev_tensor(y, torch.float64, (K.n,), "y")
+        _check_dev_tensor(alpha_out, torch.float64, (K.n,), "alpha_out")
+        o = self.opts(**opts)
+        res = CLoglikResult()
+        st = self._L.gp_solve(self._h, K._h, C.c_void_p(_ptr(y)), C.byref(o), C.c_void_p(_ptr(alpha_out)),
+                              C.byref(res))
+        if st != 0 and raise_on_error:
+            self._check(st, "gp_solve")
+        return res.as_dict()
+
+    def matvec(self, K: "Matrix", x):
+        torch = _torch()
+        _check_dev_tensor(x, torch.float64, name="x")
+        nrhs = 1 if x.dim() == 1 else int(x.shape[1])
+        y = torch.empty_like(x)
+        self._check(self._L.gp_matvec(self._h, K._h, nrhs, C.c_void_p(_ptr(x)), C.c_void_p(_ptr(y))), "gp_matvec")
+        return y
+
+    def export_csr(self, K: "Matrix"):
+        torch = _torch()
+        dev = torch.device("cuda", self.device)
+        rp = torch.empty(K.n + 1, dtype=torch.int64, device=dev)
+        col = torch.empty(max(K.nnz, 1), dtype=torch.int32, device=dev)
+        val = torch.empty(max(K.nnz, 1), dtype=torch.float64, device=dev)
+        self._check(self._L.gp_matrix_export_csr(self._h, K._h, C.c_void_p(_ptr(rp)), C.c_void_p(_ptr(col)),
+                                                 C.c_void_p(_ptr(val))), "gp_matrix_export_csr")
+        return rp, col[:K.nnz], val[:K.nnz]
+
+    def predictor(self, ds: "Dataset", theta, alpha) -> "Predictor":
+        torch = _torch()
+        _check_dev_tensor(alpha, torch.float64, (ds.n,), "alpha")
+        cs = theta_struct(theta)
+        h = C.c_void_p()
+        self._check(self._L.gp_predictor_create(self._h, ds._h, C.byref(cs), C.c_void_p(_ptr(alpha)), C.byref(h)),
+                    "gp_predictor_create")
+        return Predictor(self, h, ds)
+
+    def predict(self, pred: "Predictor", xs, precision: int = FP64, out=None):
+        torch = _torch()
+        _check_dev_tensor(xs, torch.float64, name="xs")
+        m = int(xs.shape[0])
+        if out is None:
+            out = torch.empty(m, dtype=torch.float64, device=xs.device)
+        self._check(self._L.gp_predict(self._h, pred._h, m, C.c_void_p(_ptr(xs)), int(precision),
+                                       C.c_void_p(_ptr(out))), "gp_predict")
+        return out
+
+
+class _Obj:
+    def __init__(self, ctx: Context, h):
+        self.ctx = ctx
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) and self.ctx._h:
+            self._destroy()
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Dataset(_Obj):
+    def __init__(self, ctx, h, n, d):
+        super().__init__(ctx, h)
+        self.n, self.d = int(n), int(d)
+
+    def _destroy(self):
+        self.ctx._L.gp_dataset_destroy(self.ctx._h, self._h)
+
+    def info(self):
+        n, d, nc = C.c_int64(), C.c_int32(), C.c_int64()
+        cell = (C.c_double * 3)()
+        self.ctx._L.gp_dataset_info(self._h, C.byref(n), C.byref(d), C.byref(nc), cell)
+        return dict(n=n.value, d=d.value, n_cells=nc.value, cell=list(cell)[:d.value])
+
+    def permutation(self):
+        torch = _torch()
+        p = torch.empty(self.n, dtype=torch.int32, device=torch.device("cuda", self.ctx.device))
+        self.ctx._check(self.ctx._L.gp_dataset_permutation(self.ctx._h, self._h, C.c_void_p(_ptr(p))),
+                        "gp_dataset_permutation")
+        return p
+
+
+class Matrix(_Obj):
+    def __init__(self, ctx, h, ds):
+        super().__init__(ctx, h)
+        self.ds = ds
+        n, nnz, by, pr, mr = C.c_int64(), C.c_int64(), C.c_size_t(), C.c_int32(), C.c_int64()
+        ctx._L.gp_matrix_info(h, C.byref(n), C.byref(nnz), C.byref(by), C.byref(pr), C.byref(mr))
+        self.n, self.nnz, self.bytes, self.precision, self.max_row = n.value, nnz.value, by.value, pr.value, mr.value
+
+    def _destroy(self):
+        self.ctx._L.gp_matrix_destroy(self.ctx._h, self._h)
+
+
+class Predictor(_Obj):
+    def __init__(self, ctx, h, ds):
+        super().__init__(ctx, h)
+        self.ds = ds
+
+    def _destroy(self):
+        self.ctx._L.gp_predictor_destroy(self.ctx._h, self._h)

@@ -1,0 +1,640 @@
+// Assembly of K(theta) + sigma^2 I as CSR (binned order, ascending columns).
+//
+// The pattern is   P = {(p,q): u0^2(p,q) < 1}  U  {(p,q): M(p) & M(q) != 0}
+// (local Wendland support of Eq. compSupp, or a shared bump group of
+// Eq. C_sparse; the diagonal is in both).  For a fixed theta both supports are
+// explicit balls, so the pattern is found without testing all pairs:
+//   * local pairs: each row searches the cells within R_k rings of its own
+//     cell; cells in key order and points in binned order visit candidate
+//     columns in ascending order;
+//   * group pairs: rows with a group mask M take every point of
+//     U_M = {q : M(q) & M != 0}, a sorted list shared by all rows with mask M.
+// Rows with no group bit (most rows) hold only local entries and are done one
+// row per lane.  Rows with a group bit are done one row per wave: their
+// local-only entries L'(p) = local hits with no shared group are merged with
+// U_M by rank (binary search), so each row's columns come out sorted and
+// unique.  Count and fill run the same candidate loops; the fill checks that
+// it wrote exactly the counted number of entries.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+
+#include "device.hpp"
+
+namespace gps {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kLdsList = 512;   // per-wave LDS copy of L'(p)
+
+struct AsmArgs {
+  KernelTheta kt;
+  int64_t n;
+  const double* xb;
+  const int32_t* key;
+  const int32_t* cell_start;
+  int32_t g[3];
+  int32_t R[3];
+  const uint64_t* mask;
+  const int32_t* midx;
+  const int32_t* mlist;
+  const double* F;
+  int64_t nm;
+  // group lists
+  const int32_t* did;       // nm: distinct-mask id of each masked row
+  const int64_t* uoff;      // nD + 1
+  const int32_t* ulist;     // concatenated U_M lists
+  // counts / outputs
+  int32_t* counts;          // n
+  int32_t* lcnt;            // nm
+  const int64_t* loff;      // nm + 1
+  int32_t* lscratch;        // L' lists
+  const int64_t* row_ptr;   // n + 1
+  int32_t* col;
+  void* val;
+  double* diag;
+  int* err;
+};
+
+template <int D>
+__device__ __forceinline__ void load_point(const double* xb, int64_t n, int64_t i, double* x) {
+  x[0] = xb[i];
+  if constexpr (D >= 2) x[1] = xb[n + i];
+  if constexpr (D >= 3) x[2] = xb[2 * n + i];
+}
+
+// Window bounds of the local search around cell c: for each (z, y) pencil, the
+// binned range of cells x0..x1.
+struct Window {
+  int x0, x1, y0, y1, z0, z1;
+};
+
+template <int D>
+__device__ __forceinline__ Window make_window(const AsmArgs& a, const int* c) {
+  Window w;
+  w.x0 = max(c[0] - a.R[0], 0);
+  w.x1 = min(c[0] + a.R[0], a.g[0] - 1);
+  w.y0 = D >= 2 ? max(c[1] - a.R[1], 0) : 0;
+  w.y1 = D >= 2 ? min(c[1] + a.R[1], a.g[1] - 1) : 0;
+  w.z0 = D >= 3 ? max(c[2] - a.R[2], 0) : 0;
+  w.z1 = D >= 3 ? min(c[2] + a.R[2], a.g[2] - 1) : 0;
+  return w;
+}
+
+// ---------------------------------------------------------------- features
+template <int D>
+__global__ void __launch_bounds__(kThreads) k_mask(KernelTheta kt, int64_t n, const double* __restrict__ xb,
+                                                   uint64_t* __restrict__ mask, int32_t* __restrict__ flag) {
+  const int64_t p = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x;
+  if (p >= n) return;
+  double x[3];
+  load_point<D>(xb, n, p, x);
+  const uint64_t m = point_features<D, false>(kt, x, nullptr);
+  mask[p] = m;
+  flag[p] = m != 0 ? 1 : 0;
+}
+
+__global__ void __launch_bounds__(kThreads) k_compact_masked(int64_t n, const int32_t* __restrict__ flag,
+                                                             const int32_t* __restrict__ pos,
+                                                             const uint64_t* __restrict__ mask,
+                                                             int32_t* __restrict__ midx, int32_t* __restrict__ mlist,
+                                                             uint64_t* __restrict__ mmask) {
+  const int64_t p = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x;
+  if (p >= n) return;
+  if (flag[p]) {
+    const int32_t k = pos[p];
+    midx[p] = k;
+    mlist[k] = static_cast<int32_t>(p);
+    mmask[k] = mask[p];
+  } else {
+    midx[p] = -1;
+  }
+}
+
+template <int D>
+__global__ void __launch_bounds__(kThreads) k_fvals(KernelTheta kt, int64_t n, int64_t nm, const double* __restrict__ xb,
+                                                    const int32_t* __restrict__ mlist, double* __restrict__ F) {
+  const int64_t k = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x;
+  if (k >= nm) return;
+  double x[3];
+  load_point<D>(xb, n, mlist[k], x);
+  point_features<D, true>(kt, x, F + k * kt.n1);
+}
+
+// One block per distinct mask M: U_M = masked points q (ascending) with M(q) & M != 0.
+__global__ void __launch_bounds__(kThreads) k_ulists(int64_t nm, const uint64_t* __restrict__ mmask,
+                                                     const int32_t* __restrict__ mlist,
+                                                     const uint64_t* __restrict__ dmask,
+                                                     const int64_t* __restrict__ uoff, int32_t* __restrict__ ulist) {
+  __shared__ int32_t wcount[kThreads / kWave];
+  const uint64_t M = dmask[blockIdx.x];
+  int32_t* out = ulist + uoff[blockIdx.x];
+  const int w = threadIdx.x / kWave;
+  int64_t running = 0;
+  for (int64_t b = 0; b < nm; b += kThreads) {
+    const int64_t k = b + threadIdx.x;
+    const bool hit = k < nm && (mmask[k] & M) != 0;
+    const uint64_t bal = __ballot(hit);
+    if (lane_id() == 0) wcount[w] = __popcll(bal);
+    __syncthreads();
+    int64_t before = 0, total = 0;
+    for (int i = 0; i < kThreads / kWave; ++i) {
+      if (i < w) before += wcount[i];
+      total += wcount[i];
+    }
+    if (hit) out[running + before + __popcll(bal & lanes_below())] = mlist[k];
+    running += total;
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------- rows without groups
+template <int D, bool FILL, typename VT>
+__global__ void __launch_bounds__(kThreads) k_local_rows(AsmArgs a) {
+  const int64_t p = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x;
+  if (p >= a.n) return;
+  if (a.mask[p] != 0) return;
+  double xp[3];
+  load_point<D>(a.xb, a.n, p, xp);
+  int c[3];
+  decode_key(a.key[p], a.g, c);
+  const Window w = make_window<D>(a, c);
+  int32_t cnt = 0;
+  const int64_t out = FILL ? a.row_ptr[p] : 0;
+  const int64_t len = FILL ? a.row_ptr[p + 1] - out : 0;
+  VT* val = static_cast<VT*>(a.val);
+  for (int z = w.z0; z <= w.z1; ++z)
+    for (int y = w.y0; y <= w.y1; ++y) {
+      const int64_t base = (static_cast<int64_t>(z) * a.g[1] + y) * a.g[0];
+      const int32_t s = a.cell_start[base + w.x0];
+      const int32_t e = a.cell_start[base + w.x1 + 1];
+      for (int32_t q = s; q < e; ++q) {
+        double xq[3];
+        load_point<D>(a.xb, a.n, q, xq);
+        const double u2 = scaled_sq<D>(xp, xq, a.kt.inv0);
+        if (u2 < 1.0) {
+          if constexpr (FILL) {
+            const double v = entry_value(a.kt, u2, 0, nullptr, nullptr, q == p);
+            const VT vs = static_cast<VT>(v);
+            if (cnt < len) {  // never past the counted row (a mismatch is reported below)
+              a.col[out + cnt] = q;
+              val[out + cnt] = vs;
+            }
+            if (q == p) a.diag[p] = static_cast<double>(vs);
+          }
+          ++cnt;
+        }
+      }
+    }
+  if constexpr (!FILL) {
+    a.counts[p] = cnt;
+  } else {
+    if (static_cast<int64_t>(cnt) != len) atomicOr(a.err, 1);
+  }
+}
+
+// ------------------------------------------------------- rows with groups
+__device__ __forceinline__ int64_t lower_bound_g(const int32_t* __restrict__ v, int64_t len, int32_t key) {
+  int64_t lo = 0, hi = len;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (v[mid] < key)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+// PASS 0: count L'(p) and the row; PASS 1: write L'(p) to scratch.
+template <int D, int PASS>
+__global__ void __launch_bounds__(kThreads) k_group_rows_scan(AsmArgs a) {
+  const int64_t k = (blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x) / kWave;
+  if (k >= a.nm) return;
+  const int32_t p = a.mlist[k];
+  const uint64_t mp = a.mask[p];
+  double xp[3];
+  load_point<D>(a.xb, a.n, p, xp);
+  int c[3];
+  decode_key(a.key[p], a.g, c);
+  const Window w = make_window<D>(a, c);
+  int64_t running = 0;
+  const int64_t lbase = PASS == 1 ? a.loff[k] : 0;
+  const int64_t llen = PASS == 1 ? a.loff[k + 1] - lbase : 0;
+  const int lane = lane_id();
+  for (int z = w.z0; z <= w.z1; ++z)
+    for (int y = w.y0; y <= w.y1; ++y) {
+      const int64_t base = (static_cast<int64_t>(z) * a.g[1] + y) * a.g[0];
+      const int32_t s = a.cell_start[base + w.x0];
+      const int32_t e = a.cell_start[base + w.x1 + 1];
+      for (int32_t b = s; b < e; b += kWave) {
+        const int32_t q = b + lane;
+        bool hit = false;
+        if (q < e) {
+          double xq[3];
+          load_point<D>(a.xb, a.n, q, xq);
+          const double u2 = scaled_sq<D>(xp, xq, a.kt.inv0);
+          hit = (u2 < 1.0) && ((a.mask[q] & mp) == 0);
+        }
+        const uint64_t bal = __ballot(hit);
+        if constexpr (PASS == 1) {
+          const int64_t slot = running + __popcll(bal & lanes_below());
+          if (hit && slot < llen) a.lscratch[lbase + slot] = q;
+        }
+        running += __popcll(bal);
+      }
+    }
+  if (lane == 0) {
+    const int32_t D_id = a.did[k];
+    const int64_t nu = a.uoff[D_id + 1] - a.uoff[D_id];
+    if constexpr (PASS == 0) {
+      a.lcnt[k] = static_cast<int32_t>(running);
+      a.counts[p] = static_cast<int32_t>(nu + running);
+    } else {
+      if (running != a.loff[k + 1] - a.loff[k]) atomicOr(a.err, 2);
+    }
+  }
+}
+
+template <int D, typename VT>
+__global__ void __launch_bounds__(kThreads) k_group_rows_fill(AsmArgs a) {
+  __shared__ int32_t lds[kThreads / kWave][kLdsList];
+  const int64_t k = (blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x) / kWave;
+  if (k >= a.nm) return;
+  const int wv = threadIdx.x / kWave;
+  const int lane = lane_id();
+  const int32_t p = a.mlist[k];
+  const uint64_t mp = a.mask[p];
+  double xp[3];
+  load_point<D>(a.xb, a.n, p, xp);
+  const double* Fp = a.F + k * a.kt.n1;
+  const int32_t* L = a.lscratch + a.loff[k];
+  const int64_t nL = a.loff[k + 1] - a.loff[k];
+  const int32_t D_id = a.did[k];
+  const int32_t* U = a.ulist + a.uoff[D_id];
+  const int64_t nU = a.uoff[D_id + 1] - a.uoff[D_id];
+  const int64_t out = a.row_ptr[p];
+  const int64_t len = a.row_ptr[p + 1] - out;
+  VT* val = static_cast<VT*>(a.val);
+  if (nL + nU != len) {  // counts disagree: write nothing, report
+    if (lane == 0) atomicOr(a.err, 4);
+    return;
+  }
+  // local-only entries: position = rank in L' + rank in U
+  for (int64_t j = lane; j < nL; j += kWave) {
+    const int32_t q = L[j];
+    double xq[3];
+    load_point<D>(a.xb, a.n, q, xq);
+    const double u2 = scaled_sq<D>(xp, xq, a.kt.inv0);
+    const double v = entry_value(a.kt, u2, 0, nullptr, nullptr, false);
+    const int64_t pos = j + lower_bound_g(U, nU, q);
+    a.col[out + pos] = q;
+    val[out + pos] = static_cast<VT>(v);
+  }
+  const bool in_lds = nL <= kLdsList;
+  if (in_lds) {
+    for (int64_t j = lane; j < nL; j += kWave) lds[wv][j] = L[j];
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  const int32_t* Ls = in_lds ? &lds[wv][0] : L;
+  // group entries: position = rank in U + rank in L'
+  for (int64_t kk = lane; kk < nU; kk += kWave) {
+    const int32_t u = U[kk];
+    int64_t lo = 0, hi = nL;
+    while (lo < hi) {
+      const int64_t mid = (lo + hi) >> 1;
+      if (Ls[mid] < u)
+        lo = mid + 1;
+      else
+        hi = mid;
+    }
+    const int64_t pos = kk + lo;
+    double xq[3];
+    load_point<D>(a.xb, a.n, u, xq);
+    const double u2 = scaled_sq<D>(xp, xq, a.kt.inv0);
+    const uint64_t shared = a.mask[u] & mp;
+    const double* Fq = a.F + static_cast<int64_t>(a.midx[u]) * a.kt.n1;
+    const double v = entry_value(a.kt, u2, shared, Fp, Fq, u == p);
+    const VT vs = static_cast<VT>(v);
+    a.col[out + pos] = u;
+    val[out + pos] = vs;
+    if (u == p) a.diag[p] = static_cast<double>(vs);
+  }
+}
+
+__global__ void __launch_bounds__(kThreads) k_long_flags(int64_t n, const int32_t* __restrict__ counts,
+                                                         int32_t* __restrict__ flag, int32_t* __restrict__ maxrow) {
+  const int64_t p = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x;
+  int32_t c = 0;
+  if (p < n) {
+    c = counts[p];
+    flag[p] = c > kLongRow ? 1 : 0;
+  }
+  for (int off = kWave / 2; off > 0; off >>= 1) c = max(c, __shfl_xor(c, off, kWave));
+  if (lane_id() == 0) atomicMax(maxrow, c);
+}
+
+__global__ void __launch_bounds__(kThreads) k_long_compact(int64_t n, const int32_t* __restrict__ flag,
+                                                           const int32_t* __restrict__ pos,
+                                                           int32_t* __restrict__ list) {
+  const int64_t p = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x;
+  if (p < n && flag[p]) list[pos[p]] = static_cast<int32_t>(p);
+}
+
+template <typename F3>
+void dispatch_d(int d, F3&& f) {
+  if (d == 1)
+    f(std::integral_constant<int, 1>{});
+  else if (d == 2)
+    f(std::integral_constant<int, 2>{});
+  else
+    f(std::integral_constant<int, 3>{});
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ host
+void upload_theta(gp_ctx* c, const gp_theta* th, Bump** bumps_dev, KernelTheta* kt) {
+  const int nb = th->n1 * th->n2;
+  std::vector<Bump> hb(nb);
+  for (int b = 0; b < nb; ++b) {
+    for (int k = 0; k < 3; ++k) {
+      hb[b].h[k] = k < th->d ? th->h[b * th->d + k] : 0.0;
+      hb[b].inv[k] = k < th->d ? 1.0 / th->r[b * th->d + k] : 0.0;
+    }
+    hb[b].a = th->a[b];
+    hb[b].b = th->b[b];
+  }
+  Bump* dst = static_cast<Bump*>(workspace(c, 0, sizeof(Bump) * std::max(nb, 1)));
+  Bump* staging = static_cast<Bump*>(pinned(c, sizeof(Bump) * std::max(nb, 1)));
+  std::memcpy(staging, hb.data(), sizeof(Bump) * nb);
+  GPS_HIP(hipMemcpyAsync(dst, staging, sizeof(Bump) * nb, hipMemcpyHostToDevice, c->stream));
+  // the staging buffer is reused by later calls: wait for the copy
+  GPS_HIP(hipStreamSynchronize(c->stream));
+  *bumps_dev = dst;
+  kt->d = th->d;
+  kt->n1 = th->n1;
+  kt->n2 = th->n2;
+  kt->variant = th->wendland_variant;
+  kt->s0 = th->s0;
+  kt->nugget = th->nugget;
+  for (int k = 0; k < 3; ++k) kt->inv0[k] = k < th->d ? 1.0 / th->r0[k] : 0.0;
+  kt->bumps = dst;
+}
+
+Grid make_grid(const gp_dataset* ds, const gp_theta* th) {
+  Grid g{};
+  for (int k = 0; k < 3; ++k) {
+    g.lo[k] = ds->lo[k];
+    g.cell[k] = ds->cell[k];
+    g.inv_cell[k] = 1.0 / ds->cell[k];
+    g.g[k] = ds->g[k];
+    if (k < ds->d) {
+      // rings needed so that |x_p - x_q| < r0 implies |cell_p - cell_q| <= R even
+      // after rounding of the cell computation (margin 1e-9 relative)
+      const double need = th->r0[k] * (1.0 + 1e-9) / ds->cell[k];
+      double R = std::ceil(need);
+      if (R < 1) R = 1;
+      if (R > ds->g[k]) R = ds->g[k];
+      g.R[k] = static_cast<int32_t>(R);
+    } else {
+      g.R[k] = 0;
+    }
+  }
+  return g;
+}
+
+void compute_features(gp_ctx* c, const gp_dataset* ds, const KernelTheta& kt, Features* f, int ws_base) {
+  const int64_t n = ds->n;
+  f->mask = static_cast<uint64_t*>(workspace(c, ws_base + 0, sizeof(uint64_t) * n));
+  f->midx = static_cast<int32_t*>(workspace(c, ws_base + 1, sizeof(int32_t) * n));
+  int32_t* flag = static_cast<int32_t*>(workspace(c, ws_base + 2, sizeof(int32_t) * n));
+  int32_t* pos = static_cast<int32_t*>(workspace(c, ws_base + 3, sizeof(int32_t) * (n + 1)));
+  dispatch_d(ds->d, [&](auto DD) {
+    constexpr int D = decltype(DD)::value;
+    hipLaunchKernelGGL((k_mask<D>), dim3(grid_for(n, kThreads)), dim3(kThreads), 0, c->stream, kt, n, ds->xb,
+                       f->mask, flag);
+  });
+  check_launch("mask");
+  scan_i32_to_i32(c, flag, pos, n);
+  int32_t* h = static_cast<int32_t*>(pinned(c, sizeof(int32_t)));
+  GPS_HIP(hipMemcpyAsync(h, pos + n, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+  GPS_HIP(hipStreamSynchronize(c->stream));
+  f->nm = *h;
+  f->mlist = static_cast<int32_t*>(workspace(c, ws_base + 4, sizeof(int32_t) * std::max<int64_t>(f->nm, 1)));
+  uint64_t* mmask = static_cast<uint64_t*>(workspace(c, ws_base + 5, sizeof(uint64_t) * std::max<int64_t>(f->nm, 1)));
+  f->mmask = mmask;
+  hipLaunchKernelGGL(k_compact_masked, dim3(grid_for(n, kThreads)), dim3(kThreads), 0, c->stream, n, flag, pos,
+                     f->mask, f->midx, f->mlist, mmask);
+  check_launch("compact masked");
+  f->F = static_cast<double*>(workspace(c, ws_base + 6, sizeof(double) * std::max<int64_t>(f->nm * kt.n1, 1)));
+  if (f->nm > 0) {
+    dispatch_d(ds->d, [&](auto DD) {
+      constexpr int D = decltype(DD)::value;
+      hipLaunchKernelGGL((k_fvals<D>), dim3(grid_for(f->nm, kThreads)), dim3(kThreads), 0, c->stream, kt, n, f->nm,
+                         ds->xb, f->mlist, f->F);
+    });
+    check_launch("bump values");
+  }
+}
+
+// Workspace slots used by assembly (0: bumps; 1..7: features; 8..: below)
+gp_matrix* assemble(gp_ctx* c, const gp_dataset* ds, const gp_theta* th, int prec) {
+  const int64_t n = ds->n;
+  Bump* bumps = nullptr;
+  KernelTheta kt{};
+  upload_theta(c, th, &bumps, &kt);
+  Features f;
+  compute_features(c, ds, kt, &f, 1);
+  const int64_t nm = f.nm;
+  uint64_t* mmask = f.mmask;
+  // distinct masks of the masked points (host: at most nm values)
+  std::vector<uint64_t> hm(nm);
+  std::vector<uint64_t> dmask;
+  std::vector<int64_t> uoff(1, 0);
+  std::vector<int32_t> did(nm);
+  if (nm > 0) {
+    GPS_HIP(hipMemcpyAsync(hm.data(), mmask, sizeof(uint64_t) * nm, hipMemcpyDeviceToHost, c->stream));
+    GPS_HIP(hipStreamSynchronize(c->stream));
+    std::vector<uint64_t> sorted = hm;
+    std::sort(sorted.begin(), sorted.end());
+    std::vector<int64_t> mult;
+    for (int64_t i = 0; i < nm; ++i) {
+      if (dmask.empty() || dmask.back() != sorted[i]) {
+        dmask.push_back(sorted[i]);
+        mult.push_back(0);
+      }
+      ++mult.back();
+    }
+    const size_t nD = dmask.size();
+    uoff.resize(nD + 1);
+    uoff[0] = 0;
+    for (size_t a = 0; a < nD; ++a) {
+      int64_t s = 0;
+      for (size_t b = 0; b < nD; ++b)
+        if (dmask[a] & dmask[b]) s += mult[b];
+      uoff[a + 1] = uoff[a] + s;
+    }
+    GPS_REQUIRE(uoff[nD] < (int64_t(1) << 31), GP_ENOMEM, "gp_assemble: bump group lists too large");
+    for (int64_t i = 0; i < nm; ++i)
+      did[i] = static_cast<int32_t>(std::lower_bound(dmask.begin(), dmask.end(), hm[i]) - dmask.begin());
+  }
+  const int64_t nD = static_cast<int64_t>(dmask.size());
+  const int64_t utotal = uoff.back();
+  int32_t* d_did = static_cast<int32_t*>(workspace(c, 8, sizeof(int32_t) * std::max<int64_t>(nm, 1)));
+  uint64_t* d_dmask = static_cast<uint64_t*>(workspace(c, 9, sizeof(uint64_t) * std::max<int64_t>(nD, 1)));
+  int64_t* d_uoff = static_cast<int64_t*>(workspace(c, 10, sizeof(int64_t) * (nD + 1)));
+  int32_t* d_ulist = static_cast<int32_t*>(workspace(c, 11, sizeof(int32_t) * std::max<int64_t>(utotal, 1)));
+  {
+    const size_t bytes = sizeof(int32_t) * nm + sizeof(uint64_t) * nD + sizeof(int64_t) * (nD + 1);
+    char* st = static_cast<char*>(pinned(c, bytes + 64));
+    std::memcpy(st, did.data(), sizeof(int32_t) * nm);
+    std::memcpy(st + sizeof(int32_t) * nm, dmask.data(), sizeof(uint64_t) * nD);
+    std::memcpy(st + sizeof(int32_t) * nm + sizeof(uint64_t) * nD, uoff.data(), sizeof(int64_t) * (nD + 1));
+    if (nm) GPS_HIP(hipMemcpyAsync(d_did, st, sizeof(int32_t) * nm, hipMemcpyHostToDevice, c->stream));
+    if (nD)
+      GPS_HIP(hipMemcpyAsync(d_dmask, st + sizeof(int32_t) * nm, sizeof(uint64_t) * nD, hipMemcpyHostToDevice,
+                             c->stream));
+    GPS_HIP(hipMemcpyAsync(d_uoff, st + sizeof(int32_t) * nm + sizeof(uint64_t) * nD, sizeof(int64_t) * (nD + 1),
+                           hipMemcpyHostToDevice, c->stream));
+    if (nD) {
+      hipLaunchKernelGGL(k_ulists, dim3(static_cast<unsigned>(nD)), dim3(kThreads), 0, c->stream, nm, mmask, f.mlist,
+                         d_dmask, d_uoff, d_ulist);
+      check_launch("group lists");
+    }
+    GPS_HIP(hipStreamSynchronize(c->stream));  // pinned staging is reused below
+  }
+
+  const Grid grid = make_grid(ds, th);
+  AsmArgs a{};
+  a.kt = kt;
+  a.n = n;
+  a.xb = ds->xb;
+  a.key = ds->key;
+  a.cell_start = ds->cell_start;
+  for (int k = 0; k < 3; ++k) {
+    a.g[k] = grid.g[k];
+    a.R[k] = grid.R[k];
+  }
+  a.mask = f.mask;
+  a.midx = f.midx;
+  a.mlist = f.mlist;
+  a.F = f.F;
+  a.nm = nm;
+  a.did = d_did;
+  a.uoff = d_uoff;
+  a.ulist = d_ulist;
+  a.counts = static_cast<int32_t*>(workspace(c, 12, sizeof(int32_t) * n));
+  a.lcnt = static_cast<int32_t*>(workspace(c, 13, sizeof(int32_t) * std::max<int64_t>(nm, 1)));
+  int64_t* loff = static_cast<int64_t*>(workspace(c, 14, sizeof(int64_t) * (nm + 1)));
+  a.loff = loff;
+  a.err = c->err_flag;
+  GPS_HIP(hipMemsetAsync(c->err_flag, 0, sizeof(int), c->stream));
+
+  const int d = ds->d;
+  // count passes
+  dispatch_d(d, [&](auto DD) {
+    constexpr int D = decltype(DD)::value;
+    hipLaunchKernelGGL((k_local_rows<D, false, double>), dim3(grid_for(n, kThreads)), dim3(kThreads), 0, c->stream,
+                       a);
+    if (nm > 0)
+      hipLaunchKernelGGL((k_group_rows_scan<D, 0>), dim3(grid_for(nm * kWave, kThreads)), dim3(kThreads), 0,
+                         c->stream, a);
+  });
+  check_launch("count");
+
+  std::unique_ptr<gp_matrix> m(new gp_matrix());
+  m->ds = ds;
+  m->n = n;
+  m->prec = prec;
+  m->nugget = th->nugget;
+  m->row_ptr = dev_new<int64_t>(c, n + 1);
+  m->bytes += sizeof(int64_t) * (n + 1);
+  scan_i32_to_i64(c, a.counts, m->row_ptr, n);
+  scan_i32_to_i64(c, a.lcnt, loff, nm);
+  int32_t* lflag = static_cast<int32_t*>(workspace(c, 15, sizeof(int32_t) * n));
+  int32_t* lpos = static_cast<int32_t*>(workspace(c, 16, sizeof(int32_t) * (n + 1)));
+  int32_t* maxrow = static_cast<int32_t*>(workspace(c, 17, sizeof(int32_t) * 2));
+  GPS_HIP(hipMemsetAsync(maxrow, 0, sizeof(int32_t), c->stream));
+  hipLaunchKernelGGL(k_long_flags, dim3(grid_for(n, kThreads)), dim3(kThreads), 0, c->stream, n, a.counts, lflag,
+                     maxrow);
+  check_launch("long flags");
+  scan_i32_to_i32(c, lflag, lpos, n);
+  // one synchronisation: nnz, |L'| total, number of long rows, longest row
+  struct Sizes {
+    int64_t nnz, ltot;
+    int32_t nlong, maxrow;
+  };
+  Sizes* hs = static_cast<Sizes*>(pinned(c, sizeof(Sizes)));
+  GPS_HIP(hipMemcpyAsync(&hs->nnz, m->row_ptr + n, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
+  GPS_HIP(hipMemcpyAsync(&hs->ltot, loff + nm, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
+  GPS_HIP(hipMemcpyAsync(&hs->nlong, lpos + n, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+  GPS_HIP(hipMemcpyAsync(&hs->maxrow, maxrow, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+  GPS_HIP(hipStreamSynchronize(c->stream));
+  const Sizes sz = *hs;
+  m->nnz = sz.nnz;
+  m->max_row = sz.maxrow;
+  m->n_long = sz.nlong;
+  GPS_REQUIRE(m->nnz < (int64_t(1) << 40), GP_ENOMEM, "gp_assemble: too many nonzeros");
+
+  const size_t vbytes = prec == GP_MIXED ? sizeof(float) : sizeof(double);
+  m->col = dev_new<int32_t>(c, m->nnz);
+  m->val = dev_alloc(c, vbytes * std::max<int64_t>(m->nnz, 1));
+  m->diag = dev_new<double>(c, n);
+  m->long_rows = dev_new<int32_t>(c, std::max<int64_t>(m->n_long, 1));
+  m->bytes += (sizeof(int32_t) + vbytes) * m->nnz + sizeof(double) * n + sizeof(int32_t) * m->n_long;
+  hipLaunchKernelGGL(k_long_compact, dim3(grid_for(n, kThreads)), dim3(kThreads), 0, c->stream, n, lflag, lpos,
+                     m->long_rows);
+  check_launch("long rows");
+
+  a.lscratch = static_cast<int32_t*>(workspace(c, 18, sizeof(int32_t) * std::max<int64_t>(sz.ltot, 1)));
+  a.row_ptr = m->row_ptr;
+  a.col = m->col;
+  a.val = m->val;
+  a.diag = m->diag;
+  dispatch_d(d, [&](auto DD) {
+    constexpr int D = decltype(DD)::value;
+    if (nm > 0)
+      hipLaunchKernelGGL((k_group_rows_scan<D, 1>), dim3(grid_for(nm * kWave, kThreads)), dim3(kThreads), 0,
+                         c->stream, a);
+    if (prec == GP_MIXED) {
+      hipLaunchKernelGGL((k_local_rows<D, true, float>), dim3(grid_for(n, kThreads)), dim3(kThreads), 0, c->stream,
+                         a);
+      if (nm > 0)
+        hipLaunchKernelGGL((k_group_rows_fill<D, float>), dim3(grid_for(nm * kWave, kThreads)), dim3(kThreads), 0,
+                           c->stream, a);
+    } else {
+      hipLaunchKernelGGL((k_local_rows<D, true, double>), dim3(grid_for(n, kThreads)), dim3(kThreads), 0, c->stream,
+                         a);
+      if (nm > 0)
+        hipLaunchKernelGGL((k_group_rows_fill<D, double>), dim3(grid_for(nm * kWave, kThreads)), dim3(kThreads), 0,
+                           c->stream, a);
+    }
+  });
+  check_launch("fill");
+  int* herr = static_cast<int*>(pinned(c, sizeof(int)));
+  GPS_HIP(hipMemcpyAsync(herr, c->err_flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  GPS_HIP(hipStreamSynchronize(c->stream));
+  if (*herr != 0) {
+    const int e = *herr;
+    destroy_matrix(c, m.release());
+    throw Error{GP_EDEVICE, "gp_assemble: count and fill passes disagree (code " + std::to_string(e) + ")"};
+  }
+  return m.release();
+}
+
+void destroy_matrix(gp_ctx* c, gp_matrix* m) {
+  if (!m) return;
+  const size_t vbytes = m->prec == GP_MIXED ? sizeof(float) : sizeof(double);
+  if (m->row_ptr) dev_free(c, m->row_ptr, sizeof(int64_t) * (m->n + 1));
+  if (m->col) dev_free(c, m->col, sizeof(int32_t) * std::max<int64_t>(m->nnz, 1));
+  if (m->val) dev_free(c, m->val, vbytes * std::max<int64_t>(m->nnz, 1));
+  if (m->diag) dev_free(c, m->diag, sizeof(double) * m->n);
+  if (m->long_rows) dev_free(c, m->long_rows, sizeof(int32_t) * std::max<int64_t>(m->n_long, 1));
+  delete m;
+}
+
+}  // namespace gps

@@ -1,0 +1,401 @@
+// C ABI entry points: validation, object lifetime, memory, and orchestration.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <limits>
+#include <memory>
+
+#include "internal.hpp"
+
+namespace gps {
+gp_predictor* make_predictor(gp_ctx* c, const gp_dataset* ds, const gp_theta* th, const double* alpha);
+void destroy_predictor(gp_ctx* c, gp_predictor* p);
+void predict(gp_ctx* c, const gp_predictor* p, int64_t m, const double* xs, int prec, double* out);
+
+// ------------------------------------------------------------------ memory
+void* dev_alloc(gp_ctx* c, size_t bytes) {
+  if (bytes == 0) bytes = 16;
+  void* p = nullptr;
+  if (c->alloc) {
+    p = c->alloc(bytes, c->user);
+  } else {
+    if (hipMallocAsync(&p, bytes, c->stream) != hipSuccess) {
+      (void)hipGetLastError();
+      p = nullptr;
+    }
+  }
+  if (!p) throw Error{GP_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed"};
+  c->in_use += bytes;
+  c->peak = std::max(c->peak, c->in_use);
+  return p;
+}
+
+void dev_free(gp_ctx* c, void* p, size_t bytes) {
+  if (!p) return;
+  if (bytes == 0) bytes = 16;
+  if (c->free_fn)
+    c->free_fn(p, bytes, c->user);
+  else
+    (void)hipFreeAsync(p, c->stream);
+  c->in_use -= std::min(c->in_use, bytes);
+}
+
+void* workspace(gp_ctx* c, int slot, size_t bytes) {
+  if (static_cast<size_t>(slot) >= c->slots.size()) c->slots.resize(slot + 1);
+  gp_ctx::Slot& s = c->slots[slot];
+  if (s.bytes < bytes || !s.ptr) {
+    if (s.ptr) dev_free(c, s.ptr, s.bytes);
+    s.ptr = nullptr;
+    const size_t want = std::max<size_t>(bytes + bytes / 4, 256);
+    s.ptr = dev_alloc(c, want);
+    s.bytes = want;
+  }
+  return s.ptr;
+}
+
+void* pinned(gp_ctx* c, size_t bytes) {
+  if (bytes > c->pinned_bytes) {
+    // earlier asynchronous copies may still use the old buffer
+    GPS_HIP(hipStreamSynchronize(c->stream));
+    if (c->pinned) (void)hipHostFree(c->pinned);
+    c->pinned = nullptr;
+    const size_t want = std::max<size_t>(bytes, 1 << 20);
+    GPS_HIP(hipHostMalloc(&c->pinned, want, hipHostMallocDefault));
+    c->pinned_bytes = want;
+  }
+  return c->pinned;
+}
+
+void sync(gp_ctx* c) { GPS_HIP(hipStreamSynchronize(c->stream)); }
+
+}  // namespace gps
+
+using gps::Error;
+
+namespace {
+
+template <typename F>
+gp_status guarded(gp_ctx* c, F&& f) {
+  try {
+    if (c) {
+      c->err.clear();
+      GPS_HIP(hipSetDevice(c->device));
+    }
+    f();
+    return GP_OK;
+  } catch (const Error& e) {
+    if (c) c->err = e.msg;
+    return e.st;
+  } catch (const std::bad_alloc&) {
+    if (c) c->err = "host allocation failed";
+    return GP_ENOMEM;
+  } catch (...) {
+    if (c) c->err = "unexpected internal error";
+    return GP_EDEVICE;
+  }
+}
+
+void validate_theta(const gp_theta* th, int d) {
+  GPS_REQUIRE(th != nullptr, GP_EINVAL, "theta is NULL");
+  GPS_REQUIRE(th->d == d, GP_EINVAL, "theta.d does not match the dataset");
+  GPS_REQUIRE(th->n1 >= 0 && th->n1 <= gps::kMaxGroups, GP_EINVAL, "theta.n1 must be in 0..64");
+  GPS_REQUIRE(th->n2 >= 0 && static_cast<int64_t>(th->n1) * th->n2 <= gps::kMaxBumps, GP_EINVAL,
+              "theta.n1 * theta.n2 must be <= 4096");
+  GPS_REQUIRE(th->wendland_variant == 0 || th->wendland_variant == 1, GP_EINVAL, "wendland_variant must be 0 or 1");
+  GPS_REQUIRE(std::isfinite(th->s0) && th->s0 > 0, GP_EINVAL, "s0 must be finite and > 0");
+  GPS_REQUIRE(std::isfinite(th->nugget) && th->nugget >= 0, GP_EINVAL, "nugget must be finite and >= 0");
+  for (int k = 0; k < d; ++k)
+    GPS_REQUIRE(std::isfinite(th->r0[k]) && th->r0[k] > 0, GP_EINVAL, "r0 must be finite and > 0");
+  const int nb = th->n1 * th->n2;
+  if (nb > 0) {
+    GPS_REQUIRE(th->h && th->r && th->a && th->b, GP_EINVAL, "bump arrays must not be NULL");
+    for (int i = 0; i < nb * d; ++i) {
+      GPS_REQUIRE(std::isfinite(th->h[i]), GP_EINVAL, "bump centres must be finite");
+      GPS_REQUIRE(th->r[i] > 0 && !std::isnan(th->r[i]), GP_EINVAL, "bump radii must be > 0 (+inf allowed)");
+    }
+    for (int i = 0; i < nb; ++i) {
+      GPS_REQUIRE(std::isfinite(th->a[i]) && th->a[i] >= 0, GP_EINVAL, "bump amplitudes must be finite and >= 0");
+      GPS_REQUIRE(std::isfinite(th->b[i]) && th->b[i] > 0, GP_EINVAL, "bump shapes must be finite and > 0");
+    }
+  }
+}
+
+gp_solve_opts fill_opts(const gp_solve_opts* o) {
+  gp_solve_opts d;
+  gp_solve_opts_default(&d);
+  if (!o) return d;
+  gp_solve_opts r = *o;
+  GPS_REQUIRE(std::isfinite(r.rtol) && r.rtol > 0 && r.rtol < 1, GP_EINVAL, "rtol must be in (0, 1)");
+  GPS_REQUIRE(r.max_iter >= 1, GP_EINVAL, "max_iter must be >= 1");
+  GPS_REQUIRE(r.n_probes >= 2 && r.n_probes <= 64, GP_EINVAL, "n_probes must be in 2..64");
+  GPS_REQUIRE(r.n_lanczos >= 1 && r.n_lanczos <= 128, GP_EINVAL, "n_lanczos must be in 1..128");
+  GPS_REQUIRE(r.logdet_mode >= 0 && r.logdet_mode <= 2, GP_EINVAL, "logdet_mode must be 0, 1 or 2");
+  return r;
+}
+
+}  // namespace
+
+extern "C" {
+
+void gp_solve_opts_default(gp_solve_opts* o) {
+  if (!o) return;
+  o->rtol = 1e-10;
+  o->max_iter = 10000;
+  o->n_probes = 30;
+  o->n_lanczos = 50;
+  o->logdet_mode = GP_LOGDET_SLQ;
+  o->seed = 0x5eed;
+}
+
+gp_status gp_ctx_create(int device, void* stream, gp_alloc_fn alloc, gp_free_fn free_fn, void* user, gp_ctx** out) {
+  if (!out) return GP_EINVAL;
+  *out = nullptr;
+  if ((alloc == nullptr) != (free_fn == nullptr)) return GP_EINVAL;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return GP_EINVAL;
+  std::unique_ptr<gp_ctx> c(new gp_ctx());
+  c->device = device;
+  c->stream = static_cast<hipStream_t>(stream);
+  c->alloc = alloc;
+  c->free_fn = free_fn;
+  c->user = user;
+  gp_status st = guarded(c.get(), [&] {
+    if (!alloc) {
+      hipMemPool_t pool;
+      if (hipDeviceGetDefaultMemPool(&pool, device) == hipSuccess) {
+        uint64_t thr = std::numeric_limits<uint64_t>::max();
+        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+      }
+    }
+    c->err_flag = static_cast<int*>(gps::dev_alloc(c.get(), sizeof(int) * 4));
+    gps::pinned(c.get(), 1 << 20);
+  });
+  if (st != GP_OK) return st;
+  *out = c.release();
+  return GP_OK;
+}
+
+gp_status gp_ctx_destroy(gp_ctx* c) {
+  if (!c) return GP_OK;
+  gp_status st = guarded(c, [&] {
+    for (auto& s : c->slots)
+      if (s.ptr) gps::dev_free(c, s.ptr, s.bytes);
+    c->slots.clear();
+    if (c->err_flag) gps::dev_free(c, c->err_flag, sizeof(int) * 4);
+    c->err_flag = nullptr;
+    GPS_HIP(hipStreamSynchronize(c->stream));
+    if (c->pinned) (void)hipHostFree(c->pinned);
+    c->pinned = nullptr;
+  });
+  delete c;
+  return st;
+}
+
+gp_status gp_ctx_set_stream(gp_ctx* c, void* stream) {
+  if (!c) return GP_EINVAL;
+  return guarded(c, [&] {
+    GPS_HIP(hipStreamSynchronize(c->stream));
+    c->stream = static_cast<hipStream_t>(stream);
+  });
+}
+
+const char* gp_last_error(const gp_ctx* c) { return c ? c->err.c_str() : "context is NULL"; }
+
+gp_status gp_ctx_memory(const gp_ctx* c, size_t* in_use, size_t* peak) {
+  if (!c) return GP_EINVAL;
+  if (in_use) *in_use = c->in_use;
+  if (peak) *peak = c->peak;
+  return GP_OK;
+}
+
+gp_status gp_dataset_create(gp_ctx* c, int64_t n, int32_t d, const double* x_dev, const double* cell,
+                            gp_dataset** out) {
+  if (!c || !out) return GP_EINVAL;
+  *out = nullptr;
+  return guarded(c, [&] {
+    GPS_REQUIRE(n >= 1 && n < (int64_t(1) << 31) - 1, GP_EINVAL, "gp_dataset_create: n must be in 1..2^31-2");
+    GPS_REQUIRE(d >= 1 && d <= 3, GP_EINVAL, "gp_dataset_create: d must be 1, 2 or 3");
+    GPS_REQUIRE(x_dev != nullptr, GP_EINVAL, "gp_dataset_create: x is NULL");
+    std::unique_ptr<gp_dataset> ds(new gp_dataset());
+    ds->n = n;
+    ds->d = d;
+    try {
+      gps::bin_dataset(c, ds.get(), x_dev, cell);
+    } catch (...) {
+      gps::dev_free(c, ds->xb, sizeof(double) * d * n);
+      gps::dev_free(c, ds->perm, sizeof(int32_t) * n);
+      gps::dev_free(c, ds->iperm, sizeof(int32_t) * n);
+      gps::dev_free(c, ds->key, sizeof(int32_t) * n);
+      gps::dev_free(c, ds->cell_start, sizeof(int32_t) * (ds->ncells + 1));
+      throw;
+    }
+    *out = ds.release();
+  });
+}
+
+gp_status gp_dataset_destroy(gp_ctx* c, gp_dataset* ds) {
+  if (!c) return GP_EINVAL;
+  if (!ds) return GP_OK;
+  gp_status st = guarded(c, [&] {
+    const int64_t n = ds->n;
+    gps::dev_free(c, ds->xb, sizeof(double) * ds->d * n);
+    gps::dev_free(c, ds->perm, sizeof(int32_t) * n);
+    gps::dev_free(c, ds->iperm, sizeof(int32_t) * n);
+    gps::dev_free(c, ds->key, sizeof(int32_t) * n);
+    gps::dev_free(c, ds->cell_start, sizeof(int32_t) * (ds->ncells + 1));
+  });
+  delete ds;
+  return st;
+}
+
+gp_status gp_dataset_info(const gp_dataset* ds, int64_t* n, int32_t* d, int64_t* n_cells, double* cell_out) {
+  if (!ds) return GP_EINVAL;
+  if (n) *n = ds->n;
+  if (d) *d = ds->d;
+  if (n_cells) *n_cells = ds->ncells;
+  if (cell_out)
+    for (int k = 0; k < ds->d; ++k) cell_out[k] = ds->cell[k];
+  return GP_OK;
+}
+
+gp_status gp_dataset_permutation(gp_ctx* c, const gp_dataset* ds, int32_t* perm_dev) {
+  if (!c || !ds || !perm_dev) return GP_EINVAL;
+  return guarded(c, [&] {
+    GPS_HIP(hipMemcpyAsync(perm_dev, ds->perm, sizeof(int32_t) * ds->n, hipMemcpyDeviceToDevice, c->stream));
+    GPS_HIP(hipStreamSynchronize(c->stream));
+  });
+}
+
+gp_status gp_assemble(gp_ctx* c, const gp_dataset* ds, const gp_theta* th, gp_precision prec, gp_matrix** out) {
+  if (!c || !out) return GP_EINVAL;
+  *out = nullptr;
+  return guarded(c, [&] {
+    GPS_REQUIRE(ds != nullptr, GP_EINVAL, "gp_assemble: dataset is NULL");
+    GPS_REQUIRE(prec == GP_FP64 || prec == GP_MIXED, GP_EINVAL, "gp_assemble: unknown precision");
+    validate_theta(th, ds->d);
+    *out = gps::assemble(c, ds, th, prec);
+  });
+}
+
+gp_status gp_matrix_destroy(gp_ctx* c, gp_matrix* m) {
+  if (!c) return GP_EINVAL;
+  if (!m) return GP_OK;
+  return guarded(c, [&] { gps::destroy_matrix(c, m); });
+}
+
+gp_status gp_matrix_info(const gp_matrix* m, int64_t* n, int64_t* nnz, size_t* bytes, int32_t* prec,
+                         int64_t* max_row) {
+  if (!m) return GP_EINVAL;
+  if (n) *n = m->n;
+  if (nnz) *nnz = m->nnz;
+  if (bytes) *bytes = m->bytes;
+  if (prec) *prec = m->prec;
+  if (max_row) *max_row = m->max_row;
+  return GP_OK;
+}
+
+gp_status gp_matrix_export_csr(gp_ctx* c, const gp_matrix* m, int64_t* row_ptr, int32_t* col, double* val) {
+  if (!c || !m || !row_ptr || !col || !val) return GP_EINVAL;
+  return guarded(c, [&] { gps::export_csr(c, m, row_ptr, col, val); });
+}
+
+gp_status gp_matvec(gp_ctx* c, const gp_matrix* m, int32_t nrhs, const double* x, double* y) {
+  if (!c || !m || !x || !y) return GP_EINVAL;
+  return guarded(c, [&] {
+    GPS_REQUIRE(nrhs >= 1 && nrhs <= 32, GP_EINVAL, "gp_matvec: nrhs must be in 1..32");
+    const int64_t n = m->n;
+    double* xb = static_cast<double*>(gps::workspace(c, 42, sizeof(double) * n * nrhs));
+    double* yb = static_cast<double*>(gps::workspace(c, 43, sizeof(double) * n * nrhs));
+    gps::permute_to_binned<double>(c, m->ds, nrhs, x, xb);
+    if (nrhs == 1)
+      gps::spmv_f64(c, m, xb, yb);
+    else
+      gps::spmm<double>(c, m, nrhs, nrhs, xb, yb, nullptr);
+    gps::permute_to_orig<double>(c, m->ds, nrhs, yb, y);
+    GPS_HIP(hipStreamSynchronize(c->stream));
+  });
+}
+
+static gp_status loglik_common(gp_ctx* c, const gp_matrix* m, const double* y, const gp_solve_opts* opts,
+                               double* alpha, gp_loglik_result* out, bool with_logdet) {
+  if (!c || !m || !y || !out) return GP_EINVAL;
+  std::memset(out, 0, sizeof(*out));
+  gp_status solve_status = GP_OK;
+  gp_status st = guarded(c, [&] {
+    const gp_solve_opts o = fill_opts(opts);
+    const int64_t n = m->n;
+    double* yb = static_cast<double*>(gps::workspace(c, 44, sizeof(double) * n));
+    double* xb = static_cast<double*>(gps::workspace(c, 45, sizeof(double) * n));
+    gps::permute_to_binned<double>(c, m->ds, 1, y, yb);
+    const gps::SolveResult sr = gps::pcg_solve(c, m, yb, xb, o.rtol, o.max_iter);
+    out->quad = sr.quad;
+    out->relres = sr.relres;
+    out->cg_iters = sr.iters;
+    out->refreshes = sr.refreshes;
+    GPS_REQUIRE(std::isfinite(sr.quad), GP_EINVAL, "y holds non-finite values");
+    solve_status = sr.st;
+    if (alpha) gps::permute_to_orig<double>(c, m->ds, 1, xb, alpha);
+    if (with_logdet && o.logdet_mode != GP_LOGDET_NONE) {
+      const gps::LogdetResult lr = o.logdet_mode == GP_LOGDET_EXACT
+                                       ? gps::exact_logdet(c, m, o.seed)
+                                       : gps::slq_logdet(c, m, o.seed, o.n_probes, o.n_lanczos);
+      out->logdet = lr.logdet;
+      out->logdet_se = lr.se;
+      out->lanczos_steps = lr.steps;
+      if (solve_status == GP_OK) solve_status = lr.st;
+    }
+    out->loglik = -0.5 * out->logdet - 0.5 * out->quad - 0.5 * static_cast<double>(n) * std::log(2.0 * M_PI);
+    GPS_HIP(hipStreamSynchronize(c->stream));
+  });
+  if (st != GP_OK) {
+    out->status = st;
+    return st;
+  }
+  out->status = solve_status;
+  if (solve_status != GP_OK) {
+    c->err = solve_status == GP_ENOTCONV ? "conjugate gradients did not reach rtol within max_iter"
+                                         : "non-positive curvature: matrix not positive definite";
+  }
+  return solve_status;
+}
+
+gp_status gp_loglik(gp_ctx* c, const gp_matrix* m, const double* y, const gp_solve_opts* opts, double* alpha,
+                    gp_loglik_result* out) {
+  return loglik_common(c, m, y, opts, alpha, out, true);
+}
+
+gp_status gp_solve(gp_ctx* c, const gp_matrix* m, const double* y, const gp_solve_opts* opts, double* alpha,
+                   gp_loglik_result* out) {
+  return loglik_common(c, m, y, opts, alpha, out, false);
+}
+
+gp_status gp_predictor_create(gp_ctx* c, const gp_dataset* train, const gp_theta* th, const double* alpha,
+                              gp_predictor** out) {
+  if (!c || !out) return GP_EINVAL;
+  *out = nullptr;
+  return guarded(c, [&] {
+    GPS_REQUIRE(train && alpha, GP_EINVAL, "gp_predictor_create: NULL argument");
+    validate_theta(th, train->d);
+    *out = gps::make_predictor(c, train, th, alpha);
+  });
+}
+
+gp_status gp_predictor_destroy(gp_ctx* c, gp_predictor* p) {
+  if (!c) return GP_EINVAL;
+  if (!p) return GP_OK;
+  return guarded(c, [&] { gps::destroy_predictor(c, p); });
+}
+
+gp_status gp_predict(gp_ctx* c, const gp_predictor* p, int64_t m, const double* xs, gp_precision prec,
+                     double* mean) {
+  if (!c || !p) return GP_EINVAL;
+  return guarded(c, [&] {
+    GPS_REQUIRE(m >= 0, GP_EINVAL, "gp_predict: m must be >= 0");
+    GPS_REQUIRE(m == 0 || (xs && mean), GP_EINVAL, "gp_predict: NULL buffer");
+    GPS_REQUIRE(prec == GP_FP64 || prec == GP_MIXED, GP_EINVAL, "gp_predict: unknown precision");
+    gps::predict(c, p, m, xs, prec, mean);
+    GPS_HIP(hipStreamSynchronize(c->stream));
+  });
+}
+
+}  // extern "C"

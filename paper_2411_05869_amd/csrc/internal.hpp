@@ -1,0 +1,219 @@
+// Internal declarations of the gpsparse library (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/gpsparse.h"
+
+namespace gps {
+
+constexpr int kWave = 64;
+constexpr int kMaxGroups = 64;      // n1 <= 64: group membership is one uint64 per point
+constexpr int kMaxBumps = 4096;     // n1 * n2
+constexpr int kLongRow = 128;       // rows longer than this get a wave of their own in SpMV
+
+// ------------------------------------------------------------------ errors
+struct Error {
+  gp_status st;
+  std::string msg;
+};
+
+#define GPS_HIP(expr)                                                                    \
+  do {                                                                                   \
+    hipError_t e_ = (expr);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      throw ::gps::Error{GP_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)}; \
+  } while (0)
+
+#define GPS_REQUIRE(cond, code, text)                 \
+  do {                                                \
+    if (!(cond)) throw ::gps::Error{(code), (text)};  \
+  } while (0)
+
+inline void check_launch(const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) throw Error{GP_EDEVICE, std::string(what) + ": " + hipGetErrorString(e)};
+}
+
+inline unsigned grid_for(int64_t items, int per_block) {
+  int64_t g = (items + per_block - 1) / per_block;
+  return static_cast<unsigned>(g < 1 ? 1 : g);
+}
+
+}  // namespace gps
+
+// ---------------------------------------------------------------- objects
+struct gp_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  gp_alloc_fn alloc = nullptr;
+  gp_free_fn free_fn = nullptr;
+  void* user = nullptr;
+  std::string err;
+  size_t in_use = 0, peak = 0;
+  // growable workspace slots, reused across calls on this context
+  struct Slot {
+    void* ptr = nullptr;
+    size_t bytes = 0;
+  };
+  std::vector<Slot> slots;
+  // pinned host staging for small device->host reads
+  void* pinned = nullptr;
+  size_t pinned_bytes = 0;
+  int* err_flag = nullptr;  // device int, set by kernels on consistency failures
+};
+
+struct gp_dataset {
+  int64_t n = 0;
+  int d = 0;
+  double lo[3] = {0, 0, 0};
+  double cell[3] = {1, 1, 1};
+  int32_t g[3] = {1, 1, 1};
+  int64_t ncells = 1;
+  double* xb = nullptr;         // d x n SoA, binned order
+  int32_t* perm = nullptr;      // binned -> original
+  int32_t* iperm = nullptr;     // original -> binned
+  int32_t* key = nullptr;       // cell key of each binned point
+  int32_t* cell_start = nullptr;// ncells + 1
+  int32_t max_cell = 0;         // most points in one cell
+  size_t bytes = 0;
+};
+
+struct gp_matrix {
+  const gp_dataset* ds = nullptr;
+  int64_t n = 0, nnz = 0, max_row = 0;
+  int prec = GP_FP64;
+  double nugget = 0;
+  int64_t* row_ptr = nullptr;   // n + 1
+  int32_t* col = nullptr;       // nnz, binned column ids, ascending per row
+  void* val = nullptr;          // nnz float or double
+  double* diag = nullptr;       // n, diagonal of the stored matrix (float64)
+  int32_t* long_rows = nullptr; // rows with more than kLongRow entries
+  int64_t n_long = 0;
+  size_t bytes = 0;
+};
+
+namespace gps {
+
+// bump parameters as laid out for the kernels (64 bytes each)
+struct Bump {
+  double h[3];
+  double inv[3];
+  double a, b;
+};
+
+struct Grid {
+  double lo[3];
+  double inv_cell[3];   // unused by decisions on pattern membership
+  double cell[3];
+  int32_t g[3];
+  int32_t R[3];         // neighbour rings per coordinate
+};
+
+// Per-theta point features (binned order).
+struct Features {
+  uint64_t* mask = nullptr;  // n
+  int32_t* midx = nullptr;   // n, compact index of masked points or -1
+  int32_t* mlist = nullptr;  // nm, binned ids of masked points (ascending)
+  uint64_t* mmask = nullptr; // nm, their masks
+  double* F = nullptr;       // nm x n1 values f_i
+  int64_t nm = 0;
+};
+
+struct KernelTheta {
+  int d, n1, n2, variant;
+  double s0, nugget;
+  double inv0[3];
+  const Bump* bumps;  // device, n1*n2
+};
+
+// -------------------------------------------------------------- memory
+void* dev_alloc(gp_ctx* c, size_t bytes);
+void dev_free(gp_ctx* c, void* p, size_t bytes);
+void* workspace(gp_ctx* c, int slot, size_t bytes);   // grows, never shrinks
+void* pinned(gp_ctx* c, size_t bytes);
+void sync(gp_ctx* c);
+
+template <typename T>
+T* dev_new(gp_ctx* c, size_t count) {
+  return static_cast<T*>(dev_alloc(c, count * sizeof(T) > 0 ? count * sizeof(T) : 16));
+}
+
+// RAII holder for temporaries allocated from the context
+struct TmpBuf {
+  gp_ctx* c = nullptr;
+  void* p = nullptr;
+  size_t bytes = 0;
+  TmpBuf() = default;
+  TmpBuf(gp_ctx* c_, size_t b) : c(c_), p(dev_alloc(c_, b ? b : 16)), bytes(b ? b : 16) {}
+  ~TmpBuf() {
+    if (p) dev_free(c, p, bytes);
+  }
+  TmpBuf(const TmpBuf&) = delete;
+  TmpBuf& operator=(const TmpBuf&) = delete;
+  TmpBuf(TmpBuf&& o) noexcept : c(o.c), p(o.p), bytes(o.bytes) { o.p = nullptr; }
+  template <typename T>
+  T* as() const {
+    return static_cast<T*>(p);
+  }
+};
+
+// -------------------------------------------------------------- scan
+// out[i] = sum_{j<i} in[j] for i in [0, n]; out[n] = total.  Deterministic.
+void scan_i32_to_i64(gp_ctx* c, const int32_t* in, int64_t* out, int64_t n);
+void scan_i32_to_i32(gp_ctx* c, const int32_t* in, int32_t* out, int64_t n);
+int64_t read_i64(gp_ctx* c, const int64_t* dev);   // synchronising read
+
+// -------------------------------------------------------------- stages
+void bin_dataset(gp_ctx* c, gp_dataset* ds, const double* x_dev, const double* cell);
+void upload_theta(gp_ctx* c, const gp_theta* th, Bump** bumps_dev, KernelTheta* kt);
+void compute_features(gp_ctx* c, const gp_dataset* ds, const KernelTheta& kt, Features* f,
+                      int ws_base);
+Grid make_grid(const gp_dataset* ds, const gp_theta* th);
+gp_matrix* assemble(gp_ctx* c, const gp_dataset* ds, const gp_theta* th, int prec);
+void destroy_matrix(gp_ctx* c, gp_matrix* m);
+void export_csr(gp_ctx* c, const gp_matrix* m, int64_t* row_ptr, int32_t* col, double* val);
+
+// SpMV / SpMM in binned order.
+// y = K x (float64 x and y; float32 or float64 values; float64 accumulation)
+void spmv_f64(gp_ctx* c, const gp_matrix* m, const double* x, double* y);
+// y = K x entirely in float32 (mixed-precision inner products)
+void spmv_f32(gp_ctx* c, const gp_matrix* m, const float* x, float* y);
+// Y = S K S X for k columns, X/Y n x ld row-major (S = diag(scale) or identity if null)
+template <typename T>
+void spmm(gp_ctx* c, const gp_matrix* m, int k, int ld, const T* X, T* Y, const T* scale);
+
+// original <-> binned order for n x k row-major blocks
+template <typename T>
+void permute_to_binned(gp_ctx* c, const gp_dataset* ds, int k, const T* x, T* xb);
+template <typename T>
+void permute_to_orig(gp_ctx* c, const gp_dataset* ds, int k, const T* yb, T* y);
+
+// ----------------------------------------------------------- Krylov drivers
+struct SolveResult {
+  int iters = 0;
+  int refreshes = 0;
+  double relres = 0;
+  double quad = 0;
+  gp_status st = GP_OK;
+};
+// alpha = K^-1 y (binned order); Jacobi PCG, float64 or float32-product form.
+SolveResult pcg_solve(gp_ctx* c, const gp_matrix* m, const double* yb, double* xb, double rtol, int max_iter);
+
+struct LogdetResult {
+  double logdet = 0, se = 0;
+  int steps = 0;
+  gp_status st = GP_OK;
+};
+LogdetResult slq_logdet(gp_ctx* c, const gp_matrix* m, uint64_t seed, int n_probes, int n_steps);
+LogdetResult exact_logdet(gp_ctx* c, const gp_matrix* m, uint64_t seed);
+
+// deterministic reductions
+double dot_f64(gp_ctx* c, const double* a, const double* b, int64_t n);   // synchronising
+
+}  // namespace gps

@@ -1,0 +1,763 @@
+// Krylov drivers: Jacobi-preconditioned conjugate gradients for y^T K^-1 y,
+// stochastic Lanczos quadrature for log det K, and an exact Lanczos log-det
+// with full re-orthogonalisation for small n (Sec. 3.3: the log-determinant
+// and linear-solve tasks).
+//
+// Reductions are two-level with a fixed grid (kRedBlocks blocks, grid-stride)
+// and a fixed tree, so every scalar is bitwise reproducible.  Scalars stay in
+// device memory between kernels; the host reads them only at check points.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "device.hpp"
+
+namespace gps {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kRedBlocks = 512;
+constexpr int kCheckEvery = 8;
+
+// ---------------------------------------------------------------- reductions
+template <int NV>
+__device__ __forceinline__ void block_sum_store(double (&v)[NV], double* __restrict__ out) {
+  __shared__ double sh[NV][kThreads / kWave];
+  const int w = threadIdx.x / kWave;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    double x = v[i];
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) x += __shfl_xor(x, off, kWave);
+    if (lane_id() == 0) sh[i][w] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x < NV) {
+    double s = 0;
+#pragma unroll
+    for (int j = 0; j < kThreads / kWave; ++j) s += sh[threadIdx.x][j];
+    out[blockIdx.x * NV + threadIdx.x] = s;
+  }
+}
+
+// Sums partials[b * NV + i] over b in a fixed order; result in thread i's return.
+template <int NV>
+__device__ __forceinline__ void reduce_partials(const double* __restrict__ part, int nb, double* __restrict__ res) {
+  __shared__ double sh[NV][kThreads];
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    double s = 0;
+    for (int b = threadIdx.x; b < nb; b += kThreads) s += part[b * NV + i];
+    sh[i][threadIdx.x] = s;
+  }
+  __syncthreads();
+  for (int st = kThreads / 2; st > 0; st >>= 1) {
+    if (threadIdx.x < st)
+#pragma unroll
+      for (int i = 0; i < NV; ++i) sh[i][threadIdx.x] += sh[i][threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int i = 0; i < NV; ++i) res[i] = sh[i][0];
+  __syncthreads();
+}
+
+__global__ void __launch_bounds__(kThreads) k_dot_part(int64_t n, const double* __restrict__ a,
+                                                       const double* __restrict__ b, double* __restrict__ part) {
+  double v[1] = {0};
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * kThreads)
+    v[0] += a[i] * b[i];
+  block_sum_store<1>(v, part);
+}
+
+__global__ void __launch_bounds__(kThreads) k_sum_part(const double* __restrict__ part, int nb, double* __restrict__ out) {
+  double r[1];
+  reduce_partials<1>(part, nb, r);
+  if (threadIdx.x == 0) out[0] = r[0];
+}
+
+__global__ void __launch_bounds__(kThreads) k_logsum_part(int64_t n, const double* __restrict__ a,
+                                                          double* __restrict__ part) {
+  double v[1] = {0};
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * kThreads)
+    v[0] += log(a[i]);
+  block_sum_store<1>(v, part);
+}
+
+// ---------------------------------------------------------------- PCG
+struct CgScalars {
+  double rz, rz_old, pq, alpha, beta, rr, yy, pad;
+  int status;  // 0 ok, 1 non-positive curvature / non-finite
+};
+
+__global__ void __launch_bounds__(kThreads) k_pcg_init(int64_t n, const double* __restrict__ y,
+                                                       const double* __restrict__ diag, double* __restrict__ x,
+                                                       double* __restrict__ r, double* __restrict__ z,
+                                                       double* __restrict__ p, float* __restrict__ p32,
+                                                       double* __restrict__ part) {
+  double v[3] = {0, 0, 0};
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * kThreads) {
+    const double yi = y[i];
+    const double zi = yi / diag[i];
+    x[i] = 0.0;
+    r[i] = yi;
+    z[i] = zi;
+    p[i] = zi;
+    if (p32) p32[i] = static_cast<float>(zi);
+    v[0] += yi * zi;
+    v[1] += yi * yi;
+    v[2] += yi * yi;
+  }
+  block_sum_store<3>(v, part);
+}
+
+__global__ void __launch_bounds__(kThreads) k_pcg_init_fin(const double* __restrict__ part, int nb,
+                                                           CgScalars* __restrict__ s) {
+  double r[3];
+  reduce_partials<3>(part, nb, r);
+  if (threadIdx.x == 0) {
+    s->rz = r[0];
+    s->rr = r[1];
+    s->yy = r[2];
+    s->status = 0;
+  }
+}
+
+template <typename QT>
+__global__ void __launch_bounds__(kThreads) k_pq_part(int64_t n, const double* __restrict__ p,
+                                                      const QT* __restrict__ q, double* __restrict__ part) {
+  double v[1] = {0};
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * kThreads)
+    v[0] += p[i] * static_cast<double>(q[i]);
+  block_sum_store<1>(v, part);
+}
+
+__global__ void __launch_bounds__(kThreads) k_alpha_fin(const double* __restrict__ part, int nb,
+                                                        CgScalars* __restrict__ s) {
+  double r[1];
+  reduce_partials<1>(part, nb, r);
+  if (threadIdx.x == 0) {
+    const double pq = r[0];
+    s->pq = pq;
+    if (!(pq > 0.0) || !isfinite(pq)) {
+      s->status = 1;
+      s->alpha = 0.0;
+    } else {
+      s->alpha = s->rz / pq;
+    }
+  }
+}
+
+template <typename QT>
+__global__ void __launch_bounds__(kThreads) k_pcg_update(int64_t n, const CgScalars* __restrict__ s,
+                                                         const double* __restrict__ p, const QT* __restrict__ q,
+                                                         const double* __restrict__ diag, double* __restrict__ x,
+                                                         double* __restrict__ r, double* __restrict__ z,
+                                                         double* __restrict__ part) {
+  const double alpha = s->alpha;
+  double v[2] = {0, 0};
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * kThreads) {
+    x[i] += alpha * p[i];
+    const double ri = r[i] - alpha * static_cast<double>(q[i]);
+    const double zi = ri / diag[i];
+    r[i] = ri;
+    z[i] = zi;
+    v[0] += ri * zi;
+    v[1] += ri * ri;
+  }
+  block_sum_store<2>(v, part);
+}
+
+__global__ void __launch_bounds__(kThreads) k_beta_fin(const double* __restrict__ part, int nb,
+                                                       CgScalars* __restrict__ s, int replace) {
+  double r[2];
+  reduce_partials<2>(part, nb, r);
+  if (threadIdx.x == 0) {
+    if (!replace) s->rz_old = s->rz;   // after a residual replacement rz_old is kept
+    s->rz = r[0];
+    s->rr = r[1];
+    s->beta = r[0] / s->rz_old;
+    if (!isfinite(r[0]) || !isfinite(r[1])) s->status = 1;
+  }
+}
+
+__global__ void __launch_bounds__(kThreads) k_pcg_pupdate(int64_t n, const CgScalars* __restrict__ s,
+                                                          const double* __restrict__ z, double* __restrict__ p,
+                                                          float* __restrict__ p32) {
+  const double beta = s->beta;
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * kThreads) {
+    const double pi = z[i] + beta * p[i];
+    p[i] = pi;
+    if (p32) p32[i] = static_cast<float>(pi);
+  }
+}
+
+// r = y - Kx (Kx given), z = D^-1 r, partials of r.z and r.r
+__global__ void __launch_bounds__(kThreads) k_true_resid(int64_t n, const double* __restrict__ y,
+                                                         const double* __restrict__ kx, const double* __restrict__ diag,
+                                                         double* __restrict__ r, double* __restrict__ z,
+                                                         double* __restrict__ part) {
+  double v[2] = {0, 0};
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * kThreads) {
+    const double ri = y[i] - kx[i];
+    const double zi = ri / diag[i];
+    r[i] = ri;
+    z[i] = zi;
+    v[0] += ri * zi;
+    v[1] += ri * ri;
+  }
+  block_sum_store<2>(v, part);
+}
+
+// ---------------------------------------------------------------- Lanczos
+__device__ __forceinline__ uint64_t splitmix_mix(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// Probe entry for (seed, probe, original index): sign of the SplitMix64 output at
+// counter (probe << 40 | index) + 1 of the generator started at state seed.
+__device__ __forceinline__ double rademacher(uint64_t seed, uint64_t probe, uint64_t idx) {
+  const uint64_t k = ((probe << 40) | idx) + 1ull;
+  const uint64_t out = splitmix_mix(seed + k * 0x9E3779B97F4A7C15ull);
+  return (out >> 63) ? -1.0 : 1.0;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_lz_init(int64_t n, int k, int ld, int probe0, uint64_t seed,
+                                                      const int32_t* __restrict__ perm, T* __restrict__ V,
+                                                      T* __restrict__ Vprev, double inv_sqrt_n) {
+  const int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x;
+  if (i >= n * ld) return;
+  const int64_t p = i / ld;
+  const int l = static_cast<int>(i % ld);
+  T v = 0;
+  if (l < k) v = static_cast<T>(rademacher(seed, static_cast<uint64_t>(probe0 + l), static_cast<uint64_t>(perm[p])) * inv_sqrt_n);
+  V[i] = v;
+  Vprev[i] = 0;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_scale_vec(int64_t n, const double* __restrict__ diag,
+                                                        T* __restrict__ s) {
+  const int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x;
+  if (i < n) s[i] = static_cast<T>(1.0 / sqrt(diag[i]));
+}
+
+// W[:, l] -= beta_prev[l] * Vprev[:, l]; partial sums of V[:, l] . W[:, l] (float64)
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_lz_beta_dot(int64_t n, int ld, const double* __restrict__ beta_prev,
+                                                          const T* __restrict__ V, const T* __restrict__ Vprev,
+                                                          T* __restrict__ W, double* __restrict__ part) {
+  // thread layout: 32 columns x 8 row-lanes per block
+  const int l = threadIdx.x & 31;
+  const int rl = threadIdx.x >> 5;
+  const T bp = static_cast<T>(beta_prev[l]);
+  double acc = 0;
+  for (int64_t p = blockIdx.x * 8ll + rl; p < n; p += static_cast<int64_t>(gridDim.x) * 8) {
+    const int64_t i = p * ld + l;
+    const T w = W[i] - bp * Vprev[i];
+    W[i] = w;
+    acc += static_cast<double>(V[i]) * static_cast<double>(w);
+  }
+  __shared__ double sh[8][32];
+  sh[rl][l] = acc;
+  __syncthreads();
+  if (rl == 0) {
+    double s = 0;
+    for (int j = 0; j < 8; ++j) s += sh[j][l];
+    part[blockIdx.x * 32 + l] = s;
+  }
+}
+
+// W[:, l] -= alpha[l] * V[:, l]; partial sums of |W[:, l]|^2
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_lz_alpha_norm(int64_t n, int ld, const double* __restrict__ alpha,
+                                                            const T* __restrict__ V, T* __restrict__ W,
+                                                            double* __restrict__ part) {
+  const int l = threadIdx.x & 31;
+  const int rl = threadIdx.x >> 5;
+  const T a = static_cast<T>(alpha[l]);
+  double acc = 0;
+  for (int64_t p = blockIdx.x * 8ll + rl; p < n; p += static_cast<int64_t>(gridDim.x) * 8) {
+    const int64_t i = p * ld + l;
+    const T w = W[i] - a * V[i];
+    W[i] = w;
+    acc += static_cast<double>(w) * static_cast<double>(w);
+  }
+  __shared__ double sh[8][32];
+  sh[rl][l] = acc;
+  __syncthreads();
+  if (rl == 0) {
+    double s = 0;
+    for (int j = 0; j < 8; ++j) s += sh[j][l];
+    part[blockIdx.x * 32 + l] = s;
+  }
+}
+
+struct LzState {
+  double alpha[32];
+  double beta[32];       // beta of the current step (norm of W)
+  double beta_prev[32];  // used by the next step
+  int active[32];
+  int steps[32];
+};
+
+// mode 0: alpha; mode 1: beta + breakdown (j = step index, last = final step)
+__global__ void __launch_bounds__(kThreads) k_lz_fin(const double* __restrict__ part, int nb, int k, int mode, int j,
+                                                     int last, double tol, LzState* __restrict__ st,
+                                                     double* __restrict__ Ta, double* __restrict__ Tb) {
+  // 32 columns; each of 8 groups of 32 threads sums a strided subset, fixed order
+  __shared__ double sh[8][32];
+  const int l = threadIdx.x & 31;
+  const int g = threadIdx.x >> 5;
+  double s = 0;
+  for (int b = g; b < nb; b += 8) s += part[b * 32 + l];
+  sh[g][l] = s;
+  __syncthreads();
+  if (g == 0 && l < k) {
+    double t = 0;
+    for (int q = 0; q < 8; ++q) t += sh[q][l];
+    if (mode == 0) {
+      st->alpha[l] = t;
+      if (st->active[l]) Ta[j * 32 + l] = t;
+    } else {
+      const double beta = sqrt(t);
+      if (st->active[l]) {
+        if (last) {
+          st->steps[l] = j + 1;
+        } else if (!(beta > tol) || !isfinite(beta)) {
+          st->steps[l] = j + 1;
+          st->active[l] = 0;
+        } else {
+          Tb[j * 32 + l] = beta;
+        }
+      }
+      st->beta[l] = st->active[l] ? beta : 0.0;
+      st->beta_prev[l] = st->beta[l];
+    }
+  }
+}
+
+// Vprev <- W / beta (inactive probes: 0); the caller swaps V and Vprev afterwards
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_lz_next(int64_t n, int ld, const LzState* __restrict__ st,
+                                                      const T* __restrict__ W, T* __restrict__ Vnext) {
+  const int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x;
+  if (i >= n * ld) return;
+  const int l = static_cast<int>(i % ld);
+  const bool act = l < 32 && st->active[l];
+  Vnext[i] = act ? static_cast<T>(static_cast<double>(W[i]) / st->beta[l]) : T(0);
+}
+
+// Symmetric tridiagonal eigen-decomposition by implicit QR sweeps with
+// Wilkinson shifts (Givens rotations chasing the bulge), tracking only the
+// first row of the eigenvector matrix.  a: diagonal (-> eigenvalues),
+// b: off-diagonal (destroyed), q: first row of the eigenvector matrix.
+__device__ bool tridiag_eig_first_row(double* a, double* b, double* q, int m) {
+  for (int i = 0; i < m; ++i) q[i] = i == 0 ? 1.0 : 0.0;
+  const double eps = 2.220446049250313e-16;
+  int hi = m - 1;
+  int iters = 0;
+  while (hi > 0) {
+    if (fabs(b[hi - 1]) <= eps * (fabs(a[hi - 1]) + fabs(a[hi]))) {
+      b[hi - 1] = 0.0;
+      --hi;
+      continue;
+    }
+    if (++iters > 60 * m) return false;
+    int lo = hi - 1;
+    while (lo > 0 && fabs(b[lo - 1]) > eps * (fabs(a[lo - 1]) + fabs(a[lo]))) --lo;
+    const double dlt = 0.5 * (a[hi - 1] - a[hi]);
+    const double bb = b[hi - 1];
+    const double den = dlt + copysign(hypot(dlt, bb), dlt == 0.0 ? 1.0 : dlt);
+    const double mu = a[hi] - bb * bb / den;
+    double x = a[lo] - mu;
+    double z = b[lo];
+    for (int k = lo; k < hi; ++k) {
+      const double r = hypot(x, z);
+      double c = 1.0, s = 0.0;
+      if (r != 0.0) {
+        c = x / r;
+        s = z / r;
+      }
+      if (k > lo) b[k - 1] = r;
+      const double ak = a[k], ak1 = a[k + 1], bk = b[k];
+      a[k] = c * c * ak + 2.0 * c * s * bk + s * s * ak1;
+      a[k + 1] = s * s * ak - 2.0 * c * s * bk + c * c * ak1;
+      b[k] = c * s * (ak1 - ak) + (c * c - s * s) * bk;
+      const double qk = q[k], qk1 = q[k + 1];
+      q[k] = c * qk + s * qk1;
+      q[k + 1] = -s * qk + c * qk1;
+      if (k + 1 < hi) {
+        x = b[k];
+        z = s * b[k + 1];
+        b[k + 1] = c * b[k + 1];
+      }
+    }
+  }
+  return true;
+}
+
+// One thread per probe: Gamma_l = |z|^2 sum_t tau_t^2 log theta_t.
+__global__ void k_quadrature(int k, const double* __restrict__ Ta, const double* __restrict__ Tb,
+                             const LzState* __restrict__ st, double znorm2, double* __restrict__ gam,
+                             int* __restrict__ bad) {
+  const int l = threadIdx.x;
+  if (l >= k) return;
+  double a[128], b[128], q[128];
+  const int m = st->steps[l];
+  for (int j = 0; j < m; ++j) {
+    a[j] = Ta[j * 32 + l];
+    b[j] = j + 1 < m ? Tb[j * 32 + l] : 0.0;
+  }
+  double g = 0;
+  if (!tridiag_eig_first_row(a, b, q, m)) {
+    atomicOr(bad, 1);
+  } else {
+    for (int t = 0; t < m; ++t) {
+      if (!(a[t] > 0.0)) atomicOr(bad, 2);
+      g += q[t] * q[t] * log(a[t]);
+    }
+  }
+  gam[l] = znorm2 * g;
+}
+
+// ------------------------------------------------------------- exact mode
+__global__ void __launch_bounds__(kThreads) k_gemv_t(int64_t n, int nv, const double* __restrict__ V,
+                                                     const double* __restrict__ w, double* __restrict__ h) {
+  // one block per basis vector
+  const int i = blockIdx.x;
+  if (i >= nv) return;
+  double v[1] = {0};
+  const double* vi = V + static_cast<int64_t>(i) * n;
+  for (int64_t p = threadIdx.x; p < n; p += kThreads) v[0] += vi[p] * w[p];
+  __shared__ double sh[kThreads / kWave];
+  double x = v[0];
+  for (int off = kWave / 2; off > 0; off >>= 1) x += __shfl_xor(x, off, kWave);
+  if (lane_id() == 0) sh[threadIdx.x / kWave] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0;
+    for (int j = 0; j < kThreads / kWave; ++j) s += sh[j];
+    h[i] = s;
+  }
+}
+
+__global__ void __launch_bounds__(kThreads) k_gemv_n_sub(int64_t n, int nv, const double* __restrict__ V,
+                                                         const double* __restrict__ h, double* __restrict__ w) {
+  const int64_t p = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x;
+  if (p >= n) return;
+  double s = 0;
+  for (int i = 0; i < nv; ++i) s += V[static_cast<int64_t>(i) * n + p] * h[i];
+  w[p] -= s;
+}
+
+__global__ void __launch_bounds__(kThreads) k_axpby2(int64_t n, double a, const double* __restrict__ x, double b,
+                                                     const double* __restrict__ y, double* __restrict__ w) {
+  const int64_t p = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x;
+  if (p < n) w[p] = w[p] - a * x[p] - b * y[p];
+}
+
+__global__ void __launch_bounds__(kThreads) k_scale_into(int64_t n, double s, const double* __restrict__ x,
+                                                         double* __restrict__ y) {
+  const int64_t p = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x;
+  if (p < n) y[p] = s * x[p];
+}
+
+__global__ void __launch_bounds__(kThreads) k_probe_vec(int64_t n, uint64_t seed, uint64_t probe,
+                                                        const int32_t* __restrict__ perm, double* __restrict__ v) {
+  const int64_t p = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x;
+  if (p < n) v[p] = rademacher(seed, probe, static_cast<uint64_t>(perm[p]));
+}
+
+}  // namespace
+
+// ================================================================== host
+
+double dot_f64(gp_ctx* c, const double* a, const double* b, int64_t n) {
+  double* part = static_cast<double*>(workspace(c, 40, sizeof(double) * kRedBlocks));
+  double* out = static_cast<double*>(workspace(c, 41, sizeof(double) * 2));
+  hipLaunchKernelGGL(k_dot_part, dim3(kRedBlocks), dim3(kThreads), 0, c->stream, n, a, b, part);
+  hipLaunchKernelGGL(k_sum_part, dim3(1), dim3(kThreads), 0, c->stream, part, kRedBlocks, out);
+  check_launch("dot");
+  double* h = static_cast<double*>(pinned(c, sizeof(double)));
+  GPS_HIP(hipMemcpyAsync(h, out, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  GPS_HIP(hipStreamSynchronize(c->stream));
+  return *h;
+}
+
+static double logsum_f64(gp_ctx* c, const double* a, int64_t n) {
+  double* part = static_cast<double*>(workspace(c, 40, sizeof(double) * kRedBlocks));
+  double* out = static_cast<double*>(workspace(c, 41, sizeof(double) * 2));
+  hipLaunchKernelGGL(k_logsum_part, dim3(kRedBlocks), dim3(kThreads), 0, c->stream, n, a, part);
+  hipLaunchKernelGGL(k_sum_part, dim3(1), dim3(kThreads), 0, c->stream, part, kRedBlocks, out);
+  check_launch("logsum");
+  double* h = static_cast<double*>(pinned(c, sizeof(double)));
+  GPS_HIP(hipMemcpyAsync(h, out, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  GPS_HIP(hipStreamSynchronize(c->stream));
+  return *h;
+}
+
+SolveResult pcg_solve(gp_ctx* c, const gp_matrix* m, const double* y, double* x, double rtol, int max_iter) {
+  const int64_t n = m->n;
+  const bool mixed = m->prec == GP_MIXED;
+  double* r = static_cast<double*>(workspace(c, 20, sizeof(double) * n));
+  double* z = static_cast<double*>(workspace(c, 21, sizeof(double) * n));
+  double* p = static_cast<double*>(workspace(c, 22, sizeof(double) * n));
+  double* q = static_cast<double*>(workspace(c, 23, sizeof(double) * n));
+  float* p32 = mixed ? static_cast<float*>(workspace(c, 24, sizeof(float) * n)) : nullptr;
+  float* q32 = mixed ? static_cast<float*>(workspace(c, 25, sizeof(float) * n)) : nullptr;
+  double* part = static_cast<double*>(workspace(c, 26, sizeof(double) * 4 * kRedBlocks));
+  CgScalars* s = static_cast<CgScalars*>(workspace(c, 27, sizeof(CgScalars)));
+  CgScalars* hs = static_cast<CgScalars*>(pinned(c, sizeof(CgScalars)));
+  const dim3 G(kRedBlocks), B(kThreads);
+  auto read = [&]() {
+    GPS_HIP(hipMemcpyAsync(hs, s, sizeof(CgScalars), hipMemcpyDeviceToHost, c->stream));
+    GPS_HIP(hipStreamSynchronize(c->stream));
+    return *hs;
+  };
+  auto true_residual = [&]() {
+    spmv_f64(c, m, x, q);
+    hipLaunchKernelGGL(k_true_resid, G, B, 0, c->stream, n, y, q, m->diag, r, z, part);
+    hipLaunchKernelGGL(k_beta_fin, dim3(1), B, 0, c->stream, part, kRedBlocks, s, 1);
+    check_launch("true residual");
+    return read();
+  };
+  hipLaunchKernelGGL(k_pcg_init, G, B, 0, c->stream, n, y, m->diag, x, r, z, p, p32, part);
+  hipLaunchKernelGGL(k_pcg_init_fin, dim3(1), B, 0, c->stream, part, kRedBlocks, s);
+  check_launch("pcg init");
+  CgScalars sc = read();
+  SolveResult res;
+  const double ynorm = std::sqrt(sc.yy);
+  if (ynorm == 0.0) {
+    res.relres = 0;
+    res.quad = 0;
+    return res;
+  }
+  const double target = rtol * ynorm;
+  double last_true = ynorm;   // |y - K x| at the latest recomputation
+  int it = 0;
+  bool converged = false;
+  while (it < max_iter && !converged) {
+    const int steps = std::min(kCheckEvery, max_iter - it);
+    for (int t = 0; t < steps; ++t) {
+      if (mixed) {
+        spmv_f32(c, m, p32, q32);
+        hipLaunchKernelGGL((k_pq_part<float>), G, B, 0, c->stream, n, p, q32, part);
+        hipLaunchKernelGGL(k_alpha_fin, dim3(1), B, 0, c->stream, part, kRedBlocks, s);
+        hipLaunchKernelGGL((k_pcg_update<float>), G, B, 0, c->stream, n, s, p, q32, m->diag, x, r, z, part);
+      } else {
+        spmv_f64(c, m, p, q);
+        hipLaunchKernelGGL((k_pq_part<double>), G, B, 0, c->stream, n, p, q, part);
+        hipLaunchKernelGGL(k_alpha_fin, dim3(1), B, 0, c->stream, part, kRedBlocks, s);
+        hipLaunchKernelGGL((k_pcg_update<double>), G, B, 0, c->stream, n, s, p, q, m->diag, x, r, z, part);
+      }
+      hipLaunchKernelGGL(k_beta_fin, dim3(1), B, 0, c->stream, part, kRedBlocks, s, 0);
+      if (t + 1 < steps) hipLaunchKernelGGL(k_pcg_pupdate, G, B, 0, c->stream, n, s, z, p, p32);
+      check_launch("pcg iteration");
+    }
+    it += steps;
+    sc = read();
+    if (sc.status != 0) {
+      res.st = GP_ENOTPD;
+      break;
+    }
+    const double rn = std::sqrt(sc.rr);
+    // residual replacement: at apparent convergence, or (float32 products) after the
+    // recursive residual fell by 10x since the last float64 recomputation
+    if (rn <= target || (mixed && rn <= 0.1 * last_true)) {
+      sc = true_residual();
+      ++res.refreshes;
+      last_true = std::sqrt(sc.rr);
+      if (last_true <= target) converged = true;
+    }
+    if (!converged && it < max_iter) {
+      hipLaunchKernelGGL(k_pcg_pupdate, G, B, 0, c->stream, n, s, z, p, p32);
+      check_launch("pcg direction");
+    }
+  }
+  res.iters = it;
+  if (!converged) {
+    sc = true_residual();
+    last_true = std::sqrt(sc.rr);
+    if (res.st == GP_OK) res.st = last_true <= target ? GP_OK : GP_ENOTCONV;
+  }
+  res.relres = last_true / ynorm;
+  res.quad = dot_f64(c, y, x, n);
+  return res;
+}
+
+template <typename T>
+static LogdetResult slq_impl(gp_ctx* c, const gp_matrix* m, uint64_t seed, int n_probes, int n_steps, double tol) {
+  const int64_t n = m->n;
+  const int ld = 32;
+  T* V = static_cast<T*>(workspace(c, 30, sizeof(T) * n * ld));
+  T* Vp = static_cast<T*>(workspace(c, 31, sizeof(T) * n * ld));
+  T* W = static_cast<T*>(workspace(c, 32, sizeof(T) * n * ld));
+  T* sc = static_cast<T*>(workspace(c, 33, sizeof(T) * n));
+  double* part = static_cast<double*>(workspace(c, 34, sizeof(double) * 32 * kRedBlocks));
+  LzState* st = static_cast<LzState*>(workspace(c, 35, sizeof(LzState)));
+  double* Ta = static_cast<double*>(workspace(c, 36, sizeof(double) * 32 * n_steps));
+  double* Tb = static_cast<double*>(workspace(c, 37, sizeof(double) * 32 * n_steps));
+  double* gam = static_cast<double*>(workspace(c, 38, sizeof(double) * 32));
+  int* bad = static_cast<int*>(workspace(c, 39, sizeof(int) * 2));
+  hipLaunchKernelGGL((k_scale_vec<T>), dim3(grid_for(n, kThreads)), dim3(kThreads), 0, c->stream, n, m->diag, sc);
+  check_launch("slq scale");
+  const double jac = logsum_f64(c, m->diag, n);
+  std::vector<double> gammas;
+  int max_steps = 0;
+  int nbad = 0;
+  for (int p0 = 0; p0 < n_probes; p0 += 32) {
+    const int k = std::min(32, n_probes - p0);
+    LzState init{};
+    for (int l = 0; l < 32; ++l) init.active[l] = l < k ? 1 : 0;
+    LzState* hst = static_cast<LzState*>(pinned(c, sizeof(LzState)));
+    *hst = init;
+    GPS_HIP(hipMemcpyAsync(st, hst, sizeof(LzState), hipMemcpyHostToDevice, c->stream));
+    GPS_HIP(hipMemsetAsync(bad, 0, sizeof(int), c->stream));
+    hipLaunchKernelGGL((k_lz_init<T>), dim3(grid_for(n * ld, kThreads)), dim3(kThreads), 0, c->stream, n, k, ld, p0,
+                       seed, m->ds->perm, V, Vp, 1.0 / std::sqrt(static_cast<double>(n)));
+    check_launch("lanczos init");
+    for (int j = 0; j < n_steps; ++j) {
+      const int last = j == n_steps - 1;
+      spmm<T>(c, m, ld, ld, V, W, sc);
+      hipLaunchKernelGGL((k_lz_beta_dot<T>), dim3(kRedBlocks), dim3(kThreads), 0, c->stream, n, ld, st->beta_prev, V,
+                         Vp, W, part);
+      hipLaunchKernelGGL(k_lz_fin, dim3(1), dim3(kThreads), 0, c->stream, part, kRedBlocks, k, 0, j, last, tol, st,
+                         Ta, Tb);
+      hipLaunchKernelGGL((k_lz_alpha_norm<T>), dim3(kRedBlocks), dim3(kThreads), 0, c->stream, n, ld, st->alpha, V, W,
+                         part);
+      hipLaunchKernelGGL(k_lz_fin, dim3(1), dim3(kThreads), 0, c->stream, part, kRedBlocks, k, 1, j, last, tol, st,
+                         Ta, Tb);
+      if (!last) {
+        hipLaunchKernelGGL((k_lz_next<T>), dim3(grid_for(n * ld, kThreads)), dim3(kThreads), 0, c->stream, n, ld, st,
+                           W, Vp);
+        std::swap(V, Vp);   // V <- new vector, Vp <- previous
+      }
+      check_launch("lanczos step");
+    }
+    hipLaunchKernelGGL(k_quadrature, dim3(1), dim3(64), 0, c->stream, k, Ta, Tb, st, static_cast<double>(n), gam,
+                       bad);
+    check_launch("quadrature");
+    double* hg = static_cast<double*>(pinned(c, sizeof(double) * 32 + sizeof(LzState) + 16));
+    GPS_HIP(hipMemcpyAsync(hg, gam, sizeof(double) * 32, hipMemcpyDeviceToHost, c->stream));
+    LzState* hs2 = reinterpret_cast<LzState*>(hg + 32);
+    GPS_HIP(hipMemcpyAsync(hs2, st, sizeof(LzState), hipMemcpyDeviceToHost, c->stream));
+    int* hb = reinterpret_cast<int*>(reinterpret_cast<char*>(hs2) + sizeof(LzState));
+    GPS_HIP(hipMemcpyAsync(hb, bad, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    GPS_HIP(hipStreamSynchronize(c->stream));
+    for (int l = 0; l < k; ++l) {
+      gammas.push_back(hg[l]);
+      max_steps = std::max(max_steps, hs2->steps[l]);
+    }
+    nbad |= *hb;
+  }
+  LogdetResult res;
+  double mean = 0;
+  for (double g : gammas) mean += g;
+  mean /= static_cast<double>(gammas.size());
+  double var = 0;
+  for (double g : gammas) var += (g - mean) * (g - mean);
+  res.se = gammas.size() > 1 ? std::sqrt(var / static_cast<double>(gammas.size() - 1) / gammas.size()) : 0.0;
+  res.logdet = jac + mean;
+  res.steps = max_steps;
+  if (nbad & 2) res.st = GP_ENOTPD;
+  if (nbad & 1) res.st = GP_EDEVICE;
+  return res;
+}
+
+LogdetResult slq_logdet(gp_ctx* c, const gp_matrix* m, uint64_t seed, int n_probes, int n_steps) {
+  if (m->prec == GP_MIXED) return slq_impl<float>(c, m, seed, n_probes, n_steps, 1e-5);
+  return slq_impl<double>(c, m, seed, n_probes, n_steps, 1e-10);
+}
+
+// Exact log det: Lanczos on the Jacobi-scaled matrix to dimension n with full
+// re-orthogonalisation (classical Gram-Schmidt, twice); on breakdown restart
+// with a fresh probe orthogonalised against the basis (T splits into blocks).
+// log det T from the pivots of T = L D L^T (T is positive definite).
+LogdetResult exact_logdet(gp_ctx* c, const gp_matrix* m, uint64_t seed) {
+  const int64_t n = m->n;
+  GPS_REQUIRE(n <= 8192, GP_EINVAL, "exact log-det mode is limited to n <= 8192");
+  double* Vb = static_cast<double*>(workspace(c, 50, sizeof(double) * n * n));
+  double* w = static_cast<double*>(workspace(c, 51, sizeof(double) * n));
+  double* h = static_cast<double*>(workspace(c, 52, sizeof(double) * n));
+  double* sc = static_cast<double*>(workspace(c, 53, sizeof(double) * n));
+  const dim3 B(kThreads), Gn(grid_for(n, kThreads));
+  hipLaunchKernelGGL((k_scale_vec<double>), Gn, B, 0, c->stream, n, m->diag, sc);
+  check_launch("exact scale");
+  const double jac = logsum_f64(c, m->diag, n);
+  std::vector<double> al, be;  // be[j] couples j and j+1 (0 at restarts)
+  uint64_t probe = 0;
+  auto orth2 = [&](int nv) {
+    for (int pass = 0; pass < 2 && nv > 0; ++pass) {
+      hipLaunchKernelGGL(k_gemv_t, dim3(nv), B, 0, c->stream, n, nv, Vb, w, h);
+      hipLaunchKernelGGL(k_gemv_n_sub, Gn, B, 0, c->stream, n, nv, Vb, h, w);
+    }
+    check_launch("reorthogonalise");
+  };
+  auto start_vector = [&](int nv) -> bool {
+    for (int tries = 0; tries < 8; ++tries) {
+      hipLaunchKernelGGL(k_probe_vec, Gn, B, 0, c->stream, n, seed, probe++, m->ds->perm, w);
+      check_launch("probe");
+      const double n0 = std::sqrt(static_cast<double>(n));
+      orth2(nv);
+      const double nr = std::sqrt(dot_f64(c, w, w, n));
+      if (nr > 1e-6 * n0) {
+        hipLaunchKernelGGL(k_scale_into, Gn, B, 0, c->stream, n, 1.0 / nr, w, Vb + static_cast<int64_t>(nv) * n);
+        check_launch("normalise");
+        return true;
+      }
+    }
+    return false;
+  };
+  LogdetResult res;
+  if (!start_vector(0)) throw Error{GP_EDEVICE, "exact log-det: could not start"};
+  double beta_prev = 0.0;
+  for (int64_t j = 0; j < n; ++j) {
+    const double* vj = Vb + j * n;
+    spmm<double>(c, m, 1, 1, vj, w, sc);
+    const double a = dot_f64(c, vj, w, n);
+    const double* vprev = j > 0 ? Vb + (j - 1) * n : vj;
+    hipLaunchKernelGGL(k_axpby2, Gn, B, 0, c->stream, n, a, vj, j > 0 ? beta_prev : 0.0, vprev, w);
+    check_launch("lanczos axpy");
+    orth2(static_cast<int>(j + 1));
+    al.push_back(a);
+    if (j == n - 1) break;
+    const double b = std::sqrt(dot_f64(c, w, w, n));
+    if (b > 1e-10) {
+      be.push_back(b);
+      hipLaunchKernelGGL(k_scale_into, Gn, B, 0, c->stream, n, 1.0 / b, w, Vb + (j + 1) * n);
+      check_launch("lanczos normalise");
+      beta_prev = b;
+    } else {
+      be.push_back(0.0);
+      if (!start_vector(static_cast<int>(j + 1))) throw Error{GP_EDEVICE, "exact log-det: restart failed"};
+      beta_prev = 0.0;
+    }
+  }
+  double ld = 0, piv = 0;
+  for (size_t j = 0; j < al.size(); ++j) {
+    piv = j == 0 || be[j - 1] == 0.0 ? al[j] : al[j] - be[j - 1] * be[j - 1] / piv;
+    if (!(piv > 0)) {
+      res.st = GP_ENOTPD;
+      break;
+    }
+    ld += std::log(piv);
+  }
+  res.logdet = jac + ld;
+  res.se = 0;
+  res.steps = static_cast<int>(al.size());
+  return res;
+}
+
+}  // namespace gps

@@ -1,0 +1,143 @@
+"""GPU parity of binning and assembly against the FP64 oracle.
+
+Pattern and CSR indices must be bit-exact (the support predicate is the same
+float64 expression on both sides).  FP64 entries: relative error <= 1e-12
+(floor 1e-14 max|K|); float32 entries (mixed form): <= 1.2e-7 (one float32
+rounding of a float64 value).  Bitwise symmetry K_pq == K_qp."""
+import numpy as np
+import pytest
+
+from oracle import kernel
+from workloads import Theta, config1, config2, uniform_problem
+from gpu_util import assert_pattern_equal, dev, export, host, to_scipy, value_errors
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-12
+F32_TOL = 1.2e-7
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2411_05869_amd import Context
+    return Context()
+
+
+def run_case(ctx, p, prec=0, cell="default", what=""):
+    from paper_2411_05869_amd import FP64
+    print(f"[case] {what} n={p.n} d={p.d} prec={prec} cell={cell}", flush=True)
+    ds = ctx.dataset(dev(p.x), cell=p.cell if cell == "default" else cell)
+    K = ctx.assemble(ds, p.theta, prec)
+    rp, col, val = export(ctx, K)
+    ip, ci, vo = kernel.sparse(p.x, p.theta)
+    assert_pattern_equal(rp, col, ip, ci, what)
+    err = value_errors(val, vo)
+    assert err <= (FP64_TOL if prec == FP64 else F32_TOL), f"{what}: value error {err}"
+    A = to_scipy(rp, col, val, p.n)
+    assert (A != A.T).nnz == 0, f"{what}: not bitwise symmetric"
+    assert K.nnz == ip[-1]
+    return K, rp, col, val
+
+
+@pytest.mark.parametrize("d", [1, 2, 3])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_small_uniform(ctx, d, prec):
+    p = uniform_problem(400, d, 100 + d, r0=0.08 if d > 1 else 0.01, n1=3, n2=3, bump_radius=0.2)
+    run_case(ctx, p, prec, what=f"uniform d={d}")
+
+
+@pytest.mark.parametrize("cell", [None, [0.5, 0.5], [0.013, 0.02], [0.2, 0.007]])
+def test_cell_size_does_not_change_pattern(ctx, cell):
+    p = uniform_problem(500, 2, 7, r0=0.06, n1=2, n2=3, bump_radius=0.15)
+    run_case(ctx, p, 0, cell=cell, what=f"cell={cell}")
+
+
+def test_anisotropic_radii_3d(ctx):
+    rng = np.random.default_rng(3)
+    x = np.column_stack([rng.random(600), rng.random(600), rng.integers(0, 30, 600).astype(float)])
+    th = Theta(1.3, np.array([0.2, 0.1, 3.0]), np.column_stack([rng.random(8), rng.random(8), rng.uniform(0, 30, 8)]).reshape(4, 2, 3),
+               np.tile(np.array([0.2, 0.3, 5.0]), (4, 2, 1)), rng.uniform(0.5, 1, (4, 2)), np.ones((4, 2)), 0.02)
+    from workloads import Problem
+    p = Problem("aniso", x, th, cell=np.array([0.2, 0.1, 1.0]))
+    run_case(ctx, p, 0, what="anisotropic")
+
+
+def test_infinite_bump_radius(ctx):
+    rng = np.random.default_rng(4)
+    x = np.column_stack([rng.random(300), rng.random(300), rng.integers(0, 20, 300).astype(float)])
+    r = np.tile(np.array([0.25, 0.25, np.inf]), (2, 2, 1))
+    th = Theta(1.0, np.array([0.1, 0.1, 2.0]), rng.random((2, 2, 3)), r, np.ones((2, 2)), np.ones((2, 2)), 0.01)
+    from workloads import Problem
+    run_case(ctx, Problem("spatial-bumps", x, th, cell=np.array([0.1, 0.1, 2.0])), 0, what="inf radius")
+
+
+def test_edge_cases(ctx):
+    from workloads import Problem
+    # a single point
+    p = uniform_problem(1, 2, 1, r0=0.1, n1=1, n2=1)
+    run_case(ctx, p, 0, what="n=1")
+    # duplicated points: u0^2 = 0 -> local pair; nugget only on the index diagonal
+    x = np.array([[0.3, 0.3], [0.3, 0.3], [0.9, 0.1]])
+    th = Theta(1.0, np.array([0.1, 0.1]), np.array([[[0.3, 0.31]]]), np.full((1, 1, 2), 0.05), np.ones((1, 1)),
+               np.ones((1, 1)), 0.5)
+    run_case(ctx, Problem("dups", x, th, cell=None), 0, what="duplicates")
+    # no bumps at all (n1 = 0): special case (1) of Sec. 2.2
+    th0 = Theta(2.0, np.array([0.1, 0.1]), np.zeros((0, 0, 2)), np.zeros((0, 0, 2)), np.zeros((0, 0)),
+                np.zeros((0, 0)), 0.1)
+    run_case(ctx, Problem("nobumps", np.random.default_rng(5).random((300, 2)), th0), 0, what="n1=0")
+    # amplitudes all zero: bumps structurally absent
+    p2 = uniform_problem(300, 2, 6, r0=0.1, n1=2, n2=2)
+    p2.theta.a[:] = 0.0
+    run_case(ctx, p2, 0, what="a=0")
+    # one bump covering everything: every row is dense (long rows everywhere)
+    th1 = Theta(1.0, np.array([0.05, 0.05]), np.array([[[0.5, 0.5]]]), np.full((1, 1, 2), 5.0), np.ones((1, 1)),
+                np.ones((1, 1)), 0.1)
+    run_case(ctx, Problem("dense", np.random.default_rng(6).random((700, 2)), th1), 1, what="dense group")
+    # points far outside the bumps and each other (diagonal matrix)
+    p3 = uniform_problem(200, 3, 8, r0=1e-6, n1=1, n2=1, bump_radius=1e-3)
+    run_case(ctx, p3, 0, what="diagonal")
+
+
+def test_config1(ctx):
+    run_case(ctx, config1(), 0, what="cfg1 fp64")
+    run_case(ctx, config1(), 1, what="cfg1 mixed")
+
+
+def test_config2(ctx):
+    run_case(ctx, config2(), 0, what="cfg2 fp64")
+
+
+def test_binning_is_permutation_and_deterministic(ctx):
+    p = config1()
+    ds = ctx.dataset(dev(p.x), cell=p.cell)
+    perm = host(ds.permutation())
+    assert np.array_equal(np.sort(perm), np.arange(p.n))
+    ds2 = ctx.dataset(dev(p.x), cell=p.cell)
+    assert np.array_equal(host(ds2.permutation()), perm)
+    K1 = ctx.assemble(ds, p.theta, 0)
+    K2 = ctx.assemble(ds2, p.theta, 0)
+    a, b = export(ctx, K1), export(ctx, K2)
+    for u, v in zip(a, b):
+        assert np.array_equal(u, v)
+
+
+def test_invalid_theta_is_einval(ctx):
+    from paper_2411_05869_amd import GPError
+    p = uniform_problem(50, 2, 1)
+    ds = ctx.dataset(dev(p.x))
+    bad = p.theta.copy()
+    bad.r0 = np.array([-1.0, 0.1])
+    with pytest.raises(GPError) as e:
+        ctx.assemble(ds, bad)
+    assert e.value.name == "GP_EINVAL"
+    bad = p.theta.copy()
+    bad.a = bad.a.copy()
+    bad.a[0, 0] = np.nan
+    with pytest.raises(GPError) as e:
+        ctx.assemble(ds, bad)
+    assert e.value.name == "GP_EINVAL"
+    x = p.x.copy()
+    x[3, 1] = np.inf
+    with pytest.raises(GPError) as e:
+        ctx.dataset(dev(x))
+    assert e.value.name == "GP_EINVAL"
