@@ -90,6 +90,19 @@ GP_API const char* gp_last_error(const gp_ctx* ctx);
 /* Bytes currently held by the context's workspace and live objects. */
 GP_API gp_status gp_ctx_memory(const gp_ctx* ctx, size_t* bytes_in_use, size_t* peak_bytes);
 
+/* Per-kernel timing: while enabled, the library brackets its kernel launches
+ * with HIP events on the context's stream.  gp_profile_enable clears the
+ * record; gp_profile_read synchronises and returns one entry per kernel name
+ * (launch count and total milliseconds); *n_out receives the number of
+ * distinct names even when it exceeds max_entries. */
+typedef struct gp_profile_entry {
+  char name[32];
+  int64_t count;
+  double total_ms;
+} gp_profile_entry;
+GP_API gp_status gp_profile_enable(gp_ctx* ctx, int32_t on);
+GP_API gp_status gp_profile_read(gp_ctx* ctx, int32_t max_entries, gp_profile_entry* out, int32_t* n_out);
+
 /* ------------------------------------------------------------------ dataset
  * gp_dataset_create: copies and spatially bins n points (x_dev, n x d
  * row-major float64, caller-owned, read during the call).  The points are

@@ -38,6 +38,10 @@ class CSolveOpts(C.Structure):
                 ("n_lanczos", C.c_int32), ("logdet_mode", C.c_int32), ("seed", C.c_uint64)]
 
 
+class CProfileEntry(C.Structure):
+    _fields_ = [("name", C.c_char * 32), ("count", C.c_int64), ("total_ms", C.c_double)]
+
+
 class CLoglikResult(C.Structure):
     _fields_ = [("loglik", C.c_double), ("logdet", C.c_double), ("quad", C.c_double),
                 ("logdet_se", C.c_double), ("relres", C.c_double), ("cg_iters", C.c_int32),
@@ -52,7 +56,7 @@ EXPORTS = [
     "gp_dataset_create", "gp_dataset_destroy", "gp_dataset_info", "gp_dataset_permutation",
     "gp_assemble", "gp_matrix_destroy", "gp_matrix_info", "gp_matrix_export_csr", "gp_matvec",
     "gp_solve_opts_default", "gp_loglik", "gp_solve", "gp_predictor_create", "gp_predictor_destroy",
-    "gp_predict",
+    "gp_predict", "gp_profile_enable", "gp_profile_read",
 ]
 
 
@@ -93,6 +97,8 @@ def lib():
     L.gp_predictor_create.argtypes = [P, P, C.POINTER(CTheta), P, C.POINTER(P)]
     L.gp_predictor_destroy.argtypes = [P, P]
     L.gp_predict.argtypes = [P, P, I64, P, C.c_int, P]
+    L.gp_profile_enable.argtypes = [P, I32]
+    L.gp_profile_read.argtypes = [P, I32, C.POINTER(CProfileEntry), C.POINTER(I32)]
     for name in EXPORTS:
         getattr(L, name).restype = st
     L.gp_last_error.restype = C.c_char_p
@@ -214,6 +220,18 @@ class Context:
         a, b = C.c_size_t(), C.c_size_t()
         self._L.gp_ctx_memory(self._h, C.byref(a), C.byref(b))
         return a.value, b.value
+
+    def profile(self, on: bool = True):
+        """Start (and clear) or stop per-kernel event timing inside the library."""
+        self._check(self._L.gp_profile_enable(self._h, 1 if on else 0), "gp_profile_enable")
+
+    def profile_read(self) -> dict:
+        """{kernel name: (launch count, total ms)} since profile(True)."""
+        n = C.c_int32()
+        self._check(self._L.gp_profile_read(self._h, 0, None, C.byref(n)), "gp_profile_read")
+        buf = (CProfileEntry * max(n.value, 1))()
+        self._check(self._L.gp_profile_read(self._h, n.value, buf, C.byref(n)), "gp_profile_read")
+        return {buf[i].name.decode(): (buf[i].count, buf[i].total_ms) for i in range(n.value)}
 
     # --------------------------------------------------------------- objects
     def dataset(self, x, cell=None) -> "Dataset":

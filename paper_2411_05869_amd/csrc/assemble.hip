@@ -415,6 +415,7 @@ void compute_features(gp_ctx* c, const gp_dataset* ds, const KernelTheta& kt, Fe
   int32_t* pos = static_cast<int32_t*>(workspace(c, ws_base + 3, sizeof(int32_t) * (n + 1)));
   dispatch_d(ds->d, [&](auto DD) {
     constexpr int D = decltype(DD)::value;
+    ProfScope ps(c, "asm_mask");
     hipLaunchKernelGGL((k_mask<D>), dim3(grid_for(n, kThreads)), dim3(kThreads), 0, c->stream, kt, n, ds->xb,
                        f->mask, flag);
   });
@@ -434,6 +435,7 @@ void compute_features(gp_ctx* c, const gp_dataset* ds, const KernelTheta& kt, Fe
   if (f->nm > 0) {
     dispatch_d(ds->d, [&](auto DD) {
       constexpr int D = decltype(DD)::value;
+      ProfScope ps(c, "asm_bump_values");
       hipLaunchKernelGGL((k_fvals<D>), dim3(grid_for(f->nm, kThreads)), dim3(kThreads), 0, c->stream, kt, n, f->nm,
                          ds->xb, f->mlist, f->F);
     });
@@ -501,6 +503,7 @@ gp_matrix* assemble(gp_ctx* c, const gp_dataset* ds, const gp_theta* th, int pre
     GPS_HIP(hipMemcpyAsync(d_uoff, st + sizeof(int32_t) * nm + sizeof(uint64_t) * nD, sizeof(int64_t) * (nD + 1),
                            hipMemcpyHostToDevice, c->stream));
     if (nD) {
+      ProfScope ps(c, "asm_group_lists");
       hipLaunchKernelGGL(k_ulists, dim3(static_cast<unsigned>(nD)), dim3(kThreads), 0, c->stream, nm, mmask, f.mlist,
                          d_dmask, d_uoff, d_ulist);
       check_launch("group lists");
@@ -538,11 +541,16 @@ gp_matrix* assemble(gp_ctx* c, const gp_dataset* ds, const gp_theta* th, int pre
   // count passes
   dispatch_d(d, [&](auto DD) {
     constexpr int D = decltype(DD)::value;
-    hipLaunchKernelGGL((k_local_rows<D, false, double>), dim3(grid_for(n, kThreads)), dim3(kThreads), 0, c->stream,
-                       a);
-    if (nm > 0)
+    {
+      ProfScope ps(c, "asm_count_local");
+      hipLaunchKernelGGL((k_local_rows<D, false, double>), dim3(grid_for(n, kThreads)), dim3(kThreads), 0,
+                         c->stream, a);
+    }
+    if (nm > 0) {
+      ProfScope ps(c, "asm_count_group");
       hipLaunchKernelGGL((k_group_rows_scan<D, 0>), dim3(grid_for(nm * kWave, kThreads)), dim3(kThreads), 0,
                          c->stream, a);
+    }
   });
   check_launch("count");
 
@@ -597,22 +605,28 @@ gp_matrix* assemble(gp_ctx* c, const gp_dataset* ds, const gp_theta* th, int pre
   a.diag = m->diag;
   dispatch_d(d, [&](auto DD) {
     constexpr int D = decltype(DD)::value;
-    if (nm > 0)
+    if (nm > 0) {
+      ProfScope ps(c, "asm_list_group");
       hipLaunchKernelGGL((k_group_rows_scan<D, 1>), dim3(grid_for(nm * kWave, kThreads)), dim3(kThreads), 0,
                          c->stream, a);
-    if (prec == GP_MIXED) {
-      hipLaunchKernelGGL((k_local_rows<D, true, float>), dim3(grid_for(n, kThreads)), dim3(kThreads), 0, c->stream,
-                         a);
-      if (nm > 0)
-        hipLaunchKernelGGL((k_group_rows_fill<D, float>), dim3(grid_for(nm * kWave, kThreads)), dim3(kThreads), 0,
-                           c->stream, a);
-    } else {
-      hipLaunchKernelGGL((k_local_rows<D, true, double>), dim3(grid_for(n, kThreads)), dim3(kThreads), 0, c->stream,
-                         a);
-      if (nm > 0)
-        hipLaunchKernelGGL((k_group_rows_fill<D, double>), dim3(grid_for(nm * kWave, kThreads)), dim3(kThreads), 0,
-                           c->stream, a);
     }
+    auto fill = [&](auto VTv) {
+      using VT = decltype(VTv);
+      {
+        ProfScope ps(c, "asm_fill_local");
+        hipLaunchKernelGGL((k_local_rows<D, true, VT>), dim3(grid_for(n, kThreads)), dim3(kThreads), 0, c->stream,
+                           a);
+      }
+      if (nm > 0) {
+        ProfScope ps(c, "asm_fill_group");
+        hipLaunchKernelGGL((k_group_rows_fill<D, VT>), dim3(grid_for(nm * kWave, kThreads)), dim3(kThreads), 0,
+                           c->stream, a);
+      }
+    };
+    if (prec == GP_MIXED)
+      fill(float{});
+    else
+      fill(double{});
   });
   check_launch("fill");
   int* herr = static_cast<int*>(pinned(c, sizeof(int)));

@@ -68,6 +68,15 @@ void* pinned(gp_ctx* c, size_t bytes) {
 
 void sync(gp_ctx* c) { GPS_HIP(hipStreamSynchronize(c->stream)); }
 
+hipEvent_t prof_event(gp_ctx* c) {
+  if (c->evnext == c->evpool.size()) {
+    hipEvent_t e;
+    GPS_HIP(hipEventCreate(&e));
+    c->evpool.push_back(e);
+  }
+  return c->evpool[c->evnext++];
+}
+
 }  // namespace gps
 
 using gps::Error;
@@ -186,6 +195,8 @@ gp_status gp_ctx_destroy(gp_ctx* c) {
     GPS_HIP(hipStreamSynchronize(c->stream));
     if (c->pinned) (void)hipHostFree(c->pinned);
     c->pinned = nullptr;
+    for (hipEvent_t e : c->evpool) (void)hipEventDestroy(e);
+    c->evpool.clear();
   });
   delete c;
   return st;
@@ -196,6 +207,40 @@ gp_status gp_ctx_set_stream(gp_ctx* c, void* stream) {
   return guarded(c, [&] {
     GPS_HIP(hipStreamSynchronize(c->stream));
     c->stream = static_cast<hipStream_t>(stream);
+  });
+}
+
+gp_status gp_profile_enable(gp_ctx* c, int32_t on) {
+  if (!c) return GP_EINVAL;
+  return guarded(c, [&] {
+    GPS_HIP(hipStreamSynchronize(c->stream));
+    c->prof.clear();
+    c->evnext = 0;
+    c->prof_on = on != 0;
+  });
+}
+
+gp_status gp_profile_read(gp_ctx* c, int32_t max_entries, gp_profile_entry* out, int32_t* n_out) {
+  if (!c || !n_out || (max_entries > 0 && !out)) return GP_EINVAL;
+  return guarded(c, [&] {
+    GPS_HIP(hipStreamSynchronize(c->stream));
+    std::vector<gp_profile_entry> agg;
+    for (const auto& r : c->prof) {
+      float ms = 0;
+      GPS_HIP(hipEventElapsedTime(&ms, r.a, r.b));
+      auto it = std::find_if(agg.begin(), agg.end(),
+                             [&](const gp_profile_entry& e) { return std::strncmp(e.name, r.name, 31) == 0; });
+      if (it == agg.end()) {
+        gp_profile_entry e{};
+        std::strncpy(e.name, r.name, 31);
+        agg.push_back(e);
+        it = agg.end() - 1;
+      }
+      it->count += 1;
+      it->total_ms += ms;
+    }
+    *n_out = static_cast<int32_t>(agg.size());
+    for (int32_t i = 0; i < std::min<int32_t>(max_entries, static_cast<int32_t>(agg.size())); ++i) out[i] = agg[i];
   });
 }
 

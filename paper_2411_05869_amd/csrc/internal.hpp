@@ -66,6 +66,15 @@ struct gp_ctx {
   void* pinned = nullptr;
   size_t pinned_bytes = 0;
   int* err_flag = nullptr;  // device int, set by kernels on consistency failures
+  // optional per-kernel timing with events on the context's stream
+  bool prof_on = false;
+  struct ProfRec {
+    const char* name;
+    hipEvent_t a, b;
+  };
+  std::vector<ProfRec> prof;
+  std::vector<hipEvent_t> evpool;
+  size_t evnext = 0;
 };
 
 struct gp_dataset {
@@ -160,6 +169,27 @@ struct TmpBuf {
   template <typename T>
   T* as() const {
     return static_cast<T*>(p);
+  }
+};
+
+// Brackets the launches issued in its scope with events when profiling is on.
+hipEvent_t prof_event(gp_ctx* c);
+struct ProfScope {
+  gp_ctx* c;
+  const char* name;
+  hipEvent_t a = nullptr;
+  ProfScope(gp_ctx* c_, const char* n) : c(c_), name(n) {
+    if (c->prof_on) {
+      a = prof_event(c);
+      (void)hipEventRecord(a, c->stream);
+    }
+  }
+  ~ProfScope() {
+    if (c->prof_on && a) {
+      hipEvent_t b = prof_event(c);
+      (void)hipEventRecord(b, c->stream);
+      c->prof.push_back({name, a, b});
+    }
   }
 };
 

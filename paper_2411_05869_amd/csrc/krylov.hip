@@ -553,11 +553,13 @@ SolveResult pcg_solve(gp_ctx* c, const gp_matrix* m, const double* y, double* x,
     for (int t = 0; t < steps; ++t) {
       if (mixed) {
         spmv_f32(c, m, p32, q32);
+        ProfScope ps(c, "pcg_vector_ops");
         hipLaunchKernelGGL((k_pq_part<float>), G, B, 0, c->stream, n, p, q32, part);
         hipLaunchKernelGGL(k_alpha_fin, dim3(1), B, 0, c->stream, part, kRedBlocks, s);
         hipLaunchKernelGGL((k_pcg_update<float>), G, B, 0, c->stream, n, s, p, q32, m->diag, x, r, z, part);
       } else {
         spmv_f64(c, m, p, q);
+        ProfScope ps(c, "pcg_vector_ops");
         hipLaunchKernelGGL((k_pq_part<double>), G, B, 0, c->stream, n, p, q, part);
         hipLaunchKernelGGL(k_alpha_fin, dim3(1), B, 0, c->stream, part, kRedBlocks, s);
         hipLaunchKernelGGL((k_pcg_update<double>), G, B, 0, c->stream, n, s, p, q, m->diag, x, r, z, part);
@@ -631,6 +633,7 @@ static LogdetResult slq_impl(gp_ctx* c, const gp_matrix* m, uint64_t seed, int n
     for (int j = 0; j < n_steps; ++j) {
       const int last = j == n_steps - 1;
       spmm<T>(c, m, ld, ld, V, W, sc);
+      ProfScope ps(c, "lanczos_vector_ops");
       hipLaunchKernelGGL((k_lz_beta_dot<T>), dim3(kRedBlocks), dim3(kThreads), 0, c->stream, n, ld, st->beta_prev, V,
                          Vp, W, part);
       hipLaunchKernelGGL(k_lz_fin, dim3(1), dim3(kThreads), 0, c->stream, part, kRedBlocks, k, 0, j, last, tol, st,
@@ -676,8 +679,12 @@ static LogdetResult slq_impl(gp_ctx* c, const gp_matrix* m, uint64_t seed, int n
   return res;
 }
 
+// Lanczos vectors, products and reductions are float64 for both forms; the
+// mixed form reads float32 matrix values.  Rounding the product's input or
+// accumulating it in float32 perturbs each step by ~1e-7, which the
+// recurrence's loss of orthogonality amplifies to ~5e-5 in the quadrature at
+// 50 steps; float32 values alone move the estimate by ~5e-8.
 LogdetResult slq_logdet(gp_ctx* c, const gp_matrix* m, uint64_t seed, int n_probes, int n_steps) {
-  if (m->prec == GP_MIXED) return slq_impl<float>(c, m, seed, n_probes, n_steps, 1e-5);
   return slq_impl<double>(c, m, seed, n_probes, n_steps, 1e-10);
 }
 

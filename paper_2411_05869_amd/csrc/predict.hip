@@ -184,6 +184,7 @@ void predict(gp_ctx* c, const gp_predictor* p, int64_t m, const double* xs, int 
   a.alpha32 = p->alpha32;
   a.coef = p->coef;
   const dim3 G(grid_for(m, kThreads)), B(kThreads);
+  ProfScope ps(c, prec == GP_MIXED ? "predict_f32" : "predict_f64");
   auto go = [&](auto DD) {
     constexpr int D = decltype(DD)::value;
     if (prec == GP_MIXED)

@@ -16,37 +16,37 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kG = 8;
 
+// One launch: blocks [0, nb_short) take rows of at most kLongRow entries with
+// kG lanes per row; the remaining blocks take the listed long rows, one wave
+// per row.
 template <typename VT, typename XT, typename AT, typename YT>
-__global__ void __launch_bounds__(kThreads) k_spmv_rows(int64_t n, const int64_t* __restrict__ rp,
-                                                        const int32_t* __restrict__ col, const VT* __restrict__ val,
-                                                        const XT* __restrict__ x, YT* __restrict__ y) {
-  const int64_t row = (blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x) / kG;
-  const int sub = threadIdx.x & (kG - 1);
-  if (row >= n) return;
-  const int64_t s = rp[row], e = rp[row + 1];
-  if (e - s > kLongRow) return;  // uniform within the group
-  AT acc = 0;
-  for (int64_t j = s + sub; j < e; j += kG) acc += static_cast<AT>(val[j]) * static_cast<AT>(x[col[j]]);
+__global__ void __launch_bounds__(kThreads) k_spmv(int64_t n, unsigned nb_short, int64_t nlong,
+                                                   const int32_t* __restrict__ rows, const int64_t* __restrict__ rp,
+                                                   const int32_t* __restrict__ col, const VT* __restrict__ val,
+                                                   const XT* __restrict__ x, YT* __restrict__ y) {
+  if (blockIdx.x < nb_short) {
+    const int64_t row = (blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x) / kG;
+    const int sub = threadIdx.x & (kG - 1);
+    if (row >= n) return;
+    const int64_t s = rp[row], e = rp[row + 1];
+    if (e - s > kLongRow) return;  // uniform within the group
+    AT acc = 0;
+    for (int64_t j = s + sub; j < e; j += kG) acc += static_cast<AT>(val[j]) * static_cast<AT>(x[col[j]]);
 #pragma unroll
-  for (int off = kG / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kG);
-  if (sub == 0) y[row] = static_cast<YT>(acc);
-}
-
-template <typename VT, typename XT, typename AT, typename YT>
-__global__ void __launch_bounds__(kThreads) k_spmv_long(int64_t nlong, const int32_t* __restrict__ rows,
-                                                        const int64_t* __restrict__ rp,
-                                                        const int32_t* __restrict__ col, const VT* __restrict__ val,
-                                                        const XT* __restrict__ x, YT* __restrict__ y) {
-  const int64_t w = (blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x) / kWave;
-  if (w >= nlong) return;
-  const int lane = lane_id();
-  const int32_t row = rows[w];
-  const int64_t s = rp[row], e = rp[row + 1];
-  AT acc = 0;
-  for (int64_t j = s + lane; j < e; j += kWave) acc += static_cast<AT>(val[j]) * static_cast<AT>(x[col[j]]);
+    for (int off = kG / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kG);
+    if (sub == 0) y[row] = static_cast<YT>(acc);
+  } else {
+    const int64_t w = ((blockIdx.x - nb_short) * static_cast<int64_t>(kThreads) + threadIdx.x) / kWave;
+    if (w >= nlong) return;
+    const int lane = lane_id();
+    const int32_t row = rows[w];
+    const int64_t s = rp[row], e = rp[row + 1];
+    AT acc = 0;
+    for (int64_t j = s + lane; j < e; j += kWave) acc += static_cast<AT>(val[j]) * static_cast<AT>(x[col[j]]);
 #pragma unroll
-  for (int off = kWave / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kWave);
-  if (lane == 0) y[row] = static_cast<YT>(acc);
+    for (int off = kWave / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kWave);
+    if (lane == 0) y[row] = static_cast<YT>(acc);
+  }
 }
 
 template <typename VT, typename T>
@@ -79,11 +79,11 @@ __global__ void __launch_bounds__(kThreads) k_spmm(int64_t n, int k, int ld, con
 template <typename VT, typename XT, typename AT, typename YT>
 void spmv_impl(gp_ctx* c, const gp_matrix* m, const XT* x, YT* y) {
   const VT* val = static_cast<const VT*>(m->val);
-  hipLaunchKernelGGL((k_spmv_rows<VT, XT, AT, YT>), dim3(grid_for(m->n * kG, kThreads)), dim3(kThreads), 0, c->stream,
-                     m->n, m->row_ptr, m->col, val, x, y);
-  if (m->n_long > 0)
-    hipLaunchKernelGGL((k_spmv_long<VT, XT, AT, YT>), dim3(grid_for(m->n_long * kWave, kThreads)), dim3(kThreads), 0,
-                       c->stream, m->n_long, m->long_rows, m->row_ptr, m->col, val, x, y);
+  const unsigned nb_short = grid_for(m->n * kG, kThreads);
+  const unsigned nb_long = m->n_long > 0 ? grid_for(m->n_long * kWave, kThreads) : 0;
+  ProfScope ps(c, sizeof(VT) == 4 ? (sizeof(XT) == 4 ? "spmv_f32" : "spmv_f32val_f64") : "spmv_f64");
+  hipLaunchKernelGGL((k_spmv<VT, XT, AT, YT>), dim3(nb_short + nb_long), dim3(kThreads), 0, c->stream, m->n,
+                     nb_short, m->n_long, m->long_rows, m->row_ptr, m->col, val, x, y);
   check_launch("spmv");
 }
 
@@ -106,6 +106,7 @@ void spmv_f32(gp_ctx* c, const gp_matrix* m, const float* x, float* y) {
 template <typename T>
 void spmm(gp_ctx* c, const gp_matrix* m, int k, int ld, const T* X, T* Y, const T* scale) {
   if (k > 32) throw Error{GP_EINVAL, "spmm: at most 32 right-hand sides per call"};
+  ProfScope ps(c, "spmm");
   if (m->prec == GP_MIXED)
     hipLaunchKernelGGL((k_spmm<float, T>), dim3(grid_for(m->n * 32, kThreads)), dim3(kThreads), 0, c->stream, m->n, k,
                        ld, m->row_ptr, m->col, static_cast<const float*>(m->val), X, Y, scale);
