@@ -334,7 +334,14 @@ __global__ void __launch_bounds__(kThreads) k_long_flags(int64_t n, const int32_
     flag[p] = c > kLongRow ? 1 : 0;
   }
   for (int off = kWave / 2; off > 0; off >>= 1) c = max(c, __shfl_xor(c, off, kWave));
-  if (lane_id() == 0) atomicMax(maxrow, c);
+  __shared__ int32_t wmax[kThreads / kWave];
+  if (lane_id() == 0) wmax[threadIdx.x / kWave] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int32_t m = wmax[0];
+    for (int i = 1; i < kThreads / kWave; ++i) m = max(m, wmax[i]);
+    atomicMax(maxrow, m);
+  }
 }
 
 __global__ void __launch_bounds__(kThreads) k_long_compact(int64_t n, const int32_t* __restrict__ flag,

@@ -6,8 +6,10 @@
 // row's sum is formed in the same order on every call, so results are
 // bitwise reproducible; no floating-point atomics are used.
 //
-// SpMM: one half-wave per row, lane = right-hand side (k <= 32), X and Y
-// row-major n x ld.  Optional symmetric diagonal scaling Y = S K S X.
+// SpMM: k <= 32 right-hand sides, X and Y row-major n x ld, optional
+// symmetric diagonal scaling Y = S K S X (see k_spmm).
+#include <type_traits>
+
 #include "device.hpp"
 
 namespace gps {
@@ -16,9 +18,13 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kG = 8;
 
+constexpr int kU = 4;   // independent loads in flight per lane
+
 // One launch: blocks [0, nb_short) take rows of at most kLongRow entries with
 // kG lanes per row; the remaining blocks take the listed long rows, one wave
-// per row.
+// per row.  Each lane keeps kU (column, value) pairs in flight before
+// gathering x, so a row's loads overlap instead of forming a dependent chain.
+// Lanes past the row end read the row's own index with a zero weight.
 template <typename VT, typename XT, typename AT, typename YT>
 __global__ void __launch_bounds__(kThreads) k_spmv(int64_t n, unsigned nb_short, int64_t nlong,
                                                    const int32_t* __restrict__ rows, const int64_t* __restrict__ rp,
@@ -31,7 +37,19 @@ __global__ void __launch_bounds__(kThreads) k_spmv(int64_t n, unsigned nb_short,
     const int64_t s = rp[row], e = rp[row + 1];
     if (e - s > kLongRow) return;  // uniform within the group
     AT acc = 0;
-    for (int64_t j = s + sub; j < e; j += kG) acc += static_cast<AT>(val[j]) * static_cast<AT>(x[col[j]]);
+    for (int64_t j0 = s + sub; j0 < e; j0 += kU * kG) {
+      int32_t c[kU];
+      AT v[kU];
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const int64_t j = j0 + u * kG;
+        const bool in = j < e;
+        c[u] = in ? col[j] : static_cast<int32_t>(row);
+        v[u] = in ? static_cast<AT>(val[j]) : AT(0);
+      }
+#pragma unroll
+      for (int u = 0; u < kU; ++u) acc += v[u] * static_cast<AT>(x[c[u]]);
+    }
 #pragma unroll
     for (int off = kG / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kG);
     if (sub == 0) y[row] = static_cast<YT>(acc);
@@ -42,37 +60,96 @@ __global__ void __launch_bounds__(kThreads) k_spmv(int64_t n, unsigned nb_short,
     const int32_t row = rows[w];
     const int64_t s = rp[row], e = rp[row + 1];
     AT acc = 0;
-    for (int64_t j = s + lane; j < e; j += kWave) acc += static_cast<AT>(val[j]) * static_cast<AT>(x[col[j]]);
+    for (int64_t j0 = s + lane; j0 < e; j0 += kU * kWave) {
+      int32_t c[kU];
+      AT v[kU];
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const int64_t j = j0 + u * kWave;
+        const bool in = j < e;
+        c[u] = in ? col[j] : row;
+        v[u] = in ? static_cast<AT>(val[j]) : AT(0);
+      }
+#pragma unroll
+      for (int u = 0; u < kU; ++u) acc += v[u] * static_cast<AT>(x[c[u]]);
+    }
 #pragma unroll
     for (int off = kWave / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kWave);
     if (lane == 0) y[row] = static_cast<YT>(acc);
   }
 }
 
-template <typename VT, typename T>
-__global__ void __launch_bounds__(kThreads) k_spmm(int64_t n, int k, int ld, const int64_t* __restrict__ rp,
-                                                   const int32_t* __restrict__ col, const VT* __restrict__ val,
-                                                   const T* __restrict__ X, T* __restrict__ Y,
-                                                   const T* __restrict__ scale) {
-  const int64_t row = (blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x) / 32;
-  const int c = threadIdx.x & 31;
-  if (row >= n) return;
-  const int64_t s = rp[row], e = rp[row + 1];
+// SpMM, Y = S K S X (S = diag(scale), or K X without scale), k <= 32 columns of
+// a row-major block with leading dimension ld.  Lane l works on column l & 31
+// of entry (l >> 5) of each pair of entries, so one vector load fetches two
+// consecutive (column, value) pairs and the X gathers are contiguous per half
+// wave.  Blocks [0, nb_short) give each short row one wave; the remaining
+// blocks give each long row a whole block (four waves over interleaved pairs,
+// combined in a fixed order through LDS).
+template <typename VT, typename T, bool SCALE>
+__device__ __forceinline__ T spmm_row_part(int64_t j0, int64_t e, int64_t step, int32_t self,
+                                           const int32_t* __restrict__ col, const VT* __restrict__ val,
+                                           const T* __restrict__ X, const T* __restrict__ scale, int ld, int c) {
   T acc = 0;
-  if (c < k) {
-    if (scale) {
-      for (int64_t j = s; j < e; ++j) {
-        const int32_t q = col[j];
-        acc += static_cast<T>(val[j]) * (scale[q] * X[static_cast<int64_t>(q) * ld + c]);
-      }
-      acc *= scale[row];
-    } else {
-      for (int64_t j = s; j < e; ++j) {
-        const int32_t q = col[j];
-        acc += static_cast<T>(val[j]) * X[static_cast<int64_t>(q) * ld + c];
-      }
+  for (; j0 < e; j0 += kU * step) {
+    int32_t q[kU];
+    T v[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int64_t j = j0 + u * step;
+      const bool in = j < e;
+      q[u] = in ? col[j] : self;
+      v[u] = in ? static_cast<T>(val[j]) : T(0);
     }
-    Y[row * ld + c] = acc;
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      T xv = X[static_cast<int64_t>(q[u]) * ld + c];
+      if constexpr (SCALE) xv = scale[q[u]] * xv;
+      acc += v[u] * xv;
+    }
+  }
+  return acc;
+}
+
+template <typename VT, typename T, bool SCALE>
+__global__ void __launch_bounds__(kThreads) k_spmm(int64_t n, unsigned nb_short, int64_t nlong,
+                                                   const int32_t* __restrict__ rows, int k, int ld,
+                                                   const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                                   const VT* __restrict__ val, const T* __restrict__ X,
+                                                   T* __restrict__ Y, const T* __restrict__ scale) {
+  const int lane = lane_id();
+  const int c = lane & 31;
+  const int cl = c < k ? c : k - 1;  // lanes past k re-read column k-1 (in bounds), never store
+  const int h = lane >> 5;
+  const int w = threadIdx.x / kWave;
+  if (blockIdx.x < nb_short) {
+    const int64_t row = blockIdx.x * static_cast<int64_t>(kThreads / kWave) + w;
+    if (row >= n) return;
+    const int64_t s = rp[row], e = rp[row + 1];
+    if (e - s > kLongRow) return;
+    T acc = spmm_row_part<VT, T, SCALE>(s + h, e, 2, static_cast<int32_t>(row), col, val, X, scale, ld, cl);
+    acc += __shfl_xor(acc, 32, kWave);
+    if (h == 0 && c < k) {
+      if constexpr (SCALE) acc *= scale[row];
+      Y[row * ld + c] = acc;
+    }
+  } else {
+    __shared__ T part[kThreads / kWave][32];
+    const int64_t li = blockIdx.x - nb_short;
+    if (li >= nlong) return;  // uniform over the block
+    const int32_t row = rows[li];
+    const int64_t s = rp[row], e = rp[row + 1];
+    T acc = spmm_row_part<VT, T, SCALE>(s + 2 * w + h, e, 2 * (kThreads / kWave), row, col, val, X, scale, ld, cl);
+    acc += __shfl_xor(acc, 32, kWave);
+    if (h == 0) part[w][c] = acc;
+    __syncthreads();
+    if (w == 0 && h == 0 && c < k) {
+      T t = part[0][c];
+#pragma unroll
+      for (int i = 1; i < kThreads / kWave; ++i) t += part[i][c];
+      if constexpr (SCALE) t *= scale[row];
+      Y[static_cast<int64_t>(row) * ld + c] = t;
+    }
   }
 }
 
@@ -105,14 +182,27 @@ void spmv_f32(gp_ctx* c, const gp_matrix* m, const float* x, float* y) {
 
 template <typename T>
 void spmm(gp_ctx* c, const gp_matrix* m, int k, int ld, const T* X, T* Y, const T* scale) {
-  if (k > 32) throw Error{GP_EINVAL, "spmm: at most 32 right-hand sides per call"};
+  if (k > 32 || ld < k) throw Error{GP_EINVAL, "spmm: at most 32 right-hand sides per call"};
   ProfScope ps(c, "spmm");
-  if (m->prec == GP_MIXED)
-    hipLaunchKernelGGL((k_spmm<float, T>), dim3(grid_for(m->n * 32, kThreads)), dim3(kThreads), 0, c->stream, m->n, k,
-                       ld, m->row_ptr, m->col, static_cast<const float*>(m->val), X, Y, scale);
-  else
-    hipLaunchKernelGGL((k_spmm<double, T>), dim3(grid_for(m->n * 32, kThreads)), dim3(kThreads), 0, c->stream, m->n,
-                       k, ld, m->row_ptr, m->col, static_cast<const double*>(m->val), X, Y, scale);
+  const unsigned nb_short = grid_for(m->n, kThreads / kWave);
+  const unsigned nb = nb_short + static_cast<unsigned>(m->n_long);
+  auto go = [&](auto vt, auto sc) {
+    using VT = decltype(vt);
+    constexpr bool SC = decltype(sc)::value;
+    hipLaunchKernelGGL((k_spmm<VT, T, SC>), dim3(nb), dim3(kThreads), 0, c->stream, m->n, nb_short, m->n_long,
+                       m->long_rows, k, ld, m->row_ptr, m->col, static_cast<const VT*>(m->val), X, Y, scale);
+  };
+  if (m->prec == GP_MIXED) {
+    if (scale)
+      go(float{}, std::true_type{});
+    else
+      go(float{}, std::false_type{});
+  } else {
+    if (scale)
+      go(double{}, std::true_type{});
+    else
+      go(double{}, std::false_type{});
+  }
   check_launch("spmm");
 }
 
