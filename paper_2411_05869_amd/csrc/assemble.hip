@@ -596,8 +596,9 @@ gp_matrix* assemble(gp_ctx* c, const gp_dataset* ds, const gp_theta* th, int pre
   GPS_REQUIRE(m->nnz < (int64_t(1) << 40), GP_ENOMEM, "gp_assemble: too many nonzeros");
 
   const size_t vbytes = prec == GP_MIXED ? sizeof(float) : sizeof(double);
-  m->col = dev_new<int32_t>(c, m->nnz);
-  m->val = dev_alloc(c, vbytes * std::max<int64_t>(m->nnz, 1));
+  // 64 entries of padding: SpMV reads column ids and values in aligned groups of four
+  m->col = dev_new<int32_t>(c, m->nnz + kCsrPad);
+  m->val = dev_alloc(c, vbytes * (m->nnz + kCsrPad));
   m->diag = dev_new<double>(c, n);
   m->long_rows = dev_new<int32_t>(c, std::max<int64_t>(m->n_long, 1));
   m->bytes += (sizeof(int32_t) + vbytes) * m->nnz + sizeof(double) * n + sizeof(int32_t) * m->n_long;
@@ -651,8 +652,8 @@ void destroy_matrix(gp_ctx* c, gp_matrix* m) {
   if (!m) return;
   const size_t vbytes = m->prec == GP_MIXED ? sizeof(float) : sizeof(double);
   if (m->row_ptr) dev_free(c, m->row_ptr, sizeof(int64_t) * (m->n + 1));
-  if (m->col) dev_free(c, m->col, sizeof(int32_t) * std::max<int64_t>(m->nnz, 1));
-  if (m->val) dev_free(c, m->val, vbytes * std::max<int64_t>(m->nnz, 1));
+  if (m->col) dev_free(c, m->col, sizeof(int32_t) * (m->nnz + kCsrPad));
+  if (m->val) dev_free(c, m->val, vbytes * (m->nnz + kCsrPad));
   if (m->diag) dev_free(c, m->diag, sizeof(double) * m->n);
   if (m->long_rows) dev_free(c, m->long_rows, sizeof(int32_t) * std::max<int64_t>(m->n_long, 1));
   delete m;

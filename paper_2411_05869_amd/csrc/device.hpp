@@ -90,6 +90,16 @@ __device__ __forceinline__ uint64_t point_features(const KernelTheta& kt, const 
   return mask;
 }
 
+// Workgroup b of a launch runs on XCD b % 8 (each XCD has its own L2).  This
+// maps b to a logical block index such that every XCD receives one contiguous
+// range of logical blocks; it is a bijection on [0, nb).
+constexpr unsigned kXcds = 8;
+__device__ __forceinline__ unsigned xcd_remap(unsigned b, unsigned nb) {
+  const unsigned q = nb / kXcds, r = nb % kXcds;
+  const unsigned x = b % kXcds, i = b / kXcds;
+  return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+}
+
 __device__ __forceinline__ void decode_key(int32_t key, const int32_t* g, int* c) {
   c[0] = key % g[0];
   const int32_t r = key / g[0];

@@ -16,6 +16,7 @@ constexpr int kWave = 64;
 constexpr int kMaxGroups = 64;      // n1 <= 64: group membership is one uint64 per point
 constexpr int kMaxBumps = 4096;     // n1 * n2
 constexpr int kLongRow = 128;       // rows longer than this get a wave of their own in SpMV
+constexpr int64_t kCsrPad = 64;     // padding entries after the CSR column and value arrays
 
 // ------------------------------------------------------------------ errors
 struct Error {
