@@ -62,6 +62,51 @@ def cpu_baseline(p):
                 nnz_per_s=float(ip[-1] / (t1 - t0)), n=int(x.shape[0]), loglik=r["loglik"]), (sel, ip[-1])
 
 
+def serving_legs(args, ctx, ds, p, alpha):
+    """Continuous batching: (1) the MCMC-proposal stream (Poisson, 50 req/s,
+    mixture data sets with n log-uniform in [5k, 300k], mixed precision,
+    SLQ 30 x 50, PCG rtol 1e-10) -> p50/p99 latency and evals/s; (2) posterior
+    means on the resident space-time training set, requests of 1k-50k test
+    points: all queued at once (points/s), then Poisson at half that rate
+    (p50/p99)."""
+    import numpy as np
+
+    from paper_2411_05869_amd.serve import GpuBackend, LoglikRequest, PredictRequest, Server, latency_stats
+    from workloads import config4_requests, config5_requests
+    res = {}
+    pool, reqs = config4_requests(n_requests=args.serve_requests, rate=50.0)
+    be = GpuBackend(n_slots=4)
+    for k, q in enumerate(pool):
+        be.add_dataset(f"d{k}", q.x, q.y, cell=q.cell, row_estimate=60.0)
+    requests = [LoglikRequest(f"d{k}", th, 1, arrival=t) for (t, k, th) in reqs]
+    log(f"serving: {len(requests)} log-likelihood requests at 50 req/s on 4 slots")
+    srv = Server(be, hbm_budget=64 << 30)
+    comps = srv.run(requests)
+    st = latency_stats(comps)
+    st.update(requests=len(requests), rate_per_s=50.0, slots=4, peak_reserved_gb=round(srv.peak_reserved / 2 ** 30, 3),
+              workload="mixture data sets n in [5k, 300k] (16 in the pool), log-normal proposals, mixed precision")
+    res["loglik_stream"] = st
+    # predictions on the resident training set (alpha from the last mixed step)
+    be.datasets["train"] = (ds, None)
+    be.predictors["train"] = (ctx.predictor(ds, p.theta, alpha), p.d)
+    xs = config5_requests(n_requests=200, seed=5)
+    sat = [PredictRequest("train", x, 1, 0.0) for x in xs]
+    comps = Server(be, hbm_budget=64 << 30).run(sat)
+    span = max(c.done for c in comps)
+    pts = sum(x.shape[0] for x in xs)
+    rate = len(xs) / span
+    rng = np.random.default_rng(55)
+    arr = np.cumsum(rng.exponential(1.0 / (0.5 * rate), len(xs)))
+    comps2 = Server(be, hbm_budget=64 << 30).run([PredictRequest("train", x, 1, float(t)) for x, t in zip(xs, arr)])
+    st2 = latency_stats(comps2)
+    st2.update(requests=len(xs), saturation_points_per_s=round(pts / span, 1),
+               saturation_requests_per_s=round(rate, 2), poisson_rate_per_s=round(0.5 * rate, 2),
+               max_batch=max(c.batch for c in comps))
+    res["predict_stream"] = st2
+    log(f"serving done: {json.dumps(res)}")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -70,6 +115,8 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--stations", type=int, default=3000)
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=128)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
@@ -175,6 +222,8 @@ def main():
                kernels_ms_per_step={k: round(v[1] / args.steps, 3) for k, v in sorted(prof_m.items(),
                                                                                        key=lambda kv: -kv[1][1])},
                paper_context="paper: ~66 s per likelihood (37 s covariance) at N=1,038,723 on 256 A100 (Sec. 5.2)")
+    if not args.no_serve:
+        out["serving"] = serving_legs(args, ctx, ds, p, alpha)
     if not args.no_cpu:
         log("cpu baseline (oracle on a bounded sample) ...")
         cb, (sel, snnz) = cpu_baseline(p)

@@ -1,0 +1,333 @@
+"""Continuous-batching request loop for log-likelihood and prediction requests.
+
+Requests arrive over time (e.g. the hyper-parameter proposals of many MCMC
+chains, Sec. 3.1 and Appendix C of the paper, and kriging-mean queries,
+Sec. 3.2).  The server keeps the binned data sets and the prediction caches
+resident on the device and runs requests on ``n_slots`` slots.  Each slot owns
+a HIP stream, a library context bound to it and a host worker thread; the
+library calls release the GIL, so the slots' work overlaps on the GPU.
+
+Admission is first-in first-out under an HBM budget: the request at the head
+of the queue starts as soon as a slot is free and its footprint estimate fits
+in the budget not reserved by running requests.  A request whose footprint
+exceeds the whole budget is rejected with GP_ENOMEM.  Prediction requests
+for the same predictor that are waiting together are batched into one launch
+(their test points concatenated) and split afterwards.
+
+The scheduling logic is independent of the device: a ``Backend`` runs one
+request (or batch) and estimates footprints.  ``GpuBackend`` uses the HIP
+library; tests drive the scheduler with a CPU fake backend.
+"""
+from __future__ import annotations
+
+import collections
+import dataclasses
+import queue
+import threading
+import time
+from typing import Any, Dict, List, Optional
+
+import numpy as np
+
+
+@dataclasses.dataclass
+class LoglikRequest:
+    dataset: str
+    theta: Any
+    precision: int = 1
+    arrival: float = 0.0
+    rid: int = -1
+
+
+@dataclasses.dataclass
+class PredictRequest:
+    predictor: str
+    xs: Any                    # (m, d) float64 numpy array or device tensor
+    precision: int = 0
+    arrival: float = 0.0
+    rid: int = -1
+
+
+@dataclasses.dataclass
+class Completion:
+    rid: int
+    kind: str
+    arrival: float
+    start: float
+    done: float
+    slot: int
+    result: Any = None
+    error: Optional[str] = None
+    batch: int = 1
+
+    @property
+    def latency(self) -> float:
+        return self.done - self.arrival
+
+
+class Backend:
+    """Runs requests; must be safe to call from one thread per slot."""
+
+    n_slots: int = 1
+
+    def footprint(self, req) -> int:
+        raise NotImplementedError
+
+    def run_loglik(self, slot: int, req: LoglikRequest):
+        raise NotImplementedError
+
+    def run_predict(self, slot: int, reqs: List[PredictRequest]):
+        raise NotImplementedError
+
+
+class Server:
+    """FIFO admission by footprint over ``backend.n_slots`` slots."""
+
+    def __init__(self, backend: Backend, hbm_budget: int, max_predict_batch_points: int = 1 << 20):
+        self.backend = backend
+        self.n_slots = backend.n_slots
+        self.budget = int(hbm_budget)
+        self.max_batch_points = max_predict_batch_points
+        self.peak_reserved = 0
+
+    def run(self, requests: List[Any], timeout: float = 3600.0) -> List[Completion]:
+        """Serves ``requests`` (each with an ``arrival`` offset in seconds from
+        the call) and returns one Completion per request, in request order."""
+        for i, r in enumerate(requests):
+            if r.rid < 0:
+                r.rid = i
+        pending = collections.deque(sorted(requests, key=lambda r: (r.arrival, r.rid)))
+        waiting: collections.deque = collections.deque()
+        done: Dict[int, Completion] = {}
+        cv = threading.Condition()
+        finished: collections.deque = collections.deque()
+        work = [queue.Queue() for _ in range(self.n_slots)]
+        free = list(range(self.n_slots))
+        reserved = 0
+        t0 = time.perf_counter()
+
+        def now():
+            return time.perf_counter() - t0
+
+        def worker(slot):
+            while True:
+                item = work[slot].get()
+                if item is None:
+                    return
+                batch, fp = item
+                start = now()
+                err = None
+                try:
+                    if isinstance(batch[0], LoglikRequest):
+                        res = [self.backend.run_loglik(slot, batch[0])]
+                    else:
+                        res = self.backend.run_predict(slot, batch)
+                except Exception as e:  # reported per request, the slot stays usable
+                    err = f"{type(e).__name__}: {e}"
+                    res = [None] * len(batch)
+                t = now()
+                with cv:
+                    for r, out in zip(batch, res):
+                        kind = "loglik" if isinstance(r, LoglikRequest) else "predict"
+                        finished.append(Completion(r.rid, kind, r.arrival, start, t, slot, out, err, len(batch)))
+                    finished.append(("slot", slot, fp))
+                    cv.notify_all()
+
+        threads = [threading.Thread(target=worker, args=(s,), daemon=True) for s in range(self.n_slots)]
+        for th in threads:
+            th.start()
+        total = len(requests)
+        try:
+            with cv:
+                while len(done) < total:
+                    if now() > timeout:
+                        raise TimeoutError("serving did not finish in time")
+                    t = now()
+                    while pending and pending[0].arrival <= t:
+                        waiting.append(pending.popleft())
+                    # collect completions: free slots and budget
+                    while finished:
+                        item = finished.popleft()
+                        if isinstance(item, tuple):
+                            _, slot, fp = item
+                            free.append(slot)
+                            free.sort()
+                            reserved -= fp
+                        else:
+                            done[item.rid] = item
+                    # admit from the head while a slot is free and the footprint fits
+                    while waiting and free:
+                        head = waiting[0]
+                        fp = self.backend.footprint(head)
+                        if fp > self.budget:
+                            waiting.popleft()
+                            done[head.rid] = Completion(head.rid, type(head).__name__, head.arrival, t, t, -1, None,
+                                                        f"GP_ENOMEM: footprint {fp} exceeds the budget {self.budget}")
+                            continue
+                        if reserved + fp > self.budget:
+                            break
+                        batch = [waiting.popleft()]
+                        if isinstance(head, PredictRequest):
+                            # merge waiting requests for the same predictor into one launch
+                            pts = _npts(head.xs)
+                            keep = collections.deque()
+                            while waiting:
+                                r = waiting.popleft()
+                                fr = self.backend.footprint(r)
+                                if (isinstance(r, PredictRequest) and r.predictor == head.predictor
+                                        and r.precision == head.precision
+                                        and pts + _npts(r.xs) <= self.max_batch_points
+                                        and reserved + fp + fr <= self.budget):
+                                    batch.append(r)
+                                    pts += _npts(r.xs)
+                                    fp += fr
+                                else:
+                                    keep.append(r)
+                            waiting.extend(keep)
+                        reserved += fp
+                        self.peak_reserved = max(self.peak_reserved, reserved)
+                        work[free.pop(0)].put((batch, fp))
+                    if len(done) >= total:
+                        break
+                    wait = 0.05
+                    if pending:
+                        wait = max(0.0, min(wait, pending[0].arrival - now()))
+                    if not finished:
+                        cv.wait(timeout=wait)
+        finally:
+            for q in work:
+                q.put(None)
+            for th in threads:
+                th.join(timeout=60)
+        return [done[r.rid] for r in sorted(requests, key=lambda r: r.rid)]
+
+
+def _npts(xs) -> int:
+    return int(xs.shape[0])
+
+
+def latency_stats(comps: List[Completion]) -> dict:
+    ok = [c for c in comps if c.error is None]
+    lat = np.array([c.latency for c in ok]) if ok else np.zeros(0)
+    span = (max(c.done for c in ok) - min(c.arrival for c in ok)) if ok else float("nan")
+    return dict(completed=len(ok), failed=len(comps) - len(ok),
+                p50_ms=float(np.percentile(lat, 50) * 1e3) if lat.size else float("nan"),
+                p99_ms=float(np.percentile(lat, 99) * 1e3) if lat.size else float("nan"),
+                mean_ms=float(lat.mean() * 1e3) if lat.size else float("nan"),
+                throughput_per_s=len(ok) / span if ok and span > 0 else float("nan"))
+
+
+# ------------------------------------------------------------------ GPU backend
+
+class GpuBackend(Backend):
+    """Runs requests through the HIP library, one context and stream per slot."""
+
+    def __init__(self, n_slots: int = 4, device: int = 0, solve_opts: Optional[dict] = None):
+        import torch
+
+        from . import Context
+        self.torch = torch
+        self.n_slots = n_slots
+        self.device = device
+        self.dev = torch.device("cuda", device)
+        self.setup = Context(device)
+        self.streams = [torch.cuda.Stream(device) for _ in range(n_slots)]
+        self.ctxs = [Context(device, stream=s) for s in self.streams]
+        self.datasets: Dict[str, Any] = {}
+        self.predictors: Dict[str, Any] = {}
+        self.opts = dict(seed=2411, n_probes=30, n_lanczos=50)
+        self.opts.update(solve_opts or {})
+        self.row_estimate: Dict[str, float] = {}
+
+    def add_dataset(self, name: str, x, y, cell=None, row_estimate: float = 100.0):
+        torch = self.torch
+        xd = torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device=self.dev)
+        yd = torch.as_tensor(np.ascontiguousarray(y), dtype=torch.float64, device=self.dev)
+        ds = self.setup.dataset(xd, cell=cell)
+        torch.cuda.synchronize(self.device)
+        self.datasets[name] = (ds, yd)
+        self.row_estimate[name] = row_estimate
+
+    def add_predictor(self, name: str, dataset: str, theta, alpha=None, precision: int = 0):
+        """Caches alpha = K^-1 y for theta (solved here if not given)."""
+        torch = self.torch
+        ds, yd = self.datasets[dataset]
+        if alpha is None:
+            K = self.setup.assemble(ds, theta, precision)
+            alpha = torch.empty(ds.n, dtype=torch.float64, device=self.dev)
+            self.setup.solve(K, yd, alpha)
+            K.close()
+        self.predictors[name] = (self.setup.predictor(ds, theta, alpha), ds.d)
+        torch.cuda.synchronize(self.device)
+
+    def footprint(self, req) -> int:
+        if isinstance(req, LoglikRequest):
+            ds, _ = self.datasets[req.dataset]
+            n = ds.n
+            vb = 4 if req.precision == 1 else 8
+            csr = n * self.row_estimate[req.dataset] * (4 + vb) + 24 * n
+            work = n * (3 * 32 * 8 + 8 * 8 + 16)   # Lanczos blocks + CG vectors + binning scratch
+            return int(csr + work)
+        return int(_npts(req.xs) * (8 * 3 + 8) + (1 << 16))
+
+    def run_loglik(self, slot: int, req: LoglikRequest):
+        ctx = self.ctxs[slot]
+        ds, yd = self.datasets[req.dataset]
+        with self.torch.cuda.stream(self.streams[slot]):
+            K = ctx.assemble(ds, req.theta, req.precision)
+            try:
+                self.row_estimate[req.dataset] = max(self.row_estimate[req.dataset], K.nnz / K.n * 1.1)
+                r = ctx.loglik(K, yd, raise_on_error=False, **self.opts)
+                r["nnz"] = K.nnz
+            finally:
+                K.close()
+        return r
+
+    def run_predict(self, slot: int, reqs: List[PredictRequest]):
+        torch = self.torch
+        ctx = self.ctxs[slot]
+        pred, d = self.predictors[reqs[0].predictor]
+        with torch.cuda.stream(self.streams[slot]):
+            parts = [torch.as_tensor(np.ascontiguousarray(r.xs), dtype=torch.float64, device=self.dev)
+                     if not isinstance(r.xs, torch.Tensor) else r.xs for r in reqs]
+            xs = parts[0] if len(parts) == 1 else torch.cat(parts, 0)
+            m = ctx.predict(pred, xs, precision=reqs[0].precision)
+            host = m.cpu().numpy()
+        out, o = [], 0
+        for p in parts:
+            out.append(host[o:o + p.shape[0]])
+            o += p.shape[0]
+        return out
+
+
+# ------------------------------------------------------------------ CLI
+
+def serve_loglik_stream(n_requests: int = 512, rate: float = 50.0, n_slots: int = 4, budget_gb: float = 64.0,
+                        precision: int = 1, verbose: bool = True):
+    """The MCMC-proposal workload: Poisson arrivals of log-likelihood requests
+    on a pool of 16 mixture data sets (n log-uniform in [5k, 300k])."""
+    from workloads import config4_requests
+    pool, reqs = config4_requests(n_requests=n_requests, rate=rate)
+    be = GpuBackend(n_slots=n_slots)
+    for k, p in enumerate(pool):
+        be.add_dataset(f"d{k}", p.x, p.y, cell=p.cell, row_estimate=60.0)
+    requests = [LoglikRequest(f"d{k}", th, precision, arrival=t) for (t, k, th) in reqs]
+    srv = Server(be, hbm_budget=int(budget_gb * 2 ** 30))
+    comps = srv.run(requests)
+    st = latency_stats(comps)
+    st["peak_reserved_gb"] = srv.peak_reserved / 2 ** 30
+    if verbose:
+        print(st, flush=True)
+    return st, comps
+
+
+if __name__ == "__main__":
+    import argparse
+    import json
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--requests", type=int, default=512)
+    ap.add_argument("--rate", type=float, default=50.0)
+    ap.add_argument("--slots", type=int, default=4)
+    args = ap.parse_args()
+    st, _ = serve_loglik_stream(args.requests, args.rate, args.slots)
+    print(json.dumps(st))

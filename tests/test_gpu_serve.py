@@ -1,0 +1,47 @@
+"""Serving on the GPU: every result is the same alone and in the mix (the
+kernels are deterministic, so the tolerance is zero: bitwise equality), and
+batched predictions equal single-request predictions."""
+import math
+
+import numpy as np
+import pytest
+
+from workloads import gmm_problem, perturb_theta
+
+pytestmark = pytest.mark.gpu
+
+
+def test_loglik_alone_equals_mix():
+    from paper_2411_05869_amd.serve import GpuBackend, LoglikRequest, Server
+    be = GpuBackend(n_slots=4)
+    base = []
+    for k, n in enumerate([3000, 8000, 20000]):
+        s = math.sqrt(1e5 / n)
+        p = gmm_problem(n, 700 + k, 0.0078 * s, 0.02 * s)
+        be.add_dataset(f"d{k}", p.x, p.y, cell=p.cell)
+        base.append(p.theta)
+    rng = np.random.default_rng(9)
+    reqs = [LoglikRequest(f"d{i % 3}", perturb_theta(rng, base[i % 3]), precision=i % 2) for i in range(12)]
+    alone = [be.run_loglik(0, r) for r in reqs]
+    mix = Server(be, hbm_budget=8 << 30).run([LoglikRequest(r.dataset, r.theta, r.precision, 0.0) for r in reqs])
+    assert len({c.slot for c in mix}) > 1
+    for a, c in zip(alone, mix):
+        assert c.error is None, c.error
+        for key in ("loglik", "logdet", "quad", "cg_iters", "status"):
+            assert a[key] == c.result[key], (key, a[key], c.result[key])
+    print(f"[serve] 12 requests, slots used {sorted({c.slot for c in mix})}, results identical alone and mixed")
+
+
+def test_predict_batched_equals_single():
+    from paper_2411_05869_amd.serve import GpuBackend, PredictRequest, Server
+    be = GpuBackend(n_slots=2)
+    p = gmm_problem(20000, 801, 0.0078 * math.sqrt(5), 0.02 * math.sqrt(5))
+    be.add_dataset("d", p.x, p.y, cell=p.cell)
+    be.add_predictor("pr", "d", p.theta)
+    rng = np.random.default_rng(3)
+    xs = [rng.random((int(rng.integers(10, 3000)), 2)) for _ in range(10)]
+    single = [be.run_predict(0, [PredictRequest("pr", x)])[0] for x in xs]
+    comps = Server(be, hbm_budget=1 << 30).run([PredictRequest("pr", x, 0, 0.0) for x in xs])
+    assert max(c.batch for c in comps) > 1
+    for s, c in zip(single, comps):
+        assert np.array_equal(s, c.result)
