@@ -175,12 +175,19 @@ GP_API gp_status gp_matvec(gp_ctx* ctx, const gp_matrix* m, int32_t nrhs, const 
                     double* y_dev);
 
 /* ------------------------------------------------------------ likelihood */
+typedef enum gp_precond {
+  GP_PRECOND_JACOBI = 0,        /* diagonal of K */
+  GP_PRECOND_BLOCK_JACOBI = 1   /* dense diagonal blocks over the binning cells (<= 32 points) */
+} gp_precond;
+
 typedef struct gp_solve_opts {
   double rtol;          /* stop when |y - K alpha|_2 <= rtol |y|_2 (default 1e-10) */
   int32_t max_iter;     /* conjugate-gradient iteration cap (default 10000) */
   int32_t n_probes;     /* SLQ probes (default 30, at most 64) */
   int32_t n_lanczos;    /* SLQ Lanczos steps (default 50, at most 128) */
   int32_t logdet_mode;  /* gp_logdet_mode */
+  int32_t precond;      /* gp_precond for the conjugate gradients (default block Jacobi) */
+  int32_t pad;
   uint64_t seed;        /* probe seed */
 } gp_solve_opts;
 

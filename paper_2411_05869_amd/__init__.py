@@ -16,6 +16,8 @@ from ._lib import (  # noqa: F401
     LOGDET_EXACT,
     LOGDET_NONE,
     LOGDET_SLQ,
+    PRECOND_BLOCK_JACOBI,
+    PRECOND_JACOBI,
     Context,
     Dataset,
     GPError,

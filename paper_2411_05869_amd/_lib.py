@@ -13,6 +13,7 @@ _lib = None
 
 FP64, MIXED = 0, 1
 LOGDET_SLQ, LOGDET_EXACT, LOGDET_NONE = 0, 1, 2
+PRECOND_JACOBI, PRECOND_BLOCK_JACOBI = 0, 1
 _STATUS = {0: "GP_OK", 1: "GP_EINVAL", 2: "GP_ENOMEM", 3: "GP_ENOTCONV", 4: "GP_ENOTPD", 5: "GP_EDEVICE"}
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
@@ -35,7 +36,8 @@ class CTheta(C.Structure):
 
 class CSolveOpts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("max_iter", C.c_int32), ("n_probes", C.c_int32),
-                ("n_lanczos", C.c_int32), ("logdet_mode", C.c_int32), ("seed", C.c_uint64)]
+                ("n_lanczos", C.c_int32), ("logdet_mode", C.c_int32), ("precond", C.c_int32),
+                ("pad", C.c_int32), ("seed", C.c_uint64)]
 
 
 class CProfileEntry(C.Structure):

@@ -656,6 +656,7 @@ void destroy_matrix(gp_ctx* c, gp_matrix* m) {
   if (m->val) dev_free(c, m->val, vbytes * (m->nnz + kCsrPad));
   if (m->diag) dev_free(c, m->diag, sizeof(double) * m->n);
   if (m->long_rows) dev_free(c, m->long_rows, sizeof(int32_t) * std::max<int64_t>(m->n_long, 1));
+  free_block_jacobi(c, m);
   delete m;
 }
 

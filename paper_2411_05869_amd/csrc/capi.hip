@@ -139,6 +139,8 @@ gp_solve_opts fill_opts(const gp_solve_opts* o) {
   GPS_REQUIRE(r.n_probes >= 2 && r.n_probes <= 64, GP_EINVAL, "n_probes must be in 2..64");
   GPS_REQUIRE(r.n_lanczos >= 1 && r.n_lanczos <= 128, GP_EINVAL, "n_lanczos must be in 1..128");
   GPS_REQUIRE(r.logdet_mode >= 0 && r.logdet_mode <= 2, GP_EINVAL, "logdet_mode must be 0, 1 or 2");
+  GPS_REQUIRE(r.precond == GP_PRECOND_JACOBI || r.precond == GP_PRECOND_BLOCK_JACOBI, GP_EINVAL,
+              "precond must be GP_PRECOND_JACOBI or GP_PRECOND_BLOCK_JACOBI");
   return r;
 }
 
@@ -153,6 +155,8 @@ void gp_solve_opts_default(gp_solve_opts* o) {
   o->n_probes = 30;
   o->n_lanczos = 50;
   o->logdet_mode = GP_LOGDET_SLQ;
+  o->precond = GP_PRECOND_BLOCK_JACOBI;
+  o->pad = 0;
   o->seed = 0x5eed;
 }
 
@@ -372,7 +376,8 @@ static gp_status loglik_common(gp_ctx* c, const gp_matrix* m, const double* y, c
     double* yb = static_cast<double*>(gps::workspace(c, 44, sizeof(double) * n));
     double* xb = static_cast<double*>(gps::workspace(c, 45, sizeof(double) * n));
     gps::permute_to_binned<double>(c, m->ds, 1, y, yb);
-    const gps::SolveResult sr = gps::pcg_solve(c, m, yb, xb, o.rtol, o.max_iter);
+    // the preconditioner is cached in the matrix object on first use
+    const gps::SolveResult sr = gps::pcg_solve(c, const_cast<gp_matrix*>(m), yb, xb, o.rtol, o.max_iter, o.precond);
     out->quad = sr.quad;
     out->relres = sr.relres;
     out->cg_iters = sr.iters;

@@ -105,6 +105,12 @@ struct gp_matrix {
   double* diag = nullptr;       // n, diagonal of the stored matrix (float64)
   int32_t* long_rows = nullptr; // rows with more than kLongRow entries
   int64_t n_long = 0;
+  // block-Jacobi preconditioner, built on first use (blocks = binning cells)
+  int64_t nblk = 0, binv_len = 0;
+  int32_t* bstart = nullptr;    // nblk + 1 block starts (binned rows)
+  int32_t* rowblk = nullptr;    // n, block of each row
+  int64_t* boff = nullptr;      // nblk + 1 offsets into binv
+  double* binv = nullptr;       // row-major inverses of the diagonal blocks
   size_t bytes = 0;
 };
 
@@ -233,8 +239,10 @@ struct SolveResult {
   double quad = 0;
   gp_status st = GP_OK;
 };
-// alpha = K^-1 y (binned order); Jacobi PCG, float64 or float32-product form.
-SolveResult pcg_solve(gp_ctx* c, const gp_matrix* m, const double* yb, double* xb, double rtol, int max_iter);
+// alpha = K^-1 y (binned order); preconditioned CG, float64 or float32-product form.
+SolveResult pcg_solve(gp_ctx* c, gp_matrix* m, const double* yb, double* xb, double rtol, int max_iter, int precond);
+void build_block_jacobi(gp_ctx* c, gp_matrix* m);
+void free_block_jacobi(gp_ctx* c, gp_matrix* m);
 
 struct LogdetResult {
   double logdet = 0, se = 0;

@@ -93,38 +93,64 @@ struct CgScalars {
   int status;  // 0 ok, 1 non-positive curvature / non-finite
 };
 
-__global__ void __launch_bounds__(kThreads) k_pcg_init(int64_t n, const double* __restrict__ y,
-                                                       const double* __restrict__ diag, double* __restrict__ x,
-                                                       double* __restrict__ r, double* __restrict__ z,
-                                                       double* __restrict__ p, float* __restrict__ p32,
-                                                       double* __restrict__ part) {
-  double v[3] = {0, 0, 0};
+// Preconditioner description passed to the kernels (block Jacobi if binv != null,
+// otherwise point Jacobi with the matrix diagonal).
+struct Precond {
+  const double* diag;
+  const int32_t* rowblk;
+  const int32_t* bstart;
+  const int64_t* boff;
+  const double* binv;
+};
+
+__device__ __forceinline__ double precond_row(const Precond& M, const double* __restrict__ r, int64_t i) {
+  if (!M.binv) return r[i] / M.diag[i];
+  const int32_t b = M.rowblk[i];
+  const int32_t bs = M.bstart[b];
+  const int sz = M.bstart[b + 1] - bs;
+  const double* row = M.binv + M.boff[b] + static_cast<int64_t>(i - bs) * sz;
+  double z = 0.0;
+  for (int j = 0; j < sz; ++j) z += row[j] * r[bs + j];
+  return z;
+}
+
+// x = 0, r = y; partial sums of y.y
+__global__ void __launch_bounds__(kThreads) k_pcg_init(int64_t n, const double* __restrict__ y, double* __restrict__ x,
+                                                       double* __restrict__ r, double* __restrict__ part) {
+  double v[1] = {0};
   for (int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; i < n;
        i += static_cast<int64_t>(gridDim.x) * kThreads) {
     const double yi = y[i];
-    const double zi = yi / diag[i];
     x[i] = 0.0;
     r[i] = yi;
-    z[i] = zi;
-    p[i] = zi;
-    if (p32) p32[i] = static_cast<float>(zi);
-    v[0] += yi * zi;
-    v[1] += yi * yi;
-    v[2] += yi * yi;
+    v[0] += yi * yi;
   }
-  block_sum_store<3>(v, part);
+  block_sum_store<1>(v, part);
 }
 
-__global__ void __launch_bounds__(kThreads) k_pcg_init_fin(const double* __restrict__ part, int nb,
-                                                           CgScalars* __restrict__ s) {
-  double r[3];
-  reduce_partials<3>(part, nb, r);
+__global__ void __launch_bounds__(kThreads) k_yy_fin(const double* __restrict__ part, int nb, CgScalars* __restrict__ s) {
+  double r[1];
+  reduce_partials<1>(part, nb, r);
   if (threadIdx.x == 0) {
-    s->rz = r[0];
-    s->rr = r[1];
-    s->yy = r[2];
+    s->yy = r[0];
     s->status = 0;
   }
+}
+
+// z = M^-1 r, one thread per row (full grid: the block products are short,
+// dependent gathers); per-block partial sums of r.z and r.r
+__global__ void __launch_bounds__(kThreads) k_precond(int64_t n, Precond M, const double* __restrict__ r,
+                                                      double* __restrict__ z, double* __restrict__ part) {
+  double v[2] = {0, 0};
+  const int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x;
+  if (i < n) {
+    const double ri = r[i];
+    const double zi = precond_row(M, r, i);
+    z[i] = zi;
+    v[0] = ri * zi;
+    v[1] = ri * ri;
+  }
+  block_sum_store<2>(v, part);
 }
 
 template <typename QT>
@@ -153,68 +179,54 @@ __global__ void __launch_bounds__(kThreads) k_alpha_fin(const double* __restrict
   }
 }
 
+// x += alpha p; r -= alpha q
 template <typename QT>
 __global__ void __launch_bounds__(kThreads) k_pcg_update(int64_t n, const CgScalars* __restrict__ s,
                                                          const double* __restrict__ p, const QT* __restrict__ q,
-                                                         const double* __restrict__ diag, double* __restrict__ x,
-                                                         double* __restrict__ r, double* __restrict__ z,
-                                                         double* __restrict__ part) {
+                                                         double* __restrict__ x, double* __restrict__ r) {
   const double alpha = s->alpha;
-  double v[2] = {0, 0};
   for (int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; i < n;
        i += static_cast<int64_t>(gridDim.x) * kThreads) {
     x[i] += alpha * p[i];
-    const double ri = r[i] - alpha * static_cast<double>(q[i]);
-    const double zi = ri / diag[i];
-    r[i] = ri;
-    z[i] = zi;
-    v[0] += ri * zi;
-    v[1] += ri * ri;
+    r[i] = r[i] - alpha * static_cast<double>(q[i]);
   }
-  block_sum_store<2>(v, part);
 }
 
+// mode 0: iteration (rz_old <- rz, rz <- r.z, beta = rz / rz_old)
+// mode 1: residual replacement (rz_old kept)
+// mode 2: start (rz <- r.z, no beta)
 __global__ void __launch_bounds__(kThreads) k_beta_fin(const double* __restrict__ part, int nb,
-                                                       CgScalars* __restrict__ s, int replace) {
+                                                       CgScalars* __restrict__ s, int mode) {
   double r[2];
   reduce_partials<2>(part, nb, r);
   if (threadIdx.x == 0) {
-    if (!replace) s->rz_old = s->rz;   // after a residual replacement rz_old is kept
+    if (mode == 0) s->rz_old = s->rz;
     s->rz = r[0];
     s->rr = r[1];
-    s->beta = r[0] / s->rz_old;
+    s->beta = mode == 2 ? 0.0 : r[0] / s->rz_old;
     if (!isfinite(r[0]) || !isfinite(r[1])) s->status = 1;
   }
 }
 
+// p = z + beta p (beta = 0 at the start)
 __global__ void __launch_bounds__(kThreads) k_pcg_pupdate(int64_t n, const CgScalars* __restrict__ s,
                                                           const double* __restrict__ z, double* __restrict__ p,
                                                           float* __restrict__ p32) {
   const double beta = s->beta;
   for (int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; i < n;
        i += static_cast<int64_t>(gridDim.x) * kThreads) {
-    const double pi = z[i] + beta * p[i];
+    const double pi = beta == 0.0 ? z[i] : z[i] + beta * p[i];
     p[i] = pi;
     if (p32) p32[i] = static_cast<float>(pi);
   }
 }
 
-// r = y - Kx (Kx given), z = D^-1 r, partials of r.z and r.r
+// r = y - Kx (Kx given)
 __global__ void __launch_bounds__(kThreads) k_true_resid(int64_t n, const double* __restrict__ y,
-                                                         const double* __restrict__ kx, const double* __restrict__ diag,
-                                                         double* __restrict__ r, double* __restrict__ z,
-                                                         double* __restrict__ part) {
-  double v[2] = {0, 0};
+                                                         const double* __restrict__ kx, double* __restrict__ r) {
   for (int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; i < n;
-       i += static_cast<int64_t>(gridDim.x) * kThreads) {
-    const double ri = y[i] - kx[i];
-    const double zi = ri / diag[i];
-    r[i] = ri;
-    z[i] = zi;
-    v[0] += ri * zi;
-    v[1] += ri * ri;
-  }
-  block_sum_store<2>(v, part);
+       i += static_cast<int64_t>(gridDim.x) * kThreads)
+    r[i] = y[i] - kx[i];
 }
 
 // ---------------------------------------------------------------- Lanczos
@@ -508,9 +520,17 @@ static double logsum_f64(gp_ctx* c, const double* a, int64_t n) {
   return *h;
 }
 
-SolveResult pcg_solve(gp_ctx* c, const gp_matrix* m, const double* y, double* x, double rtol, int max_iter) {
+SolveResult pcg_solve(gp_ctx* c, gp_matrix* m, const double* y, double* x, double rtol, int max_iter, int precond) {
   const int64_t n = m->n;
   const bool mixed = m->prec == GP_MIXED;
+  if (precond == GP_PRECOND_BLOCK_JACOBI) build_block_jacobi(c, m);
+  Precond M{m->diag, nullptr, nullptr, nullptr, nullptr};
+  if (precond == GP_PRECOND_BLOCK_JACOBI) {
+    M.rowblk = m->rowblk;
+    M.bstart = m->bstart;
+    M.boff = m->boff;
+    M.binv = m->binv;
+  }
   double* r = static_cast<double*>(workspace(c, 20, sizeof(double) * n));
   double* z = static_cast<double*>(workspace(c, 21, sizeof(double) * n));
   double* p = static_cast<double*>(workspace(c, 22, sizeof(double) * n));
@@ -518,6 +538,8 @@ SolveResult pcg_solve(gp_ctx* c, const gp_matrix* m, const double* y, double* x,
   float* p32 = mixed ? static_cast<float*>(workspace(c, 24, sizeof(float) * n)) : nullptr;
   float* q32 = mixed ? static_cast<float*>(workspace(c, 25, sizeof(float) * n)) : nullptr;
   double* part = static_cast<double*>(workspace(c, 26, sizeof(double) * 4 * kRedBlocks));
+  const unsigned nbp = grid_for(n, kThreads);
+  double* ppart = static_cast<double*>(workspace(c, 28, sizeof(double) * 2 * nbp));
   CgScalars* s = static_cast<CgScalars*>(workspace(c, 27, sizeof(CgScalars)));
   CgScalars* hs = static_cast<CgScalars*>(pinned(c, sizeof(CgScalars)));
   const dim3 G(kRedBlocks), B(kThreads);
@@ -526,24 +548,32 @@ SolveResult pcg_solve(gp_ctx* c, const gp_matrix* m, const double* y, double* x,
     GPS_HIP(hipStreamSynchronize(c->stream));
     return *hs;
   };
+  // z = M^-1 r and the scalars r.z, r.r (mode: see k_beta_fin)
+  auto apply_precond = [&](int mode) {
+    ProfScope ps(c, "pcg_precond");
+    hipLaunchKernelGGL(k_precond, dim3(nbp), B, 0, c->stream, n, M, r, z, ppart);
+    hipLaunchKernelGGL(k_beta_fin, dim3(1), B, 0, c->stream, ppart, static_cast<int>(nbp), s, mode);
+  };
   auto true_residual = [&]() {
     spmv_f64(c, m, x, q);
-    hipLaunchKernelGGL(k_true_resid, G, B, 0, c->stream, n, y, q, m->diag, r, z, part);
-    hipLaunchKernelGGL(k_beta_fin, dim3(1), B, 0, c->stream, part, kRedBlocks, s, 1);
+    hipLaunchKernelGGL(k_true_resid, G, B, 0, c->stream, n, y, q, r);
+    apply_precond(1);
     check_launch("true residual");
     return read();
   };
-  hipLaunchKernelGGL(k_pcg_init, G, B, 0, c->stream, n, y, m->diag, x, r, z, p, p32, part);
-  hipLaunchKernelGGL(k_pcg_init_fin, dim3(1), B, 0, c->stream, part, kRedBlocks, s);
+  {
+    ProfScope ps(c, "pcg_vector_ops");
+    hipLaunchKernelGGL(k_pcg_init, G, B, 0, c->stream, n, y, x, r, part);
+    hipLaunchKernelGGL(k_yy_fin, dim3(1), B, 0, c->stream, part, kRedBlocks, s);
+  }
+  apply_precond(2);
+  hipLaunchKernelGGL(k_pcg_pupdate, G, B, 0, c->stream, n, s, z, p, p32);
   check_launch("pcg init");
   CgScalars sc = read();
   SolveResult res;
+  GPS_REQUIRE(std::isfinite(sc.yy), GP_EINVAL, "y holds non-finite values");
   const double ynorm = std::sqrt(sc.yy);
-  if (ynorm == 0.0) {
-    res.relres = 0;
-    res.quad = 0;
-    return res;
-  }
+  if (ynorm == 0.0) return res;
   const double target = rtol * ynorm;
   double last_true = ynorm;   // |y - K x| at the latest recomputation
   int it = 0;
@@ -556,16 +586,19 @@ SolveResult pcg_solve(gp_ctx* c, const gp_matrix* m, const double* y, double* x,
         ProfScope ps(c, "pcg_vector_ops");
         hipLaunchKernelGGL((k_pq_part<float>), G, B, 0, c->stream, n, p, q32, part);
         hipLaunchKernelGGL(k_alpha_fin, dim3(1), B, 0, c->stream, part, kRedBlocks, s);
-        hipLaunchKernelGGL((k_pcg_update<float>), G, B, 0, c->stream, n, s, p, q32, m->diag, x, r, z, part);
+        hipLaunchKernelGGL((k_pcg_update<float>), G, B, 0, c->stream, n, s, p, q32, x, r);
       } else {
         spmv_f64(c, m, p, q);
         ProfScope ps(c, "pcg_vector_ops");
         hipLaunchKernelGGL((k_pq_part<double>), G, B, 0, c->stream, n, p, q, part);
         hipLaunchKernelGGL(k_alpha_fin, dim3(1), B, 0, c->stream, part, kRedBlocks, s);
-        hipLaunchKernelGGL((k_pcg_update<double>), G, B, 0, c->stream, n, s, p, q, m->diag, x, r, z, part);
+        hipLaunchKernelGGL((k_pcg_update<double>), G, B, 0, c->stream, n, s, p, q, x, r);
       }
-      hipLaunchKernelGGL(k_beta_fin, dim3(1), B, 0, c->stream, part, kRedBlocks, s, 0);
-      if (t + 1 < steps) hipLaunchKernelGGL(k_pcg_pupdate, G, B, 0, c->stream, n, s, z, p, p32);
+      apply_precond(0);
+      if (t + 1 < steps) {
+        ProfScope ps(c, "pcg_vector_ops");
+        hipLaunchKernelGGL(k_pcg_pupdate, G, B, 0, c->stream, n, s, z, p, p32);
+      }
       check_launch("pcg iteration");
     }
     it += steps;

@@ -127,3 +127,18 @@ def test_deterministic(ctx, cfg1):
         ds, Kg = _setup(ctx, p, 1)
         a.append(ctx.loglik(Kg, dev(y), seed=3))
     assert a[0] == a[1]
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_block_jacobi_matches_jacobi(ctx, cfg1, prec):
+    from paper_2411_05869_amd import LOGDET_NONE, PRECOND_BLOCK_JACOBI, PRECOND_JACOBI
+    p, K, y, ref = cfg1
+    ds, Kg = _setup(ctx, p, prec)
+    out = {}
+    for pc in (PRECOND_JACOBI, PRECOND_BLOCK_JACOBI):
+        out[pc] = ctx.loglik(Kg, dev(y), precond=pc, logdet_mode=LOGDET_NONE)
+    e = {pc: rel(out[pc]["quad"], ref["quad"]) for pc in out}
+    print(f"[precond prec={prec}] iters jacobi {out[0]['cg_iters']} block {out[1]['cg_iters']}; quad errors {e}")
+    tol = 1e-8 if prec == 0 else 1e-5
+    assert e[0] <= tol and e[1] <= tol
+    assert out[1]["cg_iters"] < out[0]["cg_iters"]
