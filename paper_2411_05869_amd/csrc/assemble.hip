@@ -26,7 +26,6 @@ namespace gps {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kLdsList = 512;   // per-wave LDS copy of L'(p)
 
 struct AsmArgs {
   KernelTheta kt;
@@ -47,6 +46,7 @@ struct AsmArgs {
   const int32_t* ulist;     // concatenated U_M lists
   // counts / outputs
   int32_t* counts;          // n
+  int32_t* gskip;           // n: leading group entries of each row (|U_M| or 0)
   int32_t* lcnt;            // nm
   const int64_t* loff;      // nm + 1
   int32_t* lscratch;        // L' lists
@@ -189,24 +189,13 @@ __global__ void __launch_bounds__(kThreads) k_local_rows(AsmArgs a) {
     }
   if constexpr (!FILL) {
     a.counts[p] = cnt;
+    a.gskip[p] = 0;
   } else {
     if (static_cast<int64_t>(cnt) != len) atomicOr(a.err, 1);
   }
 }
 
 // ------------------------------------------------------- rows with groups
-__device__ __forceinline__ int64_t lower_bound_g(const int32_t* __restrict__ v, int64_t len, int32_t key) {
-  int64_t lo = 0, hi = len;
-  while (lo < hi) {
-    const int64_t mid = (lo + hi) >> 1;
-    if (v[mid] < key)
-      lo = mid + 1;
-    else
-      hi = mid;
-  }
-  return lo;
-}
-
 // PASS 0: count L'(p) and the row; PASS 1: write L'(p) to scratch.
 template <int D, int PASS>
 __global__ void __launch_bounds__(kThreads) k_group_rows_scan(AsmArgs a) {
@@ -251,18 +240,21 @@ __global__ void __launch_bounds__(kThreads) k_group_rows_scan(AsmArgs a) {
     if constexpr (PASS == 0) {
       a.lcnt[k] = static_cast<int32_t>(running);
       a.counts[p] = static_cast<int32_t>(nu + running);
+      a.gskip[p] = static_cast<int32_t>(nu);
     } else {
       if (running != a.loff[k + 1] - a.loff[k]) atomicOr(a.err, 2);
     }
   }
 }
 
+// Row layout of a row with group mask M: first the |U_M| group entries in U_M
+// order (ascending column ids; every row with mask M shares this column list,
+// which the group-block products exploit), then the local-only entries L'(p)
+// in ascending order.
 template <int D, typename VT>
 __global__ void __launch_bounds__(kThreads) k_group_rows_fill(AsmArgs a) {
-  __shared__ int32_t lds[kThreads / kWave][kLdsList];
   const int64_t k = (blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x) / kWave;
   if (k >= a.nm) return;
-  const int wv = threadIdx.x / kWave;
   const int lane = lane_id();
   const int32_t p = a.mlist[k];
   const uint64_t mp = a.mask[p];
@@ -281,37 +273,8 @@ __global__ void __launch_bounds__(kThreads) k_group_rows_fill(AsmArgs a) {
     if (lane == 0) atomicOr(a.err, 4);
     return;
   }
-  // local-only entries: position = rank in L' + rank in U
-  for (int64_t j = lane; j < nL; j += kWave) {
-    const int32_t q = L[j];
-    double xq[3];
-    load_point<D>(a.xb, a.n, q, xq);
-    const double u2 = scaled_sq<D>(xp, xq, a.kt.inv0);
-    const double v = entry_value(a.kt, u2, 0, nullptr, nullptr, false);
-    const int64_t pos = j + lower_bound_g(U, nU, q);
-    a.col[out + pos] = q;
-    val[out + pos] = static_cast<VT>(v);
-  }
-  const bool in_lds = nL <= kLdsList;
-  if (in_lds) {
-    for (int64_t j = lane; j < nL; j += kWave) lds[wv][j] = L[j];
-  }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-  const int32_t* Ls = in_lds ? &lds[wv][0] : L;
-  // group entries: position = rank in U + rank in L'
   for (int64_t kk = lane; kk < nU; kk += kWave) {
     const int32_t u = U[kk];
-    int64_t lo = 0, hi = nL;
-    while (lo < hi) {
-      const int64_t mid = (lo + hi) >> 1;
-      if (Ls[mid] < u)
-        lo = mid + 1;
-      else
-        hi = mid;
-    }
-    const int64_t pos = kk + lo;
     double xq[3];
     load_point<D>(a.xb, a.n, u, xq);
     const double u2 = scaled_sq<D>(xp, xq, a.kt.inv0);
@@ -319,19 +282,31 @@ __global__ void __launch_bounds__(kThreads) k_group_rows_fill(AsmArgs a) {
     const double* Fq = a.F + static_cast<int64_t>(a.midx[u]) * a.kt.n1;
     const double v = entry_value(a.kt, u2, shared, Fp, Fq, u == p);
     const VT vs = static_cast<VT>(v);
-    a.col[out + pos] = u;
-    val[out + pos] = vs;
+    a.col[out + kk] = u;
+    val[out + kk] = vs;
     if (u == p) a.diag[p] = static_cast<double>(vs);
+  }
+  for (int64_t j = lane; j < nL; j += kWave) {
+    const int32_t q = L[j];
+    double xq[3];
+    load_point<D>(a.xb, a.n, q, xq);
+    const double u2 = scaled_sq<D>(xp, xq, a.kt.inv0);
+    const double v = entry_value(a.kt, u2, 0, nullptr, nullptr, false);
+    a.col[out + nU + j] = q;
+    val[out + nU + j] = static_cast<VT>(v);
   }
 }
 
+// long rows of the CSR part outside the group blocks (lengths without the
+// leading group entries); also the longest full row
 __global__ void __launch_bounds__(kThreads) k_long_flags(int64_t n, const int32_t* __restrict__ counts,
+                                                         const int32_t* __restrict__ gskip,
                                                          int32_t* __restrict__ flag, int32_t* __restrict__ maxrow) {
   const int64_t p = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x;
   int32_t c = 0;
   if (p < n) {
     c = counts[p];
-    flag[p] = c > kLongRow ? 1 : 0;
+    flag[p] = (c - gskip[p]) > kLongRow ? 1 : 0;
   }
   for (int off = kWave / 2; off > 0; off >>= 1) c = max(c, __shfl_xor(c, off, kWave));
   __shared__ int32_t wmax[kThreads / kWave];
@@ -465,12 +440,14 @@ gp_matrix* assemble(gp_ctx* c, const gp_dataset* ds, const gp_theta* th, int pre
   std::vector<uint64_t> dmask;
   std::vector<int64_t> uoff(1, 0);
   std::vector<int32_t> did(nm);
+  std::vector<int32_t> hmlist(nm);
+  std::vector<int64_t> mult;
   if (nm > 0) {
     GPS_HIP(hipMemcpyAsync(hm.data(), mmask, sizeof(uint64_t) * nm, hipMemcpyDeviceToHost, c->stream));
+    GPS_HIP(hipMemcpyAsync(hmlist.data(), f.mlist, sizeof(int32_t) * nm, hipMemcpyDeviceToHost, c->stream));
     GPS_HIP(hipStreamSynchronize(c->stream));
     std::vector<uint64_t> sorted = hm;
     std::sort(sorted.begin(), sorted.end());
-    std::vector<int64_t> mult;
     for (int64_t i = 0; i < nm; ++i) {
       if (dmask.empty() || dmask.back() != sorted[i]) {
         dmask.push_back(sorted[i]);
@@ -493,22 +470,55 @@ gp_matrix* assemble(gp_ctx* c, const gp_dataset* ds, const gp_theta* th, int pre
   }
   const int64_t nD = static_cast<int64_t>(dmask.size());
   const int64_t utotal = uoff.back();
+  // rows grouped by their mask (stable, so ascending within a mask) and cut into
+  // tiles of at most kTileRows rows for the group-block products
+  std::vector<int32_t> goff(nD + 1, 0), grows(nm);
+  for (int64_t i = 0; i < nm; ++i) ++goff[did[i] + 1];
+  for (int64_t a = 0; a < nD; ++a) goff[a + 1] += goff[a];
+  {
+    std::vector<int32_t> cur(goff.begin(), goff.end() - 1);
+    for (int64_t i = 0; i < nm; ++i) grows[cur[did[i]]++] = hmlist[i];
+  }
+  std::vector<int32_t> tiles;   // (mask id, first index in grows, row count, 0)
+  for (int64_t a = 0; a < nD; ++a)
+    for (int32_t i = goff[a]; i < goff[a + 1]; i += kTileRows)
+      tiles.insert(tiles.end(), {static_cast<int32_t>(a), i, std::min<int32_t>(kTileRows, goff[a + 1] - i), 0});
+
+  std::unique_ptr<gp_matrix> m(new gp_matrix());
+  m->ds = ds;
+  m->n = n;
+  m->prec = prec;
+  m->nugget = th->nugget;
+  m->nD = nD;
+  m->utotal = utotal;
+  m->nm = nm;
+  m->ntiles = static_cast<int64_t>(tiles.size() / 4);
+  m->gskip = dev_new<int32_t>(c, n);
+  m->g_uoff = dev_new<int64_t>(c, nD + 1);
+  m->g_ulist = dev_new<int32_t>(c, std::max<int64_t>(utotal, 1));
+  m->g_rows = dev_new<int32_t>(c, std::max<int64_t>(nm, 1));
+  m->g_tiles = dev_new<int32_t>(c, std::max<int64_t>(4 * m->ntiles, 4));
+  m->bytes += sizeof(int32_t) * (n + utotal + nm + 4 * m->ntiles) + sizeof(int64_t) * (nD + 1);
   int32_t* d_did = static_cast<int32_t*>(workspace(c, 8, sizeof(int32_t) * std::max<int64_t>(nm, 1)));
   uint64_t* d_dmask = static_cast<uint64_t*>(workspace(c, 9, sizeof(uint64_t) * std::max<int64_t>(nD, 1)));
-  int64_t* d_uoff = static_cast<int64_t*>(workspace(c, 10, sizeof(int64_t) * (nD + 1)));
-  int32_t* d_ulist = static_cast<int32_t*>(workspace(c, 11, sizeof(int32_t) * std::max<int64_t>(utotal, 1)));
+  int64_t* d_uoff = m->g_uoff;
+  int32_t* d_ulist = m->g_ulist;
   {
-    const size_t bytes = sizeof(int32_t) * nm + sizeof(uint64_t) * nD + sizeof(int64_t) * (nD + 1);
-    char* st = static_cast<char*>(pinned(c, bytes + 64));
-    std::memcpy(st, did.data(), sizeof(int32_t) * nm);
-    std::memcpy(st + sizeof(int32_t) * nm, dmask.data(), sizeof(uint64_t) * nD);
-    std::memcpy(st + sizeof(int32_t) * nm + sizeof(uint64_t) * nD, uoff.data(), sizeof(int64_t) * (nD + 1));
-    if (nm) GPS_HIP(hipMemcpyAsync(d_did, st, sizeof(int32_t) * nm, hipMemcpyHostToDevice, c->stream));
-    if (nD)
-      GPS_HIP(hipMemcpyAsync(d_dmask, st + sizeof(int32_t) * nm, sizeof(uint64_t) * nD, hipMemcpyHostToDevice,
-                             c->stream));
-    GPS_HIP(hipMemcpyAsync(d_uoff, st + sizeof(int32_t) * nm + sizeof(uint64_t) * nD, sizeof(int64_t) * (nD + 1),
-                           hipMemcpyHostToDevice, c->stream));
+    const size_t b_did = sizeof(int32_t) * nm, b_dm = sizeof(uint64_t) * nD, b_uo = sizeof(int64_t) * (nD + 1);
+    const size_t b_gr = sizeof(int32_t) * nm, b_ti = sizeof(int32_t) * tiles.size();
+    char* st = static_cast<char*>(pinned(c, b_did + b_dm + b_uo + b_gr + b_ti + 64));
+    char* o = st;
+    auto put = [&](const void* src, size_t nb, void* dst) {
+      if (!nb) return;
+      std::memcpy(o, src, nb);
+      GPS_HIP(hipMemcpyAsync(dst, o, nb, hipMemcpyHostToDevice, c->stream));
+      o += nb;
+    };
+    put(did.data(), b_did, d_did);
+    put(dmask.data(), b_dm, d_dmask);
+    put(uoff.data(), b_uo, d_uoff);
+    put(grows.data(), b_gr, m->g_rows);
+    put(tiles.data(), b_ti, m->g_tiles);
     if (nD) {
       ProfScope ps(c, "asm_group_lists");
       hipLaunchKernelGGL(k_ulists, dim3(static_cast<unsigned>(nD)), dim3(kThreads), 0, c->stream, nm, mmask, f.mlist,
@@ -538,6 +548,7 @@ gp_matrix* assemble(gp_ctx* c, const gp_dataset* ds, const gp_theta* th, int pre
   a.uoff = d_uoff;
   a.ulist = d_ulist;
   a.counts = static_cast<int32_t*>(workspace(c, 12, sizeof(int32_t) * n));
+  a.gskip = m->gskip;
   a.lcnt = static_cast<int32_t*>(workspace(c, 13, sizeof(int32_t) * std::max<int64_t>(nm, 1)));
   int64_t* loff = static_cast<int64_t*>(workspace(c, 14, sizeof(int64_t) * (nm + 1)));
   a.loff = loff;
@@ -561,11 +572,6 @@ gp_matrix* assemble(gp_ctx* c, const gp_dataset* ds, const gp_theta* th, int pre
   });
   check_launch("count");
 
-  std::unique_ptr<gp_matrix> m(new gp_matrix());
-  m->ds = ds;
-  m->n = n;
-  m->prec = prec;
-  m->nugget = th->nugget;
   m->row_ptr = dev_new<int64_t>(c, n + 1);
   m->bytes += sizeof(int64_t) * (n + 1);
   scan_i32_to_i64(c, a.counts, m->row_ptr, n);
@@ -574,8 +580,8 @@ gp_matrix* assemble(gp_ctx* c, const gp_dataset* ds, const gp_theta* th, int pre
   int32_t* lpos = static_cast<int32_t*>(workspace(c, 16, sizeof(int32_t) * (n + 1)));
   int32_t* maxrow = static_cast<int32_t*>(workspace(c, 17, sizeof(int32_t) * 2));
   GPS_HIP(hipMemsetAsync(maxrow, 0, sizeof(int32_t), c->stream));
-  hipLaunchKernelGGL(k_long_flags, dim3(grid_for(n, kThreads)), dim3(kThreads), 0, c->stream, n, a.counts, lflag,
-                     maxrow);
+  hipLaunchKernelGGL(k_long_flags, dim3(grid_for(n, kThreads)), dim3(kThreads), 0, c->stream, n, a.counts,
+                     m->gskip, lflag, maxrow);
   check_launch("long flags");
   scan_i32_to_i32(c, lflag, lpos, n);
   // one synchronisation: nnz, |L'| total, number of long rows, longest row
@@ -657,6 +663,11 @@ void destroy_matrix(gp_ctx* c, gp_matrix* m) {
   if (m->diag) dev_free(c, m->diag, sizeof(double) * m->n);
   if (m->long_rows) dev_free(c, m->long_rows, sizeof(int32_t) * std::max<int64_t>(m->n_long, 1));
   free_block_jacobi(c, m);
+  if (m->gskip) dev_free(c, m->gskip, sizeof(int32_t) * m->n);
+  if (m->g_uoff) dev_free(c, m->g_uoff, sizeof(int64_t) * (m->nD + 1));
+  if (m->g_ulist) dev_free(c, m->g_ulist, sizeof(int32_t) * std::max<int64_t>(m->utotal, 1));
+  if (m->g_rows) dev_free(c, m->g_rows, sizeof(int32_t) * std::max<int64_t>(m->nm, 1));
+  if (m->g_tiles) dev_free(c, m->g_tiles, sizeof(int32_t) * std::max<int64_t>(4 * m->ntiles, 4));
   delete m;
 }
 

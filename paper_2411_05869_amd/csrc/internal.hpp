@@ -17,6 +17,7 @@ constexpr int kMaxGroups = 64;      // n1 <= 64: group membership is one uint64 
 constexpr int kMaxBumps = 4096;     // n1 * n2
 constexpr int kLongRow = 128;       // rows longer than this get a wave of their own in SpMV
 constexpr int64_t kCsrPad = 64;     // padding entries after the CSR column and value arrays
+constexpr int kTileRows = 16;       // rows per tile of a group block
 
 // ------------------------------------------------------------------ errors
 struct Error {
@@ -105,6 +106,15 @@ struct gp_matrix {
   double* diag = nullptr;       // n, diagonal of the stored matrix (float64)
   int32_t* long_rows = nullptr; // rows with more than kLongRow entries
   int64_t n_long = 0;
+  // rows with a bump-group mask start with the group entries of their mask
+  // (|U_M| entries, shared column list U_M); the products treat these as dense
+  // blocks (rows with mask M) x (columns U_M)
+  int32_t* gskip = nullptr;     // n: number of leading group entries of each row
+  int64_t nD = 0, utotal = 0, nm = 0, ntiles = 0;
+  int64_t* g_uoff = nullptr;    // nD + 1 offsets into g_ulist
+  int32_t* g_ulist = nullptr;   // concatenated U_M (binned column ids, ascending)
+  int32_t* g_rows = nullptr;    // rows with a mask, grouped by mask
+  int32_t* g_tiles = nullptr;   // ntiles x (mask id, first index in g_rows, rows, 0)
   // block-Jacobi preconditioner, built on first use (blocks = binning cells)
   int64_t nblk = 0, binv_len = 0;
   int32_t* bstart = nullptr;    // nblk + 1 block starts (binned rows)

@@ -62,6 +62,7 @@ template <typename VT>
 __global__ void __launch_bounds__(kThreads) k_block_invert(int64_t nblk, const int32_t* __restrict__ bstart,
                                                            const int64_t* __restrict__ boff,
                                                            const int64_t* __restrict__ rp,
+                                                           const int32_t* __restrict__ gskip,
                                                            const int32_t* __restrict__ col, const VT* __restrict__ val,
                                                            double* __restrict__ binv, int* __restrict__ bad) {
   const int64_t b = (blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x) / kWave;
@@ -73,22 +74,25 @@ __global__ void __launch_bounds__(kThreads) k_block_invert(int64_t nblk, const i
 #pragma unroll
   for (int j = 0; j < kMaxBlock; ++j) a[j] = 0.0;
   if (lane < sz) {
+    // a row holds two runs of ascending columns: its group entries, then the rest
     const int32_t row = bs + lane;
-    int64_t lo = rp[row], hi = rp[row + 1];
-    // first entry with column >= bs
-    while (lo < hi) {
-      const int64_t mid = (lo + hi) >> 1;
-      if (col[mid] < bs)
-        lo = mid + 1;
-      else
-        hi = mid;
-    }
-    for (int64_t j = lo; j < rp[row + 1]; ++j) {
-      const int32_t cidx = col[j] - bs;
-      if (cidx >= sz) break;
+    const int64_t runs[3] = {rp[row], rp[row] + gskip[row], rp[row + 1]};
+    for (int rr = 0; rr < 2; ++rr) {
+      int64_t lo = runs[rr], hi = runs[rr + 1];
+      while (lo < hi) {  // first entry with column >= bs
+        const int64_t mid = (lo + hi) >> 1;
+        if (col[mid] < bs)
+          lo = mid + 1;
+        else
+          hi = mid;
+      }
+      for (int64_t j = lo; j < runs[rr + 1]; ++j) {
+        const int32_t cidx = col[j] - bs;
+        if (cidx >= sz) break;
 #pragma unroll
-      for (int t = 0; t < kMaxBlock; ++t)
-        if (t == cidx) a[t] = static_cast<double>(val[j]);
+        for (int t = 0; t < kMaxBlock; ++t)
+          if (t == cidx) a[t] = static_cast<double>(val[j]);
+      }
     }
   }
   // in-place Gauss-Jordan inversion (symmetric positive definite: no pivoting)
@@ -163,11 +167,11 @@ void build_block_jacobi(gp_ctx* c, gp_matrix* m) {
     ProfScope ps(c, "precond_setup");
     if (m->prec == GP_MIXED)
       hipLaunchKernelGGL((k_block_invert<float>), dim3(grid_for(nblk * kWave, kThreads)), dim3(kThreads), 0,
-                         c->stream, nblk, m->bstart, m->boff, m->row_ptr, m->col, static_cast<const float*>(m->val),
+                         c->stream, nblk, m->bstart, m->boff, m->row_ptr, m->gskip, m->col, static_cast<const float*>(m->val),
                          m->binv, c->err_flag);
     else
       hipLaunchKernelGGL((k_block_invert<double>), dim3(grid_for(nblk * kWave, kThreads)), dim3(kThreads), 0,
-                         c->stream, nblk, m->bstart, m->boff, m->row_ptr, m->col, static_cast<const double*>(m->val),
+                         c->stream, nblk, m->bstart, m->boff, m->row_ptr, m->gskip, m->col, static_cast<const double*>(m->val),
                          m->binv, c->err_flag);
     check_launch("block inverse");
   }

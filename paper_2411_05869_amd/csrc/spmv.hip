@@ -46,12 +46,15 @@ __device__ __forceinline__ AT spmv_part(int64_t s, int64_t e, int sub, int32_t s
   return acc;
 }
 
+// CSR part of the product (entries after each row's leading group entries).
 // One launch: blocks [0, nb_long) take the listed long rows, one wave per row
 // (dispatched first, they set the tail); the remaining blocks take rows of at
-// most kLongRow entries with kG lanes per row.
+// most kLongRow entries with kG lanes per row.  Rows with group entries add
+// the group-block part that k_group_spmv wrote to y before.
 template <typename VT, typename XT, typename AT, typename YT>
 __global__ void __launch_bounds__(kThreads) k_spmv(int64_t n, unsigned nb_long, int64_t nlong,
                                                    const int32_t* __restrict__ rows, const int64_t* __restrict__ rp,
+                                                   const int32_t* __restrict__ gskip,
                                                    const int32_t* __restrict__ col, const VT* __restrict__ val,
                                                    const XT* __restrict__ x, YT* __restrict__ y) {
   if (blockIdx.x >= nb_long) {
@@ -59,23 +62,25 @@ __global__ void __launch_bounds__(kThreads) k_spmv(int64_t n, unsigned nb_long, 
     const int64_t row = (b * static_cast<int64_t>(kThreads) + threadIdx.x) / kG;
     const int sub = threadIdx.x & (kG - 1);
     if (row >= n) return;
-    const int64_t s = rp[row], e = rp[row + 1];
+    const int32_t gs = gskip[row];
+    const int64_t s = rp[row] + gs, e = rp[row + 1];
     if (e - s > kLongRow) return;  // uniform within the group
     AT acc = spmv_part<VT, XT, AT, kG>(s, e, sub, static_cast<int32_t>(row), col, val, x);
 #pragma unroll
     for (int off = kG / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kG);
-    if (sub == 0) y[row] = static_cast<YT>(acc);
+    if (sub == 0) y[row] = static_cast<YT>(gs ? static_cast<AT>(y[row]) + acc : acc);
   } else {
     const unsigned b = xcd_remap(blockIdx.x, nb_long);
     const int64_t w = (b * static_cast<int64_t>(kThreads) + threadIdx.x) / kWave;
     if (w >= nlong) return;
     const int lane = lane_id();
     const int32_t row = rows[w];
-    const int64_t s = rp[row], e = rp[row + 1];
+    const int32_t gs = gskip[row];
+    const int64_t s = rp[row] + gs, e = rp[row + 1];
     AT acc = spmv_part<VT, XT, AT, kWave>(s, e, lane, row, col, val, x);
 #pragma unroll
     for (int off = kWave / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kWave);
-    if (lane == 0) y[row] = static_cast<YT>(acc);
+    if (lane == 0) y[row] = static_cast<YT>(gs ? static_cast<AT>(y[row]) + acc : acc);
   }
 }
 
@@ -136,7 +141,8 @@ __device__ __forceinline__ T spmm_chunk(int64_t j0, int64_t e, int32_t self, con
 template <typename VT, typename T, bool SCALE>
 __global__ void __launch_bounds__(kThreads) k_spmm(int64_t n, unsigned nb_short, int64_t nlong,
                                                    const int32_t* __restrict__ rows, int k, int ld,
-                                                   const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                                   const int64_t* __restrict__ rp, const int32_t* __restrict__ gskip,
+                                                   const int32_t* __restrict__ col,
                                                    const VT* __restrict__ val, const T* __restrict__ X,
                                                    T* __restrict__ Y, const T* __restrict__ scale) {
   const int lane = lane_id();
@@ -147,13 +153,15 @@ __global__ void __launch_bounds__(kThreads) k_spmm(int64_t n, unsigned nb_short,
   if (blockIdx.x < nb_short) {
     const int64_t row = xcd_remap(blockIdx.x, nb_short) * static_cast<int64_t>(kThreads / kWave) + w;
     if (row >= n) return;
-    const int64_t s = rp[row], e = rp[row + 1];
+    const int32_t gs = gskip[row];
+    const int64_t s = rp[row] + gs, e = rp[row + 1];
     if (e - s > kLongRow) return;
     T acc = 0;
     for (int64_t j0 = s; j0 < e; j0 += kWave)
       acc += spmm_chunk<VT, T, SCALE>(j0, e, static_cast<int32_t>(row), col, val, X, scale, ld, cl, lane, h);
     acc += __shfl_xor(acc, 32, kWave);
     if (h == 0 && c < k) {
+      if (gs) acc = Y[row * ld + c] + acc;
       if constexpr (SCALE) acc *= scale[row];
       Y[row * ld + c] = acc;
     }
@@ -162,7 +170,8 @@ __global__ void __launch_bounds__(kThreads) k_spmm(int64_t n, unsigned nb_short,
     const int64_t li = xcd_remap(blockIdx.x - nb_short, gridDim.x - nb_short);
     if (li >= nlong) return;  // uniform over the block
     const int32_t row = rows[li];
-    const int64_t s = rp[row], e = rp[row + 1];
+    const int32_t gs = gskip[row];
+    const int64_t s = rp[row] + gs, e = rp[row + 1];
     T acc = 0;
     for (int64_t j0 = s + static_cast<int64_t>(w) * kWave; j0 < e; j0 += kThreads)
       acc += spmm_chunk<VT, T, SCALE>(j0, e, row, col, val, X, scale, ld, cl, lane, h);
@@ -173,9 +182,63 @@ __global__ void __launch_bounds__(kThreads) k_spmm(int64_t n, unsigned nb_short,
       T t = part[0][c];
 #pragma unroll
       for (int i = 1; i < kThreads / kWave; ++i) t += part[i][c];
+      if (gs) t = Y[static_cast<int64_t>(row) * ld + c] + t;
       if constexpr (SCALE) t *= scale[row];
       Y[static_cast<int64_t>(row) * ld + c] = t;
     }
+  }
+}
+
+// Group-block part of the product: for the rows of one tile (same mask M,
+// at most kTileRows rows) y[row] = sum_k val[row, k] x[U_M[k]] over the
+// row's leading |U_M| entries.  x[U_M] is staged in LDS one chunk at a time
+// and each staged value serves the four rows a wave owns.
+constexpr int kGChunk = 1024;
+
+template <typename VT, typename XT, typename AT, typename YT>
+__global__ void __launch_bounds__(kThreads) k_group_spmv(const int32_t* __restrict__ tiles,
+                                                         const int32_t* __restrict__ grows,
+                                                         const int64_t* __restrict__ uoff,
+                                                         const int32_t* __restrict__ ulist,
+                                                         const int64_t* __restrict__ rp, const VT* __restrict__ val,
+                                                         const XT* __restrict__ x, YT* __restrict__ y) {
+  __shared__ AT xs[kGChunk];
+  constexpr int kRows = kTileRows / (kThreads / kWave);
+  const int4 t = reinterpret_cast<const int4*>(tiles)[xcd_remap(blockIdx.x, gridDim.x)];
+  const int32_t* U = ulist + uoff[t.x];
+  const int64_t nU = uoff[t.x + 1] - uoff[t.x];
+  const int w = threadIdx.x / kWave, lane = lane_id();
+  int64_t base[kRows];
+  bool has[kRows];
+#pragma unroll
+  for (int r = 0; r < kRows; ++r) {
+    const int i = w + r * (kThreads / kWave);
+    has[r] = i < t.z;
+    base[r] = has[r] ? rp[grows[t.y + i]] : 0;
+  }
+  AT acc[kRows];
+#pragma unroll
+  for (int r = 0; r < kRows; ++r) acc[r] = 0;
+  for (int64_t c0 = 0; c0 < nU; c0 += kGChunk) {
+    const int clen = static_cast<int>(min<int64_t>(kGChunk, nU - c0));
+    __syncthreads();
+    for (int k = threadIdx.x; k < clen; k += kThreads) xs[k] = static_cast<AT>(x[U[c0 + k]]);
+    __syncthreads();
+    for (int k = lane; k < clen; k += kWave) {
+      const AT xk = xs[k];
+      AT v[kRows];
+#pragma unroll
+      for (int r = 0; r < kRows; ++r) v[r] = has[r] ? static_cast<AT>(val[base[r] + c0 + k]) : AT(0);
+#pragma unroll
+      for (int r = 0; r < kRows; ++r) acc[r] += v[r] * xk;
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < kRows; ++r) {
+    AT a = acc[r];
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) a += __shfl_xor(a, off, kWave);
+    if (lane == 0 && has[r]) y[grows[t.y + w + r * (kThreads / kWave)]] = static_cast<YT>(a);
   }
 }
 
@@ -187,8 +250,11 @@ void spmv_impl(gp_ctx* c, const gp_matrix* m, const XT* x, YT* y) {
   const unsigned nb_short = grid_for(m->n * kG, kThreads);
   const unsigned nb_long = m->n_long > 0 ? round_up8(grid_for(m->n_long * kWave, kThreads)) : 0;
   ProfScope ps(c, sizeof(VT) == 4 ? (sizeof(XT) == 4 ? "spmv_f32" : "spmv_f32val_f64") : "spmv_f64");
+  if (m->ntiles > 0)
+    hipLaunchKernelGGL((k_group_spmv<VT, XT, AT, YT>), dim3(static_cast<unsigned>(m->ntiles)), dim3(kThreads), 0,
+                       c->stream, m->g_tiles, m->g_rows, m->g_uoff, m->g_ulist, m->row_ptr, val, x, y);
   hipLaunchKernelGGL((k_spmv<VT, XT, AT, YT>), dim3(nb_short + nb_long), dim3(kThreads), 0, c->stream, m->n,
-                     nb_long, m->n_long, m->long_rows, m->row_ptr, m->col, val, x, y);
+                     nb_long, m->n_long, m->long_rows, m->row_ptr, m->gskip, m->col, val, x, y);
   check_launch("spmv");
 }
 
@@ -208,6 +274,75 @@ void spmv_f32(gp_ctx* c, const gp_matrix* m, const float* x, float* y) {
     spmv_impl<double, float, float, float>(c, m, x, y);
 }
 
+// Group-block part of the SpMM: for the rows of one tile (same mask M),
+// Y[row, :] = sum_k val[row, k] scale[u_k] X[u_k, :] over U_M = (u_k) (the row
+// scaling is applied by the CSR part).  Chunks of kMChunk rows of X (scaled)
+// are staged in LDS; each wave owns kRows rows, stages their values for the
+// chunk in its own LDS slice, and lane (c, h) adds the entries k = h, h + 2, ...
+// of column c, so every X value read from LDS feeds kRows multiply-adds.
+constexpr int kMChunk = 64;
+
+template <typename VT, typename T, bool SCALE>
+__global__ void __launch_bounds__(kThreads) k_group_spmm(const int32_t* __restrict__ tiles,
+                                                         const int32_t* __restrict__ grows,
+                                                         const int64_t* __restrict__ uoff,
+                                                         const int32_t* __restrict__ ulist, int k, int ld,
+                                                         const int64_t* __restrict__ rp, const VT* __restrict__ val,
+                                                         const T* __restrict__ X, T* __restrict__ Y,
+                                                         const T* __restrict__ scale) {
+  constexpr int kW = kThreads / kWave;
+  constexpr int kRows = kTileRows / kW;
+  __shared__ T xs[kMChunk][32];
+  __shared__ T vs[kW][kRows][kMChunk];
+  const int4 t = reinterpret_cast<const int4*>(tiles)[xcd_remap(blockIdx.x, gridDim.x)];
+  const int32_t* U = ulist + uoff[t.x];
+  const int64_t nU = uoff[t.x + 1] - uoff[t.x];
+  const int w = threadIdx.x / kWave, lane = lane_id();
+  const int c = lane & 31, h = lane >> 5;
+  const int cl = c < k ? c : k - 1;
+  int64_t base[kRows];
+  bool has[kRows];
+#pragma unroll
+  for (int r = 0; r < kRows; ++r) {
+    const int i = w + r * kW;
+    has[r] = i < t.z;
+    base[r] = has[r] ? rp[grows[t.y + i]] : 0;
+  }
+  T acc[kRows];
+#pragma unroll
+  for (int r = 0; r < kRows; ++r) acc[r] = 0;
+  for (int64_t c0 = 0; c0 < nU; c0 += kMChunk) {
+    const int clen = static_cast<int>(min<int64_t>(kMChunk, nU - c0));
+    __syncthreads();
+    // stage X rows of the chunk: thread -> (row of chunk, column)
+    for (int idx = threadIdx.x; idx < kMChunk * 32; idx += kThreads) {
+      const int kk = idx >> 5, cc = idx & 31;
+      T v = 0;
+      if (kk < clen && cc < k) {
+        const int32_t q = U[c0 + kk];
+        v = X[static_cast<int64_t>(q) * ld + cc];
+        if constexpr (SCALE) v *= scale[q];
+      }
+      xs[kk][cc] = v;
+    }
+    // this wave's rows: values of the chunk
+#pragma unroll
+    for (int r = 0; r < kRows; ++r)
+      vs[w][r][lane] = (has[r] && lane < clen) ? static_cast<T>(val[base[r] + c0 + lane]) : T(0);
+    __syncthreads();
+    for (int kk = h; kk < clen; kk += 2) {
+      const T xv = xs[kk][cl];
+#pragma unroll
+      for (int r = 0; r < kRows; ++r) acc[r] += vs[w][r][kk] * xv;
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < kRows; ++r) {
+    const T a = acc[r] + __shfl_xor(acc[r], 32, kWave);
+    if (h == 0 && c < k && has[r]) Y[static_cast<int64_t>(grows[t.y + w + r * kW]) * ld + c] = a;
+  }
+}
+
 template <typename T>
 void spmm(gp_ctx* c, const gp_matrix* m, int k, int ld, const T* X, T* Y, const T* scale) {
   if (k > 32 || ld < k) throw Error{GP_EINVAL, "spmm: at most 32 right-hand sides per call"};
@@ -217,8 +352,13 @@ void spmm(gp_ctx* c, const gp_matrix* m, int k, int ld, const T* X, T* Y, const 
   auto go = [&](auto vt, auto sc) {
     using VT = decltype(vt);
     constexpr bool SC = decltype(sc)::value;
+    if (m->ntiles > 0)
+      hipLaunchKernelGGL((k_group_spmm<VT, T, SC>), dim3(static_cast<unsigned>(m->ntiles)), dim3(kThreads), 0,
+                         c->stream, m->g_tiles, m->g_rows, m->g_uoff, m->g_ulist, k, ld, m->row_ptr,
+                         static_cast<const VT*>(m->val), X, Y, scale);
     hipLaunchKernelGGL((k_spmm<VT, T, SC>), dim3(nb), dim3(kThreads), 0, c->stream, m->n, nb_short, m->n_long,
-                       m->long_rows, k, ld, m->row_ptr, m->col, static_cast<const VT*>(m->val), X, Y, scale);
+                       m->long_rows, k, ld, m->row_ptr, m->gskip, m->col, static_cast<const VT*>(m->val), X, Y,
+                       scale);
   };
   if (m->prec == GP_MIXED) {
     if (scale)
