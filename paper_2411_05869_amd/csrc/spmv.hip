@@ -219,18 +219,39 @@ __global__ void __launch_bounds__(kThreads) k_group_spmv(const int32_t* __restri
   AT acc[kRows];
 #pragma unroll
   for (int r = 0; r < kRows; ++r) acc[r] = 0;
+  constexpr int kPer = kGChunk / kThreads;
+  AT xr[kPer];
+  auto load = [&](int64_t c0) {
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+      const int64_t k = c0 + threadIdx.x + i * kThreads;
+      xr[i] = k < nU ? static_cast<AT>(x[U[k]]) : AT(0);
+    }
+  };
+  load(0);
   for (int64_t c0 = 0; c0 < nU; c0 += kGChunk) {
     const int clen = static_cast<int>(min<int64_t>(kGChunk, nU - c0));
-    __syncthreads();
-    for (int k = threadIdx.x; k < clen; k += kThreads) xs[k] = static_cast<AT>(x[U[c0 + k]]);
-    __syncthreads();
-    for (int k = lane; k < clen; k += kWave) {
-      const AT xk = xs[k];
-      AT v[kRows];
+    __syncthreads();  // the previous chunk has been consumed
 #pragma unroll
-      for (int r = 0; r < kRows; ++r) v[r] = has[r] ? static_cast<AT>(val[base[r] + c0 + k]) : AT(0);
+    for (int i = 0; i < kPer; ++i) xs[threadIdx.x + i * kThreads] = xr[i];
+    __syncthreads();
+    if (c0 + kGChunk < nU) load(c0 + kGChunk);   // in flight while this chunk is consumed
+    for (int k0 = lane; k0 < clen; k0 += 4 * kWave) {
+      AT v[4][kRows];
 #pragma unroll
-      for (int r = 0; r < kRows; ++r) acc[r] += v[r] * xk;
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int r = 0; r < kRows; ++r) {
+          const int k = k0 + u * kWave;
+          v[u][r] = (has[r] && k < clen) ? static_cast<AT>(val[base[r] + c0 + k]) : AT(0);
+        }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int k = k0 + u * kWave;
+        const AT xk = k < clen ? xs[k] : AT(0);
+#pragma unroll
+        for (int r = 0; r < kRows; ++r) acc[r] += v[u][r] * xk;
+      }
     }
   }
 #pragma unroll
