@@ -479,10 +479,23 @@ gp_matrix* assemble(gp_ctx* c, const gp_dataset* ds, const gp_theta* th, int pre
     std::vector<int32_t> cur(goff.begin(), goff.end() - 1);
     for (int64_t i = 0; i < nm; ++i) grows[cur[did[i]]++] = hmlist[i];
   }
-  std::vector<int32_t> tiles;   // (mask id, first index in grows, row count, 0)
-  for (int64_t a = 0; a < nD; ++a)
+  std::vector<int32_t> tiles, stiles, pieces;
+  for (int64_t a = 0; a < nD; ++a) {
+    const int32_t nu = static_cast<int32_t>(uoff[a + 1] - uoff[a]);
     for (int32_t i = goff[a]; i < goff[a + 1]; i += kTileRows)
       tiles.insert(tiles.end(), {static_cast<int32_t>(a), i, std::min<int32_t>(kTileRows, goff[a + 1] - i), 0});
+    for (int32_t i = goff[a]; i < goff[a + 1]; i += kSuperRows) {
+      const int32_t rows = std::min<int32_t>(kSuperRows, goff[a + 1] - i);
+      const int32_t np = (nu + kPiece - 1) / kPiece;
+      stiles.insert(stiles.end(), {i, rows, static_cast<int32_t>(pieces.size() / 4), np});
+      for (int32_t k0 = 0; k0 < nu; k0 += kPiece) pieces.insert(pieces.end(), {static_cast<int32_t>(a), i, rows, k0});
+    }
+  }
+  const int64_t ntiles = static_cast<int64_t>(tiles.size() / 4);
+  const int64_t nstiles = static_cast<int64_t>(stiles.size() / 4);
+  const int64_t npieces = static_cast<int64_t>(pieces.size() / 4);
+  tiles.insert(tiles.end(), stiles.begin(), stiles.end());
+  tiles.insert(tiles.end(), pieces.begin(), pieces.end());
 
   std::unique_ptr<gp_matrix> m(new gp_matrix());
   m->ds = ds;
@@ -492,13 +505,15 @@ gp_matrix* assemble(gp_ctx* c, const gp_dataset* ds, const gp_theta* th, int pre
   m->nD = nD;
   m->utotal = utotal;
   m->nm = nm;
-  m->ntiles = static_cast<int64_t>(tiles.size() / 4);
+  m->ntiles = ntiles;
+  m->nstiles = nstiles;
+  m->npieces = npieces;
   m->gskip = dev_new<int32_t>(c, n);
   m->g_uoff = dev_new<int64_t>(c, nD + 1);
   m->g_ulist = dev_new<int32_t>(c, std::max<int64_t>(utotal, 1));
   m->g_rows = dev_new<int32_t>(c, std::max<int64_t>(nm, 1));
-  m->g_tiles = dev_new<int32_t>(c, std::max<int64_t>(4 * m->ntiles, 4));
-  m->bytes += sizeof(int32_t) * (n + utotal + nm + 4 * m->ntiles) + sizeof(int64_t) * (nD + 1);
+  m->g_tiles = dev_new<int32_t>(c, std::max<int64_t>(4 * (ntiles + nstiles + npieces), 4));
+  m->bytes += sizeof(int32_t) * (n + utotal + nm + 4 * (ntiles + nstiles + npieces)) + sizeof(int64_t) * (nD + 1);
   int32_t* d_did = static_cast<int32_t*>(workspace(c, 8, sizeof(int32_t) * std::max<int64_t>(nm, 1)));
   uint64_t* d_dmask = static_cast<uint64_t*>(workspace(c, 9, sizeof(uint64_t) * std::max<int64_t>(nD, 1)));
   int64_t* d_uoff = m->g_uoff;
@@ -667,7 +682,8 @@ void destroy_matrix(gp_ctx* c, gp_matrix* m) {
   if (m->g_uoff) dev_free(c, m->g_uoff, sizeof(int64_t) * (m->nD + 1));
   if (m->g_ulist) dev_free(c, m->g_ulist, sizeof(int32_t) * std::max<int64_t>(m->utotal, 1));
   if (m->g_rows) dev_free(c, m->g_rows, sizeof(int32_t) * std::max<int64_t>(m->nm, 1));
-  if (m->g_tiles) dev_free(c, m->g_tiles, sizeof(int32_t) * std::max<int64_t>(4 * m->ntiles, 4));
+  if (m->g_tiles)
+    dev_free(c, m->g_tiles, sizeof(int32_t) * std::max<int64_t>(4 * (m->ntiles + m->nstiles + m->npieces), 4));
   delete m;
 }
 

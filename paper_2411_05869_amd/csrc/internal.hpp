@@ -18,6 +18,8 @@ constexpr int kMaxBumps = 4096;     // n1 * n2
 constexpr int kLongRow = 128;       // rows longer than this get a wave of their own in SpMV
 constexpr int64_t kCsrPad = 64;     // padding entries after the CSR column and value arrays
 constexpr int kTileRows = 16;       // rows per tile of a group block
+constexpr int kSuperRows = 64;      // rows per super-tile (multi-column products)
+constexpr int kPiece = 256;         // U_M entries per block of a multi-column product
 
 // ------------------------------------------------------------------ errors
 struct Error {
@@ -110,11 +112,16 @@ struct gp_matrix {
   // (|U_M| entries, shared column list U_M); the products treat these as dense
   // blocks (rows with mask M) x (columns U_M)
   int32_t* gskip = nullptr;     // n: number of leading group entries of each row
-  int64_t nD = 0, utotal = 0, nm = 0, ntiles = 0;
+  int64_t nD = 0, utotal = 0, nm = 0, ntiles = 0, nstiles = 0, npieces = 0;
   int64_t* g_uoff = nullptr;    // nD + 1 offsets into g_ulist
   int32_t* g_ulist = nullptr;   // concatenated U_M (binned column ids, ascending)
   int32_t* g_rows = nullptr;    // rows with a mask, grouped by mask
-  int32_t* g_tiles = nullptr;   // ntiles x (mask id, first index in g_rows, rows, 0)
+  // ntiles tiles of at most kTileRows rows, each (mask id, first index in
+  // g_rows, rows, 0); then nstiles super-tiles of at most kSuperRows rows, each
+  // (first index in g_rows, rows, first piece, pieces); then npieces pieces,
+  // each (mask id, first index in g_rows, rows, first U_M entry): a piece is
+  // a super-tile's rows times at most kPiece consecutive entries of U_M
+  int32_t* g_tiles = nullptr;
   // block-Jacobi preconditioner, built on first use (blocks = binning cells)
   int64_t nblk = 0, binv_len = 0;
   int32_t* bstart = nullptr;    // nblk + 1 block starts (binned rows)

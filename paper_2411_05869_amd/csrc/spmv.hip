@@ -295,88 +295,242 @@ void spmv_f32(gp_ctx* c, const gp_matrix* m, const float* x, float* y) {
     spmv_impl<double, float, float, float>(c, m, x, y);
 }
 
-// Group-block part of the SpMM: for the rows of one tile (same mask M),
-// Y[row, :] = sum_k val[row, k] scale[u_k] X[u_k, :] over U_M = (u_k) (the row
-// scaling is applied by the CSR part).  Chunks of kMChunk rows of X (scaled)
-// are staged in LDS; each wave owns kRows rows, stages their values for the
-// chunk in its own LDS slice, and lane (c, h) adds the entries k = h, h + 2, ...
-// of column c, so every X value read from LDS feeds kRows multiply-adds.
-constexpr int kMChunk = 64;
+namespace {
+
+// Group-block part of the SpMM on the matrix cores.  For the rows of one
+// super-tile (same mask M, at most kSuperRows rows) the product is the dense
+// contraction Y[rows, 0:32] = V[rows, U_M] (S X)[U_M, 0:32] (the row scaling is
+// applied by the CSR part).  One block takes one piece: the super-tile's rows
+// times at most kPiece consecutive entries of U_M, so that every block does a
+// similar amount of work whatever |U_M| is.  The piece's column ids and
+// scales are read into LDS first; then chunks of kMChunk rows of S X are
+// staged in LDS (double-buffered) and shared by the eight waves: waves w and
+// w + 4 own the 16 rows 16 w ... 16 w + 15 and take the first and second half
+// of the k-steps of each chunk on the 16x16x4 MFMA.  Lane (i, kk) = (lane %
+// 16, lane / 16) holds A[i][kk] = V[row 16 w + i, 4 s + kk] and B[kk][i] =
+// (S X)[U_M[4 s + kk], i] (a second MFMA covers columns 16-31).  The halves
+// are added in a fixed order; a super-tile of one piece writes Y, otherwise
+// each piece writes its partial block and k_group_reduce adds the pieces in
+// order, so the result is deterministic.  Lane l of an MFMA result holds
+// four entries v = 0..3 of column l % 16: rows l / 16 + 4 v for the FP64
+// instruction, rows 4 (l / 16) + v for FP32.
+typedef double mfma_d4 __attribute__((ext_vector_type(4)));
+typedef float mfma_f4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ mfma_d4 mfma16x16x4(double a, double b, mfma_d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ mfma_f4 mfma16x16x4(float a, float b, mfma_f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+template <typename T>
+struct MfmaAcc;
+template <>
+struct MfmaAcc<double> {
+  using type = mfma_d4;
+  static __device__ __forceinline__ int row(int kk, int v) { return kk + 4 * v; }
+};
+template <>
+struct MfmaAcc<float> {
+  using type = mfma_f4;
+  static __device__ __forceinline__ int row(int kk, int v) { return 4 * kk + v; }
+};
+
+constexpr int kMThreads = 512;                   // 8 waves: 4 row groups x 2 halves of each chunk
+constexpr int kMChunk = 64;                      // U_M entries per staged chunk
+constexpr int kMSteps = kMChunk / 4 / 2;         // MFMA k-steps per wave per chunk
+constexpr int kXPer = kMChunk * 32 / kMThreads;  // X values staged per thread
+static_assert(kSuperRows == 4 * 16, "one row group of 16 per wave pair");
+static_assert(kMSteps == 8 && kMChunk == 64, "lane (i, kk) of a wave half takes 8 consecutive entries");
+static_assert(kPiece % kMChunk == 0 && kPiece <= kMThreads, "piece = whole chunks, ids loaded in one pass");
 
 template <typename VT, typename T, bool SCALE>
-__global__ void __launch_bounds__(kThreads) k_group_spmm(const int32_t* __restrict__ tiles,
-                                                         const int32_t* __restrict__ grows,
-                                                         const int64_t* __restrict__ uoff,
-                                                         const int32_t* __restrict__ ulist, int k, int ld,
-                                                         const int64_t* __restrict__ rp, const VT* __restrict__ val,
-                                                         const T* __restrict__ X, T* __restrict__ Y,
-                                                         const T* __restrict__ scale) {
-  constexpr int kW = kThreads / kWave;
-  constexpr int kRows = kTileRows / kW;
-  __shared__ T xs[kMChunk][32];
-  __shared__ T vs[kW][kRows][kMChunk];
-  const int4 t = reinterpret_cast<const int4*>(tiles)[xcd_remap(blockIdx.x, gridDim.x)];
-  const int32_t* U = ulist + uoff[t.x];
-  const int64_t nU = uoff[t.x + 1] - uoff[t.x];
+__global__ void __launch_bounds__(kMThreads) k_group_spmm_mfma(const int32_t* __restrict__ pieces,
+                                                               const int32_t* __restrict__ grows,
+                                                               const int64_t* __restrict__ uoff,
+                                                               const int32_t* __restrict__ ulist, int k, int ld,
+                                                               const int64_t* __restrict__ rp,
+                                                               const VT* __restrict__ val, const T* __restrict__ X,
+                                                               T* __restrict__ Y, const T* __restrict__ scale,
+                                                               T* __restrict__ part) {
+  using Acc = typename MfmaAcc<T>::type;
+  __shared__ T xs[2][kMChunk][33];
+  __shared__ int32_t us[kPiece];
+  __shared__ T ss[SCALE ? kPiece : 1];
+  const unsigned pid = xcd_remap(blockIdx.x, gridDim.x);
+  const int4 t = reinterpret_cast<const int4*>(pieces)[pid];
+  const int nUall = static_cast<int>(uoff[t.x + 1] - uoff[t.x]);
+  const int kstart = t.w;
+  const int len = min(kPiece, nUall - kstart);
+  const bool whole = kstart == 0 && len == nUall;   // the only piece of its super-tile
+  if (threadIdx.x < kPiece) {
+    int32_t q = 0;
+    if (static_cast<int>(threadIdx.x) < len) q = ulist[uoff[t.x] + kstart + threadIdx.x];
+    us[threadIdx.x] = q;
+    if constexpr (SCALE) ss[threadIdx.x] = static_cast<int>(threadIdx.x) < len ? scale[q] : T(0);
+  }
   const int w = threadIdx.x / kWave, lane = lane_id();
-  const int c = lane & 31, h = lane >> 5;
-  const int cl = c < k ? c : k - 1;
-  int64_t base[kRows];
-  bool has[kRows];
+  const int rg = w & 3, half = w >> 2;   // rows 16 rg ... 16 rg + 15; steps of this half of each chunk
+  const int i = lane & 15, kk = lane >> 4;
+  const bool wave_rows = 16 * rg < t.z;  // uniform over the wave
+  // chunk entry of k-step s for this lane (the A and B operands agree on it):
+  // lane (i, kk) takes 8 consecutive entries, loaded with one vector load
+  auto ent = [&](int s) { return half * (kMChunk / 2) + 8 * kk + s; };
+  // A operands, V[row 16 rg + i, kstart + c0 + ent(s)]; rows past the tile read
+  // row 0 of the tile and are zeroed.  The loads are clamped into the row's
+  // leading U_M entries; a vector load may run up to 7 entries further, which
+  // stays inside the value array (its length carries kCsrPad entries of
+  // padding).
+  const int r = 16 * rg + i;
+  const bool rvalid = r < t.z;
+  const VT* vrow = val + rp[grows[t.y + (rvalid ? r : 0)]] + kstart;
+  VT areg[kMSteps], acur[kMSteps];
+  auto load_a = [&](int c0) {
+    const int e0 = c0 + ent(0);
+    VT v[kMSteps];
+    __builtin_memcpy(v, vrow + min(e0, len - 1), sizeof(v));
 #pragma unroll
-  for (int r = 0; r < kRows; ++r) {
-    const int i = w + r * kW;
-    has[r] = i < t.z;
-    base[r] = has[r] ? rp[grows[t.y + i]] : 0;
-  }
-  T acc[kRows];
+    for (int s = 0; s < kMSteps; ++s) areg[s] = (rvalid && e0 + s < len) ? v[s] : VT(0);
+  };
+  load_a(0);
+  __syncthreads();
+  // staging of X: thread -> (chunk row, kXPer consecutive columns); rows of
+  // at least 32 values are read with vector loads (columns past k are read
+  // but only feed output columns that are never stored)
+  constexpr int kSegs = 32 / kXPer;
+  const int xr = threadIdx.x / kSegs, xc0 = (threadIdx.x % kSegs) * kXPer;
+  const bool xvec = ld >= 32;
+  T xreg[kXPer];
+  auto load_x = [&](int c0) {
+    const int e = min(c0 + xr, len - 1);
+    const T* xp = X + static_cast<int64_t>(us[e]) * ld;
+    if (xvec) {
+      __builtin_memcpy(xreg, xp + xc0, sizeof(xreg));
+    } else {
 #pragma unroll
-  for (int r = 0; r < kRows; ++r) acc[r] = 0;
-  for (int64_t c0 = 0; c0 < nU; c0 += kMChunk) {
-    const int clen = static_cast<int>(min<int64_t>(kMChunk, nU - c0));
-    __syncthreads();
-    // stage X rows of the chunk: thread -> (row of chunk, column)
-    for (int idx = threadIdx.x; idx < kMChunk * 32; idx += kThreads) {
-      const int kk = idx >> 5, cc = idx & 31;
-      T v = 0;
-      if (kk < clen && cc < k) {
-        const int32_t q = U[c0 + kk];
-        v = X[static_cast<int64_t>(q) * ld + cc];
-        if constexpr (SCALE) v *= scale[q];
+      for (int u = 0; u < kXPer; ++u) xreg[u] = xp[min(xc0 + u, k - 1)];
+    }
+    T sq = c0 + xr < len ? T(1) : T(0);
+    if constexpr (SCALE) sq *= ss[e];
+#pragma unroll
+    for (int u = 0; u < kXPer; ++u) xreg[u] *= sq;
+  };
+  auto store_x = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < kXPer; ++u) xs[buf][xr][xc0 + u] = xreg[u];
+  };
+  Acc acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
+  load_x(0);
+  store_x(0);
+#pragma unroll
+  for (int s = 0; s < kMSteps; ++s) acur[s] = areg[s];
+  __syncthreads();
+  for (int c0 = 0, buf = 0; c0 < len; c0 += kMChunk, buf ^= 1) {
+    const bool more = c0 + kMChunk < len;  // uniform over the block
+    if (more) {
+      load_x(c0 + kMChunk);
+      load_a(c0 + kMChunk);
+    }
+    if (wave_rows) {
+      T b0[kMSteps], b1[kMSteps];
+#pragma unroll
+      for (int s = 0; s < kMSteps; ++s) {
+        b0[s] = xs[buf][ent(s)][i];
+        b1[s] = xs[buf][ent(s)][i + 16];
       }
-      xs[kk][cc] = v;
+#pragma unroll
+      for (int s = 0; s < kMSteps; ++s) {
+        const T a = static_cast<T>(acur[s]);
+        acc0 = mfma16x16x4(a, b0[s], acc0);
+        acc1 = mfma16x16x4(a, b1[s], acc1);
+      }
     }
-    // this wave's rows: values of the chunk
+    if (more) {
+      store_x(buf ^ 1);
 #pragma unroll
-    for (int r = 0; r < kRows; ++r)
-      vs[w][r][lane] = (has[r] && lane < clen) ? static_cast<T>(val[base[r] + c0 + lane]) : T(0);
+      for (int s = 0; s < kMSteps; ++s) acur[s] = areg[s];
+    }
     __syncthreads();
-    for (int kk = h; kk < clen; kk += 2) {
-      const T xv = xs[kk][cl];
+  }
+  // the second half adds into the first in a fixed order (xs is free now)
+  T(*red)[16][33] = reinterpret_cast<T(*)[16][33]>(&xs[0][0][0]);
+  static_assert(sizeof(xs) >= 4 * 16 * 33 * sizeof(T), "reduction buffer fits in the staging buffer");
+  if (half == 1 && wave_rows) {
 #pragma unroll
-      for (int r = 0; r < kRows; ++r) acc[r] += vs[w][r][kk] * xv;
+    for (int v = 0; v < 4; ++v) {
+      const int rr = MfmaAcc<T>::row(kk, v);
+      red[rg][rr][i] = acc0[v];
+      red[rg][rr][i + 16] = acc1[v];
     }
   }
+  __syncthreads();
+  if (half == 0 && wave_rows) {
 #pragma unroll
-  for (int r = 0; r < kRows; ++r) {
-    const T a = acc[r] + __shfl_xor(acc[r], 32, kWave);
-    if (h == 0 && c < k && has[r]) Y[static_cast<int64_t>(grows[t.y + w + r * kW]) * ld + c] = a;
+    for (int v = 0; v < 4; ++v) {
+      const int rr = MfmaAcc<T>::row(kk, v);
+      const int row = 16 * rg + rr;
+      if (row >= t.z) continue;
+      const T y0 = acc0[v] + red[rg][rr][i], y1 = acc1[v] + red[rg][rr][i + 16];
+      T* yr = whole ? Y + static_cast<int64_t>(grows[t.y + row]) * ld
+                    : part + (static_cast<int64_t>(pid) * kSuperRows + row) * 32;
+      const int kc = whole ? k : 32;
+      if (i < kc) yr[i] = y0;
+      if (i + 16 < kc) yr[i + 16] = y1;
+    }
   }
 }
+
+// Adds the partial blocks of the pieces of each super-tile with more than one
+// piece, in piece order, into Y.  Block (super-tile, group of kRedRows rows),
+// thread -> (row, column).
+constexpr int kRedRows = kThreads / 32;
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_group_reduce(const int32_t* __restrict__ stiles,
+                                                           const int32_t* __restrict__ grows, int k, int ld,
+                                                           const T* __restrict__ part, T* __restrict__ Y) {
+  constexpr int kGroups = kSuperRows / kRedRows;
+  const int4 t = reinterpret_cast<const int4*>(stiles)[blockIdx.x / kGroups];
+  const int row = (blockIdx.x % kGroups) * kRedRows + threadIdx.x / 32, col = threadIdx.x & 31;
+  if (t.w <= 1 || row >= t.y || col >= k) return;  // single pieces write Y themselves
+  const T* pp = part + (static_cast<int64_t>(t.z) * kSuperRows + row) * 32 + col;
+  constexpr int64_t kStride = static_cast<int64_t>(kSuperRows) * 32;
+  T acc = pp[0];
+  int p = 1;
+  for (; p + 4 <= t.w; p += 4) {
+    const T a0 = pp[p * kStride], a1 = pp[(p + 1) * kStride], a2 = pp[(p + 2) * kStride], a3 = pp[(p + 3) * kStride];
+    acc += a0;
+    acc += a1;
+    acc += a2;
+    acc += a3;
+  }
+  for (; p < t.w; ++p) acc += pp[p * kStride];
+  Y[static_cast<int64_t>(grows[t.x + row]) * ld + col] = acc;
+}
+
+}  // namespace
 
 template <typename T>
 void spmm(gp_ctx* c, const gp_matrix* m, int k, int ld, const T* X, T* Y, const T* scale) {
   if (k > 32 || ld < k) throw Error{GP_EINVAL, "spmm: at most 32 right-hand sides per call"};
   ProfScope ps(c, "spmm");
+  // partial blocks of the pieces of multi-piece super-tiles
+  T* part = m->npieces > 0 ? static_cast<T*>(workspace(c, 60, sizeof(T) * kSuperRows * 32 * m->npieces)) : nullptr;
   const unsigned nb_short = round_up8(grid_for(m->n, kThreads / kWave));
   const unsigned nb = nb_short + static_cast<unsigned>(m->n_long);
   auto go = [&](auto vt, auto sc) {
     using VT = decltype(vt);
     constexpr bool SC = decltype(sc)::value;
-    if (m->ntiles > 0)
-      hipLaunchKernelGGL((k_group_spmm<VT, T, SC>), dim3(static_cast<unsigned>(m->ntiles)), dim3(kThreads), 0,
-                         c->stream, m->g_tiles, m->g_rows, m->g_uoff, m->g_ulist, k, ld, m->row_ptr,
-                         static_cast<const VT*>(m->val), X, Y, scale);
+    if (m->npieces > 0) {
+      const int32_t* st = m->g_tiles + 4 * m->ntiles;
+      hipLaunchKernelGGL((k_group_spmm_mfma<VT, T, SC>), dim3(static_cast<unsigned>(m->npieces)), dim3(kMThreads), 0,
+                         c->stream, st + 4 * m->nstiles, m->g_rows, m->g_uoff, m->g_ulist, k, ld, m->row_ptr,
+                         static_cast<const VT*>(m->val), X, Y, scale, part);
+      hipLaunchKernelGGL((k_group_reduce<T>), dim3(static_cast<unsigned>(m->nstiles * (kSuperRows / kRedRows))),
+                         dim3(kThreads), 0, c->stream,
+                         st, m->g_rows, k, ld, part, Y);
+    }
     hipLaunchKernelGGL((k_spmm<VT, T, SC>), dim3(nb), dim3(kThreads), 0, c->stream, m->n, nb_short, m->n_long,
                        m->long_rows, k, ld, m->row_ptr, m->gskip, m->col, static_cast<const VT*>(m->val), X, Y,
                        scale);
