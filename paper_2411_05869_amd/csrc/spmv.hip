@@ -93,30 +93,40 @@ __global__ void __launch_bounds__(kThreads) k_spmv(int64_t n, unsigned nb_long, 
 // and lane l works on column l & 31, receiving the entry's column id and
 // weight from the staging lane by ds_bpermute.  All X gathers of a staged
 // chunk are independent, so kUm of them are in flight per lane.
-// Blocks [0, nb_short) give each short row (<= kLongRow entries) one wave;
-// the remaining blocks give each long row a whole block: wave w takes the
-// chunks w, w + 4, ... and the four partial rows are added in a fixed order.
+// Blocks [0, nb_short) give each wave kRowsPerWave consecutive rows: the
+// bounds of all of them are read at once, and the first chunk of the next
+// row is staged while the X gathers of the current row are in flight, so the
+// dependent loads of consecutive rows overlap.  Rows of more than kLongRow
+// entries are skipped there; the remaining blocks give each such row a whole
+// block: wave w takes the chunks w, w + 4, ... and the four partial rows are
+// added in a fixed order.
 constexpr int kUm = 8;
+constexpr int kRowsPerWave = 8;
 
 template <typename T>
 __device__ __forceinline__ T shfl_any(T v, int src) {
   return __shfl(v, src, kWave);
 }
 
+// lane l stages entry j0 + l of [j0, e): its column id q (self when past the
+// end) and weight v (0 past the end)
 template <typename VT, typename T, bool SCALE>
-__device__ __forceinline__ T spmm_chunk(int64_t j0, int64_t e, int32_t self, const int32_t* __restrict__ col,
-                                        const VT* __restrict__ val, const T* __restrict__ X,
-                                        const T* __restrict__ scale, int ld, int cl, int lane, int h) {
-  // stage up to 64 entries
+__device__ __forceinline__ void spmm_stage(int64_t j0, int64_t e, int32_t self, const int32_t* __restrict__ col,
+                                           const VT* __restrict__ val, const T* __restrict__ scale, int lane,
+                                           int32_t& q, T& v) {
   const int64_t j = j0 + lane;
-  int32_t q = self;
-  T v = 0;
+  q = self;
+  v = 0;
   if (j < e) {
     q = col[j];
     v = static_cast<T>(val[j]);
     if constexpr (SCALE) v *= scale[q];
   }
-  const int m = static_cast<int>(min<int64_t>(e - j0, kWave));
+}
+
+// sum over the m staged entries of v * X[q, column]
+template <typename T>
+__device__ __forceinline__ T spmm_consume(int32_t q, T v, int m, const T* __restrict__ X, int ld, int cl, int h) {
   const int npairs = (m + 1) >> 1;
   T acc = 0;
   for (int i0 = 0; i0 < npairs; i0 += kUm) {
@@ -138,32 +148,152 @@ __device__ __forceinline__ T spmm_chunk(int64_t j0, int64_t e, int32_t self, con
   return acc;
 }
 
-template <typename VT, typename T, bool SCALE>
+// The same sum with 16-byte X loads, for blocks whose rows hold at least 32
+// values at 16-byte alignment: lane l works on the kCpl consecutive columns
+// kCpl (l % kLpe) ... of entry slot l / kLpe, so one load instruction serves
+// kWave / kLpe entries.  Returns the lane's kCpl partial sums; the slots are
+// added by the caller.
+template <typename T>
+struct Vec16 {
+  static constexpr int kCpl = 16 / sizeof(T);   // columns per lane
+  static constexpr int kLpe = 32 / kCpl;         // lanes per entry
+  static constexpr int kEpi = kWave / kLpe;      // entries per load instruction
+  T v[kCpl];
+};
+constexpr int kUq = 4;
+
+template <typename T>
+__device__ __forceinline__ Vec16<T> spmm_consume16(int32_t q, T v, int m, const T* __restrict__ X, int ld,
+                                                    int lane) {
+  using V = Vec16<T>;
+  const int g = lane / V::kLpe, cp = lane % V::kLpe;
+  const int nq = (m + V::kEpi - 1) / V::kEpi;
+  V acc;
+#pragma unroll
+  for (int u = 0; u < V::kCpl; ++u) acc.v[u] = 0;
+  for (int i0 = 0; i0 < nq; i0 += kUq) {
+    int32_t qq[kUq];
+    T vv[kUq];
+#pragma unroll
+    for (int u = 0; u < kUq; ++u) {
+      const int src = (V::kEpi * (i0 + u) + g) & (kWave - 1);  // entries past m carry weight 0
+      qq[u] = shfl_any(q, src);
+      vv[u] = shfl_any(v, src);
+      if (i0 + u >= nq) vv[u] = 0;
+    }
+    V xv[kUq];
+#pragma unroll
+    for (int u = 0; u < kUq; ++u) __builtin_memcpy(xv[u].v, X + static_cast<int64_t>(qq[u]) * ld + cp * V::kCpl, 16);
+#pragma unroll
+    for (int u = 0; u < kUq; ++u)
+#pragma unroll
+      for (int t = 0; t < V::kCpl; ++t) acc.v[t] += vv[u] * xv[u].v[t];
+  }
+  return acc;
+}
+
+// adds the entry slots of spmm_consume16 (lanes l, l + kLpe, ...), fixed order
+template <typename T>
+__device__ __forceinline__ void slot_sum(Vec16<T>& a) {
+#pragma unroll
+  for (int off = Vec16<T>::kLpe; off < kWave; off <<= 1)
+#pragma unroll
+    for (int t = 0; t < Vec16<T>::kCpl; ++t) a.v[t] += __shfl_xor(a.v[t], off, kWave);
+}
+
+template <typename VT, typename T, bool SCALE, bool VEC>
 __global__ void __launch_bounds__(kThreads) k_spmm(int64_t n, unsigned nb_short, int64_t nlong,
                                                    const int32_t* __restrict__ rows, int k, int ld,
                                                    const int64_t* __restrict__ rp, const int32_t* __restrict__ gskip,
                                                    const int32_t* __restrict__ col,
                                                    const VT* __restrict__ val, const T* __restrict__ X,
                                                    T* __restrict__ Y, const T* __restrict__ scale) {
+  using V = Vec16<T>;
   const int lane = lane_id();
   const int c = lane & 31;
   const int cl = c < k ? c : k - 1;  // lanes past k re-read column k-1 (in bounds), never store
   const int h = lane >> 5;
   const int w = threadIdx.x / kWave;
+  // finishes a row: acc holds the pair-path sum (VEC false) or the lane's
+  // slot sums (VEC true); adds the group part already in Y, scales, stores
+  auto finish = [&](int64_t row, int32_t gs, T acc, V accv) {
+    if constexpr (VEC) {
+      slot_sum<T>(accv);
+      if (lane < V::kLpe) {
+        T* yr = Y + row * ld + lane * V::kCpl;
+#pragma unroll
+        for (int t = 0; t < V::kCpl; ++t) {
+          if (lane * V::kCpl + t >= k) break;
+          T a = accv.v[t];
+          if (gs) a = yr[t] + a;
+          if constexpr (SCALE) a *= scale[row];
+          yr[t] = a;
+        }
+      }
+    } else {
+      acc += __shfl_xor(acc, 32, kWave);
+      if (h == 0 && c < k) {
+        if (gs) acc = Y[row * ld + c] + acc;
+        if constexpr (SCALE) acc *= scale[row];
+        Y[row * ld + c] = acc;
+      }
+    }
+  };
+  auto consume = [&](int32_t q, T v, int m, T& acc, V& accv) {
+    if constexpr (VEC) {
+      const V a = spmm_consume16<T>(q, v, m, X, ld, lane);
+#pragma unroll
+      for (int t = 0; t < V::kCpl; ++t) accv.v[t] += a.v[t];
+    } else {
+      acc += spmm_consume<T>(q, v, m, X, ld, cl, h);
+    }
+  };
   if (blockIdx.x < nb_short) {
-    const int64_t row = xcd_remap(blockIdx.x, nb_short) * static_cast<int64_t>(kThreads / kWave) + w;
-    if (row >= n) return;
-    const int32_t gs = gskip[row];
-    const int64_t s = rp[row] + gs, e = rp[row + 1];
-    if (e - s > kLongRow) return;
-    T acc = 0;
-    for (int64_t j0 = s; j0 < e; j0 += kWave)
-      acc += spmm_chunk<VT, T, SCALE>(j0, e, static_cast<int32_t>(row), col, val, X, scale, ld, cl, lane, h);
-    acc += __shfl_xor(acc, 32, kWave);
-    if (h == 0 && c < k) {
-      if (gs) acc = Y[row * ld + c] + acc;
-      if constexpr (SCALE) acc *= scale[row];
-      Y[row * ld + c] = acc;
+    const int64_t r0 = (xcd_remap(blockIdx.x, nb_short) * static_cast<int64_t>(kThreads / kWave) + w) * kRowsPerWave;
+    if (r0 >= n) return;
+    const int nr = static_cast<int>(min<int64_t>(kRowsPerWave, n - r0));
+    // lane l < nr: first non-group entry, end and group flag of row r0 + l
+    int64_t rs = 0, re = 0;
+    int32_t rg = 0;
+    if (lane < nr) {
+      rg = gskip[r0 + lane];
+      rs = rp[r0 + lane] + rg;
+      re = rp[r0 + lane + 1];
+    }
+    int32_t q = 0;
+    T v = 0;
+    {
+      const int64_t s = shfl_any(rs, 0), e = shfl_any(re, 0);
+      if (e - s <= kLongRow) spmm_stage<VT, T, SCALE>(s, e, static_cast<int32_t>(r0), col, val, scale, lane, q, v);
+    }
+    for (int r = 0; r < nr; ++r) {
+      const int64_t row = r0 + r;
+      const int64_t s = shfl_any(rs, r), e = shfl_any(re, r);
+      const int32_t gs = shfl_any(rg, r);
+      // stage the next row's first chunk while this row's gathers run
+      int32_t qn = 0;
+      T vn = 0;
+      if (r + 1 < nr) {
+        const int64_t sn = shfl_any(rs, r + 1), en = shfl_any(re, r + 1);
+        if (en - sn <= kLongRow)
+          spmm_stage<VT, T, SCALE>(sn, en, static_cast<int32_t>(row + 1), col, val, scale, lane, qn, vn);
+      }
+      if (e - s <= kLongRow) {
+        T acc = 0;
+        V accv;
+#pragma unroll
+        for (int t = 0; t < V::kCpl; ++t) accv.v[t] = 0;
+        consume(q, v, static_cast<int>(min<int64_t>(e - s, kWave)), acc, accv);
+        for (int64_t j0 = s + kWave; j0 < e; j0 += kWave) {
+          int32_t q2;
+          T v2;
+          spmm_stage<VT, T, SCALE>(j0, e, static_cast<int32_t>(row), col, val, scale, lane, q2, v2);
+          consume(q2, v2, static_cast<int>(min<int64_t>(e - j0, kWave)), acc, accv);
+        }
+        finish(row, gs, acc, accv);
+      }
+      q = qn;
+      v = vn;
     }
   } else {
     __shared__ T part[kThreads / kWave][32];
@@ -173,10 +303,24 @@ __global__ void __launch_bounds__(kThreads) k_spmm(int64_t n, unsigned nb_short,
     const int32_t gs = gskip[row];
     const int64_t s = rp[row] + gs, e = rp[row + 1];
     T acc = 0;
-    for (int64_t j0 = s + static_cast<int64_t>(w) * kWave; j0 < e; j0 += kThreads)
-      acc += spmm_chunk<VT, T, SCALE>(j0, e, row, col, val, X, scale, ld, cl, lane, h);
-    acc += __shfl_xor(acc, 32, kWave);
-    if (h == 0) part[w][c] = acc;
+    V accv;
+#pragma unroll
+    for (int t = 0; t < V::kCpl; ++t) accv.v[t] = 0;
+    for (int64_t j0 = s + static_cast<int64_t>(w) * kWave; j0 < e; j0 += kThreads) {
+      int32_t q;
+      T v;
+      spmm_stage<VT, T, SCALE>(j0, e, row, col, val, scale, lane, q, v);
+      consume(q, v, static_cast<int>(min<int64_t>(e - j0, kWave)), acc, accv);
+    }
+    if constexpr (VEC) {
+      slot_sum<T>(accv);
+      if (lane < V::kLpe)
+#pragma unroll
+        for (int t = 0; t < V::kCpl; ++t) part[w][lane * V::kCpl + t] = accv.v[t];
+    } else {
+      acc += __shfl_xor(acc, 32, kWave);
+      if (h == 0) part[w][c] = acc;
+    }
     __syncthreads();
     if (w == 0 && h == 0 && c < k) {
       T t = part[0][c];
@@ -517,7 +661,7 @@ void spmm(gp_ctx* c, const gp_matrix* m, int k, int ld, const T* X, T* Y, const 
   ProfScope ps(c, "spmm");
   // partial blocks of the pieces of multi-piece super-tiles
   T* part = m->npieces > 0 ? static_cast<T*>(workspace(c, 60, sizeof(T) * kSuperRows * 32 * m->npieces)) : nullptr;
-  const unsigned nb_short = round_up8(grid_for(m->n, kThreads / kWave));
+  const unsigned nb_short = round_up8(grid_for((m->n + kRowsPerWave - 1) / kRowsPerWave, kThreads / kWave));
   const unsigned nb = nb_short + static_cast<unsigned>(m->n_long);
   auto go = [&](auto vt, auto sc) {
     using VT = decltype(vt);
@@ -531,9 +675,16 @@ void spmm(gp_ctx* c, const gp_matrix* m, int k, int ld, const T* X, T* Y, const 
                          dim3(kThreads), 0, c->stream,
                          st, m->g_rows, k, ld, part, Y);
     }
-    hipLaunchKernelGGL((k_spmm<VT, T, SC>), dim3(nb), dim3(kThreads), 0, c->stream, m->n, nb_short, m->n_long,
-                       m->long_rows, k, ld, m->row_ptr, m->gskip, m->col, static_cast<const VT*>(m->val), X, Y,
-                       scale);
+    // 16-byte X loads need rows of at least 32 values at 16-byte alignment
+    const bool vec = ld >= 32 && (ld * sizeof(T)) % 16 == 0 && reinterpret_cast<uintptr_t>(X) % 16 == 0;
+    if (vec)
+      hipLaunchKernelGGL((k_spmm<VT, T, SC, true>), dim3(nb), dim3(kThreads), 0, c->stream, m->n, nb_short,
+                         m->n_long, m->long_rows, k, ld, m->row_ptr, m->gskip, m->col, static_cast<const VT*>(m->val),
+                         X, Y, scale);
+    else
+      hipLaunchKernelGGL((k_spmm<VT, T, SC, false>), dim3(nb), dim3(kThreads), 0, c->stream, m->n, nb_short,
+                         m->n_long, m->long_rows, k, ld, m->row_ptr, m->gskip, m->col, static_cast<const VT*>(m->val),
+                         X, Y, scale);
   };
   if (m->prec == GP_MIXED) {
     if (scale)
