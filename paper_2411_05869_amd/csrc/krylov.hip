@@ -3,66 +3,24 @@
 // with full re-orthogonalisation for small n (Sec. 3.3: the log-determinant
 // and linear-solve tasks).
 //
-// Reductions are two-level with a fixed grid (kRedBlocks blocks, grid-stride)
-// and a fixed tree, so every scalar is bitwise reproducible.  Scalars stay in
-// device memory between kernels; the host reads them only at check points.
+// Reductions are two-level with a fixed grid and a fixed tree (reduce.hpp), so
+// every scalar is bitwise reproducible.  Scalars stay in device memory between
+// kernels; the host reads them only at check points.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
 
 #include "device.hpp"
+#include "reduce.hpp"
 
 namespace gps {
 namespace {
 
-constexpr int kThreads = 256;
+constexpr int kThreads = kRedThreads;
 constexpr int kRedBlocks = 512;
 constexpr int kCheckEvery = 8;
 
 // ---------------------------------------------------------------- reductions
-template <int NV>
-__device__ __forceinline__ void block_sum_store(double (&v)[NV], double* __restrict__ out) {
-  __shared__ double sh[NV][kThreads / kWave];
-  const int w = threadIdx.x / kWave;
-#pragma unroll
-  for (int i = 0; i < NV; ++i) {
-    double x = v[i];
-#pragma unroll
-    for (int off = kWave / 2; off > 0; off >>= 1) x += __shfl_xor(x, off, kWave);
-    if (lane_id() == 0) sh[i][w] = x;
-  }
-  __syncthreads();
-  if (threadIdx.x < NV) {
-    double s = 0;
-#pragma unroll
-    for (int j = 0; j < kThreads / kWave; ++j) s += sh[threadIdx.x][j];
-    out[blockIdx.x * NV + threadIdx.x] = s;
-  }
-}
-
-// Sums partials[b * NV + i] over b in a fixed order; result in thread i's return.
-template <int NV>
-__device__ __forceinline__ void reduce_partials(const double* __restrict__ part, int nb, double* __restrict__ res) {
-  __shared__ double sh[NV][kThreads];
-#pragma unroll
-  for (int i = 0; i < NV; ++i) {
-    double s = 0;
-    for (int b = threadIdx.x; b < nb; b += kThreads) s += part[b * NV + i];
-    sh[i][threadIdx.x] = s;
-  }
-  __syncthreads();
-  for (int st = kThreads / 2; st > 0; st >>= 1) {
-    if (threadIdx.x < st)
-#pragma unroll
-      for (int i = 0; i < NV; ++i) sh[i][threadIdx.x] += sh[i][threadIdx.x + st];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0)
-#pragma unroll
-    for (int i = 0; i < NV; ++i) res[i] = sh[i][0];
-  __syncthreads();
-}
-
 __global__ void __launch_bounds__(kThreads) k_dot_part(int64_t n, const double* __restrict__ a,
                                                        const double* __restrict__ b, double* __restrict__ part) {
   double v[1] = {0};
@@ -114,6 +72,83 @@ __device__ __forceinline__ double precond_row(const Precond& M, const double* __
   return z;
 }
 
+// Row i of z = M^-1 (r - alpha q): the entries of the new residual that the
+// block product needs are formed from r and q the same way as the row's own, so
+// every thread sees bitwise the same values without waiting for the others.
+template <typename QT>
+__device__ __forceinline__ double precond_row_next(const Precond& M, const double* __restrict__ r,
+                                                   const QT* __restrict__ q, double alpha, double ri, int64_t i) {
+  if (!M.binv) return ri / M.diag[i];
+  const int32_t b = M.rowblk[i];
+  const int32_t bs = M.bstart[b];
+  const int sz = M.bstart[b + 1] - bs;
+  const double* row = M.binv + M.boff[b] + static_cast<int64_t>(i - bs) * sz;
+  double z = 0.0;
+  for (int j = 0; j < sz; ++j) z += row[j] * (r[bs + j] - alpha * static_cast<double>(q[bs + j]));
+  return z;
+}
+
+// One CG step after the product q = K p.  Every block adds the kRedBlocks
+// partials of p.q (pq_part, same fixed order in every block) and forms alpha =
+// rz / pq; then, grid-stride over rows: x += alpha p, rn = r - alpha q, z =
+// M^-1 rn, and per-block partials of rn.z and rn.rn.  Block 0 records pq, alpha,
+// rz_old = rz and the status (non-positive curvature).
+template <typename QT>
+__global__ void __launch_bounds__(kThreads) k_pcg_step(int64_t n, Precond M, CgScalars* __restrict__ s,
+                                                       const double* __restrict__ pq_part,
+                                                       const double* __restrict__ p, const QT* __restrict__ q,
+                                                       double* __restrict__ x, const double* __restrict__ r,
+                                                       double* __restrict__ rn, double* __restrict__ z,
+                                                       double* __restrict__ part) {
+  double pqv[1];
+  reduce_partials<1>(pq_part, kRedBlocks, pqv);
+  const double pq = pqv[0], rz = s->rz;
+  const bool ok = pq > 0.0 && isfinite(pq);
+  const double alpha = ok ? rz / pq : 0.0;
+  double v[2] = {0, 0};
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * kThreads) {
+    x[i] += alpha * p[i];
+    const double ri = r[i] - alpha * static_cast<double>(q[i]);
+    const double zi = precond_row_next<QT>(M, r, q, alpha, ri, i);
+    rn[i] = ri;
+    z[i] = zi;
+    v[0] += ri * zi;
+    v[1] += ri * ri;
+  }
+  block_sum_store<2>(v, part);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    s->pq = pq;
+    s->alpha = alpha;
+    s->rz_old = rz;
+    if (!ok) s->status = 1;
+  }
+}
+
+// New direction after a step: every block adds the step's partials (same fixed
+// order) into rz, rr and beta = rz / rz_old, then p = z + beta p (and its
+// float32 copy).  Block 0 records rz, rr, beta and flags non-finite values.
+__global__ void __launch_bounds__(kThreads) k_pcg_direction(int64_t n, CgScalars* __restrict__ s,
+                                                            const double* __restrict__ part,
+                                                            const double* __restrict__ z, double* __restrict__ p,
+                                                            float* __restrict__ p32) {
+  double sums[2];
+  reduce_partials<2>(part, kRedBlocks, sums);
+  const double beta = sums[0] / s->rz_old;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    s->rz = sums[0];
+    s->rr = sums[1];
+    s->beta = beta;
+    if (!isfinite(sums[0]) || !isfinite(sums[1])) s->status = 1;
+  }
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * kThreads) {
+    const double pi = z[i] + beta * p[i];
+    p[i] = pi;
+    if (p32) p32[i] = static_cast<float>(pi);
+  }
+}
+
 // x = 0, r = y; partial sums of y.y
 __global__ void __launch_bounds__(kThreads) k_pcg_init(int64_t n, const double* __restrict__ y, double* __restrict__ x,
                                                        double* __restrict__ r, double* __restrict__ part) {
@@ -153,6 +188,7 @@ __global__ void __launch_bounds__(kThreads) k_precond(int64_t n, Precond M, cons
   block_sum_store<2>(v, part);
 }
 
+// per-block partials of p.q (kRedBlocks blocks, grid-stride)
 template <typename QT>
 __global__ void __launch_bounds__(kThreads) k_pq_part(int64_t n, const double* __restrict__ p,
                                                       const QT* __restrict__ q, double* __restrict__ part) {
@@ -163,36 +199,9 @@ __global__ void __launch_bounds__(kThreads) k_pq_part(int64_t n, const double* _
   block_sum_store<1>(v, part);
 }
 
-__global__ void __launch_bounds__(kThreads) k_alpha_fin(const double* __restrict__ part, int nb,
-                                                        CgScalars* __restrict__ s) {
-  double r[1];
-  reduce_partials<1>(part, nb, r);
-  if (threadIdx.x == 0) {
-    const double pq = r[0];
-    s->pq = pq;
-    if (!(pq > 0.0) || !isfinite(pq)) {
-      s->status = 1;
-      s->alpha = 0.0;
-    } else {
-      s->alpha = s->rz / pq;
-    }
-  }
-}
-
-// x += alpha p; r -= alpha q
-template <typename QT>
-__global__ void __launch_bounds__(kThreads) k_pcg_update(int64_t n, const CgScalars* __restrict__ s,
-                                                         const double* __restrict__ p, const QT* __restrict__ q,
-                                                         double* __restrict__ x, double* __restrict__ r) {
-  const double alpha = s->alpha;
-  for (int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; i < n;
-       i += static_cast<int64_t>(gridDim.x) * kThreads) {
-    x[i] += alpha * p[i];
-    r[i] = r[i] - alpha * static_cast<double>(q[i]);
-  }
-}
-
 // mode 0: iteration (rz_old <- rz, rz <- r.z, beta = rz / rz_old)
+// mode 3: iteration whose step already set rz_old
+
 // mode 1: residual replacement (rz_old kept)
 // mode 2: start (rz <- r.z, no beta)
 __global__ void __launch_bounds__(kThreads) k_beta_fin(const double* __restrict__ part, int nb,
@@ -200,7 +209,7 @@ __global__ void __launch_bounds__(kThreads) k_beta_fin(const double* __restrict_
   double r[2];
   reduce_partials<2>(part, nb, r);
   if (threadIdx.x == 0) {
-    if (mode == 0) s->rz_old = s->rz;
+    if (mode == 0) s->rz_old = s->rz;  // mode 3: set by the step
     s->rz = r[0];
     s->rr = r[1];
     s->beta = mode == 2 ? 0.0 : r[0] / s->rz_old;
@@ -531,7 +540,9 @@ SolveResult pcg_solve(gp_ctx* c, gp_matrix* m, const double* y, double* x, doubl
     M.boff = m->boff;
     M.binv = m->binv;
   }
-  double* r = static_cast<double*>(workspace(c, 20, sizeof(double) * n));
+  // the residual alternates between two buffers: a step reads one and writes the other
+  double* rc = static_cast<double*>(workspace(c, 20, sizeof(double) * n));
+  double* rnx = static_cast<double*>(workspace(c, 29, sizeof(double) * n));
   double* z = static_cast<double*>(workspace(c, 21, sizeof(double) * n));
   double* p = static_cast<double*>(workspace(c, 22, sizeof(double) * n));
   double* q = static_cast<double*>(workspace(c, 23, sizeof(double) * n));
@@ -551,19 +562,19 @@ SolveResult pcg_solve(gp_ctx* c, gp_matrix* m, const double* y, double* x, doubl
   // z = M^-1 r and the scalars r.z, r.r (mode: see k_beta_fin)
   auto apply_precond = [&](int mode) {
     ProfScope ps(c, "pcg_precond");
-    hipLaunchKernelGGL(k_precond, dim3(nbp), B, 0, c->stream, n, M, r, z, ppart);
+    hipLaunchKernelGGL(k_precond, dim3(nbp), B, 0, c->stream, n, M, rc, z, ppart);
     hipLaunchKernelGGL(k_beta_fin, dim3(1), B, 0, c->stream, ppart, static_cast<int>(nbp), s, mode);
   };
   auto true_residual = [&]() {
     spmv_f64(c, m, x, q);
-    hipLaunchKernelGGL(k_true_resid, G, B, 0, c->stream, n, y, q, r);
+    hipLaunchKernelGGL(k_true_resid, G, B, 0, c->stream, n, y, q, rc);
     apply_precond(1);
     check_launch("true residual");
     return read();
   };
   {
     ProfScope ps(c, "pcg_vector_ops");
-    hipLaunchKernelGGL(k_pcg_init, G, B, 0, c->stream, n, y, x, r, part);
+    hipLaunchKernelGGL(k_pcg_init, G, B, 0, c->stream, n, y, x, rc, part);
     hipLaunchKernelGGL(k_yy_fin, dim3(1), B, 0, c->stream, part, kRedBlocks, s);
   }
   apply_precond(2);
@@ -578,26 +589,32 @@ SolveResult pcg_solve(gp_ctx* c, gp_matrix* m, const double* y, double* x, doubl
   double last_true = ynorm;   // |y - K x| at the latest recomputation
   int it = 0;
   bool converged = false;
+  // per iteration: q = K p, partials of p.q, the step (alpha, x, r, z and the
+  // partials of r.z, r.r), the new direction (beta, p); the last step before a
+  // host check leaves the direction to after the check
+  double* pqp = part;                    // kRedBlocks partials of p.q
+  double* spart = part + kRedBlocks;     // 2 x kRedBlocks partials of r.z, r.r
   while (it < max_iter && !converged) {
     const int steps = std::min(kCheckEvery, max_iter - it);
     for (int t = 0; t < steps; ++t) {
-      if (mixed) {
+      if (mixed)
         spmv_f32(c, m, p32, q32);
-        ProfScope ps(c, "pcg_vector_ops");
-        hipLaunchKernelGGL((k_pq_part<float>), G, B, 0, c->stream, n, p, q32, part);
-        hipLaunchKernelGGL(k_alpha_fin, dim3(1), B, 0, c->stream, part, kRedBlocks, s);
-        hipLaunchKernelGGL((k_pcg_update<float>), G, B, 0, c->stream, n, s, p, q32, x, r);
-      } else {
+      else
         spmv_f64(c, m, p, q);
+      {
         ProfScope ps(c, "pcg_vector_ops");
-        hipLaunchKernelGGL((k_pq_part<double>), G, B, 0, c->stream, n, p, q, part);
-        hipLaunchKernelGGL(k_alpha_fin, dim3(1), B, 0, c->stream, part, kRedBlocks, s);
-        hipLaunchKernelGGL((k_pcg_update<double>), G, B, 0, c->stream, n, s, p, q, x, r);
-      }
-      apply_precond(0);
-      if (t + 1 < steps) {
-        ProfScope ps(c, "pcg_vector_ops");
-        hipLaunchKernelGGL(k_pcg_pupdate, G, B, 0, c->stream, n, s, z, p, p32);
+        if (mixed) {
+          hipLaunchKernelGGL((k_pq_part<float>), G, B, 0, c->stream, n, p, q32, pqp);
+          hipLaunchKernelGGL((k_pcg_step<float>), G, B, 0, c->stream, n, M, s, pqp, p, q32, x, rc, rnx, z, spart);
+        } else {
+          hipLaunchKernelGGL((k_pq_part<double>), G, B, 0, c->stream, n, p, q, pqp);
+          hipLaunchKernelGGL((k_pcg_step<double>), G, B, 0, c->stream, n, M, s, pqp, p, q, x, rc, rnx, z, spart);
+        }
+        std::swap(rc, rnx);
+        if (t + 1 < steps)
+          hipLaunchKernelGGL(k_pcg_direction, G, B, 0, c->stream, n, s, spart, z, p, p32);
+        else
+          hipLaunchKernelGGL(k_beta_fin, dim3(1), B, 0, c->stream, spart, kRedBlocks, s, 3);
       }
       check_launch("pcg iteration");
     }

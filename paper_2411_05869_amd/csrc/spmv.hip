@@ -61,26 +61,29 @@ __global__ void __launch_bounds__(kThreads) k_spmv(int64_t n, unsigned nb_long, 
     const unsigned b = xcd_remap(blockIdx.x - nb_long, gridDim.x - nb_long);
     const int64_t row = (b * static_cast<int64_t>(kThreads) + threadIdx.x) / kG;
     const int sub = threadIdx.x & (kG - 1);
-    if (row >= n) return;
-    const int32_t gs = gskip[row];
-    const int64_t s = rp[row] + gs, e = rp[row + 1];
-    if (e - s > kLongRow) return;  // uniform within the group
-    AT acc = spmv_part<VT, XT, AT, kG>(s, e, sub, static_cast<int32_t>(row), col, val, x);
+    if (row < n) {
+      const int32_t gs = gskip[row];
+      const int64_t s = rp[row] + gs, e = rp[row + 1];
+      if (e - s <= kLongRow) {  // uniform within the group
+        AT acc = spmv_part<VT, XT, AT, kG>(s, e, sub, static_cast<int32_t>(row), col, val, x);
 #pragma unroll
-    for (int off = kG / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kG);
-    if (sub == 0) y[row] = static_cast<YT>(gs ? static_cast<AT>(y[row]) + acc : acc);
+        for (int off = kG / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kG);
+        if (sub == 0) y[row] = static_cast<YT>(gs ? static_cast<AT>(y[row]) + acc : acc);
+      }
+    }
   } else {
     const unsigned b = xcd_remap(blockIdx.x, nb_long);
     const int64_t w = (b * static_cast<int64_t>(kThreads) + threadIdx.x) / kWave;
-    if (w >= nlong) return;
-    const int lane = lane_id();
-    const int32_t row = rows[w];
-    const int32_t gs = gskip[row];
-    const int64_t s = rp[row] + gs, e = rp[row + 1];
-    AT acc = spmv_part<VT, XT, AT, kWave>(s, e, lane, row, col, val, x);
+    if (w < nlong) {
+      const int lane = lane_id();
+      const int32_t row = rows[w];
+      const int32_t gs = gskip[row];
+      const int64_t s = rp[row] + gs, e = rp[row + 1];
+      AT acc = spmv_part<VT, XT, AT, kWave>(s, e, lane, row, col, val, x);
 #pragma unroll
-    for (int off = kWave / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kWave);
-    if (lane == 0) y[row] = static_cast<YT>(gs ? static_cast<AT>(y[row]) + acc : acc);
+      for (int off = kWave / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kWave);
+      if (lane == 0) y[row] = static_cast<YT>(gs ? static_cast<AT>(y[row]) + acc : acc);
+    }
   }
 }
 
