@@ -44,6 +44,10 @@ struct AsmArgs {
   const int32_t* did;       // nm: distinct-mask id of each masked row
   const int64_t* uoff;      // nD + 1
   const int32_t* ulist;     // concatenated U_M lists
+  int64_t utotal;           // their total length
+  const double* ux;         // D x utotal coordinates of the U list entries
+  const uint64_t* umask;    // utotal group masks
+  const double* uF;         // n1 x utotal values f_i
   // counts / outputs
   int32_t* counts;          // n
   int32_t* gskip;           // n: leading group entries of each row (|U_M| or 0)
@@ -149,7 +153,24 @@ __global__ void __launch_bounds__(kThreads) k_ulists(int64_t nm, const uint64_t*
   }
 }
 
+// Point data of the concatenated U_M lists in list order (coordinates, mask,
+// f_i as one array per i), so that rows read their group columns contiguously.
+template <int D>
+__global__ void __launch_bounds__(kThreads) k_ugather(AsmArgs a, double* __restrict__ ux,
+                                                      uint64_t* __restrict__ umask, double* __restrict__ uF) {
+  const int64_t j = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x;
+  if (j >= a.utotal) return;
+  const int32_t u = a.ulist[j];
+#pragma unroll
+  for (int k = 0; k < D; ++k) ux[k * a.utotal + j] = a.xb[k * a.n + u];
+  umask[j] = a.mask[u];
+  const double* f = a.F + static_cast<int64_t>(a.midx[u]) * a.kt.n1;
+  for (int i = 0; i < a.kt.n1; ++i) uF[i * a.utotal + j] = f[i];
+}
+
 // ------------------------------------------------------- rows without groups
+constexpr int kBuf = 4;
+
 template <int D, bool FILL, typename VT>
 __global__ void __launch_bounds__(kThreads) k_local_rows(AsmArgs a) {
   const int64_t p = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x;
@@ -164,6 +185,10 @@ __global__ void __launch_bounds__(kThreads) k_local_rows(AsmArgs a) {
   const int64_t out = FILL ? a.row_ptr[p] : 0;
   const int64_t len = FILL ? a.row_ptr[p + 1] - out : 0;
   VT* val = static_cast<VT*>(a.val);
+  // fill: hits are buffered kBuf at a time and written with vector stores
+  int32_t bc[kBuf];
+  VT bv[kBuf];
+  int nb = 0;
   for (int z = w.z0; z <= w.z1; ++z)
     for (int y = w.y0; y <= w.y1; ++y) {
       const int64_t base = (static_cast<int64_t>(z) * a.g[1] + y) * a.g[0];
@@ -177,11 +202,14 @@ __global__ void __launch_bounds__(kThreads) k_local_rows(AsmArgs a) {
           if constexpr (FILL) {
             const double v = entry_value(a.kt, u2, 0, nullptr, nullptr, q == p);
             const VT vs = static_cast<VT>(v);
-            if (cnt < len) {  // never past the counted row (a mismatch is reported below)
-              a.col[out + cnt] = q;
-              val[out + cnt] = vs;
-            }
             if (q == p) a.diag[p] = static_cast<double>(vs);
+            bc[nb % kBuf] = q;
+            bv[nb % kBuf] = vs;
+            ++nb;
+            if (nb % kBuf == 0 && cnt + 1 <= len) {  // never past the counted row
+              __builtin_memcpy(a.col + out + cnt + 1 - kBuf, bc, sizeof(bc));
+              __builtin_memcpy(val + out + cnt + 1 - kBuf, bv, sizeof(bv));
+            }
           }
           ++cnt;
         }
@@ -191,6 +219,12 @@ __global__ void __launch_bounds__(kThreads) k_local_rows(AsmArgs a) {
     a.counts[p] = cnt;
     a.gskip[p] = 0;
   } else {
+    const int rem = nb % kBuf;
+    if (cnt <= len)
+      for (int j = 0; j < rem; ++j) {
+        a.col[out + cnt - rem + j] = bc[j];
+        val[out + cnt - rem + j] = bv[j];
+      }
     if (static_cast<int64_t>(cnt) != len) atomicOr(a.err, 1);
   }
 }
@@ -273,14 +307,15 @@ __global__ void __launch_bounds__(kThreads) k_group_rows_fill(AsmArgs a) {
     if (lane == 0) atomicOr(a.err, 4);
     return;
   }
+  const int64_t u0 = a.uoff[D_id];
   for (int64_t kk = lane; kk < nU; kk += kWave) {
     const int32_t u = U[kk];
     double xq[3];
-    load_point<D>(a.xb, a.n, u, xq);
+#pragma unroll
+    for (int k = 0; k < D; ++k) xq[k] = a.ux[k * a.utotal + u0 + kk];
     const double u2 = scaled_sq<D>(xp, xq, a.kt.inv0);
-    const uint64_t shared = a.mask[u] & mp;
-    const double* Fq = a.F + static_cast<int64_t>(a.midx[u]) * a.kt.n1;
-    const double v = entry_value(a.kt, u2, shared, Fp, Fq, u == p);
+    const uint64_t shared = a.umask[u0 + kk] & mp;
+    const double v = entry_value(a.kt, u2, shared, Fp, a.uF + u0 + kk, u == p, 1, a.utotal);
     const VT vs = static_cast<VT>(v);
     a.col[out + kk] = u;
     val[out + kk] = vs;
@@ -562,6 +597,7 @@ gp_matrix* assemble(gp_ctx* c, const gp_dataset* ds, const gp_theta* th, int pre
   a.did = d_did;
   a.uoff = d_uoff;
   a.ulist = d_ulist;
+  a.utotal = utotal;
   a.counts = static_cast<int32_t*>(workspace(c, 12, sizeof(int32_t) * n));
   a.gskip = m->gskip;
   a.lcnt = static_cast<int32_t*>(workspace(c, 13, sizeof(int32_t) * std::max<int64_t>(nm, 1)));
@@ -628,6 +664,22 @@ gp_matrix* assemble(gp_ctx* c, const gp_dataset* ds, const gp_theta* th, int pre
   check_launch("long rows");
 
   a.lscratch = static_cast<int32_t*>(workspace(c, 18, sizeof(int32_t) * std::max<int64_t>(sz.ltot, 1)));
+  {
+    const int64_t ut = std::max<int64_t>(utotal, 1);
+    double* ux = static_cast<double*>(workspace(c, 19, sizeof(double) * 3 * ut));
+    uint64_t* umask = static_cast<uint64_t*>(workspace(c, 10, sizeof(uint64_t) * ut));
+    double* uF = static_cast<double*>(workspace(c, 11, sizeof(double) * std::max(kt.n1, 1) * ut));
+    a.ux = ux;
+    a.umask = umask;
+    a.uF = uF;
+    if (utotal > 0)
+      dispatch_d(ds->d, [&](auto DD) {
+        constexpr int D = decltype(DD)::value;
+        hipLaunchKernelGGL((k_ugather<D>), dim3(grid_for(utotal, kThreads)), dim3(kThreads), 0, c->stream, a, ux,
+                           umask, uF);
+      });
+    check_launch("group member data");
+  }
   a.row_ptr = m->row_ptr;
   a.col = m->col;
   a.val = m->val;

@@ -51,15 +51,17 @@ __device__ __forceinline__ double wendland(double u2, int variant) {
 }
 
 // Entry K_pq (Eq. C_sparse + Eq. Zcov): s0 f0 [local] + sum over shared groups
-// in increasing i of f_i(p) f_i(q) + sigma^2 [p = q].
+// in increasing i of f_i(p) f_i(q) + sigma^2 [p = q].  f_i(p) = Fp[i * sp],
+// f_i(q) = Fq[i * sq].
 __device__ __forceinline__ double entry_value(const KernelTheta& kt, double u2, uint64_t shared,
-                                              const double* Fp, const double* Fq, bool diag) {
+                                              const double* Fp, const double* Fq, bool diag, int64_t sp = 1,
+                                              int64_t sq = 1) {
 #pragma clang fp contract(off)
   double acc = (u2 < 1.0) ? kt.s0 * wendland(u2, kt.variant) : 0.0;
   while (shared) {
     const int i = __builtin_ctzll(shared);
     shared &= shared - 1;
-    acc = acc + Fp[i] * Fq[i];
+    acc = acc + Fp[i * sp] * Fq[i * sq];
   }
   if (diag) acc = acc + kt.nugget;
   return acc;

@@ -663,7 +663,7 @@ void spmm(gp_ctx* c, const gp_matrix* m, int k, int ld, const T* X, T* Y, const 
   if (k > 32 || ld < k) throw Error{GP_EINVAL, "spmm: at most 32 right-hand sides per call"};
   ProfScope ps(c, "spmm");
   // partial blocks of the pieces of multi-piece super-tiles
-  T* part = m->npieces > 0 ? static_cast<T*>(workspace(c, 60, sizeof(T) * kSuperRows * 32 * m->npieces)) : nullptr;
+  T* part = m->npieces > 0 ? static_cast<T*>(workspace(c, 55, sizeof(T) * kSuperRows * 32 * m->npieces)) : nullptr;
   const unsigned nb_short = round_up8(grid_for((m->n + kRowsPerWave - 1) / kRowsPerWave, kThreads / kWave));
   const unsigned nb = nb_short + static_cast<unsigned>(m->n_long);
   auto go = [&](auto vt, auto sc) {

@@ -307,8 +307,9 @@ def serve_loglik_stream(n_requests: int = 512, rate: float = 50.0, n_slots: int 
     """The MCMC-proposal workload: Poisson arrivals of log-likelihood requests
     on a pool of 16 mixture data sets (n log-uniform in [5k, 300k])."""
     from workloads import config4_requests
+    from . import PRECOND_JACOBI
     pool, reqs = config4_requests(n_requests=n_requests, rate=rate)
-    be = GpuBackend(n_slots=n_slots)
+    be = GpuBackend(n_slots=n_slots, solve_opts=dict(precond=PRECOND_JACOBI))
     for k, p in enumerate(pool):
         be.add_dataset(f"d{k}", p.x, p.y, cell=p.cell, row_estimate=60.0)
     requests = [LoglikRequest(f"d{k}", th, precision, arrival=t) for (t, k, th) in reqs]
