@@ -171,60 +171,137 @@ __global__ void __launch_bounds__(kThreads) k_ugather(AsmArgs a, double* __restr
 // ------------------------------------------------------- rows without groups
 constexpr int kBuf = 4;
 
+// Candidate points are read through LDS: for each pencil of the window the
+// wave's rows (consecutive in binned order, so mostly neighbouring cells) need
+// one contiguous range of points, the union of their own ranges.  When the
+// union holds at most kStage points the wave stages its coordinates in its LDS
+// slice with coalesced loads and every lane scans its own range from LDS;
+// otherwise the lanes read the points from global memory.
+constexpr int kStage = 256;
+constexpr int kCu = 2;  // candidates whose global loads are in flight together
+
+__device__ __forceinline__ void wave_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <int D, bool FILL, typename VT>
 __global__ void __launch_bounds__(kThreads) k_local_rows(AsmArgs a) {
+  __shared__ double stage[kThreads / kWave][D][kStage];
   const int64_t p = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x;
-  if (p >= a.n) return;
-  if (a.mask[p] != 0) return;
-  double xp[3];
-  load_point<D>(a.xb, a.n, p, xp);
-  int c[3];
-  decode_key(a.key[p], a.g, c);
-  const Window w = make_window<D>(a, c);
+  const int lane = lane_id();
+  double (*st)[kStage] = stage[threadIdx.x / kWave];
+  // lanes without a local-only row take part in the staging with an empty window
+  const bool row = p < a.n && a.mask[p] == 0;
+  if (__ballot(row) == 0) return;  // uniform
+  double xp[3] = {0, 0, 0};
+  Window w{0, -1, 0, 0, 0, 0};
+  if (row) {
+    load_point<D>(a.xb, a.n, p, xp);
+    int c[3];
+    decode_key(a.key[p], a.g, c);
+    w = make_window<D>(a, c);
+  }
+  // the pencils of every row's window have the same (dy, dz) offsets; rows on
+  // a grid edge have fewer, and take the ones that exist
+  int cy = 0, cz = 0;
+  if (row) {
+    int c[3];
+    decode_key(a.key[p], a.g, c);
+    cy = c[1];
+    cz = c[2];
+  }
   int32_t cnt = 0;
-  const int64_t out = FILL ? a.row_ptr[p] : 0;
-  const int64_t len = FILL ? a.row_ptr[p + 1] - out : 0;
+  const int64_t out = (FILL && row) ? a.row_ptr[p] : 0;
+  const int64_t len = (FILL && row) ? a.row_ptr[p + 1] - out : 0;
   VT* val = static_cast<VT*>(a.val);
   // fill: hits are buffered kBuf at a time and written with vector stores
   int32_t bc[kBuf];
   VT bv[kBuf];
   int nb = 0;
-  for (int z = w.z0; z <= w.z1; ++z)
-    for (int y = w.y0; y <= w.y1; ++y) {
-      const int64_t base = (static_cast<int64_t>(z) * a.g[1] + y) * a.g[0];
-      const int32_t s = a.cell_start[base + w.x0];
-      const int32_t e = a.cell_start[base + w.x1 + 1];
-      for (int32_t q = s; q < e; ++q) {
-        double xq[3];
-        load_point<D>(a.xb, a.n, q, xq);
-        const double u2 = scaled_sq<D>(xp, xq, a.kt.inv0);
-        if (u2 < 1.0) {
-          if constexpr (FILL) {
-            const double v = entry_value(a.kt, u2, 0, nullptr, nullptr, q == p);
-            const VT vs = static_cast<VT>(v);
-            if (q == p) a.diag[p] = static_cast<double>(vs);
-            bc[nb % kBuf] = q;
-            bv[nb % kBuf] = vs;
-            ++nb;
-            if (nb % kBuf == 0 && cnt + 1 <= len) {  // never past the counted row
-              __builtin_memcpy(a.col + out + cnt + 1 - kBuf, bc, sizeof(bc));
-              __builtin_memcpy(val + out + cnt + 1 - kBuf, bv, sizeof(bv));
-            }
+  auto hit_at = [&](int32_t q, double u2) {
+    if constexpr (FILL) {
+      const double v = entry_value(a.kt, u2, 0, nullptr, nullptr, q == p);
+      const VT vs = static_cast<VT>(v);
+      if (q == p) a.diag[p] = static_cast<double>(vs);
+      // shift register (constant indices keep it in registers): newest last
+#pragma unroll
+      for (int j = 0; j + 1 < kBuf; ++j) {
+        bc[j] = bc[j + 1];
+        bv[j] = bv[j + 1];
+      }
+      bc[kBuf - 1] = q;
+      bv[kBuf - 1] = vs;
+      ++nb;
+      if (nb % kBuf == 0 && cnt + 1 <= len) {  // never past the counted row
+        __builtin_memcpy(a.col + out + cnt + 1 - kBuf, bc, sizeof(bc));
+        __builtin_memcpy(val + out + cnt + 1 - kBuf, bv, sizeof(bv));
+      }
+    }
+    ++cnt;
+  };
+  const int Ry = D >= 2 ? a.R[1] : 0, Rz = D >= 3 ? a.R[2] : 0;
+  for (int dz = -Rz; dz <= Rz; ++dz)
+    for (int dy = -Ry; dy <= Ry; ++dy) {
+      // this lane's range in pencil (cy + dy, cz + dz)
+      int32_t s = 0, e = 0;
+      const int y = cy + dy, z = cz + dz;
+      if (row && y >= w.y0 && y <= w.y1 && z >= w.z0 && z <= w.z1) {
+        const int64_t base = (static_cast<int64_t>(z) * a.g[1] + y) * a.g[0];
+        s = a.cell_start[base + w.x0];
+        e = a.cell_start[base + w.x1 + 1];
+      }
+      int32_t lo = e > s ? s : INT32_MAX, hi = e > s ? e : INT32_MIN;
+#pragma unroll
+      for (int off = kWave / 2; off > 0; off >>= 1) {
+        lo = min(lo, __shfl_xor(lo, off, kWave));
+        hi = max(hi, __shfl_xor(hi, off, kWave));
+      }
+      if (hi <= lo) continue;  // uniform: no candidates for any lane
+      if (hi - lo <= kStage) {
+        wave_sync_lds();  // the previous pencil's reads are done
+        for (int32_t j = lane; j < hi - lo; j += kWave) {
+          double xq[3];
+          load_point<D>(a.xb, a.n, lo + j, xq);
+#pragma unroll
+          for (int k = 0; k < D; ++k) st[k][j] = xq[k];
+        }
+        wave_sync_lds();
+        for (int32_t q = s; q < e; ++q) {
+          double xq[3];
+#pragma unroll
+          for (int k = 0; k < D; ++k) xq[k] = st[k][q - lo];
+          const double u2 = scaled_sq<D>(xp, xq, a.kt.inv0);
+          if (u2 < 1.0) hit_at(q, u2);
+        }
+      } else {
+        for (int32_t q0 = s; q0 < e; q0 += kCu) {
+          double xq[kCu][3];
+#pragma unroll
+          for (int u = 0; u < kCu; ++u) load_point<D>(a.xb, a.n, min(q0 + u, e - 1), xq[u]);
+#pragma unroll
+          for (int u = 0; u < kCu; ++u) {
+            const double u2 = scaled_sq<D>(xp, xq[u], a.kt.inv0);
+            if (q0 + u < e && u2 < 1.0) hit_at(q0 + u, u2);
           }
-          ++cnt;
         }
       }
     }
+  if (!row) return;
   if constexpr (!FILL) {
     a.counts[p] = cnt;
     a.gskip[p] = 0;
   } else {
+    // the last nb % kBuf hits are still buffered, in bc[kBuf - rem ...]
     const int rem = nb % kBuf;
     if (cnt <= len)
-      for (int j = 0; j < rem; ++j) {
-        a.col[out + cnt - rem + j] = bc[j];
-        val[out + cnt - rem + j] = bv[j];
-      }
+#pragma unroll
+      for (int j = 0; j < kBuf; ++j)
+        if (j >= kBuf - rem) {
+          a.col[out + cnt - kBuf + j] = bc[j];
+          val[out + cnt - kBuf + j] = bv[j];
+        }
     if (static_cast<int64_t>(cnt) != len) atomicOr(a.err, 1);
   }
 }
