@@ -463,11 +463,9 @@ void upload_theta(gp_ctx* c, const gp_theta* th, Bump** bumps_dev, KernelTheta* 
     hb[b].b = th->b[b];
   }
   Bump* dst = static_cast<Bump*>(workspace(c, 0, sizeof(Bump) * std::max(nb, 1)));
-  Bump* staging = static_cast<Bump*>(pinned(c, sizeof(Bump) * std::max(nb, 1)));
+  Bump* staging = static_cast<Bump*>(pinned_for_write(c, sizeof(Bump) * std::max(nb, 1)));
   std::memcpy(staging, hb.data(), sizeof(Bump) * nb);
-  GPS_HIP(hipMemcpyAsync(dst, staging, sizeof(Bump) * nb, hipMemcpyHostToDevice, c->stream));
-  // the staging buffer is reused by later calls: wait for the copy
-  GPS_HIP(hipStreamSynchronize(c->stream));
+  h2d_async(c, dst, staging, sizeof(Bump) * nb);
   *bumps_dev = dst;
   kt->d = th->d;
   kt->n1 = th->n1;
@@ -517,7 +515,7 @@ void compute_features(gp_ctx* c, const gp_dataset* ds, const KernelTheta& kt, Fe
   scan_i32_to_i32(c, flag, pos, n);
   int32_t* h = static_cast<int32_t*>(pinned(c, sizeof(int32_t)));
   GPS_HIP(hipMemcpyAsync(h, pos + n, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
-  GPS_HIP(hipStreamSynchronize(c->stream));
+  sync(c);
   f->nm = *h;
   f->mlist = static_cast<int32_t*>(workspace(c, ws_base + 4, sizeof(int32_t) * std::max<int64_t>(f->nm, 1)));
   uint64_t* mmask = static_cast<uint64_t*>(workspace(c, ws_base + 5, sizeof(uint64_t) * std::max<int64_t>(f->nm, 1)));
@@ -538,6 +536,55 @@ void compute_features(gp_ctx* c, const gp_dataset* ds, const KernelTheta& kt, Fe
 }
 
 // Workspace slots used by assembly (0: bumps; 1..7: features; 8..: below)
+// Distinct masks of the masked points: dmask ascending, did[i] = index of hm[i]
+// in dmask, mult[a] = number of points with mask dmask[a] (hash table, then
+// the few distinct masks are sorted).
+static void distinct_masks(const std::vector<uint64_t>& hm, std::vector<uint64_t>* dmask, std::vector<int32_t>* did,
+                           std::vector<int64_t>* mult) {
+  const int64_t nm = static_cast<int64_t>(hm.size());
+  int bits = 10;
+  std::vector<uint64_t> key(size_t(1) << bits, 0);   // 0 = empty (masks are nonzero)
+  std::vector<int32_t> slot_id(size_t(1) << bits, -1);
+  std::vector<uint64_t> first;                       // distinct masks in order of appearance
+  std::vector<int32_t> tmp(nm);
+  auto find = [&](uint64_t m) -> int32_t& {
+    size_t h = static_cast<size_t>((m * 0x9E3779B97F4A7C15ull) >> (64 - bits));
+    const size_t msk = (size_t(1) << bits) - 1;
+    while (key[h] != 0 && key[h] != m) h = (h + 1) & msk;
+    key[h] = m;
+    return slot_id[h];
+  };
+  for (int64_t i = 0; i < nm; ++i) {
+    int32_t& id = find(hm[i]);
+    if (id < 0) {
+      id = static_cast<int32_t>(first.size());
+      first.push_back(hm[i]);
+      if (2 * first.size() > key.size()) {  // keep the load below one half
+        ++bits;
+        key.assign(size_t(1) << bits, 0);
+        slot_id.assign(size_t(1) << bits, -1);
+        for (size_t d = 0; d < first.size(); ++d) find(first[d]) = static_cast<int32_t>(d);
+      }
+    }
+    tmp[i] = find(hm[i]);
+  }
+  const size_t nD = first.size();
+  std::vector<int32_t> order(nD), rank(nD);
+  for (size_t d = 0; d < nD; ++d) order[d] = static_cast<int32_t>(d);
+  std::sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return first[x] < first[y]; });
+  dmask->resize(nD);
+  mult->assign(nD, 0);
+  for (size_t r = 0; r < nD; ++r) {
+    rank[order[r]] = static_cast<int32_t>(r);
+    (*dmask)[r] = first[order[r]];
+  }
+  did->resize(nm);
+  for (int64_t i = 0; i < nm; ++i) {
+    (*did)[i] = rank[tmp[i]];
+    ++(*mult)[(*did)[i]];
+  }
+}
+
 gp_matrix* assemble(gp_ctx* c, const gp_dataset* ds, const gp_theta* th, int prec) {
   const int64_t n = ds->n;
   Bump* bumps = nullptr;
@@ -547,38 +594,67 @@ gp_matrix* assemble(gp_ctx* c, const gp_dataset* ds, const gp_theta* th, int pre
   compute_features(c, ds, kt, &f, 1);
   const int64_t nm = f.nm;
   uint64_t* mmask = f.mmask;
-  // distinct masks of the masked points (host: at most nm values)
+  // masks of the masked points to the host; the local-row count pass (which
+  // needs only the masks) runs while the host groups them
   std::vector<uint64_t> hm(nm);
-  std::vector<uint64_t> dmask;
-  std::vector<int64_t> uoff(1, 0);
-  std::vector<int32_t> did(nm);
   std::vector<int32_t> hmlist(nm);
-  std::vector<int64_t> mult;
   if (nm > 0) {
     GPS_HIP(hipMemcpyAsync(hm.data(), mmask, sizeof(uint64_t) * nm, hipMemcpyDeviceToHost, c->stream));
     GPS_HIP(hipMemcpyAsync(hmlist.data(), f.mlist, sizeof(int32_t) * nm, hipMemcpyDeviceToHost, c->stream));
-    GPS_HIP(hipStreamSynchronize(c->stream));
-    std::vector<uint64_t> sorted = hm;
-    std::sort(sorted.begin(), sorted.end());
-    for (int64_t i = 0; i < nm; ++i) {
-      if (dmask.empty() || dmask.back() != sorted[i]) {
-        dmask.push_back(sorted[i]);
-        mult.push_back(0);
-      }
-      ++mult.back();
-    }
+    record_aux(c);
+  }
+  const Grid grid = make_grid(ds, th);
+  AsmArgs a{};
+  a.kt = kt;
+  a.n = n;
+  a.xb = ds->xb;
+  a.key = ds->key;
+  a.cell_start = ds->cell_start;
+  for (int k = 0; k < 3; ++k) {
+    a.g[k] = grid.g[k];
+    a.R[k] = grid.R[k];
+  }
+  a.mask = f.mask;
+  a.midx = f.midx;
+  a.mlist = f.mlist;
+  a.F = f.F;
+  a.nm = nm;
+  a.err = c->err_flag;
+  const int d = ds->d;
+  // gskip belongs to the matrix, allocated before the count pass writes it; a
+  // failure below releases whatever the matrix holds by then
+  auto release = [c](gp_matrix* x) { destroy_matrix(c, x); };
+  std::unique_ptr<gp_matrix, decltype(release)> m(new gp_matrix(), release);
+  m->ds = ds;
+  m->n = n;
+  m->prec = prec;
+  m->gskip = dev_new<int32_t>(c, n);
+  a.gskip = m->gskip;
+  a.counts = static_cast<int32_t*>(workspace(c, 12, sizeof(int32_t) * n));
+  dispatch_d(d, [&](auto DD) {
+    constexpr int D = decltype(DD)::value;
+    ProfScope ps(c, "asm_count_local");
+    hipLaunchKernelGGL((k_local_rows<D, false, double>), dim3(grid_for(n, kThreads)), dim3(kThreads), 0, c->stream,
+                       a);
+  });
+  check_launch("count local");
+  std::vector<uint64_t> dmask;
+  std::vector<int64_t> uoff(1, 0);
+  std::vector<int32_t> did;
+  std::vector<int64_t> mult;
+  if (nm > 0) {
+    wait_aux(c);
+    distinct_masks(hm, &dmask, &did, &mult);
     const size_t nD = dmask.size();
     uoff.resize(nD + 1);
     uoff[0] = 0;
-    for (size_t a = 0; a < nD; ++a) {
-      int64_t s = 0;
-      for (size_t b = 0; b < nD; ++b)
-        if (dmask[a] & dmask[b]) s += mult[b];
-      uoff[a + 1] = uoff[a] + s;
+    for (size_t x = 0; x < nD; ++x) {
+      int64_t sum = 0;
+      for (size_t y = 0; y < nD; ++y)
+        if (dmask[x] & dmask[y]) sum += mult[y];
+      uoff[x + 1] = uoff[x] + sum;
     }
     GPS_REQUIRE(uoff[nD] < (int64_t(1) << 31), GP_ENOMEM, "gp_assemble: bump group lists too large");
-    for (int64_t i = 0; i < nm; ++i)
-      did[i] = static_cast<int32_t>(std::lower_bound(dmask.begin(), dmask.end(), hm[i]) - dmask.begin());
   }
   const int64_t nD = static_cast<int64_t>(dmask.size());
   const int64_t utotal = uoff.back();
@@ -609,10 +685,6 @@ gp_matrix* assemble(gp_ctx* c, const gp_dataset* ds, const gp_theta* th, int pre
   tiles.insert(tiles.end(), stiles.begin(), stiles.end());
   tiles.insert(tiles.end(), pieces.begin(), pieces.end());
 
-  std::unique_ptr<gp_matrix> m(new gp_matrix());
-  m->ds = ds;
-  m->n = n;
-  m->prec = prec;
   m->nugget = th->nugget;
   m->nD = nD;
   m->utotal = utotal;
@@ -620,7 +692,6 @@ gp_matrix* assemble(gp_ctx* c, const gp_dataset* ds, const gp_theta* th, int pre
   m->ntiles = ntiles;
   m->nstiles = nstiles;
   m->npieces = npieces;
-  m->gskip = dev_new<int32_t>(c, n);
   m->g_uoff = dev_new<int64_t>(c, nD + 1);
   m->g_ulist = dev_new<int32_t>(c, std::max<int64_t>(utotal, 1));
   m->g_rows = dev_new<int32_t>(c, std::max<int64_t>(nm, 1));
@@ -633,12 +704,12 @@ gp_matrix* assemble(gp_ctx* c, const gp_dataset* ds, const gp_theta* th, int pre
   {
     const size_t b_did = sizeof(int32_t) * nm, b_dm = sizeof(uint64_t) * nD, b_uo = sizeof(int64_t) * (nD + 1);
     const size_t b_gr = sizeof(int32_t) * nm, b_ti = sizeof(int32_t) * tiles.size();
-    char* st = static_cast<char*>(pinned(c, b_did + b_dm + b_uo + b_gr + b_ti + 64));
+    char* st = static_cast<char*>(pinned_for_write(c, b_did + b_dm + b_uo + b_gr + b_ti + 64));
     char* o = st;
     auto put = [&](const void* src, size_t nb, void* dst) {
       if (!nb) return;
       std::memcpy(o, src, nb);
-      GPS_HIP(hipMemcpyAsync(dst, o, nb, hipMemcpyHostToDevice, c->stream));
+      h2d_async(c, dst, o, nb);
       o += nb;
     };
     put(did.data(), b_did, d_did);
@@ -652,46 +723,20 @@ gp_matrix* assemble(gp_ctx* c, const gp_dataset* ds, const gp_theta* th, int pre
                          d_dmask, d_uoff, d_ulist);
       check_launch("group lists");
     }
-    GPS_HIP(hipStreamSynchronize(c->stream));  // pinned staging is reused below
   }
 
-  const Grid grid = make_grid(ds, th);
-  AsmArgs a{};
-  a.kt = kt;
-  a.n = n;
-  a.xb = ds->xb;
-  a.key = ds->key;
-  a.cell_start = ds->cell_start;
-  for (int k = 0; k < 3; ++k) {
-    a.g[k] = grid.g[k];
-    a.R[k] = grid.R[k];
-  }
-  a.mask = f.mask;
-  a.midx = f.midx;
-  a.mlist = f.mlist;
-  a.F = f.F;
-  a.nm = nm;
   a.did = d_did;
   a.uoff = d_uoff;
   a.ulist = d_ulist;
   a.utotal = utotal;
-  a.counts = static_cast<int32_t*>(workspace(c, 12, sizeof(int32_t) * n));
-  a.gskip = m->gskip;
   a.lcnt = static_cast<int32_t*>(workspace(c, 13, sizeof(int32_t) * std::max<int64_t>(nm, 1)));
   int64_t* loff = static_cast<int64_t*>(workspace(c, 14, sizeof(int64_t) * (nm + 1)));
   a.loff = loff;
-  a.err = c->err_flag;
   GPS_HIP(hipMemsetAsync(c->err_flag, 0, sizeof(int), c->stream));
 
-  const int d = ds->d;
-  // count passes
+  // count pass of the rows with a group bit
   dispatch_d(d, [&](auto DD) {
     constexpr int D = decltype(DD)::value;
-    {
-      ProfScope ps(c, "asm_count_local");
-      hipLaunchKernelGGL((k_local_rows<D, false, double>), dim3(grid_for(n, kThreads)), dim3(kThreads), 0,
-                         c->stream, a);
-    }
     if (nm > 0) {
       ProfScope ps(c, "asm_count_group");
       hipLaunchKernelGGL((k_group_rows_scan<D, 0>), dim3(grid_for(nm * kWave, kThreads)), dim3(kThreads), 0,
@@ -722,7 +767,7 @@ gp_matrix* assemble(gp_ctx* c, const gp_dataset* ds, const gp_theta* th, int pre
   GPS_HIP(hipMemcpyAsync(&hs->ltot, loff + nm, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
   GPS_HIP(hipMemcpyAsync(&hs->nlong, lpos + n, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
   GPS_HIP(hipMemcpyAsync(&hs->maxrow, maxrow, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
-  GPS_HIP(hipStreamSynchronize(c->stream));
+  sync(c);
   const Sizes sz = *hs;
   m->nnz = sz.nnz;
   m->max_row = sz.maxrow;
@@ -789,7 +834,7 @@ gp_matrix* assemble(gp_ctx* c, const gp_dataset* ds, const gp_theta* th, int pre
   check_launch("fill");
   int* herr = static_cast<int*>(pinned(c, sizeof(int)));
   GPS_HIP(hipMemcpyAsync(herr, c->err_flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
-  GPS_HIP(hipStreamSynchronize(c->stream));
+  sync(c);
   if (*herr != 0) {
     const int e = *herr;
     destroy_matrix(c, m.release());

@@ -135,7 +135,7 @@ void bin_dataset(gp_ctx* c, gp_dataset* ds, const double* x_dev, const double* c
   check_launch("bbox");
   std::vector<double> hp(6 * nb);
   GPS_HIP(hipMemcpyAsync(hp.data(), part.p, sizeof(double) * 6 * nb, hipMemcpyDeviceToHost, c->stream));
-  GPS_HIP(hipStreamSynchronize(c->stream));
+  sync(c);
   double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
   for (int k = 0; k < d; ++k) {
     lo[k] = INFINITY;
@@ -221,7 +221,7 @@ void bin_dataset(gp_ctx* c, gp_dataset* ds, const double* x_dev, const double* c
   check_launch("gather");
   int32_t* h = static_cast<int32_t*>(pinned(c, sizeof(int32_t)));
   GPS_HIP(hipMemcpyAsync(h, mx.p, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
-  GPS_HIP(hipStreamSynchronize(c->stream));
+  sync(c);
   ds->max_cell = *h;
 }
 

@@ -56,7 +56,7 @@ void* workspace(gp_ctx* c, int slot, size_t bytes) {
 void* pinned(gp_ctx* c, size_t bytes) {
   if (bytes > c->pinned_bytes) {
     // earlier asynchronous copies may still use the old buffer
-    GPS_HIP(hipStreamSynchronize(c->stream));
+    sync(c);
     if (c->pinned) (void)hipHostFree(c->pinned);
     c->pinned = nullptr;
     const size_t want = std::max<size_t>(bytes, 1 << 20);
@@ -66,7 +66,27 @@ void* pinned(gp_ctx* c, size_t bytes) {
   return c->pinned;
 }
 
-void sync(gp_ctx* c) { GPS_HIP(hipStreamSynchronize(c->stream)); }
+void sync(gp_ctx* c) {
+  GPS_HIP(hipStreamSynchronize(c->stream));
+  c->h2d_pending = false;
+}
+
+void* pinned_for_write(gp_ctx* c, size_t bytes) {
+  if (c->h2d_pending) sync(c);
+  return pinned(c, bytes);
+}
+
+void record_aux(gp_ctx* c) {
+  if (!c->ev_aux) GPS_HIP(hipEventCreateWithFlags(&c->ev_aux, hipEventDisableTiming));
+  GPS_HIP(hipEventRecord(c->ev_aux, c->stream));
+}
+
+void wait_aux(gp_ctx* c) { GPS_HIP(hipEventSynchronize(c->ev_aux)); }
+
+void h2d_async(gp_ctx* c, void* dst, const void* src, size_t bytes) {
+  GPS_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, c->stream));
+  c->h2d_pending = true;
+}
 
 hipEvent_t prof_event(gp_ctx* c) {
   if (c->evnext == c->evpool.size()) {
@@ -196,10 +216,11 @@ gp_status gp_ctx_destroy(gp_ctx* c) {
     c->slots.clear();
     if (c->err_flag) gps::dev_free(c, c->err_flag, sizeof(int) * 4);
     c->err_flag = nullptr;
-    GPS_HIP(hipStreamSynchronize(c->stream));
+    gps::sync(c);
     if (c->pinned) (void)hipHostFree(c->pinned);
     c->pinned = nullptr;
     for (hipEvent_t e : c->evpool) (void)hipEventDestroy(e);
+    if (c->ev_aux) (void)hipEventDestroy(c->ev_aux);
     c->evpool.clear();
   });
   delete c;
@@ -209,7 +230,7 @@ gp_status gp_ctx_destroy(gp_ctx* c) {
 gp_status gp_ctx_set_stream(gp_ctx* c, void* stream) {
   if (!c) return GP_EINVAL;
   return guarded(c, [&] {
-    GPS_HIP(hipStreamSynchronize(c->stream));
+    gps::sync(c);
     c->stream = static_cast<hipStream_t>(stream);
   });
 }
@@ -217,7 +238,7 @@ gp_status gp_ctx_set_stream(gp_ctx* c, void* stream) {
 gp_status gp_profile_enable(gp_ctx* c, int32_t on) {
   if (!c) return GP_EINVAL;
   return guarded(c, [&] {
-    GPS_HIP(hipStreamSynchronize(c->stream));
+    gps::sync(c);
     c->prof.clear();
     c->evnext = 0;
     c->prof_on = on != 0;
@@ -227,7 +248,7 @@ gp_status gp_profile_enable(gp_ctx* c, int32_t on) {
 gp_status gp_profile_read(gp_ctx* c, int32_t max_entries, gp_profile_entry* out, int32_t* n_out) {
   if (!c || !n_out || (max_entries > 0 && !out)) return GP_EINVAL;
   return guarded(c, [&] {
-    GPS_HIP(hipStreamSynchronize(c->stream));
+    gps::sync(c);
     std::vector<gp_profile_entry> agg;
     for (const auto& r : c->prof) {
       float ms = 0;
@@ -311,7 +332,7 @@ gp_status gp_dataset_permutation(gp_ctx* c, const gp_dataset* ds, int32_t* perm_
   if (!c || !ds || !perm_dev) return GP_EINVAL;
   return guarded(c, [&] {
     GPS_HIP(hipMemcpyAsync(perm_dev, ds->perm, sizeof(int32_t) * ds->n, hipMemcpyDeviceToDevice, c->stream));
-    GPS_HIP(hipStreamSynchronize(c->stream));
+    gps::sync(c);
   });
 }
 
@@ -361,7 +382,7 @@ gp_status gp_matvec(gp_ctx* c, const gp_matrix* m, int32_t nrhs, const double* x
     else
       gps::spmm<double>(c, m, nrhs, nrhs, xb, yb, nullptr);
     gps::permute_to_orig<double>(c, m->ds, nrhs, yb, y);
-    GPS_HIP(hipStreamSynchronize(c->stream));
+    gps::sync(c);
   });
 }
 
@@ -395,7 +416,7 @@ static gp_status loglik_common(gp_ctx* c, const gp_matrix* m, const double* y, c
       if (solve_status == GP_OK) solve_status = lr.st;
     }
     out->loglik = -0.5 * out->logdet - 0.5 * out->quad - 0.5 * static_cast<double>(n) * std::log(2.0 * M_PI);
-    GPS_HIP(hipStreamSynchronize(c->stream));
+    gps::sync(c);
   });
   if (st != GP_OK) {
     out->status = st;
@@ -444,7 +465,7 @@ gp_status gp_predict(gp_ctx* c, const gp_predictor* p, int64_t m, const double* 
     GPS_REQUIRE(m == 0 || (xs && mean), GP_EINVAL, "gp_predict: NULL buffer");
     GPS_REQUIRE(prec == GP_FP64 || prec == GP_MIXED, GP_EINVAL, "gp_predict: unknown precision");
     gps::predict(c, p, m, xs, prec, mean);
-    GPS_HIP(hipStreamSynchronize(c->stream));
+    gps::sync(c);
   });
 }
 

@@ -89,7 +89,7 @@ void export_csr(gp_ctx* c, const gp_matrix* m, int64_t* row_ptr, int32_t* col, d
   hipLaunchKernelGGL(k_sort_rows, dim3(grid_for(n * kWave, kThreads)), dim3(kThreads), 0, c->stream, n, row_ptr,
                      tcol.as<int32_t>(), tval.as<double>(), col, val);
   check_launch("export sort");
-  GPS_HIP(hipStreamSynchronize(c->stream));
+  sync(c);
 }
 
 template <typename T>

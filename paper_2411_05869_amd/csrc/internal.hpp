@@ -70,6 +70,8 @@ struct gp_ctx {
   void* pinned = nullptr;
   size_t pinned_bytes = 0;
   int* err_flag = nullptr;  // device int, set by kernels on consistency failures
+  bool h2d_pending = false;   // a host-to-device copy from the pinned buffer may not have run yet
+  hipEvent_t ev_aux = nullptr;  // event for partial waits (created on first use)
   // optional per-kernel timing with events on the context's stream
   bool prof_on = false;
   struct ProfRec {
@@ -169,7 +171,17 @@ struct KernelTheta {
 void* dev_alloc(gp_ctx* c, size_t bytes);
 void dev_free(gp_ctx* c, void* p, size_t bytes);
 void* workspace(gp_ctx* c, int slot, size_t bytes);   // grows, never shrinks
+// Pinned host staging.  pinned() is for device-to-host reads (the host reads
+// after sync()); pinned_for_write() first waits for pending uploads from the
+// buffer, and h2d_async() issues such an upload.
 void* pinned(gp_ctx* c, size_t bytes);
+void* pinned_for_write(gp_ctx* c, size_t bytes);
+void h2d_async(gp_ctx* c, void* dst, const void* src, size_t bytes);
+// record_aux() marks the current point of the context's stream; wait_aux()
+// waits until the stream has reached it (work queued after the mark keeps
+// running meanwhile)
+void record_aux(gp_ctx* c);
+void wait_aux(gp_ctx* c);
 void sync(gp_ctx* c);
 
 template <typename T>

@@ -513,7 +513,7 @@ double dot_f64(gp_ctx* c, const double* a, const double* b, int64_t n) {
   check_launch("dot");
   double* h = static_cast<double*>(pinned(c, sizeof(double)));
   GPS_HIP(hipMemcpyAsync(h, out, sizeof(double), hipMemcpyDeviceToHost, c->stream));
-  GPS_HIP(hipStreamSynchronize(c->stream));
+  sync(c);
   return *h;
 }
 
@@ -525,7 +525,7 @@ static double logsum_f64(gp_ctx* c, const double* a, int64_t n) {
   check_launch("logsum");
   double* h = static_cast<double*>(pinned(c, sizeof(double)));
   GPS_HIP(hipMemcpyAsync(h, out, sizeof(double), hipMemcpyDeviceToHost, c->stream));
-  GPS_HIP(hipStreamSynchronize(c->stream));
+  sync(c);
   return *h;
 }
 
@@ -556,7 +556,7 @@ SolveResult pcg_solve(gp_ctx* c, gp_matrix* m, const double* y, double* x, doubl
   const dim3 G(kRedBlocks), B(kThreads);
   auto read = [&]() {
     GPS_HIP(hipMemcpyAsync(hs, s, sizeof(CgScalars), hipMemcpyDeviceToHost, c->stream));
-    GPS_HIP(hipStreamSynchronize(c->stream));
+    sync(c);
     return *hs;
   };
   // z = M^-1 r and the scalars r.z, r.r (mode: see k_beta_fin)
@@ -673,9 +673,9 @@ static LogdetResult slq_impl(gp_ctx* c, const gp_matrix* m, uint64_t seed, int n
     const int k = std::min(32, n_probes - p0);
     LzState init{};
     for (int l = 0; l < 32; ++l) init.active[l] = l < k ? 1 : 0;
-    LzState* hst = static_cast<LzState*>(pinned(c, sizeof(LzState)));
+    LzState* hst = static_cast<LzState*>(pinned_for_write(c, sizeof(LzState)));
     *hst = init;
-    GPS_HIP(hipMemcpyAsync(st, hst, sizeof(LzState), hipMemcpyHostToDevice, c->stream));
+    h2d_async(c, st, hst, sizeof(LzState));
     GPS_HIP(hipMemsetAsync(bad, 0, sizeof(int), c->stream));
     hipLaunchKernelGGL((k_lz_init<T>), dim3(grid_for(n * ld, kThreads)), dim3(kThreads), 0, c->stream, n, k, ld, p0,
                        seed, m->ds->perm, V, Vp, 1.0 / std::sqrt(static_cast<double>(n)));
@@ -708,7 +708,7 @@ static LogdetResult slq_impl(gp_ctx* c, const gp_matrix* m, uint64_t seed, int n
     GPS_HIP(hipMemcpyAsync(hs2, st, sizeof(LzState), hipMemcpyDeviceToHost, c->stream));
     int* hb = reinterpret_cast<int*>(reinterpret_cast<char*>(hs2) + sizeof(LzState));
     GPS_HIP(hipMemcpyAsync(hb, bad, sizeof(int), hipMemcpyDeviceToHost, c->stream));
-    GPS_HIP(hipStreamSynchronize(c->stream));
+    sync(c);
     for (int l = 0; l < k; ++l) {
       gammas.push_back(hg[l]);
       max_steps = std::max(max_steps, hs2->steps[l]);

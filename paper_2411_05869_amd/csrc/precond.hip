@@ -145,7 +145,7 @@ void build_block_jacobi(gp_ctx* c, gp_matrix* m) {
   scan_i32_to_i32(c, flag, pos, n);
   int32_t* h = static_cast<int32_t*>(pinned(c, sizeof(int32_t)));
   GPS_HIP(hipMemcpyAsync(h, pos + n, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
-  GPS_HIP(hipStreamSynchronize(c->stream));
+  sync(c);
   const int64_t nblk = *h;
   m->nblk = nblk;
   m->bstart = dev_new<int32_t>(c, nblk + 1);
@@ -177,7 +177,7 @@ void build_block_jacobi(gp_ctx* c, gp_matrix* m) {
   }
   int* herr = static_cast<int*>(pinned(c, sizeof(int)));
   GPS_HIP(hipMemcpyAsync(herr, c->err_flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
-  GPS_HIP(hipStreamSynchronize(c->stream));
+  sync(c);
   if (*herr) throw Error{GP_ENOTPD, "block-Jacobi setup met a non-positive pivot: matrix not positive definite"};
 }
 

@@ -152,7 +152,7 @@ gp_predictor* make_predictor(gp_ctx* c, const gp_dataset* ds, const gp_theta* th
                        p->alpha_b, p->coef);
     check_launch("group coefficients");
   }
-  GPS_HIP(hipStreamSynchronize(c->stream));
+  sync(c);
   return p.release();
 }
 

@@ -134,7 +134,7 @@ void scan_i32_to_i32(gp_ctx* c, const int32_t* in, int32_t* out, int64_t n) {
 int64_t read_i64(gp_ctx* c, const int64_t* dev) {
   int64_t* h = static_cast<int64_t*>(pinned(c, sizeof(int64_t)));
   GPS_HIP(hipMemcpyAsync(h, dev, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
-  GPS_HIP(hipStreamSynchronize(c->stream));
+  sync(c);
   return *h;
 }
 
