@@ -43,6 +43,73 @@ def spmm_bytes(n, nnz, vbytes, k, xbytes):
     return nnz * (vbytes + 4) + (n + 1) * 8 + 2 * n * k * xbytes + n * xbytes
 
 
+TRAFFIC_PROFILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                               "traffic_spmv_f32_spacetime_n1095000.md")
+SPMV_SOURCE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2411_05869_amd", "csrc", "spmv.hip")
+SPMV_F32_KERNELS = ("k_group_spmv<float, float, float, float>", "k_spmv<float, float, float, float>")
+CALIB_BYTES = 1 << 30
+
+
+def source_sha256(path):
+    import hashlib
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def stored_traffic():
+    """HBM bytes per FP32 SpMV (both kernels) from the committed counter summary,
+    or None when it is missing or the SpMV source changed since it was taken."""
+    try:
+        fields = {}
+        for line in open(TRAFFIC_PROFILE):
+            if line.startswith("- ") and ": " in line:
+                k, v = line[2:].split(": ", 1)
+                fields[k.strip()] = v.strip().strip("`")
+        if fields.get("spmv_source_sha256") != source_sha256(SPMV_SOURCE):
+            return None
+        return int(fields["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def summarize_pmc(fetch_dir, write_dir, command):
+    """Per-dispatch FETCH_SIZE / WRITE_SIZE (KiB) of the FP32 SpMV kernels, scaled
+    by what the same counters read for a copy of CALIB_BYTES bytes."""
+    import csv
+    import glob
+
+    def load(d, counter):
+        f = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+        rows = [r for r in csv.DictReader(open(f[0])) if r["Counter_Name"] == counter]
+        copy = max(float(r["Counter_Value"]) for r in rows if "copy" in r["Kernel_Name"].lower())
+        per = {}
+        for k in SPMV_F32_KERNELS:
+            v = [float(r["Counter_Value"]) for r in rows if k in r["Kernel_Name"]]
+            per[k] = (sum(v) / len(v), len(v))
+        return copy, per
+
+    cf, pf = load(fetch_dir, "FETCH_SIZE")
+    cw, pw = load(write_dir, "WRITE_SIZE")
+    sf, sw = CALIB_BYTES / (cf * 1024.0), CALIB_BYTES / (cw * 1024.0)
+    fetch = sum(v for v, _ in pf.values()) * 1024.0 * sf
+    write = sum(v for v, _ in pw.values()) * 1024.0 * sw
+    lines = ["# HBM traffic of the FP32 SpMV (conjugate-gradient product) on the space-time workload, n = 1,095,000",
+             "", "Two counter runs of the same command (run from /tmp with TMPDIR=/tmp on one MI355X), "
+             "one with `--pmc FETCH_SIZE`, one with `--pmc WRITE_SIZE`:", "", "```", command, "```", "",
+             f"Calibration: a device-to-device copy of {CALIB_BYTES} bytes (bench.py --copy-calibration) read "
+             f"FETCH_SIZE {cf:.0f} KiB and WRITE_SIZE {cw:.0f} KiB; scale factors {sf:.4f} (fetch), {sw:.4f} (write).",
+             "", "| kernel | dispatches | FETCH_SIZE KiB/dispatch | WRITE_SIZE KiB/dispatch |", "|---|---:|---:|---:|"]
+    for k in SPMV_F32_KERNELS:
+        lines.append(f"| `{k}` | {pf[k][1]} | {pf[k][0]:.0f} | {pw[k][0]:.0f} |")
+    lines += ["", "Figures read by bench.py (traffic of one SpMV = both kernels, scaled):", "",
+              f"- fetch_bytes_per_launch: {int(fetch)}", f"- write_bytes_per_launch: {int(write)}",
+              f"- traffic_bytes_per_launch: {int(fetch + write)}",
+              f"- spmv_source_sha256: `{source_sha256(SPMV_SOURCE)}`", ""]
+    with open(TRAFFIC_PROFILE, "w") as f:
+        f.write("\n".join(lines))
+    print("\n".join(lines))
+
+
 def cpu_baseline(p):
     """The oracle on a bounded sample of the same workload (same point density):
     stations in [0, 0.5]^2, days 0..72 -> about 55k points, 2.3M nonzeros."""
@@ -121,7 +188,14 @@ def main():
     ap.add_argument("--stations", type=int, default=3000)
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=128)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="copy 1 GiB device-to-device first (reference dispatch for HBM counters)")
+    ap.add_argument("--summarize-pmc", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "COMMAND"),
+                    help="write the SpMV traffic summary from two rocprofv3 --pmc output folders and exit")
     args = ap.parse_args()
+    if args.summarize_pmc:
+        summarize_pmc(*args.summarize_pmc)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
               "(the single-GPU path is the product; multi-GPU sharding is described in DESIGN.md)", file=sys.stderr)
@@ -136,6 +210,12 @@ def main():
     p = config3(n_stations=args.stations)
     log(f"workload {p.name}: n={p.n} d={p.d}")
     dev = torch.device("cuda", 0)
+    if args.copy_calibration:
+        src = torch.empty(CALIB_BYTES, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     x = torch.tensor(p.x, device=dev)
     y = torch.tensor(p.y, device=dev)
     xs_np = config5_requests(1, seed=5, m_lo=10000, m_hi=10000)[0]
@@ -177,8 +257,23 @@ def main():
         ctx.profile(False)
         return dt, res, prof
 
+    def assemble_wall(prec, reps=5):
+        # wall time of the whole assemble call (host work and synchronisations
+        # included), device idle at the start; median of reps
+        ws = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            K = ctx.assemble(ds, p.theta, prec)
+            torch.cuda.synchronize()
+            ws.append(time.perf_counter() - t0)
+            K.close()
+        return sorted(ws)[reps // 2]
+
     dt_m, res_m, prof_m = timed(MIXED, args.steps, args.warmup)
     dt_d, res_d, prof_d = timed(FP64, args.fp64_steps, min(args.warmup, 1))
+    asm_wall_m = assemble_wall(MIXED)
+    asm_wall_d = assemble_wall(FP64)
     r_m, info_m = res_m[-1]
     r_d, info_d = res_d[-1]
     ms_step = 1e3 * dt_m / args.steps
@@ -190,7 +285,8 @@ def main():
     n, nnz = p.n, info_m["nnz"]
 
     # dominant kernel of the timed region and its algorithmic bytes per launch
-    dom = max(prof_m.items(), key=lambda kv: kv[1][1])
+    known = ("spmv_f32", "spmv_f32val_f64", "spmv_f64", "spmm")  # kernels with a bytes model
+    dom = max(((k, v) for k, v in prof_m.items() if k in known), key=lambda kv: kv[1][1])
     name, (cnt, tot) = dom
     avg_s = tot / cnt / 1e3
     if name == "spmv_f32":
@@ -205,7 +301,8 @@ def main():
         b = float("nan")
     achieved = b / avg_s / 1e9
     roof = dict(bound="hbm", kernel=name, achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None, avg_us=round(avg_s * 1e6, 2),
+                frac=round(achieved / HBM_PEAK_GBS, 4),
+                traffic=stored_traffic() if name == "spmv_f32" else None, avg_us=round(avg_s * 1e6, 2),
                 launches=cnt, bytes_per_launch=int(b))
 
     out = dict(metric=METRIC, value=round(evals_m, 4), unit="loglik evals/s", n_gpus=1, steps=args.steps,
@@ -214,9 +311,11 @@ def main():
                config=dict(workload=f"space-time {p.name}: n={n}, d=3, r0=(0.03,0.03,3d), 16x4 bumps, nugget 1e-2; "
                                     "step = assemble + PCG(rtol 1e-10) + SLQ(30x50) + predict(10k points)",
                            n=n, nnz=nnz, max_row=info_m["max_row"]),
-               nnz_per_s=round(nnz / (asm_ms_m / 1e3), 1), assemble_ms=round(asm_ms_m, 3),
+               nnz_per_s=round(nnz / asm_wall_m, 1), assemble_ms=round(1e3 * asm_wall_m, 3),
+               assemble_kernels_ms=round(asm_ms_m, 3),
                fp64=dict(value=round(evals_d, 4), unit="loglik evals/s", ms_per_step=round(1e3 * dt_d / args.fp64_steps, 2),
-                         nnz_per_s=round(nnz / (asm_ms_d / 1e3), 1), assemble_ms=round(asm_ms_d, 3),
+                         nnz_per_s=round(nnz / asm_wall_d, 1), assemble_ms=round(1e3 * asm_wall_d, 3),
+                         assemble_kernels_ms=round(asm_ms_d, 3),
                          loglik=r_d["loglik"], cg_iters=r_d["cg_iters"]),
                mixed=dict(loglik=r_m["loglik"], logdet=r_m["logdet"], quad=r_m["quad"], logdet_se=r_m["logdet_se"],
                           cg_iters=r_m["cg_iters"], refreshes=r_m["refreshes"], relres=r_m["relres"],

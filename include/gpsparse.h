@@ -150,11 +150,15 @@ typedef struct gp_theta {
 
 /* ------------------------------------------------------------------ matrix
  * gp_assemble: builds K(theta) + sigma^2 I for the dataset as a CSR matrix
- * owned by the library, rows and columns in binned order, ascending column
- * indices, full symmetric storage.  The pattern is exactly the set of pairs
- * that pass a support test (local Wendland support, a shared bump group, or
- * the diagonal); entries whose value underflows stay stored.  Values are
- * float64 (GP_FP64) or float32 rounded from float64 (GP_MIXED).
+ * owned by the library, rows and columns in binned order, full symmetric
+ * storage, every column once per row.  A row of a point with no bump group
+ * holds its columns in ascending order.  A row of a point whose bump-group
+ * mask is M first holds the columns U_M = {q : mask(q) & M != 0} in ascending
+ * order (one list shared by all rows with mask M), then its remaining local
+ * columns in ascending order.  The pattern is exactly the set of pairs that
+ * pass a support test (local Wendland support, a shared bump group, or the
+ * diagonal); entries whose value underflows stay stored.  Values are float64
+ * (GP_FP64) or float32 rounded from float64 (GP_MIXED).
  * Errors: GP_EINVAL (theta), GP_ENOMEM, GP_EDEVICE (device error or the
  * count and fill passes disagree). */
 GP_API gp_status gp_assemble(gp_ctx* ctx, const gp_dataset* ds, const gp_theta* theta,
@@ -207,8 +211,9 @@ typedef struct gp_loglik_result {
 } gp_loglik_result;
 
 /* gp_loglik: log p(y | theta) for the residual y = z - W beta (y_dev: n
- * float64 in ORIGINAL point order).  Quadratic form by Jacobi-preconditioned
- * conjugate gradients on K; log det by stochastic Lanczos quadrature on the
+ * float64 in ORIGINAL point order).  Quadratic form by preconditioned
+ * conjugate gradients on K (gp_precond); log det by stochastic Lanczos
+ * quadrature on the
  * Jacobi-scaled matrix (or exact Lanczos, see gp_logdet_mode).  With a
  * GP_MIXED matrix the products run in float32 and the residual
  * recomputation, Lanczos coefficients, quadrature and quadratic form in
@@ -236,8 +241,10 @@ GP_API gp_status gp_predictor_destroy(gp_ctx* ctx, gp_predictor* p);
 /* gp_predict: posterior mean m(x*) = sum_q C_y(x*, x_q) alpha_q (no nugget)
  * for m test points (xstar_dev: m x d row-major float64) into mean_dev (m
  * float64).  The cross-covariance is evaluated and applied in one pass and
- * never stored.  GP_MIXED evaluates the cross-covariance in float32.
- * Errors: GP_EINVAL (m < 0, non-finite), GP_EDEVICE. */
+ * never stored.  GP_MIXED evaluates the cross-covariance in float32.  Test
+ * coordinates are device data and are not checked: a non-finite test point
+ * passes no support test and gets mean 0.
+ * Errors: GP_EINVAL (m < 0, NULL buffers, unknown precision), GP_EDEVICE. */
 GP_API gp_status gp_predict(gp_ctx* ctx, const gp_predictor* p, int64_t m, const double* xstar_dev,
                      gp_precision prec, double* mean_dev);
 

@@ -90,9 +90,11 @@ __device__ __forceinline__ double precond_row_next(const Precond& M, const doubl
 
 // One CG step after the product q = K p.  Every block adds the kRedBlocks
 // partials of p.q (pq_part, same fixed order in every block) and forms alpha =
-// rz / pq; then, grid-stride over rows: x += alpha p, rn = r - alpha q, z =
-// M^-1 rn, and per-block partials of rn.z and rn.rn.  Block 0 records pq, alpha,
-// rz_old = rz and the status (non-positive curvature).
+// rz / pq; then, one thread per row (the block-Jacobi product is a short chain
+// of dependent gathers, so the full grid keeps enough of them in flight):
+// x += alpha p, rn = r - alpha q, z = M^-1 rn, and per-block partials of rn.z and
+// rn.rn.  Block 0 records pq, alpha, rz_old = rz and the status (non-positive
+// curvature).
 template <typename QT>
 __global__ void __launch_bounds__(kThreads) k_pcg_step(int64_t n, Precond M, CgScalars* __restrict__ s,
                                                        const double* __restrict__ pq_part,
@@ -106,15 +108,15 @@ __global__ void __launch_bounds__(kThreads) k_pcg_step(int64_t n, Precond M, CgS
   const bool ok = pq > 0.0 && isfinite(pq);
   const double alpha = ok ? rz / pq : 0.0;
   double v[2] = {0, 0};
-  for (int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; i < n;
-       i += static_cast<int64_t>(gridDim.x) * kThreads) {
+  const int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x;
+  if (i < n) {
     x[i] += alpha * p[i];
     const double ri = r[i] - alpha * static_cast<double>(q[i]);
     const double zi = precond_row_next<QT>(M, r, q, alpha, ri, i);
     rn[i] = ri;
     z[i] = zi;
-    v[0] += ri * zi;
-    v[1] += ri * ri;
+    v[0] = ri * zi;
+    v[1] = ri * ri;
   }
   block_sum_store<2>(v, part);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -125,15 +127,15 @@ __global__ void __launch_bounds__(kThreads) k_pcg_step(int64_t n, Precond M, CgS
   }
 }
 
-// New direction after a step: every block adds the step's partials (same fixed
-// order) into rz, rr and beta = rz / rz_old, then p = z + beta p (and its
+// New direction after a step: every block adds the step's nb partials (same
+// fixed order) into rz, rr and beta = rz / rz_old, then p = z + beta p (and its
 // float32 copy).  Block 0 records rz, rr, beta and flags non-finite values.
 __global__ void __launch_bounds__(kThreads) k_pcg_direction(int64_t n, CgScalars* __restrict__ s,
-                                                            const double* __restrict__ part,
+                                                            const double* __restrict__ part, int nb,
                                                             const double* __restrict__ z, double* __restrict__ p,
                                                             float* __restrict__ p32) {
   double sums[2];
-  reduce_partials<2>(part, kRedBlocks, sums);
+  reduce_partials<2>(part, nb, sums);
   const double beta = sums[0] / s->rz_old;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     s->rz = sums[0];
@@ -333,21 +335,31 @@ struct LzState {
   int steps[32];
 };
 
-// mode 0: alpha; mode 1: beta + breakdown (j = step index, last = final step)
-__global__ void __launch_bounds__(kThreads) k_lz_fin(const double* __restrict__ part, int nb, int k, int mode, int j,
-                                                     int last, double tol, LzState* __restrict__ st,
-                                                     double* __restrict__ Ta, double* __restrict__ Tb) {
-  // 32 columns; each of 8 groups of 32 threads sums a strided subset, fixed order
-  __shared__ double sh[8][32];
+// mode 0: alpha; mode 1: beta + breakdown (j = step index, last = final step).
+// 32 columns; each of kFinGroups groups of 32 threads sums the partials b = g,
+// g + kFinGroups, ... of its column (four interleaved accumulators, so several
+// loads are in flight), then the groups are added in order.
+constexpr int kFinGroups = 32;
+
+__global__ void __launch_bounds__(kFinGroups * 32) k_lz_fin(const double* __restrict__ part, int nb, int k, int mode,
+                                                            int j, int last, double tol, LzState* __restrict__ st,
+                                                            double* __restrict__ Ta, double* __restrict__ Tb) {
+  __shared__ double sh[kFinGroups][32];
   const int l = threadIdx.x & 31;
   const int g = threadIdx.x >> 5;
-  double s = 0;
-  for (int b = g; b < nb; b += 8) s += part[b * 32 + l];
-  sh[g][l] = s;
+  double a4[4] = {0, 0, 0, 0};
+  int b = g;
+  for (; b + 3 * kFinGroups < nb; b += 4 * kFinGroups)
+#pragma unroll
+    for (int u = 0; u < 4; ++u) a4[u] += part[(b + u * kFinGroups) * 32 + l];
+#pragma unroll
+  for (int u = 0; u < 3; ++u)
+    if (b + u * kFinGroups < nb) a4[u] += part[(b + u * kFinGroups) * 32 + l];
+  sh[g][l] = (a4[0] + a4[1]) + (a4[2] + a4[3]);
   __syncthreads();
   if (g == 0 && l < k) {
     double t = 0;
-    for (int q = 0; q < 8; ++q) t += sh[q][l];
+    for (int q = 0; q < kFinGroups; ++q) t += sh[q][l];
     if (mode == 0) {
       st->alpha[l] = t;
       if (st->active[l]) Ta[j * 32 + l] = t;
@@ -593,7 +605,7 @@ SolveResult pcg_solve(gp_ctx* c, gp_matrix* m, const double* y, double* x, doubl
   // partials of r.z, r.r), the new direction (beta, p); the last step before a
   // host check leaves the direction to after the check
   double* pqp = part;                    // kRedBlocks partials of p.q
-  double* spart = part + kRedBlocks;     // 2 x kRedBlocks partials of r.z, r.r
+  double* spart = ppart;                 // 2 x nbp partials of r.z, r.r
   while (it < max_iter && !converged) {
     const int steps = std::min(kCheckEvery, max_iter - it);
     for (int t = 0; t < steps; ++t) {
@@ -605,16 +617,18 @@ SolveResult pcg_solve(gp_ctx* c, gp_matrix* m, const double* y, double* x, doubl
         ProfScope ps(c, "pcg_vector_ops");
         if (mixed) {
           hipLaunchKernelGGL((k_pq_part<float>), G, B, 0, c->stream, n, p, q32, pqp);
-          hipLaunchKernelGGL((k_pcg_step<float>), G, B, 0, c->stream, n, M, s, pqp, p, q32, x, rc, rnx, z, spart);
+          hipLaunchKernelGGL((k_pcg_step<float>), dim3(nbp), B, 0, c->stream, n, M, s, pqp, p, q32, x, rc, rnx, z,
+                             spart);
         } else {
           hipLaunchKernelGGL((k_pq_part<double>), G, B, 0, c->stream, n, p, q, pqp);
-          hipLaunchKernelGGL((k_pcg_step<double>), G, B, 0, c->stream, n, M, s, pqp, p, q, x, rc, rnx, z, spart);
+          hipLaunchKernelGGL((k_pcg_step<double>), dim3(nbp), B, 0, c->stream, n, M, s, pqp, p, q, x, rc, rnx, z,
+                             spart);
         }
         std::swap(rc, rnx);
         if (t + 1 < steps)
-          hipLaunchKernelGGL(k_pcg_direction, G, B, 0, c->stream, n, s, spart, z, p, p32);
+          hipLaunchKernelGGL(k_pcg_direction, G, B, 0, c->stream, n, s, spart, static_cast<int>(nbp), z, p, p32);
         else
-          hipLaunchKernelGGL(k_beta_fin, dim3(1), B, 0, c->stream, spart, kRedBlocks, s, 3);
+          hipLaunchKernelGGL(k_beta_fin, dim3(1), B, 0, c->stream, spart, static_cast<int>(nbp), s, 3);
       }
       check_launch("pcg iteration");
     }
@@ -686,11 +700,11 @@ static LogdetResult slq_impl(gp_ctx* c, const gp_matrix* m, uint64_t seed, int n
       ProfScope ps(c, "lanczos_vector_ops");
       hipLaunchKernelGGL((k_lz_beta_dot<T>), dim3(kRedBlocks), dim3(kThreads), 0, c->stream, n, ld, st->beta_prev, V,
                          Vp, W, part);
-      hipLaunchKernelGGL(k_lz_fin, dim3(1), dim3(kThreads), 0, c->stream, part, kRedBlocks, k, 0, j, last, tol, st,
+      hipLaunchKernelGGL(k_lz_fin, dim3(1), dim3(kFinGroups * 32), 0, c->stream, part, kRedBlocks, k, 0, j, last, tol, st,
                          Ta, Tb);
       hipLaunchKernelGGL((k_lz_alpha_norm<T>), dim3(kRedBlocks), dim3(kThreads), 0, c->stream, n, ld, st->alpha, V, W,
                          part);
-      hipLaunchKernelGGL(k_lz_fin, dim3(1), dim3(kThreads), 0, c->stream, part, kRedBlocks, k, 1, j, last, tol, st,
+      hipLaunchKernelGGL(k_lz_fin, dim3(1), dim3(kFinGroups * 32), 0, c->stream, part, kRedBlocks, k, 1, j, last, tol, st,
                          Ta, Tb);
       if (!last) {
         hipLaunchKernelGGL((k_lz_next<T>), dim3(grid_for(n * ld, kThreads)), dim3(kThreads), 0, c->stream, n, ld, st,
