@@ -442,12 +442,21 @@ __device__ bool tridiag_eig_first_row(double* a, double* b, double* q, int m) {
 }
 
 // One thread per probe: Gamma_l = |z|^2 sum_t tau_t^2 log theta_t.
-__global__ void k_quadrature(int k, const double* __restrict__ Ta, const double* __restrict__ Tb,
-                             const LzState* __restrict__ st, double znorm2, double* __restrict__ gam,
-                             int* __restrict__ bad) {
-  const int l = threadIdx.x;
+// One thread per probe; the tridiagonal matrix and the eigenvector row live in
+// LDS (rows padded against bank conflicts), kQuadProbes probes per block.
+constexpr int kQuadProbes = 8;
+constexpr int kQuadMax = 128;
+
+__global__ void __launch_bounds__(kQuadProbes) k_quadrature(int k, const double* __restrict__ Ta,
+                                                            const double* __restrict__ Tb,
+                                                            const LzState* __restrict__ st, double znorm2,
+                                                            double* __restrict__ gam, int* __restrict__ bad) {
+  __shared__ double sa[kQuadProbes][kQuadMax + 1], sb[kQuadProbes][kQuadMax + 1], sq[kQuadProbes][kQuadMax + 1];
+  const int l = blockIdx.x * kQuadProbes + threadIdx.x;
   if (l >= k) return;
-  double a[128], b[128], q[128];
+  double* a = sa[threadIdx.x];
+  double* b = sb[threadIdx.x];
+  double* q = sq[threadIdx.x];
   const int m = st->steps[l];
   for (int j = 0; j < m; ++j) {
     a[j] = Ta[j * 32 + l];
@@ -713,7 +722,7 @@ static LogdetResult slq_impl(gp_ctx* c, const gp_matrix* m, uint64_t seed, int n
       }
       check_launch("lanczos step");
     }
-    hipLaunchKernelGGL(k_quadrature, dim3(1), dim3(64), 0, c->stream, k, Ta, Tb, st, static_cast<double>(n), gam,
+    hipLaunchKernelGGL(k_quadrature, dim3((k + kQuadProbes - 1) / kQuadProbes), dim3(kQuadProbes), 0, c->stream, k, Ta, Tb, st, static_cast<double>(n), gam,
                        bad);
     check_launch("quadrature");
     double* hg = static_cast<double*>(pinned(c, sizeof(double) * 32 + sizeof(LzState) + 16));

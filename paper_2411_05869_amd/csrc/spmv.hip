@@ -18,30 +18,31 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kG = 8;
 
-constexpr int kU = 4;   // independent loads in flight per lane
 
 inline unsigned round_up8(unsigned v) { return (v + 7u) & ~7u; }
 
 // Partial row sum over entries [s, e) for lane `sub` of a group of G lanes: each
-// lane keeps kU (column, value) pairs in flight before gathering x, so a row's
-// loads overlap instead of forming a dependent chain.  Lanes past the row end
-// read x[self] with weight 0.
+// lane takes 4 consecutive entries at a time (column ids and values by one
+// 16-byte load each; a load may run up to 3 entries past the row, which stays
+// inside the padded arrays) and gathers their 4 x values together.  Entries past
+// the row end read x[self] with weight 0.
 template <typename VT, typename XT, typename AT, int G>
 __device__ __forceinline__ AT spmv_part(int64_t s, int64_t e, int sub, int32_t self, const int32_t* __restrict__ col,
                                         const VT* __restrict__ val, const XT* __restrict__ x) {
   AT acc = 0;
-  for (int64_t j0 = s + sub; j0 < e; j0 += kU * G) {
-    int32_t c[kU];
-    AT v[kU];
+  for (int64_t j0 = s + 4 * sub; j0 < e; j0 += 4 * G) {
+    int32_t c[4];
+    VT v[4];
+    __builtin_memcpy(c, col + j0, sizeof(c));
+    __builtin_memcpy(v, val + j0, sizeof(v));
 #pragma unroll
-    for (int u = 0; u < kU; ++u) {
-      const int64_t j = j0 + u * G;
-      const bool in = j < e;
-      c[u] = in ? col[j] : self;
-      v[u] = in ? static_cast<AT>(val[j]) : AT(0);
+    for (int u = 0; u < 4; ++u) {
+      const bool in = j0 + u < e;
+      c[u] = in ? c[u] : self;
+      v[u] = in ? v[u] : VT(0);
     }
 #pragma unroll
-    for (int u = 0; u < kU; ++u) acc += v[u] * static_cast<AT>(x[c[u]]);
+    for (int u = 0; u < 4; ++u) acc += static_cast<AT>(v[u]) * static_cast<AT>(x[c[u]]);
   }
   return acc;
 }
