@@ -1,0 +1,153 @@
+"""GPU parity at the benchmark's sizes.
+
+* Space-time workload, n = 1,095,000, in the launch configuration bench.py
+  times: sampled rows of the assembled matrix against the oracle's brute-force
+  row (every point tested with the pinned predicate): pattern bit-exact, values
+  within 1e-13 relative (float64; exp and sqrt may differ by an ulp between
+  libraries) and equal to the float32 rounding of the oracle's value (mixed).
+* Same workload: the float64 solve alpha, checked row by row with oracle rows:
+  |y_p - sum_q K_pq alpha_q| must stay within the global stopping bound
+  1e-10 |y|_2 (plus the rounding of the oracle's own row sum).
+* Same workload: kriging means at sampled test points against the oracle's
+  sparse cross-covariance rows (float64 1e-10, mixed 2e-7 of sum |C| |alpha|).
+* Mixture workload, n = 100,000: quadratic form and alpha against the oracle's
+  K = A + F F^T split (SuperLU on the local part, Woodbury for the bump groups);
+  1e-8 (float64) / 1e-5 (mixed); the SLQ log det against the exact one within
+  3 standard errors.
+"""
+import copy
+
+import numpy as np
+import pytest
+
+from oracle import kernel, likelihood, predict
+from workloads import config2, config3, config5_requests
+from gpu_util import dev, host, rel
+
+pytestmark = pytest.mark.gpu
+
+N_ROWS = 100
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2411_05869_amd import Context
+    return Context()
+
+
+@pytest.fixture(scope="module")
+def cfg3(ctx):
+    p = config3()
+    M, F = kernel.features(p.x, p.theta)
+    ds = ctx.dataset(dev(p.x), cell=p.cell)
+    rows = np.random.default_rng(2024).choice(p.n, N_ROWS, replace=False)
+    # always include rows with a bump group (long rows) in the sample
+    masked = np.nonzero(M.any(axis=1))[0]
+    rows = np.unique(np.concatenate([rows, np.random.default_rng(7).choice(masked, 20, replace=False)]))
+    oracle_rows = {int(r): kernel.row(p.x, p.theta, int(r), M, F) for r in rows}
+    return p, ds, oracle_rows
+
+
+def _gpu_rows(ctx, K, rows):
+    import torch
+    rp, col, val = ctx.export_csr(K)
+    out = {}
+    for r in rows:
+        s, e = int(rp[r]), int(rp[r + 1])
+        out[r] = (host(col[s:e]).astype(np.int64), host(val[s:e]))
+    del rp, col, val
+    torch.cuda.empty_cache()
+    return out
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_config3_sampled_rows(ctx, cfg3, prec):
+    p, ds, orows = cfg3
+    K = ctx.assemble(ds, p.theta, prec)
+    assert K.n == p.n
+    g = _gpu_rows(ctx, K, orows.keys())
+    worst = 0.0
+    for r, (oc, ov) in orows.items():
+        gc, gv = g[r]
+        assert np.array_equal(gc, oc), f"row {r}: pattern differs ({gc.size} vs {oc.size} entries)"
+        if prec == 0:
+            err = np.abs(gv - ov) / np.maximum(np.abs(ov), 1e-300)
+            worst = max(worst, float(err.max()))
+        else:
+            assert np.array_equal(gv.astype(np.float32), ov.astype(np.float32)), f"row {r}: float32 values"
+    print(f"[cfg3 rows prec={prec}] {len(orows)} rows, {sum(v[0].size for v in orows.values())} entries, "
+          f"max rel value error {worst:.2e}, nnz {K.nnz}")
+    assert worst <= 1e-13
+
+
+def test_config3_solve_residual_rows(ctx, cfg3):
+    import torch
+    p, ds, orows = cfg3
+    K = ctx.assemble(ds, p.theta, 0)
+    alpha = torch.empty(p.n, dtype=torch.float64, device="cuda")
+    r = ctx.solve(K, dev(p.y), alpha, rtol=1e-10)
+    a = host(alpha)
+    ynorm = float(np.linalg.norm(p.y))
+    worst = 0.0
+    for row, (oc, ov) in orows.items():
+        terms = ov * a[oc]
+        res = abs(p.y[row] - terms.sum())
+        bound = 1e-10 * ynorm + 1e-13 * np.abs(terms).sum()
+        worst = max(worst, res / bound)
+    print(f"[cfg3 residual rows] iters {r['cg_iters']} relres {r['relres']:.2e}; worst |r_p| / bound {worst:.3f}")
+    assert r["status"] == 0 and r["relres"] <= 1e-10
+    assert worst <= 1.0
+
+
+def test_config3_predict_sampled(ctx, cfg3):
+    import torch
+    p, ds, _ = cfg3
+    K = ctx.assemble(ds, p.theta, 0)
+    alpha = torch.empty(p.n, dtype=torch.float64, device="cuda")
+    ctx.solve(K, dev(p.y), alpha, rtol=1e-10)
+    a = host(alpha)
+    xs = config5_requests(1, seed=55, m_lo=60, m_hi=60)[0]
+    ref = predict.mean_rows(xs, p.x, p.theta, a)
+    rp, cols, vals = kernel.cross_entries(xs, p.x, p.theta)
+    scale = np.array([np.abs(vals[rp[i]:rp[i + 1]]) @ np.abs(a[cols[rp[i]:rp[i + 1]]])
+                      for i in range(xs.shape[0])]) + 1e-300
+    pred = ctx.predictor(ds, p.theta, alpha)
+    for prec, tol in ((0, 1e-10), (1, 2e-7)):
+        m = host(ctx.predict(pred, dev(xs), precision=prec))
+        err = float(np.max(np.abs(m - ref) / scale))
+        print(f"[cfg3 predict prec={prec}] {xs.shape[0]} points, max scaled error {err:.2e}")
+        assert err <= tol
+
+
+@pytest.fixture(scope="module")
+def cfg2_ref():
+    p = config2()
+    th_local = copy.deepcopy(p.theta)
+    th_local.a = np.zeros_like(np.asarray(th_local.a, np.float64))
+    ip, ci, vv = kernel.sparse(p.x, th_local)
+    A = kernel.to_scipy(ip, ci, vv, p.n)
+    M, F = kernel.features(p.x, p.theta)
+    ref = likelihood.split_woodbury(A, np.where(M, F, 0.0), p.y)
+    return p, ref
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-8), (1, 1e-5)])
+def test_config2_loglik(ctx, cfg2_ref, prec, tol):
+    import torch
+    p, ref = cfg2_ref
+    ds = ctx.dataset(dev(p.x), cell=p.cell)
+    K = ctx.assemble(ds, p.theta, prec)
+    alpha = torch.empty(p.n, dtype=torch.float64, device="cuda")
+    r = ctx.loglik(K, dev(p.y), alpha_out=alpha, seed=20241108)
+    e_quad = rel(r["quad"], ref["quad"])
+    e_alpha = float(np.abs(host(alpha) - ref["alpha"]).max() / np.abs(ref["alpha"]).max())
+    gap = abs(r["logdet"] - ref["logdet"])
+    print(f"[cfg2 prec={prec}] iters {r['cg_iters']} quad rel {e_quad:.2e} alpha rel {e_alpha:.2e}; "
+          f"SLQ logdet {r['logdet']:.10g} exact {ref['logdet']:.10g} |gap| {gap:.3g} = "
+          f"{gap / r['logdet_se']:.2f} SE; loglik(exact logdet) rel "
+          f"{rel(likelihood.assemble(ref['logdet'], r['quad'], p.n), ref['loglik']):.2e}")
+    assert r["status"] == 0
+    assert e_quad <= tol
+    if prec == 0:
+        assert e_alpha <= tol
+    assert gap <= 3 * r["logdet_se"]
