@@ -90,11 +90,14 @@ __device__ __forceinline__ double precond_row_next(const Precond& M, const doubl
 
 // One CG step after the product q = K p.  Every block adds the kRedBlocks
 // partials of p.q (pq_part, same fixed order in every block) and forms alpha =
-// rz / pq; then, one thread per row (the block-Jacobi product is a short chain
-// of dependent gathers, so the full grid keeps enough of them in flight):
+// rz / pq; then, kStepRows rows per thread (the block-Jacobi product is a
+// short chain of dependent gathers, so a nearly full grid keeps enough of them
+// in flight):
 // x += alpha p, rn = r - alpha q, z = M^-1 rn, and per-block partials of rn.z and
 // rn.rn.  Block 0 records pq, alpha, rz_old = rz and the status (non-positive
 // curvature).
+constexpr int kStepRows = 2;
+
 template <typename QT>
 __global__ void __launch_bounds__(kThreads) k_pcg_step(int64_t n, Precond M, CgScalars* __restrict__ s,
                                                        const double* __restrict__ pq_part,
@@ -108,15 +111,18 @@ __global__ void __launch_bounds__(kThreads) k_pcg_step(int64_t n, Precond M, CgS
   const bool ok = pq > 0.0 && isfinite(pq);
   const double alpha = ok ? rz / pq : 0.0;
   double v[2] = {0, 0};
-  const int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x;
-  if (i < n) {
-    x[i] += alpha * p[i];
-    const double ri = r[i] - alpha * static_cast<double>(q[i]);
-    const double zi = precond_row_next<QT>(M, r, q, alpha, ri, i);
-    rn[i] = ri;
-    z[i] = zi;
-    v[0] = ri * zi;
-    v[1] = ri * ri;
+#pragma unroll
+  for (int u = 0; u < kStepRows; ++u) {
+    const int64_t i = (blockIdx.x * static_cast<int64_t>(kStepRows) + u) * kThreads + threadIdx.x;
+    if (i < n) {
+      x[i] += alpha * p[i];
+      const double ri = r[i] - alpha * static_cast<double>(q[i]);
+      const double zi = precond_row_next<QT>(M, r, q, alpha, ri, i);
+      rn[i] = ri;
+      z[i] = zi;
+      v[0] += ri * zi;
+      v[1] += ri * ri;
+    }
   }
   block_sum_store<2>(v, part);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -571,6 +577,7 @@ SolveResult pcg_solve(gp_ctx* c, gp_matrix* m, const double* y, double* x, doubl
   float* q32 = mixed ? static_cast<float*>(workspace(c, 25, sizeof(float) * n)) : nullptr;
   double* part = static_cast<double*>(workspace(c, 26, sizeof(double) * 4 * kRedBlocks));
   const unsigned nbp = grid_for(n, kThreads);
+  const unsigned nbs = grid_for(n, kThreads * kStepRows);
   double* ppart = static_cast<double*>(workspace(c, 28, sizeof(double) * 2 * nbp));
   CgScalars* s = static_cast<CgScalars*>(workspace(c, 27, sizeof(CgScalars)));
   CgScalars* hs = static_cast<CgScalars*>(pinned(c, sizeof(CgScalars)));
@@ -614,7 +621,7 @@ SolveResult pcg_solve(gp_ctx* c, gp_matrix* m, const double* y, double* x, doubl
   // partials of r.z, r.r), the new direction (beta, p); the last step before a
   // host check leaves the direction to after the check
   double* pqp = part;                    // kRedBlocks partials of p.q
-  double* spart = ppart;                 // 2 x nbp partials of r.z, r.r
+  double* spart = ppart;                 // 2 x nbs partials of r.z, r.r
   while (it < max_iter && !converged) {
     const int steps = std::min(kCheckEvery, max_iter - it);
     for (int t = 0; t < steps; ++t) {
@@ -626,18 +633,18 @@ SolveResult pcg_solve(gp_ctx* c, gp_matrix* m, const double* y, double* x, doubl
         ProfScope ps(c, "pcg_vector_ops");
         if (mixed) {
           hipLaunchKernelGGL((k_pq_part<float>), G, B, 0, c->stream, n, p, q32, pqp);
-          hipLaunchKernelGGL((k_pcg_step<float>), dim3(nbp), B, 0, c->stream, n, M, s, pqp, p, q32, x, rc, rnx, z,
+          hipLaunchKernelGGL((k_pcg_step<float>), dim3(nbs), B, 0, c->stream, n, M, s, pqp, p, q32, x, rc, rnx, z,
                              spart);
         } else {
           hipLaunchKernelGGL((k_pq_part<double>), G, B, 0, c->stream, n, p, q, pqp);
-          hipLaunchKernelGGL((k_pcg_step<double>), dim3(nbp), B, 0, c->stream, n, M, s, pqp, p, q, x, rc, rnx, z,
+          hipLaunchKernelGGL((k_pcg_step<double>), dim3(nbs), B, 0, c->stream, n, M, s, pqp, p, q, x, rc, rnx, z,
                              spart);
         }
         std::swap(rc, rnx);
         if (t + 1 < steps)
-          hipLaunchKernelGGL(k_pcg_direction, G, B, 0, c->stream, n, s, spart, static_cast<int>(nbp), z, p, p32);
+          hipLaunchKernelGGL(k_pcg_direction, G, B, 0, c->stream, n, s, spart, static_cast<int>(nbs), z, p, p32);
         else
-          hipLaunchKernelGGL(k_beta_fin, dim3(1), B, 0, c->stream, spart, static_cast<int>(nbp), s, 3);
+          hipLaunchKernelGGL(k_beta_fin, dim3(1), B, 0, c->stream, spart, static_cast<int>(nbs), s, 3);
       }
       check_launch("pcg iteration");
     }

@@ -384,21 +384,34 @@ __global__ void __launch_bounds__(kThreads) k_group_spmv(const int32_t* __restri
     for (int i = 0; i < kPer; ++i) xs[threadIdx.x + i * kThreads] = xr[i];
     __syncthreads();
     if (c0 + kGChunk < nU) load(c0 + kGChunk);   // in flight while this chunk is consumed
-    for (int k0 = lane; k0 < clen; k0 += 4 * kWave) {
-      AT v[4][kRows];
+    // lane takes entries k .. k + 3 (one 16-byte load per row for float32
+    // values; a load may run past the row's group entries into the padded
+    // array, and those entries get weight 0), two such groups in flight
+    for (int k0 = 4 * lane; k0 < clen; k0 += 2 * 4 * kWave) {
+      VT v[2][kRows][4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
+      for (int h = 0; h < 2; ++h) {
+        const int k = k0 + h * 4 * kWave;
 #pragma unroll
         for (int r = 0; r < kRows; ++r) {
-          const int k = k0 + u * kWave;
-          v[u][r] = (has[r] && k < clen) ? static_cast<AT>(val[base[r] + c0 + k]) : AT(0);
+          if (k < clen) {  // a group past the chunk is not loaded (it could run past the array)
+            __builtin_memcpy(v[h][r], val + base[r] + c0 + k, 4 * sizeof(VT));
+          } else {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) v[h][r][u] = VT(0);
+          }
         }
+      }
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int k = k0 + u * kWave;
-        const AT xk = k < clen ? xs[k] : AT(0);
+      for (int h = 0; h < 2; ++h) {
+        const int k = k0 + h * 4 * kWave;
+        AT xk[4];
 #pragma unroll
-        for (int r = 0; r < kRows; ++r) acc[r] += v[u][r] * xk;
+        for (int u = 0; u < 4; ++u) xk[u] = k + u < clen ? xs[min(k + u, kGChunk - 1)] : AT(0);
+#pragma unroll
+        for (int r = 0; r < kRows; ++r)
+#pragma unroll
+          for (int u = 0; u < 4; ++u) acc[r] += (has[r] ? static_cast<AT>(v[h][r][u]) : AT(0)) * xk[u];
       }
     }
   }
