@@ -11,6 +11,7 @@
 // matrix in float64 (Gauss-Jordan without pivoting, one wave per block, lane i
 // holding row i) and applied as a small dense product per row.
 #include <algorithm>
+#include <type_traits>
 
 #include "device.hpp"
 
@@ -56,25 +57,35 @@ __global__ void __launch_bounds__(kThreads) k_block_sizes(int64_t nblk, int64_t 
   bsq[b] = static_cast<int32_t>(sz * sz);
 }
 
-// One wave per block: gather the dense block from the CSR (its columns are a
-// contiguous run of each row, rows being sorted), invert in place.
-template <typename VT>
+// Gauss-Jordan inversion of the diagonal blocks with BS lanes per block (a
+// wave takes 64 / BS blocks): lane i of the group holds row i of the block.
+// One launch per size class takes the blocks with BS/2 < size <= BS (BS = 4
+// also takes sizes 1..2), so the work follows the block's own size.  The
+// dense block is gathered from the CSR (its columns are a contiguous run of
+// each of the row's two ascending runs: group entries, then the rest).
+template <typename VT, int BS>
 __global__ void __launch_bounds__(kThreads) k_block_invert(int64_t nblk, const int32_t* __restrict__ bstart,
                                                            const int64_t* __restrict__ boff,
                                                            const int64_t* __restrict__ rp,
                                                            const int32_t* __restrict__ gskip,
                                                            const int32_t* __restrict__ col, const VT* __restrict__ val,
                                                            double* __restrict__ binv, int* __restrict__ bad) {
-  const int64_t b = (blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x) / kWave;
-  if (b >= nblk) return;
-  const int lane = lane_id();
-  const int32_t bs = bstart[b];
-  const int sz = bstart[b + 1] - bs;
-  double a[kMaxBlock];
+  const int64_t g = (blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x) / BS;
+  const int lane = threadIdx.x % BS;
+  // every lane of a group sees the same block; groups past the end or of
+  // another size class take no part but still join the shuffles (width BS)
+  int32_t bs = 0;
+  int sz = 0;
+  if (g < nblk) {
+    bs = bstart[g];
+    sz = bstart[g + 1] - bs;
+  }
+  const bool mine = g < nblk && sz <= BS && (BS == 4 ? true : sz > BS / 2);
+  if (__ballot(mine) == 0) return;  // uniform: no block of this class in the wave
+  double a[BS];
 #pragma unroll
-  for (int j = 0; j < kMaxBlock; ++j) a[j] = 0.0;
-  if (lane < sz) {
-    // a row holds two runs of ascending columns: its group entries, then the rest
+  for (int j = 0; j < BS; ++j) a[j] = 0.0;
+  if (mine && lane < sz) {
     const int32_t row = bs + lane;
     const int64_t runs[3] = {rp[row], rp[row] + gskip[row], rp[row + 1]};
     for (int rr = 0; rr < 2; ++rr) {
@@ -90,43 +101,48 @@ __global__ void __launch_bounds__(kThreads) k_block_invert(int64_t nblk, const i
         const int32_t cidx = col[j] - bs;
         if (cidx >= sz) break;
 #pragma unroll
-        for (int t = 0; t < kMaxBlock; ++t)
+        for (int t = 0; t < BS; ++t)
           if (t == cidx) a[t] = static_cast<double>(val[j]);
       }
     }
   }
   // in-place Gauss-Jordan inversion (symmetric positive definite: no pivoting)
   bool ok = true;
-  for (int k = 0; k < sz; ++k) {
-    double rk[kMaxBlock];
+  const int steps = mine ? sz : 0;
+  int wsteps = steps;  // pivots needed by any group of the wave
 #pragma unroll
-    for (int j = 0; j < kMaxBlock; ++j) rk[j] = __shfl(a[j], k, kWave);
+  for (int off = kWave / 2; off > 0; off >>= 1) wsteps = max(wsteps, __shfl_xor(wsteps, off, kWave));
+  for (int k = 0; k < wsteps; ++k) {
+    double rk[BS];
+#pragma unroll
+    for (int j = 0; j < BS; ++j) rk[j] = __shfl(a[j], k, BS);
+    if (k >= steps) continue;  // uniform within the group
     double piv = 0.0;
 #pragma unroll
-    for (int j = 0; j < kMaxBlock; ++j)
+    for (int j = 0; j < BS; ++j)
       if (j == k) piv = rk[j];
     if (!(piv > 0.0)) ok = false;
     const double ip = 1.0 / piv;
     // pivot row: a[k][j] /= piv, a[k][k] = 1 / piv
 #pragma unroll
-    for (int j = 0; j < kMaxBlock; ++j) rk[j] = (j == k) ? ip : rk[j] * ip;
+    for (int j = 0; j < BS; ++j) rk[j] = (j == k) ? ip : rk[j] * ip;
     if (lane == k) {
 #pragma unroll
-      for (int j = 0; j < kMaxBlock; ++j) a[j] = rk[j];
+      for (int j = 0; j < BS; ++j) a[j] = rk[j];
     } else if (lane < sz) {
       double f = 0.0;
 #pragma unroll
-      for (int j = 0; j < kMaxBlock; ++j)
+      for (int j = 0; j < BS; ++j)
         if (j == k) f = a[j];
 #pragma unroll
-      for (int j = 0; j < kMaxBlock; ++j) a[j] = (j == k) ? -f * ip : a[j] - f * rk[j];
+      for (int j = 0; j < BS; ++j) a[j] = (j == k) ? -f * ip : a[j] - f * rk[j];
     }
   }
-  if (!ok && lane == 0) atomicOr(bad, 1);
-  if (lane < sz) {
-    double* out = binv + boff[b] + static_cast<int64_t>(lane) * sz;
+  if (mine && !ok && lane == 0) atomicOr(bad, 1);
+  if (mine && lane < sz) {
+    double* out = binv + boff[g] + static_cast<int64_t>(lane) * sz;
 #pragma unroll
-    for (int j = 0; j < kMaxBlock; ++j)
+    for (int j = 0; j < BS; ++j)
       if (j < sz) out[j] = a[j];
   }
 }
@@ -165,14 +181,24 @@ void build_block_jacobi(gp_ctx* c, gp_matrix* m) {
   GPS_HIP(hipMemsetAsync(c->err_flag, 0, sizeof(int), c->stream));
   {
     ProfScope ps(c, "precond_setup");
+    auto go = [&](auto vt) {
+      using VT = decltype(vt);
+      const VT* val = static_cast<const VT*>(m->val);
+      auto one = [&](auto bsz) {
+        constexpr int BS = decltype(bsz)::value;
+        hipLaunchKernelGGL((k_block_invert<VT, BS>), dim3(grid_for(nblk * BS, kThreads)), dim3(kThreads), 0,
+                           c->stream, nblk, m->bstart, m->boff, m->row_ptr, m->gskip, m->col, val, m->binv,
+                           c->err_flag);
+      };
+      one(std::integral_constant<int, 4>{});
+      one(std::integral_constant<int, 8>{});
+      one(std::integral_constant<int, 16>{});
+      one(std::integral_constant<int, 32>{});
+    };
     if (m->prec == GP_MIXED)
-      hipLaunchKernelGGL((k_block_invert<float>), dim3(grid_for(nblk * kWave, kThreads)), dim3(kThreads), 0,
-                         c->stream, nblk, m->bstart, m->boff, m->row_ptr, m->gskip, m->col, static_cast<const float*>(m->val),
-                         m->binv, c->err_flag);
+      go(float{});
     else
-      hipLaunchKernelGGL((k_block_invert<double>), dim3(grid_for(nblk * kWave, kThreads)), dim3(kThreads), 0,
-                         c->stream, nblk, m->bstart, m->boff, m->row_ptr, m->gskip, m->col, static_cast<const double*>(m->val),
-                         m->binv, c->err_flag);
+      go(double{});
     check_launch("block inverse");
   }
   int* herr = static_cast<int*>(pinned(c, sizeof(int)));
