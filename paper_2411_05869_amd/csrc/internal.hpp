@@ -250,9 +250,11 @@ void export_csr(gp_ctx* c, const gp_matrix* m, int64_t* row_ptr, int32_t* col, d
 void spmv_f64(gp_ctx* c, const gp_matrix* m, const double* x, double* y);
 // y = K x entirely in float32 (mixed-precision inner products)
 void spmv_f32(gp_ctx* c, const gp_matrix* m, const float* x, float* y);
-// Y = S K S X for k columns, X/Y n x ld row-major (S = diag(scale) or identity if null)
+// Y = S K S X D for k columns, X/Y n x ld row-major (S = diag(scale) or identity
+// if null; D = diag(colscale), a device array of k values, or identity if null)
 template <typename T>
-void spmm(gp_ctx* c, const gp_matrix* m, int k, int ld, const T* X, T* Y, const T* scale);
+void spmm(gp_ctx* c, const gp_matrix* m, int k, int ld, const T* X, T* Y, const T* scale,
+          const double* colscale = nullptr);
 
 // original <-> binned order for n x k row-major blocks
 template <typename T>

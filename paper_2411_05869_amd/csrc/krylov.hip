@@ -264,13 +264,13 @@ __device__ __forceinline__ double rademacher(uint64_t seed, uint64_t probe, uint
 template <typename T>
 __global__ void __launch_bounds__(kThreads) k_lz_init(int64_t n, int k, int ld, int probe0, uint64_t seed,
                                                       const int32_t* __restrict__ perm, T* __restrict__ V,
-                                                      T* __restrict__ Vprev, double inv_sqrt_n) {
+                                                      T* __restrict__ Vprev) {
   const int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x;
   if (i >= n * ld) return;
   const int64_t p = i / ld;
   const int l = static_cast<int>(i % ld);
   T v = 0;
-  if (l < k) v = static_cast<T>(rademacher(seed, static_cast<uint64_t>(probe0 + l), static_cast<uint64_t>(perm[p])) * inv_sqrt_n);
+  if (l < k) v = static_cast<T>(rademacher(seed, static_cast<uint64_t>(probe0 + l), static_cast<uint64_t>(perm[p])));
   V[i] = v;
   Vprev[i] = 0;
 }
@@ -282,21 +282,35 @@ __global__ void __launch_bounds__(kThreads) k_scale_vec(int64_t n, const double*
   if (i < n) s[i] = static_cast<T>(1.0 / sqrt(diag[i]));
 }
 
-// W[:, l] -= beta_prev[l] * Vprev[:, l]; partial sums of V[:, l] . W[:, l] (float64)
+// The Lanczos vectors are kept unnormalised: v_j = w_{j-1} * inv_cur, with w the
+// residual block of the previous step, so no pass normalises them; the products
+// and the alpha / beta kernels apply the factor where v is read.
+struct LzState {
+  double alpha[32];
+  double beta[32];       // beta of the current step (norm of W)
+  double beta_prev[32];  // used by the next step
+  double inv_cur[32];    // v_j = Vcur * inv_cur (0 for finished probes)
+  double inv_prev[32];   // v_{j-1} = Vprev * inv_prev
+  int active[32];
+  int steps[32];
+};
+
+// W[:, l] -= beta_prev[l] * v_{j-1}[:, l]; partial sums of v_j[:, l] . W[:, l] (float64)
 template <typename T>
-__global__ void __launch_bounds__(kThreads) k_lz_beta_dot(int64_t n, int ld, const double* __restrict__ beta_prev,
+__global__ void __launch_bounds__(kThreads) k_lz_beta_dot(int64_t n, int ld, const LzState* __restrict__ st,
                                                           const T* __restrict__ V, const T* __restrict__ Vprev,
                                                           T* __restrict__ W, double* __restrict__ part) {
   // thread layout: 32 columns x 8 row-lanes per block
   const int l = threadIdx.x & 31;
   const int rl = threadIdx.x >> 5;
-  const T bp = static_cast<T>(beta_prev[l]);
+  const T bp = static_cast<T>(st->beta_prev[l]);
+  const T ic = static_cast<T>(st->inv_cur[l]), ip = static_cast<T>(st->inv_prev[l]);
   double acc = 0;
   for (int64_t p = blockIdx.x * 8ll + rl; p < n; p += static_cast<int64_t>(gridDim.x) * 8) {
     const int64_t i = p * ld + l;
-    const T w = W[i] - bp * Vprev[i];
+    const T w = W[i] - bp * (Vprev[i] * ip);
     W[i] = w;
-    acc += static_cast<double>(V[i]) * static_cast<double>(w);
+    acc += static_cast<double>(V[i] * ic) * static_cast<double>(w);
   }
   __shared__ double sh[8][32];
   sh[rl][l] = acc;
@@ -308,18 +322,19 @@ __global__ void __launch_bounds__(kThreads) k_lz_beta_dot(int64_t n, int ld, con
   }
 }
 
-// W[:, l] -= alpha[l] * V[:, l]; partial sums of |W[:, l]|^2
+// W[:, l] -= alpha[l] * v_j[:, l]; partial sums of |W[:, l]|^2
 template <typename T>
-__global__ void __launch_bounds__(kThreads) k_lz_alpha_norm(int64_t n, int ld, const double* __restrict__ alpha,
+__global__ void __launch_bounds__(kThreads) k_lz_alpha_norm(int64_t n, int ld, const LzState* __restrict__ st,
                                                             const T* __restrict__ V, T* __restrict__ W,
                                                             double* __restrict__ part) {
   const int l = threadIdx.x & 31;
   const int rl = threadIdx.x >> 5;
-  const T a = static_cast<T>(alpha[l]);
+  const T a = static_cast<T>(st->alpha[l]);
+  const T ic = static_cast<T>(st->inv_cur[l]);
   double acc = 0;
   for (int64_t p = blockIdx.x * 8ll + rl; p < n; p += static_cast<int64_t>(gridDim.x) * 8) {
     const int64_t i = p * ld + l;
-    const T w = W[i] - a * V[i];
+    const T w = W[i] - a * (V[i] * ic);
     W[i] = w;
     acc += static_cast<double>(w) * static_cast<double>(w);
   }
@@ -333,13 +348,6 @@ __global__ void __launch_bounds__(kThreads) k_lz_alpha_norm(int64_t n, int ld, c
   }
 }
 
-struct LzState {
-  double alpha[32];
-  double beta[32];       // beta of the current step (norm of W)
-  double beta_prev[32];  // used by the next step
-  int active[32];
-  int steps[32];
-};
 
 // mode 0: alpha; mode 1: beta + breakdown (j = step index, last = final step).
 // 32 columns; each of kFinGroups groups of 32 threads sums the partials b = g,
@@ -383,19 +391,11 @@ __global__ void __launch_bounds__(kFinGroups * 32) k_lz_fin(const double* __rest
       }
       st->beta[l] = st->active[l] ? beta : 0.0;
       st->beta_prev[l] = st->beta[l];
+      // the residual block becomes the next v (unnormalised); finished probes get 0
+      st->inv_prev[l] = st->inv_cur[l];
+      st->inv_cur[l] = st->active[l] ? 1.0 / beta : 0.0;
     }
   }
-}
-
-// Vprev <- W / beta (inactive probes: 0); the caller swaps V and Vprev afterwards
-template <typename T>
-__global__ void __launch_bounds__(kThreads) k_lz_next(int64_t n, int ld, const LzState* __restrict__ st,
-                                                      const T* __restrict__ W, T* __restrict__ Vnext) {
-  const int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x;
-  if (i >= n * ld) return;
-  const int l = static_cast<int>(i % ld);
-  const bool act = l < 32 && st->active[l];
-  Vnext[i] = act ? static_cast<T>(static_cast<double>(W[i]) / st->beta[l]) : T(0);
 }
 
 // Symmetric tridiagonal eigen-decomposition by implicit QR sweeps with
@@ -702,30 +702,35 @@ static LogdetResult slq_impl(gp_ctx* c, const gp_matrix* m, uint64_t seed, int n
   for (int p0 = 0; p0 < n_probes; p0 += 32) {
     const int k = std::min(32, n_probes - p0);
     LzState init{};
-    for (int l = 0; l < 32; ++l) init.active[l] = l < k ? 1 : 0;
+    for (int l = 0; l < 32; ++l) {
+      init.active[l] = l < k ? 1 : 0;
+      init.inv_cur[l] = l < k ? 1.0 / std::sqrt(static_cast<double>(n)) : 0.0;  // v_1 = +-1 / sqrt(n)
+    }
     LzState* hst = static_cast<LzState*>(pinned_for_write(c, sizeof(LzState)));
     *hst = init;
     h2d_async(c, st, hst, sizeof(LzState));
     GPS_HIP(hipMemsetAsync(bad, 0, sizeof(int), c->stream));
     hipLaunchKernelGGL((k_lz_init<T>), dim3(grid_for(n * ld, kThreads)), dim3(kThreads), 0, c->stream, n, k, ld, p0,
-                       seed, m->ds->perm, V, Vp, 1.0 / std::sqrt(static_cast<double>(n)));
+                       seed, m->ds->perm, V, Vp);
     check_launch("lanczos init");
     for (int j = 0; j < n_steps; ++j) {
       const int last = j == n_steps - 1;
-      spmm<T>(c, m, ld, ld, V, W, sc);
+      spmm<T>(c, m, ld, ld, V, W, sc, st->inv_cur);   // W = A v_j
       ProfScope ps(c, "lanczos_vector_ops");
-      hipLaunchKernelGGL((k_lz_beta_dot<T>), dim3(kRedBlocks), dim3(kThreads), 0, c->stream, n, ld, st->beta_prev, V,
-                         Vp, W, part);
+      hipLaunchKernelGGL((k_lz_beta_dot<T>), dim3(kRedBlocks), dim3(kThreads), 0, c->stream, n, ld, st, V, Vp, W,
+                         part);
       hipLaunchKernelGGL(k_lz_fin, dim3(1), dim3(kFinGroups * 32), 0, c->stream, part, kRedBlocks, k, 0, j, last, tol, st,
                          Ta, Tb);
-      hipLaunchKernelGGL((k_lz_alpha_norm<T>), dim3(kRedBlocks), dim3(kThreads), 0, c->stream, n, ld, st->alpha, V, W,
+      hipLaunchKernelGGL((k_lz_alpha_norm<T>), dim3(kRedBlocks), dim3(kThreads), 0, c->stream, n, ld, st, V, W,
                          part);
       hipLaunchKernelGGL(k_lz_fin, dim3(1), dim3(kFinGroups * 32), 0, c->stream, part, kRedBlocks, k, 1, j, last, tol, st,
                          Ta, Tb);
       if (!last) {
-        hipLaunchKernelGGL((k_lz_next<T>), dim3(grid_for(n * ld, kThreads)), dim3(kThreads), 0, c->stream, n, ld, st,
-                           W, Vp);
-        std::swap(V, Vp);   // V <- new vector, Vp <- previous
+        // rotate: the residual block W holds the next (unnormalised) v
+        T* old_prev = Vp;
+        Vp = V;
+        V = W;
+        W = old_prev;
       }
       check_launch("lanczos step");
     }

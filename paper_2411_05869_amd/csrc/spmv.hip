@@ -211,13 +211,23 @@ __global__ void __launch_bounds__(kThreads) k_spmm(int64_t n, unsigned nb_short,
                                                    const int64_t* __restrict__ rp, const int32_t* __restrict__ gskip,
                                                    const int32_t* __restrict__ col,
                                                    const VT* __restrict__ val, const T* __restrict__ X,
-                                                   T* __restrict__ Y, const T* __restrict__ scale) {
+                                                   T* __restrict__ Y, const T* __restrict__ scale,
+                                                   const double* __restrict__ colscale) {
   using V = Vec16<T>;
   const int lane = lane_id();
   const int c = lane & 31;
   const int cl = c < k ? c : k - 1;  // lanes past k re-read column k-1 (in bounds), never store
   const int h = lane >> 5;
   const int w = threadIdx.x / kWave;
+  // column factors, read once: lane c (pair path) or the lane's kCpl columns (VEC)
+  T csc = 1, csv[V::kCpl];
+#pragma unroll
+  for (int t = 0; t < V::kCpl; ++t) csv[t] = 1;
+  if (colscale) {
+    csc = static_cast<T>(colscale[cl]);
+#pragma unroll
+    for (int t = 0; t < V::kCpl; ++t) csv[t] = static_cast<T>(colscale[min((lane % V::kLpe) * V::kCpl + t, k - 1)]);
+  }
   // finishes a row: acc holds the pair-path sum (VEC false) or the lane's
   // slot sums (VEC true); adds the group part already in Y, scales, stores
   auto finish = [&](int64_t row, int32_t gs, T acc, V accv) {
@@ -231,6 +241,7 @@ __global__ void __launch_bounds__(kThreads) k_spmm(int64_t n, unsigned nb_short,
           T a = accv.v[t];
           if (gs) a = yr[t] + a;
           if constexpr (SCALE) a *= scale[row];
+          if (colscale) a *= csv[t];
           yr[t] = a;
         }
       }
@@ -239,6 +250,7 @@ __global__ void __launch_bounds__(kThreads) k_spmm(int64_t n, unsigned nb_short,
       if (h == 0 && c < k) {
         if (gs) acc = Y[row * ld + c] + acc;
         if constexpr (SCALE) acc *= scale[row];
+        if (colscale) acc *= csc;
         Y[row * ld + c] = acc;
       }
     }
@@ -332,6 +344,7 @@ __global__ void __launch_bounds__(kThreads) k_spmm(int64_t n, unsigned nb_short,
       for (int i = 1; i < kThreads / kWave; ++i) t += part[i][c];
       if (gs) t = Y[static_cast<int64_t>(row) * ld + c] + t;
       if constexpr (SCALE) t *= scale[row];
+      if (colscale) t *= csc;
       Y[static_cast<int64_t>(row) * ld + c] = t;
     }
   }
@@ -673,7 +686,7 @@ __global__ void __launch_bounds__(kThreads) k_group_reduce(const int32_t* __rest
 }  // namespace
 
 template <typename T>
-void spmm(gp_ctx* c, const gp_matrix* m, int k, int ld, const T* X, T* Y, const T* scale) {
+void spmm(gp_ctx* c, const gp_matrix* m, int k, int ld, const T* X, T* Y, const T* scale, const double* colscale) {
   if (k > 32 || ld < k) throw Error{GP_EINVAL, "spmm: at most 32 right-hand sides per call"};
   ProfScope ps(c, "spmm");
   // partial blocks of the pieces of multi-piece super-tiles
@@ -697,11 +710,11 @@ void spmm(gp_ctx* c, const gp_matrix* m, int k, int ld, const T* X, T* Y, const 
     if (vec)
       hipLaunchKernelGGL((k_spmm<VT, T, SC, true>), dim3(nb), dim3(kThreads), 0, c->stream, m->n, nb_short,
                          m->n_long, m->long_rows, k, ld, m->row_ptr, m->gskip, m->col, static_cast<const VT*>(m->val),
-                         X, Y, scale);
+                         X, Y, scale, colscale);
     else
       hipLaunchKernelGGL((k_spmm<VT, T, SC, false>), dim3(nb), dim3(kThreads), 0, c->stream, m->n, nb_short,
                          m->n_long, m->long_rows, k, ld, m->row_ptr, m->gskip, m->col, static_cast<const VT*>(m->val),
-                         X, Y, scale);
+                         X, Y, scale, colscale);
   };
   if (m->prec == GP_MIXED) {
     if (scale)
@@ -717,7 +730,8 @@ void spmm(gp_ctx* c, const gp_matrix* m, int k, int ld, const T* X, T* Y, const 
   check_launch("spmm");
 }
 
-template void spmm<float>(gp_ctx*, const gp_matrix*, int, int, const float*, float*, const float*);
-template void spmm<double>(gp_ctx*, const gp_matrix*, int, int, const double*, double*, const double*);
+template void spmm<float>(gp_ctx*, const gp_matrix*, int, int, const float*, float*, const float*, const double*);
+template void spmm<double>(gp_ctx*, const gp_matrix*, int, int, const double*, double*, const double*,
+                           const double*);
 
 }  // namespace gps
