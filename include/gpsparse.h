@@ -184,14 +184,28 @@ typedef enum gp_precond {
   GP_PRECOND_BLOCK_JACOBI = 1   /* dense diagonal blocks over the binning cells (<= 32 points) */
 } gp_precond;
 
+/* Linear solver for alpha = K^-1 y.  MINRES is the method the paper used
+ * (Sec. 3.3; Paige and Saunders): it needs K symmetric only (the
+ * preconditioner positive definite); conjugate gradients are cheaper per step
+ * on a positive-definite K.  AUTO runs conjugate gradients; if they end with
+ * GP_ENOTCONV it continues with MINRES from their last iterate, if they meet
+ * non-positive curvature (GP_ENOTPD) it runs MINRES from zero (either way up to
+ * max_iter more steps).  MINRES forms its products in float64 arithmetic on
+ * the stored values (float32 values for a GP_MIXED matrix). */
+typedef enum gp_solver {
+  GP_SOLVER_CG = 0,
+  GP_SOLVER_MINRES = 1,
+  GP_SOLVER_AUTO = 2
+} gp_solver;
+
 typedef struct gp_solve_opts {
   double rtol;          /* stop when |y - K alpha|_2 <= rtol |y|_2 (default 1e-10) */
-  int32_t max_iter;     /* conjugate-gradient iteration cap (default 10000) */
+  int32_t max_iter;     /* iteration cap of each solver (default 10000) */
   int32_t n_probes;     /* SLQ probes (default 30, at most 64) */
   int32_t n_lanczos;    /* SLQ Lanczos steps (default 50, at most 128) */
   int32_t logdet_mode;  /* gp_logdet_mode */
-  int32_t precond;      /* gp_precond for the conjugate gradients (default block Jacobi) */
-  int32_t pad;
+  int32_t precond;      /* gp_precond for the solver (default block Jacobi) */
+  int32_t solver;       /* gp_solver (default GP_SOLVER_AUTO) */
   uint64_t seed;        /* probe seed */
 } gp_solve_opts;
 
@@ -208,14 +222,17 @@ typedef struct gp_loglik_result {
   int32_t refreshes;    /* float64 true-residual recomputations */
   int32_t lanczos_steps;/* Lanczos steps taken (max over probes; n in exact mode) */
   int32_t status;       /* gp_status of the solve */
+  int32_t minres_iters; /* MINRES iterations (0 when it did not run) */
+  int32_t reserved;
 } gp_loglik_result;
 
 /* gp_loglik: log p(y | theta) for the residual y = z - W beta (y_dev: n
  * float64 in ORIGINAL point order).  Quadratic form by preconditioned
- * conjugate gradients on K (gp_precond); log det by stochastic Lanczos
+ * conjugate gradients and/or MINRES on K (gp_solver, gp_precond); log det by
+ * stochastic Lanczos
  * quadrature on the
  * Jacobi-scaled matrix (or exact Lanczos, see gp_logdet_mode).  With a
- * GP_MIXED matrix the products run in float32 and the residual
+ * GP_MIXED matrix the conjugate-gradient products run in float32 and the residual
  * recomputation, Lanczos coefficients, quadrature and quadratic form in
  * float64.  alpha_dev (n float64, original order, may be NULL) receives
  * K^-1 y.  opts may be NULL (defaults).

@@ -18,6 +18,9 @@ from ._lib import (  # noqa: F401
     LOGDET_SLQ,
     PRECOND_BLOCK_JACOBI,
     PRECOND_JACOBI,
+    SOLVER_AUTO,
+    SOLVER_CG,
+    SOLVER_MINRES,
     Context,
     Dataset,
     GPError,

@@ -14,6 +14,7 @@ _lib = None
 FP64, MIXED = 0, 1
 LOGDET_SLQ, LOGDET_EXACT, LOGDET_NONE = 0, 1, 2
 PRECOND_JACOBI, PRECOND_BLOCK_JACOBI = 0, 1
+SOLVER_CG, SOLVER_MINRES, SOLVER_AUTO = 0, 1, 2
 _STATUS = {0: "GP_OK", 1: "GP_EINVAL", 2: "GP_ENOMEM", 3: "GP_ENOTCONV", 4: "GP_ENOTPD", 5: "GP_EDEVICE"}
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
@@ -37,7 +38,7 @@ class CTheta(C.Structure):
 class CSolveOpts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("max_iter", C.c_int32), ("n_probes", C.c_int32),
                 ("n_lanczos", C.c_int32), ("logdet_mode", C.c_int32), ("precond", C.c_int32),
-                ("pad", C.c_int32), ("seed", C.c_uint64)]
+                ("solver", C.c_int32), ("seed", C.c_uint64)]
 
 
 class CProfileEntry(C.Structure):
@@ -47,7 +48,8 @@ class CProfileEntry(C.Structure):
 class CLoglikResult(C.Structure):
     _fields_ = [("loglik", C.c_double), ("logdet", C.c_double), ("quad", C.c_double),
                 ("logdet_se", C.c_double), ("relres", C.c_double), ("cg_iters", C.c_int32),
-                ("refreshes", C.c_int32), ("lanczos_steps", C.c_int32), ("status", C.c_int32)]
+                ("refreshes", C.c_int32), ("lanczos_steps", C.c_int32), ("status", C.c_int32),
+                ("minres_iters", C.c_int32), ("reserved", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -161,6 +161,8 @@ gp_solve_opts fill_opts(const gp_solve_opts* o) {
   GPS_REQUIRE(r.logdet_mode >= 0 && r.logdet_mode <= 2, GP_EINVAL, "logdet_mode must be 0, 1 or 2");
   GPS_REQUIRE(r.precond == GP_PRECOND_JACOBI || r.precond == GP_PRECOND_BLOCK_JACOBI, GP_EINVAL,
               "precond must be GP_PRECOND_JACOBI or GP_PRECOND_BLOCK_JACOBI");
+  GPS_REQUIRE(r.solver >= GP_SOLVER_CG && r.solver <= GP_SOLVER_AUTO, GP_EINVAL,
+              "solver must be GP_SOLVER_CG, GP_SOLVER_MINRES or GP_SOLVER_AUTO");
   return r;
 }
 
@@ -176,7 +178,7 @@ void gp_solve_opts_default(gp_solve_opts* o) {
   o->n_lanczos = 50;
   o->logdet_mode = GP_LOGDET_SLQ;
   o->precond = GP_PRECOND_BLOCK_JACOBI;
-  o->pad = 0;
+  o->solver = GP_SOLVER_AUTO;
   o->seed = 0x5eed;
 }
 
@@ -398,11 +400,22 @@ static gp_status loglik_common(gp_ctx* c, const gp_matrix* m, const double* y, c
     double* xb = static_cast<double*>(gps::workspace(c, 45, sizeof(double) * n));
     gps::permute_to_binned<double>(c, m->ds, 1, y, yb);
     // the preconditioner is cached in the matrix object on first use
-    const gps::SolveResult sr = gps::pcg_solve(c, const_cast<gp_matrix*>(m), yb, xb, o.rtol, o.max_iter, o.precond);
+    gp_matrix* mm = const_cast<gp_matrix*>(m);
+    gps::SolveResult sr;
+    if (o.solver != GP_SOLVER_MINRES) {
+      sr = gps::pcg_solve(c, mm, yb, xb, o.rtol, o.max_iter, o.precond);
+      out->cg_iters = sr.iters;
+      out->refreshes = sr.refreshes;
+    }
+    if (o.solver == GP_SOLVER_MINRES || (o.solver == GP_SOLVER_AUTO && sr.st != GP_OK)) {
+      // after GP_ENOTCONV from the conjugate gradients' last iterate; after
+      // non-positive curvature (their iterate is then no useful start) from zero
+      const bool warm = o.solver == GP_SOLVER_AUTO && sr.st == GP_ENOTCONV;
+      sr = gps::minres_solve(c, mm, yb, xb, warm, o.rtol, o.max_iter, o.precond);
+      out->minres_iters = sr.iters;
+    }
     out->quad = sr.quad;
     out->relres = sr.relres;
-    out->cg_iters = sr.iters;
-    out->refreshes = sr.refreshes;
     GPS_REQUIRE(std::isfinite(sr.quad), GP_EINVAL, "y holds non-finite values");
     solve_status = sr.st;
     if (alpha) gps::permute_to_orig<double>(c, m->ds, 1, xb, alpha);
@@ -424,7 +437,7 @@ static gp_status loglik_common(gp_ctx* c, const gp_matrix* m, const double* y, c
   }
   out->status = solve_status;
   if (solve_status != GP_OK) {
-    c->err = solve_status == GP_ENOTCONV ? "conjugate gradients did not reach rtol within max_iter"
+    c->err = solve_status == GP_ENOTCONV ? "the solver did not reach rtol within max_iter"
                                          : "non-positive curvature: matrix not positive definite";
   }
   return solve_status;

@@ -272,6 +272,10 @@ struct SolveResult {
 };
 // alpha = K^-1 y (binned order); preconditioned CG, float64 or float32-product form.
 SolveResult pcg_solve(gp_ctx* c, gp_matrix* m, const double* yb, double* xb, double rtol, int max_iter, int precond);
+// alpha = K^-1 y by preconditioned MINRES (float64 products on the stored
+// values); warm: start from the x passed in, else from 0.
+SolveResult minres_solve(gp_ctx* c, gp_matrix* m, const double* yb, double* xb, bool warm, double rtol, int max_iter,
+                         int precond);
 void build_block_jacobi(gp_ctx* c, gp_matrix* m);
 void free_block_jacobi(gp_ctx* c, gp_matrix* m);
 

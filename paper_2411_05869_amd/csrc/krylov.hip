@@ -679,6 +679,250 @@ SolveResult pcg_solve(gp_ctx* c, gp_matrix* m, const double* y, double* x, doubl
   return res;
 }
 
+namespace {
+
+// ---------------------------------------------------------------- MINRES
+// Preconditioned MINRES (Paige and Saunders; the paper's solver, Sec. 3.3):
+// Lanczos in the M-inner product, Givens rotations on its tridiagonal matrix,
+// three-term search directions.  Products in float64 arithmetic on the stored
+// values; all vectors and scalars float64.  Scalars stay on the device; a
+// one-thread kernel applies each rotation.
+struct MrScalars {
+  double beta, oldb, alfa, dbar, epsln, phibar, cs, sn, phi, gamma, delta, oldeps;
+  double beta1, rr;
+  int it, status;
+};
+
+// beta1 = sqrt(r . z) (start); the rotation state starts as in the reference method
+__global__ void k_mr_start(const double* __restrict__ part, int nb, MrScalars* __restrict__ s) {
+  double r[2];
+  reduce_partials<2>(part, nb, r);
+  if (threadIdx.x == 0) {
+    const double b = sqrt(r[0]);
+    s->beta1 = b;
+    s->beta = b;
+    s->oldb = 0.0;
+    s->dbar = 0.0;
+    s->epsln = 0.0;
+    s->phibar = b;
+    s->cs = -1.0;
+    s->sn = 0.0;
+    s->it = 0;
+    s->status = (isfinite(b) && r[0] >= 0.0) ? 0 : 1;
+  }
+}
+
+// v = z / beta (first vector)
+__global__ void __launch_bounds__(kThreads) k_mr_first_v(int64_t n, const MrScalars* __restrict__ s,
+                                                         const double* __restrict__ z, double* __restrict__ v) {
+  const double sc = 1.0 / s->beta;
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * kThreads)
+    v[i] = sc * z[i];
+}
+
+// partials of v . y1 with y1 = q - (beta / oldb) r1 (the second term from the
+// second step on)
+__global__ void __launch_bounds__(kThreads) k_mr_alpha(int64_t n, const MrScalars* __restrict__ s,
+                                                       const double* __restrict__ q, const double* __restrict__ r1,
+                                                       const double* __restrict__ v, double* __restrict__ part) {
+  const double f = s->it >= 1 ? s->beta / s->oldb : 0.0;
+  double acc[1] = {0.0};
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * kThreads) {
+    const double y1 = s->it >= 1 ? q[i] - f * r1[i] : q[i];
+    acc[0] += v[i] * y1;
+  }
+  block_sum_store<1>(acc, part);
+}
+
+__global__ void k_mr_alpha_fin(const double* __restrict__ part, int nb, MrScalars* __restrict__ s) {
+  double r[1];
+  reduce_partials<1>(part, nb, r);
+  if (threadIdx.x == 0) s->alfa = r[0];
+}
+
+// new Lanczos vector rn = (q - (beta/oldb) r1) - (alfa/beta) r2 and z = M^-1 rn;
+// partials of rn . z.  Entries of rn needed by the block product are formed
+// the same way from q, r1, r2, so no thread waits for another.
+__device__ __forceinline__ double mr_next(const MrScalars& s, double f, const double* q, const double* r1,
+                                          const double* r2, int64_t j) {
+  const double y1 = s.it >= 1 ? q[j] - f * r1[j] : q[j];
+  return y1 - (s.alfa / s.beta) * r2[j];
+}
+
+__global__ void __launch_bounds__(kThreads) k_mr_lanczos(int64_t n, Precond M, const MrScalars* __restrict__ sp,
+                                                         const double* __restrict__ q, const double* __restrict__ r1,
+                                                         const double* __restrict__ r2, double* __restrict__ rn,
+                                                         double* __restrict__ z, double* __restrict__ part) {
+  const MrScalars s = *sp;
+  const double f = s.it >= 1 ? s.beta / s.oldb : 0.0;
+  double v[1] = {0.0};
+  const int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x;
+  if (i < n) {
+    const double ri = mr_next(s, f, q, r1, r2, i);
+    double zi;
+    if (!M.binv) {
+      zi = ri / M.diag[i];
+    } else {
+      const int32_t b = M.rowblk[i];
+      const int32_t bs = M.bstart[b];
+      const int sz = M.bstart[b + 1] - bs;
+      const double* row = M.binv + M.boff[b] + static_cast<int64_t>(i - bs) * sz;
+      zi = 0.0;
+      for (int j = 0; j < sz; ++j) zi += row[j] * mr_next(s, f, q, r1, r2, bs + j);
+    }
+    rn[i] = ri;
+    z[i] = zi;
+    v[0] = ri * zi;
+  }
+  block_sum_store<1>(v, part);
+}
+
+// beta of the new vector and one Givens rotation of the tridiagonal matrix
+__global__ void k_mr_rotate(const double* __restrict__ part, int nb, MrScalars* __restrict__ s) {
+  double r[1];
+  reduce_partials<1>(part, nb, r);
+  if (threadIdx.x == 0) {
+    if (!(r[0] >= 0.0) || !isfinite(r[0])) s->status = 1;
+    s->oldb = s->beta;
+    s->beta = sqrt(fmax(r[0], 0.0));
+    s->oldeps = s->epsln;
+    s->delta = s->cs * s->dbar + s->sn * s->alfa;
+    const double gbar = s->sn * s->dbar - s->cs * s->alfa;
+    s->epsln = s->sn * s->beta;
+    s->dbar = -s->cs * s->beta;
+    const double gamma = fmax(hypot(gbar, s->beta), 2.2250738585072014e-308);
+    s->gamma = gamma;
+    s->cs = gbar / gamma;
+    s->sn = s->beta / gamma;
+    s->phi = s->cs * s->phibar;
+    s->phibar = s->sn * s->phibar;
+    s->it += 1;
+  }
+}
+
+// w = (v - oldeps w1 - delta w2) / gamma into the buffer of w1 (oldest);
+// x += phi w; next v = z / beta
+__global__ void __launch_bounds__(kThreads) k_mr_update(int64_t n, const MrScalars* __restrict__ s,
+                                                        double* __restrict__ w1, const double* __restrict__ w2,
+                                                        double* __restrict__ x, double* __restrict__ v,
+                                                        const double* __restrict__ z) {
+  const double oldeps = s->oldeps, delta = s->delta, gamma = s->gamma, phi = s->phi;
+  const double sc = s->beta > 0.0 ? 1.0 / s->beta : 0.0;
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * kThreads) {
+    const double w = (v[i] - oldeps * w1[i] - delta * w2[i]) / gamma;
+    w1[i] = w;
+    x[i] += phi * w;
+    v[i] = sc * z[i];
+  }
+}
+
+}  // namespace
+
+SolveResult minres_solve(gp_ctx* c, gp_matrix* m, const double* y, double* x, bool warm, double rtol, int max_iter,
+                         int precond) {
+  const int64_t n = m->n;
+  if (precond == GP_PRECOND_BLOCK_JACOBI) build_block_jacobi(c, m);
+  Precond M{m->diag, nullptr, nullptr, nullptr, nullptr};
+  if (precond == GP_PRECOND_BLOCK_JACOBI) {
+    M.rowblk = m->rowblk;
+    M.bstart = m->bstart;
+    M.boff = m->boff;
+    M.binv = m->binv;
+  }
+  double* buf[8];
+  for (int k = 0; k < 8; ++k) buf[k] = static_cast<double*>(workspace(c, 80 + k, sizeof(double) * n));
+  double *r1 = buf[0], *r2 = buf[1], *rn = buf[2], *z = buf[3], *v = buf[4], *q = buf[5];
+  double *wa = buf[6], *wb = buf[7];  // w1 (oldest), w2 (newest)
+  const unsigned nbp = grid_for(n, kThreads);
+  double* part = static_cast<double*>(workspace(c, 88, sizeof(double) * 2 * std::max<unsigned>(nbp, kRedBlocks)));
+  MrScalars* s = static_cast<MrScalars*>(workspace(c, 89, sizeof(MrScalars)));
+  MrScalars* hs = static_cast<MrScalars*>(pinned(c, sizeof(MrScalars)));
+  const dim3 G(kRedBlocks), B(kThreads);
+  auto read = [&]() {
+    GPS_HIP(hipMemcpyAsync(hs, s, sizeof(MrScalars), hipMemcpyDeviceToHost, c->stream));
+    sync(c);
+    return *hs;
+  };
+  // |y|, |y|_{M^-1}: the true-residual check starts once the estimate is
+  // below 100 rtol |y|_{M^-1} (the two norms differ by at most sqrt(cond M))
+  const double ynorm = std::sqrt(dot_f64(c, y, y, n));
+  SolveResult res;
+  GPS_REQUIRE(std::isfinite(ynorm), GP_EINVAL, "y holds non-finite values");
+  if (ynorm == 0.0) {
+    GPS_HIP(hipMemsetAsync(x, 0, sizeof(double) * n, c->stream));
+    return res;
+  }
+  auto residual_into = [&](double* r) {  // r = y - K x
+    spmv_f64(c, m, x, q);
+    hipLaunchKernelGGL(k_true_resid, G, B, 0, c->stream, n, y, q, r);
+  };
+  auto apply_m = [&](const double* r) {  // z = M^-1 r, partials of (r.z, r.r)
+    hipLaunchKernelGGL(k_precond, dim3(nbp), B, 0, c->stream, n, M, r, z, part);
+  };
+  // |y|_{M^-1}
+  apply_m(y);
+  hipLaunchKernelGGL(k_mr_start, dim3(1), B, 0, c->stream, part, static_cast<int>(nbp), s);
+  const double ym = read().beta1;
+  if (warm) {
+    residual_into(r1);
+  } else {
+    GPS_HIP(hipMemsetAsync(x, 0, sizeof(double) * n, c->stream));
+    GPS_HIP(hipMemcpyAsync(r1, y, sizeof(double) * n, hipMemcpyDeviceToDevice, c->stream));
+  }
+  GPS_HIP(hipMemcpyAsync(r2, r1, sizeof(double) * n, hipMemcpyDeviceToDevice, c->stream));
+  GPS_HIP(hipMemsetAsync(wa, 0, sizeof(double) * n, c->stream));
+  GPS_HIP(hipMemsetAsync(wb, 0, sizeof(double) * n, c->stream));
+  apply_m(r1);
+  hipLaunchKernelGGL(k_mr_start, dim3(1), B, 0, c->stream, part, static_cast<int>(nbp), s);
+  hipLaunchKernelGGL(k_mr_first_v, G, B, 0, c->stream, n, s, z, v);
+  check_launch("minres start");
+  MrScalars sc = read();
+  double true_rel = std::sqrt(dot_f64(c, r1, r1, n)) / ynorm;
+  int it = 0;
+  bool converged = true_rel <= rtol;
+  if (!(sc.beta1 > 0.0)) converged = true;
+  while (!converged && it < max_iter && sc.status == 0) {
+    const int steps = std::min(kCheckEvery, max_iter - it);
+    for (int t = 0; t < steps; ++t) {
+      spmv_f64(c, m, v, q);
+      ProfScope ps(c, "minres_vector_ops");
+      hipLaunchKernelGGL(k_mr_alpha, G, B, 0, c->stream, n, s, q, r1, v, part);
+      hipLaunchKernelGGL(k_mr_alpha_fin, dim3(1), B, 0, c->stream, part, kRedBlocks, s);
+      hipLaunchKernelGGL(k_mr_lanczos, dim3(nbp), B, 0, c->stream, n, M, s, q, r1, r2, rn, z, part);
+      hipLaunchKernelGGL(k_mr_rotate, dim3(1), B, 0, c->stream, part, static_cast<int>(nbp), s);
+      hipLaunchKernelGGL(k_mr_update, G, B, 0, c->stream, n, s, wa, wb, x, v, z);
+      check_launch("minres step");
+      // rotate: r1 <- r2, r2 <- rn; w1 <- w2, w2 <- the new w (written over w1)
+      double* t1 = r1;
+      r1 = r2;
+      r2 = rn;
+      rn = t1;
+      std::swap(wa, wb);
+    }
+    it += steps;
+    sc = read();
+    if (sc.status != 0) break;
+    if (sc.phibar <= 100.0 * rtol * ym || sc.beta == 0.0) {
+      residual_into(rn);
+      true_rel = std::sqrt(dot_f64(c, rn, rn, n)) / ynorm;
+      if (true_rel <= rtol || sc.beta == 0.0) converged = true;
+    }
+  }
+  if (!converged && sc.status == 0) {
+    residual_into(rn);
+    true_rel = std::sqrt(dot_f64(c, rn, rn, n)) / ynorm;
+    converged = true_rel <= rtol;
+  }
+  res.iters = it;
+  res.relres = true_rel;
+  res.st = sc.status != 0 ? GP_ENOTPD : (converged ? GP_OK : GP_ENOTCONV);
+  res.quad = dot_f64(c, y, x, n);
+  return res;
+}
+
 template <typename T>
 static LogdetResult slq_impl(gp_ctx* c, const gp_matrix* m, uint64_t seed, int n_probes, int n_steps, double tol) {
   const int64_t n = m->n;
