@@ -11,6 +11,9 @@ defines, in float64 throughout:
                    the entries of K = C_sparse + sigma^2 I (Sec. 2.1, Eq.
                    bumpFcn, sumOfBumps, C_sparse, compSupp; Sec. 3.1, Eq. Zcov),
                    as a dense brute-force matrix or a KD-tree-built sparse one.
+* ``core``       - the core kernel C_core of C_y = C_core x C_sparse (Eq.
+                   sparseCov): stationary Matern and the parametric
+                   nonstationary kernel of Eq. PScov (Appendix B).
 * ``likelihood`` - the Gaussian log-likelihood (Sec. 3.1 Eq. Zmarg, Sec. 3.3)
                    by dense Cholesky, by sparse LU, and by the split
                    K = A + F F^T with the determinant lemma / Woodbury identity.

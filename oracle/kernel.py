@@ -1,4 +1,4 @@
-"""Oracle: the covariance C_z = C_sparse + sigma^2 I of the paper, in float64.
+"""Oracle: the covariance C_z = C_core C_sparse + sigma^2 I of the paper, in float64.
 
 Test infrastructure only (see the package docstring): never imported by the
 HIP product path.
@@ -11,9 +11,9 @@ Definitions followed (Sec. 2.1 and 3.1):
 * Wendland part (Eq. compSupp): f0 = (1-u)^8 (35 u^3 + 25 u^2 + 8 u + 1)
   for u = |x - x'| / r0 < 1, else 0;
 * sparse kernel (Eq. C_sparse): C_sparse = s0 f0 + sum_i f_i(x) f_i(x');
-* with a unit core kernel (Sec. 2.2, special case (1) removes only the
-  bumps; here C_core = 1 is used throughout) and the nugget of Eq. Zcov on
-  the index diagonal: K_pq = C_sparse(x_p, x_q) + sigma^2 [p = q].
+* times the core kernel (Eq. sparseCov; ``oracle.core``, C_core = 1 unless
+  the hyper-parameters carry one) and the nugget of Eq. Zcov on the index
+  diagonal: K_pq = C_core(x_p, x_q) C_sparse(x_p, x_q) + sigma^2 [p = q].
 
 Readings where the paper is silent or ambiguous:
 
@@ -37,6 +37,8 @@ from __future__ import annotations
 
 import numpy as np
 from scipy.spatial import cKDTree
+
+from . import core
 
 
 def _theta_arrays(th):
@@ -107,10 +109,12 @@ def local_sq(xp, xq, th):
 
 
 def entries(xp, xq, Mp, Mq, Fp, Fq, same, th):
-    """K_pq for aligned arrays of pairs (Eq. C_sparse + Eq. Zcov).
+    """K_pq for aligned arrays of pairs (Eq. sparseCov, Eq. C_sparse, Eq. Zcov).
 
-    K = s0 f0(u) [u0^2 < 1] + sum_i [M_i(p) and M_i(q)] f_i(p) f_i(q) + sigma^2 [p = q],
-    the group sum taken in increasing i.
+    K = C_core(p, q) (s0 f0(u) [u0^2 < 1] + sum_i [M_i(p) and M_i(q)] f_i(p) f_i(q))
+        + sigma^2 [p = q],
+    the group sum taken in increasing i; C_core = 1 unless th.core is set
+    (``oracle.core``).
     """
     u2 = local_sq(xp, xq, th)
     L = u2 < 1.0
@@ -120,6 +124,9 @@ def entries(xp, xq, Mp, Mq, Fp, Fq, same, th):
     for i in range(n1):
         both = Mp[..., i] & Mq[..., i]
         val = val + np.where(both, Fp[..., i] * Fq[..., i], 0.0)
+    cr = getattr(th, "core", None)
+    if cr is not None and cr.kind != core.NONE:
+        val = core.value(xp, xq, cr) * val
     val = val + np.where(same, float(th.nugget), 0.0)
     return val
 

@@ -8,7 +8,7 @@ residual y = z - W beta passed in and a zero prior mean at the test points
 
     m(x*) = sum_q C_y(x*, x_q) alpha_q,   alpha = C_z^{-1} y,
 
-where C_y is C_sparse with a unit core kernel and carries no nugget (the
+where C_y = C_core C_sparse (Eq. sparseCov) carries no nugget (the
 nugget belongs to the observations z, Eq. Zcov).  At the training inputs
 m(X) = (C_z - sigma^2 I) alpha = y - sigma^2 alpha.
 """

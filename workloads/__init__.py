@@ -32,6 +32,38 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 
 
 @dataclasses.dataclass
+class Core:
+    """Core kernel C_core of C_y = C_core x C_sparse (Eq. sparseCov).
+
+    kind: 0 none (C_core = 1), 1 stationary Matern sigma0^2 M_nu(|(x-x')/ell|),
+    2 parametric nonstationary (Eq. PScov) with log sigma(x) = log sigma0 +
+    sum_m s_m(x) phi_sigma[m], log Sigma(x) = log Sigma0 + sum_m s_m(x)
+    phi_Sigma[m] and Gaussian radial basis functions s_m with centres
+    ``centers`` (M, d) and per-coordinate widths ``width`` (d,).
+    nu2 = 2 nu in {1, 3, 5}, or 0 for nu = infinity.
+    """
+
+    kind: int
+    nu2: int = 5
+    sigma0: float = 1.0
+    ell: np.ndarray = dataclasses.field(default_factory=lambda: np.ones(3))
+    Sigma0: float = 1.0
+    centers: np.ndarray = dataclasses.field(default_factory=lambda: np.zeros((0, 1)))
+    width: np.ndarray = dataclasses.field(default_factory=lambda: np.ones(3))
+    phi_sigma: np.ndarray = dataclasses.field(default_factory=lambda: np.zeros(0))
+    phi_Sigma: np.ndarray = dataclasses.field(default_factory=lambda: np.zeros(0))
+
+    @property
+    def n_basis(self) -> int:
+        return int(np.asarray(self.phi_sigma).shape[0])
+
+    def copy(self) -> "Core":
+        return Core(int(self.kind), int(self.nu2), float(self.sigma0), np.array(self.ell, np.float64),
+                    float(self.Sigma0), np.array(self.centers, np.float64), np.array(self.width, np.float64),
+                    np.array(self.phi_sigma, np.float64), np.array(self.phi_Sigma, np.float64))
+
+
+@dataclasses.dataclass
 class Theta:
     """Hyper-parameters of C_sparse plus the nugget (Sec. 2.1, Eq. C_sparse).
 
@@ -49,6 +81,7 @@ class Theta:
     b: np.ndarray
     nugget: float
     wendland_variant: int = 0
+    core: "Core | None" = None
 
     @property
     def d(self) -> int:
@@ -65,7 +98,7 @@ class Theta:
     def copy(self) -> "Theta":
         return Theta(float(self.s0), self.r0.copy(), self.h.copy(), self.r.copy(),
                      self.a.copy(), self.b.copy(), float(self.nugget),
-                     int(self.wendland_variant))
+                     int(self.wendland_variant), None if self.core is None else self.core.copy())
 
 
 @dataclasses.dataclass
@@ -156,6 +189,30 @@ def gmm_problem(n: int, seed: int, r0: float, bump_radius: float, *, n1=4, n2=4,
     r0v = np.array([r0, r0])
     th = Theta(1.0, r0v, h, r, a, b, nugget, 0)
     return Problem(name, x, th, y=y, cell=r0v * 1.15)
+
+
+def random_core(kind: int, d: int, seed: int, *, nu2: int = 5, n_basis: int = 4, ell: float = 0.08,
+                sigma0: float = 1.3, Sigma0: float = 1.0, width: float = 0.35, phi_sd: float = 0.6) -> Core:
+    """A core kernel with seeded parameters: basis centres U[0,1]^d, coefficients
+    N(0, phi_sd^2) (so sigma(x) and Sigma(x) vary by a factor of a few over the unit
+    cube), per-coordinate scales ell and widths ``width``."""
+    rng = np.random.default_rng(seed)
+    centers = rng.uniform(0.0, 1.0, size=(n_basis, d))
+    phi_s = rng.normal(0.0, phi_sd, size=n_basis)
+    phi_S = rng.normal(0.0, phi_sd, size=n_basis)
+    ellv = np.ones(3)
+    ellv[:d] = ell
+    wv = np.ones(3)
+    wv[:d] = width
+    return Core(int(kind), int(nu2), float(sigma0), ellv, float(Sigma0), centers, wv, phi_s, phi_S)
+
+
+def core_problem(kind: int, d: int, n: int = 1500, seed: int = 11, nu2: int = 5, **kw) -> Problem:
+    """A uniform problem (2 x 2 bumps) whose kernel carries a core kernel."""
+    p = uniform_problem(n, d, seed, r0=0.09 if d == 1 else (0.07 if d == 2 else 0.15), n1=2, n2=2,
+                        bump_radius=0.25, name=f"core{kind}-d{d}-n{n}")
+    p.theta.core = random_core(kind, d, seed + 1000, nu2=nu2, **kw)
+    return p
 
 
 def config2() -> Problem:
