@@ -133,7 +133,45 @@ GP_API gp_status gp_dataset_permutation(gp_ctx* ctx, const gp_dataset* ds, int32
  *   b      n1*n2 shapes (> 0)
  * Support tests use the float64 expression sum_k ((x_k - c_k) * (1 / r_k))^2
  * < 1 evaluated left to right without fused multiply-add.
- * Limits: 1 <= n1 <= 64, n1*n2 <= 4096, s0 > 0, nugget >= 0. */
+ * Limits: 1 <= n1 <= 64, n1*n2 <= 4096, s0 > 0, nugget >= 0.
+ * core (optional) multiplies C_sparse, see gp_core. */
+/* Core kernel C_core of C_y = C_core x C_sparse (Sec. 2, Eq. sparseCov; the
+ * nugget is added after the product).  The core is strictly positive, so it
+ * never changes the sparsity pattern; it only scales the stored values.
+ *   GP_CORE_MATERN:   sigma0^2 M_nu(|(x - x') / ell|)             (Sec. 2.3)
+ *   GP_CORE_PACIOREK: sigma(x) sigma(x') (Sigma(x) Sigma(x'))^(d/4)
+ *                     / ((Sigma(x) + Sigma(x')) / 2)^(d/2) M_nu(sqrt(Q)),
+ *                     Q = |(x - x') / ell|^2 / ((Sigma(x) + Sigma(x')) / 2)
+ *                     (Appendix B, Eq. PScov, its denominator read as
+ *                     Sigma(x) + Sigma(x')), with log-linear fields
+ *                     log sigma(x) = log sigma0 + sum_m s_m(x) phi_sigma[m],
+ *                     log Sigma(x) = log Sigma0 + sum_m s_m(x) phi_Sigma[m],
+ *                     s_m(x) = exp(-|(x - centers[m]) / width|^2 / 2).
+ * M_nu is the Matern correlation 2^(1-nu)/Gamma(nu) (sqrt(2 nu) t)^nu
+ * K_nu(sqrt(2 nu) t) at nu = nu2 / 2 in {1/2, 3/2, 5/2}, or exp(-t^2/2) for
+ * nu2 = 0 (the limit nu -> infinity).  Host memory, copied by each call.
+ * Limits: sigma0, ell[k], Sigma0, width[k] finite and > 0; 0 <= n_basis <= 16;
+ * centers (n_basis x d), phi_sigma, phi_Sigma (n_basis) finite. */
+typedef enum gp_core_kind {
+  GP_CORE_NONE = 0,      /* C_core = 1 */
+  GP_CORE_MATERN = 1,
+  GP_CORE_PACIOREK = 2
+} gp_core_kind;
+
+typedef struct gp_core {
+  int32_t kind;            /* gp_core_kind */
+  int32_t nu2;             /* 2 nu: 1, 3 or 5; 0 for nu = infinity */
+  double sigma0;
+  double ell[3];
+  double Sigma0;           /* PACIOREK only */
+  int32_t n_basis;         /* PACIOREK only */
+  int32_t reserved;
+  const double* centers;   /* n_basis x d, row-major */
+  double width[3];
+  const double* phi_sigma; /* n_basis */
+  const double* phi_Sigma; /* n_basis */
+} gp_core;
+
 typedef struct gp_theta {
   int32_t d;
   int32_t n1;
@@ -146,6 +184,7 @@ typedef struct gp_theta {
   const double* a;
   const double* b;
   double nugget;
+  const gp_core* core;       /* NULL: C_core = 1 */
 } gp_theta;
 
 /* ------------------------------------------------------------------ matrix

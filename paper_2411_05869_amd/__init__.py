@@ -11,6 +11,9 @@ nothing here falls back to a CPU implementation.
 from __future__ import annotations
 
 from ._lib import (  # noqa: F401
+    CORE_MATERN,
+    CORE_NONE,
+    CORE_PACIOREK,
     FP64,
     MIXED,
     LOGDET_EXACT,

@@ -15,6 +15,7 @@ FP64, MIXED = 0, 1
 LOGDET_SLQ, LOGDET_EXACT, LOGDET_NONE = 0, 1, 2
 PRECOND_JACOBI, PRECOND_BLOCK_JACOBI = 0, 1
 SOLVER_CG, SOLVER_MINRES, SOLVER_AUTO = 0, 1, 2
+CORE_NONE, CORE_MATERN, CORE_PACIOREK = 0, 1, 2
 _STATUS = {0: "GP_OK", 1: "GP_EINVAL", 2: "GP_ENOMEM", 3: "GP_ENOTCONV", 4: "GP_ENOTPD", 5: "GP_EDEVICE"}
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
@@ -28,11 +29,18 @@ class GPError(RuntimeError):
         self.name = _STATUS.get(status, str(status))
 
 
+class CCore(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("nu2", C.c_int32), ("sigma0", C.c_double), ("ell", C.c_double * 3),
+                ("Sigma0", C.c_double), ("n_basis", C.c_int32), ("reserved", C.c_int32),
+                ("centers", C.POINTER(C.c_double)), ("width", C.c_double * 3),
+                ("phi_sigma", C.POINTER(C.c_double)), ("phi_Sigma", C.POINTER(C.c_double))]
+
+
 class CTheta(C.Structure):
     _fields_ = [("d", C.c_int32), ("n1", C.c_int32), ("n2", C.c_int32), ("wendland_variant", C.c_int32),
                 ("s0", C.c_double), ("r0", C.c_double * 3), ("h", C.POINTER(C.c_double)),
                 ("r", C.POINTER(C.c_double)), ("a", C.POINTER(C.c_double)), ("b", C.POINTER(C.c_double)),
-                ("nugget", C.c_double)]
+                ("nugget", C.c_double), ("core", C.POINTER(CCore))]
 
 
 class CSolveOpts(C.Structure):
@@ -155,7 +163,29 @@ def theta_struct(th):
     cs.a = a.ctypes.data_as(dp)
     cs.b = b.ctypes.data_as(dp)
     cs.nugget = float(th.nugget)
-    cs._keep = (h, r, a, b)
+    keep = [h, r, a, b]
+    core = getattr(th, "core", None)
+    if core is not None and int(core.kind) != CORE_NONE:
+        cc = CCore()
+        cc.kind, cc.nu2 = int(core.kind), int(core.nu2)
+        cc.sigma0, cc.Sigma0 = float(core.sigma0), float(core.Sigma0)
+        ell = np.asarray(core.ell, np.float64).reshape(-1)
+        width = np.asarray(core.width, np.float64).reshape(-1)
+        for k in range(3):
+            cc.ell[k] = float(ell[k]) if k < ell.size else 1.0
+            cc.width[k] = float(width[k]) if k < width.size else 1.0
+        ps = np.ascontiguousarray(np.asarray(core.phi_sigma, np.float64).reshape(-1))
+        pS = np.ascontiguousarray(np.asarray(core.phi_Sigma, np.float64).reshape(-1))
+        ctr = np.ascontiguousarray(np.asarray(core.centers, np.float64).reshape(-1))
+        cc.n_basis = int(ps.size) if cc.kind == CORE_PACIOREK else 0
+        if cc.n_basis and (pS.size != ps.size or ctr.size != ps.size * d):
+            raise ValueError("core: centers must be (n_basis, d) and phi_sigma, phi_Sigma (n_basis,)")
+        cc.centers = ctr.ctypes.data_as(dp)
+        cc.phi_sigma = ps.ctypes.data_as(dp)
+        cc.phi_Sigma = pS.ctypes.data_as(dp)
+        cs.core = C.pointer(cc)
+        keep += [cc, ps, pS, ctr]
+    cs._keep = tuple(keep)
     return cs
 
 

@@ -186,7 +186,7 @@ __device__ __forceinline__ void wave_sync_lds() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <int D, bool FILL, typename VT>
+template <int D, bool FILL, typename VT, int CK = 0>
 __global__ void __launch_bounds__(kThreads) k_local_rows(AsmArgs a) {
   __shared__ double stage[kThreads / kWave][D][kStage];
   const int64_t p = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x;
@@ -202,6 +202,14 @@ __global__ void __launch_bounds__(kThreads) k_local_rows(AsmArgs a) {
     int c[3];
     decode_key(a.key[p], a.g, c);
     w = make_window<D>(a, c);
+  }
+  // nonstationary core: fields of the row's point
+  double sp = 0.0, Sp = 0.0;
+  if constexpr (CK == 2) {
+    if (row) {
+      sp = a.kt.core.sig[p];
+      Sp = a.kt.core.Sig[p];
+    }
   }
   // the pencils of every row's window have the same (dy, dz) offsets; rows on
   // a grid edge have fewer, and take the ones that exist
@@ -220,9 +228,12 @@ __global__ void __launch_bounds__(kThreads) k_local_rows(AsmArgs a) {
   int32_t bc[kBuf];
   VT bv[kBuf];
   int nb = 0;
-  auto hit_at = [&](int32_t q, double u2) {
+  auto hit_at = [&](int32_t q, double u2, const double* xq) {
     if constexpr (FILL) {
-      const double v = entry_value(a.kt, u2, 0, nullptr, nullptr, q == p);
+      double cv = 1.0;
+      if constexpr (CK == 1) cv = core_value<D, 1>(a.kt.core, xp, xq, 0.0, 0.0, 0.0, 0.0);
+      if constexpr (CK == 2) cv = core_value<D, 2>(a.kt.core, xp, xq, sp, Sp, a.kt.core.sig[q], a.kt.core.Sig[q]);
+      const double v = entry_value(a.kt, u2, 0, nullptr, nullptr, q == p, 1, 1, cv);
       const VT vs = static_cast<VT>(v);
       if (q == p) a.diag[p] = static_cast<double>(vs);
       // shift register (constant indices keep it in registers): newest last
@@ -273,7 +284,7 @@ __global__ void __launch_bounds__(kThreads) k_local_rows(AsmArgs a) {
 #pragma unroll
           for (int k = 0; k < D; ++k) xq[k] = st[k][q - lo];
           const double u2 = scaled_sq<D>(xp, xq, a.kt.inv0);
-          if (u2 < 1.0) hit_at(q, u2);
+          if (u2 < 1.0) hit_at(q, u2, xq);
         }
       } else {
         for (int32_t q0 = s; q0 < e; q0 += kCu) {
@@ -283,7 +294,7 @@ __global__ void __launch_bounds__(kThreads) k_local_rows(AsmArgs a) {
 #pragma unroll
           for (int u = 0; u < kCu; ++u) {
             const double u2 = scaled_sq<D>(xp, xq[u], a.kt.inv0);
-            if (q0 + u < e && u2 < 1.0) hit_at(q0 + u, u2);
+            if (q0 + u < e && u2 < 1.0) hit_at(q0 + u, u2, xq[u]);
           }
         }
       }
@@ -362,7 +373,7 @@ __global__ void __launch_bounds__(kThreads) k_group_rows_scan(AsmArgs a) {
 // order (ascending column ids; every row with mask M shares this column list,
 // which the group-block products exploit), then the local-only entries L'(p)
 // in ascending order.
-template <int D, typename VT>
+template <int D, typename VT, int CK = 0>
 __global__ void __launch_bounds__(kThreads) k_group_rows_fill(AsmArgs a) {
   const int64_t k = (blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x) / kWave;
   if (k >= a.nm) return;
@@ -385,6 +396,16 @@ __global__ void __launch_bounds__(kThreads) k_group_rows_fill(AsmArgs a) {
     return;
   }
   const int64_t u0 = a.uoff[D_id];
+  double sp = 0.0, Sp = 0.0;
+  if constexpr (CK == 2) {
+    sp = a.kt.core.sig[p];
+    Sp = a.kt.core.Sig[p];
+  }
+  auto core_at = [&](int32_t q, const double* xq) {
+    if constexpr (CK == 1) return core_value<D, 1>(a.kt.core, xp, xq, 0.0, 0.0, 0.0, 0.0);
+    if constexpr (CK == 2) return core_value<D, 2>(a.kt.core, xp, xq, sp, Sp, a.kt.core.sig[q], a.kt.core.Sig[q]);
+    return 1.0;
+  };
   for (int64_t kk = lane; kk < nU; kk += kWave) {
     const int32_t u = U[kk];
     double xq[3];
@@ -392,7 +413,7 @@ __global__ void __launch_bounds__(kThreads) k_group_rows_fill(AsmArgs a) {
     for (int k = 0; k < D; ++k) xq[k] = a.ux[k * a.utotal + u0 + kk];
     const double u2 = scaled_sq<D>(xp, xq, a.kt.inv0);
     const uint64_t shared = a.umask[u0 + kk] & mp;
-    const double v = entry_value(a.kt, u2, shared, Fp, a.uF + u0 + kk, u == p, 1, a.utotal);
+    const double v = entry_value(a.kt, u2, shared, Fp, a.uF + u0 + kk, u == p, 1, a.utotal, core_at(u, xq));
     const VT vs = static_cast<VT>(v);
     a.col[out + kk] = u;
     val[out + kk] = vs;
@@ -403,7 +424,7 @@ __global__ void __launch_bounds__(kThreads) k_group_rows_fill(AsmArgs a) {
     double xq[3];
     load_point<D>(a.xb, a.n, q, xq);
     const double u2 = scaled_sq<D>(xp, xq, a.kt.inv0);
-    const double v = entry_value(a.kt, u2, 0, nullptr, nullptr, false);
+    const double v = entry_value(a.kt, u2, 0, nullptr, nullptr, false, 1, 1, core_at(q, xq));
     a.col[out + nU + j] = q;
     val[out + nU + j] = static_cast<VT>(v);
   }
@@ -436,6 +457,30 @@ __global__ void __launch_bounds__(kThreads) k_long_compact(int64_t n, const int3
                                                            int32_t* __restrict__ list) {
   const int64_t p = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x;
   if (p < n && flag[p]) list[pos[p]] = static_cast<int32_t>(p);
+}
+
+// sigma(x_p), Sigma(x_p) of the nonstationary core for every binned point
+template <int D>
+__global__ void __launch_bounds__(kThreads) k_core_fields(CoreBasis cb, int64_t n, const double* __restrict__ xb,
+                                                          double* __restrict__ sig, double* __restrict__ Sig) {
+  const int64_t p = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x;
+  if (p >= n) return;
+  double x[3];
+  load_point<D>(xb, n, p, x);
+  double s, S;
+  core_point_fields<D>(cb, x, &s, &S);
+  sig[p] = s;
+  Sig[p] = S;
+}
+
+template <typename F3>
+void dispatch_core(int kind, F3&& f) {
+  if (kind == GP_CORE_MATERN)
+    f(std::integral_constant<int, 1>{});
+  else if (kind == GP_CORE_PACIOREK)
+    f(std::integral_constant<int, 2>{});
+  else
+    f(std::integral_constant<int, 0>{});
 }
 
 template <typename F3>
@@ -475,6 +520,42 @@ void upload_theta(gp_ctx* c, const gp_theta* th, Bump** bumps_dev, KernelTheta* 
   kt->nugget = th->nugget;
   for (int k = 0; k < 3; ++k) kt->inv0[k] = k < th->d ? 1.0 / th->r0[k] : 0.0;
   kt->bumps = dst;
+  core_params(th, &kt->core, nullptr);
+}
+
+void core_params(const gp_theta* th, KernelCore* kc, CoreBasis* cb) {
+  *kc = KernelCore{};
+  kc->kind = GP_CORE_NONE;
+  if (cb) *cb = CoreBasis{};
+  const gp_core* co = th->core;
+  if (!co || co->kind == GP_CORE_NONE) return;
+  const int d = th->d;
+  kc->kind = co->kind;
+  kc->nu2 = co->nu2;
+  kc->s2 = co->sigma0 * co->sigma0;
+  for (int k = 0; k < 3; ++k) kc->inv_ell[k] = k < d ? 1.0 / co->ell[k] : 0.0;
+  if (cb && co->kind == GP_CORE_PACIOREK) {
+    cb->nb = co->n_basis;
+    cb->log_sigma0 = std::log(co->sigma0);
+    cb->log_Sigma0 = std::log(co->Sigma0);
+    for (int m = 0; m < co->n_basis; ++m) {
+      for (int k = 0; k < d; ++k) cb->c[m][k] = co->centers[m * d + k];
+      cb->phi_s[m] = co->phi_sigma[m];
+      cb->phi_S[m] = co->phi_Sigma[m];
+    }
+    for (int k = 0; k < 3; ++k) cb->w[k] = k < d ? co->width[k] : 1.0;
+  }
+}
+
+void core_fields(gp_ctx* c, const gp_dataset* ds, const CoreBasis& cb, double* sig, double* Sig) {
+  const int64_t n = ds->n;
+  dispatch_d(ds->d, [&](auto DD) {
+    constexpr int D = decltype(DD)::value;
+    ProfScope ps(c, "asm_core_fields");
+    hipLaunchKernelGGL((k_core_fields<D>), dim3(grid_for(n, kThreads)), dim3(kThreads), 0, c->stream, cb, n, ds->xb,
+                       sig, Sig);
+  });
+  check_launch("core fields");
 }
 
 Grid make_grid(const gp_dataset* ds, const gp_theta* th) {
@@ -602,6 +683,16 @@ gp_matrix* assemble(gp_ctx* c, const gp_dataset* ds, const gp_theta* th, int pre
     GPS_HIP(hipMemcpyAsync(hm.data(), mmask, sizeof(uint64_t) * nm, hipMemcpyDeviceToHost, c->stream));
     GPS_HIP(hipMemcpyAsync(hmlist.data(), f.mlist, sizeof(int32_t) * nm, hipMemcpyDeviceToHost, c->stream));
     record_aux(c);
+  }
+  if (kt.core.kind == GP_CORE_PACIOREK) {
+    KernelCore unused;
+    CoreBasis cb;
+    core_params(th, &unused, &cb);
+    double* sig = static_cast<double*>(workspace(c, 90, sizeof(double) * n));
+    double* Sig = static_cast<double*>(workspace(c, 91, sizeof(double) * n));
+    core_fields(c, ds, cb, sig, Sig);
+    kt.core.sig = sig;
+    kt.core.Sig = Sig;
   }
   const Grid grid = make_grid(ds, th);
   AsmArgs a{};
@@ -815,16 +906,19 @@ gp_matrix* assemble(gp_ctx* c, const gp_dataset* ds, const gp_theta* th, int pre
     }
     auto fill = [&](auto VTv) {
       using VT = decltype(VTv);
-      {
-        ProfScope ps(c, "asm_fill_local");
-        hipLaunchKernelGGL((k_local_rows<D, true, VT>), dim3(grid_for(n, kThreads)), dim3(kThreads), 0, c->stream,
-                           a);
-      }
-      if (nm > 0) {
-        ProfScope ps(c, "asm_fill_group");
-        hipLaunchKernelGGL((k_group_rows_fill<D, VT>), dim3(grid_for(nm * kWave, kThreads)), dim3(kThreads), 0,
-                           c->stream, a);
-      }
+      dispatch_core(kt.core.kind, [&](auto CC) {
+        constexpr int CK = decltype(CC)::value;
+        {
+          ProfScope ps(c, "asm_fill_local");
+          hipLaunchKernelGGL((k_local_rows<D, true, VT, CK>), dim3(grid_for(n, kThreads)), dim3(kThreads), 0,
+                             c->stream, a);
+        }
+        if (nm > 0) {
+          ProfScope ps(c, "asm_fill_group");
+          hipLaunchKernelGGL((k_group_rows_fill<D, VT, CK>), dim3(grid_for(nm * kWave, kThreads)), dim3(kThreads),
+                             0, c->stream, a);
+        }
+      });
     };
     if (prec == GP_MIXED)
       fill(float{});

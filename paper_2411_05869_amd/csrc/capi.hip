@@ -147,6 +147,28 @@ void validate_theta(const gp_theta* th, int d) {
       GPS_REQUIRE(std::isfinite(th->b[i]) && th->b[i] > 0, GP_EINVAL, "bump shapes must be finite and > 0");
     }
   }
+  const gp_core* co = th->core;
+  if (co && co->kind != GP_CORE_NONE) {
+    auto pos = [](double v) { return std::isfinite(v) && v > 0; };
+    GPS_REQUIRE(co->kind == GP_CORE_MATERN || co->kind == GP_CORE_PACIOREK, GP_EINVAL,
+                "core.kind must be GP_CORE_NONE, GP_CORE_MATERN or GP_CORE_PACIOREK");
+    GPS_REQUIRE(co->nu2 == 0 || co->nu2 == 1 || co->nu2 == 3 || co->nu2 == 5, GP_EINVAL, "core.nu2 must be 0, 1, 3 or 5");
+    GPS_REQUIRE(pos(co->sigma0), GP_EINVAL, "core.sigma0 must be finite and > 0");
+    for (int k = 0; k < d; ++k) GPS_REQUIRE(pos(co->ell[k]), GP_EINVAL, "core.ell must be finite and > 0");
+    if (co->kind == GP_CORE_PACIOREK) {
+      GPS_REQUIRE(pos(co->Sigma0), GP_EINVAL, "core.Sigma0 must be finite and > 0");
+      GPS_REQUIRE(co->n_basis >= 0 && co->n_basis <= gps::kMaxBasis, GP_EINVAL, "core.n_basis must be in 0..16");
+      for (int k = 0; k < d; ++k) GPS_REQUIRE(pos(co->width[k]), GP_EINVAL, "core.width must be finite and > 0");
+      if (co->n_basis > 0) {
+        GPS_REQUIRE(co->centers && co->phi_sigma && co->phi_Sigma, GP_EINVAL, "core basis arrays must not be NULL");
+        for (int i = 0; i < co->n_basis * d; ++i)
+          GPS_REQUIRE(std::isfinite(co->centers[i]), GP_EINVAL, "core.centers must be finite");
+        for (int i = 0; i < co->n_basis; ++i)
+          GPS_REQUIRE(std::isfinite(co->phi_sigma[i]) && std::isfinite(co->phi_Sigma[i]), GP_EINVAL,
+                      "core basis coefficients must be finite");
+      }
+    }
+  }
 }
 
 gp_solve_opts fill_opts(const gp_solve_opts* o) {

@@ -50,12 +50,13 @@ __device__ __forceinline__ double wendland(double u2, int variant) {
   return t8 * poly;
 }
 
-// Entry K_pq (Eq. C_sparse + Eq. Zcov): s0 f0 [local] + sum over shared groups
-// in increasing i of f_i(p) f_i(q) + sigma^2 [p = q].  f_i(p) = Fp[i * sp],
-// f_i(q) = Fq[i * sq].
+// Entry K_pq (Eq. sparseCov, Eq. C_sparse, Eq. Zcov): core x (s0 f0 [local] +
+// sum over shared groups in increasing i of f_i(p) f_i(q)) + sigma^2 [p = q].
+// f_i(p) = Fp[i * sp], f_i(q) = Fq[i * sq]; core = C_core(x_p, x_q), 1 without
+// a core kernel (a product with 1 is exact).
 __device__ __forceinline__ double entry_value(const KernelTheta& kt, double u2, uint64_t shared,
                                               const double* Fp, const double* Fq, bool diag, int64_t sp = 1,
-                                              int64_t sq = 1) {
+                                              int64_t sq = 1, double core = 1.0) {
 #pragma clang fp contract(off)
   double acc = (u2 < 1.0) ? kt.s0 * wendland(u2, kt.variant) : 0.0;
   while (shared) {
@@ -63,8 +64,70 @@ __device__ __forceinline__ double entry_value(const KernelTheta& kt, double u2, 
     shared &= shared - 1;
     acc = acc + Fp[i * sp] * Fq[i * sq];
   }
+  acc = core * acc;
   if (diag) acc = acc + kt.nugget;
   return acc;
+}
+
+// Matern correlation M_nu(t) (Rasmussen-Williams scaling sqrt(2 nu) t) at
+// nu = nu2 / 2 from t and t2 = t^2; nu2 = 0 is the limit exp(-t^2 / 2).
+__device__ __forceinline__ double matern(double t, double t2, int nu2) {
+#pragma clang fp contract(off)
+  if (nu2 == 0) return exp(-0.5 * t2);
+  if (nu2 == 1) return exp(-t);
+  if (nu2 == 3) {
+    const double a = 1.7320508075688772 * t;
+    return (1.0 + a) * exp(-a);
+  }
+  const double a = 2.23606797749979 * t;
+  return (1.0 + a + a * a / 3.0) * exp(-a);
+}
+
+// Core kernel value C_core(x_p, x_q) (Eq. sparseCov): CK = 1 stationary
+// Matern sigma0^2 M_nu(|(x_p - x_q) / ell|); CK = 2 the nonstationary kernel
+// of Eq. PScov from the fields (sp, Sp) at x_p and (sq, Sq) at x_q, its
+// prefactor (Sp Sq)^(d/4) / ((Sp + Sq)/2)^(d/2) written as g^(d/2) with
+// g = 2 sqrt(Sp Sq) / (Sp + Sq).  Every operation is symmetric in p and q, so
+// the value is bitwise the same for (p, q) and (q, p).
+template <int D, int CK>
+__device__ __forceinline__ double core_value(const KernelCore& kc, const double* xp, const double* xq, double sp,
+                                             double Sp, double sq, double Sq) {
+#pragma clang fp contract(off)
+  const double r2 = scaled_sq<D>(xp, xq, kc.inv_ell);
+  if constexpr (CK == 1) {
+    return kc.s2 * matern(__builtin_sqrt(r2), r2, kc.nu2);
+  } else {
+    const double sum = Sp + Sq;
+    const double avg = 0.5 * sum;
+    const double g = 2.0 * __builtin_sqrt(Sp * Sq) / sum;
+    double pre;
+    if constexpr (D == 1) pre = __builtin_sqrt(g);
+    else if constexpr (D == 2) pre = g;
+    else pre = g * __builtin_sqrt(g);
+    const double q2 = r2 / avg;
+    return (sp * sq) * pre * matern(__builtin_sqrt(q2), q2, kc.nu2);
+  }
+}
+
+// sigma(x), Sigma(x) of the nonstationary core: basis functions and
+// coefficients summed in increasing m.
+template <int D>
+__device__ __forceinline__ void core_point_fields(const CoreBasis& cb, const double* x, double* sig, double* Sig) {
+#pragma clang fp contract(off)
+  double ls = cb.log_sigma0, lS = cb.log_Sigma0;
+  for (int m = 0; m < cb.nb; ++m) {
+    double acc = 0.0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      const double z = (x[k] - cb.c[m][k]) / cb.w[k];
+      acc = acc + z * z;
+    }
+    const double s = exp(-0.5 * acc);
+    ls = ls + s * cb.phi_s[m];
+    lS = lS + s * cb.phi_S[m];
+  }
+  *sig = exp(ls);
+  *Sig = exp(lS);
 }
 
 // Point features: group mask and (optionally) the bump sums f_i (Eq. bumpFcn,

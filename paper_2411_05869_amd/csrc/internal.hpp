@@ -15,6 +15,7 @@ namespace gps {
 constexpr int kWave = 64;
 constexpr int kMaxGroups = 64;      // n1 <= 64: group membership is one uint64 per point
 constexpr int kMaxBumps = 4096;     // n1 * n2
+constexpr int kMaxBasis = 16;       // basis functions of the nonstationary core
 constexpr int kLongRow = 128;       // rows longer than this get a wave of their own in SpMV
 constexpr int64_t kCsrPad = 64;     // padding entries after the CSR column and value arrays
 constexpr int kTileRows = 16;       // rows per tile of a group block
@@ -160,11 +161,34 @@ struct Features {
   int64_t nm = 0;
 };
 
+// Core kernel as the entry kernels use it: kind (GP_CORE_*), nu2, sigma0^2,
+// 1 / ell; for the nonstationary core the per-point fields sigma(x_p) and
+// Sigma(x_p) of the training points in binned order (device).
+struct KernelCore {
+  int kind, nu2;
+  double s2;
+  double inv_ell[3];
+  const double* sig;
+  const double* Sig;
+};
+
+// Parameters of the log-linear fields of the nonstationary core (Eq. PScov):
+// log sigma = log sigma0 + sum_m s_m phi_s[m], log Sigma = log Sigma0 +
+// sum_m s_m phi_S[m], s_m(x) = exp(-|(x - c[m]) / w|^2 / 2).
+struct CoreBasis {
+  int nb;
+  double log_sigma0, log_Sigma0;
+  double c[kMaxBasis][3];
+  double w[3];
+  double phi_s[kMaxBasis], phi_S[kMaxBasis];
+};
+
 struct KernelTheta {
   int d, n1, n2, variant;
   double s0, nugget;
   double inv0[3];
   const Bump* bumps;  // device, n1*n2
+  KernelCore core;
 };
 
 // -------------------------------------------------------------- memory
@@ -238,6 +262,11 @@ int64_t read_i64(gp_ctx* c, const int64_t* dev);   // synchronising read
 // -------------------------------------------------------------- stages
 void bin_dataset(gp_ctx* c, gp_dataset* ds, const double* x_dev, const double* cell);
 void upload_theta(gp_ctx* c, const gp_theta* th, Bump** bumps_dev, KernelTheta* kt);
+// Core parameters of theta (kind GP_CORE_NONE when theta has none); the field
+// pointers of kc are left null.
+void core_params(const gp_theta* th, KernelCore* kc, CoreBasis* cb);
+// sigma(x_p), Sigma(x_p) of every binned point of ds (nonstationary core)
+void core_fields(gp_ctx* c, const gp_dataset* ds, const CoreBasis& cb, double* sig, double* Sig);
 void compute_features(gp_ctx* c, const gp_dataset* ds, const KernelTheta& kt, Features* f,
                       int ws_base);
 Grid make_grid(const gp_dataset* ds, const gp_theta* th);

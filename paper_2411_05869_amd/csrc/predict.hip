@@ -7,6 +7,12 @@
 //            = sum_{i in M(x*)} f_i(x*) c_i,   c_i = sum_q f_i(x_q) alpha_q,
 //     the rank-n1 structure of the bump term (Proposition 1's proof), with
 //     c_i computed once per (theta, alpha) when the predictor is created.
+// With a core kernel (Eq. sparseCov) both parts are multiplied by
+// C_core(x*, x_q) inside the sums.  The bump part then no longer factors
+// through c_i: a wave per test point with a group bit sums
+//   sum_q C_core(x*, x_q) sum_{i in M(x*) & M(q)} f_i(x*) f_i(x_q) alpha_q
+// over the masked training points (their data copied when the predictor is
+// created).
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -23,6 +29,15 @@ struct gp_predictor {
   double* alpha_b = nullptr;  // n, binned order
   double* coef = nullptr;     // n1 (at least 1)
   float* alpha32 = nullptr;   // n, float32 copy for the mixed form
+  // core kernel: basis of the nonstationary fields, the fields of the training
+  // points (binned order), and the masked training points' data
+  gps::CoreBasis cb{};
+  double* sig = nullptr;      // n (nonstationary core)
+  double* Sig = nullptr;      // n
+  int64_t nm = 0;
+  int32_t* mlist = nullptr;   // nm binned ids of the masked training points
+  uint64_t* mmask = nullptr;  // nm group masks
+  double* mF = nullptr;       // nm x n1 values f_i
 };
 
 namespace gps {
@@ -62,11 +77,16 @@ struct PredArgs {
   const double* alpha;
   const float* alpha32;
   const double* coef;
+  // core kernel: masked training points
+  int64_t nm;
+  const int32_t* mlist;
+  const uint64_t* mmask;
+  const double* mF;
 };
 
-template <int D, bool MIXED>
-__global__ void __launch_bounds__(kThreads) k_predict(PredArgs a, int64_t m, const double* __restrict__ xs,
-                                                      double* __restrict__ out) {
+template <int D, bool MIXED, int CK>
+__global__ void __launch_bounds__(kThreads) k_predict(PredArgs a, CoreBasis cb, int64_t m,
+                                                      const double* __restrict__ xs, double* __restrict__ out) {
   const int64_t t = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x;
   if (t >= m) return;
   double xp[3];
@@ -75,6 +95,8 @@ __global__ void __launch_bounds__(kThreads) k_predict(PredArgs a, int64_t m, con
     xp[k] = xs[t * D + k];
     c[k] = cell_coord(xp[k], a.lo[k], a.cell[k]);
   }
+  double sp = 0.0, Sp = 0.0;
+  if constexpr (CK == 2) core_point_fields<D>(cb, xp, &sp, &Sp);
   int lo_[3] = {0, 0, 0}, hi_[3] = {0, 0, 0};
   bool empty = false;
   for (int k = 0; k < D; ++k) {
@@ -96,7 +118,10 @@ __global__ void __launch_bounds__(kThreads) k_predict(PredArgs a, int64_t m, con
           if constexpr (D >= 3) xq[2] = a.xb[2 * a.n + q];
           const double u2 = scaled_sq<D>(xp, xq, a.kt.inv0);
           if (u2 < 1.0) {
-            const double v = a.kt.s0 * wendland(u2, a.kt.variant);
+            double v = a.kt.s0 * wendland(u2, a.kt.variant);
+            if constexpr (CK == 1) v = core_value<D, 1>(a.kt.core, xp, xq, 0.0, 0.0, 0.0, 0.0) * v;
+            if constexpr (CK == 2)
+              v = core_value<D, 2>(a.kt.core, xp, xq, sp, Sp, a.kt.core.sig[q], a.kt.core.Sig[q]) * v;
             if constexpr (MIXED)
               acc += static_cast<double>(static_cast<float>(v) * a.alpha32[q]);
             else
@@ -105,9 +130,9 @@ __global__ void __launch_bounds__(kThreads) k_predict(PredArgs a, int64_t m, con
         }
       }
   }
-  // bump groups of the test point
+  // bump groups of the test point (with a core kernel: k_predict_groups)
   double gsum = 0.0;
-  for (int i = 0; i < a.kt.n1; ++i) {
+  for (int i = 0; CK == 0 && i < a.kt.n1; ++i) {
     double f = 0.0;
     bool in_group = false;
     for (int j = 0; j < a.kt.n2; ++j) {
@@ -121,6 +146,67 @@ __global__ void __launch_bounds__(kThreads) k_predict(PredArgs a, int64_t m, con
     if (in_group) gsum += f * a.coef[i];
   }
   out[t] = acc + gsum;
+}
+
+// Bump part with a core kernel: one wave per test point.  Lane i < n1 forms
+// f_i(x*) (bumps of group i in j order) into LDS; the lanes then stride over
+// the masked training points and the wave adds its lanes in a fixed order.
+template <int D, int CK>
+__global__ void __launch_bounds__(kThreads) k_predict_groups(PredArgs a, CoreBasis cb, int64_t m,
+                                                             const double* __restrict__ xs, double* __restrict__ out) {
+  __shared__ double fs[kThreads / kWave][kWave];
+  const int64_t t = (blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x) / kWave;
+  if (t >= m) return;  // uniform per wave
+  const int lane = lane_id();
+  double* f = fs[threadIdx.x / kWave];
+  double xp[3];
+  for (int k = 0; k < D; ++k) xp[k] = xs[t * D + k];
+  bool in_group = false;
+  double fi = 0.0;
+  if (lane < a.kt.n1) {
+#pragma clang fp contract(off)
+    for (int j = 0; j < a.kt.n2; ++j) {
+      const Bump& bp = a.kt.bumps[lane * a.kt.n2 + j];
+      const double ub2 = scaled_sq<D>(xp, bp.h, bp.inv);
+      if (bp.a > 0.0 && ub2 < 1.0) {
+        in_group = true;
+        fi = fi + bp.a * exp(bp.b * (1.0 - 1.0 / (1.0 - ub2)));
+      }
+    }
+  }
+  const uint64_t mask = __ballot(in_group);
+  if (mask == 0) return;  // uniform
+  f[lane] = fi;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  double sp = 0.0, Sp = 0.0;
+  if constexpr (CK == 2) core_point_fields<D>(cb, xp, &sp, &Sp);
+  double acc = 0.0;
+  for (int64_t j = lane; j < a.nm; j += kWave) {
+    uint64_t sh = a.mmask[j] & mask;
+    if (!sh) continue;
+    double bsum = 0.0;
+    while (sh) {
+      const int i = __builtin_ctzll(sh);
+      sh &= sh - 1;
+      bsum += f[i] * a.mF[j * a.kt.n1 + i];
+    }
+    const int32_t q = a.mlist[j];
+    double xq[3];
+    xq[0] = a.xb[q];
+    if constexpr (D >= 2) xq[1] = a.xb[a.n + q];
+    if constexpr (D >= 3) xq[2] = a.xb[2 * a.n + q];
+    double cv;
+    if constexpr (CK == 1)
+      cv = core_value<D, 1>(a.kt.core, xp, xq, 0.0, 0.0, 0.0, 0.0);
+    else
+      cv = core_value<D, 2>(a.kt.core, xp, xq, sp, Sp, a.kt.core.sig[q], a.kt.core.Sig[q]);
+    acc += cv * bsum * a.alpha[q];
+  }
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kWave);
+  if (lane == 0) out[t] += acc;
 }
 
 }  // namespace
@@ -145,12 +231,32 @@ gp_predictor* make_predictor(gp_ctx* c, const gp_dataset* ds, const gp_theta* th
   permute_to_binned<double>(c, ds, 1, alpha, p->alpha_b);
   hipLaunchKernelGGL(k_to_f32, dim3(grid_for(n, kThreads)), dim3(kThreads), 0, c->stream, n, p->alpha_b, p->alpha32);
   check_launch("alpha f32");
+  KernelCore kc;
+  core_params(th, &kc, &p->cb);
+  if (kc.kind == GP_CORE_PACIOREK) {
+    p->sig = dev_new<double>(c, n);
+    p->Sig = dev_new<double>(c, n);
+    core_fields(c, ds, p->cb, p->sig, p->Sig);
+    kc.sig = p->sig;
+    kc.Sig = p->Sig;
+  }
+  p->kt.core = kc;
   if (th->n1 > 0) {
     Features f;
     compute_features(c, ds, kt, &f, 60);
     hipLaunchKernelGGL(k_group_coef, dim3(th->n1), dim3(kThreads), 0, c->stream, f.nm, th->n1, f.F, f.mlist,
                        p->alpha_b, p->coef);
     check_launch("group coefficients");
+    if (kc.kind != GP_CORE_NONE && f.nm > 0) {
+      // the feature arrays live in workspace slots: keep copies
+      p->nm = f.nm;
+      p->mlist = dev_new<int32_t>(c, f.nm);
+      p->mmask = dev_new<uint64_t>(c, f.nm);
+      p->mF = dev_new<double>(c, f.nm * th->n1);
+      GPS_HIP(hipMemcpyAsync(p->mlist, f.mlist, sizeof(int32_t) * f.nm, hipMemcpyDeviceToDevice, c->stream));
+      GPS_HIP(hipMemcpyAsync(p->mmask, f.mmask, sizeof(uint64_t) * f.nm, hipMemcpyDeviceToDevice, c->stream));
+      GPS_HIP(hipMemcpyAsync(p->mF, f.F, sizeof(double) * f.nm * th->n1, hipMemcpyDeviceToDevice, c->stream));
+    }
   }
   sync(c);
   return p.release();
@@ -163,6 +269,11 @@ void destroy_predictor(gp_ctx* c, gp_predictor* p) {
   dev_free(c, p->alpha_b, sizeof(double) * n);
   dev_free(c, p->alpha32, sizeof(float) * n);
   dev_free(c, p->coef, sizeof(double) * std::max(p->kt.n1, 1));
+  if (p->sig) dev_free(c, p->sig, sizeof(double) * n);
+  if (p->Sig) dev_free(c, p->Sig, sizeof(double) * n);
+  if (p->mlist) dev_free(c, p->mlist, sizeof(int32_t) * p->nm);
+  if (p->mmask) dev_free(c, p->mmask, sizeof(uint64_t) * p->nm);
+  if (p->mF) dev_free(c, p->mF, sizeof(double) * p->nm * p->kt.n1);
   delete p;
 }
 
@@ -183,14 +294,32 @@ void predict(gp_ctx* c, const gp_predictor* p, int64_t m, const double* xs, int 
   a.alpha = p->alpha_b;
   a.alpha32 = p->alpha32;
   a.coef = p->coef;
+  a.nm = p->nm;
+  a.mlist = p->mlist;
+  a.mmask = p->mmask;
+  a.mF = p->mF;
   const dim3 G(grid_for(m, kThreads)), B(kThreads);
   ProfScope ps(c, prec == GP_MIXED ? "predict_f32" : "predict_f64");
   auto go = [&](auto DD) {
     constexpr int D = decltype(DD)::value;
-    if (prec == GP_MIXED)
-      hipLaunchKernelGGL((k_predict<D, true>), G, B, 0, c->stream, a, m, xs, out);
+    auto with_core = [&](auto CC) {
+      constexpr int CK = decltype(CC)::value;
+      if (prec == GP_MIXED)
+        hipLaunchKernelGGL((k_predict<D, true, CK>), G, B, 0, c->stream, a, p->cb, m, xs, out);
+      else
+        hipLaunchKernelGGL((k_predict<D, false, CK>), G, B, 0, c->stream, a, p->cb, m, xs, out);
+      if constexpr (CK != 0) {
+        if (p->nm > 0)
+          hipLaunchKernelGGL((k_predict_groups<D, CK>), dim3(grid_for(m * kWave, kThreads)), B, 0, c->stream, a,
+                             p->cb, m, xs, out);
+      }
+    };
+    if (p->kt.core.kind == GP_CORE_MATERN)
+      with_core(std::integral_constant<int, 1>{});
+    else if (p->kt.core.kind == GP_CORE_PACIOREK)
+      with_core(std::integral_constant<int, 2>{});
     else
-      hipLaunchKernelGGL((k_predict<D, false>), G, B, 0, c->stream, a, m, xs, out);
+      with_core(std::integral_constant<int, 0>{});
   };
   if (ds->d == 1)
     go(std::integral_constant<int, 1>{});

@@ -36,3 +36,32 @@ def test_binding_names_match_header():
     assert sorted(_lib.EXPORTS) == declared()
     L = _lib.lib()
     assert L.gp_last_error(None) == b"context is NULL"
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """Sizes and field offsets of the ctypes structures equal those the C
+    compiler gives the header's structures."""
+    import shutil
+    import subprocess
+    from paper_2411_05869_amd import _lib
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = {"gp_theta": _lib.CTheta, "gp_core": _lib.CCore, "gp_solve_opts": _lib.CSolveOpts,
+               "gp_loglik_result": _lib.CLoglikResult}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "gpsparse.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'  printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, f"-I{os.path.join(ROOT, 'include')}", str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l}
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
