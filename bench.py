@@ -178,6 +178,50 @@ def serving_legs(args, ctx, ds, p, alpha):
     return res
 
 
+def core_legs(ctx, ds, p, y, xs, opts, reps=2):
+    """Same space-time workload with a core kernel (stationary Matern nu = 5/2,
+    then the nonstationary core): assemble wall time, one mixed-form step
+    (assemble + likelihood + 10k-point prediction) and the prediction alone."""
+    import copy
+
+    import torch
+
+    from paper_2411_05869_amd import MIXED
+    from workloads import spacetime_core
+    res = {}
+    alpha = torch.empty(p.n, dtype=torch.float64, device="cuda")
+    for name, kind in (("matern52", 1), ("paciorek_nu52", 2)):
+        th = copy.copy(p.theta)
+        th.core = spacetime_core(kind)
+        asm, steps, preds = [], [], []
+        r = None
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            K = ctx.assemble(ds, th, MIXED)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            r = ctx.loglik(K, y, alpha_out=alpha, **opts)
+            pred = ctx.predictor(ds, th, alpha)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            ctx.predict(pred, xs, precision=MIXED)
+            torch.cuda.synchronize()
+            t3 = time.perf_counter()
+            asm.append(t1 - t0)
+            steps.append(t3 - t0)
+            preds.append(t3 - t2)
+            nnz = K.nnz
+            K.close()
+            pred.close()
+        res[name] = dict(assemble_ms=round(1e3 * min(asm), 3), nnz_per_s=round(nnz / min(asm), 1),
+                         step_ms=round(1e3 * min(steps), 2), evals_per_s=round(1 / min(steps), 3),
+                         predict_10k_ms=round(1e3 * min(preds), 3), cg_iters=r["cg_iters"],
+                         minres_iters=r["minres_iters"], loglik=r["loglik"])
+        log(f"core {name}: {res[name]}")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -188,6 +232,7 @@ def main():
     ap.add_argument("--stations", type=int, default=3000)
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=128)
+    ap.add_argument("--no-core", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="copy 1 GiB device-to-device first (reference dispatch for HBM counters)")
     ap.add_argument("--summarize-pmc", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "COMMAND"),
@@ -327,6 +372,8 @@ def main():
                paper_context="paper: ~66 s per likelihood (37 s covariance) at N=1,038,723 on 256 A100 (Sec. 5.2)")
     if not args.no_serve:
         out["serving"] = serving_legs(args, ctx, ds, p, alpha)
+    if not args.no_core:
+        out["core"] = core_legs(ctx, ds, p, y, xs, opts)
     if not args.no_cpu:
         log("cpu baseline (oracle on a bounded sample) ...")
         cb, (sel, snnz) = cpu_baseline(p)

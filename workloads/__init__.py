@@ -253,6 +253,19 @@ def config3(n_stations: int = 3000, n_days: int = 365, seed: int = 3) -> Problem
     return Problem(f"cfg3-spacetime-{n_stations}x{n_days}", x, th, y=y, cell=cell)
 
 
+def spacetime_core(kind: int, seed: int = 33, nu2: int = 5, n_basis: int = 8) -> Core:
+    """A core kernel for the space-time workload: scales ell = (0.05, 0.05, 10
+    days); for the nonstationary core, basis centres uniform over the domain
+    [0,1]^2 x [0,365] days with widths (0.25, 0.25, 60 days) and coefficients
+    N(0, 0.5^2)."""
+    rng = np.random.default_rng(seed)
+    centers = rng.uniform(0.0, 1.0, size=(n_basis, 3)) * np.array([1.0, 1.0, 365.0])
+    phi_s = rng.normal(0.0, 0.5, size=n_basis)
+    phi_S = rng.normal(0.0, 0.5, size=n_basis)
+    return Core(int(kind), int(nu2), 1.0, np.array([0.05, 0.05, 10.0]), 1.0, centers,
+                np.array([0.25, 0.25, 60.0]), phi_s, phi_S)
+
+
 # ---------------------------------------------------------------- serving ---
 
 def config4_pool(n_datasets: int = 16, base_seed: int = 4000):
