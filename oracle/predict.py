@@ -11,7 +11,16 @@ residual y = z - W beta passed in and a zero prior mean at the test points
 where C_y = C_core C_sparse (Eq. sparseCov) carries no nugget (the
 nugget belongs to the observations z, Eq. Zcov).  At the training inputs
 m(X) = (C_z - sigma^2 I) alpha = y - sigma^2 alpha.
+
+The same passage gives the conditional covariance
+C_{y|z} = C_y - C_{y,z} C_z^{-1} C_{z,y}; its diagonal at the test points is
+
+    v(x*) = C_y(x*, x*) - c^T C_z^{-1} c,   c = C_{z,y}(., x*),
+
+the posterior variance of the latent process (no nugget: a new observation
+would add sigma^2).
 """
+
 from __future__ import annotations
 
 import numpy as np
@@ -47,3 +56,26 @@ def mean_rows(xs, x, th, alpha):
     for s in range(xs.shape[0]):
         out[s] = vals[rp[s]:rp[s + 1]] @ alpha[cols[rp[s]:rp[s + 1]]]
     return out
+
+
+def prior_variance(xs, th):
+    """C_y(x*, x*) for every test point (Eq. sparseCov at x = x'; no nugget)."""
+    xs = np.asarray(xs, np.float64)
+    Ms, Fs = kernel.features(xs, th)
+    return kernel.entries(xs, xs, Ms, Ms, Fs, Fs, np.zeros(xs.shape[0], bool), th)
+
+
+def variance(xs, x, th):
+    """diag C_{y|z} at the test points: C_y(x*, x*) - c^T C_z^{-1} c, with the
+    dense Cholesky factor L of C_z (c^T C_z^{-1} c = |L^{-1} c|^2)."""
+    import scipy.linalg as sla
+    xs = np.asarray(xs, np.float64)
+    x = np.asarray(x, np.float64)
+    K, _ = kernel.dense(x, th)
+    L = np.linalg.cholesky(K)
+    rp, cols, vals = kernel.cross_entries(xs, x, th)
+    C = np.zeros((x.shape[0], xs.shape[0]))
+    for s in range(xs.shape[0]):
+        C[cols[rp[s]:rp[s + 1]], s] = vals[rp[s]:rp[s + 1]]
+    V = sla.solve_triangular(L, C, lower=True)
+    return prior_variance(xs, th) - np.sum(V * V, axis=0)

@@ -6,6 +6,7 @@ import math
 import os
 
 import numpy as np
+import pytest
 import scipy.stats
 
 from oracle import kernel, likelihood, predict, slq
@@ -141,3 +142,43 @@ def test_predict_closed_form_single_point():
                np.ones((1, 1)), 0.2, 0)
     m = predict.mean(np.array([[0.5], [2.0]]), np.array([[0.0]]), th, np.array([3.0]))
     assert m[0] == 1.5 * 0.06103515625 * 3.0 and m[1] == 0.0
+
+
+def test_variance_at_training_inputs_closed_form():
+    # c = K e_p - sigma^2 e_p gives v_p = sigma^2 - sigma^4 (K^-1)_pp
+    from workloads import uniform_problem
+    p = uniform_problem(300, 2, 12, r0=0.1, n1=2, n2=2, bump_radius=0.3)
+    K, _ = kernel.dense(p.x, p.theta)
+    Kinv = np.linalg.inv(K)
+    s2 = p.theta.nugget
+    idx = np.arange(0, 300, 7)
+    v = predict.variance(p.x[idx], p.x, p.theta)
+    assert np.allclose(v, s2 - s2 * s2 * np.diag(Kinv)[idx], rtol=1e-9, atol=1e-14)
+
+
+@pytest.mark.parametrize("with_core", [False, True])
+def test_variance_is_the_joint_schur_complement(with_core):
+    # v = 1 / (J^-1)_00 for the joint covariance J of (y(x*), z)
+    from workloads import core_problem, uniform_problem
+    p = core_problem(2, 2, n=250, seed=4) if with_core else uniform_problem(250, 2, 13, r0=0.1, n1=2, n2=2,
+                                                                             bump_radius=0.3)
+    K, _ = kernel.dense(p.x, p.theta)
+    xs = np.random.default_rng(1).uniform(0, 1, (12, 2))
+    v = predict.variance(xs, p.x, p.theta)
+    prior = predict.prior_variance(xs, p.theta)
+    rp, cols, vals = kernel.cross_entries(xs, p.x, p.theta)
+    for s in range(xs.shape[0]):
+        c = np.zeros(p.n)
+        c[cols[rp[s]:rp[s + 1]]] = vals[rp[s]:rp[s + 1]]
+        J = np.block([[np.array([[prior[s]]]), c[None, :]], [c[:, None], K]])
+        assert math.isclose(v[s], 1.0 / np.linalg.inv(J)[0, 0], rel_tol=1e-8)
+        assert 0.0 < v[s] <= prior[s]
+
+
+def test_variance_far_from_data_is_the_prior():
+    from workloads import uniform_problem
+    p = uniform_problem(200, 2, 14, r0=0.1, n1=2, n2=2, bump_radius=0.2)
+    xs = np.array([[5.0, 5.0], [-3.0, 0.5]])
+    v = predict.variance(xs, p.x, p.theta)
+    assert np.array_equal(v, predict.prior_variance(xs, p.theta))
+    assert np.array_equal(v, np.full(2, p.theta.s0))
