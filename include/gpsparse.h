@@ -304,6 +304,34 @@ GP_API gp_status gp_predictor_destroy(gp_ctx* ctx, gp_predictor* p);
 GP_API gp_status gp_predict(gp_ctx* ctx, const gp_predictor* p, int64_t m, const double* xstar_dev,
                      gp_precision prec, double* mean_dev);
 
+/* gp_predict_var: posterior variance of the latent process at m test points
+ * (Sec. 3.2: the diagonal of C_{y|z} = C_y - C_{y,z} C_z^{-1} C_{z,y}),
+ *   var(x*) = C_y(x*, x*) - c^T K^{-1} c,   c = C_{z,y}(., x*)  (no nugget),
+ * into var_dev (m float64, device).  K must have been assembled with theta
+ * (checked against a fingerprint of every hyper-parameter).  The test points
+ * (xstar_dev: m x d row-major float64, device) are taken 32 at a time: their
+ * cross-covariance columns are formed on the device and K W = C is solved by
+ * 32 Jacobi-preconditioned conjugate-gradient recurrences in lockstep (one
+ * sparse product with 32 columns per step, float64 vectors, the matrix's
+ * stored values), each stopping when |c_s - K w_s| <= opts->rtol |c_s|; a
+ * float64 true residual is taken at the end.  opts may be NULL (defaults;
+ * rtol and max_iter are used).  Work space: six n x 32 float64 blocks.
+ * out (may be NULL) receives iteration counts and the largest final relative
+ * residual.
+ * Errors: GP_EINVAL (theta differs from K's, m < 0, NULL buffers),
+ * GP_ENOTCONV (a column missed rtol within max_iter steps; var holds the
+ * last iterate's values), GP_ENOTPD, GP_ENOMEM, GP_EDEVICE. */
+typedef struct gp_var_result {
+  int64_t iters;            /* iterations summed over the batches */
+  int32_t max_batch_iters;  /* most iterations of one batch */
+  int32_t status;           /* gp_status */
+  double relres;            /* largest final |c - K w| / |c| */
+} gp_var_result;
+
+GP_API gp_status gp_predict_var(gp_ctx* ctx, const gp_matrix* K, const gp_theta* theta, int64_t m,
+                         const double* xstar_dev, const gp_solve_opts* opts, double* var_dev,
+                         gp_var_result* out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -100,3 +100,18 @@ def split_woodbury(A, F, y, dense_A: bool = False):
     alpha = Ay - AF @ Sc
     logdet = logdetA + logdetS
     return dict(logdet=logdet, quad=quad, loglik=assemble(logdet, quad, len(y)), alpha=alpha)
+
+
+def split_solve(A, F, B):
+    """K^{-1} B for K = A + F F^T (A sparse SPD, F n x n1, B n x k) by the
+    Woodbury identity: A^{-1} B - A^{-1} F S^{-1} F^T A^{-1} B with
+    S = I + F^T A^{-1} F; one SuperLU factorisation of A."""
+    F = np.asarray(F, np.float64)
+    B = np.asarray(B, np.float64)
+    f = SparseLU(A)
+    AB = f.solve(B)
+    if F.shape[1] == 0:
+        return AB
+    AF = f.solve(F)
+    S = np.eye(F.shape[1]) + F.T @ AF
+    return AB - AF @ np.linalg.solve(S, F.T @ AB)

@@ -79,3 +79,28 @@ def variance(xs, x, th):
         C[cols[rp[s]:rp[s + 1]], s] = vals[rp[s]:rp[s + 1]]
     V = sla.solve_triangular(L, C, lower=True)
     return prior_variance(xs, th) - np.sum(V * V, axis=0)
+
+
+def variance_split(xs, x, th):
+    """The same diagonal through the split K = A + F F^T of Proposition 1's
+    proof (A: the local Wendland part plus the nugget, F: the bump sums of the
+    masked points), for larger n without a core kernel: c^T K^{-1} c with
+    K^{-1} C from one sparse factorisation (``likelihood.split_solve``)."""
+    import copy
+
+    from . import likelihood
+    xs = np.asarray(xs, np.float64)
+    x = np.asarray(x, np.float64)
+    if getattr(th, "core", None) is not None and th.core.kind != 0:
+        raise ValueError("the split K = A + F F^T needs a unit core kernel")
+    th_local = copy.deepcopy(th)
+    th_local.a = np.zeros_like(np.asarray(th_local.a, np.float64))
+    ip, ci, vv = kernel.sparse(x, th_local)
+    A = kernel.to_scipy(ip, ci, vv, x.shape[0])
+    M, F = kernel.features(x, th)
+    rp, cols, vals = kernel.cross_entries(xs, x, th, M=M, F=F)
+    C = np.zeros((x.shape[0], xs.shape[0]))
+    for s in range(xs.shape[0]):
+        C[cols[rp[s]:rp[s + 1]], s] = vals[rp[s]:rp[s + 1]]
+    W = likelihood.split_solve(A, np.where(M, F, 0.0), C)
+    return prior_variance(xs, th) - np.sum(C * W, axis=0)

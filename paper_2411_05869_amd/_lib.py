@@ -63,12 +63,20 @@ class CLoglikResult(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class CVarResult(C.Structure):
+    _fields_ = [("iters", C.c_int64), ("max_batch_iters", C.c_int32), ("status", C.c_int32),
+                ("relres", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 EXPORTS = [
     "gp_ctx_create", "gp_ctx_destroy", "gp_ctx_set_stream", "gp_last_error", "gp_ctx_memory",
     "gp_dataset_create", "gp_dataset_destroy", "gp_dataset_info", "gp_dataset_permutation",
     "gp_assemble", "gp_matrix_destroy", "gp_matrix_info", "gp_matrix_export_csr", "gp_matvec",
     "gp_solve_opts_default", "gp_loglik", "gp_solve", "gp_predictor_create", "gp_predictor_destroy",
-    "gp_predict", "gp_profile_enable", "gp_profile_read",
+    "gp_predict", "gp_predict_var", "gp_profile_enable", "gp_profile_read",
 ]
 
 
@@ -109,6 +117,7 @@ def lib():
     L.gp_predictor_create.argtypes = [P, P, C.POINTER(CTheta), P, C.POINTER(P)]
     L.gp_predictor_destroy.argtypes = [P, P]
     L.gp_predict.argtypes = [P, P, I64, P, C.c_int, P]
+    L.gp_predict_var.argtypes = [P, P, C.POINTER(CTheta), I64, P, C.POINTER(CSolveOpts), P, C.POINTER(CVarResult)]
     L.gp_profile_enable.argtypes = [P, I32]
     L.gp_profile_read.argtypes = [P, I32, C.POINTER(CProfileEntry), C.POINTER(I32)]
     for name in EXPORTS:
@@ -358,6 +367,23 @@ class Context:
         self._check(self._L.gp_predict(self._h, pred._h, m, C.c_void_p(_ptr(xs)), int(precision),
                                        C.c_void_p(_ptr(out))), "gp_predict")
         return out
+
+    def predict_var(self, K: "Matrix", theta, xs, out=None, raise_on_error: bool = True, **opts):
+        """Posterior variance of the latent process at the rows of xs (device,
+        m x d float64); K must be assembled with theta.  Returns (var, result)."""
+        torch = _torch()
+        _check_dev_tensor(xs, torch.float64, name="xs")
+        m = int(xs.shape[0])
+        if out is None:
+            out = torch.empty(m, dtype=torch.float64, device=xs.device)
+        cs = theta_struct(theta)
+        o = self.opts(**opts)
+        res = CVarResult()
+        st = self._L.gp_predict_var(self._h, K._h, C.byref(cs), m, C.c_void_p(_ptr(xs)), C.byref(o),
+                                    C.c_void_p(_ptr(out)), C.byref(res))
+        if st != 0 and raise_on_error:
+            self._check(st, "gp_predict_var")
+        return out, res.as_dict()
 
 
 class _Obj:

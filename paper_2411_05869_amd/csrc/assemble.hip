@@ -523,6 +523,47 @@ void upload_theta(gp_ctx* c, const gp_theta* th, Bump** bumps_dev, KernelTheta* 
   core_params(th, &kt->core, nullptr);
 }
 
+uint64_t theta_hash(const gp_theta* th) {
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&](const void* p, size_t bytes) {
+    const unsigned char* b = static_cast<const unsigned char*>(p);
+    for (size_t i = 0; i < bytes; ++i) {
+      h ^= b[i];
+      h *= 1099511628211ull;
+    }
+  };
+  auto arr = [&](const double* p, int64_t count) {
+    if (p && count > 0) mix(p, sizeof(double) * static_cast<size_t>(count));
+  };
+  const int d = th->d, nb = th->n1 * th->n2;
+  const int32_t ints[4] = {th->d, th->n1, th->n2, th->wendland_variant};
+  mix(ints, sizeof(ints));
+  mix(&th->s0, sizeof(double));
+  arr(th->r0, d);
+  arr(th->h, static_cast<int64_t>(nb) * d);
+  arr(th->r, static_cast<int64_t>(nb) * d);
+  arr(th->a, nb);
+  arr(th->b, nb);
+  mix(&th->nugget, sizeof(double));
+  const gp_core* co = th->core;
+  const int32_t kind = co ? co->kind : GP_CORE_NONE;
+  mix(&kind, sizeof(kind));
+  if (kind != GP_CORE_NONE) {
+    mix(&co->nu2, sizeof(co->nu2));
+    mix(&co->sigma0, sizeof(double));
+    arr(co->ell, d);
+    if (kind == GP_CORE_PACIOREK) {
+      mix(&co->Sigma0, sizeof(double));
+      mix(&co->n_basis, sizeof(co->n_basis));
+      arr(co->width, d);
+      arr(co->centers, static_cast<int64_t>(co->n_basis) * d);
+      arr(co->phi_sigma, co->n_basis);
+      arr(co->phi_Sigma, co->n_basis);
+    }
+  }
+  return h;
+}
+
 void core_params(const gp_theta* th, KernelCore* kc, CoreBasis* cb) {
   *kc = KernelCore{};
   kc->kind = GP_CORE_NONE;
@@ -777,6 +818,7 @@ gp_matrix* assemble(gp_ctx* c, const gp_dataset* ds, const gp_theta* th, int pre
   tiles.insert(tiles.end(), pieces.begin(), pieces.end());
 
   m->nugget = th->nugget;
+  m->theta_hash = theta_hash(th);
   m->nD = nD;
   m->utotal = utotal;
   m->nm = nm;

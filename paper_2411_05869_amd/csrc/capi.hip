@@ -504,4 +504,36 @@ gp_status gp_predict(gp_ctx* c, const gp_predictor* p, int64_t m, const double* 
   });
 }
 
+gp_status gp_predict_var(gp_ctx* c, const gp_matrix* K, const gp_theta* th, int64_t m, const double* xs,
+                         const gp_solve_opts* opts, double* var, gp_var_result* out) {
+  if (!c || !K) return GP_EINVAL;
+  if (out) std::memset(out, 0, sizeof(*out));
+  gp_status solve_status = GP_OK;
+  gp_status st = guarded(c, [&] {
+    validate_theta(th, K->ds->d);
+    GPS_REQUIRE(gps::theta_hash(th) == K->theta_hash, GP_EINVAL,
+                "gp_predict_var: theta differs from the hyper-parameters K was assembled with");
+    GPS_REQUIRE(m >= 0, GP_EINVAL, "gp_predict_var: m must be >= 0");
+    GPS_REQUIRE(m == 0 || (xs && var), GP_EINVAL, "gp_predict_var: NULL buffer");
+    const gp_solve_opts o = fill_opts(opts);
+    const gps::VarResult r = gps::predict_variance(c, K, th, m, xs, o.rtol, o.max_iter, var);
+    gps::sync(c);
+    if (out) {
+      out->iters = r.iters;
+      out->max_batch_iters = r.max_batch_iters;
+      out->relres = r.relres;
+    }
+    solve_status = r.st;
+  });
+  if (st != GP_OK) {
+    if (out) out->status = st;
+    return st;
+  }
+  if (out) out->status = solve_status;
+  if (solve_status != GP_OK)
+    c->err = solve_status == GP_ENOTCONV ? "gp_predict_var: a column did not reach rtol within max_iter"
+                                         : "gp_predict_var: non-positive curvature";
+  return solve_status;
+}
+
 }  // extern "C"

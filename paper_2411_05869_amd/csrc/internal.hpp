@@ -105,6 +105,7 @@ struct gp_matrix {
   int64_t n = 0, nnz = 0, max_row = 0;
   int prec = GP_FP64;
   double nugget = 0;
+  uint64_t theta_hash = 0;      // theta_hash() of the hyper-parameters assembled with
   int64_t* row_ptr = nullptr;   // n + 1
   int32_t* col = nullptr;       // nnz, binned column ids, ascending per row
   void* val = nullptr;          // nnz float or double
@@ -303,6 +304,18 @@ struct SolveResult {
 SolveResult pcg_solve(gp_ctx* c, gp_matrix* m, const double* yb, double* xb, double rtol, int max_iter, int precond);
 // alpha = K^-1 y by preconditioned MINRES (float64 products on the stored
 // values); warm: start from the x passed in, else from 0.
+// diag C_{y|z} at ntest test points (xs: ntest x d row-major, device; var:
+// ntest doubles, device), 32 test points per batch
+struct VarResult {
+  int iters = 0;
+  int max_batch_iters = 0;
+  double relres = 0;
+  gp_status st = GP_OK;
+};
+VarResult predict_variance(gp_ctx* c, const gp_matrix* m, const gp_theta* th, int64_t ntest, const double* xs,
+                           double rtol, int max_iter, double* var);
+// fingerprint of every hyper-parameter of theta (FNV-1a over their bits)
+uint64_t theta_hash(const gp_theta* th);
 SolveResult minres_solve(gp_ctx* c, gp_matrix* m, const double* yb, double* xb, bool warm, double rtol, int max_iter,
                          int precond);
 void build_block_jacobi(gp_ctx* c, gp_matrix* m);

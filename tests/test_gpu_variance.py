@@ -1,0 +1,137 @@
+"""GPU parity of the posterior variance diag C_{y|z} (Sec. 3.2) against the
+FP64 oracle.
+
+The variance is a difference prior - c^T K^-1 c that cancels where data are
+dense, so errors are measured against the prior variance C_y(x*, x*):
+|v_gpu - v_oracle| <= 1e-8 prior (float64 matrix) and 1e-5 prior (float32
+matrix values; the oracle's matrix is float64).  Cases: d = 1, 2, 3, a core
+kernel, test-point counts that are not multiples of the 32-point batch,
+points at training inputs and far from all data (variance = prior exactly),
+the mixture workload at n = 100,000 against the oracle's sparse split
+solve, and at n = 1,095,000 the properties 0 < v <= v_S for the oracle's
+variance v_S given a subset S of the data (conditioning on more data cannot
+raise the variance) and v = prior far from the data.
+"""
+import numpy as np
+import pytest
+
+from oracle import kernel, predict
+from workloads import config1, config2, config3, core_problem, uniform_problem
+from gpu_util import dev, host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2411_05869_amd import Context
+    return Context()
+
+
+def _gpu_var(ctx, p, xs, prec, **opts):
+    ds = ctx.dataset(dev(p.x), cell=p.cell)
+    K = ctx.assemble(ds, p.theta, prec)
+    v, r = ctx.predict_var(K, p.theta, dev(xs), **opts)
+    return host(v), r
+
+
+def _check(v, ref, prior, prec, what):
+    err = float(np.max(np.abs(v - ref) / prior))
+    print(f"[{what} prec={prec}] {v.size} points, max |dv| / prior {err:.2e}, "
+          f"min v/prior {float(np.min(ref / prior)):.2e}")
+    assert err <= (1e-8 if prec == 0 else 1e-5)
+
+
+@pytest.mark.parametrize("d", [1, 2, 3])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_variance_matches_oracle(ctx, d, prec):
+    p = uniform_problem(700, d, 80 + d, r0=0.12 if d > 1 else 0.02, n1=3, n2=2, bump_radius=0.25)
+    rng = np.random.default_rng(d)
+    xs = np.concatenate([rng.uniform(-0.1, 1.1, (70, d)), p.x[:5], np.full((2, d), 7.0)])
+    ref = predict.variance(xs, p.x, p.theta)
+    prior = predict.prior_variance(xs, p.theta)
+    v, r = _gpu_var(ctx, p, xs, prec)
+    print(f"[var d={d}] iters {r['iters']} (max batch {r['max_batch_iters']}) relres {r['relres']:.2e}")
+    assert r["status"] == 0 and r["relres"] <= 1e-10
+    _check(v, ref, prior, prec, f"var d={d}")
+    assert np.array_equal(v[-2:], prior[-2:])  # far from every training point: the prior, exactly
+    assert np.all(v > 0)
+
+
+@pytest.mark.parametrize("kind", [1, 2])
+def test_variance_with_core(ctx, kind):
+    p = core_problem(kind, 2, n=900, seed=70)
+    xs = np.random.default_rng(3).uniform(0, 1, (40, 2))
+    ref = predict.variance(xs, p.x, p.theta)
+    prior = predict.prior_variance(xs, p.theta)
+    for prec in (0, 1):
+        v, r = _gpu_var(ctx, p, xs, prec)
+        assert r["status"] == 0
+        _check(v, ref, prior, prec, f"var core kind={kind}")
+
+
+def test_variance_config1(ctx):
+    p = config1()
+    xs = np.random.default_rng(11).uniform(0, 1, (33, 2))
+    ref = predict.variance(xs, p.x, p.theta)
+    prior = predict.prior_variance(xs, p.theta)
+    for prec in (0, 1):
+        v, _ = _gpu_var(ctx, p, xs, prec)
+        _check(v, ref, prior, prec, "var config1")
+
+
+def test_variance_config2_split_oracle(ctx):
+    p = config2()
+    rng = np.random.default_rng(12)
+    xs = np.concatenate([p.x[rng.choice(p.n, 20, replace=False)] + rng.normal(0, 0.01, (20, 2)),
+                         rng.uniform(0, 1, (20, 2))])
+    ref = predict.variance_split(xs, p.x, p.theta)
+    prior = predict.prior_variance(xs, p.theta)
+    for prec in (0, 1):
+        v, r = _gpu_var(ctx, p, xs, prec)
+        print(f"[var config2 prec={prec}] iters {r['iters']} relres {r['relres']:.2e}")
+        assert r["status"] == 0
+        _check(v, ref, prior, prec, "var config2")
+
+
+def test_variance_config3_properties(ctx):
+    from scipy.spatial import cKDTree
+    p = config3()
+    rng = np.random.default_rng(13)
+    pts = rng.choice(p.n, 6, replace=False)
+    xs = np.concatenate([p.x[pts] + np.array([0.004, -0.003, 0.5]), np.array([[5.0, 5.0, 1000.0]])])
+    prior = predict.prior_variance(xs, p.theta)
+    v, r = _gpu_var(ctx, p, xs, 0)
+    print(f"[var config3] iters {r['iters']} relres {r['relres']:.2e} v/prior {v / prior}")
+    assert r["status"] == 0 and r["relres"] <= 1e-10
+    assert v[-1] == prior[-1]
+    assert np.all(v > 0) and np.all(v <= prior)
+    # oracle variance given the 1500 nearest training points (scaled by the Wendland radii)
+    r0 = np.asarray(p.theta.r0)
+    tree = cKDTree(p.x / r0)
+    for s in range(len(pts)):
+        _, idx = tree.query(xs[s] / r0, k=1500)
+        vs = predict.variance(xs[s:s + 1], p.x[np.sort(idx)], p.theta)[0]
+        print(f"[var config3] point {s}: gpu {v[s]:.6e} <= subset oracle {vs:.6e}")
+        assert v[s] <= vs * (1 + 1e-9) + 1e-12 * prior[s]
+
+
+def test_theta_mismatch_is_einval(ctx):
+    from paper_2411_05869_amd import GPError
+    p = uniform_problem(300, 2, 3)
+    ds = ctx.dataset(dev(p.x), cell=p.cell)
+    K = ctx.assemble(ds, p.theta, 0)
+    th = p.theta.copy()
+    th.nugget = th.nugget * 1.0000001
+    with pytest.raises(GPError) as e:
+        ctx.predict_var(K, th, dev(np.zeros((3, 2))))
+    assert e.value.status == 1
+
+
+def test_empty_request(ctx):
+    import torch
+    p = uniform_problem(300, 2, 3)
+    ds = ctx.dataset(dev(p.x), cell=p.cell)
+    K = ctx.assemble(ds, p.theta, 0)
+    v, r = ctx.predict_var(K, p.theta, torch.zeros((0, 2), dtype=torch.float64, device="cuda"))
+    assert v.numel() == 0 and r["iters"] == 0

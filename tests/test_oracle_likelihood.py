@@ -182,3 +182,11 @@ def test_variance_far_from_data_is_the_prior():
     v = predict.variance(xs, p.x, p.theta)
     assert np.array_equal(v, predict.prior_variance(xs, p.theta))
     assert np.array_equal(v, np.full(2, p.theta.s0))
+
+
+def test_variance_split_route_matches_dense():
+    from workloads import uniform_problem
+    p = uniform_problem(900, 2, 15, r0=0.07, n1=3, n2=2, bump_radius=0.25)
+    xs = np.random.default_rng(2).uniform(-0.1, 1.1, (40, 2))
+    assert np.allclose(predict.variance_split(xs, p.x, p.theta), predict.variance(xs, p.x, p.theta),
+                       rtol=1e-10, atol=1e-13)
