@@ -178,6 +178,36 @@ def serving_legs(args, ctx, ds, p, alpha):
     return res
 
 
+def variance_leg(ctx, ds, p, xs, npts=64):
+    """Posterior variance at npts of the prediction points (batches of 32):
+    wall time per point, iterations and the sparse product's share."""
+    import torch
+
+    from paper_2411_05869_amd import FP64, MIXED
+    res = {}
+    for name, prec in (("mixed", MIXED), ("fp64", FP64)):
+        K = ctx.assemble(ds, p.theta, prec)
+        pts = xs[:npts].contiguous()
+        ctx.predict_var(K, p.theta, pts[:32].contiguous())  # warm the work space
+        torch.cuda.synchronize()
+        ctx.profile(True)
+        t0 = time.perf_counter()
+        v, r = ctx.predict_var(K, p.theta, pts)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        prof = ctx.profile_read()
+        ctx.profile(False)
+        K.close()
+        sp = prof.get("spmm", (0, 0.0))
+        res[name] = dict(points=npts, seconds=round(dt, 4), points_per_s=round(npts / dt, 2),
+                         iters=r["iters"], max_batch_iters=r["max_batch_iters"], relres=r["relres"],
+                         spmm_ms=round(sp[1], 2), spmm_avg_us=round(1e3 * sp[1] / max(sp[0], 1), 1),
+                         vector_ms=round(prof.get("var_vector_ops", (0, 0.0))[1], 2),
+                         mean_var=float(v.mean()))
+        log(f"variance {name}: {res[name]}")
+    return res
+
+
 def core_legs(ctx, ds, p, y, xs, opts, reps=2):
     """Same space-time workload with a core kernel (stationary Matern nu = 5/2,
     then the nonstationary core): assemble wall time, one mixed-form step
@@ -233,6 +263,8 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=128)
     ap.add_argument("--no-core", action="store_true")
+    ap.add_argument("--no-var", action="store_true")
+    ap.add_argument("--var-points", type=int, default=64)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="copy 1 GiB device-to-device first (reference dispatch for HBM counters)")
     ap.add_argument("--summarize-pmc", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "COMMAND"),
@@ -374,6 +406,8 @@ def main():
         out["serving"] = serving_legs(args, ctx, ds, p, alpha)
     if not args.no_core:
         out["core"] = core_legs(ctx, ds, p, y, xs, opts)
+    if not args.no_var:
+        out["variance"] = variance_leg(ctx, ds, p, xs, args.var_points)
     if not args.no_cpu:
         log("cpu baseline (oracle on a bounded sample) ...")
         cb, (sel, snnz) = cpu_baseline(p)

@@ -195,12 +195,35 @@ __device__ __forceinline__ void col_partials(const double (&v)[NV], double* __re
   }
 }
 
-// sums the partials of value v for column col over nb blocks in block order
+// Column totals of the partials of nb blocks, in a fixed order: thread
+// (chunk, col) = (threadIdx.x / 32, threadIdx.x % 32) of a kFinThreads-thread
+// block adds the partials of its chunk of consecutive blocks, then thread col
+// adds the chunks in order.  tot[v] is valid in threads 0..31 (column
+// threadIdx.x); every thread of the block must call it.
+constexpr int kFinThreads = 1024;
+constexpr int kChunks = kFinThreads / kC;
+
 template <int NV>
-__device__ __forceinline__ double col_total(const double* __restrict__ part, int nb, int v, int col) {
-  double s = 0.0;
-  for (int b = 0; b < nb; ++b) s += part[(static_cast<int64_t>(b) * NV + v) * kC + col];
-  return s;
+__device__ __forceinline__ void col_totals(const double* __restrict__ part, int nb, double (&tot)[NV]) {
+  __shared__ double sh[NV][kChunks][kC];
+  const int col = threadIdx.x % kC, ch = threadIdx.x / kC;
+  const int per = (nb + kChunks - 1) / kChunks;
+  const int b0 = min(nb, ch * per), b1 = min(nb, b0 + per);
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    double s = 0.0;
+    for (int b = b0; b < b1; ++b) s += part[(static_cast<int64_t>(b) * NV + v) * kC + col];
+    sh[v][ch][col] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < kC) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      double s = 0.0;
+      for (int c = 0; c < kChunks; ++c) s += sh[v][c][col];
+      tot[v] = s;
+    }
+  }
 }
 
 #define ROW_LOOP(n)                                                                                 \
@@ -230,12 +253,13 @@ __global__ void __launch_bounds__(kThreads) k_bcg_start(int64_t n, const double*
 
 // mode 0: first start (|c|^2 = r.r, a column with c = 0 is never active);
 // mode 1: restart from the true residual (active columns stay active)
-__global__ void __launch_bounds__(kThreads) k_bcg_start_fin(const double* __restrict__ part, int nb,
-                                                            BcgScalars* __restrict__ S, double tol2, int mode) {
+__global__ void __launch_bounds__(kFinThreads) k_bcg_start_fin(const double* __restrict__ part, int nb,
+                                                               BcgScalars* __restrict__ S, double tol2, int mode) {
+  double t[2];
+  col_totals<2>(part, nb, t);
   if (threadIdx.x >= kC) return;
   const int col = threadIdx.x;
-  const double rz = col_total<2>(part, nb, 0, col);
-  const double rr = col_total<2>(part, nb, 1, col);
+  const double rz = t[0], rr = t[1];
   S->rz[col] = rz;
   S->rr[col] = rr;
   if (mode == 0) {
@@ -258,11 +282,13 @@ __global__ void __launch_bounds__(kThreads) k_bcg_pq(int64_t n, const double* __
   col_partials<1>(v, part);
 }
 
-__global__ void __launch_bounds__(kThreads) k_bcg_alpha(const double* __restrict__ part, int nb,
-                                                        BcgScalars* __restrict__ S) {
+__global__ void __launch_bounds__(kFinThreads) k_bcg_alpha(const double* __restrict__ part, int nb,
+                                                           BcgScalars* __restrict__ S) {
+  double t[1];
+  col_totals<1>(part, nb, t);
   if (threadIdx.x >= kC) return;
   const int col = threadIdx.x;
-  const double pq = col_total<1>(part, nb, 0, col);
+  const double pq = t[0];
   S->pq[col] = pq;
   double a = 0.0;
   if (S->active[col]) {
@@ -298,12 +324,13 @@ __global__ void __launch_bounds__(kThreads) k_bcg_update(int64_t n, const BcgSca
   col_partials<2>(v, part);
 }
 
-__global__ void __launch_bounds__(kThreads) k_bcg_beta(const double* __restrict__ part, int nb,
-                                                       BcgScalars* __restrict__ S, double tol2) {
+__global__ void __launch_bounds__(kFinThreads) k_bcg_beta(const double* __restrict__ part, int nb,
+                                                          BcgScalars* __restrict__ S, double tol2) {
+  double t[2];
+  col_totals<2>(part, nb, t);
   if (threadIdx.x >= kC) return;
   const int col = threadIdx.x;
-  const double rz = col_total<2>(part, nb, 0, col);
-  const double rr = col_total<2>(part, nb, 1, col);
+  const double rz = t[0], rr = t[1];
   const bool act = S->active[col] != 0;
   S->beta[col] = act ? rz / S->rz[col] : 0.0;
   S->rz[col] = rz;
@@ -339,13 +366,14 @@ __global__ void __launch_bounds__(kThreads) k_bcg_final(int64_t n, const double*
 }
 
 // true residual per column into S->rr; v_s = prior_s - c_s . w_s for s < nbatch
-__global__ void __launch_bounds__(kThreads) k_bcg_var(const double* __restrict__ part, int nb,
-                                                      BcgScalars* __restrict__ S, const double* __restrict__ prior,
-                                                      int nbatch, double* __restrict__ var) {
+__global__ void __launch_bounds__(kFinThreads) k_bcg_var(const double* __restrict__ part, int nb,
+                                                         BcgScalars* __restrict__ S, const double* __restrict__ prior,
+                                                         int nbatch, double* __restrict__ var) {
+  double t[2];
+  col_totals<2>(part, nb, t);
   if (threadIdx.x >= kC) return;
   const int col = threadIdx.x;
-  const double rr = col_total<2>(part, nb, 0, col);
-  const double cw = col_total<2>(part, nb, 1, col);
+  const double rr = t[0], cw = t[1];
   S->rr[col] = rr;
   if (col < nbatch) var[col] = prior[col] - cw;
 }
@@ -422,7 +450,7 @@ VarResult predict_variance(gp_ctx* c, const gp_matrix* m, const gp_theta* th, in
   double* prior = static_cast<double*>(workspace(c, 118, sizeof(double) * kC));
   BcgScalars* hs = static_cast<BcgScalars*>(pinned(c, sizeof(BcgScalars)));
   const unsigned nbv = static_cast<unsigned>(std::min<int64_t>(kVBlocks, (n + kRowsPer - 1) / kRowsPer));
-  const dim3 B(kThreads), G(nbv);
+  const dim3 B(kThreads), G(nbv), FB(kFinThreads);
   const double tol2 = rtol * rtol;
   auto read = [&]() {
     GPS_HIP(hipMemcpyAsync(hs, S, sizeof(BcgScalars), hipMemcpyDeviceToHost, c->stream));
@@ -446,7 +474,7 @@ VarResult predict_variance(gp_ctx* c, const gp_matrix* m, const gp_theta* th, in
     }
     hipLaunchKernelGGL(k_zero, dim3(grid_for(n * kC, kThreads)), B, 0, c->stream, n * kC, W);
     hipLaunchKernelGGL(k_bcg_start, G, B, 0, c->stream, n, X, nullptr, m->diag, R, Z, P, part);
-    hipLaunchKernelGGL(k_bcg_start_fin, dim3(1), B, 0, c->stream, part, static_cast<int>(nbv), S, tol2, 0);
+    hipLaunchKernelGGL(k_bcg_start_fin, dim3(1), FB, 0, c->stream, part, static_cast<int>(nbv), S, tol2, 0);
     check_launch("variance start");
     BcgScalars hsc = read();
     int it = 0, refresh = 0;
@@ -461,7 +489,7 @@ VarResult predict_variance(gp_ctx* c, const gp_matrix* m, const gp_theta* th, in
         if (refresh >= kMaxRefresh) break;
         spmm<double>(c, m, kC, kC, W, Q, nullptr);
         hipLaunchKernelGGL(k_bcg_start, G, B, 0, c->stream, n, X, Q, m->diag, R, Z, P, part);
-        hipLaunchKernelGGL(k_bcg_start_fin, dim3(1), B, 0, c->stream, part, static_cast<int>(nbv), S, tol2, 1);
+        hipLaunchKernelGGL(k_bcg_start_fin, dim3(1), FB, 0, c->stream, part, static_cast<int>(nbv), S, tol2, 1);
         check_launch("variance restart");
         ++refresh;
         hsc = read();
@@ -473,9 +501,9 @@ VarResult predict_variance(gp_ctx* c, const gp_matrix* m, const gp_theta* th, in
         spmm<double>(c, m, kC, kC, P, Q, nullptr);
         ProfScope ps(c, "var_vector_ops");
         hipLaunchKernelGGL(k_bcg_pq, G, B, 0, c->stream, n, P, Q, part);
-        hipLaunchKernelGGL(k_bcg_alpha, dim3(1), B, 0, c->stream, part, static_cast<int>(nbv), S);
+        hipLaunchKernelGGL(k_bcg_alpha, dim3(1), FB, 0, c->stream, part, static_cast<int>(nbv), S);
         hipLaunchKernelGGL(k_bcg_update, G, B, 0, c->stream, n, S, P, Q, m->diag, W, R, Z, part);
-        hipLaunchKernelGGL(k_bcg_beta, dim3(1), B, 0, c->stream, part, static_cast<int>(nbv), S, tol2);
+        hipLaunchKernelGGL(k_bcg_beta, dim3(1), FB, 0, c->stream, part, static_cast<int>(nbv), S, tol2);
         hipLaunchKernelGGL(k_bcg_dir, G, B, 0, c->stream, n, S, Z, P);
         check_launch("variance step");
       }
@@ -485,7 +513,7 @@ VarResult predict_variance(gp_ctx* c, const gp_matrix* m, const gp_theta* th, in
     // true residual and the variances of this batch
     spmm<double>(c, m, kC, kC, W, Q, nullptr);
     hipLaunchKernelGGL(k_bcg_final, G, B, 0, c->stream, n, X, Q, W, part);
-    hipLaunchKernelGGL(k_bcg_var, dim3(1), B, 0, c->stream, part, static_cast<int>(nbv), S, prior, nb, var + m0);
+    hipLaunchKernelGGL(k_bcg_var, dim3(1), FB, 0, c->stream, part, static_cast<int>(nbv), S, prior, nb, var + m0);
     check_launch("variance final");
     hsc = read();
     res.iters += it;
