@@ -266,6 +266,57 @@ def spacetime_core(kind: int, seed: int = 33, nu2: int = 5, n_basis: int = 8) ->
                 np.array([0.25, 0.25, 60.0]), phi_s, phi_S)
 
 
+# ------------------------------------------------------------------ MCMC ---
+
+@dataclasses.dataclass
+class McmcPriors:
+    """Prior bounds and initial proposal scales for the chain of Appendix C.
+
+    beta ~ N(0, beta_var I); s0 ~ U(0, s0_max); r0_k ~ U(0, r0_max_k);
+    nugget ~ U(0, nugget_max); h_ijk ~ U(lo_k, hi_k); r_ijk ~ U(0, r_max_k);
+    a_ij ~ Bernoulli(pi_ij), pi_ij ~ U(0, 1); with a Matern core also
+    sigma0 ~ U(0, sigma0_max) and ell_k ~ U(0, ell_max_k).  sd_* are the
+    initial random-walk standard deviations of each coordinate.
+    """
+
+    lo: np.ndarray
+    hi: np.ndarray
+    r0_max: np.ndarray
+    r_max: np.ndarray
+    ell_max: np.ndarray = dataclasses.field(default_factory=lambda: np.full(3, 1e5))
+    beta_var: float = 100.0 ** 2
+    s0_max: float = 1e5
+    nugget_max: float = 1e5
+    sigma0_max: float = 1e5
+    sd_beta: float = 0.05
+    sd_s0: float = 0.05
+    sd_r0: float = 0.002
+    sd_nugget: float = 0.001
+    sd_core: float = 0.02
+    sd_h: float = 0.01
+    sd_r: float = 0.005
+
+
+def mcmc_draws(seed: int, n_iter: int, p: int, d2: int, d3: int, nb: int) -> list:
+    """Random numbers of n_iter chain iterations, drawn in a fixed order per
+    iteration: z1 (p normals, block 1), u1; z2 (d2 normals, block 2), u2;
+    z3 (d3 normals, block 3), u3; ua (nb uniforms, amplitude proposals), u4;
+    ub (nb uniforms, Gibbs draws of pi)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n_iter):
+        out.append(dict(z1=rng.standard_normal(p), u1=rng.random(), z2=rng.standard_normal(d2), u2=rng.random(),
+                        z3=rng.standard_normal(d3), u3=rng.random(), ua=rng.random(nb), u4=rng.random(),
+                        ub=rng.random(nb)))
+    return out
+
+
+def mean_covariates(x: np.ndarray) -> np.ndarray:
+    """Covariates of a linear prior mean: an intercept and the coordinates,
+    as a (1 + d, n) array (row k = covariate k)."""
+    return np.vstack([np.ones(x.shape[0]), np.asarray(x, np.float64).T])
+
+
 # ---------------------------------------------------------------- serving ---
 
 def config4_pool(n_datasets: int = 16, base_seed: int = 4000):
