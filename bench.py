@@ -208,6 +208,41 @@ def variance_leg(ctx, ds, p, xs, npts=64):
     return res
 
 
+def mcmc_leg(ctx, n_iter=8):
+    """MCMC training (four Metropolis-Hastings blocks and the Gibbs step per
+    iteration) on the 100k-point mixture workload, mixed form with SLQ."""
+    import numpy as np
+    import torch
+
+    from paper_2411_05869_amd.mcmc import Chain
+    from workloads import McmcPriors, config2, mcmc_draws, mean_covariates
+    p = config2()
+    th = p.theta.copy()
+    th.a = np.ones_like(th.a)
+    W = mean_covariates(p.x)
+    z = np.array([0.2, 0.5, -0.4]) @ W + p.y
+    dev = torch.device("cuda", 0)
+    ds = ctx.dataset(torch.tensor(p.x, device=dev), cell=p.cell)
+    pri = McmcPriors(lo=np.zeros(3), hi=np.ones(3), r0_max=np.full(3, 0.5), r_max=np.full(3, 0.2))
+    nb = th.a.size
+    draws = mcmc_draws(19, n_iter + 1, W.shape[0], 4, 2 * nb * 2, nb)
+    ch = Chain(ctx, ds, torch.tensor(z, device=dev), torch.tensor(W, device=dev), th, np.zeros(W.shape[0]),
+               np.full(th.a.shape, 0.5), pri)
+    ch.step(draws[0])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    recs = [ch.step(dr) for dr in draws[1:]]
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ch.close()
+    acc = np.sum([r["acc"] for r in recs], axis=0).tolist()
+    res = dict(workload=f"{p.name}: n={p.n}, 3 mean coefficients, 16 bumps (64 centre/radius coordinates)",
+               iterations=n_iter, seconds=round(dt, 3), iters_per_s=round(n_iter / dt, 3), accepted_per_block=acc,
+               loglik_first=recs[0]["loglik"], loglik_last=recs[-1]["loglik"])
+    log(f"mcmc: {res}")
+    return res
+
+
 def core_legs(ctx, ds, p, y, xs, opts, reps=2):
     """Same space-time workload with a core kernel (stationary Matern nu = 5/2,
     then the nonstationary core): assemble wall time, one mixed-form step
@@ -264,6 +299,7 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=128)
     ap.add_argument("--no-core", action="store_true")
     ap.add_argument("--no-var", action="store_true")
+    ap.add_argument("--no-mcmc", action="store_true")
     ap.add_argument("--var-points", type=int, default=64)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="copy 1 GiB device-to-device first (reference dispatch for HBM counters)")
@@ -408,6 +444,8 @@ def main():
         out["core"] = core_legs(ctx, ds, p, y, xs, opts)
     if not args.no_var:
         out["variance"] = variance_leg(ctx, ds, p, xs, args.var_points)
+    if not args.no_mcmc:
+        out["mcmc"] = mcmc_leg(ctx)
     if not args.no_cpu:
         log("cpu baseline (oracle on a bounded sample) ...")
         cb, (sel, snnz) = cpu_baseline(p)

@@ -304,6 +304,16 @@ GP_API gp_status gp_predictor_destroy(gp_ctx* ctx, gp_predictor* p);
 GP_API gp_status gp_predict(gp_ctx* ctx, const gp_predictor* p, int64_t m, const double* xstar_dev,
                      gp_precision prec, double* mean_dev);
 
+/* gp_mean_residual: y = z - W beta, the residual of the prior mean
+ * E[z] = W beta of Sec. 3.1 (Eq. Zmarg), the y_dev that gp_loglik and gp_solve
+ * take.  W_dev: n x p covariates stored column by column (W[k * n + i] is
+ * covariate k of point i, ORIGINAL point order), device; beta: p float64 in
+ * host memory, copied by the call; z_dev, y_dev: n float64, device (y may
+ * alias z).  p = 0 copies z.
+ * Errors: GP_EINVAL (n < 1, p < 0, NULL buffers, non-finite beta), GP_EDEVICE. */
+GP_API gp_status gp_mean_residual(gp_ctx* ctx, int64_t n, int32_t p, const double* W_dev, const double* beta,
+                           const double* z_dev, double* y_dev);
+
 /* gp_predict_var: posterior variance of the latent process at m test points
  * (Sec. 3.2: the diagonal of C_{y|z} = C_y - C_{y,z} C_z^{-1} C_{z,y}),
  *   var(x*) = C_y(x*, x*) - c^T K^{-1} c,   c = C_{z,y}(., x*)  (no nugget),

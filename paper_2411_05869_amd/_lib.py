@@ -76,7 +76,7 @@ EXPORTS = [
     "gp_dataset_create", "gp_dataset_destroy", "gp_dataset_info", "gp_dataset_permutation",
     "gp_assemble", "gp_matrix_destroy", "gp_matrix_info", "gp_matrix_export_csr", "gp_matvec",
     "gp_solve_opts_default", "gp_loglik", "gp_solve", "gp_predictor_create", "gp_predictor_destroy",
-    "gp_predict", "gp_predict_var", "gp_profile_enable", "gp_profile_read",
+    "gp_predict", "gp_predict_var", "gp_mean_residual", "gp_profile_enable", "gp_profile_read",
 ]
 
 
@@ -117,6 +117,7 @@ def lib():
     L.gp_predictor_create.argtypes = [P, P, C.POINTER(CTheta), P, C.POINTER(P)]
     L.gp_predictor_destroy.argtypes = [P, P]
     L.gp_predict.argtypes = [P, P, I64, P, C.c_int, P]
+    L.gp_mean_residual.argtypes = [P, I64, I32, P, C.POINTER(D), P, P]
     L.gp_predict_var.argtypes = [P, P, C.POINTER(CTheta), I64, P, C.POINTER(CSolveOpts), P, C.POINTER(CVarResult)]
     L.gp_profile_enable.argtypes = [P, I32]
     L.gp_profile_read.argtypes = [P, I32, C.POINTER(CProfileEntry), C.POINTER(I32)]
@@ -366,6 +367,23 @@ class Context:
             out = torch.empty(m, dtype=torch.float64, device=xs.device)
         self._check(self._L.gp_predict(self._h, pred._h, m, C.c_void_p(_ptr(xs)), int(precision),
                                        C.c_void_p(_ptr(out))), "gp_predict")
+        return out
+
+    def mean_residual(self, W, beta, z, out=None):
+        """y = z - W beta; W: (p, n) device float64 (row k = covariate k, the
+        column-major n x p matrix of the C call), beta: p host values."""
+        torch = _torch()
+        _check_dev_tensor(z, torch.float64, name="z")
+        n = int(z.shape[0])
+        b = np.ascontiguousarray(np.asarray(beta, np.float64).reshape(-1))
+        p = int(b.size)
+        if p:
+            _check_dev_tensor(W, torch.float64, (p, n), "W")
+        if out is None:
+            out = torch.empty_like(z)
+        self._check(self._L.gp_mean_residual(self._h, n, p, C.c_void_p(_ptr(W)) if p else None,
+                                             b.ctypes.data_as(C.POINTER(C.c_double)), C.c_void_p(_ptr(z)),
+                                             C.c_void_p(_ptr(out))), "gp_mean_residual")
         return out
 
     def predict_var(self, K: "Matrix", theta, xs, out=None, raise_on_error: bool = True, **opts):

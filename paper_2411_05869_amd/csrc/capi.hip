@@ -504,6 +504,19 @@ gp_status gp_predict(gp_ctx* c, const gp_predictor* p, int64_t m, const double* 
   });
 }
 
+gp_status gp_mean_residual(gp_ctx* c, int64_t n, int32_t p, const double* W, const double* beta, const double* z,
+                           double* y) {
+  if (!c) return GP_EINVAL;
+  return guarded(c, [&] {
+    GPS_REQUIRE(n >= 1 && p >= 0, GP_EINVAL, "gp_mean_residual: n must be >= 1 and p >= 0");
+    GPS_REQUIRE(z && y && (p == 0 || (W && beta)), GP_EINVAL, "gp_mean_residual: NULL buffer");
+    for (int k = 0; k < p; ++k)
+      GPS_REQUIRE(std::isfinite(beta[k]), GP_EINVAL, "gp_mean_residual: beta must be finite");
+    gps::mean_residual(c, n, p, W, beta, z, y);
+    gps::sync(c);
+  });
+}
+
 gp_status gp_predict_var(gp_ctx* c, const gp_matrix* K, const gp_theta* th, int64_t m, const double* xs,
                          const gp_solve_opts* opts, double* var, gp_var_result* out) {
   if (!c || !K) return GP_EINVAL;

@@ -314,6 +314,9 @@ struct VarResult {
 };
 VarResult predict_variance(gp_ctx* c, const gp_matrix* m, const gp_theta* th, int64_t ntest, const double* xs,
                            double rtol, int max_iter, double* var);
+// y = z - W beta (W: n x p column-major, device; beta: p values, host)
+void mean_residual(gp_ctx* c, int64_t n, int p, const double* W, const double* beta_host, const double* z,
+                   double* y);
 // fingerprint of every hyper-parameter of theta (FNV-1a over their bits)
 uint64_t theta_hash(const gp_theta* th);
 SolveResult minres_solve(gp_ctx* c, gp_matrix* m, const double* yb, double* xb, bool warm, double rtol, int max_iter,

@@ -314,7 +314,7 @@ def mcmc_draws(seed: int, n_iter: int, p: int, d2: int, d3: int, nb: int) -> lis
 def mean_covariates(x: np.ndarray) -> np.ndarray:
     """Covariates of a linear prior mean: an intercept and the coordinates,
     as a (1 + d, n) array (row k = covariate k)."""
-    return np.vstack([np.ones(x.shape[0]), np.asarray(x, np.float64).T])
+    return np.ascontiguousarray(np.vstack([np.ones(x.shape[0]), np.asarray(x, np.float64).T]))
 
 
 # ---------------------------------------------------------------- serving ---
