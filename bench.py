@@ -44,9 +44,11 @@ def spmm_bytes(n, nnz, vbytes, k, xbytes):
 
 
 TRAFFIC_PROFILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
-                               "traffic_spmv_f32_spacetime_n1095000.md")
+                               "traffic_spmv_f32val_f64_spacetime_n1095000.md")
 SPMV_SOURCE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2411_05869_amd", "csrc", "spmv.hip")
-SPMV_F32_KERNELS = ("k_group_spmv<float, float, float, float>", "k_spmv<float, float, float, float>")
+# the conjugate-gradient product of the mixed form: float32 values, float64 vectors
+SPMV_KERNELS = ("k_group_spmv<float, double, double, double>", "k_spmv<float, double, double, double>")
+SPMV_PROFILE_NAME = "spmv_f32val_f64"
 CALIB_BYTES = 1 << 30
 
 
@@ -57,7 +59,7 @@ def source_sha256(path):
 
 
 def stored_traffic():
-    """HBM bytes per FP32 SpMV (both kernels) from the committed counter summary,
+    """HBM bytes per mixed-form SpMV (both kernels) from the committed counter summary,
     or None when it is missing or the SpMV source changed since it was taken."""
     try:
         fields = {}
@@ -73,7 +75,7 @@ def stored_traffic():
 
 
 def summarize_pmc(fetch_dir, write_dir, command):
-    """Per-dispatch FETCH_SIZE / WRITE_SIZE (KiB) of the FP32 SpMV kernels, scaled
+    """Per-dispatch FETCH_SIZE / WRITE_SIZE (KiB) of the mixed-form SpMV kernels, scaled
     by what the same counters read for a copy of CALIB_BYTES bytes."""
     import csv
     import glob
@@ -83,7 +85,7 @@ def summarize_pmc(fetch_dir, write_dir, command):
         rows = [r for r in csv.DictReader(open(f[0])) if r["Counter_Name"] == counter]
         copy = max(float(r["Counter_Value"]) for r in rows if "copy" in r["Kernel_Name"].lower())
         per = {}
-        for k in SPMV_F32_KERNELS:
+        for k in SPMV_KERNELS:
             v = [float(r["Counter_Value"]) for r in rows if k in r["Kernel_Name"]]
             per[k] = (sum(v) / len(v), len(v))
         return copy, per
@@ -93,13 +95,14 @@ def summarize_pmc(fetch_dir, write_dir, command):
     sf, sw = CALIB_BYTES / (cf * 1024.0), CALIB_BYTES / (cw * 1024.0)
     fetch = sum(v for v, _ in pf.values()) * 1024.0 * sf
     write = sum(v for v, _ in pw.values()) * 1024.0 * sw
-    lines = ["# HBM traffic of the FP32 SpMV (conjugate-gradient product) on the space-time workload, n = 1,095,000",
+    lines = ["# HBM traffic of the mixed-form SpMV (float32 values, float64 vectors; the conjugate-gradient "
+             "product) on the space-time workload, n = 1,095,000",
              "", "Two counter runs of the same command (run from /tmp with TMPDIR=/tmp on one MI355X), "
              "one with `--pmc FETCH_SIZE`, one with `--pmc WRITE_SIZE`:", "", "```", command, "```", "",
              f"Calibration: a device-to-device copy of {CALIB_BYTES} bytes (bench.py --copy-calibration) read "
              f"FETCH_SIZE {cf:.0f} KiB and WRITE_SIZE {cw:.0f} KiB; scale factors {sf:.4f} (fetch), {sw:.4f} (write).",
              "", "| kernel | dispatches | FETCH_SIZE KiB/dispatch | WRITE_SIZE KiB/dispatch |", "|---|---:|---:|---:|"]
-    for k in SPMV_F32_KERNELS:
+    for k in SPMV_KERNELS:
         lines.append(f"| `{k}` | {pf[k][1]} | {pf[k][0]:.0f} | {pw[k][0]:.0f} |")
     lines += ["", "Figures read by bench.py (traffic of one SpMV = both kernels, scaled):", "",
               f"- fetch_bytes_per_launch: {int(fetch)}", f"- write_bytes_per_launch: {int(write)}",
@@ -415,7 +418,7 @@ def main():
     achieved = b / avg_s / 1e9
     roof = dict(bound="hbm", kernel=name, achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=round(achieved / HBM_PEAK_GBS, 4),
-                traffic=stored_traffic() if name == "spmv_f32" else None, avg_us=round(avg_s * 1e6, 2),
+                traffic=stored_traffic() if name == SPMV_PROFILE_NAME else None, avg_us=round(avg_s * 1e6, 2),
                 launches=cnt, bytes_per_launch=int(b))
 
     out = dict(metric=METRIC, value=round(evals_m, 4), unit="loglik evals/s", n_gpus=1, steps=args.steps,

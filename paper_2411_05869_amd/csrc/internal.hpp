@@ -278,8 +278,6 @@ void export_csr(gp_ctx* c, const gp_matrix* m, int64_t* row_ptr, int32_t* col, d
 // SpMV / SpMM in binned order.
 // y = K x (float64 x and y; float32 or float64 values; float64 accumulation)
 void spmv_f64(gp_ctx* c, const gp_matrix* m, const double* x, double* y);
-// y = K x entirely in float32 (mixed-precision inner products)
-void spmv_f32(gp_ctx* c, const gp_matrix* m, const float* x, float* y);
 // Y = S K S X D for k columns, X/Y n x ld row-major (S = diag(scale) or identity
 // if null; D = diag(colscale), a device array of k values, or identity if null)
 template <typename T>
@@ -300,7 +298,8 @@ struct SolveResult {
   double quad = 0;
   gp_status st = GP_OK;
 };
-// alpha = K^-1 y (binned order); preconditioned CG, float64 or float32-product form.
+// alpha = K^-1 y (binned order); preconditioned CG with float64 vectors and
+// products on the stored values (float32 for a GP_MIXED matrix).
 SolveResult pcg_solve(gp_ctx* c, gp_matrix* m, const double* yb, double* xb, double rtol, int max_iter, int precond);
 // alpha = K^-1 y by preconditioned MINRES (float64 products on the stored
 // values); warm: start from the x passed in, else from 0.

@@ -134,12 +134,11 @@ __global__ void __launch_bounds__(kThreads) k_pcg_step(int64_t n, Precond M, CgS
 }
 
 // New direction after a step: every block adds the step's nb partials (same
-// fixed order) into rz, rr and beta = rz / rz_old, then p = z + beta p (and its
-// float32 copy).  Block 0 records rz, rr, beta and flags non-finite values.
+// fixed order) into rz, rr and beta = rz / rz_old, then p = z + beta p.  Block
+// 0 records rz, rr, beta and flags non-finite values.
 __global__ void __launch_bounds__(kThreads) k_pcg_direction(int64_t n, CgScalars* __restrict__ s,
                                                             const double* __restrict__ part, int nb,
-                                                            const double* __restrict__ z, double* __restrict__ p,
-                                                            float* __restrict__ p32) {
+                                                            const double* __restrict__ z, double* __restrict__ p) {
   double sums[2];
   reduce_partials<2>(part, nb, sums);
   const double beta = sums[0] / s->rz_old;
@@ -151,9 +150,7 @@ __global__ void __launch_bounds__(kThreads) k_pcg_direction(int64_t n, CgScalars
   }
   for (int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; i < n;
        i += static_cast<int64_t>(gridDim.x) * kThreads) {
-    const double pi = z[i] + beta * p[i];
-    p[i] = pi;
-    if (p32) p32[i] = static_cast<float>(pi);
+    p[i] = z[i] + beta * p[i];
   }
 }
 
@@ -227,15 +224,11 @@ __global__ void __launch_bounds__(kThreads) k_beta_fin(const double* __restrict_
 
 // p = z + beta p (beta = 0 at the start)
 __global__ void __launch_bounds__(kThreads) k_pcg_pupdate(int64_t n, const CgScalars* __restrict__ s,
-                                                          const double* __restrict__ z, double* __restrict__ p,
-                                                          float* __restrict__ p32) {
+                                                          const double* __restrict__ z, double* __restrict__ p) {
   const double beta = s->beta;
   for (int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; i < n;
-       i += static_cast<int64_t>(gridDim.x) * kThreads) {
-    const double pi = beta == 0.0 ? z[i] : z[i] + beta * p[i];
-    p[i] = pi;
-    if (p32) p32[i] = static_cast<float>(pi);
-  }
+       i += static_cast<int64_t>(gridDim.x) * kThreads)
+    p[i] = beta == 0.0 ? z[i] : z[i] + beta * p[i];
 }
 
 // r = y - Kx (Kx given)
@@ -558,7 +551,6 @@ static double logsum_f64(gp_ctx* c, const double* a, int64_t n) {
 
 SolveResult pcg_solve(gp_ctx* c, gp_matrix* m, const double* y, double* x, double rtol, int max_iter, int precond) {
   const int64_t n = m->n;
-  const bool mixed = m->prec == GP_MIXED;
   if (precond == GP_PRECOND_BLOCK_JACOBI) build_block_jacobi(c, m);
   Precond M{m->diag, nullptr, nullptr, nullptr, nullptr};
   if (precond == GP_PRECOND_BLOCK_JACOBI) {
@@ -573,8 +565,6 @@ SolveResult pcg_solve(gp_ctx* c, gp_matrix* m, const double* y, double* x, doubl
   double* z = static_cast<double*>(workspace(c, 21, sizeof(double) * n));
   double* p = static_cast<double*>(workspace(c, 22, sizeof(double) * n));
   double* q = static_cast<double*>(workspace(c, 23, sizeof(double) * n));
-  float* p32 = mixed ? static_cast<float*>(workspace(c, 24, sizeof(float) * n)) : nullptr;
-  float* q32 = mixed ? static_cast<float*>(workspace(c, 25, sizeof(float) * n)) : nullptr;
   double* part = static_cast<double*>(workspace(c, 26, sizeof(double) * 4 * kRedBlocks));
   const unsigned nbp = grid_for(n, kThreads);
   const unsigned nbs = grid_for(n, kThreads * kStepRows);
@@ -606,7 +596,7 @@ SolveResult pcg_solve(gp_ctx* c, gp_matrix* m, const double* y, double* x, doubl
     hipLaunchKernelGGL(k_yy_fin, dim3(1), B, 0, c->stream, part, kRedBlocks, s);
   }
   apply_precond(2);
-  hipLaunchKernelGGL(k_pcg_pupdate, G, B, 0, c->stream, n, s, z, p, p32);
+  hipLaunchKernelGGL(k_pcg_pupdate, G, B, 0, c->stream, n, s, z, p);
   check_launch("pcg init");
   CgScalars sc = read();
   SolveResult res;
@@ -625,24 +615,16 @@ SolveResult pcg_solve(gp_ctx* c, gp_matrix* m, const double* y, double* x, doubl
   while (it < max_iter && !converged) {
     const int steps = std::min(kCheckEvery, max_iter - it);
     for (int t = 0; t < steps; ++t) {
-      if (mixed)
-        spmv_f32(c, m, p32, q32);
-      else
-        spmv_f64(c, m, p, q);
+      // float64 vectors; a GP_MIXED matrix contributes its float32 values
+      spmv_f64(c, m, p, q);
       {
         ProfScope ps(c, "pcg_vector_ops");
-        if (mixed) {
-          hipLaunchKernelGGL((k_pq_part<float>), G, B, 0, c->stream, n, p, q32, pqp);
-          hipLaunchKernelGGL((k_pcg_step<float>), dim3(nbs), B, 0, c->stream, n, M, s, pqp, p, q32, x, rc, rnx, z,
-                             spart);
-        } else {
-          hipLaunchKernelGGL((k_pq_part<double>), G, B, 0, c->stream, n, p, q, pqp);
-          hipLaunchKernelGGL((k_pcg_step<double>), dim3(nbs), B, 0, c->stream, n, M, s, pqp, p, q, x, rc, rnx, z,
-                             spart);
-        }
+        hipLaunchKernelGGL((k_pq_part<double>), G, B, 0, c->stream, n, p, q, pqp);
+        hipLaunchKernelGGL((k_pcg_step<double>), dim3(nbs), B, 0, c->stream, n, M, s, pqp, p, q, x, rc, rnx, z,
+                           spart);
         std::swap(rc, rnx);
         if (t + 1 < steps)
-          hipLaunchKernelGGL(k_pcg_direction, G, B, 0, c->stream, n, s, spart, static_cast<int>(nbs), z, p, p32);
+          hipLaunchKernelGGL(k_pcg_direction, G, B, 0, c->stream, n, s, spart, static_cast<int>(nbs), z, p);
         else
           hipLaunchKernelGGL(k_beta_fin, dim3(1), B, 0, c->stream, spart, static_cast<int>(nbs), s, 3);
       }
@@ -655,16 +637,16 @@ SolveResult pcg_solve(gp_ctx* c, gp_matrix* m, const double* y, double* x, doubl
       break;
     }
     const double rn = std::sqrt(sc.rr);
-    // residual replacement: at apparent convergence, or (float32 products) after the
-    // recursive residual fell by 10x since the last float64 recomputation
-    if (rn <= target || (mixed && rn <= 0.1 * last_true)) {
+    // at apparent convergence the residual is recomputed as y - K x and replaces
+    // the recursive one
+    if (rn <= target) {
       sc = true_residual();
       ++res.refreshes;
       last_true = std::sqrt(sc.rr);
       if (last_true <= target) converged = true;
     }
     if (!converged && it < max_iter) {
-      hipLaunchKernelGGL(k_pcg_pupdate, G, B, 0, c->stream, n, s, z, p, p32);
+      hipLaunchKernelGGL(k_pcg_pupdate, G, B, 0, c->stream, n, s, z, p);
       check_launch("pcg direction");
     }
   }

@@ -462,12 +462,6 @@ void spmv_f64(gp_ctx* c, const gp_matrix* m, const double* x, double* y) {
     spmv_impl<double, double, double, double>(c, m, x, y);
 }
 
-void spmv_f32(gp_ctx* c, const gp_matrix* m, const float* x, float* y) {
-  if (m->prec == GP_MIXED)
-    spmv_impl<float, float, float, float>(c, m, x, y);
-  else
-    spmv_impl<double, float, float, float>(c, m, x, y);
-}
 
 namespace {
 
