@@ -399,11 +399,13 @@ __global__ void __launch_bounds__(kThreads) k_group_spmv(const int32_t* __restri
     if (c0 + kGChunk < nU) load(c0 + kGChunk);   // in flight while this chunk is consumed
     // lane takes entries k .. k + 3 (one 16-byte load per row for float32
     // values; a load may run past the row's group entries into the padded
-    // array, and those entries get weight 0), two such groups in flight
-    for (int k0 = 4 * lane; k0 < clen; k0 += 2 * 4 * kWave) {
-      VT v[2][kRows][4];
+    // array, and those entries get weight 0); one such group per row at a time
+    // keeps the kernel at 80 registers (6 waves per SIMD), which measured
+    // faster than two groups in flight at 4 waves per SIMD
+    for (int k0 = 4 * lane; k0 < clen; k0 += 4 * kWave) {
+      VT v[1][kRows][4];
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
+      for (int h = 0; h < 1; ++h) {
         const int k = k0 + h * 4 * kWave;
 #pragma unroll
         for (int r = 0; r < kRows; ++r) {
@@ -416,7 +418,7 @@ __global__ void __launch_bounds__(kThreads) k_group_spmv(const int32_t* __restri
         }
       }
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
+      for (int h = 0; h < 1; ++h) {
         const int k = k0 + h * 4 * kWave;
         AT xk[4];
 #pragma unroll
