@@ -811,6 +811,21 @@ gp_matrix* assemble(gp_ctx* c, const gp_dataset* ds, const gp_theta* th, int pre
       for (int32_t k0 = 0; k0 < nu; k0 += kPiece) pieces.insert(pieces.end(), {static_cast<int32_t>(a), i, rows, k0});
     }
   }
+  // largest group blocks first, so that the short ones fill the tail of the launch
+  {
+    const size_t nt = tiles.size() / 4;
+    std::vector<int32_t> idx(nt);
+    for (size_t i = 0; i < nt; ++i) idx[i] = static_cast<int32_t>(i);
+    auto work = [&](int32_t i) {
+      const int32_t a = tiles[4 * i];
+      return (uoff[a + 1] - uoff[a]) * static_cast<int64_t>(tiles[4 * i + 2]);
+    };
+    std::stable_sort(idx.begin(), idx.end(), [&](int32_t x, int32_t y) { return work(x) > work(y); });
+    std::vector<int32_t> sorted(tiles.size());
+    for (size_t i = 0; i < nt; ++i)
+      for (int f = 0; f < 4; ++f) sorted[4 * i + f] = tiles[4 * idx[i] + f];
+    tiles.swap(sorted);
+  }
   const int64_t ntiles = static_cast<int64_t>(tiles.size() / 4);
   const int64_t nstiles = static_cast<int64_t>(stiles.size() / 4);
   const int64_t npieces = static_cast<int64_t>(pieces.size() / 4);

@@ -121,7 +121,7 @@ struct gp_matrix {
   int32_t* g_ulist = nullptr;   // concatenated U_M (binned column ids, ascending)
   int32_t* g_rows = nullptr;    // rows with a mask, grouped by mask
   // ntiles tiles of at most kTileRows rows, each (mask id, first index in
-  // g_rows, rows, 0); then nstiles super-tiles of at most kSuperRows rows, each
+  // g_rows, rows, 0), largest (|U_M| x rows) first; then nstiles super-tiles of at most kSuperRows rows, each
   // (first index in g_rows, rows, first piece, pieces); then npieces pieces,
   // each (mask id, first index in g_rows, rows, first U_M entry): a piece is
   // a super-tile's rows times at most kPiece consecutive entries of U_M

@@ -365,7 +365,9 @@ __global__ void __launch_bounds__(kThreads) k_group_spmv(const int32_t* __restri
                                                          const XT* __restrict__ x, YT* __restrict__ y) {
   __shared__ AT xs[kGChunk];
   constexpr int kRows = kTileRows / (kThreads / kWave);
-  const int4 t = reinterpret_cast<const int4*>(tiles)[xcd_remap(blockIdx.x, gridDim.x)];
+  // tiles come largest first; block b runs on XCD b % 8, so every XCD gets an
+  // equal share of large and small tiles and the small ones fill the tail
+  const int4 t = reinterpret_cast<const int4*>(tiles)[blockIdx.x];
   const int32_t* U = ulist + uoff[t.x];
   const int64_t nU = uoff[t.x + 1] - uoff[t.x];
   const int w = threadIdx.x / kWave, lane = lane_id();
