@@ -299,7 +299,25 @@ __global__ void __launch_bounds__(kThreads) k_lz_beta_dot(int64_t n, int ld, con
   const T bp = static_cast<T>(st->beta_prev[l]);
   const T ic = static_cast<T>(st->inv_cur[l]), ip = static_cast<T>(st->inv_prev[l]);
   double acc = 0;
-  for (int64_t p = blockIdx.x * 8ll + rl; p < n; p += static_cast<int64_t>(gridDim.x) * 8) {
+  const int64_t S = static_cast<int64_t>(gridDim.x) * 8;
+  int64_t p = blockIdx.x * 8ll + rl;
+  for (; p + 3 * S < n; p += 4 * S) {
+    T wv[4], vv[4], pv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t i = (p + u * S) * ld + l;
+      wv[u] = W[i];
+      vv[u] = V[i];
+      pv[u] = Vprev[i];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const T w = wv[u] - bp * (pv[u] * ip);
+      W[(p + u * S) * ld + l] = w;
+      acc += static_cast<double>(vv[u] * ic) * static_cast<double>(w);
+    }
+  }
+  for (; p < n; p += S) {
     const int64_t i = p * ld + l;
     const T w = W[i] - bp * (Vprev[i] * ip);
     W[i] = w;
@@ -325,7 +343,24 @@ __global__ void __launch_bounds__(kThreads) k_lz_alpha_norm(int64_t n, int ld, c
   const T a = static_cast<T>(st->alpha[l]);
   const T ic = static_cast<T>(st->inv_cur[l]);
   double acc = 0;
-  for (int64_t p = blockIdx.x * 8ll + rl; p < n; p += static_cast<int64_t>(gridDim.x) * 8) {
+  const int64_t S = static_cast<int64_t>(gridDim.x) * 8;
+  int64_t p = blockIdx.x * 8ll + rl;
+  for (; p + 3 * S < n; p += 4 * S) {
+    T wv[4], vv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t i = (p + u * S) * ld + l;
+      wv[u] = W[i];
+      vv[u] = V[i];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const T w = wv[u] - a * (vv[u] * ic);
+      W[(p + u * S) * ld + l] = w;
+      acc += static_cast<double>(w) * static_cast<double>(w);
+    }
+  }
+  for (; p < n; p += S) {
     const int64_t i = p * ld + l;
     const T w = W[i] - a * (V[i] * ic);
     W[i] = w;
