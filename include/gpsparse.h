@@ -54,7 +54,7 @@ typedef enum gp_status {
 
 typedef enum gp_precision {
   GP_FP64 = 0,      /* float64 values, vectors and accumulation */
-  GP_MIXED = 1      /* float32 values and SpMV/SpMM, float64 residuals and reductions */
+  GP_MIXED = 1      /* float32 stored values; products with float64 vectors and accumulation */
 } gp_precision;
 
 typedef enum gp_logdet_mode {
@@ -268,13 +268,12 @@ typedef struct gp_loglik_result {
 /* gp_loglik: log p(y | theta) for the residual y = z - W beta (y_dev: n
  * float64 in ORIGINAL point order).  Quadratic form by preconditioned
  * conjugate gradients and/or MINRES on K (gp_solver, gp_precond); log det by
- * stochastic Lanczos
- * quadrature on the
- * Jacobi-scaled matrix (or exact Lanczos, see gp_logdet_mode).  With a
- * GP_MIXED matrix the conjugate-gradient products run in float32 and the residual
- * recomputation, Lanczos coefficients, quadrature and quadratic form in
- * float64.  alpha_dev (n float64, original order, may be NULL) receives
- * K^-1 y.  opts may be NULL (defaults).
+ * stochastic Lanczos quadrature on the Jacobi-scaled matrix (or exact
+ * Lanczos, see gp_logdet_mode).  Every product reads the matrix's stored
+ * values (float32 for a GP_MIXED matrix) with float64 vectors and float64
+ * accumulation; vectors, Lanczos coefficients, quadrature and the quadratic
+ * form are float64.  alpha_dev (n float64, original order, may be NULL)
+ * receives K^-1 y.  opts may be NULL (defaults).
  * Errors: GP_EINVAL, GP_ENOMEM, GP_ENOTCONV (result and alpha hold the last
  * iterate), GP_ENOTPD, GP_EDEVICE. */
 GP_API gp_status gp_loglik(gp_ctx* ctx, const gp_matrix* m, const double* y_dev,
