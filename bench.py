@@ -401,13 +401,11 @@ def main():
     n, nnz = p.n, info_m["nnz"]
 
     # dominant kernel of the timed region and its algorithmic bytes per launch
-    known = ("spmv_f32", "spmv_f32val_f64", "spmv_f64", "spmm")  # kernels with a bytes model
+    known = ("spmv_f32val_f64", "spmv_f64", "spmm")  # kernels with a bytes model
     dom = max(((k, v) for k, v in prof_m.items() if k in known), key=lambda kv: kv[1][1])
     name, (cnt, tot) = dom
     avg_s = tot / cnt / 1e3
-    if name == "spmv_f32":
-        b = spmv_bytes(n, nnz, 4, 4)
-    elif name == "spmv_f32val_f64":
+    if name == "spmv_f32val_f64":
         b = spmv_bytes(n, nnz, 4, 8)
     elif name == "spmv_f64":
         b = spmv_bytes(n, nnz, 8, 8)
