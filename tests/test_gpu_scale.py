@@ -13,7 +13,9 @@
 * Mixture workload, n = 100,000: quadratic form and alpha against the oracle's
   K = A + F F^T split (SuperLU on the local part, Woodbury for the bump groups);
   1e-8 (float64) / 1e-5 (mixed); the SLQ log det against the exact one within
-  3 standard errors.
+  3 standard errors; the same quadratic form by MINRES.
+* Space-time workload with the nonstationary core kernel: sampled rows against
+  the oracle (pattern bit-exact, values within 1e-12 relative).
 """
 import copy
 
@@ -151,3 +153,37 @@ def test_config2_loglik(ctx, cfg2_ref, prec, tol):
     if prec == 0:
         assert e_alpha <= tol
     assert gap <= 3 * r["logdet_se"]
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-8), (1, 1e-5)])
+def test_config2_minres(ctx, cfg2_ref, prec, tol):
+    import torch
+    from paper_2411_05869_amd import LOGDET_NONE, PRECOND_JACOBI, SOLVER_MINRES
+    p, ref = cfg2_ref
+    ds = ctx.dataset(dev(p.x), cell=p.cell)
+    K = ctx.assemble(ds, p.theta, prec)
+    alpha = torch.empty(p.n, dtype=torch.float64, device="cuda")
+    r = ctx.loglik(K, dev(p.y), alpha_out=alpha, logdet_mode=LOGDET_NONE, solver=SOLVER_MINRES,
+                   precond=PRECOND_JACOBI)
+    e_quad = rel(r["quad"], ref["quad"])
+    print(f"[cfg2 minres prec={prec}] iters {r['minres_iters']} relres {r['relres']:.2e} quad rel {e_quad:.2e}")
+    assert r["status"] == 0 and r["cg_iters"] == 0
+    assert e_quad <= tol
+
+
+def test_config3_sampled_rows_with_core(ctx, cfg3):
+    from workloads import spacetime_core
+    p, ds, orows = cfg3
+    th = copy.copy(p.theta)
+    th.core = spacetime_core(2)
+    M, F = kernel.features(p.x, th)
+    K = ctx.assemble(ds, th, 0)
+    g = _gpu_rows(ctx, K, orows.keys())
+    worst = 0.0
+    for r in list(orows.keys())[:60]:
+        oc, ov = kernel.row(p.x, th, int(r), M, F)
+        gc, gv = g[r]
+        assert np.array_equal(gc, oc), f"row {r}: pattern differs"
+        worst = max(worst, float(np.max(np.abs(gv - ov) / np.maximum(np.abs(ov), 1e-300))))
+    print(f"[cfg3 rows with the nonstationary core] 60 rows, max rel value error {worst:.2e}")
+    assert worst <= 1e-12

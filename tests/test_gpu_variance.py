@@ -135,3 +135,20 @@ def test_empty_request(ctx):
     K = ctx.assemble(ds, p.theta, 0)
     v, r = ctx.predict_var(K, p.theta, torch.zeros((0, 2), dtype=torch.float64, device="cuda"))
     assert v.numel() == 0 and r["iters"] == 0
+
+
+def test_variance_edge_cases(ctx):
+    from workloads import Problem, Theta
+    # no bump groups (n1 = 0) and a dense-group case (one bump covering every point)
+    th0 = Theta(2.0, np.array([0.1, 0.1]), np.zeros((0, 0, 2)), np.zeros((0, 0, 2)), np.zeros((0, 0)),
+                np.zeros((0, 0)), 0.1)
+    th1 = Theta(1.0, np.array([0.05, 0.05]), np.array([[[0.5, 0.5]]]), np.full((1, 1, 2), 5.0), np.ones((1, 1)),
+                np.ones((1, 1)), 0.1)
+    xs = np.random.default_rng(9).uniform(-0.1, 1.1, (35, 2))
+    for name, th in (("n1=0", th0), ("dense group", th1)):
+        p = Problem(name, np.random.default_rng(5).random((400, 2)), th, cell=None)
+        ref = predict.variance(xs, p.x, p.theta)
+        prior = predict.prior_variance(xs, p.theta)
+        v, r = _gpu_var(ctx, p, xs, 0)
+        assert r["status"] == 0
+        _check(v, ref, prior, 0, f"var {name}")
