@@ -484,16 +484,11 @@ namespace {
 // are added in a fixed order; a super-tile of one piece writes Y, otherwise
 // each piece writes its partial block and k_group_reduce adds the pieces in
 // order, so the result is deterministic.  Lane l of an MFMA result holds
-// four entries v = 0..3 of column l % 16: rows l / 16 + 4 v for the FP64
-// instruction, rows 4 (l / 16) + v for FP32.
+// four entries v = 0..3 of column l % 16: rows l / 16 + 4 v.
 typedef double mfma_d4 __attribute__((ext_vector_type(4)));
-typedef float mfma_f4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ mfma_d4 mfma16x16x4(double a, double b, mfma_d4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-}
-__device__ __forceinline__ mfma_f4 mfma16x16x4(float a, float b, mfma_f4 c) {
-  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
 template <typename T>
@@ -502,11 +497,6 @@ template <>
 struct MfmaAcc<double> {
   using type = mfma_d4;
   static __device__ __forceinline__ int row(int kk, int v) { return kk + 4 * v; }
-};
-template <>
-struct MfmaAcc<float> {
-  using type = mfma_f4;
-  static __device__ __forceinline__ int row(int kk, int v) { return 4 * kk + v; }
 };
 
 constexpr int kMThreads = 512;                   // 8 waves: 4 row groups x 2 halves of each chunk
@@ -728,7 +718,6 @@ void spmm(gp_ctx* c, const gp_matrix* m, int k, int ld, const T* X, T* Y, const 
   check_launch("spmm");
 }
 
-template void spmm<float>(gp_ctx*, const gp_matrix*, int, int, const float*, float*, const float*, const double*);
 template void spmm<double>(gp_ctx*, const gp_matrix*, int, int, const double*, double*, const double*,
                            const double*);
 
