@@ -12,8 +12,12 @@ Definitions followed (Sec. 2.1 and 3.1):
   for u = |x - x'| / r0 < 1, else 0;
 * sparse kernel (Eq. C_sparse): C_sparse = s0 f0 + sum_i f_i(x) f_i(x');
 * times the core kernel (Eq. sparseCov; ``oracle.core``, C_core = 1 unless
-  the hyper-parameters carry one) and the nugget of Eq. Zcov on the index
-  diagonal: K_pq = C_core(x_p, x_q) C_sparse(x_p, x_q) + sigma^2 [p = q].
+  the hyper-parameters carry one) plus the error variances of Eq. Zcov on the
+  index diagonal, Delta = diag[tau^2(x_1), ..., tau^2(x_N)], here a constant
+  nugget sigma^2 plus optional per-point values tau2[p] (``th.tau2``, original
+  point order):
+  K_pq = C_core(x_p, x_q) C_sparse(x_p, x_q) + (sigma^2 + tau2[p]) [p = q],
+  the two diagonal terms added in that order.
 
 Readings where the paper is silent or ambiguous:
 
@@ -108,13 +112,28 @@ def local_sq(xp, xq, th):
     return scaled_sq([xp[..., k] - xq[..., k] for k in range(d)], inv)
 
 
-def entries(xp, xq, Mp, Mq, Fp, Fq, same, th):
+def tau2_of(th, n=None):
+    """The per-point error variances th.tau2 (float64, original order) or None;
+    checks length n, finiteness and tau2 >= 0."""
+    t = getattr(th, "tau2", None)
+    if t is None:
+        return None
+    t = np.asarray(t, np.float64).reshape(-1)
+    if n is not None and t.shape[0] != n:
+        raise ValueError("tau2 must hold one value per point")
+    if not (np.all(np.isfinite(t)) and np.all(t >= 0.0)):
+        raise ValueError("tau2 must be finite and >= 0")
+    return t
+
+
+def entries(xp, xq, Mp, Mq, Fp, Fq, same, th, tau=None):
     """K_pq for aligned arrays of pairs (Eq. sparseCov, Eq. C_sparse, Eq. Zcov).
 
     K = C_core(p, q) (s0 f0(u) [u0^2 < 1] + sum_i [M_i(p) and M_i(q)] f_i(p) f_i(q))
-        + sigma^2 [p = q],
+        + sigma^2 [p = q] + tau [p = q],
     the group sum taken in increasing i; C_core = 1 unless th.core is set
-    (``oracle.core``).
+    (``oracle.core``); ``tau`` holds tau2 of each pair's row point (aligned
+    with the pairs), or None for no per-point term.
     """
     u2 = local_sq(xp, xq, th)
     L = u2 < 1.0
@@ -128,6 +147,8 @@ def entries(xp, xq, Mp, Mq, Fp, Fq, same, th):
     if cr is not None and cr.kind != core.NONE:
         val = core.value(xp, xq, cr) * val
     val = val + np.where(same, float(th.nugget), 0.0)
+    if tau is not None:
+        val = val + np.where(same, tau, 0.0)
     return val
 
 
@@ -143,6 +164,7 @@ def dense(x, th, nugget: bool = True, block: int = 512):
     x = np.asarray(x, np.float64)
     n = x.shape[0]
     M, F = features(x, th)
+    t2 = tau2_of(th, n) if nugget else None
     K = np.zeros((n, n))
     P = np.zeros((n, n), bool)
     idx = np.arange(n)
@@ -156,7 +178,8 @@ def dense(x, th, nugget: bool = True, block: int = 512):
         else:
             same_n = same
         P[s:e] = pattern_pred(xp, xq, M[s:e, None, :], M[None, :, :], same, th)
-        v = entries(xp, xq, M[s:e, None, :], M[None, :, :], F[s:e, None, :], F[None, :, :], same_n, th)
+        v = entries(xp, xq, M[s:e, None, :], M[None, :, :], F[s:e, None, :], F[None, :, :], same_n, th,
+                    None if t2 is None else t2[s:e, None])
         K[s:e] = np.where(P[s:e], v, 0.0)
     return K, P
 
@@ -170,7 +193,9 @@ def row(x, th, p: int, M=None, F=None):
     same = np.arange(n) == p
     P = pattern_pred(x[p][None, :], x, M[p][None, :], M, same, th)
     cols = np.nonzero(P)[0]
-    vals = entries(x[p][None, :], x[cols], M[p][None, :], M[cols], F[p][None, :], F[cols], cols == p, th)
+    t2 = tau2_of(th, n)
+    vals = entries(x[p][None, :], x[cols], M[p][None, :], M[cols], F[p][None, :], F[cols], cols == p, th,
+                   None if t2 is None else t2[p])
     return cols, vals
 
 
@@ -207,11 +232,13 @@ def sparse(x, th, return_features: bool = False):
     cols = keys % n
     del keys
     vals = np.empty(rows.shape[0])
+    t2 = tau2_of(th, n)
     chunk = 1 << 22
     for s in range(0, rows.shape[0], chunk):
         e = min(rows.shape[0], s + chunk)
         rp, cq = rows[s:e], cols[s:e]
-        vals[s:e] = entries(x[rp], x[cq], M[rp], M[cq], F[rp], F[cq], rp == cq, th)
+        vals[s:e] = entries(x[rp], x[cq], M[rp], M[cq], F[rp], F[cq], rp == cq, th,
+                            None if t2 is None else t2[rp])
     indptr = np.zeros(n + 1, np.int64)
     np.cumsum(np.bincount(rows, minlength=n), out=indptr[1:])
     if return_features:

@@ -82,6 +82,10 @@ class Theta:
     nugget: float
     wendland_variant: int = 0
     core: "Core | None" = None
+    # per-point error variances tau^2(x_p) of Eq. Zcov added to the nugget on
+    # the diagonal: None, a float64 array (n,) in original point order, or a
+    # CUDA float64 tensor of that shape (used in place by the library binding)
+    tau2: object = None
 
     @property
     def d(self) -> int:
@@ -98,7 +102,8 @@ class Theta:
     def copy(self) -> "Theta":
         return Theta(float(self.s0), self.r0.copy(), self.h.copy(), self.r.copy(),
                      self.a.copy(), self.b.copy(), float(self.nugget),
-                     int(self.wendland_variant), None if self.core is None else self.core.copy())
+                     int(self.wendland_variant), None if self.core is None else self.core.copy(),
+                     self.tau2)
 
 
 @dataclasses.dataclass
@@ -137,6 +142,12 @@ def _bumps(rng, n1, n2, lo, hi, radius, amp_lo=0.5, amp_hi=1.0):
     a = rng.uniform(amp_lo, amp_hi, (n1, n2))
     b = np.ones((n1, n2))
     return h, r, a, b
+
+
+def noise_variances(n: int, seed: int, lo: float = 0.0, hi: float = 0.05) -> np.ndarray:
+    """Per-point error variances tau^2(x_p) ~ U(lo, hi) (Eq. Zcov's Delta),
+    float64 (n,) in original point order."""
+    return np.random.default_rng(seed).uniform(lo, hi, n)
 
 
 def uniform_problem(n: int, d: int, seed: int, *, r0=0.05, n1=2, n2=2, bump_radius=0.2,
