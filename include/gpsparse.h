@@ -89,6 +89,13 @@ GP_API gp_status gp_ctx_set_stream(gp_ctx* ctx, void* stream);
 GP_API const char* gp_last_error(const gp_ctx* ctx);
 /* Bytes currently held by the context's workspace and live objects. */
 GP_API gp_status gp_ctx_memory(const gp_ctx* ctx, size_t* bytes_in_use, size_t* peak_bytes);
+/* HBM budget of the context: a device allocation that would raise the bytes
+ * in use (as gp_ctx_memory counts them: datasets, matrices, predictors and
+ * work space of this context) above `bytes` fails with GP_ENOMEM before the
+ * allocator is called; the call that needed it returns GP_ENOMEM and frees
+ * what it had allocated.  0 = no budget (the default).  Memory already held
+ * is kept even if it exceeds a new, smaller budget. */
+GP_API gp_status gp_ctx_set_hbm_budget(gp_ctx* ctx, size_t bytes);
 
 /* Per-kernel timing: while enabled, the library brackets its kernel launches
  * with HIP events on the context's stream.  gp_profile_enable clears the
@@ -123,8 +130,11 @@ GP_API gp_status gp_dataset_info(const gp_dataset* ds, int64_t* n, int32_t* d, i
 GP_API gp_status gp_dataset_permutation(gp_ctx* ctx, const gp_dataset* ds, int32_t* perm_dev);
 
 /* ------------------------------------------------------- hyper-parameters
- * theta_sparse of Sec. 2.1 (s0, r0, {h_ij, a_ij, b_ij, r_ij}) plus the
- * nugget sigma^2 of Eq. Zcov, all in host memory, copied by each call.
+ * theta_sparse of Sec. 2.1 (s0, r0, {h_ij, a_ij, b_ij, r_ij}) plus the error
+ * variances of Eq. Zcov, Delta = diag[tau^2(x_1), ..., tau^2(x_N)], given as a
+ * constant nugget sigma^2 and optional per-point values tau2; all in host
+ * memory and copied by each call, except tau2 (device memory, read during the
+ * call only).
  *   r0[k]  coordinate-specific Wendland radii (> 0; Appendix E uses
  *          per-coordinate truncation radii); u = |((x - x') / r0)|.
  *   h      n1*n2*d bump centres, bump (i, j) at h[(i*n2 + j)*d + k]
@@ -134,7 +144,13 @@ GP_API gp_status gp_dataset_permutation(gp_ctx* ctx, const gp_dataset* ds, int32
  * Support tests use the float64 expression sum_k ((x_k - c_k) * (1 / r_k))^2
  * < 1 evaluated left to right without fused multiply-add.
  * Limits: 1 <= n1 <= 64, n1*n2 <= 4096, s0 > 0, nugget >= 0.
- * core (optional) multiplies C_sparse, see gp_core. */
+ * core (optional) multiplies C_sparse, see gp_core.
+ * tau2 (optional, NULL for none): n float64 values in device memory, in the
+ * dataset's original point order, finite and >= 0 (checked on the device:
+ * GP_EINVAL otherwise).  The diagonal entry of row p is
+ * C_core C_sparse + sigma^2 + tau2[p], added in that order.  Only gp_assemble
+ * reads it: the cross-covariances of gp_predict and gp_predict_var carry no
+ * error variances. */
 /* Core kernel C_core of C_y = C_core x C_sparse (Sec. 2, Eq. sparseCov; the
  * nugget is added after the product).  The core is strictly positive, so it
  * never changes the sparsity pattern; it only scales the stored values.
@@ -185,6 +201,7 @@ typedef struct gp_theta {
   const double* b;
   double nugget;
   const gp_core* core;       /* NULL: C_core = 1 */
+  const double* tau2;        /* device, n values in original order, or NULL */
 } gp_theta;
 
 /* ------------------------------------------------------------------ matrix
@@ -317,7 +334,8 @@ GP_API gp_status gp_mean_residual(gp_ctx* ctx, int64_t n, int32_t p, const doubl
  * (Sec. 3.2: the diagonal of C_{y|z} = C_y - C_{y,z} C_z^{-1} C_{z,y}),
  *   var(x*) = C_y(x*, x*) - c^T K^{-1} c,   c = C_{z,y}(., x*)  (no nugget),
  * into var_dev (m float64, device).  K must have been assembled with theta
- * (checked against a fingerprint of every hyper-parameter).  The test points
+ * (checked against a fingerprint of every hyper-parameter except tau2, which
+ * enters K only and is not read here).  The test points
  * (xstar_dev: m x d row-major float64, device) are taken 32 at a time: their
  * cross-covariance columns are formed on the device and K W = C is solved by
  * 32 Jacobi-preconditioned conjugate-gradient recurrences in lockstep (one

@@ -40,7 +40,7 @@ class CTheta(C.Structure):
     _fields_ = [("d", C.c_int32), ("n1", C.c_int32), ("n2", C.c_int32), ("wendland_variant", C.c_int32),
                 ("s0", C.c_double), ("r0", C.c_double * 3), ("h", C.POINTER(C.c_double)),
                 ("r", C.POINTER(C.c_double)), ("a", C.POINTER(C.c_double)), ("b", C.POINTER(C.c_double)),
-                ("nugget", C.c_double), ("core", C.POINTER(CCore))]
+                ("nugget", C.c_double), ("core", C.POINTER(CCore)), ("tau2", C.c_void_p)]
 
 
 class CSolveOpts(C.Structure):
@@ -73,6 +73,7 @@ class CVarResult(C.Structure):
 
 EXPORTS = [
     "gp_ctx_create", "gp_ctx_destroy", "gp_ctx_set_stream", "gp_last_error", "gp_ctx_memory",
+    "gp_ctx_set_hbm_budget",
     "gp_dataset_create", "gp_dataset_destroy", "gp_dataset_info", "gp_dataset_permutation",
     "gp_assemble", "gp_matrix_destroy", "gp_matrix_info", "gp_matrix_export_csr", "gp_matvec",
     "gp_solve_opts_default", "gp_loglik", "gp_solve", "gp_predictor_create", "gp_predictor_destroy",
@@ -100,6 +101,7 @@ def lib():
     L.gp_last_error.argtypes = [P]
     L.gp_last_error.restype = C.c_char_p
     L.gp_ctx_memory.argtypes = [P, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]
+    L.gp_ctx_set_hbm_budget.argtypes = [P, C.c_size_t]
     L.gp_dataset_create.argtypes = [P, I64, I32, P, C.POINTER(D), C.POINTER(P)]
     L.gp_dataset_destroy.argtypes = [P, P]
     L.gp_dataset_info.argtypes = [P, C.POINTER(I64), C.POINTER(I32), C.POINTER(I64), C.POINTER(D)]
@@ -150,9 +152,13 @@ def _check_dev_tensor(t, dtype, shape=None, name="tensor"):
         raise ValueError(f"{name} must have shape {shape}, got {tuple(t.shape)}")
 
 
-def theta_struct(th):
+def theta_struct(th, n=None, device=None, with_tau2=True):
     """C struct for an object with fields s0, r0, h, r, a, b, nugget (numpy) and
-    wendland_variant; the numpy buffers are kept alive on the struct."""
+    wendland_variant, optionally core and tau2; the buffers are kept alive on
+    the struct.  tau2 (per-point error variances, original order) may be a
+    contiguous CUDA float64 tensor of n values, used in place, or a host array,
+    copied to ``device``; n checks its length.  with_tau2=False leaves it out
+    (for calls that do not read it)."""
     r0 = np.ascontiguousarray(np.asarray(th.r0, np.float64))
     d = int(r0.shape[0])
     a = np.ascontiguousarray(np.asarray(th.a, np.float64))
@@ -195,6 +201,15 @@ def theta_struct(th):
         cc.phi_Sigma = pS.ctypes.data_as(dp)
         cs.core = C.pointer(cc)
         keep += [cc, ps, pS, ctr]
+    t2 = getattr(th, "tau2", None) if with_tau2 else None
+    if t2 is not None:
+        torch = _torch()
+        if not isinstance(t2, torch.Tensor):
+            dev = torch.device("cuda", 0 if device is None else device)
+            t2 = torch.tensor(np.ascontiguousarray(np.asarray(t2, np.float64).reshape(-1)), device=dev)
+        _check_dev_tensor(t2, torch.float64, None if n is None else (n,), "tau2")
+        cs.tau2 = t2.data_ptr()
+        keep.append(t2)
     cs._keep = tuple(keep)
     return cs
 
@@ -265,6 +280,11 @@ class Context:
         self._L.gp_ctx_memory(self._h, C.byref(a), C.byref(b))
         return a.value, b.value
 
+    def set_hbm_budget(self, nbytes: int = 0):
+        """Cap the device bytes this context may hold (0: no cap); allocations past
+        it fail with GPError status GP_ENOMEM."""
+        self._check(self._L.gp_ctx_set_hbm_budget(self._h, int(nbytes)), "gp_ctx_set_hbm_budget")
+
     def profile(self, on: bool = True):
         """Start (and clear) or stop per-kernel event timing inside the library."""
         self._check(self._L.gp_profile_enable(self._h, 1 if on else 0), "gp_profile_enable")
@@ -294,7 +314,7 @@ class Context:
         return Dataset(self, h, n, d)
 
     def assemble(self, ds: "Dataset", theta, precision: int = FP64) -> "Matrix":
-        cs = theta_struct(theta)
+        cs = theta_struct(theta, ds.n, self.device)
         h = C.c_void_p()
         self._check(self._L.gp_assemble(self._h, ds._h, C.byref(cs), int(precision), C.byref(h)), "gp_assemble")
         return Matrix(self, h, ds)
@@ -353,7 +373,7 @@ class Context:
     def predictor(self, ds: "Dataset", theta, alpha) -> "Predictor":
         torch = _torch()
         _check_dev_tensor(alpha, torch.float64, (ds.n,), "alpha")
-        cs = theta_struct(theta)
+        cs = theta_struct(theta, with_tau2=False)
         h = C.c_void_p()
         self._check(self._L.gp_predictor_create(self._h, ds._h, C.byref(cs), C.c_void_p(_ptr(alpha)), C.byref(h)),
                     "gp_predictor_create")
@@ -394,7 +414,7 @@ class Context:
         m = int(xs.shape[0])
         if out is None:
             out = torch.empty(m, dtype=torch.float64, device=xs.device)
-        cs = theta_struct(theta)
+        cs = theta_struct(theta, with_tau2=False)
         o = self.opts(**opts)
         res = CVarResult()
         st = self._L.gp_predict_var(self._h, K._h, C.byref(cs), m, C.c_void_p(_ptr(xs)), C.byref(o),

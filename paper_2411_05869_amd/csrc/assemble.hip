@@ -168,6 +168,13 @@ __global__ void __launch_bounds__(kThreads) k_ugather(AsmArgs a, double* __restr
   for (int i = 0; i < a.kt.n1; ++i) uF[i * a.utotal + j] = f[i];
 }
 
+// flags a per-point error variance that is not finite or is negative
+__global__ void __launch_bounds__(kThreads) k_check_tau2(int64_t n, const double* __restrict__ t,
+                                                         int* __restrict__ err) {
+  const int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x;
+  if (i < n && !(t[i] >= 0.0 && t[i] <= 1.7976931348623157e308)) atomicOr(err, 1);
+}
+
 // ------------------------------------------------------- rows without groups
 constexpr int kBuf = 4;
 
@@ -233,7 +240,7 @@ __global__ void __launch_bounds__(kThreads) k_local_rows(AsmArgs a) {
       double cv = 1.0;
       if constexpr (CK == 1) cv = core_value<D, 1>(a.kt.core, xp, xq, 0.0, 0.0, 0.0, 0.0);
       if constexpr (CK == 2) cv = core_value<D, 2>(a.kt.core, xp, xq, sp, Sp, a.kt.core.sig[q], a.kt.core.Sig[q]);
-      const double v = entry_value(a.kt, u2, 0, nullptr, nullptr, q == p, 1, 1, cv);
+      const double v = entry_value(a.kt, u2, 0, nullptr, nullptr, q == p, 1, 1, cv, p);
       const VT vs = static_cast<VT>(v);
       if (q == p) a.diag[p] = static_cast<double>(vs);
       // shift register (constant indices keep it in registers): newest last
@@ -413,7 +420,7 @@ __global__ void __launch_bounds__(kThreads) k_group_rows_fill(AsmArgs a) {
     for (int k = 0; k < D; ++k) xq[k] = a.ux[k * a.utotal + u0 + kk];
     const double u2 = scaled_sq<D>(xp, xq, a.kt.inv0);
     const uint64_t shared = a.umask[u0 + kk] & mp;
-    const double v = entry_value(a.kt, u2, shared, Fp, a.uF + u0 + kk, u == p, 1, a.utotal, core_at(u, xq));
+    const double v = entry_value(a.kt, u2, shared, Fp, a.uF + u0 + kk, u == p, 1, a.utotal, core_at(u, xq), p);
     const VT vs = static_cast<VT>(v);
     a.col[out + kk] = u;
     val[out + kk] = vs;
@@ -545,6 +552,7 @@ uint64_t theta_hash(const gp_theta* th) {
   arr(th->a, nb);
   arr(th->b, nb);
   mix(&th->nugget, sizeof(double));
+  // tau2 is not hashed: it enters the matrix only, never C_y
   const gp_core* co = th->core;
   const int32_t kind = co ? co->kind : GP_CORE_NONE;
   mix(&kind, sizeof(kind));
@@ -712,6 +720,19 @@ gp_matrix* assemble(gp_ctx* c, const gp_dataset* ds, const gp_theta* th, int pre
   Bump* bumps = nullptr;
   KernelTheta kt{};
   upload_theta(c, th, &bumps, &kt);
+  if (th->tau2) {
+    // per-point error variances to binned order, checked before any work
+    double* t2 = static_cast<double*>(workspace(c, 121, sizeof(double) * n));
+    permute_to_binned<double>(c, ds, 1, th->tau2, t2);
+    GPS_HIP(hipMemsetAsync(c->err_flag, 0, sizeof(int), c->stream));
+    hipLaunchKernelGGL(k_check_tau2, dim3(grid_for(n, kThreads)), dim3(kThreads), 0, c->stream, n, t2, c->err_flag);
+    check_launch("tau2 check");
+    int* herr = static_cast<int*>(pinned(c, sizeof(int)));
+    GPS_HIP(hipMemcpyAsync(herr, c->err_flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    sync(c);
+    GPS_REQUIRE(*herr == 0, GP_EINVAL, "gp_assemble: tau2 must be finite and >= 0");
+    kt.tau2 = t2;
+  }
   Features f;
   compute_features(c, ds, kt, &f, 1);
   const int64_t nm = f.nm;

@@ -15,6 +15,9 @@ void predict(gp_ctx* c, const gp_predictor* p, int64_t m, const double* xs, int 
 // ------------------------------------------------------------------ memory
 void* dev_alloc(gp_ctx* c, size_t bytes) {
   if (bytes == 0) bytes = 16;
+  if (c->budget && bytes > c->budget - std::min(c->budget, c->in_use))
+    throw Error{GP_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes exceeds the context's HBM budget (" +
+                               std::to_string(c->in_use) + " of " + std::to_string(c->budget) + " bytes in use)"};
   void* p = nullptr;
   if (c->alloc) {
     p = c->alloc(bytes, c->user);
@@ -294,6 +297,12 @@ gp_status gp_profile_read(gp_ctx* c, int32_t max_entries, gp_profile_entry* out,
 }
 
 const char* gp_last_error(const gp_ctx* c) { return c ? c->err.c_str() : "context is NULL"; }
+
+gp_status gp_ctx_set_hbm_budget(gp_ctx* c, size_t bytes) {
+  if (!c) return GP_EINVAL;
+  c->budget = bytes;
+  return GP_OK;
+}
 
 gp_status gp_ctx_memory(const gp_ctx* c, size_t* in_use, size_t* peak) {
   if (!c) return GP_EINVAL;

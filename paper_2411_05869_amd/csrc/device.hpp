@@ -56,7 +56,7 @@ __device__ __forceinline__ double wendland(double u2, int variant) {
 // a core kernel (a product with 1 is exact).
 __device__ __forceinline__ double entry_value(const KernelTheta& kt, double u2, uint64_t shared,
                                               const double* Fp, const double* Fq, bool diag, int64_t sp = 1,
-                                              int64_t sq = 1, double core = 1.0) {
+                                              int64_t sq = 1, double core = 1.0, int64_t row = 0) {
 #pragma clang fp contract(off)
   double acc = (u2 < 1.0) ? kt.s0 * wendland(u2, kt.variant) : 0.0;
   while (shared) {
@@ -65,7 +65,10 @@ __device__ __forceinline__ double entry_value(const KernelTheta& kt, double u2, 
     acc = acc + Fp[i * sp] * Fq[i * sq];
   }
   acc = core * acc;
-  if (diag) acc = acc + kt.nugget;
+  if (diag) {
+    acc = acc + kt.nugget;
+    if (kt.tau2) acc = acc + kt.tau2[row];  // Delta_pp = sigma^2 + tau2[p] (Eq. Zcov)
+  }
   return acc;
 }
 

@@ -61,6 +61,7 @@ struct gp_ctx {
   void* user = nullptr;
   std::string err;
   size_t in_use = 0, peak = 0;
+  size_t budget = 0;  // 0: none
   // growable workspace slots, reused across calls on this context
   struct Slot {
     void* ptr = nullptr;
@@ -190,6 +191,7 @@ struct KernelTheta {
   double inv0[3];
   const Bump* bumps;  // device, n1*n2
   KernelCore core;
+  const double* tau2;  // device, per-point error variances in binned order, or null
 };
 
 // -------------------------------------------------------------- memory

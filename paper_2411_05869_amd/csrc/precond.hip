@@ -149,8 +149,21 @@ __global__ void __launch_bounds__(kThreads) k_block_invert(int64_t nblk, const i
 
 }  // namespace
 
+static void build_block_jacobi_impl(gp_ctx* c, gp_matrix* m);
+
 void build_block_jacobi(gp_ctx* c, gp_matrix* m) {
   if (m->binv) return;
+  // a failure (allocation, non-positive pivot) leaves no partial state behind,
+  // so a later call builds the preconditioner again from scratch
+  try {
+    build_block_jacobi_impl(c, m);
+  } catch (...) {
+    free_block_jacobi(c, m);
+    throw;
+  }
+}
+
+static void build_block_jacobi_impl(gp_ctx* c, gp_matrix* m) {
   const gp_dataset* ds = m->ds;
   const int64_t n = m->n;
   int32_t* flag = static_cast<int32_t*>(workspace(c, 70, sizeof(int32_t) * n));
@@ -177,7 +190,6 @@ void build_block_jacobi(gp_ctx* c, gp_matrix* m) {
   const int64_t total = read_i64(c, m->boff + nblk);
   m->binv_len = total;
   m->binv = dev_new<double>(c, std::max<int64_t>(total, 1));
-  m->bytes += sizeof(int32_t) * (nblk + 1 + n) + sizeof(int64_t) * (nblk + 1) + sizeof(double) * total;
   GPS_HIP(hipMemsetAsync(c->err_flag, 0, sizeof(int), c->stream));
   {
     ProfScope ps(c, "precond_setup");
@@ -205,6 +217,7 @@ void build_block_jacobi(gp_ctx* c, gp_matrix* m) {
   GPS_HIP(hipMemcpyAsync(herr, c->err_flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
   sync(c);
   if (*herr) throw Error{GP_ENOTPD, "block-Jacobi setup met a non-positive pivot: matrix not positive definite"};
+  m->bytes += sizeof(int32_t) * (nblk + 1 + n) + sizeof(int64_t) * (nblk + 1) + sizeof(double) * total;
 }
 
 void free_block_jacobi(gp_ctx* c, gp_matrix* m) {

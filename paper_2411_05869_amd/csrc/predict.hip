@@ -211,8 +211,12 @@ __global__ void __launch_bounds__(kThreads) k_predict_groups(PredArgs a, CoreBas
 
 }  // namespace
 
+void destroy_predictor(gp_ctx* c, gp_predictor* p);
+
 gp_predictor* make_predictor(gp_ctx* c, const gp_dataset* ds, const gp_theta* th, const double* alpha) {
-  std::unique_ptr<gp_predictor> p(new gp_predictor());
+  // a failure part-way releases whatever device memory the predictor holds by then
+  auto release = [c](gp_predictor* x) { destroy_predictor(c, x); };
+  std::unique_ptr<gp_predictor, decltype(release)> p(new gp_predictor(), release);
   p->ds = ds;
   Bump* tmp_bumps = nullptr;
   KernelTheta kt{};

@@ -1,0 +1,87 @@
+"""The context's HBM budget (gp_ctx_set_hbm_budget): an allocation past it
+fails with GP_ENOMEM, the failing call frees what it had allocated, and the
+context keeps working once the budget is lifted.
+
+Leaks are measured by running "fail, then succeed" on one context and
+"succeed" alone on another: the work space both keep is the same, so the
+bytes in use must agree.  The cases cover assembly, the block-Jacobi
+preconditioner built inside a solve (a failure there must not leave a partial
+preconditioner behind: the later solve must match a fresh context's result
+bitwise), and predictor creation."""
+import numpy as np
+import pytest
+
+from workloads import config1
+from gpu_util import dev
+
+pytestmark = pytest.mark.gpu
+
+ENOMEM = 2
+
+
+def _ctx():
+    from paper_2411_05869_amd import Context
+    return Context()
+
+
+def _expect_enomem(fn):
+    from paper_2411_05869_amd import GPError
+    with pytest.raises(GPError) as e:
+        fn()
+    assert e.value.status == ENOMEM, e.value
+
+
+def test_assemble_over_budget():
+    p = config1()
+    a, b = _ctx(), _ctx()
+    ds_a, ds_b = a.dataset(dev(p.x), cell=p.cell), b.dataset(dev(p.x), cell=p.cell)
+    a.set_hbm_budget(a.memory()[0] + (64 << 10))
+    _expect_enomem(lambda: a.assemble(ds_a, p.theta, 0))
+    a.set_hbm_budget(0)
+    Ka, Kb = a.assemble(ds_a, p.theta, 0), b.assemble(ds_b, p.theta, 0)
+    print(f"[budget assemble] in use {a.memory()[0]} vs fresh {b.memory()[0]}")
+    assert a.memory()[0] == b.memory()[0]
+    assert Ka.nnz == Kb.nnz
+
+
+def test_preconditioner_over_budget_leaves_no_partial_state():
+    from paper_2411_05869_amd import LOGDET_NONE
+    p = config1()
+    a, b = _ctx(), _ctx()
+    ds_a, ds_b = a.dataset(dev(p.x), cell=p.cell), b.dataset(dev(p.x), cell=p.cell)
+    Ka, Kb = a.assemble(ds_a, p.theta, 0), b.assemble(ds_b, p.theta, 0)
+    y = dev(np.random.default_rng(1).standard_normal(p.n))
+    # room for the solve's vectors but not for the preconditioner's inverses:
+    # find a budget at which the solve fails, growing it until the call passes
+    base = a.memory()[0]
+    failed = False
+    for extra in (16 << 10, 64 << 10, 256 << 10, 1 << 20, 4 << 20):
+        a.set_hbm_budget(base + extra)
+        r = a.loglik(Ka, y, raise_on_error=False, logdet_mode=LOGDET_NONE)
+        if r["status"] == ENOMEM:
+            failed = True
+        else:
+            break
+    assert failed
+    a.set_hbm_budget(0)
+    ra = a.loglik(Ka, y)
+    rb = b.loglik(Kb, y)
+    print(f"[budget precond] in use {a.memory()[0]} vs fresh {b.memory()[0]}; iters {ra['cg_iters']} {rb['cg_iters']}")
+    assert ra == rb
+    assert a.memory()[0] == b.memory()[0]
+
+
+def test_predictor_over_budget():
+    import torch
+    p = config1()
+    a, b = _ctx(), _ctx()
+    ds_a, ds_b = a.dataset(dev(p.x), cell=p.cell), b.dataset(dev(p.x), cell=p.cell)
+    alpha = dev(np.random.default_rng(2).standard_normal(p.n))
+    a.set_hbm_budget(a.memory()[0] + 4096)
+    _expect_enomem(lambda: a.predictor(ds_a, p.theta, alpha))
+    a.set_hbm_budget(0)
+    pa, pb = a.predictor(ds_a, p.theta, alpha), b.predictor(ds_b, p.theta, alpha)
+    xs = dev(np.random.default_rng(3).random((100, 2)))
+    assert torch.equal(a.predict(pa, xs), b.predict(pb, xs))
+    print(f"[budget predictor] in use {a.memory()[0]} vs fresh {b.memory()[0]}")
+    assert a.memory()[0] == b.memory()[0]
