@@ -43,6 +43,8 @@ def spmm_bytes(n, nnz, vbytes, k, xbytes):
     return nnz * (vbytes + 4) + (n + 1) * 8 + 2 * n * k * xbytes + n * xbytes
 
 
+EXACT_LOGLIK = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests", "golden",
+                            "spacetime_n1095000_exact.json")
 TRAFFIC_PROFILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
                                "traffic_spmv_f32val_f64_spacetime_n1095000.md")
 SPMV_SOURCE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2411_05869_amd", "csrc", "spmv.hip")
@@ -50,6 +52,24 @@ SPMV_SOURCE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_24
 SPMV_KERNELS = ("k_group_spmv<float, double, double, double>", "k_spmv<float, double, double, double>")
 SPMV_PROFILE_NAME = "spmv_f32val_f64"
 CALIB_BYTES = 1 << 30
+
+
+def vs_exact(r, workload):
+    """Errors of a GPU log-likelihood against the exact one of the same workload
+    (the oracle's day-blocked split, stored by tests/golden/make_spacetime_exact.py):
+    the quadratic form and log-likelihood relative, the SLQ log det in its
+    standard errors; None when the stored value is missing or for another workload."""
+    try:
+        with open(EXACT_LOGLIK) as f:
+            g = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if g.get("workload") != workload:
+        return None
+    return dict(quad_rel=abs(r["quad"] - g["quad"]) / abs(g["quad"]),
+                logdet_gap_se=abs(r["logdet"] - g["logdet"]) / r["logdet_se"],
+                logdet_rel=abs(r["logdet"] - g["logdet"]) / abs(g["logdet"]),
+                loglik_rel=abs(r["loglik"] - g["loglik"]) / abs(g["loglik"]), exact_loglik=g["loglik"])
 
 
 def source_sha256(path):
@@ -430,10 +450,11 @@ def main():
                fp64=dict(value=round(evals_d, 4), unit="loglik evals/s", ms_per_step=round(1e3 * dt_d / args.fp64_steps, 2),
                          nnz_per_s=round(nnz / asm_wall_d, 1), assemble_ms=round(1e3 * asm_wall_d, 3),
                          assemble_kernels_ms=round(asm_ms_d, 3),
-                         loglik=r_d["loglik"], cg_iters=r_d["cg_iters"]),
+                         loglik=r_d["loglik"], cg_iters=r_d["cg_iters"], vs_exact=vs_exact(r_d, p.name)),
                mixed=dict(loglik=r_m["loglik"], logdet=r_m["logdet"], quad=r_m["quad"], logdet_se=r_m["logdet_se"],
                           cg_iters=r_m["cg_iters"], refreshes=r_m["refreshes"], relres=r_m["relres"],
-                          rel_vs_fp64=abs(r_m["loglik"] - r_d["loglik"]) / abs(r_d["loglik"])),
+                          rel_vs_fp64=abs(r_m["loglik"] - r_d["loglik"]) / abs(r_d["loglik"]),
+                          vs_exact=vs_exact(r_m, p.name)),
                binning_ms=round(1e3 * t_bin, 2),
                roofline=roof,
                kernels_ms_per_step={k: round(v[1] / args.steps, 3) for k, v in sorted(prof_m.items(),

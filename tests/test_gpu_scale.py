@@ -16,8 +16,15 @@
   3 standard errors; the same quadratic form by MINRES.
 * Space-time workload with the nonstationary core kernel: sampled rows against
   the oracle (pattern bit-exact, values within 1e-12 relative).
+* Space-time workload, whole log-likelihood against the exact one in
+  tests/golden/spacetime_n1095000_exact.json (written by the oracle's
+  day-blocked split, make_spacetime_exact.py): quadratic form 1e-8 (float64) /
+  1e-5 (mixed); the SLQ log det within 3 of its standard errors of the exact
+  log det.
 """
 import copy
+import json
+import os
 
 import numpy as np
 import pytest
@@ -187,3 +194,21 @@ def test_config3_sampled_rows_with_core(ctx, cfg3):
         worst = max(worst, float(np.max(np.abs(gv - ov) / np.maximum(np.abs(ov), 1e-300))))
     print(f"[cfg3 rows with the nonstationary core] 60 rows, max rel value error {worst:.2e}")
     assert worst <= 1e-12
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-8), (1, 1e-5)])
+def test_config3_loglik_against_exact(ctx, cfg3, prec, tol):
+    with open(os.path.join(os.path.dirname(__file__), "golden", "spacetime_n1095000_exact.json")) as f:
+        gold = json.load(f)
+    p, ds, _ = cfg3
+    assert gold["n"] == p.n and gold["workload"] == p.name
+    K = ctx.assemble(ds, p.theta, prec)
+    r = ctx.loglik(K, dev(p.y))
+    e_quad = rel(r["quad"], gold["quad"])
+    gap = abs(r["logdet"] - gold["logdet"])
+    print(f"[cfg3 exact prec={prec}] iters {r['cg_iters']} quad rel {e_quad:.2e}; SLQ logdet {r['logdet']:.10g} "
+          f"exact {gold['logdet']:.10g} |gap| {gap:.4g} = {gap / r['logdet_se']:.2f} SE "
+          f"({gap / abs(gold['logdet']):.2e} relative); loglik rel {rel(r['loglik'], gold['loglik']):.2e}")
+    K.close()
+    assert r["status"] == 0 and e_quad <= tol
+    assert gap <= 3 * r["logdet_se"]

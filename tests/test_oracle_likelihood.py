@@ -190,3 +190,28 @@ def test_variance_split_route_matches_dense():
     xs = np.random.default_rng(2).uniform(-0.1, 1.1, (40, 2))
     assert np.allclose(predict.variance_split(xs, p.x, p.theta), predict.variance(xs, p.x, p.theta),
                        rtol=1e-10, atol=1e-13)
+
+
+@pytest.mark.parametrize("with_tau2", [False, True])
+def test_banded_split_equals_dense_cholesky(with_tau2):
+    # the day-blocked route (block Cholesky of the local part, determinant
+    # lemma, Woodbury) against LAPACK on the dense K of a small space-time set
+    from workloads import config3, noise_variances
+    p = config3(n_stations=50, n_days=40)
+    th = p.theta.copy()
+    if with_tau2:
+        th.tau2 = noise_variances(p.n, 8, 0.0, 0.05)
+    K, _ = kernel.dense(p.x, th)
+    ref = likelihood.dense_cholesky(K, p.y)
+    r = likelihood.banded_split(p.x, th, p.y)
+    assert r["blocks"] == 40 and r["half_width"] == 2
+    assert abs(r["logdet"] - ref["logdet"]) <= 1e-10 * abs(ref["logdet"])
+    assert abs(r["quad"] - ref["quad"]) <= 1e-10 * abs(ref["quad"])
+    # the input order does not matter (the points are grouped by day inside)
+    perm = np.random.default_rng(1).permutation(p.n)
+    th_p = th.copy()
+    if with_tau2:
+        th_p.tau2 = th.tau2[perm]
+    r2 = likelihood.banded_split(p.x[perm], th_p, p.y[perm])
+    assert abs(r2["logdet"] - r["logdet"]) <= 1e-11 * abs(r["logdet"])
+    assert abs(r2["quad"] - r["quad"]) <= 1e-11 * abs(r["quad"])
