@@ -355,6 +355,8 @@ class Context:
     def matvec(self, K: "Matrix", x):
         torch = _torch()
         _check_dev_tensor(x, torch.float64, name="x")
+        if x.dim() not in (1, 2) or x.shape[0] != K.n:
+            raise ValueError(f"x must have shape ({K.n},) or ({K.n}, k), got {tuple(x.shape)}")
         nrhs = 1 if x.dim() == 1 else int(x.shape[1])
         y = torch.empty_like(x)
         self._check(self._L.gp_matvec(self._h, K._h, nrhs, C.c_void_p(_ptr(x)), C.c_void_p(_ptr(y))), "gp_matvec")
@@ -382,9 +384,12 @@ class Context:
     def predict(self, pred: "Predictor", xs, precision: int = FP64, out=None):
         torch = _torch()
         _check_dev_tensor(xs, torch.float64, name="xs")
+        if xs.dim() != 2 or xs.shape[1] != pred.ds.d:
+            raise ValueError(f"xs must be (m, {pred.ds.d}), got {tuple(xs.shape)}")
         m = int(xs.shape[0])
         if out is None:
             out = torch.empty(m, dtype=torch.float64, device=xs.device)
+        _check_dev_tensor(out, torch.float64, (m,), "out")
         self._check(self._L.gp_predict(self._h, pred._h, m, C.c_void_p(_ptr(xs)), int(precision),
                                        C.c_void_p(_ptr(out))), "gp_predict")
         return out
@@ -394,6 +399,8 @@ class Context:
         column-major n x p matrix of the C call), beta: p host values."""
         torch = _torch()
         _check_dev_tensor(z, torch.float64, name="z")
+        if z.dim() != 1:
+            raise ValueError("z must be one-dimensional")
         n = int(z.shape[0])
         b = np.ascontiguousarray(np.asarray(beta, np.float64).reshape(-1))
         p = int(b.size)
@@ -401,6 +408,7 @@ class Context:
             _check_dev_tensor(W, torch.float64, (p, n), "W")
         if out is None:
             out = torch.empty_like(z)
+        _check_dev_tensor(out, torch.float64, (n,), "out")
         self._check(self._L.gp_mean_residual(self._h, n, p, C.c_void_p(_ptr(W)) if p else None,
                                              b.ctypes.data_as(C.POINTER(C.c_double)), C.c_void_p(_ptr(z)),
                                              C.c_void_p(_ptr(out))), "gp_mean_residual")
@@ -411,9 +419,12 @@ class Context:
         m x d float64); K must be assembled with theta.  Returns (var, result)."""
         torch = _torch()
         _check_dev_tensor(xs, torch.float64, name="xs")
+        if xs.dim() != 2 or xs.shape[1] != K.ds.d:
+            raise ValueError(f"xs must be (m, {K.ds.d}), got {tuple(xs.shape)}")
         m = int(xs.shape[0])
         if out is None:
             out = torch.empty(m, dtype=torch.float64, device=xs.device)
+        _check_dev_tensor(out, torch.float64, (m,), "out")
         cs = theta_struct(theta, with_tau2=False)
         o = self.opts(**opts)
         res = CVarResult()

@@ -9,7 +9,7 @@ import pytest
 
 from oracle import kernel
 from workloads import Theta, config1, config2, uniform_problem
-from gpu_util import assert_pattern_equal, dev, export, host, to_scipy, value_errors
+from gpu_util import assert_pattern_equal, dev, export, host, rel, to_scipy, value_errors
 
 pytestmark = pytest.mark.gpu
 
@@ -119,6 +119,31 @@ def test_binning_is_permutation_and_deterministic(ctx):
     a, b = export(ctx, K1), export(ctx, K2)
     for u, v in zip(a, b):
         assert np.array_equal(u, v)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_permutation_invariance(ctx, prec):
+    # shuffled input points: the exported matrix (in the caller's order) is the
+    # original one under the permutation, pattern and values bitwise; the
+    # quadratic form agrees to rounding (the binned order inside a cell follows
+    # the input order, so sums run in another order)
+    from paper_2411_05869_amd import LOGDET_NONE
+    p = uniform_problem(800, 3, 17, r0=0.15, n1=3, n2=2, bump_radius=0.3)
+    perm = np.random.default_rng(4).permutation(p.n)
+    y = np.random.default_rng(5).standard_normal(p.n)
+    out = []
+    for xx, yy in ((p.x, y), (p.x[perm], y[perm])):
+        ds = ctx.dataset(dev(xx), cell=p.cell)
+        K = ctx.assemble(ds, p.theta, prec)
+        out.append((to_scipy(*export(ctx, K), p.n), ctx.loglik(K, dev(yy), logdet_mode=LOGDET_NONE)))
+    (A, r1), (A2, r2) = out
+    Ap = A[perm][:, perm].tocsr()
+    Ap.sort_indices()
+    A2.sort_indices()
+    assert np.array_equal(A2.indptr, Ap.indptr) and np.array_equal(A2.indices, Ap.indices)
+    assert np.array_equal(A2.data, Ap.data)
+    print(f"[permutation prec={prec}] nnz {A.nnz} quad rel {rel(r1['quad'], r2['quad']):.2e}")
+    assert rel(r1["quad"], r2["quad"]) <= (1e-12 if prec == 0 else 1e-9)
 
 
 def test_invalid_theta_is_einval(ctx):

@@ -1,0 +1,102 @@
+"""GPU parity of the matrix products y = K x and Y = K X (gp_matvec: the
+group-block GEMV and the CSR SpMV for one right-hand side, the MFMA group
+blocks and the CSR SpMM for 2..32) against the oracle's matrix.
+
+The GPU adds the same products in another order, so every row of the FP64
+form is held to |y_p - y_ref,p| <= 1e-13 (|K| |x|)_p, y_ref the product with
+the oracle's float64 values.  The mixed form stores each value rounded to
+float32 (relative error <= 2^-24) and multiplies in float64, so its bound is
+(2^-24 + 1e-13) (|K| |x|)_p; float32 accumulation would break it (about
+sqrt(row length) 2^-24).  Sizes: config 1 (n = 2000; several tiles, a ragged tail, dense
+group rows) with 1, 2, 7 and 32 right-hand sides, and the n = 1,095,000
+space-time workload on sampled rows (oracle rows one at a time, the launch
+configuration of the benchmark).  Shape errors in the binding are refused
+before any device work."""
+import numpy as np
+import pytest
+
+from oracle import kernel
+from workloads import config1, config3
+from gpu_util import dev, host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2411_05869_amd import Context
+    return Context()
+
+
+def _check_rows(y, ref, bound, prec, what):
+    tol = 1e-13 if prec == 0 else 2.0 ** -24 + 1e-13
+    err = np.abs(y - ref)
+    worst = float(np.max(err / (bound + 1e-300)))
+    print(f"[{what}] worst |dy| / (|K||x|) {worst:.2e} (bound {tol:.2e})")
+    assert np.all(err <= tol * bound + 1e-300), what
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("k", [1, 2, 7, 32])
+def test_products_config1(ctx, prec, k):
+    p = config1()
+    A = kernel.to_scipy(*kernel.sparse(p.x, p.theta), p.n)
+    rng = np.random.default_rng(10 + k)
+    X = rng.standard_normal((p.n, k)) if k > 1 else rng.standard_normal(p.n)
+    ds = ctx.dataset(dev(p.x), cell=p.cell)
+    K = ctx.assemble(ds, p.theta, prec)
+    Y = host(ctx.matvec(K, dev(X)))
+    absA = abs(A)
+    _check_rows(Y, A @ X, absA @ np.abs(X), prec, f"cfg1 prec={prec} k={k}")
+
+
+@pytest.fixture(scope="module")
+def cfg3_rows():
+    p = config3()
+    M, F = kernel.features(p.x, p.theta)
+    rng = np.random.default_rng(31)
+    masked = np.nonzero(M.any(axis=1))[0]
+    rows = np.unique(np.concatenate([rng.choice(p.n, 40, replace=False), rng.choice(masked, 20, replace=False)]))
+    return p, {int(r): kernel.row(p.x, p.theta, int(r), M, F) for r in rows}
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("k", [1, 32])
+def test_products_config3_sampled_rows(ctx, cfg3_rows, prec, k):
+    import torch
+    p, orows = cfg3_rows
+    rng = np.random.default_rng(40 + k)
+    X = rng.standard_normal((p.n, k)) if k > 1 else rng.standard_normal(p.n)
+    ds = ctx.dataset(dev(p.x), cell=p.cell)
+    K = ctx.assemble(ds, p.theta, prec)
+    Y = host(ctx.matvec(K, dev(X)))
+    K.close()
+    torch.cuda.empty_cache()
+    rows = sorted(orows)
+    ref, bound = [], []
+    for r in rows:
+        c, v = orows[r]
+        ref.append(v @ X[c])
+        bound.append(np.abs(v) @ np.abs(X[c]))
+    _check_rows(Y[rows], np.array(ref), np.array(bound), prec, f"cfg3 prec={prec} k={k} ({len(rows)} rows)")
+
+
+def test_binding_refuses_bad_shapes(ctx):
+    import torch
+    p = config1()
+    ds = ctx.dataset(dev(p.x), cell=p.cell)
+    K = ctx.assemble(ds, p.theta, 0)
+    with pytest.raises(ValueError):
+        ctx.matvec(K, dev(np.zeros(p.n - 1)))
+    with pytest.raises(ValueError):
+        ctx.matvec(K, dev(np.zeros((p.n, 2, 2))))
+    alpha = torch.zeros(p.n, dtype=torch.float64, device="cuda")
+    pred = ctx.predictor(ds, p.theta, alpha)
+    with pytest.raises(ValueError):
+        ctx.predict(pred, dev(np.zeros((5, 3))))
+    with pytest.raises(ValueError):
+        ctx.predict(pred, dev(np.zeros((5, 2))), out=torch.zeros(4, dtype=torch.float64, device="cuda"))
+    with pytest.raises(ValueError):
+        ctx.predict_var(K, p.theta, dev(np.zeros(10)))
+    with pytest.raises(ValueError):
+        ctx.mean_residual(None, [], dev(np.zeros(p.n)), out=torch.zeros(3, dtype=torch.float64, device="cuda"))
