@@ -113,6 +113,14 @@ struct gp_matrix {
   double* diag = nullptr;       // n, diagonal of the stored matrix (float64)
   int32_t* long_rows = nullptr; // rows with more than kLongRow entries
   int64_t n_long = 0;
+  // row quads for the multi-column product, built on first use: for the
+  // group of binned rows 4g .. 4g+3, the ascending union of their CSR-part
+  // columns (rows with more than kLongRow entries left out) with the four
+  // rows' values per column (0 where a row has no entry)
+  int64_t nquad = 0;             // union entries over all groups
+  int64_t* qptr = nullptr;       // ceil(n / 4) + 1 offsets
+  int32_t* qcol = nullptr;       // nquad
+  void* qval = nullptr;          // 4 * nquad float or double
   // rows with a bump-group mask start with the group entries of their mask
   // (|U_M| entries, shared column list U_M); the products treat these as dense
   // blocks (rows with mask M) x (columns U_M)
@@ -323,6 +331,7 @@ uint64_t theta_hash(const gp_theta* th);
 SolveResult minres_solve(gp_ctx* c, gp_matrix* m, const double* yb, double* xb, bool warm, double rtol, int max_iter,
                          int precond);
 void build_block_jacobi(gp_ctx* c, gp_matrix* m);
+void free_quads(gp_ctx* c, gp_matrix* m);
 void free_block_jacobi(gp_ctx* c, gp_matrix* m);
 
 struct LogdetResult {

@@ -673,6 +673,285 @@ __global__ void __launch_bounds__(kThreads) k_group_reduce(const int32_t* __rest
 
 }  // namespace
 
+namespace {
+
+// ------------------------------------------------------------ row quads
+constexpr int kQuad = 4;
+
+// orders the LDS accesses of one wave (its own slice; no block barrier)
+__device__ __forceinline__ void wave_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// The CSR-part column lists of the rows of group g (rows with more than
+// kLongRow entries count as empty): begin and end of each.
+__device__ __forceinline__ void quad_lists(int64_t n, int64_t g, const int64_t* __restrict__ rp,
+                                           const int32_t* __restrict__ gskip, int64_t (&h)[kQuad],
+                                           int64_t (&e)[kQuad]) {
+#pragma unroll
+  for (int i = 0; i < kQuad; ++i) {
+    const int64_t r = g * kQuad + i;
+    h[i] = e[i] = 0;
+    if (r < n) {
+      const int64_t s = rp[r] + gskip[r], t = rp[r + 1];
+      if (t - s <= kLongRow) {
+        h[i] = s;
+        e[i] = t;
+      }
+    }
+  }
+}
+
+// first index of list[0, len) with list[i] >= c (lower) or > c (upper)
+template <bool UPPER>
+__device__ __forceinline__ int list_bound(const int32_t* lst, int len, int32_t c) {
+  int lo = 0, hi = len;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (UPPER ? lst[mid] <= c : lst[mid] < c)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+// One wave per group.  The four rows' CSR-part column lists (ascending, at
+// most kLongRow each) are loaded into the wave's LDS slice; every entry (row
+// i, position j, column c) finds its place in the merged order by (column,
+// row): j plus, in each other row k, the number of columns < c (k > i) or
+// <= c (k < i).  Equal columns are then adjacent, at most one per row; the
+// first of each run starts a union entry, numbered by a ballot scan.
+// PASS 0 writes the union length of each group, PASS 1 the ascending union
+// with the four rows' values (0 where a row lacks the column).
+constexpr int kQuadMax = kQuad * kLongRow;
+
+template <typename VT, int PASS>
+__global__ void __launch_bounds__(kThreads) k_quad_build(int64_t n, int64_t ngroups, const int64_t* __restrict__ rp,
+                                                         const int32_t* __restrict__ gskip,
+                                                         const int32_t* __restrict__ col, const VT* __restrict__ val,
+                                                         int32_t* __restrict__ cnt, const int64_t* __restrict__ qptr,
+                                                         int32_t* __restrict__ qcol, VT* __restrict__ qval) {
+  __shared__ int32_t lc[kThreads / kWave][kQuad][kLongRow];
+  __shared__ int32_t mc[kThreads / kWave][kQuadMax];
+  __shared__ int16_t mij[kThreads / kWave][kQuadMax];  // row * kLongRow + position
+  const int lane = lane_id(), w = threadIdx.x / kWave;
+  const int64_t g = blockIdx.x * static_cast<int64_t>(kThreads / kWave) + w;
+  if (g >= ngroups) return;  // uniform over the wave
+  int64_t h[kQuad], e[kQuad];
+  quad_lists(n, g, rp, gskip, h, e);
+  int len[kQuad], off[kQuad + 1];
+  off[0] = 0;
+#pragma unroll
+  for (int i = 0; i < kQuad; ++i) {
+    len[i] = static_cast<int>(e[i] - h[i]);
+    off[i + 1] = off[i] + len[i];
+  }
+  const int T = off[kQuad];
+#pragma unroll
+  for (int i = 0; i < kQuad; ++i)
+    for (int j = lane; j < len[i]; j += kWave) lc[w][i][j] = col[h[i] + j];
+  wave_sync_lds();
+  for (int t = lane; t < T; t += kWave) {
+    int i = 0;
+#pragma unroll
+    for (int k = 1; k < kQuad; ++k)
+      if (t >= off[k]) i = k;
+    const int j = t - off[i];
+    const int32_t c = lc[w][i][j];
+    int pos = j;
+#pragma unroll
+    for (int k = 0; k < kQuad; ++k) {
+      if (k < i) pos += list_bound<true>(lc[w][k], len[k], c);
+      if (k > i) pos += list_bound<false>(lc[w][k], len[k], c);
+    }
+    mc[w][pos] = c;
+    mij[w][pos] = static_cast<int16_t>(i * kLongRow + j);
+  }
+  wave_sync_lds();
+  int64_t out0 = PASS == 1 ? qptr[g] : 0;
+  int running = 0;
+  for (int b = 0; b < T; b += kWave) {
+    const int p = b + lane;
+    const bool first = p < T && (p == 0 || mc[w][p] != mc[w][p - 1]);
+    const uint64_t bal = __ballot(first);
+    if constexpr (PASS == 1) {
+      if (first) {
+        const int64_t out = out0 + running + __popcll(bal & lanes_below());
+        const int32_t c = mc[w][p];
+        VT v[kQuad];
+#pragma unroll
+        for (int i = 0; i < kQuad; ++i) v[i] = VT(0);
+#pragma unroll
+        for (int d = 0; d < kQuad; ++d) {
+          if (p + d < T && mc[w][p + d] == c) {
+            const int ij = mij[w][p + d];
+            const int row = ij / kLongRow, j = ij % kLongRow;
+#pragma unroll
+            for (int i = 0; i < kQuad; ++i)
+              if (row == i) v[i] = val[h[i] + j];
+          }
+        }
+        qcol[out] = c;
+#pragma unroll
+        for (int i = 0; i < kQuad; ++i) qval[out * kQuad + i] = v[i];
+      }
+    }
+    running += __popcll(bal);
+  }
+  if constexpr (PASS == 0)
+    if (lane == 0) cnt[g] = running;
+}
+
+// CSR part of Y = S K S X D for the short rows, four rows at a time (four
+// consecutive binned rows share most of their local columns: at the
+// space-time workload a union entry serves 1.9 row entries): lane l
+// stages union entry j0 + l of the group (column id and the four rows'
+// weights, times the column's scale) in the wave's LDS slice; then each
+// 16-byte load of an X row serves all four rows.  The same column split as
+// spmm_consume16 (lane l: kCpl columns of entry slot l / kLpe), slot sums in
+// a fixed order, group part added from Y.
+constexpr int kQuadsPerWave = 2;
+constexpr int kQuadUq = 2;  // X loads in flight per lane (two keep the kernel at 68 registers)
+
+template <typename VT, bool SCALE>
+__global__ void __launch_bounds__(kThreads) k_spmm_quad(int64_t n, int64_t ngroups, const int64_t* __restrict__ qptr,
+                                                        const int32_t* __restrict__ qcol,
+                                                        const VT* __restrict__ qval, const int64_t* __restrict__ rp,
+                                                        const int32_t* __restrict__ gskip, int k, int ld,
+                                                        const double* __restrict__ X, double* __restrict__ Y,
+                                                        const double* __restrict__ scale,
+                                                        const double* __restrict__ colscale) {
+  using V = Vec16<double>;
+  __shared__ int32_t sq[kThreads / kWave][kWave];
+  __shared__ double sv[kThreads / kWave][kWave][kQuad];
+  const int lane = lane_id(), w = threadIdx.x / kWave;
+  const int gs_lane = lane / V::kLpe, cp = lane % V::kLpe;
+  double csv[V::kCpl];
+#pragma unroll
+  for (int t = 0; t < V::kCpl; ++t) csv[t] = colscale ? colscale[min(cp * V::kCpl + t, k - 1)] : 1.0;
+  const int64_t wave = static_cast<int64_t>(xcd_remap(blockIdx.x, gridDim.x)) * (kThreads / kWave) + w;
+  for (int gi = 0; gi < kQuadsPerWave; ++gi) {
+    const int64_t g = wave * kQuadsPerWave + gi;
+    if (g >= ngroups) return;  // uniform over the wave
+    const int64_t s = qptr[g], e = qptr[g + 1];
+    V acc[kQuad];
+#pragma unroll
+    for (int r = 0; r < kQuad; ++r)
+#pragma unroll
+      for (int t = 0; t < V::kCpl; ++t) acc[r].v[t] = 0;
+    for (int64_t j0 = s; j0 < e; j0 += kWave) {
+      const int m = static_cast<int>(min<int64_t>(kWave, e - j0));
+      wave_sync_lds();  // the previous chunk has been read
+      {
+        int32_t q = 0;
+        double v[kQuad] = {};
+        if (lane < m) {
+          q = qcol[j0 + lane];
+          const double sc = SCALE ? scale[q] : 1.0;
+#pragma unroll
+          for (int r = 0; r < kQuad; ++r) v[r] = static_cast<double>(qval[(j0 + lane) * kQuad + r]) * sc;
+        }
+        sq[w][lane] = q;
+#pragma unroll
+        for (int r = 0; r < kQuad; ++r) sv[w][lane][r] = v[r];
+      }
+      wave_sync_lds();
+      const int nq = (m + V::kEpi - 1) / V::kEpi;
+      for (int i0 = 0; i0 < nq; i0 += kQuadUq) {
+        int32_t qq[kQuadUq];
+        double vv[kQuadUq][kQuad];
+#pragma unroll
+        for (int u = 0; u < kQuadUq; ++u) {
+          const int idx = (V::kEpi * (i0 + u) + gs_lane) & (kWave - 1);  // past m: q = 0, weights 0
+          qq[u] = sq[w][idx];
+#pragma unroll
+          for (int r = 0; r < kQuad; ++r) vv[u][r] = (i0 + u < nq) ? sv[w][idx][r] : 0.0;
+        }
+        V xv[kQuadUq];
+#pragma unroll
+        for (int u = 0; u < kQuadUq; ++u)
+          __builtin_memcpy(xv[u].v, X + static_cast<int64_t>(qq[u]) * ld + cp * V::kCpl, 16);
+#pragma unroll
+        for (int u = 0; u < kQuadUq; ++u)
+#pragma unroll
+          for (int r = 0; r < kQuad; ++r)
+#pragma unroll
+            for (int t = 0; t < V::kCpl; ++t) acc[r].v[t] += vv[u][r] * xv[u].v[t];
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < kQuad; ++r) {
+      const int64_t row = g * kQuad + r;
+      slot_sum<double>(acc[r]);
+      if (row >= n) continue;
+      const int64_t rs = rp[row] + gskip[row], re = rp[row + 1];
+      if (re - rs > kLongRow) continue;  // written by the long-row blocks
+      if (lane < V::kLpe) {
+        const int32_t gsk = gskip[row];
+        double* yr = Y + row * ld + lane * V::kCpl;
+#pragma unroll
+        for (int t = 0; t < V::kCpl; ++t) {
+          if (lane * V::kCpl + t >= k) break;
+          double a = acc[r].v[t];
+          if (gsk) a = yr[t] + a;
+          if constexpr (SCALE) a *= scale[row];
+          if (colscale) a *= csv[t];
+          yr[t] = a;
+        }
+      }
+    }
+  }
+}
+
+}  // namespace
+
+void free_quads(gp_ctx* c, gp_matrix* m) {
+  const size_t vbytes = m->prec == GP_MIXED ? sizeof(float) : sizeof(double);
+  const int64_t ng = (m->n + kQuad - 1) / kQuad;
+  if (m->qptr) dev_free(c, m->qptr, sizeof(int64_t) * (ng + 1));
+  if (m->qcol) dev_free(c, m->qcol, sizeof(int32_t) * std::max<int64_t>(m->nquad, 1));
+  if (m->qval) dev_free(c, m->qval, vbytes * kQuad * std::max<int64_t>(m->nquad, 1));
+  m->qptr = nullptr;
+  m->qcol = nullptr;
+  m->qval = nullptr;
+  m->nquad = 0;
+}
+
+static void build_quads(gp_ctx* c, gp_matrix* m) {
+  if (m->qptr) return;
+  const int64_t n = m->n, ng = (n + kQuad - 1) / kQuad;
+  try {
+    int32_t* cnt = static_cast<int32_t*>(workspace(c, 122, sizeof(int32_t) * ng));
+    m->qptr = dev_new<int64_t>(c, ng + 1);
+    auto go = [&](auto vt) {
+      using VT = decltype(vt);
+      const VT* val = static_cast<const VT*>(m->val);
+      const unsigned nbb = grid_for(ng, kThreads / kWave);
+      hipLaunchKernelGGL((k_quad_build<VT, 0>), dim3(nbb), dim3(kThreads), 0, c->stream, n, ng,
+                         m->row_ptr, m->gskip, m->col, val, cnt, nullptr, nullptr, nullptr);
+      check_launch("quad count");
+      scan_i32_to_i64(c, cnt, m->qptr, ng);
+      m->nquad = read_i64(c, m->qptr + ng);
+      m->qcol = dev_new<int32_t>(c, std::max<int64_t>(m->nquad, 1));
+      m->qval = dev_alloc(c, sizeof(VT) * kQuad * std::max<int64_t>(m->nquad, 1));
+      hipLaunchKernelGGL((k_quad_build<VT, 1>), dim3(nbb), dim3(kThreads), 0, c->stream, n, ng,
+                         m->row_ptr, m->gskip, m->col, val, nullptr, m->qptr, m->qcol, static_cast<VT*>(m->qval));
+      check_launch("quad fill");
+      m->bytes += sizeof(int64_t) * (ng + 1) + (sizeof(int32_t) + sizeof(VT) * kQuad) * m->nquad;
+    };
+    if (m->prec == GP_MIXED)
+      go(float{});
+    else
+      go(double{});
+  } catch (...) {
+    free_quads(c, m);
+    throw;
+  }
+}
+
 template <typename T>
 void spmm(gp_ctx* c, const gp_matrix* m, int k, int ld, const T* X, T* Y, const T* scale, const double* colscale) {
   if (k > 32 || ld < k) throw Error{GP_EINVAL, "spmm: at most 32 right-hand sides per call"};
@@ -695,6 +974,23 @@ void spmm(gp_ctx* c, const gp_matrix* m, int k, int ld, const T* X, T* Y, const 
     }
     // 16-byte X loads need rows of at least 32 values at 16-byte alignment
     const bool vec = ld >= 32 && (ld * sizeof(T)) % 16 == 0 && reinterpret_cast<uintptr_t>(X) % 16 == 0;
+    if constexpr (std::is_same<T, double>::value) {
+      if (vec) {
+        gp_matrix* mm = const_cast<gp_matrix*>(m);  // the quads are a cache of the matrix
+        build_quads(c, mm);
+        const int64_t ng = (m->n + kQuad - 1) / kQuad;
+        const unsigned nbq = static_cast<unsigned>(
+            round_up8(grid_for((ng + kQuadsPerWave - 1) / kQuadsPerWave, kThreads / kWave)));
+        hipLaunchKernelGGL((k_spmm_quad<VT, SC>), dim3(nbq), dim3(kThreads), 0, c->stream, m->n, ng, mm->qptr,
+                           mm->qcol, static_cast<const VT*>(mm->qval), m->row_ptr, m->gskip, k, ld, X, Y, scale,
+                           colscale);
+        if (m->n_long > 0)
+          hipLaunchKernelGGL((k_spmm<VT, T, SC, true>), dim3(static_cast<unsigned>(m->n_long)), dim3(kThreads), 0,
+                             c->stream, m->n, 0u, m->n_long, m->long_rows, k, ld, m->row_ptr, m->gskip, m->col,
+                             static_cast<const VT*>(m->val), X, Y, scale, colscale);
+        return;
+      }
+    }
     if (vec)
       hipLaunchKernelGGL((k_spmm<VT, T, SC, true>), dim3(nb), dim3(kThreads), 0, c->stream, m->n, nb_short,
                          m->n_long, m->long_rows, k, ld, m->row_ptr, m->gskip, m->col, static_cast<const VT*>(m->val),
