@@ -265,9 +265,13 @@ class GpuBackend(Backend):
             ds, _ = self.datasets[req.dataset]
             n = ds.n
             vb = 4 if req.precision == 1 else 8
-            csr = n * self.row_estimate[req.dataset] * (4 + vb) + 24 * n
+            nnz = n * self.row_estimate[req.dataset]
+            csr = nnz * (4 + vb) + 24 * n
+            # row quads of the 32-column products: one union entry (a column id
+            # and four values) per 1.5 nonzeros or fewer
+            quads = nnz / 1.5 * (4 + 4 * vb)
             work = n * (3 * 32 * 8 + 8 * 8 + 16)   # Lanczos blocks + CG vectors + binning scratch
-            return int(csr + work)
+            return int(csr + quads + work)
         return int(_npts(req.xs) * (8 * 3 + 8) + (1 << 16))
 
     def run_loglik(self, slot: int, req: LoglikRequest):
