@@ -343,11 +343,12 @@ GP_API gp_status gp_mean_residual(gp_ctx* ctx, int64_t n, int32_t p, const doubl
  * enters K only and is not read here).  The test points
  * (xstar_dev: m x d row-major float64, device) are taken 32 at a time: their
  * cross-covariance columns are formed on the device and K W = C is solved by
- * 32 Jacobi-preconditioned conjugate-gradient recurrences in lockstep (one
- * sparse product with 32 columns per step, float64 vectors, the matrix's
- * stored values), each stopping when |c_s - K w_s| <= opts->rtol |c_s|; a
- * float64 true residual is taken at the end.  opts may be NULL (defaults;
- * rtol and max_iter are used).  Work space: six n x 32 float64 blocks.
+ * 32 preconditioned conjugate-gradient recurrences in lockstep (one sparse
+ * product with 32 columns per step, float64 vectors, the matrix's stored
+ * values; opts->precond: block Jacobi, the default, or Jacobi), each stopping
+ * when |c_s - K w_s| <= opts->rtol |c_s|; a float64 true residual is taken at
+ * the end.  opts may be NULL (defaults; rtol, max_iter and precond are used).
+ * Work space: seven n x 32 float64 blocks.
  * out (may be NULL) receives iteration counts and the largest final relative
  * residual.
  * Errors: GP_EINVAL (theta differs from K's, m < 0, NULL buffers),

@@ -538,7 +538,7 @@ gp_status gp_predict_var(gp_ctx* c, const gp_matrix* K, const gp_theta* th, int6
     GPS_REQUIRE(m >= 0, GP_EINVAL, "gp_predict_var: m must be >= 0");
     GPS_REQUIRE(m == 0 || (xs && var), GP_EINVAL, "gp_predict_var: NULL buffer");
     const gp_solve_opts o = fill_opts(opts);
-    const gps::VarResult r = gps::predict_variance(c, K, th, m, xs, o.rtol, o.max_iter, var);
+    const gps::VarResult r = gps::predict_variance(c, K, th, m, xs, o.rtol, o.max_iter, o.precond, var);
     gps::sync(c);
     if (out) {
       out->iters = r.iters;

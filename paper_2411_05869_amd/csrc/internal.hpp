@@ -322,7 +322,7 @@ struct VarResult {
   gp_status st = GP_OK;
 };
 VarResult predict_variance(gp_ctx* c, const gp_matrix* m, const gp_theta* th, int64_t ntest, const double* xs,
-                           double rtol, int max_iter, double* var);
+                           double rtol, int max_iter, int precond, double* var);
 // y = z - W beta (W: n x p column-major, device; beta: p values, host)
 void mean_residual(gp_ctx* c, int64_t n, int p, const double* W, const double* beta_host, const double* z,
                    double* y);

@@ -7,7 +7,8 @@
 //      (Wendland) entries of its cell window, then a wave per test point adds
 //      the bump-group entries over the masked training points;
 //   2. K W = X is solved by 32 conjugate-gradient recurrences in lockstep
-//      (one SpMM per step; Jacobi preconditioner; per-column scalars; a column
+//      (one SpMM per step; block-Jacobi or Jacobi preconditioner; per-column
+//      scalars; a column
 //      stops changing once |r_s| <= rtol |c_s|), with a float64 true residual
 //      X - K W at the end (the recurrences restart from it if it is not small
 //      enough);
@@ -226,6 +227,31 @@ __device__ __forceinline__ void col_totals(const double* __restrict__ part, int 
   }
 }
 
+// Preconditioner of the recurrences: the matrix diagonal, or (binv set) the
+// block-Jacobi inverses over the binning cells (row-major per block).  Row i of
+// z = M^-1 r needs r on the rows of its block; the caller passes a function
+// that forms r for any row, so every thread sees the same values without
+// waiting for the others.
+struct VarPrecond {
+  const double* diag;
+  const int32_t* rowblk;
+  const int32_t* bstart;
+  const int64_t* boff;
+  const double* binv;
+};
+
+template <typename F>
+__device__ __forceinline__ double var_precond(const VarPrecond& M, int64_t i, double ri, F&& r_at) {
+  if (!M.binv) return ri / M.diag[i];
+  const int32_t b = M.rowblk[i];
+  const int32_t bs = M.bstart[b];
+  const int sz = M.bstart[b + 1] - bs;
+  const double* row = M.binv + M.boff[b] + static_cast<int64_t>(i - bs) * sz;
+  double z = 0.0;
+  for (int j = 0; j < sz; ++j) z += row[j] * r_at(bs + j);
+  return z;
+}
+
 #define ROW_LOOP(n)                                                                                 \
   for (int64_t i = static_cast<int64_t>(blockIdx.x) * kRowsPer + threadIdx.x / kC; i < (n);       \
        i += static_cast<int64_t>(gridDim.x) * kRowsPer)
@@ -233,15 +259,16 @@ __device__ __forceinline__ void col_totals(const double* __restrict__ part, int 
 // R = X - KW (KW given, or W = 0 when kw is null); Z = R / diag; P = Z;
 // partials of r.z and r.r
 __global__ void __launch_bounds__(kThreads) k_bcg_start(int64_t n, const double* __restrict__ X,
-                                                        const double* __restrict__ kw, const double* __restrict__ diag,
+                                                        const double* __restrict__ kw, VarPrecond M,
                                                         double* __restrict__ R, double* __restrict__ Z,
                                                         double* __restrict__ P, double* __restrict__ part) {
   const int col = threadIdx.x % kC;
   double v[2] = {0.0, 0.0};
   ROW_LOOP(n) {
     const int64_t e = i * kC + col;
-    const double r = kw ? X[e] - kw[e] : X[e];
-    const double z = r / diag[i];
+    auto r_at = [&](int64_t q) { return kw ? X[q * kC + col] - kw[q * kC + col] : X[q * kC + col]; };
+    const double r = r_at(i);
+    const double z = var_precond(M, i, r, r_at);
     R[e] = r;
     Z[e] = z;
     P[e] = z;
@@ -302,21 +329,25 @@ __global__ void __launch_bounds__(kFinThreads) k_bcg_alpha(const double* __restr
   S->alpha[col] = a;
 }
 
-// W += alpha P; R -= alpha Q; Z = R / diag; partials of r.z and r.r
+// W += alpha P; Rout = Rin - alpha Q; Z = M^-1 Rout; partials of r.z and r.r.
+// The residual alternates between two buffers: the block product reads the
+// old residual of the neighbouring rows, which no thread overwrites.
 __global__ void __launch_bounds__(kThreads) k_bcg_update(int64_t n, const BcgScalars* __restrict__ S,
                                                          const double* __restrict__ P, const double* __restrict__ Q,
-                                                         const double* __restrict__ diag, double* __restrict__ W,
-                                                         double* __restrict__ R, double* __restrict__ Z,
-                                                         double* __restrict__ part) {
+                                                         VarPrecond M, double* __restrict__ W,
+                                                         const double* __restrict__ Rin, double* __restrict__ Rout,
+                                                         double* __restrict__ Z, double* __restrict__ part) {
   const int col = threadIdx.x % kC;
   const double a = S->alpha[col];
   double v[2] = {0.0, 0.0};
   ROW_LOOP(n) {
     const int64_t e = i * kC + col;
-    const double r = R[e] - a * Q[e];
-    const double z = r / diag[i];
+    // the new residual of any row of the block, formed as for the row itself
+    auto r_at = [&](int64_t q) { return Rin[q * kC + col] - a * Q[q * kC + col]; };
+    const double r = r_at(i);
+    const double z = var_precond(M, i, r, r_at);
     W[e] += a * P[e];
-    R[e] = r;
+    Rout[e] = r;
     Z[e] = z;
     v[0] += r * z;
     v[1] += r * r;
@@ -401,9 +432,19 @@ void dispatch_dk(int d, int kind, F3&& f) {
 }  // namespace
 
 VarResult predict_variance(gp_ctx* c, const gp_matrix* m, const gp_theta* th, int64_t ntest, const double* xs,
-                           double rtol, int max_iter, double* var) {
+                           double rtol, int max_iter, int precond, double* var) {
   VarResult res;
   if (ntest == 0) return res;
+  VarPrecond M{m->diag, nullptr, nullptr, nullptr, nullptr};
+  if (precond == GP_PRECOND_BLOCK_JACOBI) {
+    // the inverses are cached in the matrix object on first use
+    gp_matrix* mm = const_cast<gp_matrix*>(m);
+    build_block_jacobi(c, mm);
+    M.rowblk = mm->rowblk;
+    M.bstart = mm->bstart;
+    M.boff = mm->boff;
+    M.binv = mm->binv;
+  }
   const gp_dataset* ds = m->ds;
   const int64_t n = m->n;
   const int d = ds->d;
@@ -441,6 +482,7 @@ VarResult predict_variance(gp_ctx* c, const gp_matrix* m, const gp_theta* th, in
   const size_t blk = sizeof(double) * n * kC;
   double* X = static_cast<double*>(workspace(c, 110, blk));
   double* R = static_cast<double*>(workspace(c, 111, blk));
+  double* R2 = static_cast<double*>(workspace(c, 119, blk));  // the residual alternates between R and R2
   double* Z = static_cast<double*>(workspace(c, 112, blk));
   double* P = static_cast<double*>(workspace(c, 113, blk));
   double* Q = static_cast<double*>(workspace(c, 114, blk));
@@ -473,7 +515,7 @@ VarResult predict_variance(gp_ctx* c, const gp_matrix* m, const gp_theta* th, in
       check_launch("variance cross-covariance");
     }
     hipLaunchKernelGGL(k_zero, dim3(grid_for(n * kC, kThreads)), B, 0, c->stream, n * kC, W);
-    hipLaunchKernelGGL(k_bcg_start, G, B, 0, c->stream, n, X, nullptr, m->diag, R, Z, P, part);
+    hipLaunchKernelGGL(k_bcg_start, G, B, 0, c->stream, n, X, nullptr, M, R, Z, P, part);
     hipLaunchKernelGGL(k_bcg_start_fin, dim3(1), FB, 0, c->stream, part, static_cast<int>(nbv), S, tol2, 0);
     check_launch("variance start");
     BcgScalars hsc = read();
@@ -488,7 +530,7 @@ VarResult predict_variance(gp_ctx* c, const gp_matrix* m, const gp_theta* th, in
         // recurrences done: check the float64 true residual, restart once it is not small enough
         if (refresh >= kMaxRefresh) break;
         spmm<double>(c, m, kC, kC, W, Q, nullptr);
-        hipLaunchKernelGGL(k_bcg_start, G, B, 0, c->stream, n, X, Q, m->diag, R, Z, P, part);
+        hipLaunchKernelGGL(k_bcg_start, G, B, 0, c->stream, n, X, Q, M, R, Z, P, part);
         hipLaunchKernelGGL(k_bcg_start_fin, dim3(1), FB, 0, c->stream, part, static_cast<int>(nbv), S, tol2, 1);
         check_launch("variance restart");
         ++refresh;
@@ -502,7 +544,8 @@ VarResult predict_variance(gp_ctx* c, const gp_matrix* m, const gp_theta* th, in
         ProfScope ps(c, "var_vector_ops");
         hipLaunchKernelGGL(k_bcg_pq, G, B, 0, c->stream, n, P, Q, part);
         hipLaunchKernelGGL(k_bcg_alpha, dim3(1), FB, 0, c->stream, part, static_cast<int>(nbv), S);
-        hipLaunchKernelGGL(k_bcg_update, G, B, 0, c->stream, n, S, P, Q, m->diag, W, R, Z, part);
+        hipLaunchKernelGGL(k_bcg_update, G, B, 0, c->stream, n, S, P, Q, M, W, R, R2, Z, part);
+        std::swap(R, R2);
         hipLaunchKernelGGL(k_bcg_beta, dim3(1), FB, 0, c->stream, part, static_cast<int>(nbv), S, tol2);
         hipLaunchKernelGGL(k_bcg_dir, G, B, 0, c->stream, n, S, Z, P);
         check_launch("variance step");
