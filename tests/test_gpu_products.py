@@ -10,8 +10,10 @@ float32 (relative error <= 2^-24) and multiplies in float64, so its bound is
 sqrt(row length) 2^-24).  Sizes: config 1 (n = 2000; several tiles, a ragged tail, dense
 group rows) with 1, 2, 7 and 32 right-hand sides, and the n = 1,095,000
 space-time workload on sampled rows (oracle rows one at a time, the launch
-configuration of the benchmark).  Shape errors in the binding are refused
-before any device work."""
+configuration of the benchmark), and n = 1003 (an incomplete last group of four
+rows for the 32-column path) with a dense cluster of rows longer than 128
+entries beside short ones.  Shape errors in the binding are refused before any
+device work."""
 import numpy as np
 import pytest
 
@@ -100,3 +102,25 @@ def test_binding_refuses_bad_shapes(ctx):
         ctx.predict_var(K, p.theta, dev(np.zeros(10)))
     with pytest.raises(ValueError):
         ctx.mean_residual(None, [], dev(np.zeros(p.n)), out=torch.zeros(3, dtype=torch.float64, device="cuda"))
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("k", [1, 7, 32])
+def test_products_ragged_and_long_rows(ctx, prec, k):
+    # n = 1003 (the last group of four rows is incomplete) and a dense cluster
+    # whose rows hold more than 128 local entries (the long-row path), next to
+    # scattered short rows
+    from workloads import Problem, Theta
+    rng = np.random.default_rng(77)
+    x = np.concatenate([0.5 + 0.03 * rng.standard_normal((500, 2)), rng.random((503, 2))])
+    th = Theta(1.0, np.array([0.04, 0.04]), np.array([[[0.2, 0.8]], [[0.8, 0.2]]]), np.full((2, 1, 2), 0.15),
+               np.ones((2, 1)), np.ones((2, 1)), 0.05)
+    p = Problem("ragged-long", x, th, cell=None)
+    A = kernel.to_scipy(*kernel.sparse(p.x, p.theta), p.n)
+    lens = np.diff(A.indptr)
+    assert p.n % 4 != 0 and lens.max() > 128 and lens.min() < 128
+    X = rng.standard_normal((p.n, k)) if k > 1 else rng.standard_normal(p.n)
+    ds = ctx.dataset(dev(p.x))
+    K = ctx.assemble(ds, p.theta, prec)
+    Y = host(ctx.matvec(K, dev(X)))
+    _check_rows(Y, A @ X, abs(A) @ np.abs(X), prec, f"ragged/long prec={prec} k={k} (rows > 128: {(lens > 128).sum()})")
