@@ -124,3 +124,32 @@ def test_products_ragged_and_long_rows(ctx, prec, k):
     K = ctx.assemble(ds, p.theta, prec)
     Y = host(ctx.matvec(K, dev(X)))
     _check_rows(Y, A @ X, abs(A) @ np.abs(X), prec, f"ragged/long prec={prec} k={k} (rows > 128: {(lens > 128).sum()})")
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 6])
+def test_tiny_sizes(ctx, n):
+    # fewer points than one group of four rows, and one or two groups: the
+    # products (1 and 32 columns) and a whole log-likelihood (CG, SLQ and
+    # the exact mode) against the oracle's dense matrix
+    from oracle import likelihood
+    from paper_2411_05869_amd import LOGDET_EXACT
+    from workloads import uniform_problem
+    p = uniform_problem(n, 2, 90 + n, r0=0.6, n1=1, n2=1, bump_radius=0.5)
+    A = kernel.to_scipy(*kernel.sparse(p.x, p.theta), p.n)
+    Kd = A.toarray()
+    rng = np.random.default_rng(n)
+    ds = ctx.dataset(dev(p.x))
+    K = ctx.assemble(ds, p.theta, 0)
+    for k in (1, 32):
+        X = rng.standard_normal((p.n, k)) if k > 1 else rng.standard_normal(p.n)
+        Y = host(ctx.matvec(K, dev(X)))
+        _check_rows(Y, A @ X, abs(A) @ np.abs(X), 0, f"n={n} k={k}")
+    y = rng.standard_normal(p.n)
+    ref = likelihood.dense_cholesky(Kd, y)
+    for mode in (0, LOGDET_EXACT):
+        r = ctx.loglik(K, dev(y), logdet_mode=mode)
+        print(f"[tiny n={n} mode={mode}] loglik {r['loglik']:.12g} ref {ref['loglik']:.12g} steps {r['lanczos_steps']}")
+        assert r["status"] == 0
+        assert abs(r["quad"] - ref["quad"]) <= 1e-10 * abs(ref["quad"])
+        if mode == LOGDET_EXACT or n == 1:  # one point: the probe estimate is exact
+            assert abs(r["logdet"] - ref["logdet"]) <= 1e-10 * max(1.0, abs(ref["logdet"]))
