@@ -333,8 +333,8 @@ def main():
         summarize_pmc(*args.summarize_pmc)
         return
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
-              "(the single-GPU path is the product; multi-GPU sharding is described in DESIGN.md)", file=sys.stderr)
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the library runs on one GPU; "
+              "sharding the rows across GPUs is not implemented)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
