@@ -89,7 +89,9 @@ __global__ void __launch_bounds__(kThreads) k_spmv(int64_t n, unsigned nb_long, 
 }
 
 // SpMM, Y = S K S X (S = diag(scale), or K X without scale), k <= 32 columns of
-// a row-major block with leading dimension ld.
+// a row-major block with leading dimension ld: the CSR part row by row.  With
+// 16-byte X loads (VEC) only its long-row blocks run (nb_short = 0); the
+// short rows then go through the row quads (k_spmm_quad).
 //
 // A wave stages 64 consecutive entries of a row at a time: lane l loads entry
 // l (column id and value * scale[column]) with one coalesced access.  The
@@ -922,6 +924,7 @@ void free_quads(gp_ctx* c, gp_matrix* m) {
 
 static void build_quads(gp_ctx* c, gp_matrix* m) {
   if (m->qptr) return;
+  ProfScope ps(c, "quad_build");
   const int64_t n = m->n, ng = (n + kQuad - 1) / kQuad;
   try {
     int32_t* cnt = static_cast<int32_t*>(workspace(c, 122, sizeof(int32_t) * ng));
@@ -954,7 +957,12 @@ static void build_quads(gp_ctx* c, gp_matrix* m) {
 
 template <typename T>
 void spmm(gp_ctx* c, const gp_matrix* m, int k, int ld, const T* X, T* Y, const T* scale, const double* colscale) {
+  static_assert(std::is_same<T, double>::value, "the products take float64 vectors");
   if (k > 32 || ld < k) throw Error{GP_EINVAL, "spmm: at most 32 right-hand sides per call"};
+  // 16-byte X loads need rows of at least 32 values at 16-byte alignment
+  const bool vec = ld >= 32 && (ld * sizeof(T)) % 16 == 0 && reinterpret_cast<uintptr_t>(X) % 16 == 0;
+  gp_matrix* mm = const_cast<gp_matrix*>(m);  // the quads are a cache of the matrix
+  if (vec) build_quads(c, mm);
   ProfScope ps(c, "spmm");
   // partial blocks of the pieces of multi-piece super-tiles
   T* part = m->npieces > 0 ? static_cast<T*>(workspace(c, 55, sizeof(T) * kSuperRows * 32 * m->npieces)) : nullptr;
@@ -972,33 +980,23 @@ void spmm(gp_ctx* c, const gp_matrix* m, int k, int ld, const T* X, T* Y, const 
                          dim3(kThreads), 0, c->stream,
                          st, m->g_rows, k, ld, part, Y);
     }
-    // 16-byte X loads need rows of at least 32 values at 16-byte alignment
-    const bool vec = ld >= 32 && (ld * sizeof(T)) % 16 == 0 && reinterpret_cast<uintptr_t>(X) % 16 == 0;
-    if constexpr (std::is_same<T, double>::value) {
-      if (vec) {
-        gp_matrix* mm = const_cast<gp_matrix*>(m);  // the quads are a cache of the matrix
-        build_quads(c, mm);
-        const int64_t ng = (m->n + kQuad - 1) / kQuad;
-        const unsigned nbq = static_cast<unsigned>(
-            round_up8(grid_for((ng + kQuadsPerWave - 1) / kQuadsPerWave, kThreads / kWave)));
-        hipLaunchKernelGGL((k_spmm_quad<VT, SC>), dim3(nbq), dim3(kThreads), 0, c->stream, m->n, ng, mm->qptr,
-                           mm->qcol, static_cast<const VT*>(mm->qval), m->row_ptr, m->gskip, k, ld, X, Y, scale,
-                           colscale);
-        if (m->n_long > 0)
-          hipLaunchKernelGGL((k_spmm<VT, T, SC, true>), dim3(static_cast<unsigned>(m->n_long)), dim3(kThreads), 0,
-                             c->stream, m->n, 0u, m->n_long, m->long_rows, k, ld, m->row_ptr, m->gskip, m->col,
-                             static_cast<const VT*>(m->val), X, Y, scale, colscale);
-        return;
-      }
-    }
-    if (vec)
-      hipLaunchKernelGGL((k_spmm<VT, T, SC, true>), dim3(nb), dim3(kThreads), 0, c->stream, m->n, nb_short,
-                         m->n_long, m->long_rows, k, ld, m->row_ptr, m->gskip, m->col, static_cast<const VT*>(m->val),
-                         X, Y, scale, colscale);
-    else
+    if (vec) {
+      // short rows over the row quads; the long rows by k_spmm's block-per-row path
+      const int64_t ng = (m->n + kQuad - 1) / kQuad;
+      const unsigned nbq =
+          static_cast<unsigned>(round_up8(grid_for((ng + kQuadsPerWave - 1) / kQuadsPerWave, kThreads / kWave)));
+      hipLaunchKernelGGL((k_spmm_quad<VT, SC>), dim3(nbq), dim3(kThreads), 0, c->stream, m->n, ng, mm->qptr,
+                         mm->qcol, static_cast<const VT*>(mm->qval), m->row_ptr, m->gskip, k, ld, X, Y, scale,
+                         colscale);
+      if (m->n_long > 0)
+        hipLaunchKernelGGL((k_spmm<VT, T, SC, true>), dim3(static_cast<unsigned>(m->n_long)), dim3(kThreads), 0,
+                           c->stream, m->n, 0u, m->n_long, m->long_rows, k, ld, m->row_ptr, m->gskip, m->col,
+                           static_cast<const VT*>(m->val), X, Y, scale, colscale);
+    } else {
       hipLaunchKernelGGL((k_spmm<VT, T, SC, false>), dim3(nb), dim3(kThreads), 0, c->stream, m->n, nb_short,
                          m->n_long, m->long_rows, k, ld, m->row_ptr, m->gskip, m->col, static_cast<const VT*>(m->val),
                          X, Y, scale, colscale);
+    }
   };
   if (m->prec == GP_MIXED) {
     if (scale)
