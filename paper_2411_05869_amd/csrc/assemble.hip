@@ -944,9 +944,13 @@ gp_matrix* assemble(gp_ctx* c, const gp_dataset* ds, const gp_theta* th, int pre
   GPS_REQUIRE(m->nnz < (int64_t(1) << 40), GP_ENOMEM, "gp_assemble: too many nonzeros");
 
   const size_t vbytes = prec == GP_MIXED ? sizeof(float) : sizeof(double);
-  // 64 entries of padding: SpMV reads column ids and values in aligned groups of four
+  // 64 entries of padding: the products read column ids and values in groups
+  // of four that can run past a row's end.  The padding is zeroed: a value read
+  // there is multiplied by a zero weight, and 0 x (stale NaN or Inf) is NaN.
   m->col = dev_new<int32_t>(c, m->nnz + kCsrPad);
   m->val = dev_alloc(c, vbytes * (m->nnz + kCsrPad));
+  GPS_HIP(hipMemsetAsync(m->col + m->nnz, 0, sizeof(int32_t) * kCsrPad, c->stream));
+  GPS_HIP(hipMemsetAsync(static_cast<char*>(m->val) + vbytes * m->nnz, 0, vbytes * kCsrPad, c->stream));
   m->diag = dev_new<double>(c, n);
   m->long_rows = dev_new<int32_t>(c, std::max<int64_t>(m->n_long, 1));
   m->bytes += (sizeof(int32_t) + vbytes) * m->nnz + sizeof(double) * n + sizeof(int32_t) * m->n_long;
