@@ -221,7 +221,8 @@ GP_API gp_status gp_assemble(gp_ctx* ctx, const gp_dataset* ds, const gp_theta* 
                       gp_precision prec, gp_matrix** out);
 GP_API gp_status gp_matrix_destroy(gp_ctx* ctx, gp_matrix* m);
 /* n, nnz, bytes held by the matrix (CSR arrays, group tables and the caches
- * built on first use: block-Jacobi inverses, row quads), precision, longest row. */
+ * built on first use: int16 column offsets, block-Jacobi inverses, row
+ * quads), precision, longest row. */
 GP_API gp_status gp_matrix_info(const gp_matrix* m, int64_t* n, int64_t* nnz, size_t* bytes,
                          int32_t* prec, int64_t* max_row);
 /* Writes the matrix in ORIGINAL point order with ascending columns into
@@ -231,8 +232,10 @@ GP_API gp_status gp_matrix_export_csr(gp_ctx* ctx, const gp_matrix* m, int64_t* 
                                int32_t* col_dev, double* val_dev);
 /* Y = K X for nrhs right-hand sides, X and Y n x nrhs row-major float64 in
  * ORIGINAL point order (device).  Uses the matrix's value precision with
- * float64 accumulation.  The first product with 32 columns (nrhs = 32 here,
- * and the Lanczos blocks of gp_loglik) builds a cache kept with the matrix
+ * float64 accumulation.  The first one-column product stores the columns of
+ * the rows' local parts as int16 offsets from the row (2 bytes per nonzero;
+ * kept unless an offset does not fit).  The first product with 32 columns
+ * (nrhs = 32 here, and the Lanczos blocks of gp_loglik) builds a cache kept with the matrix
  * until it is destroyed: for every four consecutive binned rows the union of
  * their columns with the four rows' values (about 5 bytes per nonzero in the
  * mixed form, 9 in float64). */

@@ -482,6 +482,12 @@ class Matrix(_Obj):
         ctx._L.gp_matrix_info(h, C.byref(n), C.byref(nnz), C.byref(by), C.byref(pr), C.byref(mr))
         self.n, self.nnz, self.bytes, self.precision, self.max_row = n.value, nnz.value, by.value, pr.value, mr.value
 
+    def held_bytes(self) -> int:
+        """Device bytes the matrix holds now, including the caches built on first use."""
+        by = C.c_size_t()
+        self.ctx._L.gp_matrix_info(self._h, None, None, C.byref(by), None, None)
+        return by.value
+
     def _destroy(self):
         self.ctx._L.gp_matrix_destroy(self.ctx._h, self._h)
 

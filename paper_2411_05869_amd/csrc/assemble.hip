@@ -1029,6 +1029,7 @@ void destroy_matrix(gp_ctx* c, gp_matrix* m) {
   if (m->long_rows) dev_free(c, m->long_rows, sizeof(int32_t) * std::max<int64_t>(m->n_long, 1));
   free_block_jacobi(c, m);
   free_quads(c, m);
+  free_col16(c, m);
   if (m->gskip) dev_free(c, m->gskip, sizeof(int32_t) * m->n);
   if (m->g_uoff) dev_free(c, m->g_uoff, sizeof(int64_t) * (m->nD + 1));
   if (m->g_ulist) dev_free(c, m->g_ulist, sizeof(int32_t) * std::max<int64_t>(m->utotal, 1));

@@ -113,6 +113,10 @@ struct gp_matrix {
   double* diag = nullptr;       // n, diagonal of the stored matrix (float64)
   int32_t* long_rows = nullptr; // rows with more than kLongRow entries
   int64_t n_long = 0;
+  // column offsets col - row as int16 for the CSR part (nnz + kCsrPad), built
+  // on the first one-column product; null when an offset does not fit
+  int16_t* col16 = nullptr;
+  bool col16_tried = false;
   // row quads for the multi-column product, built on first use: for the
   // group of binned rows 4g .. 4g+3, the ascending union of their CSR-part
   // columns (rows with more than kLongRow entries left out) with the four
@@ -332,6 +336,7 @@ SolveResult minres_solve(gp_ctx* c, gp_matrix* m, const double* yb, double* xb, 
                          int precond);
 void build_block_jacobi(gp_ctx* c, gp_matrix* m);
 void free_quads(gp_ctx* c, gp_matrix* m);
+void free_col16(gp_ctx* c, gp_matrix* m);
 void free_block_jacobi(gp_ctx* c, gp_matrix* m);
 
 struct LogdetResult {

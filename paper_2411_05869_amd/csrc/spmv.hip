@@ -47,7 +47,32 @@ __device__ __forceinline__ AT spmv_part(int64_t s, int64_t e, int sub, int32_t s
   return acc;
 }
 
+// The same sum with the column ids stored as int16 offsets from the row.
+template <typename VT, typename XT, typename AT, int G>
+__device__ __forceinline__ AT spmv_part16(int64_t s, int64_t e, int sub, int32_t self, const int16_t* __restrict__ off,
+                                          const VT* __restrict__ val, const XT* __restrict__ x) {
+  AT acc = 0;
+  for (int64_t j0 = s + 4 * sub; j0 < e; j0 += 4 * G) {
+    int16_t o[4];
+    VT v[4];
+    __builtin_memcpy(o, off + j0, sizeof(o));
+    __builtin_memcpy(v, val + j0, sizeof(v));
+    int32_t c[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const bool in = j0 + u < e;
+      c[u] = in ? self + static_cast<int32_t>(o[u]) : self;
+      v[u] = in ? v[u] : VT(0);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc += static_cast<AT>(v[u]) * static_cast<AT>(x[c[u]]);
+  }
+  return acc;
+}
+
 // CSR part of the product (entries after each row's leading group entries).
+// With off16 (int16 offsets col - row, two bytes per entry instead of four)
+// the short rows read the offsets; the long rows always read col.
 // One launch: blocks [0, nb_long) take the listed long rows, one wave per row
 // (dispatched first, they set the tail); the remaining blocks take rows of at
 // most kLongRow entries with kG lanes per row.  Rows with group entries add
@@ -57,7 +82,8 @@ __global__ void __launch_bounds__(kThreads) k_spmv(int64_t n, unsigned nb_long, 
                                                    const int32_t* __restrict__ rows, const int64_t* __restrict__ rp,
                                                    const int32_t* __restrict__ gskip,
                                                    const int32_t* __restrict__ col, const VT* __restrict__ val,
-                                                   const XT* __restrict__ x, YT* __restrict__ y) {
+                                                   const XT* __restrict__ x, YT* __restrict__ y,
+                                                   const int16_t* __restrict__ off16) {
   if (blockIdx.x >= nb_long) {
     const unsigned b = xcd_remap(blockIdx.x - nb_long, gridDim.x - nb_long);
     const int64_t row = (b * static_cast<int64_t>(kThreads) + threadIdx.x) / kG;
@@ -66,7 +92,8 @@ __global__ void __launch_bounds__(kThreads) k_spmv(int64_t n, unsigned nb_long, 
       const int32_t gs = gskip[row];
       const int64_t s = rp[row] + gs, e = rp[row + 1];
       if (e - s <= kLongRow) {  // uniform within the group
-        AT acc = spmv_part<VT, XT, AT, kG>(s, e, sub, static_cast<int32_t>(row), col, val, x);
+        AT acc = off16 ? spmv_part16<VT, XT, AT, kG>(s, e, sub, static_cast<int32_t>(row), off16, val, x)
+                       : spmv_part<VT, XT, AT, kG>(s, e, sub, static_cast<int32_t>(row), col, val, x);
 #pragma unroll
         for (int off = kG / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kG);
         if (sub == 0) y[row] = static_cast<YT>(gs ? static_cast<AT>(y[row]) + acc : acc);
@@ -402,8 +429,9 @@ __global__ void __launch_bounds__(kThreads) k_group_spmv(const int32_t* __restri
     __syncthreads();
     if (c0 + kGChunk < nU) load(c0 + kGChunk);   // in flight while this chunk is consumed
     // lane takes entries k .. k + 3 (one 16-byte load per row for float32
-    // values; a load may run past the row's group entries into the padded
-    // array, and those entries get weight 0); one such group per row at a time
+    // values; a load may run past the row's group entries, into the row's
+    // CSR part, the next row or the zeroed padding after the last row, and
+    // those entries get weight 0); one such group per row at a time
     // keeps the kernel at 80 registers (6 waves per SIMD), which measured
     // faster than two groups in flight at 4 waves per SIMD
     for (int k0 = 4 * lane; k0 < clen; k0 += 4 * kWave) {
@@ -443,6 +471,24 @@ __global__ void __launch_bounds__(kThreads) k_group_spmv(const int32_t* __restri
   }
 }
 
+// offsets col - row of the CSR part (flag 1 when one does not fit in int16)
+__global__ void __launch_bounds__(kThreads) k_col16(int64_t n, const int64_t* __restrict__ rp,
+                                                    const int32_t* __restrict__ gskip, const int32_t* __restrict__ col,
+                                                    int16_t* __restrict__ off, int* __restrict__ err) {
+  // kG lanes per row, as in the product, so consecutive lanes touch consecutive entries
+  const int64_t t = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x;
+  const int64_t row = t / kG;
+  if (row >= n) return;
+  for (int64_t j = rp[row] + gskip[row] + (t & (kG - 1)); j < rp[row + 1]; j += kG) {
+    const int64_t d = static_cast<int64_t>(col[j]) - row;
+    if (d < -32768 || d > 32767) {
+      atomicOr(err, 1);
+      return;
+    }
+    off[j] = static_cast<int16_t>(d);
+  }
+}
+
 template <typename VT, typename XT, typename AT, typename YT>
 void spmv_impl(gp_ctx* c, const gp_matrix* m, const XT* x, YT* y) {
   const VT* val = static_cast<const VT*>(m->val);
@@ -455,13 +501,37 @@ void spmv_impl(gp_ctx* c, const gp_matrix* m, const XT* x, YT* y) {
     hipLaunchKernelGGL((k_group_spmv<VT, XT, AT, YT>), dim3(static_cast<unsigned>(m->ntiles)), dim3(kThreads), 0,
                        c->stream, m->g_tiles, m->g_rows, m->g_uoff, m->g_ulist, m->row_ptr, val, x, y);
   hipLaunchKernelGGL((k_spmv<VT, XT, AT, YT>), dim3(nb_short + nb_long), dim3(kThreads), 0, c->stream, m->n,
-                     nb_long, m->n_long, m->long_rows, m->row_ptr, m->gskip, m->col, val, x, y);
+                     nb_long, m->n_long, m->long_rows, m->row_ptr, m->gskip, m->col, val, x, y, m->col16);
   check_launch("spmv");
 }
 
 }  // namespace
 
+void free_col16(gp_ctx* c, gp_matrix* m) {
+  if (m->col16) dev_free(c, m->col16, sizeof(int16_t) * (m->nnz + kCsrPad));
+  m->col16 = nullptr;
+}
+
+static void build_col16(gp_ctx* c, gp_matrix* m) {
+  if (m->col16_tried) return;
+  m->col16_tried = true;
+  ProfScope ps(c, "col16_build");
+  m->col16 = dev_new<int16_t>(c, m->nnz + kCsrPad);
+  GPS_HIP(hipMemsetAsync(c->err_flag, 0, sizeof(int), c->stream));
+  hipLaunchKernelGGL(k_col16, dim3(grid_for(m->n * kG, kThreads)), dim3(kThreads), 0, c->stream, m->n, m->row_ptr,
+                     m->gskip, m->col, m->col16, c->err_flag);
+  check_launch("col16");
+  int* h = static_cast<int*>(pinned(c, sizeof(int)));
+  GPS_HIP(hipMemcpyAsync(h, c->err_flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  sync(c);
+  if (*h)
+    free_col16(c, m);
+  else
+    m->bytes += sizeof(int16_t) * (m->nnz + kCsrPad);
+}
+
 void spmv_f64(gp_ctx* c, const gp_matrix* m, const double* x, double* y) {
+  build_col16(c, const_cast<gp_matrix*>(m));
   if (m->prec == GP_MIXED)
     spmv_impl<float, double, double, double>(c, m, x, y);
   else

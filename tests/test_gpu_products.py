@@ -12,8 +12,10 @@ group rows) with 1, 2, 7 and 32 right-hand sides, and the n = 1,095,000
 space-time workload on sampled rows (oracle rows one at a time, the launch
 configuration of the benchmark), and n = 1003 (an incomplete last group of four
 rows for the 32-column path) with a dense cluster of rows longer than 128
-entries beside short ones.  Shape errors in the binding are refused before any
-device work."""
+entries beside short ones.  The one-column product's int16 column offsets are
+checked where they fit (config 1) and where they do not (cells wider than 32767
+binned positions: the product reads the int32 columns).  Shape errors in the
+binding are refused before any device work."""
 import numpy as np
 import pytest
 
@@ -153,3 +155,27 @@ def test_tiny_sizes(ctx, n):
         assert abs(r["quad"] - ref["quad"]) <= 1e-10 * abs(ref["quad"])
         if mode == LOGDET_EXACT or n == 1:  # one point: the probe estimate is exact
             assert abs(r["logdet"] - ref["logdet"]) <= 1e-10 * max(1.0, abs(ref["logdet"]))
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_column_offsets_and_their_fallback(ctx, prec):
+    # the one-column product stores local columns as int16 offsets from the row
+    # when they fit: here (cells 0.4 high, about 20,000 points per row of
+    # cells) they do not, so the product reads the int32 columns; on config 1
+    # they fit.  Both against the oracle.
+    from workloads import Problem, Theta
+    rng = np.random.default_rng(5)
+    x = rng.random((80000, 2))
+    th = Theta(1.0, np.array([0.0005, 0.4]), np.zeros((0, 0, 2)), np.zeros((0, 0, 2)), np.zeros((0, 0)),
+               np.zeros((0, 0)), 0.1)
+    for p, fits in ((Problem("wide offsets", x, th, cell=np.array([0.0005, 0.6])), False), (config1(), True)):
+        A = kernel.to_scipy(*kernel.sparse(p.x, p.theta), p.n)
+        xv = rng.standard_normal(p.n)
+        ds = ctx.dataset(dev(p.x), cell=p.cell)
+        K = ctx.assemble(ds, p.theta, prec)
+        before = K.held_bytes()
+        y = host(ctx.matvec(K, dev(xv)))
+        grown = K.held_bytes() - before
+        print(f"[offsets {p.name} prec={prec}] cache bytes {grown} (2 (nnz + 64) = {2 * (K.nnz + 64)})")
+        assert grown == (2 * (K.nnz + 64) if fits else 0)
+        _check_rows(y, A @ xv, abs(A) @ np.abs(xv), prec, f"offsets {p.name} prec={prec}")
