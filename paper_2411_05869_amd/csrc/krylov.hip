@@ -19,6 +19,7 @@ namespace {
 constexpr int kThreads = kRedThreads;
 constexpr int kRedBlocks = 512;
 constexpr int kCheckEvery = 8;
+constexpr int kLoadBatch = 4;  // strided elements a thread loads at once in the streaming kernels
 
 // ---------------------------------------------------------------- reductions
 __global__ void __launch_bounds__(kThreads) k_dot_part(int64_t n, const double* __restrict__ a,
@@ -139,6 +140,20 @@ __global__ void __launch_bounds__(kThreads) k_pcg_step(int64_t n, Precond M, CgS
 __global__ void __launch_bounds__(kThreads) k_pcg_direction(int64_t n, CgScalars* __restrict__ s,
                                                             const double* __restrict__ part, int nb,
                                                             const double* __restrict__ z, double* __restrict__ p) {
+  // the first batch of z and p is requested before the partial sums are
+  // reduced, and each later batch before the previous one is stored
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * kThreads;
+  const int64_t i0 = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x;
+  double zv[kLoadBatch], pv[kLoadBatch];
+  auto load = [&](int64_t i) {
+#pragma unroll
+    for (int u = 0; u < kLoadBatch; ++u) {
+      const int64_t k = i + u * stride;
+      zv[u] = k < n ? z[k] : 0.0;
+      pv[u] = k < n ? p[k] : 0.0;
+    }
+  };
+  load(i0);
   double sums[2];
   reduce_partials<2>(part, nb, sums);
   const double beta = sums[0] / s->rz_old;
@@ -148,9 +163,14 @@ __global__ void __launch_bounds__(kThreads) k_pcg_direction(int64_t n, CgScalars
     s->beta = beta;
     if (!isfinite(sums[0]) || !isfinite(sums[1])) s->status = 1;
   }
-  for (int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; i < n;
-       i += static_cast<int64_t>(gridDim.x) * kThreads) {
-    p[i] = z[i] + beta * p[i];
+  for (int64_t i = i0; i < n; i += kLoadBatch * stride) {
+    double out[kLoadBatch];
+#pragma unroll
+    for (int u = 0; u < kLoadBatch; ++u) out[u] = zv[u] + beta * pv[u];
+    if (i + kLoadBatch * stride < n) load(i + kLoadBatch * stride);
+#pragma unroll
+    for (int u = 0; u < kLoadBatch; ++u)
+      if (i + u * stride < n) p[i + u * stride] = out[u];
   }
 }
 
@@ -197,10 +217,22 @@ __global__ void __launch_bounds__(kThreads) k_precond(int64_t n, Precond M, cons
 template <typename QT>
 __global__ void __launch_bounds__(kThreads) k_pq_part(int64_t n, const double* __restrict__ p,
                                                       const QT* __restrict__ q, double* __restrict__ part) {
+  // four strided elements loaded at once, then added in the order of a plain
+  // grid-stride loop (the sum does not depend on the unrolling)
   double v[1] = {0};
-  for (int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; i < n;
-       i += static_cast<int64_t>(gridDim.x) * kThreads)
-    v[0] += p[i] * static_cast<double>(q[i]);
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * kThreads;
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; i < n; i += kLoadBatch * stride) {
+    double pv[kLoadBatch], qv[kLoadBatch];
+#pragma unroll
+    for (int u = 0; u < kLoadBatch; ++u) {
+      const int64_t k = i + u * stride;
+      pv[u] = k < n ? p[k] : 0.0;
+      qv[u] = k < n ? static_cast<double>(q[k]) : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kLoadBatch; ++u)
+      if (i + u * stride < n) v[0] += pv[u] * qv[u];
+  }
   block_sum_store<1>(v, part);
 }
 
