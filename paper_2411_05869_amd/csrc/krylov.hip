@@ -73,22 +73,6 @@ __device__ __forceinline__ double precond_row(const Precond& M, const double* __
   return z;
 }
 
-// Row i of z = M^-1 (r - alpha q): the entries of the new residual that the
-// block product needs are formed from r and q the same way as the row's own, so
-// every thread sees bitwise the same values without waiting for the others.
-template <typename QT>
-__device__ __forceinline__ double precond_row_next(const Precond& M, const double* __restrict__ r,
-                                                   const QT* __restrict__ q, double alpha, double ri, int64_t i) {
-  if (!M.binv) return ri / M.diag[i];
-  const int32_t b = M.rowblk[i];
-  const int32_t bs = M.bstart[b];
-  const int sz = M.bstart[b + 1] - bs;
-  const double* row = M.binv + M.boff[b] + static_cast<int64_t>(i - bs) * sz;
-  double z = 0.0;
-  for (int j = 0; j < sz; ++j) z += row[j] * (r[bs + j] - alpha * static_cast<double>(q[bs + j]));
-  return z;
-}
-
 // One CG step after the product q = K p.  Every block adds the kRedBlocks
 // partials of p.q (pq_part, same fixed order in every block) and forms alpha =
 // rz / pq; then, kStepRows rows per thread (the block-Jacobi product is a
@@ -98,6 +82,7 @@ __device__ __forceinline__ double precond_row_next(const Precond& M, const doubl
 // rn.rn.  Block 0 records pq, alpha, rz_old = rz and the status (non-positive
 // curvature).
 constexpr int kStepRows = 2;
+constexpr int kPreEntries = 4;  // block entries per row loaded before alpha is known (blocks average 2.8 points)
 
 template <typename QT>
 __global__ void __launch_bounds__(kThreads) k_pcg_step(int64_t n, Precond M, CgScalars* __restrict__ s,
@@ -106,6 +91,46 @@ __global__ void __launch_bounds__(kThreads) k_pcg_step(int64_t n, Precond M, CgS
                                                        double* __restrict__ x, const double* __restrict__ r,
                                                        double* __restrict__ rn, double* __restrict__ z,
                                                        double* __restrict__ part) {
+  // Everything a row reads is independent of alpha, so the row's vectors, its
+  // block (row -> block -> start and offset) and the block's first kPreEntries
+  // weights and r, q values are requested before the kRedBlocks partials of
+  // p.q are reduced; the arithmetic afterwards is the same, in the same order.
+  // Row i of z = M^-1 (r - alpha q) forms the block's entries of the new
+  // residual from r and q the same way as the row's own, so every thread sees
+  // bitwise the same values without waiting for the others.
+  double xv[kStepRows], pv[kStepRows], rv[kStepRows], qv[kStepRows], dv[kStepRows];
+  constexpr int kPreSlots = kPreEntries > 0 ? kPreEntries : 1;
+  double wpre[kStepRows][kPreSlots], rpre[kStepRows][kPreSlots], qpre[kStepRows][kPreSlots];
+  const double* brow[kStepRows];
+  int32_t bs[kStepRows];
+  int sz[kStepRows];
+#pragma unroll
+  for (int u = 0; u < kStepRows; ++u) {
+    const int64_t i = (blockIdx.x * static_cast<int64_t>(kStepRows) + u) * kThreads + threadIdx.x;
+    sz[u] = 0;
+    if (i < n) {
+      xv[u] = x[i];
+      pv[u] = p[i];
+      rv[u] = r[i];
+      qv[u] = static_cast<double>(q[i]);
+      if (M.binv) {
+        const int32_t b = M.rowblk[i];
+        bs[u] = M.bstart[b];
+        sz[u] = M.bstart[b + 1] - bs[u];
+        brow[u] = M.binv + M.boff[b] + static_cast<int64_t>(i - bs[u]) * sz[u];
+#pragma unroll
+        for (int j = 0; j < kPreEntries; ++j) {
+          if (j < sz[u]) {
+            wpre[u][j] = brow[u][j];
+            rpre[u][j] = r[bs[u] + j];
+            qpre[u][j] = static_cast<double>(q[bs[u] + j]);
+          }
+        }
+      } else {
+        dv[u] = M.diag[i];
+      }
+    }
+  }
   double pqv[1];
   reduce_partials<1>(pq_part, kRedBlocks, pqv);
   const double pq = pqv[0], rz = s->rz;
@@ -116,9 +141,20 @@ __global__ void __launch_bounds__(kThreads) k_pcg_step(int64_t n, Precond M, CgS
   for (int u = 0; u < kStepRows; ++u) {
     const int64_t i = (blockIdx.x * static_cast<int64_t>(kStepRows) + u) * kThreads + threadIdx.x;
     if (i < n) {
-      x[i] += alpha * p[i];
-      const double ri = r[i] - alpha * static_cast<double>(q[i]);
-      const double zi = precond_row_next<QT>(M, r, q, alpha, ri, i);
+      x[i] = xv[u] + alpha * pv[u];
+      const double ri = rv[u] - alpha * qv[u];
+      double zi;
+      if (M.binv) {
+        // z_i = sum_j binv[i][j] (r_j - alpha q_j) over the block, j ascending
+        zi = 0.0;
+#pragma unroll
+        for (int j = 0; j < kPreEntries; ++j)
+          if (j < sz[u]) zi += wpre[u][j] * (rpre[u][j] - alpha * qpre[u][j]);
+        for (int j = kPreEntries; j < sz[u]; ++j)
+          zi += brow[u][j] * (r[bs[u] + j] - alpha * static_cast<double>(q[bs[u] + j]));
+      } else {
+        zi = ri / dv[u];
+      }
       rn[i] = ri;
       z[i] = zi;
       v[0] += ri * zi;
