@@ -28,6 +28,7 @@ constexpr int kThreads = 256;
 constexpr int kC = 32;                 // right-hand sides per batch
 constexpr int kRowsPer = kThreads / kC;  // rows handled together by a block
 constexpr unsigned kVBlocks = 1024;    // blocks of the column-reduction kernels
+constexpr int kRowBatch = 4;           // strided rows a thread loads at once in the column reductions
 constexpr int kCheckEvery = 8;
 constexpr int kMaxRefresh = 3;
 
@@ -300,11 +301,21 @@ __global__ void __launch_bounds__(kFinThreads) k_bcg_start_fin(const double* __r
 
 __global__ void __launch_bounds__(kThreads) k_bcg_pq(int64_t n, const double* __restrict__ P,
                                                      const double* __restrict__ Q, double* __restrict__ part) {
+  // four strided rows loaded at once, added in the order of the plain row loop
   const int col = threadIdx.x % kC;
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * kRowsPer;
   double v[1] = {0.0};
-  ROW_LOOP(n) {
-    const int64_t e = i * kC + col;
-    v[0] += P[e] * Q[e];
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * kRowsPer + threadIdx.x / kC; i < n; i += kRowBatch * stride) {
+    double pv[kRowBatch], qv[kRowBatch];
+#pragma unroll
+    for (int u = 0; u < kRowBatch; ++u) {
+      const int64_t k = i + u * stride;
+      pv[u] = k < n ? P[k * kC + col] : 0.0;
+      qv[u] = k < n ? Q[k * kC + col] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kRowBatch; ++u)
+      if (i + u * stride < n) v[0] += pv[u] * qv[u];
   }
   col_partials<1>(v, part);
 }
@@ -339,14 +350,28 @@ __global__ void __launch_bounds__(kThreads) k_bcg_update(int64_t n, const BcgSca
                                                          double* __restrict__ Z, double* __restrict__ part) {
   const int col = threadIdx.x % kC;
   const double a = S->alpha[col];
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * kRowsPer;
+  const int64_t i0 = static_cast<int64_t>(blockIdx.x) * kRowsPer + threadIdx.x / kC;
+  // the next row's R, Q, W and P are requested before the current row is
+  // processed (same arithmetic, same order)
+  double rn = 0.0, qn = 0.0, wn = 0.0, pn = 0.0;
+  if (i0 < n) {
+    const int64_t e = i0 * kC + col;
+    rn = Rin[e], qn = Q[e], wn = W[e], pn = P[e];
+  }
   double v[2] = {0.0, 0.0};
-  ROW_LOOP(n) {
+  for (int64_t i = i0; i < n; i += stride) {
     const int64_t e = i * kC + col;
+    const double ri = rn, qi = qn, wi = wn, pi = pn;
+    if (i + stride < n) {
+      const int64_t f = (i + stride) * kC + col;
+      rn = Rin[f], qn = Q[f], wn = W[f], pn = P[f];
+    }
     // the new residual of any row of the block, formed as for the row itself
     auto r_at = [&](int64_t q) { return Rin[q * kC + col] - a * Q[q * kC + col]; };
-    const double r = r_at(i);
+    const double r = ri - a * qi;
     const double z = var_precond(M, i, r, r_at);
-    W[e] += a * P[e];
+    W[e] = wi + a * pi;
     Rout[e] = r;
     Z[e] = z;
     v[0] += r * z;
@@ -493,6 +518,8 @@ VarResult predict_variance(gp_ctx* c, const gp_matrix* m, const gp_theta* th, in
   BcgScalars* hs = static_cast<BcgScalars*>(pinned(c, sizeof(BcgScalars)));
   const unsigned nbv = static_cast<unsigned>(std::min<int64_t>(kVBlocks, (n + kRowsPer - 1) / kRowsPer));
   const dim3 B(kThreads), G(nbv), FB(kFinThreads);
+  // element-wise kernels without a reduction take a row per thread
+  const dim3 Gfull(static_cast<unsigned>((n + kRowsPer - 1) / kRowsPer));
   const double tol2 = rtol * rtol;
   auto read = [&]() {
     GPS_HIP(hipMemcpyAsync(hs, S, sizeof(BcgScalars), hipMemcpyDeviceToHost, c->stream));
@@ -547,7 +574,7 @@ VarResult predict_variance(gp_ctx* c, const gp_matrix* m, const gp_theta* th, in
         hipLaunchKernelGGL(k_bcg_update, G, B, 0, c->stream, n, S, P, Q, M, W, R, R2, Z, part);
         std::swap(R, R2);
         hipLaunchKernelGGL(k_bcg_beta, dim3(1), FB, 0, c->stream, part, static_cast<int>(nbv), S, tol2);
-        hipLaunchKernelGGL(k_bcg_dir, G, B, 0, c->stream, n, S, Z, P);
+        hipLaunchKernelGGL(k_bcg_dir, Gfull, B, 0, c->stream, n, S, Z, P);
         check_launch("variance step");
       }
       it += steps;
