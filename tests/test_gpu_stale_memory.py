@@ -9,7 +9,8 @@ NaN and released, so the library's arrays and work spaces are carved from
 NaN-filled memory.  The library is deterministic (fixed reduction grids, cells
 sorted after binning, counter-based probes), so every result must agree
 bitwise: log-likelihoods (SLQ and exact log det) in both precisions, 1-, 7- and
-32-column products, the solve and the kriging mean, and posterior variances for
+32-column products, the solve (conjugate gradients and MINRES), the kriging mean
+(float64 and float32 evaluation), and posterior variances for
 a ragged number of test points (37: one full and one partial block of 32)."""
 import numpy as np
 import pytest
@@ -31,7 +32,7 @@ def _fill_pools_with_nan():
 
 def _run(p, y, X, xs):
     import torch
-    from paper_2411_05869_amd import Context, LOGDET_EXACT
+    from paper_2411_05869_amd import Context, LOGDET_EXACT, MIXED, SOLVER_MINRES
     ctx = Context()
     ds = ctx.dataset(dev(p.x), cell=p.cell)
     out = {}
@@ -45,10 +46,13 @@ def _run(p, y, X, xs):
         for k in (1, 7, 32):
             out[f"mv{prec}_{k}"] = host(ctx.matvec(K, dev(X[:, 0] if k == 1 else X[:, :k])))
         alpha = torch.empty(p.n, dtype=torch.float64, device="cuda")
+        r = ctx.solve(K, dev(y), alpha, solver=SOLVER_MINRES)
+        out[f"minres{prec}"] = np.append(host(alpha), r["minres_iters"])
         ctx.solve(K, dev(y), alpha)
         out[f"alpha{prec}"] = host(alpha)
         pred = ctx.predictor(ds, p.theta, alpha)
         out[f"mean{prec}"] = host(ctx.predict(pred, dev(xs)))
+        out[f"mean32_{prec}"] = host(ctx.predict(pred, dev(xs), precision=MIXED))
         pred.close()
         var, res = ctx.predict_var(K, p.theta, dev(xs))
         out[f"var{prec}"] = np.append(host(var), res["iters"])
