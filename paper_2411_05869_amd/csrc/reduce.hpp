@@ -38,15 +38,31 @@ __device__ __forceinline__ void block_sum_store(double (&v)[NV], double* __restr
 
 // Sums part[b * NV + i] over b in a fixed order (partials written by an earlier
 // launch); the result is returned to every thread of the block.
+// A thread loads four of its strided partials at once and adds them in the
+// order of a plain strided loop.
 template <int NV>
 __device__ __forceinline__ void reduce_partials(const double* __restrict__ part, int nb, double* __restrict__ res) {
+  constexpr int kBatch = 4;
   __shared__ double sh[NV][kRedThreads];
+  double s[NV];
 #pragma unroll
-  for (int i = 0; i < NV; ++i) {
-    double s = 0;
-    for (int b = threadIdx.x; b < nb; b += kRedThreads) s += part[b * NV + i];
-    sh[i][threadIdx.x] = s;
+  for (int i = 0; i < NV; ++i) s[i] = 0;
+  for (int b0 = threadIdx.x; b0 < nb; b0 += kBatch * kRedThreads) {
+    double v[kBatch][NV];
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      const int b = b0 + u * kRedThreads;
+#pragma unroll
+      for (int i = 0; i < NV; ++i) v[u][i] = b < nb ? part[b * NV + i] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u)
+      if (b0 + u * kRedThreads < nb)
+#pragma unroll
+        for (int i = 0; i < NV; ++i) s[i] += v[u][i];
   }
+#pragma unroll
+  for (int i = 0; i < NV; ++i) sh[i][threadIdx.x] = s[i];
   __syncthreads();
   for (int st = kRedThreads / 2; st > 0; st >>= 1) {
     if (threadIdx.x < st)
