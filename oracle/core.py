@@ -7,7 +7,7 @@ Definitions followed:
 * the kernel is the product C_y(x, x') = C_core(x, x') C_sparse(x, x')
   (Sec. 2, Eq. sparseCov); the nugget of Eq. Zcov is added afterwards, on the
   index diagonal, and is not multiplied by the core;
-* Matern correlation with smoothness nu (Sec. 2.3 names the Matern class; the
+* Matern correlation with smoothness nu (Sec. 2.2 names the Matern class; the
   paper's experiments use nu = 5/2, Sec. 4.1):
       M_nu(t) = 2^(1-nu) / Gamma(nu) (sqrt(2 nu) t)^nu K_nu(sqrt(2 nu) t),
   used here through its closed forms at the half-integers nu = 1/2, 3/2, 5/2

@@ -81,7 +81,7 @@ def test_edge_cases(ctx):
     th = Theta(1.0, np.array([0.1, 0.1]), np.array([[[0.3, 0.31]]]), np.full((1, 1, 2), 0.05), np.ones((1, 1)),
                np.ones((1, 1)), 0.5)
     run_case(ctx, Problem("dups", x, th, cell=None), 0, what="duplicates")
-    # no bumps at all (n1 = 0): special case (1) of Sec. 2.2
+    # no bumps at all (n1 = 0): special case (1) of Sec. 2.3
     th0 = Theta(2.0, np.array([0.1, 0.1]), np.zeros((0, 0, 2)), np.zeros((0, 0, 2)), np.zeros((0, 0)),
                 np.zeros((0, 0)), 0.1)
     run_case(ctx, Problem("nobumps", np.random.default_rng(5).random((300, 2)), th0), 0, what="n1=0")

@@ -1,6 +1,6 @@
 """Pins of the oracle's covariance against closed forms, invariants and
 brute force (Sec. 2.1 Eq. bumpFcn / sumOfBumps / C_sparse / compSupp,
-Proposition 1, Sec. 2.2 special case (1), Sec. 3.1 Eq. Zcov)."""
+Proposition 1, Sec. 2.3 special case (1), Sec. 3.1 Eq. Zcov)."""
 import os
 
 import numpy as np
@@ -66,7 +66,7 @@ def test_support_boundary_is_strict():
 
 
 def test_equispaced_1d_closed_form_matrix():
-    # Sec. 2.2 special case (1) (no bumps): spacing r0/2 -> neighbours at u = 1/2,
+    # Sec. 2.3 special case (1) (no bumps): spacing r0/2 -> neighbours at u = 1/2,
     # second neighbours at u = 1 (outside).  K = s0 W + sigma^2 I exactly known.
     g = gold()
     s0, nug = 2.0, 0.25
