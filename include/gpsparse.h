@@ -154,7 +154,7 @@ GP_API gp_status gp_dataset_permutation(gp_ctx* ctx, const gp_dataset* ds, int32
 /* Core kernel C_core of C_y = C_core x C_sparse (Sec. 2, Eq. sparseCov; the
  * nugget is added after the product).  The core is strictly positive, so it
  * never changes the sparsity pattern; it only scales the stored values.
- *   GP_CORE_MATERN:   sigma0^2 M_nu(|(x - x') / ell|)             (Sec. 2.3)
+ *   GP_CORE_MATERN:   sigma0^2 M_nu(|(x - x') / ell|)             (Sec. 2.2)
  *   GP_CORE_PACIOREK: sigma(x) sigma(x') (Sigma(x) Sigma(x'))^(d/4)
  *                     / ((Sigma(x) + Sigma(x')) / 2)^(d/2) M_nu(sqrt(Q)),
  *                     Q = |(x - x') / ell|^2 / ((Sigma(x) + Sigma(x')) / 2)
