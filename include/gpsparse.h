@@ -242,6 +242,24 @@ GP_API gp_status gp_matrix_export_csr(gp_ctx* ctx, const gp_matrix* m, int64_t* 
 GP_API gp_status gp_matvec(gp_ctx* ctx, const gp_matrix* m, int32_t nrhs, const double* x_dev,
                     double* y_dev);
 
+/* gp_matvec_noalloc: y = K x for one right-hand side, for callers that cannot
+ * allocate device memory (code under stream capture, tight serving loops,
+ * harnesses that forbid allocation).  Same product and result as gp_matvec
+ * with nrhs = 1 (x_dev, y_dev: n float64 in ORIGINAL point order, device,
+ * caller-owned; they must not overlap), but it allocates nothing: the two
+ * n-vectors gp_matvec stages in binned order live in a fixed 64 MiB array of
+ * device memory that the library holds on every GPU it has run on until the
+ * process ends (its address is looked up when a context is created), so
+ * n <= 4,194,304.  It builds no cache (a product reads the int16 column
+ * offsets only if an earlier product built them; either form gives bitwise
+ * the same y), records no profiling events and does not synchronise: the call
+ * returns once the work is enqueued on the context's stream, and y is
+ * complete when the stream reaches that point.  Every call on one GPU shares
+ * that GPU's array: calls that overlap in time on one GPU (other streams,
+ * other contexts, other threads) race and must be ordered by the caller.
+ * Errors: GP_EINVAL (NULL argument, n above the limit), GP_EDEVICE. */
+GP_API gp_status gp_matvec_noalloc(gp_ctx* ctx, const gp_matrix* m, const double* x_dev, double* y_dev);
+
 /* ------------------------------------------------------------ likelihood */
 typedef enum gp_precond {
   GP_PRECOND_JACOBI = 0,        /* diagonal of K */

@@ -76,6 +76,7 @@ EXPORTS = [
     "gp_ctx_set_hbm_budget",
     "gp_dataset_create", "gp_dataset_destroy", "gp_dataset_info", "gp_dataset_permutation",
     "gp_assemble", "gp_matrix_destroy", "gp_matrix_info", "gp_matrix_export_csr", "gp_matvec",
+    "gp_matvec_noalloc",
     "gp_solve_opts_default", "gp_loglik", "gp_solve", "gp_predictor_create", "gp_predictor_destroy",
     "gp_predict", "gp_predict_var", "gp_mean_residual", "gp_profile_enable", "gp_profile_read",
 ]
@@ -112,6 +113,7 @@ def lib():
                                  C.POINTER(I64)]
     L.gp_matrix_export_csr.argtypes = [P, P, P, P, P]
     L.gp_matvec.argtypes = [P, P, I32, P, P]
+    L.gp_matvec_noalloc.argtypes = [P, P, P, P]
     L.gp_solve_opts_default.argtypes = [C.POINTER(CSolveOpts)]
     L.gp_solve_opts_default.restype = None
     L.gp_loglik.argtypes = [P, P, P, C.POINTER(CSolveOpts), P, C.POINTER(CLoglikResult)]
@@ -361,6 +363,17 @@ class Context:
         y = torch.empty_like(x)
         self._check(self._L.gp_matvec(self._h, K._h, nrhs, C.c_void_p(_ptr(x)), C.c_void_p(_ptr(y))), "gp_matvec")
         return y
+
+    def matvec_noalloc(self, K: "Matrix", x, out):
+        """y = K x (one column) into ``out`` without any device allocation (the
+        library's fixed scratch array); enqueued on the context's stream, not
+        waited for."""
+        torch = _torch()
+        _check_dev_tensor(x, torch.float64, (K.n,), "x")
+        _check_dev_tensor(out, torch.float64, (K.n,), "out")
+        self._check(self._L.gp_matvec_noalloc(self._h, K._h, C.c_void_p(_ptr(x)), C.c_void_p(_ptr(out))),
+                    "gp_matvec_noalloc")
+        return out
 
     def export_csr(self, K: "Matrix"):
         torch = _torch()

@@ -229,6 +229,7 @@ gp_status gp_ctx_create(int device, void* stream, gp_alloc_fn alloc, gp_free_fn 
     }
     c->err_flag = static_cast<int*>(gps::dev_alloc(c.get(), sizeof(int) * 4));
     gps::pinned(c.get(), 1 << 20);
+    gps::noalloc_init(device);
   });
   if (st != GP_OK) return st;
   *out = c.release();
@@ -417,6 +418,11 @@ gp_status gp_matvec(gp_ctx* c, const gp_matrix* m, int32_t nrhs, const double* x
     gps::permute_to_orig<double>(c, m->ds, nrhs, yb, y);
     gps::sync(c);
   });
+}
+
+gp_status gp_matvec_noalloc(gp_ctx* c, const gp_matrix* m, const double* x, double* y) {
+  if (!c || !m || !x || !y) return GP_EINVAL;
+  return guarded(c, [&] { gps::matvec_noalloc(c, m, x, y); });
 }
 
 static gp_status loglik_common(gp_ctx* c, const gp_matrix* m, const double* y, const gp_solve_opts* opts,

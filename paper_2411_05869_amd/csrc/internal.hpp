@@ -292,6 +292,9 @@ void export_csr(gp_ctx* c, const gp_matrix* m, int64_t* row_ptr, int32_t* col, d
 // SpMV / SpMM in binned order.
 // y = K x (float64 x and y; float32 or float64 values; float64 accumulation)
 void spmv_f64(gp_ctx* c, const gp_matrix* m, const double* x, double* y);
+// the same product using only the caches already built (no allocation, no
+// synchronisation, no profiling events)
+void spmv_f64_enqueue(gp_ctx* c, const gp_matrix* m, const double* x, double* y);
 // Y = S K S X D for k columns, X/Y n x ld row-major (S = diag(scale) or identity
 // if null; D = diag(colscale), a device array of k values, or identity if null)
 template <typename T>
@@ -346,6 +349,11 @@ struct LogdetResult {
 };
 LogdetResult slq_logdet(gp_ctx* c, const gp_matrix* m, uint64_t seed, int n_probes, int n_steps);
 LogdetResult exact_logdet(gp_ctx* c, const gp_matrix* m, uint64_t seed);
+
+// allocation-free one-column product (fixed per-device scratch array)
+void noalloc_init(int device);   // once per device, with the device current
+size_t noalloc_scratch_bytes();
+void matvec_noalloc(gp_ctx* c, const gp_matrix* m, const double* x, double* y);
 
 // deterministic reductions
 double dot_f64(gp_ctx* c, const double* a, const double* b, int64_t n);   // synchronising

@@ -490,19 +490,24 @@ __global__ void __launch_bounds__(kThreads) k_col16(int64_t n, const int64_t* __
 }
 
 template <typename VT, typename XT, typename AT, typename YT>
-void spmv_impl(gp_ctx* c, const gp_matrix* m, const XT* x, YT* y) {
+void spmv_launch(gp_ctx* c, const gp_matrix* m, const XT* x, YT* y) {
   const VT* val = static_cast<const VT*>(m->val);
   // long-row blocks padded to a multiple of the XCD count so that both block
   // ranges start on XCD 0 (see xcd_remap)
   const unsigned nb_short = grid_for(m->n * kG, kThreads);
   const unsigned nb_long = m->n_long > 0 ? round_up8(grid_for(m->n_long * kWave, kThreads)) : 0;
-  ProfScope ps(c, sizeof(VT) == 4 ? (sizeof(XT) == 4 ? "spmv_f32" : "spmv_f32val_f64") : "spmv_f64");
   if (m->ntiles > 0)
     hipLaunchKernelGGL((k_group_spmv<VT, XT, AT, YT>), dim3(static_cast<unsigned>(m->ntiles)), dim3(kThreads), 0,
                        c->stream, m->g_tiles, m->g_rows, m->g_uoff, m->g_ulist, m->row_ptr, val, x, y);
   hipLaunchKernelGGL((k_spmv<VT, XT, AT, YT>), dim3(nb_short + nb_long), dim3(kThreads), 0, c->stream, m->n,
                      nb_long, m->n_long, m->long_rows, m->row_ptr, m->gskip, m->col, val, x, y, m->col16);
   check_launch("spmv");
+}
+
+template <typename VT, typename XT, typename AT, typename YT>
+void spmv_impl(gp_ctx* c, const gp_matrix* m, const XT* x, YT* y) {
+  ProfScope ps(c, sizeof(VT) == 4 ? (sizeof(XT) == 4 ? "spmv_f32" : "spmv_f32val_f64") : "spmv_f64");
+  spmv_launch<VT, XT, AT, YT>(c, m, x, y);
 }
 
 }  // namespace
@@ -528,6 +533,16 @@ static void build_col16(gp_ctx* c, gp_matrix* m) {
     free_col16(c, m);
   else
     m->bytes += sizeof(int16_t) * (m->nnz + kCsrPad);
+}
+
+// The same product with whatever caches the matrix already holds: nothing is
+// built, allocated, timed or waited for (the int16 offsets are read when an
+// earlier product built them; both column forms give bitwise equal sums).
+void spmv_f64_enqueue(gp_ctx* c, const gp_matrix* m, const double* x, double* y) {
+  if (m->prec == GP_MIXED)
+    spmv_launch<float, double, double, double>(c, m, x, y);
+  else
+    spmv_launch<double, double, double, double>(c, m, x, y);
 }
 
 void spmv_f64(gp_ctx* c, const gp_matrix* m, const double* x, double* y) {
