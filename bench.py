@@ -5,7 +5,9 @@ d = 3; anisotropic Wendland radii (0.03, 0.03, 3 days); 16 x 4 space-time
 bumps; nugget 1e-2), resident on the device.  One step is one pass of the
 hot path for one hyper-parameter vector:
     assemble K(theta) + sigma^2 I  ->  log-likelihood (Jacobi PCG for
-    y^T K^-1 y to rtol 1e-10, SLQ log det with 30 probes x 50 Lanczos steps)
+    y^T K^-1 y to rtol 1e-10, SLQ log det with 30 probes x 100 Lanczos steps,
+    the depth at which the estimate of this workload has converged: with 50
+    steps its quadrature bias is 0.1-0.3%, several standard errors)
     ->  posterior mean at 10,000 test points with the solved alpha.
 The mixed form (float32 values and PCG products, float64 residuals,
 Lanczos vectors and reductions) is the headline; the float64 form is
@@ -41,6 +43,47 @@ def spmv_bytes(n, nnz, vbytes, xbytes):
 def spmm_bytes(n, nnz, vbytes, k, xbytes):
     # values + column ids + row pointers + X read once + Y written + scale vector
     return nnz * (vbytes + 4) + (n + 1) * 8 + 2 * n * k * xbytes + n * xbytes
+
+
+def spmv_format_bytes(n, lo, vbytes, xbytes=8):
+    """Bytes one one-column product must move in the format the library stores
+    (gp_matrix_layout): the group blocks' values (no column ids), the other
+    entries' values and column ids (int16 offsets when built), the row
+    pointer and group-skip count of every row, x once and y once, the group
+    rows' partial y read back, and per group tile of 16 rows its U_M list
+    (column id and x value per entry)."""
+    cb = 2 if lo["col16"] else 4
+    return (lo["nnz_group"] * vbytes + lo["nnz_csr"] * (vbytes + cb) + n * (8 + 4 + 2 * xbytes)
+            + lo["group_rows"] * xbytes + lo["gemv_stage_entries"] * (4 + xbytes))
+
+
+def spmm_format_bytes(n, lo, vbytes, k=32, xbytes=8):
+    """Bytes one 32-column product must move in the stored format: the group
+    blocks' values, the four-row union entries (column id, four values), the
+    listed rows' codes, X read once, Y written once, the group rows' partial
+    Y read back, the row scale, and per group super-tile of 64 rows its U_M
+    list (column id and X row)."""
+    row = k * xbytes
+    return (lo["nnz_group"] * vbytes + lo["quad_entries"] * (4 + 4 * vbytes) + lo["listed_rows"] * 4
+            + n * (2 * row + xbytes) + lo["group_rows"] * row + lo["gemm_stage_entries"] * (4 + row))
+
+
+def copy_peak_gbs(torch, dev, nbytes=1 << 30, reps=5):
+    """Measured device-to-device copy rate (read + write bytes per second) of a
+    1 GiB buffer, best of reps, timed with events on the current stream."""
+    src = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    best = float("inf")
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        dst.copy_(src)
+        b.record()
+        b.synchronize()
+        best = min(best, a.elapsed_time(b) / 1e3)
+    del src, dst
+    return 2 * nbytes / best / 1e9
 
 
 EXACT_LOGLIK = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests", "golden",
@@ -182,7 +225,7 @@ def serving_legs(args, ctx, ds, p, alpha):
     res["loglik_stream"] = st
     # predictions on the resident training set (alpha from the last mixed step)
     be.datasets["train"] = (ds, None)
-    be.predictors["train"] = (ctx.predictor(ds, p.theta, alpha), p.d)
+    be.predictors["train"] = (ctx.predictor(ds, p.theta, alpha), p.d, 0)
     xs = config5_requests(n_requests=200, seed=5)
     sat = [PredictRequest("train", x, 1, 0.0) for x in xs]
     comps = Server(be, hbm_budget=64 << 30).run(sat)
@@ -317,6 +360,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--fp64-steps", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--lanczos", type=int, default=100, help="Lanczos steps of the timed log det (30 probes)")
     ap.add_argument("--stations", type=int, default=3000)
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=128)
@@ -352,6 +396,8 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    copy_gbs = copy_peak_gbs(torch, dev)
+    log(f"measured 1 GiB device copy: {copy_gbs:.0f} GB/s (read + write)")
     x = torch.tensor(p.x, device=dev)
     y = torch.tensor(p.y, device=dev)
     xs_np = config5_requests(1, seed=5, m_lo=10000, m_hi=10000)[0]
@@ -363,28 +409,28 @@ def main():
     torch.cuda.synchronize()
     t_bin = time.perf_counter() - t0
     alpha = torch.empty(p.n, dtype=torch.float64, device=dev)
-    opts = dict(seed=2411, n_probes=30, n_lanczos=50)
+    opts = dict(seed=2411, n_probes=30, n_lanczos=args.lanczos)
 
-    def step(prec):
+    def step(prec, o=None):
         K = ctx.assemble(ds, p.theta, prec)
-        r = ctx.loglik(K, y, alpha_out=alpha, **opts)
+        r = ctx.loglik(K, y, alpha_out=alpha, **(o or opts))
         pred = ctx.predictor(ds, p.theta, alpha)
         ctx.predict(pred, xs, precision=prec)
-        info = dict(nnz=K.nnz, max_row=K.max_row, bytes=K.bytes)
+        info = dict(nnz=K.nnz, max_row=K.max_row, bytes=K.bytes, layout=K.layout())
         K.close()
         pred.close()
         return r, info
 
-    def timed(prec, steps, warmup):
+    def timed(prec, steps, warmup, o=None):
         for i in range(warmup):
-            step(prec)
+            step(prec, o)
             log(f"warmup {i + 1}/{warmup} prec={prec} done")
         torch.cuda.synchronize()
         ctx.profile(True)
         t0 = time.perf_counter()
         res = []
         for i in range(steps):
-            res.append(step(prec))
+            res.append(step(prec, o))
             log(f"step {i + 1}/{steps} prec={prec}: loglik={res[-1][0]['loglik']:.10g} "
                 f"cg_iters={res[-1][0]['cg_iters']}")
         torch.cuda.synchronize()
@@ -408,6 +454,9 @@ def main():
 
     dt_m, res_m, prof_m = timed(MIXED, args.steps, args.warmup)
     dt_d, res_d, prof_d = timed(FP64, args.fp64_steps, min(args.warmup, 1))
+    # the same mixed step with 50 Lanczos steps, for comparison with the converged depth
+    o50 = dict(opts, n_lanczos=50)
+    dt_50, res_50, _ = timed(MIXED, 2, 0, o50)
     asm_wall_m = assemble_wall(MIXED)
     asm_wall_d = assemble_wall(FP64)
     r_m, info_m = res_m[-1]
@@ -420,30 +469,41 @@ def main():
     asm_ms_d = sum(prof_d[k][1] for k in asm_keys if k in prof_d) / args.fp64_steps
     n, nnz = p.n, info_m["nnz"]
 
-    # dominant kernel of the timed region and its algorithmic bytes per launch
-    known = ("spmv_f32val_f64", "spmv_f64", "spmm")  # kernels with a bytes model
-    dom = max(((k, v) for k, v in prof_m.items() if k in known), key=lambda kv: kv[1][1])
-    name, (cnt, tot) = dom
-    avg_s = tot / cnt / 1e3
-    if name == "spmv_f32val_f64":
-        b = spmv_bytes(n, nnz, 4, 8)
-    elif name == "spmv_f64":
-        b = spmv_bytes(n, nnz, 8, 8)
-    elif name == "spmm":
-        b = spmm_bytes(n, nnz, 4, 32, 8)
-    else:
-        b = float("nan")
-    achieved = b / avg_s / 1e9
-    roof = dict(bound="hbm", kernel=name, achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                frac=round(achieved / HBM_PEAK_GBS, 4),
-                traffic=stored_traffic() if name == SPMV_PROFILE_NAME else None, avg_us=round(avg_s * 1e6, 2),
-                launches=cnt, bytes_per_launch=int(b))
+    # the main kernels of the timed region: bytes per launch in the stored
+    # format (gp_matrix_layout), the plain-CSR figure of the same matrix
+    # beside it, and the mean launch time from the library's events
+    lo = info_m["layout"]
+    models = {"spmv_f32val_f64": (spmv_format_bytes(n, lo, 4), spmv_bytes(n, nnz, 4, 8)),
+              "spmm": (spmm_format_bytes(n, lo, 4), spmm_bytes(n, nnz, 4, 32, 8))}
+
+    def roofline(name):
+        cnt, tot = prof_m[name]
+        avg_s = tot / cnt / 1e3
+        b, bcsr = models[name]
+        achieved = b / avg_s / 1e9
+        return dict(bound="hbm", kernel=name, achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(achieved / HBM_PEAK_GBS, 4),
+                    traffic=stored_traffic() if name == SPMV_PROFILE_NAME else None, avg_us=round(avg_s * 1e6, 2),
+                    launches=cnt, bytes_per_launch=int(b), bytes_model="stored format (gp_matrix_layout)",
+                    effective_plain_csr=dict(bytes_per_launch=int(bcsr), achieved=round(bcsr / avg_s / 1e9, 1),
+                                             frac=round(bcsr / avg_s / 1e9 / HBM_PEAK_GBS, 4)))
+
+    present = [k for k in models if k in prof_m]
+    dom = max(present, key=lambda k: prof_m[k][1])
+    roof = roofline(dom)
+    others = {k: roofline(k) for k in present if k != dom}
+    asm_b = nnz * 8.1
+    others["assembly"] = dict(bound="hbm", achieved=round(asm_b / (asm_ms_m / 1e3) / 1e9, 1), peak=HBM_PEAK_GBS,
+                              unit="GB/s", frac=round(asm_b / (asm_ms_m / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+                              bytes_per_launch=int(asm_b), bytes_model="8.1 B per stored entry (int32 column id, "
+                              "float32 value, row pointer and point data)", kernels_ms=round(asm_ms_m, 3))
+    r50 = res_50[-1][0]
 
     out = dict(metric=METRIC, value=round(evals_m, 4), unit="loglik evals/s", n_gpus=1, steps=args.steps,
                warmup=args.warmup, ms_per_step=round(ms_step, 2), higher_is_better=True, scaling="weak",
                vs_baseline=None, dtype="f32/f64", data="synthetic",
                config=dict(workload=f"space-time {p.name}: n={n}, d=3, r0=(0.03,0.03,3d), 16x4 bumps, nugget 1e-2; "
-                                    "step = assemble + PCG(rtol 1e-10) + SLQ(30x50) + predict(10k points)",
+                                    f"step = assemble + PCG(rtol 1e-10) + SLQ(30x{args.lanczos}) + predict(10k points)",
                            n=n, nnz=nnz, max_row=info_m["max_row"]),
                nnz_per_s=round(nnz / asm_wall_m, 1), assemble_ms=round(1e3 * asm_wall_m, 3),
                assemble_kernels_ms=round(asm_ms_m, 3),
@@ -455,8 +515,13 @@ def main():
                           cg_iters=r_m["cg_iters"], refreshes=r_m["refreshes"], relres=r_m["relres"],
                           rel_vs_fp64=abs(r_m["loglik"] - r_d["loglik"]) / abs(r_d["loglik"]),
                           vs_exact=vs_exact(r_m, p.name)),
+               mixed_30x50=dict(value=round(2 / dt_50, 4), unit="loglik evals/s", ms_per_step=round(1e3 * dt_50 / 2, 2),
+                                logdet=r50["logdet"], logdet_se=r50["logdet_se"], vs_exact=vs_exact(r50, p.name)),
                binning_ms=round(1e3 * t_bin, 2),
                roofline=roof,
+               roofline_other=others,
+               hbm_copy_gbs=round(copy_gbs, 1),
+               matrix_layout=lo,
                kernels_ms_per_step={k: round(v[1] / args.steps, 3) for k, v in sorted(prof_m.items(),
                                                                                        key=lambda kv: -kv[1][1])},
                paper_context="paper: ~66 s per likelihood (37 s covariance) at N=1,038,723 on 256 A100 (Sec. 5.2)")

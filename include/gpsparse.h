@@ -225,6 +225,29 @@ GP_API gp_status gp_matrix_destroy(gp_ctx* ctx, gp_matrix* m);
  * quads), precision, longest row. */
 GP_API gp_status gp_matrix_info(const gp_matrix* m, int64_t* n, int64_t* nnz, size_t* bytes,
                          int32_t* prec, int64_t* max_row);
+/* Storage layout of the matrix, for byte accounting: the entries of the
+ * rows' group blocks (stored without column ids: rows with mask M share the
+ * list U_M), the other entries (column ids stored, read by the one-column
+ * product as int16 offsets when col16 = 1), the U_M entries the group
+ * products stage (one pass over U_M per tile of 16 rows for one column, per
+ * super-tile of 64 rows for several), and the cache of the 32-column product
+ * (0 until the first such product built it): the rows listed in groups of
+ * four and the entries of the four-row column unions. */
+typedef struct gp_matrix_layout_info {
+  int64_t nnz_group;          /* entries in group blocks */
+  int64_t nnz_csr;            /* the other entries */
+  int64_t group_rows;         /* rows with a group block */
+  int64_t group_masks;        /* distinct group masks M */
+  int64_t group_list_entries; /* sum of |U_M| */
+  int64_t gemv_stage_entries; /* U_M entries read by one one-column product */
+  int64_t gemm_stage_entries; /* U_M entries read by one multi-column product */
+  int64_t long_rows;          /* rows whose other entries exceed 128 */
+  int32_t col16;              /* int16 column offsets built and used */
+  int32_t reserved;
+  int64_t listed_rows;        /* rows listed for the four-row unions (padded) */
+  int64_t quad_entries;       /* entries of the four-row unions */
+} gp_matrix_layout_info;
+GP_API gp_status gp_matrix_layout(const gp_matrix* m, gp_matrix_layout_info* out);
 /* Writes the matrix in ORIGINAL point order with ascending columns into
  * caller device buffers: row_ptr_dev (n+1 int64), col_dev (nnz int32),
  * val_dev (nnz float64; float32 values are widened).  Debug/parity path. */
@@ -345,6 +368,23 @@ GP_API gp_status gp_predictor_destroy(gp_ctx* ctx, gp_predictor* p);
  * Errors: GP_EINVAL (m < 0, NULL buffers, unknown precision), GP_EDEVICE. */
 GP_API gp_status gp_predict(gp_ctx* ctx, const gp_predictor* p, int64_t m, const double* xstar_dev,
                      gp_precision prec, double* mean_dev);
+
+/* gp_predict_batch: the kriging means of Sec. 3.2 for nreq requests in one
+ * launch (Sec. 3.3: many prediction requests are served together).  Request
+ * r asks for the mean of predictor preds[r] (host array of nreq pointers;
+ * requests may share a predictor or use predictors of other hyper-parameters
+ * or training datasets) at the rows row_offsets[r] .. row_offsets[r+1] - 1 of
+ * xstar_dev (row_offsets: host array of nreq + 1 non-decreasing values,
+ * row_offsets[0] = 0; empty requests allowed); xstar_dev (row_offsets[nreq] x d
+ * row-major float64, device) and mean_dev (row_offsets[nreq] float64, device)
+ * hold all requests' rows back to back.  Every row gets the value gp_predict
+ * gives for it with the same predictor and precision.  All predictors must
+ * share the dimension d and the core kernel kind.
+ * Errors: GP_EINVAL (nreq < 0, NULL arguments, offsets not starting at 0 or
+ * decreasing, mixed d or core kinds, unknown precision), GP_EDEVICE. */
+GP_API gp_status gp_predict_batch(gp_ctx* ctx, int32_t nreq, const gp_predictor* const* preds,
+                                  const int64_t* row_offsets, const double* xstar_dev, gp_precision prec,
+                                  double* mean_dev);
 
 /* gp_mean_residual: y = z - W beta, the residual of the prior mean
  * E[z] = W beta of Sec. 3.1 (Eq. Zmarg), the y_dev that gp_loglik and gp_solve

@@ -63,6 +63,16 @@ class CLoglikResult(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class CMatrixLayout(C.Structure):
+    _fields_ = [("nnz_group", C.c_int64), ("nnz_csr", C.c_int64), ("group_rows", C.c_int64),
+                ("group_masks", C.c_int64), ("group_list_entries", C.c_int64), ("gemv_stage_entries", C.c_int64),
+                ("gemm_stage_entries", C.c_int64), ("long_rows", C.c_int64), ("col16", C.c_int32), ("reserved", C.c_int32), ("listed_rows", C.c_int64),
+                ("quad_entries", C.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
 class CVarResult(C.Structure):
     _fields_ = [("iters", C.c_int64), ("max_batch_iters", C.c_int32), ("status", C.c_int32),
                 ("relres", C.c_double)]
@@ -76,7 +86,7 @@ EXPORTS = [
     "gp_ctx_set_hbm_budget",
     "gp_dataset_create", "gp_dataset_destroy", "gp_dataset_info", "gp_dataset_permutation",
     "gp_assemble", "gp_matrix_destroy", "gp_matrix_info", "gp_matrix_export_csr", "gp_matvec",
-    "gp_matvec_noalloc",
+    "gp_matvec_noalloc", "gp_matrix_layout", "gp_predict_batch",
     "gp_solve_opts_default", "gp_loglik", "gp_solve", "gp_predictor_create", "gp_predictor_destroy",
     "gp_predict", "gp_predict_var", "gp_mean_residual", "gp_profile_enable", "gp_profile_read",
 ]
@@ -114,6 +124,7 @@ def lib():
     L.gp_matrix_export_csr.argtypes = [P, P, P, P, P]
     L.gp_matvec.argtypes = [P, P, I32, P, P]
     L.gp_matvec_noalloc.argtypes = [P, P, P, P]
+    L.gp_matrix_layout.argtypes = [P, C.POINTER(CMatrixLayout)]
     L.gp_solve_opts_default.argtypes = [C.POINTER(CSolveOpts)]
     L.gp_solve_opts_default.restype = None
     L.gp_loglik.argtypes = [P, P, P, C.POINTER(CSolveOpts), P, C.POINTER(CLoglikResult)]
@@ -121,6 +132,7 @@ def lib():
     L.gp_predictor_create.argtypes = [P, P, C.POINTER(CTheta), P, C.POINTER(P)]
     L.gp_predictor_destroy.argtypes = [P, P]
     L.gp_predict.argtypes = [P, P, I64, P, C.c_int, P]
+    L.gp_predict_batch.argtypes = [P, I32, C.POINTER(P), C.POINTER(I64), P, C.c_int, P]
     L.gp_mean_residual.argtypes = [P, I64, I32, P, C.POINTER(D), P, P]
     L.gp_predict_var.argtypes = [P, P, C.POINTER(CTheta), I64, P, C.POINTER(CSolveOpts), P, C.POINTER(CVarResult)]
     L.gp_profile_enable.argtypes = [P, I32]
@@ -407,6 +419,28 @@ class Context:
                                        C.c_void_p(_ptr(out))), "gp_predict")
         return out
 
+    def predict_batch(self, preds, xs, row_offsets, precision: int = FP64, out=None):
+        """Means of several requests in one launch: request r takes predictor
+        preds[r] at rows row_offsets[r]:row_offsets[r+1] of xs (device, m x d)."""
+        torch = _torch()
+        _check_dev_tensor(xs, torch.float64, name="xs")
+        nreq = len(preds)
+        off = np.ascontiguousarray(np.asarray(row_offsets, np.int64).reshape(-1))
+        if off.size != nreq + 1:
+            raise ValueError("row_offsets must have len(preds) + 1 entries")
+        m = int(off[-1]) if nreq else 0
+        d = preds[0].ds.d if nreq else xs.shape[1]
+        if xs.dim() != 2 or xs.shape[0] != m or xs.shape[1] != d:
+            raise ValueError(f"xs must be ({m}, {d}), got {tuple(xs.shape)}")
+        if out is None:
+            out = torch.empty(m, dtype=torch.float64, device=xs.device)
+        _check_dev_tensor(out, torch.float64, (m,), "out")
+        hp = (C.c_void_p * max(nreq, 1))(*[p._h.value for p in preds])
+        self._check(self._L.gp_predict_batch(self._h, nreq, hp, off.ctypes.data_as(C.POINTER(C.c_int64)),
+                                             C.c_void_p(_ptr(xs)), int(precision), C.c_void_p(_ptr(out))),
+                    "gp_predict_batch")
+        return out
+
     def mean_residual(self, W, beta, z, out=None):
         """y = z - W beta; W: (p, n) device float64 (row k = covariate k, the
         column-major n x p matrix of the C call), beta: p host values."""
@@ -500,6 +534,14 @@ class Matrix(_Obj):
         by = C.c_size_t()
         self.ctx._L.gp_matrix_info(self._h, None, None, C.byref(by), None, None)
         return by.value
+
+    def layout(self) -> dict:
+        """Storage layout counts (gp_matrix_layout), for byte accounting."""
+        lo = CMatrixLayout()
+        st = self.ctx._L.gp_matrix_layout(self._h, C.byref(lo))
+        if st != 0:
+            raise GPError(st, "gp_matrix_layout")
+        return lo.as_dict()
 
     def _destroy(self):
         self.ctx._L.gp_matrix_destroy(self.ctx._h, self._h)

@@ -821,8 +821,12 @@ gp_matrix* assemble(gp_ctx* c, const gp_dataset* ds, const gp_theta* th, int pre
     for (int64_t i = 0; i < nm; ++i) grows[cur[did[i]]++] = hmlist[i];
   }
   std::vector<int32_t> tiles, stiles, pieces;
+  int64_t nnz_group = 0, gemv_stage = 0, gemm_stage = 0;
   for (int64_t a = 0; a < nD; ++a) {
     const int32_t nu = static_cast<int32_t>(uoff[a + 1] - uoff[a]);
+    nnz_group += static_cast<int64_t>(goff[a + 1] - goff[a]) * nu;
+    gemv_stage += static_cast<int64_t>((goff[a + 1] - goff[a] + kTileRows - 1) / kTileRows) * nu;
+    gemm_stage += static_cast<int64_t>((goff[a + 1] - goff[a] + kSuperRows - 1) / kSuperRows) * nu;
     for (int32_t i = goff[a]; i < goff[a + 1]; i += kTileRows)
       tiles.insert(tiles.end(), {static_cast<int32_t>(a), i, std::min<int32_t>(kTileRows, goff[a + 1] - i), 0});
     for (int32_t i = goff[a]; i < goff[a + 1]; i += kSuperRows) {
@@ -855,6 +859,9 @@ gp_matrix* assemble(gp_ctx* c, const gp_dataset* ds, const gp_theta* th, int pre
 
   m->nugget = th->nugget;
   m->theta_hash = theta_hash(th);
+  m->nnz_group = nnz_group;
+  m->gemv_stage = gemv_stage;
+  m->gemm_stage = gemm_stage;
   m->nD = nD;
   m->utotal = utotal;
   m->nm = nm;

@@ -11,6 +11,8 @@ namespace gps {
 gp_predictor* make_predictor(gp_ctx* c, const gp_dataset* ds, const gp_theta* th, const double* alpha);
 void destroy_predictor(gp_ctx* c, gp_predictor* p);
 void predict(gp_ctx* c, const gp_predictor* p, int64_t m, const double* xs, int prec, double* out);
+void predict_batch(gp_ctx* c, int32_t nreq, const gp_predictor* const* preds, const int64_t* roff_host,
+                   const double* xs, int prec, double* out);
 
 // ------------------------------------------------------------------ memory
 void* dev_alloc(gp_ctx* c, size_t bytes) {
@@ -398,6 +400,23 @@ gp_status gp_matrix_info(const gp_matrix* m, int64_t* n, int64_t* nnz, size_t* b
   return GP_OK;
 }
 
+gp_status gp_matrix_layout(const gp_matrix* m, gp_matrix_layout_info* out) {
+  if (!m || !out) return GP_EINVAL;
+  std::memset(out, 0, sizeof(*out));
+  out->nnz_group = m->nnz_group;
+  out->nnz_csr = m->nnz - m->nnz_group;
+  out->group_rows = m->nm;
+  out->group_masks = m->nD;
+  out->group_list_entries = m->utotal;
+  out->gemv_stage_entries = m->gemv_stage;
+  out->gemm_stage_entries = m->gemm_stage;
+  out->long_rows = m->n_long;
+  out->col16 = m->col16 ? 1 : 0;
+  out->listed_rows = m->ntrow;
+  out->quad_entries = m->nquad;
+  return GP_OK;
+}
+
 gp_status gp_matrix_export_csr(gp_ctx* c, const gp_matrix* m, int64_t* row_ptr, int32_t* col, double* val) {
   if (!c || !m || !row_ptr || !col || !val) return GP_EINVAL;
   return guarded(c, [&] { gps::export_csr(c, m, row_ptr, col, val); });
@@ -515,6 +534,27 @@ gp_status gp_predict(gp_ctx* c, const gp_predictor* p, int64_t m, const double* 
     GPS_REQUIRE(m == 0 || (xs && mean), GP_EINVAL, "gp_predict: NULL buffer");
     GPS_REQUIRE(prec == GP_FP64 || prec == GP_MIXED, GP_EINVAL, "gp_predict: unknown precision");
     gps::predict(c, p, m, xs, prec, mean);
+    gps::sync(c);
+  });
+}
+
+gp_status gp_predict_batch(gp_ctx* c, int32_t nreq, const gp_predictor* const* preds, const int64_t* row_offsets,
+                           const double* xs, gp_precision prec, double* mean) {
+  if (!c) return GP_EINVAL;
+  return guarded(c, [&] {
+    GPS_REQUIRE(nreq >= 0, GP_EINVAL, "gp_predict_batch: nreq must be >= 0");
+    if (nreq == 0) return;
+    GPS_REQUIRE(preds && row_offsets, GP_EINVAL, "gp_predict_batch: NULL argument");
+    GPS_REQUIRE(prec == GP_FP64 || prec == GP_MIXED, GP_EINVAL, "gp_predict_batch: unknown precision");
+    GPS_REQUIRE(row_offsets[0] == 0, GP_EINVAL, "gp_predict_batch: row_offsets[0] must be 0");
+    for (int32_t r = 0; r < nreq; ++r) {
+      GPS_REQUIRE(preds[r] != nullptr, GP_EINVAL, "gp_predict_batch: NULL predictor");
+      GPS_REQUIRE(row_offsets[r + 1] >= row_offsets[r], GP_EINVAL,
+                  "gp_predict_batch: row_offsets must be non-decreasing");
+    }
+    const int64_t m = row_offsets[nreq];
+    GPS_REQUIRE(m == 0 || (xs && mean), GP_EINVAL, "gp_predict_batch: NULL buffer");
+    gps::predict_batch(c, nreq, preds, row_offsets, xs, prec, mean);
     gps::sync(c);
   });
 }

@@ -117,19 +117,29 @@ struct gp_matrix {
   // on the first one-column product; null when an offset does not fit
   int16_t* col16 = nullptr;
   bool col16_tried = false;
-  // row quads for the multi-column product, built on first use: for the
-  // group of binned rows 4g .. 4g+3, the ascending union of their CSR-part
-  // columns (rows with more than kLongRow entries left out) with the four
-  // rows' values per column (0 where a row has no entry)
-  int64_t nquad = 0;             // union entries over all groups
-  int64_t* qptr = nullptr;       // ceil(n / 4) + 1 offsets
-  int32_t* qcol = nullptr;       // nquad
+  // row quads of the multi-column product, built on first use.  The rows
+  // are listed line by line along the grid axis with the most cells (a line:
+  // the cells with every other cell coordinate fixed, one after another,
+  // binned order within a cell), each line padded to a multiple of four
+  // rows; quad q (listed rows 4q .. 4q+3) holds the ascending union of its
+  // rows' CSR-part columns (rows with more than kLongRow such entries left
+  // out) with the four rows' values per column (0 where a row has none).
+  int64_t ntrow = 0;             // listed rows (padded)
+  // per listed row: -1 (padding, or a row with more than kLongRow entries
+  // past its group part), the binned row (no group part) or -(row + 2)
+  int32_t* trow = nullptr;
+  int64_t nquad = 0;             // union entries over all quads
+  int64_t* qptr = nullptr;       // ntrow / 4 + 1 offsets
+  int32_t* qcol = nullptr;       // nquad column ids
   void* qval = nullptr;          // 4 * nquad float or double
   // rows with a bump-group mask start with the group entries of their mask
   // (|U_M| entries, shared column list U_M); the products treat these as dense
   // blocks (rows with mask M) x (columns U_M)
   int32_t* gskip = nullptr;     // n: number of leading group entries of each row
   int64_t nD = 0, utotal = 0, nm = 0, ntiles = 0, nstiles = 0, npieces = 0;
+  int64_t nnz_group = 0;        // entries in the group blocks (sum of gskip)
+  int64_t gemv_stage = 0;       // U_M entries staged by the one-column group product (sum over its tiles)
+  int64_t gemm_stage = 0;       // U_M entries staged by the multi-column group product (sum over super-tiles)
   int64_t* g_uoff = nullptr;    // nD + 1 offsets into g_ulist
   int32_t* g_ulist = nullptr;   // concatenated U_M (binned column ids, ascending)
   int32_t* g_rows = nullptr;    // rows with a mask, grouped by mask

@@ -84,17 +84,12 @@ struct PredArgs {
   const double* mF;
 };
 
+// The mean at one test point xp (local part over the cell window, plus the
+// bump groups through c_i when there is no core kernel).
 template <int D, bool MIXED, int CK>
-__global__ void __launch_bounds__(kThreads) k_predict(PredArgs a, CoreBasis cb, int64_t m,
-                                                      const double* __restrict__ xs, double* __restrict__ out) {
-  const int64_t t = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x;
-  if (t >= m) return;
-  double xp[3];
+__device__ __forceinline__ double predict_point(const PredArgs& a, const CoreBasis& cb, const double* xp) {
   int c[3] = {0, 0, 0};
-  for (int k = 0; k < D; ++k) {
-    xp[k] = xs[t * D + k];
-    c[k] = cell_coord(xp[k], a.lo[k], a.cell[k]);
-  }
+  for (int k = 0; k < D; ++k) c[k] = cell_coord(xp[k], a.lo[k], a.cell[k]);
   double sp = 0.0, Sp = 0.0;
   if constexpr (CK == 2) core_point_fields<D>(cb, xp, &sp, &Sp);
   int lo_[3] = {0, 0, 0}, hi_[3] = {0, 0, 0};
@@ -145,20 +140,57 @@ __global__ void __launch_bounds__(kThreads) k_predict(PredArgs a, CoreBasis cb, 
     }
     if (in_group) gsum += f * a.coef[i];
   }
-  out[t] = acc + gsum;
+  return acc + gsum;
+}
+
+template <int D, bool MIXED, int CK>
+__global__ void __launch_bounds__(kThreads) k_predict(PredArgs a, CoreBasis cb, int64_t m,
+                                                      const double* __restrict__ xs, double* __restrict__ out) {
+  const int64_t t = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x;
+  if (t >= m) return;
+  double xp[3];
+  for (int k = 0; k < D; ++k) xp[k] = xs[t * D + k];
+  out[t] = predict_point<D, MIXED, CK>(a, cb, xp);
+}
+
+// Request of row t of a batch: the last r with roff[r] <= t (empty requests
+// share their offset with the next one).
+__device__ __forceinline__ int batch_request(const int64_t* __restrict__ roff, int nreq, int64_t t) {
+  int lo = 0, hi = nreq - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (roff[mid] <= t)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+// Batched form: the rows of all requests in one launch, each row with the
+// arguments of its request's predictor.
+template <int D, bool MIXED, int CK>
+__global__ void __launch_bounds__(kThreads) k_predict_batch(const PredArgs* __restrict__ args,
+                                                            const CoreBasis* __restrict__ cbs,
+                                                            const int32_t* __restrict__ req_pred,
+                                                            const int64_t* __restrict__ roff, int nreq, int64_t m,
+                                                            const double* __restrict__ xs, double* __restrict__ out) {
+  const int64_t t = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x;
+  if (t >= m) return;
+  const int pi = req_pred[batch_request(roff, nreq, t)];
+  double xp[3];
+  for (int k = 0; k < D; ++k) xp[k] = xs[t * D + k];
+  out[t] = predict_point<D, MIXED, CK>(args[pi], cbs[pi], xp);
 }
 
 // Bump part with a core kernel: one wave per test point.  Lane i < n1 forms
 // f_i(x*) (bumps of group i in j order) into LDS; the lanes then stride over
 // the masked training points and the wave adds its lanes in a fixed order.
 template <int D, int CK>
-__global__ void __launch_bounds__(kThreads) k_predict_groups(PredArgs a, CoreBasis cb, int64_t m,
-                                                             const double* __restrict__ xs, double* __restrict__ out) {
-  __shared__ double fs[kThreads / kWave][kWave];
-  const int64_t t = (blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x) / kWave;
-  if (t >= m) return;  // uniform per wave
+__device__ __forceinline__ void predict_groups_point(const PredArgs& a, const CoreBasis& cb, int64_t t,
+                                                     const double* __restrict__ xs, double* __restrict__ out,
+                                                     double* f) {
   const int lane = lane_id();
-  double* f = fs[threadIdx.x / kWave];
   double xp[3];
   for (int k = 0; k < D; ++k) xp[k] = xs[t * D + k];
   bool in_group = false;
@@ -207,6 +239,30 @@ __global__ void __launch_bounds__(kThreads) k_predict_groups(PredArgs a, CoreBas
 #pragma unroll
   for (int off = kWave / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kWave);
   if (lane == 0) out[t] += acc;
+}
+
+template <int D, int CK>
+__global__ void __launch_bounds__(kThreads) k_predict_groups(PredArgs a, CoreBasis cb, int64_t m,
+                                                             const double* __restrict__ xs, double* __restrict__ out) {
+  __shared__ double fs[kThreads / kWave][kWave];
+  const int64_t t = (blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x) / kWave;
+  if (t >= m) return;  // uniform per wave
+  predict_groups_point<D, CK>(a, cb, t, xs, out, fs[threadIdx.x / kWave]);
+}
+
+template <int D, int CK>
+__global__ void __launch_bounds__(kThreads) k_predict_groups_batch(const PredArgs* __restrict__ args,
+                                                                   const CoreBasis* __restrict__ cbs,
+                                                                   const int32_t* __restrict__ req_pred,
+                                                                   const int64_t* __restrict__ roff, int nreq,
+                                                                   int64_t m, const double* __restrict__ xs,
+                                                                   double* __restrict__ out) {
+  __shared__ double fs[kThreads / kWave][kWave];
+  const int64_t t = (blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x) / kWave;
+  if (t >= m) return;  // uniform per wave
+  const int pi = req_pred[batch_request(roff, nreq, t)];
+  if (args[pi].nm == 0) return;  // no masked training points: no group part (uniform per wave)
+  predict_groups_point<D, CK>(args[pi], cbs[pi], t, xs, out, fs[threadIdx.x / kWave]);
 }
 
 }  // namespace
@@ -281,8 +337,7 @@ void destroy_predictor(gp_ctx* c, gp_predictor* p) {
   delete p;
 }
 
-void predict(gp_ctx* c, const gp_predictor* p, int64_t m, const double* xs, int prec, double* out) {
-  if (m == 0) return;
+static PredArgs pred_args(const gp_predictor* p) {
   const gp_dataset* ds = p->ds;
   PredArgs a{};
   a.kt = p->kt;
@@ -302,6 +357,13 @@ void predict(gp_ctx* c, const gp_predictor* p, int64_t m, const double* xs, int 
   a.mlist = p->mlist;
   a.mmask = p->mmask;
   a.mF = p->mF;
+  return a;
+}
+
+void predict(gp_ctx* c, const gp_predictor* p, int64_t m, const double* xs, int prec, double* out) {
+  if (m == 0) return;
+  const gp_dataset* ds = p->ds;
+  const PredArgs a = pred_args(p);
   const dim3 G(grid_for(m, kThreads)), B(kThreads);
   ProfScope ps(c, prec == GP_MIXED ? "predict_f32" : "predict_f64");
   auto go = [&](auto DD) {
@@ -332,6 +394,82 @@ void predict(gp_ctx* c, const gp_predictor* p, int64_t m, const double* xs, int 
   else
     go(std::integral_constant<int, 3>{});
   check_launch("predict");
+}
+
+void predict_batch(gp_ctx* c, int32_t nreq, const gp_predictor* const* preds, const int64_t* roff_host,
+                   const double* xs, int prec, double* out) {
+  for (int32_t r = 0; r < nreq; ++r) {
+    GPS_REQUIRE(preds[r]->ds->d == preds[0]->ds->d, GP_EINVAL,
+                "gp_predict_batch: all predictors must have the same dimension");
+    GPS_REQUIRE(preds[r]->kt.core.kind == preds[0]->kt.core.kind, GP_EINVAL,
+                "gp_predict_batch: all predictors must have the same core kernel kind");
+  }
+  const int64_t m = roff_host[nreq];
+  if (m == 0) return;
+  // distinct predictors, in order of first appearance
+  std::vector<const gp_predictor*> uniq;
+  std::vector<int32_t> req_pred(nreq);
+  for (int32_t r = 0; r < nreq; ++r) {
+    int32_t k = 0;
+    while (k < static_cast<int32_t>(uniq.size()) && uniq[k] != preds[r]) ++k;
+    if (k == static_cast<int32_t>(uniq.size())) uniq.push_back(preds[r]);
+    req_pred[r] = k;
+  }
+  const int d = uniq[0]->ds->d;
+  const int ck = uniq[0]->kt.core.kind;
+  bool any_nm = false;
+  for (const gp_predictor* p : uniq) any_nm = any_nm || p->nm > 0;
+  const size_t np = uniq.size();
+  const size_t b_args = sizeof(PredArgs) * np, b_cb = sizeof(CoreBasis) * np;
+  const size_t b_req = sizeof(int32_t) * nreq, b_off = sizeof(int64_t) * (nreq + 1);
+  auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
+  const size_t total = up(b_args) + up(b_cb) + up(b_req) + up(b_off);
+  char* dbuf = static_cast<char*>(workspace(c, 123, total));
+  char* hbuf = static_cast<char*>(pinned_for_write(c, total));
+  PredArgs* ha = reinterpret_cast<PredArgs*>(hbuf);
+  CoreBasis* hc = reinterpret_cast<CoreBasis*>(hbuf + up(b_args));
+  for (size_t k = 0; k < np; ++k) {
+    ha[k] = pred_args(uniq[k]);
+    hc[k] = uniq[k]->cb;
+  }
+  std::memcpy(hbuf + up(b_args) + up(b_cb), req_pred.data(), b_req);
+  std::memcpy(hbuf + up(b_args) + up(b_cb) + up(b_req), roff_host, b_off);
+  h2d_async(c, dbuf, hbuf, total);
+  const PredArgs* da = reinterpret_cast<const PredArgs*>(dbuf);
+  const CoreBasis* dc = reinterpret_cast<const CoreBasis*>(dbuf + up(b_args));
+  const int32_t* dreq = reinterpret_cast<const int32_t*>(dbuf + up(b_args) + up(b_cb));
+  const int64_t* droff = reinterpret_cast<const int64_t*>(dbuf + up(b_args) + up(b_cb) + up(b_req));
+  const dim3 G(grid_for(m, kThreads)), B(kThreads);
+  ProfScope ps(c, prec == GP_MIXED ? "predict_batch_f32" : "predict_batch_f64");
+  auto go = [&](auto DD) {
+    constexpr int D = decltype(DD)::value;
+    auto with_core = [&](auto CC) {
+      constexpr int CK = decltype(CC)::value;
+      if (prec == GP_MIXED)
+        hipLaunchKernelGGL((k_predict_batch<D, true, CK>), G, B, 0, c->stream, da, dc, dreq, droff, nreq, m, xs, out);
+      else
+        hipLaunchKernelGGL((k_predict_batch<D, false, CK>), G, B, 0, c->stream, da, dc, dreq, droff, nreq, m, xs,
+                           out);
+      if constexpr (CK != 0) {
+        if (any_nm)
+          hipLaunchKernelGGL((k_predict_groups_batch<D, CK>), dim3(grid_for(m * kWave, kThreads)), B, 0, c->stream,
+                             da, dc, dreq, droff, nreq, m, xs, out);
+      }
+    };
+    if (ck == GP_CORE_MATERN)
+      with_core(std::integral_constant<int, 1>{});
+    else if (ck == GP_CORE_PACIOREK)
+      with_core(std::integral_constant<int, 2>{});
+    else
+      with_core(std::integral_constant<int, 0>{});
+  };
+  if (d == 1)
+    go(std::integral_constant<int, 1>{});
+  else if (d == 2)
+    go(std::integral_constant<int, 2>{});
+  else
+    go(std::integral_constant<int, 3>{});
+  check_launch("predict batch");
 }
 
 }  // namespace gps

@@ -8,6 +8,7 @@
 //
 // SpMM: k <= 32 right-hand sides, X and Y row-major n x ld, optional
 // symmetric diagonal scaling Y = S K S X (see k_spmm).
+#include <algorithm>
 #include <type_traits>
 
 #include "device.hpp"
@@ -763,7 +764,89 @@ __global__ void __launch_bounds__(kThreads) k_group_reduce(const int32_t* __rest
 namespace {
 
 // ------------------------------------------------------------ row quads
+// The CSR part of the 32-column product reads one 256-byte row of X per
+// stored entry.  Rows next to each other along the grid axis with the most
+// cells (at the space-time workload: one station on consecutive days) share
+// most of their columns, so the rows are listed line by line along that axis
+// (a line: the cells with all other cell coordinates fixed, binned order
+// within a cell) and every four consecutive listed rows form a quad that
+// stores the ascending union of its rows' columns once, with the four rows'
+// values per entry: one gather of an X row serves four rows.  Consecutive
+// quads of a line share many X rows, which then come from the caches.
 constexpr int kQuad = 4;
+constexpr int kLineThreads = 256;
+
+struct LineGeom {
+  int a;            // axis along which a line runs
+  int nother;       // number of other axes
+  int o[2];         // the other axes, fastest first
+  int32_t g[3];     // cells per axis
+  int64_t stride[3];
+};
+
+// exclusive prefix sum over the block of v (kLineThreads threads); *total
+// receives the block's sum
+__device__ __forceinline__ int32_t block_excl_scan(int32_t v, int32_t* total) {
+  __shared__ int32_t wsum[kLineThreads / kWave];
+  const int lane = lane_id(), w = threadIdx.x / kWave;
+  int32_t x = v;
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    const int32_t y = __shfl_up(x, off, kWave);
+    if (lane >= off) x += y;
+  }
+  __syncthreads();  // wsum of an earlier call has been read
+  if (lane == kWave - 1) wsum[w] = x;
+  __syncthreads();
+  int32_t before = 0, all = 0;
+#pragma unroll
+  for (int i = 0; i < kLineThreads / kWave; ++i) {
+    if (i < w) before += wsum[i];
+    all += wsum[i];
+  }
+  *total = all;
+  return before + x - v;
+}
+
+// Block per line.  PASS 0: the line's row count padded to a multiple of four
+// (lpad).  PASS 1: the line's rows in order of their cells along the line
+// (binned order within a cell), then the padding (-1).
+template <int PASS>
+__global__ void __launch_bounds__(kLineThreads) k_line_rows(LineGeom lg, const int32_t* __restrict__ cell_start,
+                                                             int32_t* __restrict__ lpad, const int64_t* __restrict__ loff,
+                                                             int32_t* __restrict__ trow) {
+  const int64_t L = blockIdx.x;
+  int64_t base = 0, r = L;
+  for (int j = 0; j < lg.nother; ++j) {
+    const int ax = lg.o[j];
+    base += (r % lg.g[ax]) * lg.stride[ax];
+    r /= lg.g[ax];
+  }
+  const int64_t sa = lg.stride[lg.a];
+  const int ga = lg.g[lg.a];
+  const int64_t out0 = PASS == 1 ? loff[L] : 0;
+  int64_t running = 0;
+  for (int i0 = 0; i0 < ga; i0 += kLineThreads) {
+    const int i = i0 + static_cast<int>(threadIdx.x);
+    int32_t cs = 0, cnt = 0;
+    if (i < ga) {
+      const int64_t key = base + i * sa;
+      cs = cell_start[key];
+      cnt = cell_start[key + 1] - cs;
+    }
+    int32_t total;
+    const int32_t ex = block_excl_scan(cnt, &total);
+    if constexpr (PASS == 1)
+      for (int32_t j = 0; j < cnt; ++j) trow[out0 + running + ex + j] = cs + j;
+    running += total;
+  }
+  const int64_t pad = (running + kQuad - 1) / kQuad * kQuad;
+  if constexpr (PASS == 0) {
+    if (threadIdx.x == 0) lpad[L] = static_cast<int32_t>(pad);
+  } else {
+    for (int64_t j = running + threadIdx.x; j < pad; j += kLineThreads) trow[out0 + j] = -1;
+  }
+}
 
 // orders the LDS accesses of one wave (its own slice; no block barrier)
 __device__ __forceinline__ void wave_sync_lds() {
@@ -772,16 +855,17 @@ __device__ __forceinline__ void wave_sync_lds() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// The CSR-part column lists of the rows of group g (rows with more than
-// kLongRow entries count as empty): begin and end of each.
-__device__ __forceinline__ void quad_lists(int64_t n, int64_t g, const int64_t* __restrict__ rp,
-                                           const int32_t* __restrict__ gskip, int64_t (&h)[kQuad],
-                                           int64_t (&e)[kQuad]) {
+// The CSR-part column lists of the rows of quad g (listed rows 4g .. 4g+3;
+// padding and rows with more than kLongRow entries count as empty): begin and
+// end of each.
+__device__ __forceinline__ void quad_lists(int64_t g, const int32_t* __restrict__ trow,
+                                           const int64_t* __restrict__ rp, const int32_t* __restrict__ gskip,
+                                           int64_t (&h)[kQuad], int64_t (&e)[kQuad]) {
 #pragma unroll
   for (int i = 0; i < kQuad; ++i) {
-    const int64_t r = g * kQuad + i;
+    const int32_t r = trow[g * kQuad + i];
     h[i] = e[i] = 0;
-    if (r < n) {
+    if (r >= 0) {
       const int64_t s = rp[r] + gskip[r], t = rp[r + 1];
       if (t - s <= kLongRow) {
         h[i] = s;
@@ -805,18 +889,19 @@ __device__ __forceinline__ int list_bound(const int32_t* lst, int len, int32_t c
   return lo;
 }
 
-// One wave per group.  The four rows' CSR-part column lists (ascending, at
+// One wave per quad.  The four rows' CSR-part column lists (ascending, at
 // most kLongRow each) are loaded into the wave's LDS slice; every entry (row
 // i, position j, column c) finds its place in the merged order by (column,
 // row): j plus, in each other row k, the number of columns < c (k > i) or
 // <= c (k < i).  Equal columns are then adjacent, at most one per row; the
-// first of each run starts a union entry, numbered by a ballot scan.
-// PASS 0 writes the union length of each group, PASS 1 the ascending union
-// with the four rows' values (0 where a row lacks the column).
+// first of each run starts a quad entry, numbered by a ballot scan.
+// PASS 0 writes the number of entries of each quad, PASS 1 the ascending
+// column ids with the four rows' values (0 where a row lacks the column).
 constexpr int kQuadMax = kQuad * kLongRow;
 
 template <typename VT, int PASS>
-__global__ void __launch_bounds__(kThreads) k_quad_build(int64_t n, int64_t ngroups, const int64_t* __restrict__ rp,
+__global__ void __launch_bounds__(kThreads) k_quad_build(int64_t ngroups, const int32_t* __restrict__ trow,
+                                                         const int64_t* __restrict__ rp,
                                                          const int32_t* __restrict__ gskip,
                                                          const int32_t* __restrict__ col, const VT* __restrict__ val,
                                                          int32_t* __restrict__ cnt, const int64_t* __restrict__ qptr,
@@ -828,7 +913,7 @@ __global__ void __launch_bounds__(kThreads) k_quad_build(int64_t n, int64_t ngro
   const int64_t g = blockIdx.x * static_cast<int64_t>(kThreads / kWave) + w;
   if (g >= ngroups) return;  // uniform over the wave
   int64_t h[kQuad], e[kQuad];
-  quad_lists(n, g, rp, gskip, h, e);
+  quad_lists(g, trow, rp, gskip, h, e);
   int len[kQuad], off[kQuad + 1];
   off[0] = 0;
 #pragma unroll
@@ -892,9 +977,25 @@ __global__ void __launch_bounds__(kThreads) k_quad_build(int64_t n, int64_t ngro
     if (lane == 0) cnt[g] = running;
 }
 
-// CSR part of Y = S K S X D for the short rows, four rows at a time (four
-// consecutive binned rows share most of their local columns: at the
-// space-time workload a union entry serves 1.9 row entries): lane l
+// Row codes of the listed rows for the product: -1 for padding and for rows
+// with more than kLongRow entries past their group part, the row for a row
+// without a group part, -(row + 2) for a row with one.
+__global__ void __launch_bounds__(kThreads) k_quad_codes(int64_t ntrow, const int32_t* __restrict__ trow,
+                                                         const int64_t* __restrict__ rp,
+                                                         const int32_t* __restrict__ gskip, int32_t* __restrict__ code) {
+  const int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x;
+  if (i >= ntrow) return;
+  const int32_t r = trow[i];
+  int32_t c = -1;
+  if (r >= 0) {
+    const int32_t gs = gskip[r];
+    if (rp[r + 1] - rp[r] - gs <= kLongRow) c = gs ? -r - 2 : r;
+  }
+  code[i] = c;
+}
+
+// CSR part of Y = S K S X D for the short rows, one quad at a time (four
+// consecutive listed rows share most of their local columns): lane l
 // stages union entry j0 + l of the group (column id and the four rows'
 // weights, times the column's scale) in the wave's LDS slice; then each
 // 16-byte load of an X row serves all four rows.  The same column split as
@@ -904,10 +1005,10 @@ constexpr int kQuadsPerWave = 2;
 constexpr int kQuadUq = 2;  // X loads in flight per lane (two keep the kernel at 68 registers)
 
 template <typename VT, bool SCALE>
-__global__ void __launch_bounds__(kThreads) k_spmm_quad(int64_t n, int64_t ngroups, const int64_t* __restrict__ qptr,
+__global__ void __launch_bounds__(kThreads) k_spmm_quad(int64_t ngroups, const int64_t* __restrict__ qptr,
                                                         const int32_t* __restrict__ qcol,
-                                                        const VT* __restrict__ qval, const int64_t* __restrict__ rp,
-                                                        const int32_t* __restrict__ gskip, int k, int ld,
+                                                        const VT* __restrict__ qval, const int32_t* __restrict__ code,
+                                                        int k, int ld,
                                                         const double* __restrict__ X, double* __restrict__ Y,
                                                         const double* __restrict__ scale,
                                                         const double* __restrict__ colscale) {
@@ -971,19 +1072,18 @@ __global__ void __launch_bounds__(kThreads) k_spmm_quad(int64_t n, int64_t ngrou
     }
 #pragma unroll
     for (int r = 0; r < kQuad; ++r) {
-      const int64_t row = g * kQuad + r;
       slot_sum<double>(acc[r]);
-      if (row >= n) continue;
-      const int64_t rs = rp[row] + gskip[row], re = rp[row + 1];
-      if (re - rs > kLongRow) continue;  // written by the long-row blocks
+      const int32_t cr = code[g * kQuad + r];
+      if (cr == -1) continue;  // padding, or a row written by the long-row blocks
+      const bool grow = cr < -1;
+      const int64_t row = grow ? -static_cast<int64_t>(cr) - 2 : cr;
       if (lane < V::kLpe) {
-        const int32_t gsk = gskip[row];
         double* yr = Y + row * ld + lane * V::kCpl;
 #pragma unroll
         for (int t = 0; t < V::kCpl; ++t) {
           if (lane * V::kCpl + t >= k) break;
           double a = acc[r].v[t];
-          if (gsk) a = yr[t] + a;
+          if (grow) a = yr[t] + a;
           if constexpr (SCALE) a *= scale[row];
           if (colscale) a *= csv[t];
           yr[t] = a;
@@ -997,38 +1097,73 @@ __global__ void __launch_bounds__(kThreads) k_spmm_quad(int64_t n, int64_t ngrou
 
 void free_quads(gp_ctx* c, gp_matrix* m) {
   const size_t vbytes = m->prec == GP_MIXED ? sizeof(float) : sizeof(double);
-  const int64_t ng = (m->n + kQuad - 1) / kQuad;
+  const int64_t ng = m->ntrow / kQuad;
+  if (m->trow) dev_free(c, m->trow, sizeof(int32_t) * std::max<int64_t>(m->ntrow, 1));
   if (m->qptr) dev_free(c, m->qptr, sizeof(int64_t) * (ng + 1));
   if (m->qcol) dev_free(c, m->qcol, sizeof(int32_t) * std::max<int64_t>(m->nquad, 1));
   if (m->qval) dev_free(c, m->qval, vbytes * kQuad * std::max<int64_t>(m->nquad, 1));
+  m->trow = nullptr;
   m->qptr = nullptr;
   m->qcol = nullptr;
   m->qval = nullptr;
-  m->nquad = 0;
+  m->ntrow = m->nquad = 0;
 }
 
 static void build_quads(gp_ctx* c, gp_matrix* m) {
   if (m->qptr) return;
   ProfScope ps(c, "quad_build");
-  const int64_t n = m->n, ng = (n + kQuad - 1) / kQuad;
+  const gp_dataset* ds = m->ds;
   try {
-    int32_t* cnt = static_cast<int32_t*>(workspace(c, 122, sizeof(int32_t) * ng));
+    // lines along the axis with the most cells (ties: the lowest axis)
+    LineGeom lg{};
+    lg.a = 0;
+    for (int k = 1; k < ds->d; ++k)
+      if (ds->g[k] > ds->g[lg.a]) lg.a = k;
+    int64_t st = 1;
+    for (int k = 0; k < 3; ++k) {
+      lg.g[k] = k < ds->d ? ds->g[k] : 1;
+      lg.stride[k] = st;
+      st *= lg.g[k];
+    }
+    lg.nother = 0;
+    for (int k = 0; k < ds->d; ++k)
+      if (k != lg.a) lg.o[lg.nother++] = k;
+    const int64_t nlines = ds->ncells / lg.g[lg.a];
+    GPS_REQUIRE(nlines * lg.g[lg.a] == ds->ncells, GP_EDEVICE, "quad build: grid does not match the dataset's cells");
+    TmpBuf lpad(c, sizeof(int32_t) * nlines), loff(c, sizeof(int64_t) * (nlines + 1));
+    hipLaunchKernelGGL((k_line_rows<0>), dim3(static_cast<unsigned>(nlines)), dim3(kLineThreads), 0, c->stream, lg,
+                       ds->cell_start, lpad.as<int32_t>(), nullptr, nullptr);
+    check_launch("line rows");
+    scan_i32_to_i64(c, lpad.as<int32_t>(), loff.as<int64_t>(), nlines);
+    m->ntrow = read_i64(c, loff.as<int64_t>() + nlines);
+    GPS_REQUIRE(m->ntrow < (int64_t(1) << 31), GP_ENOMEM, "quad build: too many rows");
+    m->trow = dev_new<int32_t>(c, std::max<int64_t>(m->ntrow, 1));
+    TmpBuf trow(c, sizeof(int32_t) * std::max<int64_t>(m->ntrow, 1));
+    hipLaunchKernelGGL((k_line_rows<1>), dim3(static_cast<unsigned>(nlines)), dim3(kLineThreads), 0, c->stream, lg,
+                       ds->cell_start, nullptr, loff.as<int64_t>(), trow.as<int32_t>());
+    check_launch("line rows");
+    const int64_t ng = m->ntrow / kQuad;
+    TmpBuf cnt(c, sizeof(int32_t) * std::max<int64_t>(ng, 1));
     m->qptr = dev_new<int64_t>(c, ng + 1);
     auto go = [&](auto vt) {
       using VT = decltype(vt);
       const VT* val = static_cast<const VT*>(m->val);
       const unsigned nbb = grid_for(ng, kThreads / kWave);
-      hipLaunchKernelGGL((k_quad_build<VT, 0>), dim3(nbb), dim3(kThreads), 0, c->stream, n, ng,
-                         m->row_ptr, m->gskip, m->col, val, cnt, nullptr, nullptr, nullptr);
+      hipLaunchKernelGGL((k_quad_build<VT, 0>), dim3(nbb), dim3(kThreads), 0, c->stream, ng, trow.as<int32_t>(),
+                         m->row_ptr, m->gskip, m->col, val, cnt.as<int32_t>(), nullptr, nullptr, nullptr);
       check_launch("quad count");
-      scan_i32_to_i64(c, cnt, m->qptr, ng);
+      scan_i32_to_i64(c, cnt.as<int32_t>(), m->qptr, ng);
       m->nquad = read_i64(c, m->qptr + ng);
       m->qcol = dev_new<int32_t>(c, std::max<int64_t>(m->nquad, 1));
       m->qval = dev_alloc(c, sizeof(VT) * kQuad * std::max<int64_t>(m->nquad, 1));
-      hipLaunchKernelGGL((k_quad_build<VT, 1>), dim3(nbb), dim3(kThreads), 0, c->stream, n, ng,
+      hipLaunchKernelGGL((k_quad_build<VT, 1>), dim3(nbb), dim3(kThreads), 0, c->stream, ng, trow.as<int32_t>(),
                          m->row_ptr, m->gskip, m->col, val, nullptr, m->qptr, m->qcol, static_cast<VT*>(m->qval));
       check_launch("quad fill");
-      m->bytes += sizeof(int64_t) * (ng + 1) + (sizeof(int32_t) + sizeof(VT) * kQuad) * m->nquad;
+      hipLaunchKernelGGL(k_quad_codes, dim3(grid_for(m->ntrow, kThreads)), dim3(kThreads), 0, c->stream, m->ntrow,
+                         trow.as<int32_t>(), m->row_ptr, m->gskip, m->trow);
+      check_launch("quad row codes");
+      sync(c);  // the temporaries are released when their scopes end
+      m->bytes += sizeof(int32_t) * m->ntrow + sizeof(int64_t) * (ng + 1) + (sizeof(int32_t) + sizeof(VT) * kQuad) * m->nquad;
     };
     if (m->prec == GP_MIXED)
       go(float{});
@@ -1067,12 +1202,13 @@ void spmm(gp_ctx* c, const gp_matrix* m, int k, int ld, const T* X, T* Y, const 
     }
     if (vec) {
       // short rows over the row quads; the long rows by k_spmm's block-per-row path
-      const int64_t ng = (m->n + kQuad - 1) / kQuad;
-      const unsigned nbq =
-          static_cast<unsigned>(round_up8(grid_for((ng + kQuadsPerWave - 1) / kQuadsPerWave, kThreads / kWave)));
-      hipLaunchKernelGGL((k_spmm_quad<VT, SC>), dim3(nbq), dim3(kThreads), 0, c->stream, m->n, ng, mm->qptr,
-                         mm->qcol, static_cast<const VT*>(mm->qval), m->row_ptr, m->gskip, k, ld, X, Y, scale,
-                         colscale);
+      const int64_t ng = mm->ntrow / kQuad;
+      if (ng > 0) {
+        const unsigned nbq =
+            static_cast<unsigned>(round_up8(grid_for((ng + kQuadsPerWave - 1) / kQuadsPerWave, kThreads / kWave)));
+        hipLaunchKernelGGL((k_spmm_quad<VT, SC>), dim3(nbq), dim3(kThreads), 0, c->stream, ng, mm->qptr, mm->qcol,
+                           static_cast<const VT*>(mm->qval), mm->trow, k, ld, X, Y, scale, colscale);
+      }
       if (m->n_long > 0)
         hipLaunchKernelGGL((k_spmm<VT, T, SC, true>), dim3(static_cast<unsigned>(m->n_long)), dim3(kThreads), 0,
                            c->stream, m->n, 0u, m->n_long, m->long_rows, k, ld, m->row_ptr, m->gskip, m->col,

@@ -11,8 +11,10 @@ Admission is first-in first-out under an HBM budget: the request at the head
 of the queue starts as soon as a slot is free and its footprint estimate fits
 in the budget not reserved by running requests.  A request whose footprint
 exceeds the whole budget is rejected with GP_ENOMEM.  Prediction requests
-for the same predictor that are waiting together are batched into one launch
-(their test points concatenated) and split afterwards.
+that are waiting together are batched into one launch (gp_predict_batch: the
+rows of all requests back to back with a row-offset table, each request with
+its own predictor) when the backend can run them together, and split
+afterwards.
 
 The scheduling logic is independent of the device: a ``Backend`` runs one
 request (or batch) and estimates footprints.  ``GpuBackend`` uses the HIP
@@ -78,6 +80,10 @@ class Backend:
 
     def run_predict(self, slot: int, reqs: List[PredictRequest]):
         raise NotImplementedError
+
+    def can_batch(self, a: PredictRequest, b: PredictRequest) -> bool:
+        """Whether b may join a's prediction launch (default: same predictor)."""
+        return a.predictor == b.predictor and a.precision == b.precision
 
 
 class Server:
@@ -168,14 +174,13 @@ class Server:
                             break
                         batch = [waiting.popleft()]
                         if isinstance(head, PredictRequest):
-                            # merge waiting requests for the same predictor into one launch
+                            # merge waiting requests the backend can run in the same launch
                             pts = _npts(head.xs)
                             keep = collections.deque()
                             while waiting:
                                 r = waiting.popleft()
                                 fr = self.backend.footprint(r)
-                                if (isinstance(r, PredictRequest) and r.predictor == head.predictor
-                                        and r.precision == head.precision
+                                if (isinstance(r, PredictRequest) and _can_batch(self.backend, head, r)
                                         and pts + _npts(r.xs) <= self.max_batch_points
                                         and reserved + fp + fr <= self.budget):
                                     batch.append(r)
@@ -204,6 +209,11 @@ class Server:
 
 def _npts(xs) -> int:
     return int(xs.shape[0])
+
+
+def _can_batch(backend, a: PredictRequest, b: PredictRequest) -> bool:
+    f = getattr(backend, "can_batch", None)
+    return f(a, b) if f is not None else Backend.can_batch(backend, a, b)
 
 
 def latency_stats(comps: List[Completion]) -> dict:
@@ -257,8 +267,15 @@ class GpuBackend(Backend):
             alpha = torch.empty(ds.n, dtype=torch.float64, device=self.dev)
             self.setup.solve(K, yd, alpha)
             K.close()
-        self.predictors[name] = (self.setup.predictor(ds, theta, alpha), ds.d)
+        core = getattr(theta, "core", None)
+        kind = int(core.kind) if core is not None else 0
+        self.predictors[name] = (self.setup.predictor(ds, theta, alpha), ds.d, kind)
         torch.cuda.synchronize(self.device)
+
+    def can_batch(self, a: PredictRequest, b: PredictRequest) -> bool:
+        # one gp_predict_batch launch takes predictors of one dimension and core kind
+        pa, pb = self.predictors[a.predictor], self.predictors[b.predictor]
+        return a.precision == b.precision and pa[1:] == pb[1:]
 
     def footprint(self, req) -> int:
         if isinstance(req, LoglikRequest):
@@ -290,12 +307,13 @@ class GpuBackend(Backend):
     def run_predict(self, slot: int, reqs: List[PredictRequest]):
         torch = self.torch
         ctx = self.ctxs[slot]
-        pred, d = self.predictors[reqs[0].predictor]
+        preds = [self.predictors[r.predictor][0] for r in reqs]
         with torch.cuda.stream(self.streams[slot]):
             parts = [torch.as_tensor(np.ascontiguousarray(r.xs), dtype=torch.float64, device=self.dev)
                      if not isinstance(r.xs, torch.Tensor) else r.xs for r in reqs]
             xs = parts[0] if len(parts) == 1 else torch.cat(parts, 0)
-            m = ctx.predict(pred, xs, precision=reqs[0].precision)
+            off = np.concatenate([[0], np.cumsum([q.shape[0] for q in parts])])
+            m = ctx.predict_batch(preds, xs, off, precision=reqs[0].precision)
             host = m.cpu().numpy()
         out, o = [], 0
         for p in parts:

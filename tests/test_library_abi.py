@@ -48,7 +48,7 @@ def test_struct_layouts_match_header(tmp_path):
     if cc is None:
         pytest.skip("no C compiler")
     structs = {"gp_theta": _lib.CTheta, "gp_core": _lib.CCore, "gp_solve_opts": _lib.CSolveOpts,
-               "gp_loglik_result": _lib.CLoglikResult}
+               "gp_loglik_result": _lib.CLoglikResult, "gp_matrix_layout_info": _lib.CMatrixLayout}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "gpsparse.h"', "int main(void) {"]
     for cname, py in structs.items():
         lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
