@@ -60,7 +60,12 @@ typedef enum gp_precision {
 typedef enum gp_logdet_mode {
   GP_LOGDET_SLQ = 0,    /* stochastic Lanczos quadrature (Sec. 3.3 Lanczos log-det) */
   GP_LOGDET_EXACT = 1,  /* Lanczos to dimension n with full re-orthogonalisation (n <= 8192) */
-  GP_LOGDET_NONE = 2    /* skip the log-determinant (quadratic form only) */
+  GP_LOGDET_NONE = 2,   /* skip the log-determinant (quadratic form only) */
+  GP_LOGDET_SLQ_REORTH = 3  /* the SLQ estimator with every residual re-orthogonalised
+                               against all Lanczos vectors (classical Gram-Schmidt,
+                               twice): the basis stays orthonormal to rounding, so runs
+                               that differ only in rounding agree closely (parity runs);
+                               work space n_lanczos x n x 32 float64 */
 } gp_logdet_mode;
 
 typedef struct gp_ctx gp_ctx;

@@ -68,16 +68,26 @@ def rademacher(seed: int, probe: int, orig_index):
     return np.where((out >> np.uint64(63)) != 0, -1.0, 1.0)
 
 
-def lanczos(matvec, v1, k: int, tol: float):
-    """Plain three-term Lanczos from unit v1; returns (alpha[0:j], beta[0:j-1])."""
+def lanczos(matvec, v1, k: int, tol: float, reorth: bool = False):
+    """Three-term Lanczos from unit v1; returns (alpha[0:j], beta[0:j-1]).
+
+    Plain by default.  With ``reorth`` every new residual is made orthogonal
+    to all Lanczos vectors so far by classical Gram-Schmidt applied twice
+    (w -= Q (Q^T w), twice) after the alpha step, so the basis stays
+    orthonormal to rounding and the recurrence does not amplify rounding."""
     alphas, betas = [], []
     v_prev = np.zeros_like(v1)
     v = v1
     beta_prev = 0.0
+    basis = [v1]
     for j in range(k):
         w = matvec(v) - beta_prev * v_prev
         a = float(v @ w)
         w = w - a * v
+        if reorth:
+            Q = np.array(basis)
+            for _ in range(2):
+                w = w - Q.T @ (Q @ w)
         alphas.append(a)
         if j == k - 1:
             break
@@ -87,6 +97,8 @@ def lanczos(matvec, v1, k: int, tol: float):
         betas.append(b)
         v_prev, v = v, w / b
         beta_prev = b
+        if reorth:
+            basis.append(v)
     return np.array(alphas), np.array(betas)
 
 
@@ -100,10 +112,11 @@ def gauss_quadrature_log(alphas, betas, znorm2: float) -> float:
 
 
 def slq_logdet(A, seed: int, n_probes: int = 30, n_steps: int = 50, tol: float = 1e-10,
-               orig_index=None):
+               orig_index=None, reorth: bool = False):
     """SLQ estimate of log det A for sparse or dense SPD A (rows in the order
-    of ``orig_index``; identity order if None).  Returns dict with the
-    estimate, its standard error, per-probe quadratures and the Jacobi part."""
+    of ``orig_index``; identity order if None); plain Lanczos, or with full
+    re-orthogonalisation (``reorth``).  Returns dict with the estimate, its
+    standard error, per-probe quadratures and the Jacobi part."""
     n = A.shape[0]
     diag = np.asarray(A.diagonal(), np.float64)
     s = 1.0 / np.sqrt(diag)
@@ -118,7 +131,7 @@ def slq_logdet(A, seed: int, n_probes: int = 30, n_steps: int = 50, tol: float =
     for l in range(n_probes):
         z = rademacher(seed, l, orig_index)
         znorm2 = float(z @ z)
-        al, be = lanczos(matvec, z / math.sqrt(znorm2), n_steps, tol)
+        al, be = lanczos(matvec, z / math.sqrt(znorm2), n_steps, tol, reorth)
         gam[l] = gauss_quadrature_log(al, be, znorm2)
         steps[l] = len(al)
     jac = float(np.sum(np.log(diag)))

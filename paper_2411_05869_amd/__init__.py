@@ -18,6 +18,7 @@ from ._lib import (  # noqa: F401
     MIXED,
     LOGDET_EXACT,
     LOGDET_NONE,
+    LOGDET_SLQ_REORTH,
     LOGDET_SLQ,
     PRECOND_BLOCK_JACOBI,
     PRECOND_JACOBI,

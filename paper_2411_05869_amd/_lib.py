@@ -12,7 +12,7 @@ _LIB_PATH = os.path.join(_HERE, "libgpsparse.so")
 _lib = None
 
 FP64, MIXED = 0, 1
-LOGDET_SLQ, LOGDET_EXACT, LOGDET_NONE = 0, 1, 2
+LOGDET_SLQ, LOGDET_EXACT, LOGDET_NONE, LOGDET_SLQ_REORTH = 0, 1, 2, 3
 PRECOND_JACOBI, PRECOND_BLOCK_JACOBI = 0, 1
 SOLVER_CG, SOLVER_MINRES, SOLVER_AUTO = 0, 1, 2
 CORE_NONE, CORE_MATERN, CORE_PACIOREK = 0, 1, 2

@@ -185,7 +185,7 @@ gp_solve_opts fill_opts(const gp_solve_opts* o) {
   GPS_REQUIRE(r.max_iter >= 1, GP_EINVAL, "max_iter must be >= 1");
   GPS_REQUIRE(r.n_probes >= 2 && r.n_probes <= 64, GP_EINVAL, "n_probes must be in 2..64");
   GPS_REQUIRE(r.n_lanczos >= 1 && r.n_lanczos <= 128, GP_EINVAL, "n_lanczos must be in 1..128");
-  GPS_REQUIRE(r.logdet_mode >= 0 && r.logdet_mode <= 2, GP_EINVAL, "logdet_mode must be 0, 1 or 2");
+  GPS_REQUIRE(r.logdet_mode >= 0 && r.logdet_mode <= 3, GP_EINVAL, "logdet_mode must be 0, 1, 2 or 3");
   GPS_REQUIRE(r.precond == GP_PRECOND_JACOBI || r.precond == GP_PRECOND_BLOCK_JACOBI, GP_EINVAL,
               "precond must be GP_PRECOND_JACOBI or GP_PRECOND_BLOCK_JACOBI");
   GPS_REQUIRE(r.solver >= GP_SOLVER_CG && r.solver <= GP_SOLVER_AUTO, GP_EINVAL,
@@ -476,9 +476,10 @@ static gp_status loglik_common(gp_ctx* c, const gp_matrix* m, const double* y, c
     solve_status = sr.st;
     if (alpha) gps::permute_to_orig<double>(c, m->ds, 1, xb, alpha);
     if (with_logdet && o.logdet_mode != GP_LOGDET_NONE) {
-      const gps::LogdetResult lr = o.logdet_mode == GP_LOGDET_EXACT
-                                       ? gps::exact_logdet(c, m, o.seed)
-                                       : gps::slq_logdet(c, m, o.seed, o.n_probes, o.n_lanczos);
+      const gps::LogdetResult lr =
+          o.logdet_mode == GP_LOGDET_EXACT
+              ? gps::exact_logdet(c, m, o.seed)
+              : gps::slq_logdet(c, m, o.seed, o.n_probes, o.n_lanczos, o.logdet_mode == GP_LOGDET_SLQ_REORTH);
       out->logdet = lr.logdet;
       out->logdet_se = lr.se;
       out->lanczos_steps = lr.steps;

@@ -357,7 +357,9 @@ struct LogdetResult {
   int steps = 0;
   gp_status st = GP_OK;
 };
-LogdetResult slq_logdet(gp_ctx* c, const gp_matrix* m, uint64_t seed, int n_probes, int n_steps);
+// reorth: full re-orthogonalisation against every Lanczos block (work space
+// n_steps x n x 32 float64)
+LogdetResult slq_logdet(gp_ctx* c, const gp_matrix* m, uint64_t seed, int n_probes, int n_steps, bool reorth);
 LogdetResult exact_logdet(gp_ctx* c, const gp_matrix* m, uint64_t seed);
 
 // allocation-free one-column product (fixed per-device scratch array)

@@ -445,6 +445,74 @@ __global__ void __launch_bounds__(kThreads) k_lz_alpha_norm(int64_t n, int ld, c
 }
 
 
+// Full re-orthogonalisation (classical Gram-Schmidt, applied twice by the
+// driver) of the residual block W against the normalised Lanczos vectors
+// Q[0..nv) (each n x 32): H[i][l] = sum_p Q[i][p][l] W[p][l], then
+// W[:, l] -= sum_i H[i][l] Q[i][:, l].  Block (b, i) of k_ro_dot adds rows
+// b * 8 + r, stride 8 gridDim.x, for its eight row lanes r, then the lanes in
+// order; k_ro_fin adds the blocks of each vector in order.
+__global__ void __launch_bounds__(kThreads) k_lz_store_q(int64_t n, const double* __restrict__ V,
+                                                         const LzState* __restrict__ st, double* __restrict__ Qj) {
+  const int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x;
+  if (i < n * 32) Qj[i] = V[i] * st->inv_cur[i & 31];
+}
+
+__global__ void __launch_bounds__(kThreads) k_ro_dot(int64_t n, const double* __restrict__ Q,
+                                                     const double* __restrict__ W, double* __restrict__ part) {
+  const int l = threadIdx.x & 31;
+  const int rl = threadIdx.x >> 5;
+  const int64_t vi = blockIdx.y;
+  const double* q = Q + vi * n * 32;
+  double acc = 0;
+  for (int64_t p = blockIdx.x * 8ll + rl; p < n; p += static_cast<int64_t>(gridDim.x) * 8) acc += q[p * 32 + l] * W[p * 32 + l];
+  __shared__ double sh[8][32];
+  sh[rl][l] = acc;
+  __syncthreads();
+  if (rl == 0) {
+    double t = 0;
+    for (int j = 0; j < 8; ++j) t += sh[j][l];
+    part[(vi * gridDim.x + blockIdx.x) * 32 + l] = t;
+  }
+}
+
+__global__ void __launch_bounds__(32) k_ro_fin(const double* __restrict__ part, int nb, double* __restrict__ H) {
+  const int64_t vi = blockIdx.x;
+  const int l = threadIdx.x;
+  double t = 0;
+  for (int b = 0; b < nb; ++b) t += part[(vi * nb + b) * 32 + l];
+  H[vi * 32 + l] = t;
+}
+
+__global__ void __launch_bounds__(kThreads) k_ro_update(int64_t n, int nv, const double* __restrict__ Q,
+                                                        const double* __restrict__ H, double* __restrict__ W) {
+  const int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x;
+  if (i >= n * 32) return;
+  const int l = static_cast<int>(i & 31);
+  double w = W[i];
+  for (int v = 0; v < nv; ++v) w -= H[v * 32 + l] * Q[static_cast<int64_t>(v) * n * 32 + i];
+  W[i] = w;
+}
+
+// partial sums of |W[:, l]|^2 (after re-orthogonalisation)
+__global__ void __launch_bounds__(kThreads) k_lz_norm(int64_t n, const double* __restrict__ W,
+                                                      double* __restrict__ part) {
+  const int l = threadIdx.x & 31;
+  const int rl = threadIdx.x >> 5;
+  double acc = 0;
+  for (int64_t p = blockIdx.x * 8ll + rl; p < n; p += static_cast<int64_t>(gridDim.x) * 8) {
+    const double w = W[p * 32 + l];
+    acc += w * w;
+  }
+  __shared__ double sh[8][32];
+  sh[rl][l] = acc;
+  __syncthreads();
+  if (rl == 0) {
+    double t = 0;
+    for (int j = 0; j < 8; ++j) t += sh[j][l];
+    part[blockIdx.x * 32 + l] = t;
+  }
+}
+
 // mode 0: alpha; mode 1: beta + breakdown (j = step index, last = final step).
 // 32 columns; each of kFinGroups groups of 32 threads sums the partials b = g,
 // g + kFinGroups, ... of its column (four interleaved accumulators, so several
@@ -1009,9 +1077,15 @@ SolveResult minres_solve(gp_ctx* c, gp_matrix* m, const double* y, double* x, bo
 }
 
 template <typename T>
-static LogdetResult slq_impl(gp_ctx* c, const gp_matrix* m, uint64_t seed, int n_probes, int n_steps, double tol) {
+static LogdetResult slq_impl(gp_ctx* c, const gp_matrix* m, uint64_t seed, int n_probes, int n_steps, double tol,
+                             bool reorth) {
   const int64_t n = m->n;
   const int ld = 32;
+  // full re-orthogonalisation keeps every normalised Lanczos block
+  double* Qall = reorth ? static_cast<double*>(workspace(c, 57, sizeof(double) * n * ld * n_steps)) : nullptr;
+  constexpr int kRoBlocks = 256;
+  double* ropart = reorth ? static_cast<double*>(workspace(c, 58, sizeof(double) * 32 * kRoBlocks * n_steps)) : nullptr;
+  double* H = reorth ? static_cast<double*>(workspace(c, 59, sizeof(double) * 32 * n_steps)) : nullptr;
   T* V = static_cast<T*>(workspace(c, 30, sizeof(T) * n * ld));
   T* Vp = static_cast<T*>(workspace(c, 31, sizeof(T) * n * ld));
   T* W = static_cast<T*>(workspace(c, 32, sizeof(T) * n * ld));
@@ -1052,6 +1126,19 @@ static LogdetResult slq_impl(gp_ctx* c, const gp_matrix* m, uint64_t seed, int n
                          Ta, Tb);
       hipLaunchKernelGGL((k_lz_alpha_norm<T>), dim3(kRedBlocks), dim3(kThreads), 0, c->stream, n, ld, st, V, W,
                          part);
+      if (reorth) {
+        // W -= Q Q^T W twice over q_0 .. q_j, then |W|^2 afresh
+        double* Qj = Qall + static_cast<int64_t>(j) * n * ld;
+        hipLaunchKernelGGL(k_lz_store_q, dim3(grid_for(n * ld, kThreads)), dim3(kThreads), 0, c->stream, n, V, st, Qj);
+        for (int pass = 0; pass < 2; ++pass) {
+          hipLaunchKernelGGL(k_ro_dot, dim3(kRoBlocks, j + 1), dim3(kThreads), 0, c->stream, n, Qall, W, ropart);
+          hipLaunchKernelGGL(k_ro_fin, dim3(j + 1), dim3(32), 0, c->stream, ropart, kRoBlocks, H);
+          hipLaunchKernelGGL(k_ro_update, dim3(grid_for(n * ld, kThreads)), dim3(kThreads), 0, c->stream, n, j + 1,
+                             Qall, H, W);
+        }
+        hipLaunchKernelGGL(k_lz_norm, dim3(kRedBlocks), dim3(kThreads), 0, c->stream, n, W, part);
+        check_launch("lanczos reorthogonalisation");
+      }
       hipLaunchKernelGGL(k_lz_fin, dim3(1), dim3(kFinGroups * 32), 0, c->stream, part, kRedBlocks, k, 1, j, last, tol, st,
                          Ta, Tb);
       if (!last) {
@@ -1098,8 +1185,8 @@ static LogdetResult slq_impl(gp_ctx* c, const gp_matrix* m, uint64_t seed, int n
 // accumulating it in float32 perturbs each step by ~1e-7, which the
 // recurrence's loss of orthogonality amplifies to ~5e-5 in the quadrature at
 // 50 steps; float32 values alone move the estimate by ~5e-8.
-LogdetResult slq_logdet(gp_ctx* c, const gp_matrix* m, uint64_t seed, int n_probes, int n_steps) {
-  return slq_impl<double>(c, m, seed, n_probes, n_steps, 1e-10);
+LogdetResult slq_logdet(gp_ctx* c, const gp_matrix* m, uint64_t seed, int n_probes, int n_steps, bool reorth) {
+  return slq_impl<double>(c, m, seed, n_probes, n_steps, 1e-10, reorth);
 }
 
 // Exact log det: Lanczos on the Jacobi-scaled matrix to dimension n with full

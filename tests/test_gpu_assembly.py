@@ -103,8 +103,9 @@ def test_config1(ctx):
     run_case(ctx, config1(), 1, what="cfg1 mixed")
 
 
-def test_config2(ctx):
-    run_case(ctx, config2(), 0, what="cfg2 fp64")
+@pytest.mark.parametrize("prec", [0, 1])
+def test_config2(ctx, prec):
+    run_case(ctx, config2(), prec, what=f"cfg2 {'fp64' if prec == 0 else 'mixed'}")
 
 
 def test_binning_is_permutation_and_deterministic(ctx):

@@ -115,6 +115,38 @@ def test_slq_quadrature_exact_with_few_distinct_eigenvalues():
         assert abs(r["gammas"][l] - z @ logAh @ z) <= 1e-8 * abs(z @ logAh @ z) + 1e-9
 
 
+def test_slq_reorth_to_full_dimension_is_exact():
+    # Lanczos with full re-orthogonalisation run to the full dimension n spans
+    # the whole space, so its Gauss quadrature is z^T log(Ahat) z exactly; the
+    # spectrum spreads over four decades with many distinct eigenvalues, where
+    # the plain recurrence loses orthogonality long before n steps.
+    rng = np.random.default_rng(12)
+    n = 90
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    lam = np.logspace(-2, 2, n)
+    A = (Q * lam) @ Q.T
+    A = 0.5 * (A + A.T)
+    r = slq.slq_logdet(A, seed=3, n_probes=4, n_steps=n, reorth=True)
+    s = 1.0 / np.sqrt(np.diag(A))
+    Ah = s[:, None] * A * s[None, :]
+    w, V = np.linalg.eigh(Ah)
+    logAh = (V * np.log(w)) @ V.T
+    for l in range(4):
+        z = slq.rademacher(3, l, np.arange(n))
+        ref = z @ logAh @ z
+        assert abs(r["gammas"][l] - ref) <= 1e-9 * np.abs(z) @ np.abs(logAh) @ np.abs(z)
+
+
+def test_slq_reorth_matches_plain_while_orthogonality_holds():
+    # on a well-conditioned matrix and few steps the plain recurrence keeps its
+    # vectors orthogonal to rounding, and both forms give the same quadrature
+    p = config1()
+    K, _ = kernel.dense(p.x, p.theta)
+    a = slq.slq_logdet(K, seed=8, n_probes=3, n_steps=6)
+    b = slq.slq_logdet(K, seed=8, n_probes=3, n_steps=6, reorth=True)
+    assert np.allclose(a["gammas"], b["gammas"], rtol=1e-9, atol=0)
+
+
 def test_slq_within_three_se_of_exact_config1():
     p = config1()
     K, _ = kernel.dense(p.x, p.theta)
