@@ -187,11 +187,25 @@ def cpu_baseline(p):
     t1 = time.perf_counter()
     r = likelihood.sparse_lu(kernel.to_scipy(ip, ci, vo, x.shape[0]), y)
     t2 = time.perf_counter()
+    try:
+        from threadpoolctl import threadpool_info
+        blas = [dict(api=i.get("internal_api"), threads=i.get("num_threads")) for i in threadpool_info()]
+    except Exception:  # reported as unknown
+        blas = None
+    try:
+        with open(EXACT_LOGLIK) as f:
+            ex = json.load(f)
+        exact = dict(seconds=ex["seconds"], n=ex["n"], method=ex["method"],
+                     note="the oracle's exact log-likelihood of the whole workload (day-blocked split), "
+                          "timed once when tests/golden/make_spacetime_exact.py wrote it, on an 8-core host")
+    except (OSError, KeyError, ValueError):
+        exact = None
     return dict(value=1.0 / (t2 - t0), unit="loglik evals/s", cores=1, kind="oracle",
                 sample=f"same generator and theta restricted to stations in [0,0.5]^2 x days 0-72: n={x.shape[0]}, "
                        f"nnz={int(ip[-1])}; KD-tree pattern + float64 entries ({t1 - t0:.2f} s, "
                        f"{ip[-1] / (t1 - t0):.3g} nnz/s) then SuperLU exact log-likelihood ({t2 - t1:.2f} s); "
                        f"single-threaded (cKDTree, NumPy elementwise, SuperLU)",
+                host_cpus=os.cpu_count(), blas_threads=blas, full_workload_exact=exact,
                 nnz_per_s=float(ip[-1] / (t1 - t0)), n=int(x.shape[0]), loglik=r["loglik"]), (sel, ip[-1])
 
 

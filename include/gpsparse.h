@@ -350,6 +350,31 @@ typedef struct gp_loglik_result {
 GP_API gp_status gp_loglik(gp_ctx* ctx, const gp_matrix* m, const double* y_dev,
                     const gp_solve_opts* opts, double* alpha_dev, gp_loglik_result* out);
 
+/* gp_loglik_async: the log-likelihood of gp_loglik (Sec. 3.1 Eq. Zmarg; the
+ * log-det and solve tasks of Sec. 3.3), enqueued on the context's stream
+ * without waiting for it: every decision of the solver (convergence checks,
+ * the true-residual pass) is taken on the device, so nothing is read back to
+ * the host.  The conjugate gradients are enqueued in blocks of 8 iterations
+ * up to opts->max_iter; the iterations after convergence return at once
+ * (a few microseconds each), so set max_iter near the expected count, e.g.
+ * twice that of an earlier evaluation on the same data (GP_ENOTCONV in
+ * out->status when it is not enough).  The last kernel writes the result
+ * into *out, which must be pinned host memory (hipHostMalloc) or device
+ * memory; if event (a hipEvent_t, or NULL) is given it is recorded on the
+ * stream after that kernel: *out and alpha_dev are complete once the event
+ * has completed.  Errors found on the device (GP_ENOTCONV, GP_ENOTPD,
+ * non-finite y) are reported in out->status only.  Solver: conjugate
+ * gradients (GP_SOLVER_AUTO runs them without the MINRES fallback); logdet
+ * mode GP_LOGDET_SLQ, GP_LOGDET_SLQ_REORTH or GP_LOGDET_NONE.  The first
+ * likelihood of a matrix builds its product and preconditioner caches with
+ * host synchronisations, then enqueues the rest.  The context's work space
+ * is in use until the event completes: later calls on the same context and
+ * stream are ordered after it.
+ * Errors (returned): GP_EINVAL (arguments, solver, GP_LOGDET_EXACT, out not
+ * reachable by the device), GP_ENOMEM, GP_EDEVICE. */
+GP_API gp_status gp_loglik_async(gp_ctx* ctx, const gp_matrix* m, const double* y_dev, const gp_solve_opts* opts,
+                                 double* alpha_dev, gp_loglik_result* out, void* event);
+
 /* gp_solve: alpha = K^-1 y only (the quadratic-form task of Sec. 3.3). */
 GP_API gp_status gp_solve(gp_ctx* ctx, const gp_matrix* m, const double* y_dev,
                    const gp_solve_opts* opts, double* alpha_dev, gp_loglik_result* out);

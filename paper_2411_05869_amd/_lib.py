@@ -86,7 +86,7 @@ EXPORTS = [
     "gp_ctx_set_hbm_budget",
     "gp_dataset_create", "gp_dataset_destroy", "gp_dataset_info", "gp_dataset_permutation",
     "gp_assemble", "gp_matrix_destroy", "gp_matrix_info", "gp_matrix_export_csr", "gp_matvec",
-    "gp_matvec_noalloc", "gp_matrix_layout", "gp_predict_batch",
+    "gp_matvec_noalloc", "gp_matrix_layout", "gp_predict_batch", "gp_loglik_async",
     "gp_solve_opts_default", "gp_loglik", "gp_solve", "gp_predictor_create", "gp_predictor_destroy",
     "gp_predict", "gp_predict_var", "gp_mean_residual", "gp_profile_enable", "gp_profile_read",
 ]
@@ -129,6 +129,7 @@ def lib():
     L.gp_solve_opts_default.restype = None
     L.gp_loglik.argtypes = [P, P, P, C.POINTER(CSolveOpts), P, C.POINTER(CLoglikResult)]
     L.gp_solve.argtypes = [P, P, P, C.POINTER(CSolveOpts), P, C.POINTER(CLoglikResult)]
+    L.gp_loglik_async.argtypes = [P, P, P, C.POINTER(CSolveOpts), P, P, P]
     L.gp_predictor_create.argtypes = [P, P, C.POINTER(CTheta), P, C.POINTER(P)]
     L.gp_predictor_destroy.argtypes = [P, P]
     L.gp_predict.argtypes = [P, P, I64, P, C.c_int, P]
@@ -354,6 +355,26 @@ class Context:
             self._check(st, "gp_loglik")
         return res.as_dict()
 
+    def loglik_async(self, K: "Matrix", y, alpha_out=None, event=None, **opts):
+        """Enqueues gp_loglik_async and returns (pending, event): pending.result()
+        waits for the event and returns the result dict (status included).
+        ``event``: a torch.cuda.Event (created here if None), recorded by the
+        library after its last kernel."""
+        torch = _torch()
+        _check_dev_tensor(y, torch.float64, (K.n,), "y")
+        if alpha_out is not None:
+            _check_dev_tensor(alpha_out, torch.float64, (K.n,), "alpha_out")
+        o = self.opts(**opts)
+        buf = torch.zeros(C.sizeof(CLoglikResult), dtype=torch.uint8, pin_memory=True)
+        if event is None:
+            event = torch.cuda.Event()
+        event.record(self.stream)   # creates the HIP event the library records again
+        st = self._L.gp_loglik_async(self._h, K._h, C.c_void_p(_ptr(y)), C.byref(o),
+                                     C.c_void_p(_ptr(alpha_out)) if alpha_out is not None else None,
+                                     C.c_void_p(buf.data_ptr()), C.c_void_p(event.cuda_event))
+        self._check(st, "gp_loglik_async")
+        return _PendingLoglik(buf, event), event
+
     def solve(self, K: "Matrix", y, alpha_out, raise_on_error: bool = True, **opts) -> dict:
         torch = _torch()
         _check_dev_tensor(y, torch.float64, (K.n,), "y")
@@ -480,6 +501,21 @@ class Context:
         if st != 0 and raise_on_error:
             self._check(st, "gp_predict_var")
         return out, res.as_dict()
+
+
+class _PendingLoglik:
+    """The result of gp_loglik_async: valid once its event has completed."""
+
+    def __init__(self, buf, event):
+        self.buf = buf      # pinned memory the device writes the result into
+        self.event = event
+
+    def done(self) -> bool:
+        return self.event.query()
+
+    def result(self) -> dict:
+        self.event.synchronize()
+        return CLoglikResult.from_address(self.buf.data_ptr()).as_dict()
 
 
 class _Obj:

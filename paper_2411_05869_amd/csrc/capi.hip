@@ -500,6 +500,72 @@ static gp_status loglik_common(gp_ctx* c, const gp_matrix* m, const double* y, c
   return solve_status;
 }
 
+namespace {
+
+// The result of the device-driven likelihood, written by the device into the
+// caller's (pinned or device) memory: -1/2 logdet - 1/2 quad - (n/2) log 2 pi.
+__global__ void k_loglik_result(gps::DeviceSolve sv, const gps::DeviceLogdet* __restrict__ ld, int with_logdet,
+                                double half_n_log2pi, gp_loglik_result* __restrict__ out) {
+#pragma clang fp contract(off)
+  gp_loglik_result r{};
+  r.quad = *sv.quad;
+  r.relres = *sv.relres;
+  r.cg_iters = *sv.iters;
+  r.refreshes = *sv.refreshes;
+  int st = *sv.status;
+  if (with_logdet) {
+    r.logdet = ld->logdet;
+    r.logdet_se = ld->se;
+    r.lanczos_steps = ld->steps;
+    if (st == GP_OK) st = ld->status;
+  }
+  r.loglik = -0.5 * r.logdet - 0.5 * r.quad - half_n_log2pi;
+  r.status = st;
+  *out = r;
+}
+
+}  // namespace
+
+gp_status gp_loglik_async(gp_ctx* c, const gp_matrix* m, const double* y, const gp_solve_opts* opts, double* alpha,
+                          gp_loglik_result* out, void* event) {
+  if (!c || !m || !y || !out) return GP_EINVAL;
+  return guarded(c, [&] {
+    const gp_solve_opts o = fill_opts(opts);
+    GPS_REQUIRE(o.solver == GP_SOLVER_CG || o.solver == GP_SOLVER_AUTO, GP_EINVAL,
+                "gp_loglik_async: the solver must be GP_SOLVER_CG (or AUTO, run as CG)");
+    GPS_REQUIRE(o.logdet_mode != GP_LOGDET_EXACT, GP_EINVAL, "gp_loglik_async: GP_LOGDET_EXACT is not available");
+    // the result is written by a kernel: it must be memory the device can reach
+    hipPointerAttribute_t attr{};
+    const hipError_t pe = hipPointerGetAttributes(&attr, out);
+    (void)hipGetLastError();
+    GPS_REQUIRE(pe == hipSuccess && (attr.type == hipMemoryTypeHost || attr.type == hipMemoryTypeDevice ||
+                                     attr.type == hipMemoryTypeManaged),
+                GP_EINVAL, "gp_loglik_async: out must be pinned host memory (or device memory)");
+    const int64_t n = m->n;
+    gp_matrix* mm = const_cast<gp_matrix*>(m);
+    // caches of the products and the preconditioner (built with host
+    // synchronisations the first time a matrix is used, not again)
+    gps::build_product_caches(c, mm);
+    if (o.precond == GP_PRECOND_BLOCK_JACOBI) gps::build_block_jacobi(c, mm);
+    double* yb = static_cast<double*>(gps::workspace(c, 44, sizeof(double) * n));
+    double* xb = static_cast<double*>(gps::workspace(c, 45, sizeof(double) * n));
+    gps::permute_to_binned<double>(c, m->ds, 1, y, yb);
+    gps::DeviceSolve sv{};
+    gps::pcg_solve_device(c, mm, yb, xb, o.rtol, o.max_iter, o.precond, &sv);
+    if (alpha) gps::permute_to_orig<double>(c, m->ds, 1, xb, alpha);
+    const bool with_logdet = o.logdet_mode != GP_LOGDET_NONE;
+    gps::DeviceLogdet* ld = static_cast<gps::DeviceLogdet*>(gps::workspace(c, 124, sizeof(gps::DeviceLogdet)));
+    if (with_logdet)
+      gps::slq_logdet_device(c, m, o.seed, o.n_probes, o.n_lanczos, o.logdet_mode == GP_LOGDET_SLQ_REORTH, ld);
+    // (n/2) log(2 pi) formed on the host as gp_loglik forms it
+    const double half_n_log2pi = 0.5 * static_cast<double>(n) * std::log(2.0 * M_PI);
+    hipLaunchKernelGGL(k_loglik_result, dim3(1), dim3(1), 0, c->stream, sv, ld, with_logdet ? 1 : 0, half_n_log2pi,
+                       out);
+    gps::check_launch("loglik result");
+    if (event) GPS_HIP(hipEventRecord(static_cast<hipEvent_t>(event), c->stream));
+  });
+}
+
 gp_status gp_loglik(gp_ctx* c, const gp_matrix* m, const double* y, const gp_solve_opts* opts, double* alpha,
                     gp_loglik_result* out) {
   return loglik_common(c, m, y, opts, alpha, out, true);

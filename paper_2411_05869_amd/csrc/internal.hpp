@@ -301,7 +301,12 @@ void export_csr(gp_ctx* c, const gp_matrix* m, int64_t* row_ptr, int32_t* col, d
 
 // SpMV / SpMM in binned order.
 // y = K x (float64 x and y; float32 or float64 values; float64 accumulation)
-void spmv_f64(gp_ctx* c, const gp_matrix* m, const double* x, double* y);
+// skip (device int or null): when it holds a nonzero value at run time the
+// product's kernels return at once (device-side control of the solvers)
+void spmv_f64(gp_ctx* c, const gp_matrix* m, const double* x, double* y, const int* skip = nullptr);
+// builds the caches the products read (int16 offsets, row quads) now, with
+// host synchronisations, so that later products need none
+void build_product_caches(gp_ctx* c, gp_matrix* m);
 // the same product using only the caches already built (no allocation, no
 // synchronisation, no profiling events)
 void spmv_f64_enqueue(gp_ctx* c, const gp_matrix* m, const double* x, double* y);
@@ -366,6 +371,27 @@ LogdetResult exact_logdet(gp_ctx* c, const gp_matrix* m, uint64_t seed);
 void noalloc_init(int device);   // once per device, with the device current
 size_t noalloc_scratch_bytes();
 void matvec_noalloc(gp_ctx* c, const gp_matrix* m, const double* x, double* y);
+
+// Device-driven forms (no host read before the end; used by gp_loglik_async).
+// pcg_solve_device enqueues the conjugate gradients up to max_iter with
+// every decision taken on the device; its results stay in device memory, at
+// the addresses it returns.  The matrix's caches must be built already.
+struct DeviceSolve {
+  const double* quad;
+  const int* iters;
+  const int* refreshes;
+  const int* status;
+  const double* relres;
+};
+void pcg_solve_device(gp_ctx* c, gp_matrix* m, const double* yb, double* xb, double rtol, int max_iter, int precond,
+                      DeviceSolve* out);
+struct DeviceLogdet {
+  double logdet, se;
+  int steps, status;
+};
+// writes the SLQ estimate into out (device memory)
+void slq_logdet_device(gp_ctx* c, const gp_matrix* m, uint64_t seed, int n_probes, int n_steps, bool reorth,
+                       DeviceLogdet* out);
 
 // deterministic reductions
 double dot_f64(gp_ctx* c, const double* a, const double* b, int64_t n);   // synchronising

@@ -90,7 +90,8 @@ __global__ void __launch_bounds__(kThreads) k_pcg_step(int64_t n, Precond M, CgS
                                                        const double* __restrict__ p, const QT* __restrict__ q,
                                                        double* __restrict__ x, const double* __restrict__ r,
                                                        double* __restrict__ rn, double* __restrict__ z,
-                                                       double* __restrict__ part) {
+                                                       double* __restrict__ part, const int* __restrict__ skip) {
+  if (skip && *skip) return;
   // Everything a row reads is independent of alpha, so the row's vectors, its
   // block (row -> block -> start and offset) and the block's first kPreEntries
   // weights and r, q values are requested before the kRedBlocks partials of
@@ -175,7 +176,9 @@ __global__ void __launch_bounds__(kThreads) k_pcg_step(int64_t n, Precond M, CgS
 // 0 records rz, rr, beta and flags non-finite values.
 __global__ void __launch_bounds__(kThreads) k_pcg_direction(int64_t n, CgScalars* __restrict__ s,
                                                             const double* __restrict__ part, int nb,
-                                                            const double* __restrict__ z, double* __restrict__ p) {
+                                                            const double* __restrict__ z, double* __restrict__ p,
+                                                            const int* __restrict__ skip) {
+  if (skip && *skip) return;
   // the first batch of z and p is requested before the partial sums are
   // reduced, and each later batch before the previous one is stored
   const int64_t stride = static_cast<int64_t>(gridDim.x) * kThreads;
@@ -236,7 +239,9 @@ __global__ void __launch_bounds__(kThreads) k_yy_fin(const double* __restrict__ 
 // z = M^-1 r, one thread per row (full grid: the block products are short,
 // dependent gathers); per-block partial sums of r.z and r.r
 __global__ void __launch_bounds__(kThreads) k_precond(int64_t n, Precond M, const double* __restrict__ r,
-                                                      double* __restrict__ z, double* __restrict__ part) {
+                                                      double* __restrict__ z, double* __restrict__ part,
+                                                      const int* __restrict__ skip = nullptr) {
+  if (skip && *skip) return;
   double v[2] = {0, 0};
   const int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x;
   if (i < n) {
@@ -252,7 +257,9 @@ __global__ void __launch_bounds__(kThreads) k_precond(int64_t n, Precond M, cons
 // per-block partials of p.q (kRedBlocks blocks, grid-stride)
 template <typename QT>
 __global__ void __launch_bounds__(kThreads) k_pq_part(int64_t n, const double* __restrict__ p,
-                                                      const QT* __restrict__ q, double* __restrict__ part) {
+                                                      const QT* __restrict__ q, double* __restrict__ part,
+                                                      const int* __restrict__ skip) {
+  if (skip && *skip) return;
   // four strided elements loaded at once, then added in the order of a plain
   // grid-stride loop (the sum does not depend on the unrolling)
   double v[1] = {0};
@@ -278,7 +285,9 @@ __global__ void __launch_bounds__(kThreads) k_pq_part(int64_t n, const double* _
 // mode 1: residual replacement (rz_old kept)
 // mode 2: start (rz <- r.z, no beta)
 __global__ void __launch_bounds__(kThreads) k_beta_fin(const double* __restrict__ part, int nb,
-                                                       CgScalars* __restrict__ s, int mode) {
+                                                       CgScalars* __restrict__ s, int mode,
+                                                       const int* __restrict__ skip = nullptr) {
+  if (skip && *skip) return;
   double r[2];
   reduce_partials<2>(part, nb, r);
   if (threadIdx.x == 0) {
@@ -292,7 +301,9 @@ __global__ void __launch_bounds__(kThreads) k_beta_fin(const double* __restrict_
 
 // p = z + beta p (beta = 0 at the start)
 __global__ void __launch_bounds__(kThreads) k_pcg_pupdate(int64_t n, const CgScalars* __restrict__ s,
-                                                          const double* __restrict__ z, double* __restrict__ p) {
+                                                          const double* __restrict__ z, double* __restrict__ p,
+                                                          const int* __restrict__ skip = nullptr) {
+  if (skip && *skip) return;
   const double beta = s->beta;
   for (int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; i < n;
        i += static_cast<int64_t>(gridDim.x) * kThreads)
@@ -301,7 +312,9 @@ __global__ void __launch_bounds__(kThreads) k_pcg_pupdate(int64_t n, const CgSca
 
 // r = y - Kx (Kx given)
 __global__ void __launch_bounds__(kThreads) k_true_resid(int64_t n, const double* __restrict__ y,
-                                                         const double* __restrict__ kx, double* __restrict__ r) {
+                                                         const double* __restrict__ kx, double* __restrict__ r,
+                                                         const int* __restrict__ skip = nullptr) {
+  if (skip && *skip) return;
   for (int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; i < n;
        i += static_cast<int64_t>(gridDim.x) * kThreads)
     r[i] = y[i] - kx[i];
@@ -790,12 +803,12 @@ SolveResult pcg_solve(gp_ctx* c, gp_matrix* m, const double* y, double* x, doubl
       spmv_f64(c, m, p, q);
       {
         ProfScope ps(c, "pcg_vector_ops");
-        hipLaunchKernelGGL((k_pq_part<double>), G, B, 0, c->stream, n, p, q, pqp);
+        hipLaunchKernelGGL((k_pq_part<double>), G, B, 0, c->stream, n, p, q, pqp, nullptr);
         hipLaunchKernelGGL((k_pcg_step<double>), dim3(nbs), B, 0, c->stream, n, M, s, pqp, p, q, x, rc, rnx, z,
-                           spart);
+                           spart, nullptr);
         std::swap(rc, rnx);
         if (t + 1 < steps)
-          hipLaunchKernelGGL(k_pcg_direction, G, B, 0, c->stream, n, s, spart, static_cast<int>(nbs), z, p);
+          hipLaunchKernelGGL(k_pcg_direction, G, B, 0, c->stream, n, s, spart, static_cast<int>(nbs), z, p, nullptr);
         else
           hipLaunchKernelGGL(k_beta_fin, dim3(1), B, 0, c->stream, spart, static_cast<int>(nbs), s, 3);
       }
@@ -830,6 +843,156 @@ SolveResult pcg_solve(gp_ctx* c, gp_matrix* m, const double* y, double* x, doubl
   res.relres = last_true / ynorm;
   res.quad = dot_f64(c, y, x, n);
   return res;
+}
+
+namespace {
+
+// ------------------------------------------------ device-driven conjugate gradients
+// The iterations of pcg_solve with every decision taken on the device: the
+// host enqueues blocks of kCheckEvery iterations up to max_iter; after each
+// block a one-thread kernel compares the recursive residual with the target
+// and, at apparent convergence, lets the true-residual pass run; every kernel
+// of the iterations returns at once once the solve has ended (skip flags).
+struct CgCtl {
+  int skip_iter;    // nonzero: the iterations are over (converged or failed)
+  int skip_true;    // nonzero: no true-residual pass after this block
+  int skip_final;   // nonzero: no final true residual (converged, or y = 0)
+  int iters, refreshes, status;
+  double target;    // rtol |y|_2 (compared with |r|_2 as the host form does)
+  double relres;
+};
+
+__global__ void k_ctl_init(const CgScalars* __restrict__ s, CgCtl* __restrict__ ctl, double rtol) {
+  const double yy = s->yy;
+  ctl->iters = 0;
+  ctl->refreshes = 0;
+  ctl->skip_true = 1;
+  ctl->relres = 0.0;
+  ctl->target = rtol * sqrt(yy);
+  if (!isfinite(yy)) {
+    ctl->status = GP_EINVAL;
+    ctl->skip_iter = ctl->skip_final = 1;
+  } else if (yy == 0.0) {
+    ctl->status = GP_OK;  // x = 0 is exact
+    ctl->skip_iter = ctl->skip_final = 1;
+  } else {
+    ctl->status = GP_OK;
+    ctl->skip_iter = ctl->skip_final = 0;
+  }
+}
+
+__global__ void k_ctl_check(const CgScalars* __restrict__ s, CgCtl* __restrict__ ctl, int steps) {
+  if (ctl->skip_iter) return;
+  ctl->iters += steps;
+  if (s->status != 0) {
+    ctl->status = GP_ENOTPD;
+    ctl->skip_iter = 1;
+    return;
+  }
+  ctl->skip_true = sqrt(s->rr) <= ctl->target ? 0 : 1;
+}
+
+__global__ void k_ctl_after_true(const CgScalars* __restrict__ s, CgCtl* __restrict__ ctl) {
+  if (ctl->skip_true) return;
+  ctl->skip_true = 1;
+  ctl->refreshes += 1;
+  if (sqrt(s->rr) <= ctl->target) {
+    ctl->skip_iter = 1;
+    ctl->skip_final = 1;
+    ctl->relres = sqrt(s->rr) / sqrt(s->yy);
+  }
+}
+
+__global__ void k_ctl_end(const CgScalars* __restrict__ s, CgCtl* __restrict__ ctl) {
+  if (!ctl->skip_iter) {
+    ctl->status = GP_ENOTCONV;
+    ctl->skip_iter = 1;
+  }
+}
+
+__global__ void k_ctl_relres(const CgScalars* __restrict__ s, CgCtl* __restrict__ ctl) {
+  if (!ctl->skip_final) {
+    ctl->relres = sqrt(s->rr) / sqrt(s->yy);
+    if (ctl->status == GP_ENOTCONV && sqrt(s->rr) <= ctl->target) ctl->status = GP_OK;
+  }
+}
+
+}  // namespace
+
+void pcg_solve_device(gp_ctx* c, gp_matrix* m, const double* y, double* x, double rtol, int max_iter, int precond,
+                      DeviceSolve* out) {
+  const int64_t n = m->n;
+  Precond M{m->diag, nullptr, nullptr, nullptr, nullptr};
+  if (precond == GP_PRECOND_BLOCK_JACOBI) {
+    M.rowblk = m->rowblk;
+    M.bstart = m->bstart;
+    M.boff = m->boff;
+    M.binv = m->binv;
+  }
+  double* rc = static_cast<double*>(workspace(c, 20, sizeof(double) * n));
+  double* rnx = static_cast<double*>(workspace(c, 29, sizeof(double) * n));
+  double* z = static_cast<double*>(workspace(c, 21, sizeof(double) * n));
+  double* p = static_cast<double*>(workspace(c, 22, sizeof(double) * n));
+  double* q = static_cast<double*>(workspace(c, 23, sizeof(double) * n));
+  double* part = static_cast<double*>(workspace(c, 26, sizeof(double) * 4 * kRedBlocks));
+  const unsigned nbp = grid_for(n, kThreads);
+  const unsigned nbs = grid_for(n, kThreads * kStepRows);
+  double* ppart = static_cast<double*>(workspace(c, 28, sizeof(double) * 2 * nbp));
+  CgScalars* s = static_cast<CgScalars*>(workspace(c, 27, sizeof(CgScalars)));
+  CgCtl* ctl = static_cast<CgCtl*>(workspace(c, 24, sizeof(CgCtl)));
+  const int* skip_iter = &ctl->skip_iter;
+  const int* skip_true = &ctl->skip_true;
+  const int* skip_final = &ctl->skip_final;
+  const dim3 G(kRedBlocks), B(kThreads);
+  auto true_residual = [&](const int* gate) {
+    spmv_f64(c, m, x, q, gate);
+    hipLaunchKernelGGL(k_true_resid, G, B, 0, c->stream, n, y, q, rc, gate);
+    hipLaunchKernelGGL(k_precond, dim3(nbp), B, 0, c->stream, n, M, rc, z, ppart, gate);
+    hipLaunchKernelGGL(k_beta_fin, dim3(1), B, 0, c->stream, ppart, static_cast<int>(nbp), s, 1, gate);
+  };
+  hipLaunchKernelGGL(k_pcg_init, G, B, 0, c->stream, n, y, x, rc, part);
+  hipLaunchKernelGGL(k_yy_fin, dim3(1), B, 0, c->stream, part, kRedBlocks, s);
+  hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(1), 0, c->stream, s, ctl, rtol);
+  hipLaunchKernelGGL(k_precond, dim3(nbp), B, 0, c->stream, n, M, rc, z, ppart, skip_iter);
+  hipLaunchKernelGGL(k_beta_fin, dim3(1), B, 0, c->stream, ppart, static_cast<int>(nbp), s, 2, skip_iter);
+  hipLaunchKernelGGL(k_pcg_pupdate, G, B, 0, c->stream, n, s, z, p, skip_iter);
+  check_launch("pcg init");
+  double* pqp = part;
+  double* spart = ppart;
+  for (int it = 0; it < max_iter; it += kCheckEvery) {
+    const int steps = std::min(kCheckEvery, max_iter - it);
+    for (int t = 0; t < steps; ++t) {
+      spmv_f64(c, m, p, q, skip_iter);
+      ProfScope ps(c, "pcg_vector_ops");
+      hipLaunchKernelGGL((k_pq_part<double>), G, B, 0, c->stream, n, p, q, pqp, skip_iter);
+      hipLaunchKernelGGL((k_pcg_step<double>), dim3(nbs), B, 0, c->stream, n, M, s, pqp, p, q, x, rc, rnx, z,
+                         spart, skip_iter);
+      std::swap(rc, rnx);
+      if (t + 1 < steps)
+        hipLaunchKernelGGL(k_pcg_direction, G, B, 0, c->stream, n, s, spart, static_cast<int>(nbs), z, p, skip_iter);
+      else
+        hipLaunchKernelGGL(k_beta_fin, dim3(1), B, 0, c->stream, spart, static_cast<int>(nbs), s, 3, skip_iter);
+    }
+    hipLaunchKernelGGL(k_ctl_check, dim3(1), dim3(1), 0, c->stream, s, ctl, steps);
+    true_residual(skip_true);
+    hipLaunchKernelGGL(k_ctl_after_true, dim3(1), dim3(1), 0, c->stream, s, ctl);
+    hipLaunchKernelGGL(k_pcg_pupdate, G, B, 0, c->stream, n, s, z, p, skip_iter);
+    check_launch("pcg iteration block");
+  }
+  hipLaunchKernelGGL(k_ctl_end, dim3(1), dim3(1), 0, c->stream, s, ctl);
+  true_residual(skip_final);
+  hipLaunchKernelGGL(k_ctl_relres, dim3(1), dim3(1), 0, c->stream, s, ctl);
+  // quad = y . x
+  double* qd = static_cast<double*>(workspace(c, 25, sizeof(double) * 2));
+  double* dpart = static_cast<double*>(workspace(c, 40, sizeof(double) * kRedBlocks));
+  hipLaunchKernelGGL(k_dot_part, G, B, 0, c->stream, n, y, x, dpart);
+  hipLaunchKernelGGL(k_sum_part, dim3(1), B, 0, c->stream, dpart, kRedBlocks, qd);
+  check_launch("pcg end");
+  out->quad = qd;
+  out->iters = &ctl->iters;
+  out->refreshes = &ctl->refreshes;
+  out->status = &ctl->status;
+  out->relres = &ctl->relres;
 }
 
 namespace {
@@ -1076,9 +1239,53 @@ SolveResult minres_solve(gp_ctx* c, gp_matrix* m, const double* y, double* x, bo
   return res;
 }
 
+namespace {
+
+// device-driven SLQ pieces: the Lanczos state of a batch of probes, the
+// per-probe quadratures collected across batches, and the estimate
+__global__ void k_lz_state_init(LzState* __restrict__ st, int k, double inv0) {
+  const int l = threadIdx.x;
+  if (l >= 32) return;
+  st->alpha[l] = st->beta[l] = st->beta_prev[l] = st->inv_prev[l] = 0.0;
+  st->active[l] = l < k ? 1 : 0;
+  st->inv_cur[l] = l < k ? inv0 : 0.0;
+  st->steps[l] = 0;
+}
+
+__global__ void k_slq_collect(const LzState* __restrict__ st, const double* __restrict__ gam, int k, int p0,
+                              double* __restrict__ gam_all, int* __restrict__ steps_all) {
+  const int l = threadIdx.x;
+  if (l < k) {
+    gam_all[p0 + l] = gam[l];
+    steps_all[p0 + l] = st->steps[l];
+  }
+}
+
+// mean and standard error over the probes, in the host form's order and without
+// fused multiply-adds, so the figures equal the synchronous path's bitwise
+__global__ void k_slq_final(const double* __restrict__ gam_all, const int* __restrict__ steps_all, int np,
+                            const double* __restrict__ jac, const int* __restrict__ bad, DeviceLogdet* __restrict__ out) {
+#pragma clang fp contract(off)
+  double mean = 0;
+  int ms = 0;
+  for (int i = 0; i < np; ++i) {
+    mean += gam_all[i];
+    ms = max(ms, steps_all[i]);
+  }
+  mean /= static_cast<double>(np);
+  double var = 0;
+  for (int i = 0; i < np; ++i) var += (gam_all[i] - mean) * (gam_all[i] - mean);
+  out->se = np > 1 ? sqrt(var / static_cast<double>(np - 1) / np) : 0.0;
+  out->logdet = jac[0] + mean;
+  out->steps = ms;
+  out->status = (bad[0] & 1) ? GP_EDEVICE : ((bad[0] & 2) ? GP_ENOTPD : GP_OK);
+}
+
+}  // namespace
+
 template <typename T>
 static LogdetResult slq_impl(gp_ctx* c, const gp_matrix* m, uint64_t seed, int n_probes, int n_steps, double tol,
-                             bool reorth) {
+                             bool reorth, DeviceLogdet* dev_out = nullptr) {
   const int64_t n = m->n;
   const int ld = 32;
   // full re-orthogonalisation keeps every normalised Lanczos block
@@ -1098,21 +1305,44 @@ static LogdetResult slq_impl(gp_ctx* c, const gp_matrix* m, uint64_t seed, int n
   int* bad = static_cast<int*>(workspace(c, 39, sizeof(int) * 2));
   hipLaunchKernelGGL((k_scale_vec<T>), dim3(grid_for(n, kThreads)), dim3(kThreads), 0, c->stream, n, m->diag, sc);
   check_launch("slq scale");
-  const double jac = logsum_f64(c, m->diag, n);
+  const bool dev = dev_out != nullptr;
+  double jac = 0.0;
+  double* djac = nullptr;
+  double* gam_all = nullptr;
+  int* steps_all = nullptr;
+  int* bad_all = nullptr;
+  if (dev) {
+    // Jacobi part, probe results and failure flags stay on the device
+    djac = static_cast<double*>(workspace(c, 46, sizeof(double) * 2));
+    double* jpart = static_cast<double*>(workspace(c, 47, sizeof(double) * kRedBlocks));
+    hipLaunchKernelGGL(k_logsum_part, dim3(kRedBlocks), dim3(kThreads), 0, c->stream, n, m->diag, jpart);
+    hipLaunchKernelGGL(k_sum_part, dim3(1), dim3(kThreads), 0, c->stream, jpart, kRedBlocks, djac);
+    gam_all = static_cast<double*>(workspace(c, 48, sizeof(double) * 64));
+    steps_all = static_cast<int*>(workspace(c, 49, sizeof(int) * 64));
+    bad_all = bad;
+    GPS_HIP(hipMemsetAsync(bad_all, 0, sizeof(int), c->stream));
+  } else {
+    jac = logsum_f64(c, m->diag, n);
+  }
   std::vector<double> gammas;
   int max_steps = 0;
   int nbad = 0;
   for (int p0 = 0; p0 < n_probes; p0 += 32) {
     const int k = std::min(32, n_probes - p0);
-    LzState init{};
-    for (int l = 0; l < 32; ++l) {
-      init.active[l] = l < k ? 1 : 0;
-      init.inv_cur[l] = l < k ? 1.0 / std::sqrt(static_cast<double>(n)) : 0.0;  // v_1 = +-1 / sqrt(n)
+    const double inv0 = 1.0 / std::sqrt(static_cast<double>(n));  // v_1 = +-1 / sqrt(n)
+    if (dev) {
+      hipLaunchKernelGGL(k_lz_state_init, dim3(1), dim3(32), 0, c->stream, st, k, inv0);
+    } else {
+      LzState init{};
+      for (int l = 0; l < 32; ++l) {
+        init.active[l] = l < k ? 1 : 0;
+        init.inv_cur[l] = l < k ? inv0 : 0.0;
+      }
+      LzState* hst = static_cast<LzState*>(pinned_for_write(c, sizeof(LzState)));
+      *hst = init;
+      h2d_async(c, st, hst, sizeof(LzState));
+      GPS_HIP(hipMemsetAsync(bad, 0, sizeof(int), c->stream));
     }
-    LzState* hst = static_cast<LzState*>(pinned_for_write(c, sizeof(LzState)));
-    *hst = init;
-    h2d_async(c, st, hst, sizeof(LzState));
-    GPS_HIP(hipMemsetAsync(bad, 0, sizeof(int), c->stream));
     hipLaunchKernelGGL((k_lz_init<T>), dim3(grid_for(n * ld, kThreads)), dim3(kThreads), 0, c->stream, n, k, ld, p0,
                        seed, m->ds->perm, V, Vp);
     check_launch("lanczos init");
@@ -1153,6 +1383,11 @@ static LogdetResult slq_impl(gp_ctx* c, const gp_matrix* m, uint64_t seed, int n
     hipLaunchKernelGGL(k_quadrature, dim3((k + kQuadProbes - 1) / kQuadProbes), dim3(kQuadProbes), 0, c->stream, k, Ta, Tb, st, static_cast<double>(n), gam,
                        bad);
     check_launch("quadrature");
+    if (dev) {
+      hipLaunchKernelGGL(k_slq_collect, dim3(1), dim3(32), 0, c->stream, st, gam, k, p0, gam_all, steps_all);
+      check_launch("slq collect");
+      continue;
+    }
     double* hg = static_cast<double*>(pinned(c, sizeof(double) * 32 + sizeof(LzState) + 16));
     GPS_HIP(hipMemcpyAsync(hg, gam, sizeof(double) * 32, hipMemcpyDeviceToHost, c->stream));
     LzState* hs2 = reinterpret_cast<LzState*>(hg + 32);
@@ -1167,6 +1402,12 @@ static LogdetResult slq_impl(gp_ctx* c, const gp_matrix* m, uint64_t seed, int n
     nbad |= *hb;
   }
   LogdetResult res;
+  if (dev) {
+    hipLaunchKernelGGL(k_slq_final, dim3(1), dim3(1), 0, c->stream, gam_all, steps_all, n_probes, djac, bad_all,
+                       dev_out);
+    check_launch("slq final");
+    return res;
+  }
   double mean = 0;
   for (double g : gammas) mean += g;
   mean /= static_cast<double>(gammas.size());
@@ -1187,6 +1428,11 @@ static LogdetResult slq_impl(gp_ctx* c, const gp_matrix* m, uint64_t seed, int n
 // 50 steps; float32 values alone move the estimate by ~5e-8.
 LogdetResult slq_logdet(gp_ctx* c, const gp_matrix* m, uint64_t seed, int n_probes, int n_steps, bool reorth) {
   return slq_impl<double>(c, m, seed, n_probes, n_steps, 1e-10, reorth);
+}
+
+void slq_logdet_device(gp_ctx* c, const gp_matrix* m, uint64_t seed, int n_probes, int n_steps, bool reorth,
+                       DeviceLogdet* out) {
+  slq_impl<double>(c, m, seed, n_probes, n_steps, 1e-10, reorth, out);
 }
 
 // Exact log det: Lanczos on the Jacobi-scaled matrix to dimension n with full

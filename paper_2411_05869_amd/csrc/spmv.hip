@@ -84,7 +84,8 @@ __global__ void __launch_bounds__(kThreads) k_spmv(int64_t n, unsigned nb_long, 
                                                    const int32_t* __restrict__ gskip,
                                                    const int32_t* __restrict__ col, const VT* __restrict__ val,
                                                    const XT* __restrict__ x, YT* __restrict__ y,
-                                                   const int16_t* __restrict__ off16) {
+                                                   const int16_t* __restrict__ off16, const int* __restrict__ skip) {
+  if (skip && *skip) return;  // a device-side decision cancelled this product
   if (blockIdx.x >= nb_long) {
     const unsigned b = xcd_remap(blockIdx.x - nb_long, gridDim.x - nb_long);
     const int64_t row = (b * static_cast<int64_t>(kThreads) + threadIdx.x) / kG;
@@ -392,7 +393,9 @@ __global__ void __launch_bounds__(kThreads) k_group_spmv(const int32_t* __restri
                                                          const int64_t* __restrict__ uoff,
                                                          const int32_t* __restrict__ ulist,
                                                          const int64_t* __restrict__ rp, const VT* __restrict__ val,
-                                                         const XT* __restrict__ x, YT* __restrict__ y) {
+                                                         const XT* __restrict__ x, YT* __restrict__ y,
+                                                         const int* __restrict__ skip) {
+  if (skip && *skip) return;  // uniform over the launch
   __shared__ AT xs[kGChunk];
   constexpr int kRows = kTileRows / (kThreads / kWave);
   // tiles come largest first; block b runs on XCD b % 8, so every XCD gets an
@@ -491,7 +494,7 @@ __global__ void __launch_bounds__(kThreads) k_col16(int64_t n, const int64_t* __
 }
 
 template <typename VT, typename XT, typename AT, typename YT>
-void spmv_launch(gp_ctx* c, const gp_matrix* m, const XT* x, YT* y) {
+void spmv_launch(gp_ctx* c, const gp_matrix* m, const XT* x, YT* y, const int* skip = nullptr) {
   const VT* val = static_cast<const VT*>(m->val);
   // long-row blocks padded to a multiple of the XCD count so that both block
   // ranges start on XCD 0 (see xcd_remap)
@@ -499,16 +502,16 @@ void spmv_launch(gp_ctx* c, const gp_matrix* m, const XT* x, YT* y) {
   const unsigned nb_long = m->n_long > 0 ? round_up8(grid_for(m->n_long * kWave, kThreads)) : 0;
   if (m->ntiles > 0)
     hipLaunchKernelGGL((k_group_spmv<VT, XT, AT, YT>), dim3(static_cast<unsigned>(m->ntiles)), dim3(kThreads), 0,
-                       c->stream, m->g_tiles, m->g_rows, m->g_uoff, m->g_ulist, m->row_ptr, val, x, y);
+                       c->stream, m->g_tiles, m->g_rows, m->g_uoff, m->g_ulist, m->row_ptr, val, x, y, skip);
   hipLaunchKernelGGL((k_spmv<VT, XT, AT, YT>), dim3(nb_short + nb_long), dim3(kThreads), 0, c->stream, m->n,
-                     nb_long, m->n_long, m->long_rows, m->row_ptr, m->gskip, m->col, val, x, y, m->col16);
+                     nb_long, m->n_long, m->long_rows, m->row_ptr, m->gskip, m->col, val, x, y, m->col16, skip);
   check_launch("spmv");
 }
 
 template <typename VT, typename XT, typename AT, typename YT>
-void spmv_impl(gp_ctx* c, const gp_matrix* m, const XT* x, YT* y) {
+void spmv_impl(gp_ctx* c, const gp_matrix* m, const XT* x, YT* y, const int* skip) {
   ProfScope ps(c, sizeof(VT) == 4 ? (sizeof(XT) == 4 ? "spmv_f32" : "spmv_f32val_f64") : "spmv_f64");
-  spmv_launch<VT, XT, AT, YT>(c, m, x, y);
+  spmv_launch<VT, XT, AT, YT>(c, m, x, y, skip);
 }
 
 }  // namespace
@@ -546,12 +549,12 @@ void spmv_f64_enqueue(gp_ctx* c, const gp_matrix* m, const double* x, double* y)
     spmv_launch<double, double, double, double>(c, m, x, y);
 }
 
-void spmv_f64(gp_ctx* c, const gp_matrix* m, const double* x, double* y) {
+void spmv_f64(gp_ctx* c, const gp_matrix* m, const double* x, double* y, const int* skip) {
   build_col16(c, const_cast<gp_matrix*>(m));
   if (m->prec == GP_MIXED)
-    spmv_impl<float, double, double, double>(c, m, x, y);
+    spmv_impl<float, double, double, double>(c, m, x, y, skip);
   else
-    spmv_impl<double, double, double, double>(c, m, x, y);
+    spmv_impl<double, double, double, double>(c, m, x, y, skip);
 }
 
 
@@ -1235,5 +1238,10 @@ void spmm(gp_ctx* c, const gp_matrix* m, int k, int ld, const T* X, T* Y, const 
 
 template void spmm<double>(gp_ctx*, const gp_matrix*, int, int, const double*, double*, const double*,
                            const double*);
+
+void build_product_caches(gp_ctx* c, gp_matrix* m) {
+  build_col16(c, m);
+  build_quads(c, m);
+}
 
 }  // namespace gps
