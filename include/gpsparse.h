@@ -375,6 +375,33 @@ GP_API gp_status gp_loglik(gp_ctx* ctx, const gp_matrix* m, const double* y_dev,
 GP_API gp_status gp_loglik_async(gp_ctx* ctx, const gp_matrix* m, const double* y_dev, const gp_solve_opts* opts,
                                  double* alpha_dev, gp_loglik_result* out, void* event);
 
+/* gp_loglik_batch: the log-likelihoods of nreq problems (Sec. 3.1 Eq. Zmarg),
+ * evaluated together: the sampler of Appendix C evaluates many
+ * hyper-parameter proposals whose matrices are small (a few thousand to tens
+ * of thousands of rows, Sec. 3.3), each too small to fill the device alone.
+ * The matrices K[r] (one precision; each of its own dataset and theta) are
+ * stacked into one block-diagonal matrix, so every product, vector and
+ * reduction launch serves all problems; each problem keeps its own scalars,
+ * convergence test and probes, and stops on its own (its vector work ends,
+ * the shared products run until every problem has ended).  Each result
+ * equals what gp_loglik returns for that problem alone, bitwise.
+ * y_dev[r]: n_r float64 in the ORIGINAL order of K[r]'s dataset;
+ * alpha_dev (may be NULL, as may alpha_dev[r]) receives K[r]^-1 y[r].
+ * out: nreq results in host memory (the call waits for the device; it reads
+ * back one flag per 8 iterations to stop once all problems have ended).
+ * Solver: GP_SOLVER_CG, or GP_SOLVER_AUTO, where a problem whose conjugate
+ * gradients end in GP_ENOTCONV or GP_ENOTPD is evaluated again alone by
+ * gp_loglik (MINRES fallback); logdet mode GP_LOGDET_SLQ or GP_LOGDET_NONE.
+ * The call builds each matrix's product and preconditioner caches if needed
+ * and a stacked copy of the matrices (about their total size) that it frees
+ * before it returns.
+ * Returns GP_OK when every problem succeeded, else the status of the first
+ * that did not (each out[r].status holds its own; a non-finite y[r] gives
+ * GP_EINVAL there); GP_EINVAL (arguments, solver, logdet mode, mixed
+ * precisions), GP_ENOMEM or GP_EDEVICE for the whole call. */
+GP_API gp_status gp_loglik_batch(gp_ctx* ctx, int32_t nreq, const gp_matrix* const* K, const double* const* y_dev,
+                                 const gp_solve_opts* opts, double* const* alpha_dev, gp_loglik_result* out);
+
 /* gp_solve: alpha = K^-1 y only (the quadratic-form task of Sec. 3.3). */
 GP_API gp_status gp_solve(gp_ctx* ctx, const gp_matrix* m, const double* y_dev,
                    const gp_solve_opts* opts, double* alpha_dev, gp_loglik_result* out);

@@ -87,6 +87,7 @@ EXPORTS = [
     "gp_dataset_create", "gp_dataset_destroy", "gp_dataset_info", "gp_dataset_permutation",
     "gp_assemble", "gp_matrix_destroy", "gp_matrix_info", "gp_matrix_export_csr", "gp_matvec",
     "gp_matvec_noalloc", "gp_matrix_layout", "gp_predict_batch", "gp_loglik_async",
+    "gp_loglik_batch",
     "gp_solve_opts_default", "gp_loglik", "gp_solve", "gp_predictor_create", "gp_predictor_destroy",
     "gp_predict", "gp_predict_var", "gp_mean_residual", "gp_profile_enable", "gp_profile_read",
 ]
@@ -130,6 +131,8 @@ def lib():
     L.gp_loglik.argtypes = [P, P, P, C.POINTER(CSolveOpts), P, C.POINTER(CLoglikResult)]
     L.gp_solve.argtypes = [P, P, P, C.POINTER(CSolveOpts), P, C.POINTER(CLoglikResult)]
     L.gp_loglik_async.argtypes = [P, P, P, C.POINTER(CSolveOpts), P, P, P]
+    L.gp_loglik_batch.argtypes = [P, C.c_int32, C.POINTER(P), C.POINTER(P), C.POINTER(CSolveOpts), C.POINTER(P),
+                                  C.POINTER(CLoglikResult)]
     L.gp_predictor_create.argtypes = [P, P, C.POINTER(CTheta), P, C.POINTER(P)]
     L.gp_predictor_destroy.argtypes = [P, P]
     L.gp_predict.argtypes = [P, P, I64, P, C.c_int, P]
@@ -374,6 +377,31 @@ class Context:
                                      C.c_void_p(buf.data_ptr()), C.c_void_p(event.cuda_event))
         self._check(st, "gp_loglik_async")
         return _PendingLoglik(buf, event), event
+
+    def loglik_batch(self, Ks, ys, alpha_outs=None, raise_on_error: bool = True, **opts) -> list:
+        """gp_loglik_batch: the likelihoods of several problems in shared
+        launches; returns one result dict per problem (status included)."""
+        torch = _torch()
+        R = len(Ks)
+        if R == 0 or len(ys) != R or (alpha_outs is not None and len(alpha_outs) != R):
+            raise ValueError("loglik_batch: one y (and alpha_out) per matrix")
+        for K, y in zip(Ks, ys):
+            _check_dev_tensor(y, torch.float64, (K.n,), "y")
+        if alpha_outs is not None:
+            for K, a in zip(Ks, alpha_outs):
+                if a is not None:
+                    _check_dev_tensor(a, torch.float64, (K.n,), "alpha_out")
+        o = self.opts(**opts)
+        mats = (C.c_void_p * R)(*[K._h.value for K in Ks])
+        yp = (C.c_void_p * R)(*[_ptr(y) for y in ys])
+        ap = None
+        if alpha_outs is not None:
+            ap = (C.c_void_p * R)(*[_ptr(a) if a is not None else None for a in alpha_outs])
+        res = (CLoglikResult * R)()
+        st = self._L.gp_loglik_batch(self._h, R, mats, yp, C.byref(o), ap, res)
+        if st != 0 and raise_on_error:
+            self._check(st, "gp_loglik_batch")
+        return [r.as_dict() for r in res]
 
     def solve(self, K: "Matrix", y, alpha_out, raise_on_error: bool = True, **opts) -> dict:
         torch = _torch()

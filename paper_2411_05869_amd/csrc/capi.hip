@@ -502,26 +502,32 @@ static gp_status loglik_common(gp_ctx* c, const gp_matrix* m, const double* y, c
 
 namespace {
 
-// The result of the device-driven likelihood, written by the device into the
-// caller's (pinned or device) memory: -1/2 logdet - 1/2 quad - (n/2) log 2 pi.
+// The results of the device-driven likelihood of R problems, written by the
+// device into the caller's (pinned or device) memory:
+// -1/2 logdet - 1/2 quad - (n/2) log 2 pi, with (n/2) log 2 pi formed on the
+// host as gp_loglik forms it (half_n_log2pi[r], or half1 for one problem).
 __global__ void k_loglik_result(gps::DeviceSolve sv, const gps::DeviceLogdet* __restrict__ ld, int with_logdet,
-                                double half_n_log2pi, gp_loglik_result* __restrict__ out) {
+                                const double* __restrict__ half_n_log2pi, double half1, int R,
+                                gp_loglik_result* __restrict__ out) {
 #pragma clang fp contract(off)
-  gp_loglik_result r{};
-  r.quad = *sv.quad;
-  r.relres = *sv.relres;
-  r.cg_iters = *sv.iters;
-  r.refreshes = *sv.refreshes;
-  int st = *sv.status;
-  if (with_logdet) {
-    r.logdet = ld->logdet;
-    r.logdet_se = ld->se;
-    r.lanczos_steps = ld->steps;
-    if (st == GP_OK) st = ld->status;
+  for (int q = threadIdx.x; q < R; q += blockDim.x) {
+    const gps::CgCtl& ctl = sv.ctl[q];
+    gp_loglik_result r{};
+    r.quad = sv.quad[q];
+    r.relres = ctl.relres;
+    r.cg_iters = ctl.iters;
+    r.refreshes = ctl.refreshes;
+    int st = ctl.status;
+    if (with_logdet) {
+      r.logdet = ld[q].logdet;
+      r.logdet_se = ld[q].se;
+      r.lanczos_steps = ld[q].steps;
+      if (st == GP_OK) st = ld[q].status;
+    }
+    r.loglik = -0.5 * r.logdet - 0.5 * r.quad - (half_n_log2pi ? half_n_log2pi[q] : half1);
+    r.status = st;
+    out[q] = r;
   }
-  r.loglik = -0.5 * r.logdet - 0.5 * r.quad - half_n_log2pi;
-  r.status = st;
-  *out = r;
 }
 
 }  // namespace
@@ -559,11 +565,105 @@ gp_status gp_loglik_async(gp_ctx* c, const gp_matrix* m, const double* y, const 
       gps::slq_logdet_device(c, m, o.seed, o.n_probes, o.n_lanczos, o.logdet_mode == GP_LOGDET_SLQ_REORTH, ld);
     // (n/2) log(2 pi) formed on the host as gp_loglik forms it
     const double half_n_log2pi = 0.5 * static_cast<double>(n) * std::log(2.0 * M_PI);
-    hipLaunchKernelGGL(k_loglik_result, dim3(1), dim3(1), 0, c->stream, sv, ld, with_logdet ? 1 : 0, half_n_log2pi,
-                       out);
+    hipLaunchKernelGGL(k_loglik_result, dim3(1), dim3(64), 0, c->stream, sv, ld, with_logdet ? 1 : 0, nullptr,
+                       half_n_log2pi, 1, out);
     gps::check_launch("loglik result");
     if (event) GPS_HIP(hipEventRecord(static_cast<hipEvent_t>(event), c->stream));
   });
+}
+
+gp_status gp_loglik_batch(gp_ctx* c, int32_t nreq, const gp_matrix* const* K, const double* const* y,
+                          const gp_solve_opts* opts, double* const* alpha, gp_loglik_result* out) {
+  if (!c || !K || !y || !out || nreq < 1) return GP_EINVAL;
+  for (int r = 0; r < nreq; ++r)
+    if (!K[r] || !y[r]) return GP_EINVAL;
+  std::memset(out, 0, sizeof(gp_loglik_result) * nreq);
+  const gp_solve_opts o = fill_opts(opts);
+  gp_status st = guarded(c, [&] {
+    GPS_REQUIRE(o.solver == GP_SOLVER_CG || o.solver == GP_SOLVER_AUTO, GP_EINVAL,
+                "gp_loglik_batch: the solver must be GP_SOLVER_CG or GP_SOLVER_AUTO");
+    GPS_REQUIRE(o.logdet_mode == GP_LOGDET_SLQ || o.logdet_mode == GP_LOGDET_NONE, GP_EINVAL,
+                "gp_loglik_batch: the log det mode must be GP_LOGDET_SLQ or GP_LOGDET_NONE");
+    const int R = nreq;
+    const bool bj = o.precond == GP_PRECOND_BLOCK_JACOBI;
+    for (int r = 0; r < R; ++r) {
+      gp_matrix* mm = const_cast<gp_matrix*>(K[r]);
+      GPS_REQUIRE(mm->ds != nullptr, GP_EINVAL, "gp_loglik_batch: a matrix has no dataset");
+      gps::build_product_caches(c, mm);
+      if (bj) gps::build_block_jacobi(c, mm);
+    }
+    auto release = [c](gp_matrix* x) { gps::destroy_matrix(c, x); };
+    std::unique_ptr<gp_matrix, decltype(release)> S(gps::stack_matrices(c, R, K, bj), release);
+    const int64_t n = S->n;
+    // per problem: row offsets, 1 / sqrt(n_r) (the first Lanczos scale), (n_r / 2) log 2 pi
+    std::vector<int64_t> off(R + 1, 0);
+    int64_t nmax = 0;
+    for (int r = 0; r < R; ++r) {
+      off[r + 1] = off[r] + K[r]->n;
+      nmax = std::max(nmax, K[r]->n);
+    }
+    const size_t tb = sizeof(int64_t) * (R + 1) + 2 * sizeof(double) * R;
+    char* h = static_cast<char*>(gps::pinned_for_write(c, tb));
+    std::memcpy(h, off.data(), sizeof(int64_t) * (R + 1));
+    double* hinv = reinterpret_cast<double*>(h + sizeof(int64_t) * (R + 1));
+    double* hhalf = hinv + R;
+    for (int r = 0; r < R; ++r) {
+      hinv[r] = 1.0 / std::sqrt(static_cast<double>(K[r]->n));
+      hhalf[r] = 0.5 * static_cast<double>(K[r]->n) * std::log(2.0 * M_PI);
+    }
+    char* dtab = static_cast<char*>(gps::workspace(c, 131, tb));
+    gps::h2d_async(c, dtab, h, tb);
+    const int64_t* doff = reinterpret_cast<const int64_t*>(dtab);
+    const double* dinv = reinterpret_cast<const double*>(dtab + sizeof(int64_t) * (R + 1));
+    const double* dhalf = dinv + R;
+    // stacked right-hand sides and probe keys (each problem's own original indices)
+    double* yb = static_cast<double*>(gps::workspace(c, 44, sizeof(double) * n));
+    double* xb = static_cast<double*>(gps::workspace(c, 45, sizeof(double) * n));
+    int32_t* perm = static_cast<int32_t*>(gps::workspace(c, 132, sizeof(int32_t) * n));
+    for (int r = 0; r < R; ++r) {
+      gps::permute_to_binned<double>(c, K[r]->ds, 1, y[r], yb + off[r]);
+      GPS_HIP(hipMemcpyAsync(perm + off[r], K[r]->ds->perm, sizeof(int32_t) * K[r]->n, hipMemcpyDeviceToDevice,
+                             c->stream));
+    }
+    gps::DeviceSolve sv{};
+    gps::pcg_solve_batch(c, S.get(), yb, xb, o.rtol, o.max_iter, o.precond, R, doff, nmax, &sv);
+    if (alpha)
+      for (int r = 0; r < R; ++r)
+        if (alpha[r]) gps::permute_to_orig<double>(c, K[r]->ds, 1, xb + off[r], alpha[r]);
+    const bool with_logdet = o.logdet_mode == GP_LOGDET_SLQ;
+    gps::DeviceLogdet* ld = static_cast<gps::DeviceLogdet*>(gps::workspace(c, 133, sizeof(gps::DeviceLogdet) * R));
+    if (with_logdet) {
+      gps::SlqBatch b;
+      b.R = R;
+      b.off = doff;
+      b.inv0 = dinv;
+      b.perm = perm;
+      b.nmax = nmax;
+      gps::slq_logdet_batch(c, S.get(), o.seed, o.n_probes, o.n_lanczos, b, ld);
+    }
+    gp_loglik_result* dres = static_cast<gp_loglik_result*>(gps::workspace(c, 134, sizeof(gp_loglik_result) * R));
+    hipLaunchKernelGGL(k_loglik_result, dim3(1), dim3(64), 0, c->stream, sv, ld, with_logdet ? 1 : 0, dhalf, 0.0, R,
+                       dres);
+    gps::check_launch("loglik batch result");
+    gp_loglik_result* hres = static_cast<gp_loglik_result*>(gps::pinned(c, sizeof(gp_loglik_result) * R));
+    GPS_HIP(hipMemcpyAsync(hres, dres, sizeof(gp_loglik_result) * R, hipMemcpyDeviceToHost, c->stream));
+    gps::sync(c);
+    std::memcpy(out, hres, sizeof(gp_loglik_result) * R);
+  });
+  if (st != GP_OK) {
+    for (int r = 0; r < nreq; ++r) out[r].status = st;
+    return st;
+  }
+  // GP_SOLVER_AUTO: a problem whose conjugate gradients did not succeed is
+  // evaluated again alone, where MINRES takes over as in gp_loglik
+  gp_status first = GP_OK;
+  for (int r = 0; r < nreq; ++r) {
+    if (o.solver == GP_SOLVER_AUTO && (out[r].status == GP_ENOTCONV || out[r].status == GP_ENOTPD))
+      (void)loglik_common(c, K[r], y[r], &o, alpha ? alpha[r] : nullptr, &out[r], true);
+    if (first == GP_OK && out[r].status != GP_OK) first = static_cast<gp_status>(out[r].status);
+  }
+  if (first != GP_OK) c->err = "at least one problem of the batch did not succeed (see its status)";
+  return first;
 }
 
 gp_status gp_loglik(gp_ctx* c, const gp_matrix* m, const double* y, const gp_solve_opts* opts, double* alpha,

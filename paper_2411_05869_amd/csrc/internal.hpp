@@ -307,6 +307,10 @@ void spmv_f64(gp_ctx* c, const gp_matrix* m, const double* x, double* y, const i
 // builds the caches the products read (int16 offsets, row quads) now, with
 // host synchronisations, so that later products need none
 void build_product_caches(gp_ctx* c, gp_matrix* m);
+// Block-diagonal stack of R assembled matrices of one precision, whose product
+// caches (and block-Jacobi blocks, when block_jacobi) are built: a new matrix
+// with no dataset, row r of problem q at stacked row (rows of problems < q) + r.
+gp_matrix* stack_matrices(gp_ctx* c, int R, const gp_matrix* const* ms, bool block_jacobi);
 // the same product using only the caches already built (no allocation, no
 // synchronisation, no profiling events)
 void spmv_f64_enqueue(gp_ctx* c, const gp_matrix* m, const double* x, double* y);
@@ -376,15 +380,33 @@ void matvec_noalloc(gp_ctx* c, const gp_matrix* m, const double* x, double* y);
 // pcg_solve_device enqueues the conjugate gradients up to max_iter with
 // every decision taken on the device; its results stay in device memory, at
 // the addresses it returns.  The matrix's caches must be built already.
+// Control state of a device-driven conjugate-gradient solve (one per problem
+// of a batch), in device memory.
+struct CgCtl {
+  int skip_iter;    // nonzero: the iterations are over (converged or failed)
+  int skip_true;    // nonzero: no true-residual pass after this block
+  int skip_final;   // nonzero: no final true residual (converged, or y = 0)
+  int iters, refreshes, status;
+  double target;    // rtol |y|_2 (compared with |r|_2 as the host form does)
+  double relres;
+};
+// the flags every problem of a batch shares (all problems' flags set)
+struct CtlAll {
+  int skip_iter, skip_true, skip_final;
+};
+// results of a device-driven solve of R problems: quad[r], ctl[r]
 struct DeviceSolve {
   const double* quad;
-  const int* iters;
-  const int* refreshes;
-  const int* status;
-  const double* relres;
+  const CgCtl* ctl;
 };
 void pcg_solve_device(gp_ctx* c, gp_matrix* m, const double* yb, double* xb, double rtol, int max_iter, int precond,
                       DeviceSolve* out);
+// R problems stacked along the rows of m (a block-diagonal matrix; off: R + 1
+// device row offsets, nmax the longest problem), each solved as
+// pcg_solve_device would solve it alone; the host checks after every block
+// of iterations whether all have ended.
+void pcg_solve_batch(gp_ctx* c, gp_matrix* m, const double* yb, double* xb, double rtol, int max_iter, int precond,
+                     int R, const int64_t* off, int64_t nmax, DeviceSolve* out);
 struct DeviceLogdet {
   double logdet, se;
   int steps, status;
@@ -392,6 +414,18 @@ struct DeviceLogdet {
 // writes the SLQ estimate into out (device memory)
 void slq_logdet_device(gp_ctx* c, const gp_matrix* m, uint64_t seed, int n_probes, int n_steps, bool reorth,
                        DeviceLogdet* out);
+// R problems stacked along the rows of m, each estimated as slq_logdet_device
+// would estimate it alone (same probes, keyed by the problem's own original
+// indices); out[r] per problem
+struct SlqBatch {
+  int R = 0;
+  const int64_t* off = nullptr;   // R + 1 device row offsets
+  const double* inv0 = nullptr;   // R device values 1 / sqrt(n_r)
+  const int32_t* perm = nullptr;  // stacked rows -> the problem's original index
+  int64_t nmax = 0;               // rows of the longest problem
+};
+void slq_logdet_batch(gp_ctx* c, const gp_matrix* m, uint64_t seed, int n_probes, int n_steps, const SlqBatch& b,
+                      DeviceLogdet* out);
 
 // deterministic reductions
 double dot_f64(gp_ctx* c, const double* a, const double* b, int64_t n);   // synchronising

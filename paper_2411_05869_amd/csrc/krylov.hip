@@ -21,9 +21,38 @@ constexpr int kRedBlocks = 512;
 constexpr int kCheckEvery = 8;
 constexpr int kLoadBatch = 4;  // strided elements a thread loads at once in the streaming kernels
 
+// A batched solve stacks independent problems along the rows (a block-diagonal
+// matrix, vectors concatenated); blockIdx.y selects the problem.  Every
+// problem keeps the grid, the partial-sum layout and the reduction order a
+// solve of its own length uses, so its scalars equal that solve's bitwise.
+// off == nullptr: one problem, of the length the kernel is given.
+struct Seg {
+  const int64_t* off = nullptr;  // problems + 1 row offsets into the stacked vectors
+  int pstride = 0;               // doubles between the partial-sum arrays of consecutive problems
+};
+
+// first row of this block's problem; n becomes its length
+__device__ __forceinline__ int64_t seg_begin(const Seg& g, int64_t& n) {
+  if (!g.off) return 0;
+  const int64_t b = g.off[blockIdx.y];
+  n = g.off[blockIdx.y + 1] - b;
+  return b;
+}
+
+// blocks of a per-row grid of a problem of n rows (grid_for on the device)
+__device__ __forceinline__ int seg_blocks(int64_t n, int per_block) {
+  const int64_t b = (n + per_block - 1) / per_block;
+  return static_cast<int>(b < 1 ? 1 : b);
+}
+
 // ---------------------------------------------------------------- reductions
 __global__ void __launch_bounds__(kThreads) k_dot_part(int64_t n, const double* __restrict__ a,
-                                                       const double* __restrict__ b, double* __restrict__ part) {
+                                                       const double* __restrict__ b, double* __restrict__ part,
+                                                       Seg g = {}) {
+  const int64_t o = seg_begin(g, n);
+  a += o;
+  b += o;
+  part += blockIdx.y * g.pstride;
   double v[1] = {0};
   for (int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; i < n;
        i += static_cast<int64_t>(gridDim.x) * kThreads)
@@ -31,14 +60,18 @@ __global__ void __launch_bounds__(kThreads) k_dot_part(int64_t n, const double* 
   block_sum_store<1>(v, part);
 }
 
-__global__ void __launch_bounds__(kThreads) k_sum_part(const double* __restrict__ part, int nb, double* __restrict__ out) {
+__global__ void __launch_bounds__(kThreads) k_sum_part(const double* __restrict__ part, int nb, double* __restrict__ out,
+                                                       Seg g = {}) {
+  part += blockIdx.y * g.pstride;
   double r[1];
   reduce_partials<1>(part, nb, r);
-  if (threadIdx.x == 0) out[0] = r[0];
+  if (threadIdx.x == 0) out[blockIdx.y] = r[0];
 }
 
 __global__ void __launch_bounds__(kThreads) k_logsum_part(int64_t n, const double* __restrict__ a,
-                                                          double* __restrict__ part) {
+                                                          double* __restrict__ part, Seg g = {}) {
+  a += seg_begin(g, n);
+  part += blockIdx.y * g.pstride;
   double v[1] = {0};
   for (int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; i < n;
        i += static_cast<int64_t>(gridDim.x) * kThreads)
@@ -51,6 +84,17 @@ struct CgScalars {
   double rz, rz_old, pq, alpha, beta, rr, yy, pad;
   int status;  // 0 ok, 1 non-positive curvature / non-finite
 };
+
+// The skip flags of a device-driven solve (CgCtl, one per problem of a batch)
+// are read by every kernel of the iterations: a kernel returns at once while
+// its problem's flag is set.
+constexpr int kCtlInts = static_cast<int>(sizeof(CgCtl) / sizeof(int));  // flag stride between problems
+static_assert(sizeof(CgCtl) % sizeof(int) == 0, "CgCtl is a whole number of ints");
+
+// this block's problem's skip flag (null: never skip)
+__device__ __forceinline__ bool seg_skip(const int* skip) {
+  return skip && skip[blockIdx.y * kCtlInts];
+}
 
 // Preconditioner description passed to the kernels (block Jacobi if binv != null,
 // otherwise point Jacobi with the matrix diagonal).
@@ -90,8 +134,15 @@ __global__ void __launch_bounds__(kThreads) k_pcg_step(int64_t n, Precond M, CgS
                                                        const double* __restrict__ p, const QT* __restrict__ q,
                                                        double* __restrict__ x, const double* __restrict__ r,
                                                        double* __restrict__ rn, double* __restrict__ z,
-                                                       double* __restrict__ part, const int* __restrict__ skip) {
-  if (skip && *skip) return;
+                                                       double* __restrict__ part, const int* __restrict__ skip,
+                                                       Seg g = {}) {
+  if (seg_skip(skip)) return;
+  const int64_t o = seg_begin(g, n);
+  if (g.off && static_cast<int>(blockIdx.x) >= seg_blocks(n, kThreads * kStepRows)) return;
+  const int64_t e = o + n;  // rows o .. e of the stacked vectors (the preconditioner is indexed by stacked rows)
+  s += blockIdx.y;
+  pq_part += blockIdx.y * g.pstride;
+  part += blockIdx.y * g.pstride;
   // Everything a row reads is independent of alpha, so the row's vectors, its
   // block (row -> block -> start and offset) and the block's first kPreEntries
   // weights and r, q values are requested before the kRedBlocks partials of
@@ -107,9 +158,9 @@ __global__ void __launch_bounds__(kThreads) k_pcg_step(int64_t n, Precond M, CgS
   int sz[kStepRows];
 #pragma unroll
   for (int u = 0; u < kStepRows; ++u) {
-    const int64_t i = (blockIdx.x * static_cast<int64_t>(kStepRows) + u) * kThreads + threadIdx.x;
+    const int64_t i = o + (blockIdx.x * static_cast<int64_t>(kStepRows) + u) * kThreads + threadIdx.x;
     sz[u] = 0;
-    if (i < n) {
+    if (i < e) {
       xv[u] = x[i];
       pv[u] = p[i];
       rv[u] = r[i];
@@ -140,8 +191,8 @@ __global__ void __launch_bounds__(kThreads) k_pcg_step(int64_t n, Precond M, CgS
   double v[2] = {0, 0};
 #pragma unroll
   for (int u = 0; u < kStepRows; ++u) {
-    const int64_t i = (blockIdx.x * static_cast<int64_t>(kStepRows) + u) * kThreads + threadIdx.x;
-    if (i < n) {
+    const int64_t i = o + (blockIdx.x * static_cast<int64_t>(kStepRows) + u) * kThreads + threadIdx.x;
+    if (i < e) {
       x[i] = xv[u] + alpha * pv[u];
       const double ri = rv[u] - alpha * qv[u];
       double zi;
@@ -177,8 +228,14 @@ __global__ void __launch_bounds__(kThreads) k_pcg_step(int64_t n, Precond M, CgS
 __global__ void __launch_bounds__(kThreads) k_pcg_direction(int64_t n, CgScalars* __restrict__ s,
                                                             const double* __restrict__ part, int nb,
                                                             const double* __restrict__ z, double* __restrict__ p,
-                                                            const int* __restrict__ skip) {
-  if (skip && *skip) return;
+                                                            const int* __restrict__ skip, Seg g = {}) {
+  if (seg_skip(skip)) return;
+  const int64_t o = seg_begin(g, n);
+  if (g.off) nb = seg_blocks(n, kThreads * kStepRows);  // the step's partials of this problem
+  z += o;
+  p += o;
+  s += blockIdx.y;
+  part += blockIdx.y * g.pstride;
   // the first batch of z and p is requested before the partial sums are
   // reduced, and each later batch before the previous one is stored
   const int64_t stride = static_cast<int64_t>(gridDim.x) * kThreads;
@@ -215,7 +272,12 @@ __global__ void __launch_bounds__(kThreads) k_pcg_direction(int64_t n, CgScalars
 
 // x = 0, r = y; partial sums of y.y
 __global__ void __launch_bounds__(kThreads) k_pcg_init(int64_t n, const double* __restrict__ y, double* __restrict__ x,
-                                                       double* __restrict__ r, double* __restrict__ part) {
+                                                       double* __restrict__ r, double* __restrict__ part, Seg g = {}) {
+  const int64_t o = seg_begin(g, n);
+  y += o;
+  x += o;
+  r += o;
+  part += blockIdx.y * g.pstride;
   double v[1] = {0};
   for (int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; i < n;
        i += static_cast<int64_t>(gridDim.x) * kThreads) {
@@ -227,7 +289,10 @@ __global__ void __launch_bounds__(kThreads) k_pcg_init(int64_t n, const double* 
   block_sum_store<1>(v, part);
 }
 
-__global__ void __launch_bounds__(kThreads) k_yy_fin(const double* __restrict__ part, int nb, CgScalars* __restrict__ s) {
+__global__ void __launch_bounds__(kThreads) k_yy_fin(const double* __restrict__ part, int nb, CgScalars* __restrict__ s,
+                                                     Seg g = {}) {
+  part += blockIdx.y * g.pstride;
+  s += blockIdx.y;
   double r[1];
   reduce_partials<1>(part, nb, r);
   if (threadIdx.x == 0) {
@@ -240,11 +305,14 @@ __global__ void __launch_bounds__(kThreads) k_yy_fin(const double* __restrict__ 
 // dependent gathers); per-block partial sums of r.z and r.r
 __global__ void __launch_bounds__(kThreads) k_precond(int64_t n, Precond M, const double* __restrict__ r,
                                                       double* __restrict__ z, double* __restrict__ part,
-                                                      const int* __restrict__ skip = nullptr) {
-  if (skip && *skip) return;
+                                                      const int* __restrict__ skip = nullptr, Seg g = {}) {
+  if (seg_skip(skip)) return;
+  const int64_t o = seg_begin(g, n);
+  if (g.off && static_cast<int>(blockIdx.x) >= seg_blocks(n, kThreads)) return;
+  part += blockIdx.y * g.pstride;
   double v[2] = {0, 0};
-  const int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x;
-  if (i < n) {
+  const int64_t i = o + blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x;  // stacked row
+  if (i < o + n) {
     const double ri = r[i];
     const double zi = precond_row(M, r, i);
     z[i] = zi;
@@ -258,8 +326,12 @@ __global__ void __launch_bounds__(kThreads) k_precond(int64_t n, Precond M, cons
 template <typename QT>
 __global__ void __launch_bounds__(kThreads) k_pq_part(int64_t n, const double* __restrict__ p,
                                                       const QT* __restrict__ q, double* __restrict__ part,
-                                                      const int* __restrict__ skip) {
-  if (skip && *skip) return;
+                                                      const int* __restrict__ skip, Seg g = {}) {
+  if (seg_skip(skip)) return;
+  const int64_t o = seg_begin(g, n);
+  p += o;
+  q += o;
+  part += blockIdx.y * g.pstride;
   // four strided elements loaded at once, then added in the order of a plain
   // grid-stride loop (the sum does not depend on the unrolling)
   double v[1] = {0};
@@ -284,10 +356,17 @@ __global__ void __launch_bounds__(kThreads) k_pq_part(int64_t n, const double* _
 
 // mode 1: residual replacement (rz_old kept)
 // mode 2: start (rz <- r.z, no beta)
+// (batched: per_block = rows per partial of the kernel that wrote them)
 __global__ void __launch_bounds__(kThreads) k_beta_fin(const double* __restrict__ part, int nb,
                                                        CgScalars* __restrict__ s, int mode,
-                                                       const int* __restrict__ skip = nullptr) {
-  if (skip && *skip) return;
+                                                       const int* __restrict__ skip = nullptr, Seg g = {},
+                                                       int per_block = 0) {
+  if (seg_skip(skip)) return;
+  int64_t n = 0;
+  seg_begin(g, n);
+  if (g.off) nb = seg_blocks(n, per_block);
+  part += blockIdx.y * g.pstride;
+  s += blockIdx.y;
   double r[2];
   reduce_partials<2>(part, nb, r);
   if (threadIdx.x == 0) {
@@ -302,9 +381,12 @@ __global__ void __launch_bounds__(kThreads) k_beta_fin(const double* __restrict_
 // p = z + beta p (beta = 0 at the start)
 __global__ void __launch_bounds__(kThreads) k_pcg_pupdate(int64_t n, const CgScalars* __restrict__ s,
                                                           const double* __restrict__ z, double* __restrict__ p,
-                                                          const int* __restrict__ skip = nullptr) {
-  if (skip && *skip) return;
-  const double beta = s->beta;
+                                                          const int* __restrict__ skip = nullptr, Seg g = {}) {
+  if (seg_skip(skip)) return;
+  const int64_t o = seg_begin(g, n);
+  z += o;
+  p += o;
+  const double beta = s[blockIdx.y].beta;
   for (int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; i < n;
        i += static_cast<int64_t>(gridDim.x) * kThreads)
     p[i] = beta == 0.0 ? z[i] : z[i] + beta * p[i];
@@ -313,8 +395,12 @@ __global__ void __launch_bounds__(kThreads) k_pcg_pupdate(int64_t n, const CgSca
 // r = y - Kx (Kx given)
 __global__ void __launch_bounds__(kThreads) k_true_resid(int64_t n, const double* __restrict__ y,
                                                          const double* __restrict__ kx, double* __restrict__ r,
-                                                         const int* __restrict__ skip = nullptr) {
-  if (skip && *skip) return;
+                                                         const int* __restrict__ skip = nullptr, Seg g = {}) {
+  if (seg_skip(skip)) return;
+  const int64_t o = seg_begin(g, n);
+  y += o;
+  kx += o;
+  r += o;
   for (int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; i < n;
        i += static_cast<int64_t>(gridDim.x) * kThreads)
     r[i] = y[i] - kx[i];
@@ -373,7 +459,13 @@ struct LzState {
 template <typename T>
 __global__ void __launch_bounds__(kThreads) k_lz_beta_dot(int64_t n, int ld, const LzState* __restrict__ st,
                                                           const T* __restrict__ V, const T* __restrict__ Vprev,
-                                                          T* __restrict__ W, double* __restrict__ part) {
+                                                          T* __restrict__ W, double* __restrict__ part, Seg g = {}) {
+  const int64_t o = seg_begin(g, n) * ld;
+  V += o;
+  Vprev += o;
+  W += o;
+  st += blockIdx.y;
+  part += blockIdx.y * g.pstride;
   // thread layout: 32 columns x 8 row-lanes per block
   const int l = threadIdx.x & 31;
   const int rl = threadIdx.x >> 5;
@@ -418,7 +510,12 @@ __global__ void __launch_bounds__(kThreads) k_lz_beta_dot(int64_t n, int ld, con
 template <typename T>
 __global__ void __launch_bounds__(kThreads) k_lz_alpha_norm(int64_t n, int ld, const LzState* __restrict__ st,
                                                             const T* __restrict__ V, T* __restrict__ W,
-                                                            double* __restrict__ part) {
+                                                            double* __restrict__ part, Seg g = {}) {
+  const int64_t o = seg_begin(g, n) * ld;
+  V += o;
+  W += o;
+  st += blockIdx.y;
+  part += blockIdx.y * g.pstride;
   const int l = threadIdx.x & 31;
   const int rl = threadIdx.x >> 5;
   const T a = static_cast<T>(st->alpha[l]);
@@ -532,9 +629,15 @@ __global__ void __launch_bounds__(kThreads) k_lz_norm(int64_t n, const double* _
 // loads are in flight), then the groups are added in order.
 constexpr int kFinGroups = 32;
 
+// (batched: problem blockIdx.y, its coefficients tstride doubles apart)
 __global__ void __launch_bounds__(kFinGroups * 32) k_lz_fin(const double* __restrict__ part, int nb, int k, int mode,
                                                             int j, int last, double tol, LzState* __restrict__ st,
-                                                            double* __restrict__ Ta, double* __restrict__ Tb) {
+                                                            double* __restrict__ Ta, double* __restrict__ Tb,
+                                                            Seg sg = {}, int64_t tstride = 0) {
+  part += blockIdx.y * sg.pstride;
+  st += blockIdx.y;
+  Ta += blockIdx.y * tstride;
+  Tb += blockIdx.y * tstride;
   __shared__ double sh[kFinGroups][32];
   const int l = threadIdx.x & 31;
   const int g = threadIdx.x >> 5;
@@ -630,10 +733,22 @@ __device__ bool tridiag_eig_first_row(double* a, double* b, double* q, int m) {
 constexpr int kQuadProbes = 8;
 constexpr int kQuadMax = 128;
 
+// (batched: problem blockIdx.y, |z|^2 its length)
 __global__ void __launch_bounds__(kQuadProbes) k_quadrature(int k, const double* __restrict__ Ta,
                                                             const double* __restrict__ Tb,
                                                             const LzState* __restrict__ st, double znorm2,
-                                                            double* __restrict__ gam, int* __restrict__ bad) {
+                                                            double* __restrict__ gam, int* __restrict__ bad,
+                                                            Seg sg = {}, int64_t tstride = 0) {
+  if (sg.off) {
+    int64_t n = 0;
+    seg_begin(sg, n);
+    znorm2 = static_cast<double>(n);
+    Ta += blockIdx.y * tstride;
+    Tb += blockIdx.y * tstride;
+    st += blockIdx.y;
+    gam += blockIdx.y * 32;
+    bad += blockIdx.y;
+  }
   __shared__ double sa[kQuadProbes][kQuadMax + 1], sb[kQuadProbes][kQuadMax + 1], sq[kQuadProbes][kQuadMax + 1];
   const int l = blockIdx.x * kQuadProbes + threadIdx.x;
   if (l >= k) return;
@@ -850,77 +965,115 @@ namespace {
 // ------------------------------------------------ device-driven conjugate gradients
 // The iterations of pcg_solve with every decision taken on the device: the
 // host enqueues blocks of kCheckEvery iterations up to max_iter; after each
-// block a one-thread kernel compares the recursive residual with the target
+// block a control kernel compares the recursive residual with the target
 // and, at apparent convergence, lets the true-residual pass run; every kernel
 // of the iterations returns at once once the solve has ended (skip flags).
-struct CgCtl {
-  int skip_iter;    // nonzero: the iterations are over (converged or failed)
-  int skip_true;    // nonzero: no true-residual pass after this block
-  int skip_final;   // nonzero: no final true residual (converged, or y = 0)
-  int iters, refreshes, status;
-  double target;    // rtol |y|_2 (compared with |r|_2 as the host form does)
-  double relres;
-};
+// For a batch the control kernels take one thread per problem and also gather
+// the flags the problems share: a product of the stacked matrix is skipped
+// only once every problem has set its flag.
+constexpr int kCtlThreads = 64;
 
-__global__ void k_ctl_init(const CgScalars* __restrict__ s, CgCtl* __restrict__ ctl, double rtol) {
-  const double yy = s->yy;
-  ctl->iters = 0;
-  ctl->refreshes = 0;
-  ctl->skip_true = 1;
-  ctl->relres = 0.0;
-  ctl->target = rtol * sqrt(yy);
-  if (!isfinite(yy)) {
-    ctl->status = GP_EINVAL;
-    ctl->skip_iter = ctl->skip_final = 1;
-  } else if (yy == 0.0) {
-    ctl->status = GP_OK;  // x = 0 is exact
-    ctl->skip_iter = ctl->skip_final = 1;
-  } else {
-    ctl->status = GP_OK;
-    ctl->skip_iter = ctl->skip_final = 0;
+__device__ void ctl_gather(const CgCtl* __restrict__ ctl, int R, CtlAll* __restrict__ all) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int si = 1, st = 1, sf = 1;
+    for (int r = 0; r < R; ++r) {
+      si &= ctl[r].skip_iter != 0;
+      st &= ctl[r].skip_true != 0;
+      sf &= ctl[r].skip_final != 0;
+    }
+    all->skip_iter = si;
+    all->skip_true = st;
+    all->skip_final = sf;
   }
 }
 
-__global__ void k_ctl_check(const CgScalars* __restrict__ s, CgCtl* __restrict__ ctl, int steps) {
-  if (ctl->skip_iter) return;
-  ctl->iters += steps;
-  if (s->status != 0) {
-    ctl->status = GP_ENOTPD;
-    ctl->skip_iter = 1;
-    return;
+__global__ void __launch_bounds__(kCtlThreads) k_ctl_init(const CgScalars* __restrict__ s, CgCtl* __restrict__ ctl,
+                                                          double rtol, int R, CtlAll* __restrict__ all) {
+  for (int r = threadIdx.x; r < R; r += kCtlThreads) {
+    CgCtl* cr = ctl + r;
+    const double yy = s[r].yy;
+    cr->iters = 0;
+    cr->refreshes = 0;
+    cr->skip_true = 1;
+    cr->relres = 0.0;
+    cr->target = rtol * sqrt(yy);
+    if (!isfinite(yy)) {
+      cr->status = GP_EINVAL;
+      cr->skip_iter = cr->skip_final = 1;
+    } else if (yy == 0.0) {
+      cr->status = GP_OK;  // x = 0 is exact
+      cr->skip_iter = cr->skip_final = 1;
+    } else {
+      cr->status = GP_OK;
+      cr->skip_iter = cr->skip_final = 0;
+    }
   }
-  ctl->skip_true = sqrt(s->rr) <= ctl->target ? 0 : 1;
+  ctl_gather(ctl, R, all);
 }
 
-__global__ void k_ctl_after_true(const CgScalars* __restrict__ s, CgCtl* __restrict__ ctl) {
-  if (ctl->skip_true) return;
-  ctl->skip_true = 1;
-  ctl->refreshes += 1;
-  if (sqrt(s->rr) <= ctl->target) {
-    ctl->skip_iter = 1;
-    ctl->skip_final = 1;
-    ctl->relres = sqrt(s->rr) / sqrt(s->yy);
+__global__ void __launch_bounds__(kCtlThreads) k_ctl_check(const CgScalars* __restrict__ s, CgCtl* __restrict__ ctl,
+                                                           int steps, int R, CtlAll* __restrict__ all) {
+  for (int r = threadIdx.x; r < R; r += kCtlThreads) {
+    CgCtl* cr = ctl + r;
+    if (cr->skip_iter) continue;
+    cr->iters += steps;
+    if (s[r].status != 0) {
+      cr->status = GP_ENOTPD;
+      cr->skip_iter = 1;
+      continue;
+    }
+    cr->skip_true = sqrt(s[r].rr) <= cr->target ? 0 : 1;
   }
+  ctl_gather(ctl, R, all);
 }
 
-__global__ void k_ctl_end(const CgScalars* __restrict__ s, CgCtl* __restrict__ ctl) {
-  if (!ctl->skip_iter) {
-    ctl->status = GP_ENOTCONV;
-    ctl->skip_iter = 1;
+__global__ void __launch_bounds__(kCtlThreads) k_ctl_after_true(const CgScalars* __restrict__ s,
+                                                                CgCtl* __restrict__ ctl, int R,
+                                                                CtlAll* __restrict__ all) {
+  for (int r = threadIdx.x; r < R; r += kCtlThreads) {
+    CgCtl* cr = ctl + r;
+    if (cr->skip_true) continue;
+    cr->skip_true = 1;
+    cr->refreshes += 1;
+    if (sqrt(s[r].rr) <= cr->target) {
+      cr->skip_iter = 1;
+      cr->skip_final = 1;
+      cr->relres = sqrt(s[r].rr) / sqrt(s[r].yy);
+    }
   }
+  ctl_gather(ctl, R, all);
 }
 
-__global__ void k_ctl_relres(const CgScalars* __restrict__ s, CgCtl* __restrict__ ctl) {
-  if (!ctl->skip_final) {
-    ctl->relres = sqrt(s->rr) / sqrt(s->yy);
-    if (ctl->status == GP_ENOTCONV && sqrt(s->rr) <= ctl->target) ctl->status = GP_OK;
+__global__ void __launch_bounds__(kCtlThreads) k_ctl_end(CgCtl* __restrict__ ctl, int R, CtlAll* __restrict__ all) {
+  for (int r = threadIdx.x; r < R; r += kCtlThreads) {
+    if (!ctl[r].skip_iter) {
+      ctl[r].status = GP_ENOTCONV;
+      ctl[r].skip_iter = 1;
+    }
+  }
+  ctl_gather(ctl, R, all);
+}
+
+__global__ void __launch_bounds__(kCtlThreads) k_ctl_relres(const CgScalars* __restrict__ s, CgCtl* __restrict__ ctl,
+                                                            int R) {
+  for (int r = threadIdx.x; r < R; r += kCtlThreads) {
+    CgCtl* cr = ctl + r;
+    if (!cr->skip_final) {
+      cr->relres = sqrt(s[r].rr) / sqrt(s[r].yy);
+      if (cr->status == GP_ENOTCONV && sqrt(s[r].rr) <= cr->target) cr->status = GP_OK;
+    }
   }
 }
 
 }  // namespace
 
-void pcg_solve_device(gp_ctx* c, gp_matrix* m, const double* y, double* x, double rtol, int max_iter, int precond,
-                      DeviceSolve* out) {
+// One device-driven solve, or a batch of R problems stacked along the rows of
+// m (off: R + 1 device row offsets, nmax the longest problem).  poll: the host
+// reads the shared iteration flag after every block of iterations and stops
+// enqueueing once every problem has ended.
+static void pcg_device_impl(gp_ctx* c, gp_matrix* m, const double* y, double* x, double rtol, int max_iter,
+                            int precond, int R, const int64_t* off, int64_t nmax, bool poll, DeviceSolve* out) {
   const int64_t n = m->n;
   Precond M{m->diag, nullptr, nullptr, nullptr, nullptr};
   if (precond == GP_PRECOND_BLOCK_JACOBI) {
@@ -929,70 +1082,99 @@ void pcg_solve_device(gp_ctx* c, gp_matrix* m, const double* y, double* x, doubl
     M.boff = m->boff;
     M.binv = m->binv;
   }
+  const bool batch = off != nullptr;
+  const int64_t nrow = batch ? nmax : n;  // rows of the longest problem: sets the per-row grids
+  const unsigned nbp = grid_for(nrow, kThreads);
+  const unsigned nbs = grid_for(nrow, kThreads * kStepRows);
+  Seg g;
+  if (batch) {
+    g.off = off;
+    g.pstride = static_cast<int>(std::max<int64_t>(4 * kRedBlocks, 2 * static_cast<int64_t>(nbp)));
+  }
+  const size_t pbytes = sizeof(double) * (batch ? static_cast<size_t>(R) * g.pstride : 4 * kRedBlocks);
+  const size_t ppbytes = sizeof(double) * (batch ? static_cast<size_t>(R) * g.pstride : 2 * nbp);
   double* rc = static_cast<double*>(workspace(c, 20, sizeof(double) * n));
   double* rnx = static_cast<double*>(workspace(c, 29, sizeof(double) * n));
   double* z = static_cast<double*>(workspace(c, 21, sizeof(double) * n));
   double* p = static_cast<double*>(workspace(c, 22, sizeof(double) * n));
   double* q = static_cast<double*>(workspace(c, 23, sizeof(double) * n));
-  double* part = static_cast<double*>(workspace(c, 26, sizeof(double) * 4 * kRedBlocks));
-  const unsigned nbp = grid_for(n, kThreads);
-  const unsigned nbs = grid_for(n, kThreads * kStepRows);
-  double* ppart = static_cast<double*>(workspace(c, 28, sizeof(double) * 2 * nbp));
-  CgScalars* s = static_cast<CgScalars*>(workspace(c, 27, sizeof(CgScalars)));
-  CgCtl* ctl = static_cast<CgCtl*>(workspace(c, 24, sizeof(CgCtl)));
+  double* part = static_cast<double*>(workspace(c, 26, pbytes));
+  double* ppart = static_cast<double*>(workspace(c, 28, ppbytes));
+  CgScalars* s = static_cast<CgScalars*>(workspace(c, 27, sizeof(CgScalars) * R));
+  CgCtl* ctl = static_cast<CgCtl*>(workspace(c, 24, sizeof(CgCtl) * R));
+  CtlAll* all = static_cast<CtlAll*>(workspace(c, 130, sizeof(CtlAll)));
+  // per-problem flags for the vector kernels, shared flags for the products
   const int* skip_iter = &ctl->skip_iter;
   const int* skip_true = &ctl->skip_true;
   const int* skip_final = &ctl->skip_final;
-  const dim3 G(kRedBlocks), B(kThreads);
-  auto true_residual = [&](const int* gate) {
-    spmv_f64(c, m, x, q, gate);
-    hipLaunchKernelGGL(k_true_resid, G, B, 0, c->stream, n, y, q, rc, gate);
-    hipLaunchKernelGGL(k_precond, dim3(nbp), B, 0, c->stream, n, M, rc, z, ppart, gate);
-    hipLaunchKernelGGL(k_beta_fin, dim3(1), B, 0, c->stream, ppart, static_cast<int>(nbp), s, 1, gate);
+  const unsigned Ry = static_cast<unsigned>(R);
+  const dim3 G(kRedBlocks, Ry), B(kThreads), G1(1, Ry), GP(nbp, Ry), GS(nbs, Ry), C(kCtlThreads);
+  auto true_residual = [&](const int* gate, const int* shared_gate) {
+    spmv_f64(c, m, x, q, shared_gate);
+    hipLaunchKernelGGL(k_true_resid, G, B, 0, c->stream, nrow, y, q, rc, gate, g);
+    hipLaunchKernelGGL(k_precond, GP, B, 0, c->stream, nrow, M, rc, z, ppart, gate, g);
+    hipLaunchKernelGGL(k_beta_fin, G1, B, 0, c->stream, ppart, static_cast<int>(nbp), s, 1, gate, g, kThreads);
   };
-  hipLaunchKernelGGL(k_pcg_init, G, B, 0, c->stream, n, y, x, rc, part);
-  hipLaunchKernelGGL(k_yy_fin, dim3(1), B, 0, c->stream, part, kRedBlocks, s);
-  hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(1), 0, c->stream, s, ctl, rtol);
-  hipLaunchKernelGGL(k_precond, dim3(nbp), B, 0, c->stream, n, M, rc, z, ppart, skip_iter);
-  hipLaunchKernelGGL(k_beta_fin, dim3(1), B, 0, c->stream, ppart, static_cast<int>(nbp), s, 2, skip_iter);
-  hipLaunchKernelGGL(k_pcg_pupdate, G, B, 0, c->stream, n, s, z, p, skip_iter);
+  hipLaunchKernelGGL(k_pcg_init, G, B, 0, c->stream, nrow, y, x, rc, part, g);
+  hipLaunchKernelGGL(k_yy_fin, G1, B, 0, c->stream, part, kRedBlocks, s, g);
+  hipLaunchKernelGGL(k_ctl_init, dim3(1), C, 0, c->stream, s, ctl, rtol, R, all);
+  hipLaunchKernelGGL(k_precond, GP, B, 0, c->stream, nrow, M, rc, z, ppart, skip_iter, g);
+  hipLaunchKernelGGL(k_beta_fin, G1, B, 0, c->stream, ppart, static_cast<int>(nbp), s, 2, skip_iter, g, kThreads);
+  hipLaunchKernelGGL(k_pcg_pupdate, G, B, 0, c->stream, nrow, s, z, p, skip_iter, g);
   check_launch("pcg init");
   double* pqp = part;
   double* spart = ppart;
+  int* hflag = poll ? static_cast<int*>(pinned(c, sizeof(int))) : nullptr;
   for (int it = 0; it < max_iter; it += kCheckEvery) {
     const int steps = std::min(kCheckEvery, max_iter - it);
     for (int t = 0; t < steps; ++t) {
-      spmv_f64(c, m, p, q, skip_iter);
+      spmv_f64(c, m, p, q, &all->skip_iter);
       ProfScope ps(c, "pcg_vector_ops");
-      hipLaunchKernelGGL((k_pq_part<double>), G, B, 0, c->stream, n, p, q, pqp, skip_iter);
-      hipLaunchKernelGGL((k_pcg_step<double>), dim3(nbs), B, 0, c->stream, n, M, s, pqp, p, q, x, rc, rnx, z,
-                         spart, skip_iter);
+      hipLaunchKernelGGL((k_pq_part<double>), G, B, 0, c->stream, nrow, p, q, pqp, skip_iter, g);
+      hipLaunchKernelGGL((k_pcg_step<double>), GS, B, 0, c->stream, nrow, M, s, pqp, p, q, x, rc, rnx, z,
+                         spart, skip_iter, g);
       std::swap(rc, rnx);
       if (t + 1 < steps)
-        hipLaunchKernelGGL(k_pcg_direction, G, B, 0, c->stream, n, s, spart, static_cast<int>(nbs), z, p, skip_iter);
+        hipLaunchKernelGGL(k_pcg_direction, G, B, 0, c->stream, nrow, s, spart, static_cast<int>(nbs), z, p,
+                           skip_iter, g);
       else
-        hipLaunchKernelGGL(k_beta_fin, dim3(1), B, 0, c->stream, spart, static_cast<int>(nbs), s, 3, skip_iter);
+        hipLaunchKernelGGL(k_beta_fin, G1, B, 0, c->stream, spart, static_cast<int>(nbs), s, 3, skip_iter, g,
+                           kThreads * kStepRows);
     }
-    hipLaunchKernelGGL(k_ctl_check, dim3(1), dim3(1), 0, c->stream, s, ctl, steps);
-    true_residual(skip_true);
-    hipLaunchKernelGGL(k_ctl_after_true, dim3(1), dim3(1), 0, c->stream, s, ctl);
-    hipLaunchKernelGGL(k_pcg_pupdate, G, B, 0, c->stream, n, s, z, p, skip_iter);
+    hipLaunchKernelGGL(k_ctl_check, dim3(1), C, 0, c->stream, s, ctl, steps, R, all);
+    true_residual(skip_true, &all->skip_true);
+    hipLaunchKernelGGL(k_ctl_after_true, dim3(1), C, 0, c->stream, s, ctl, R, all);
+    hipLaunchKernelGGL(k_pcg_pupdate, G, B, 0, c->stream, nrow, s, z, p, skip_iter, g);
     check_launch("pcg iteration block");
+    if (poll) {
+      GPS_HIP(hipMemcpyAsync(hflag, &all->skip_iter, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+      sync(c);
+      if (*hflag) break;
+    }
   }
-  hipLaunchKernelGGL(k_ctl_end, dim3(1), dim3(1), 0, c->stream, s, ctl);
-  true_residual(skip_final);
-  hipLaunchKernelGGL(k_ctl_relres, dim3(1), dim3(1), 0, c->stream, s, ctl);
-  // quad = y . x
-  double* qd = static_cast<double*>(workspace(c, 25, sizeof(double) * 2));
-  double* dpart = static_cast<double*>(workspace(c, 40, sizeof(double) * kRedBlocks));
-  hipLaunchKernelGGL(k_dot_part, G, B, 0, c->stream, n, y, x, dpart);
-  hipLaunchKernelGGL(k_sum_part, dim3(1), B, 0, c->stream, dpart, kRedBlocks, qd);
+  hipLaunchKernelGGL(k_ctl_end, dim3(1), C, 0, c->stream, ctl, R, all);
+  true_residual(skip_final, &all->skip_final);
+  hipLaunchKernelGGL(k_ctl_relres, dim3(1), C, 0, c->stream, s, ctl, R);
+  // quad = y . x per problem
+  Seg gq = g;
+  if (batch) gq.pstride = kRedBlocks;
+  double* qd = static_cast<double*>(workspace(c, 25, sizeof(double) * std::max(R, 2)));
+  double* dpart = static_cast<double*>(workspace(c, 40, sizeof(double) * kRedBlocks * R));
+  hipLaunchKernelGGL(k_dot_part, G, B, 0, c->stream, nrow, y, x, dpart, gq);
+  hipLaunchKernelGGL(k_sum_part, G1, B, 0, c->stream, dpart, kRedBlocks, qd, gq);
   check_launch("pcg end");
   out->quad = qd;
-  out->iters = &ctl->iters;
-  out->refreshes = &ctl->refreshes;
-  out->status = &ctl->status;
-  out->relres = &ctl->relres;
+  out->ctl = ctl;
+}
+
+void pcg_solve_device(gp_ctx* c, gp_matrix* m, const double* y, double* x, double rtol, int max_iter, int precond,
+                      DeviceSolve* out) {
+  pcg_device_impl(c, m, y, x, rtol, max_iter, precond, 1, nullptr, m->n, false, out);
+}
+
+void pcg_solve_batch(gp_ctx* c, gp_matrix* m, const double* y, double* x, double rtol, int max_iter, int precond,
+                     int R, const int64_t* off, int64_t nmax, DeviceSolve* out) {
+  pcg_device_impl(c, m, y, x, rtol, max_iter, precond, R, off, nmax, true, out);
 }
 
 namespace {
@@ -1243,9 +1425,12 @@ namespace {
 
 // device-driven SLQ pieces: the Lanczos state of a batch of probes, the
 // per-probe quadratures collected across batches, and the estimate
-__global__ void k_lz_state_init(LzState* __restrict__ st, int k, double inv0) {
+// (batched: problem blockIdx.y starts from inv0s[blockIdx.y])
+__global__ void k_lz_state_init(LzState* __restrict__ st, int k, double inv0, const double* __restrict__ inv0s) {
   const int l = threadIdx.x;
   if (l >= 32) return;
+  st += blockIdx.y;
+  if (inv0s) inv0 = inv0s[blockIdx.y];
   st->alpha[l] = st->beta[l] = st->beta_prev[l] = st->inv_prev[l] = 0.0;
   st->active[l] = l < k ? 1 : 0;
   st->inv_cur[l] = l < k ? inv0 : 0.0;
@@ -1253,7 +1438,11 @@ __global__ void k_lz_state_init(LzState* __restrict__ st, int k, double inv0) {
 }
 
 __global__ void k_slq_collect(const LzState* __restrict__ st, const double* __restrict__ gam, int k, int p0,
-                              double* __restrict__ gam_all, int* __restrict__ steps_all) {
+                              double* __restrict__ gam_all, int* __restrict__ steps_all, int np) {
+  st += blockIdx.y;
+  gam += blockIdx.y * 32;
+  gam_all += blockIdx.y * np;
+  steps_all += blockIdx.y * np;
   const int l = threadIdx.x;
   if (l < k) {
     gam_all[p0 + l] = gam[l];
@@ -1266,6 +1455,11 @@ __global__ void k_slq_collect(const LzState* __restrict__ st, const double* __re
 __global__ void k_slq_final(const double* __restrict__ gam_all, const int* __restrict__ steps_all, int np,
                             const double* __restrict__ jac, const int* __restrict__ bad, DeviceLogdet* __restrict__ out) {
 #pragma clang fp contract(off)
+  gam_all += blockIdx.y * np;
+  steps_all += blockIdx.y * np;
+  jac += blockIdx.y;
+  bad += blockIdx.y;
+  out += blockIdx.y;
   double mean = 0;
   int ms = 0;
   for (int i = 0; i < np; ++i) {
@@ -1281,13 +1475,39 @@ __global__ void k_slq_final(const double* __restrict__ gam_all, const int* __res
   out->status = (bad[0] & 1) ? GP_EDEVICE : ((bad[0] & 2) ? GP_ENOTPD : GP_OK);
 }
 
+// W[:, l] *= inv_cur[l] of the row's problem (l < k): the column factor a
+// single problem's product applies as its last multiplication
+__global__ void __launch_bounds__(kThreads) k_lz_colscale(int64_t n, int k, int ld, const LzState* __restrict__ st,
+                                                          double* __restrict__ W, Seg g) {
+  const int64_t o = seg_begin(g, n);
+  const double* f = st[blockIdx.y].inv_cur;
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; i < n * 32;
+       i += static_cast<int64_t>(gridDim.x) * kThreads) {
+    const int l = static_cast<int>(i & 31);
+    if (l < k) W[(o + (i >> 5)) * ld + l] *= f[l];
+  }
+}
+
 }  // namespace
 
 template <typename T>
 static LogdetResult slq_impl(gp_ctx* c, const gp_matrix* m, uint64_t seed, int n_probes, int n_steps, double tol,
-                             bool reorth, DeviceLogdet* dev_out = nullptr) {
+                             bool reorth, DeviceLogdet* dev_out = nullptr, const SlqBatch* bt = nullptr) {
   const int64_t n = m->n;
   const int ld = 32;
+  // a batch: R problems stacked along the rows, each with its own Lanczos
+  // state, coefficients, partial sums and estimate (dev_out[r])
+  const int R = bt ? bt->R : 1;
+  const unsigned Ry = static_cast<unsigned>(R);
+  const int64_t nrow = bt ? bt->nmax : n;
+  Seg gl, gj;
+  if (bt) {
+    gl.off = gj.off = bt->off;
+    gl.pstride = 32 * kRedBlocks;
+    gj.pstride = kRedBlocks;
+  }
+  const int64_t tstride = static_cast<int64_t>(32) * n_steps;
+  const int32_t* perm = bt ? bt->perm : m->ds->perm;
   // full re-orthogonalisation keeps every normalised Lanczos block
   double* Qall = reorth ? static_cast<double*>(workspace(c, 57, sizeof(double) * n * ld * n_steps)) : nullptr;
   constexpr int kRoBlocks = 256;
@@ -1297,12 +1517,12 @@ static LogdetResult slq_impl(gp_ctx* c, const gp_matrix* m, uint64_t seed, int n
   T* Vp = static_cast<T*>(workspace(c, 31, sizeof(T) * n * ld));
   T* W = static_cast<T*>(workspace(c, 32, sizeof(T) * n * ld));
   T* sc = static_cast<T*>(workspace(c, 33, sizeof(T) * n));
-  double* part = static_cast<double*>(workspace(c, 34, sizeof(double) * 32 * kRedBlocks));
-  LzState* st = static_cast<LzState*>(workspace(c, 35, sizeof(LzState)));
-  double* Ta = static_cast<double*>(workspace(c, 36, sizeof(double) * 32 * n_steps));
-  double* Tb = static_cast<double*>(workspace(c, 37, sizeof(double) * 32 * n_steps));
-  double* gam = static_cast<double*>(workspace(c, 38, sizeof(double) * 32));
-  int* bad = static_cast<int*>(workspace(c, 39, sizeof(int) * 2));
+  double* part = static_cast<double*>(workspace(c, 34, sizeof(double) * 32 * kRedBlocks * R));
+  LzState* st = static_cast<LzState*>(workspace(c, 35, sizeof(LzState) * R));
+  double* Ta = static_cast<double*>(workspace(c, 36, sizeof(double) * tstride * R));
+  double* Tb = static_cast<double*>(workspace(c, 37, sizeof(double) * tstride * R));
+  double* gam = static_cast<double*>(workspace(c, 38, sizeof(double) * 32 * R));
+  int* bad = static_cast<int*>(workspace(c, 39, sizeof(int) * std::max(R, 2)));
   hipLaunchKernelGGL((k_scale_vec<T>), dim3(grid_for(n, kThreads)), dim3(kThreads), 0, c->stream, n, m->diag, sc);
   check_launch("slq scale");
   const bool dev = dev_out != nullptr;
@@ -1313,14 +1533,14 @@ static LogdetResult slq_impl(gp_ctx* c, const gp_matrix* m, uint64_t seed, int n
   int* bad_all = nullptr;
   if (dev) {
     // Jacobi part, probe results and failure flags stay on the device
-    djac = static_cast<double*>(workspace(c, 46, sizeof(double) * 2));
-    double* jpart = static_cast<double*>(workspace(c, 47, sizeof(double) * kRedBlocks));
-    hipLaunchKernelGGL(k_logsum_part, dim3(kRedBlocks), dim3(kThreads), 0, c->stream, n, m->diag, jpart);
-    hipLaunchKernelGGL(k_sum_part, dim3(1), dim3(kThreads), 0, c->stream, jpart, kRedBlocks, djac);
-    gam_all = static_cast<double*>(workspace(c, 48, sizeof(double) * 64));
-    steps_all = static_cast<int*>(workspace(c, 49, sizeof(int) * 64));
+    djac = static_cast<double*>(workspace(c, 46, sizeof(double) * std::max(R, 2)));
+    double* jpart = static_cast<double*>(workspace(c, 47, sizeof(double) * kRedBlocks * R));
+    hipLaunchKernelGGL(k_logsum_part, dim3(kRedBlocks, Ry), dim3(kThreads), 0, c->stream, nrow, m->diag, jpart, gj);
+    hipLaunchKernelGGL(k_sum_part, dim3(1, Ry), dim3(kThreads), 0, c->stream, jpart, kRedBlocks, djac, gj);
+    gam_all = static_cast<double*>(workspace(c, 48, sizeof(double) * n_probes * R));
+    steps_all = static_cast<int*>(workspace(c, 49, sizeof(int) * n_probes * R));
     bad_all = bad;
-    GPS_HIP(hipMemsetAsync(bad_all, 0, sizeof(int), c->stream));
+    GPS_HIP(hipMemsetAsync(bad_all, 0, sizeof(int) * R, c->stream));
   } else {
     jac = logsum_f64(c, m->diag, n);
   }
@@ -1331,7 +1551,7 @@ static LogdetResult slq_impl(gp_ctx* c, const gp_matrix* m, uint64_t seed, int n
     const int k = std::min(32, n_probes - p0);
     const double inv0 = 1.0 / std::sqrt(static_cast<double>(n));  // v_1 = +-1 / sqrt(n)
     if (dev) {
-      hipLaunchKernelGGL(k_lz_state_init, dim3(1), dim3(32), 0, c->stream, st, k, inv0);
+      hipLaunchKernelGGL(k_lz_state_init, dim3(1, Ry), dim3(32), 0, c->stream, st, k, inv0, bt ? bt->inv0 : nullptr);
     } else {
       LzState init{};
       for (int l = 0; l < 32; ++l) {
@@ -1344,18 +1564,22 @@ static LogdetResult slq_impl(gp_ctx* c, const gp_matrix* m, uint64_t seed, int n
       GPS_HIP(hipMemsetAsync(bad, 0, sizeof(int), c->stream));
     }
     hipLaunchKernelGGL((k_lz_init<T>), dim3(grid_for(n * ld, kThreads)), dim3(kThreads), 0, c->stream, n, k, ld, p0,
-                       seed, m->ds->perm, V, Vp);
+                       seed, perm, V, Vp);
     check_launch("lanczos init");
     for (int j = 0; j < n_steps; ++j) {
       const int last = j == n_steps - 1;
-      spmm<T>(c, m, ld, ld, V, W, sc, st->inv_cur);   // W = A v_j
+      // W = A v_j (a batch applies each problem's column factors afterwards)
+      spmm<T>(c, m, ld, ld, V, W, sc, bt ? nullptr : st->inv_cur);
+      if (bt)
+        hipLaunchKernelGGL(k_lz_colscale, dim3(grid_for(nrow * 32, kThreads), Ry), dim3(kThreads), 0, c->stream,
+                           nrow, k, ld, st, W, gl);
       ProfScope ps(c, "lanczos_vector_ops");
-      hipLaunchKernelGGL((k_lz_beta_dot<T>), dim3(kRedBlocks), dim3(kThreads), 0, c->stream, n, ld, st, V, Vp, W,
-                         part);
-      hipLaunchKernelGGL(k_lz_fin, dim3(1), dim3(kFinGroups * 32), 0, c->stream, part, kRedBlocks, k, 0, j, last, tol, st,
-                         Ta, Tb);
-      hipLaunchKernelGGL((k_lz_alpha_norm<T>), dim3(kRedBlocks), dim3(kThreads), 0, c->stream, n, ld, st, V, W,
-                         part);
+      hipLaunchKernelGGL((k_lz_beta_dot<T>), dim3(kRedBlocks, Ry), dim3(kThreads), 0, c->stream, nrow, ld, st, V, Vp,
+                         W, part, gl);
+      hipLaunchKernelGGL(k_lz_fin, dim3(1, Ry), dim3(kFinGroups * 32), 0, c->stream, part, kRedBlocks, k, 0, j, last,
+                         tol, st, Ta, Tb, gl, tstride);
+      hipLaunchKernelGGL((k_lz_alpha_norm<T>), dim3(kRedBlocks, Ry), dim3(kThreads), 0, c->stream, nrow, ld, st, V, W,
+                         part, gl);
       if (reorth) {
         // W -= Q Q^T W twice over q_0 .. q_j, then |W|^2 afresh
         double* Qj = Qall + static_cast<int64_t>(j) * n * ld;
@@ -1369,8 +1593,8 @@ static LogdetResult slq_impl(gp_ctx* c, const gp_matrix* m, uint64_t seed, int n
         hipLaunchKernelGGL(k_lz_norm, dim3(kRedBlocks), dim3(kThreads), 0, c->stream, n, W, part);
         check_launch("lanczos reorthogonalisation");
       }
-      hipLaunchKernelGGL(k_lz_fin, dim3(1), dim3(kFinGroups * 32), 0, c->stream, part, kRedBlocks, k, 1, j, last, tol, st,
-                         Ta, Tb);
+      hipLaunchKernelGGL(k_lz_fin, dim3(1, Ry), dim3(kFinGroups * 32), 0, c->stream, part, kRedBlocks, k, 1, j, last,
+                         tol, st, Ta, Tb, gl, tstride);
       if (!last) {
         // rotate: the residual block W holds the next (unnormalised) v
         T* old_prev = Vp;
@@ -1380,11 +1604,12 @@ static LogdetResult slq_impl(gp_ctx* c, const gp_matrix* m, uint64_t seed, int n
       }
       check_launch("lanczos step");
     }
-    hipLaunchKernelGGL(k_quadrature, dim3((k + kQuadProbes - 1) / kQuadProbes), dim3(kQuadProbes), 0, c->stream, k, Ta, Tb, st, static_cast<double>(n), gam,
-                       bad);
+    hipLaunchKernelGGL(k_quadrature, dim3((k + kQuadProbes - 1) / kQuadProbes, Ry), dim3(kQuadProbes), 0, c->stream, k,
+                       Ta, Tb, st, static_cast<double>(n), gam, bad, gl, tstride);
     check_launch("quadrature");
     if (dev) {
-      hipLaunchKernelGGL(k_slq_collect, dim3(1), dim3(32), 0, c->stream, st, gam, k, p0, gam_all, steps_all);
+      hipLaunchKernelGGL(k_slq_collect, dim3(1, Ry), dim3(32), 0, c->stream, st, gam, k, p0, gam_all, steps_all,
+                         n_probes);
       check_launch("slq collect");
       continue;
     }
@@ -1403,7 +1628,7 @@ static LogdetResult slq_impl(gp_ctx* c, const gp_matrix* m, uint64_t seed, int n
   }
   LogdetResult res;
   if (dev) {
-    hipLaunchKernelGGL(k_slq_final, dim3(1), dim3(1), 0, c->stream, gam_all, steps_all, n_probes, djac, bad_all,
+    hipLaunchKernelGGL(k_slq_final, dim3(1, Ry), dim3(1), 0, c->stream, gam_all, steps_all, n_probes, djac, bad_all,
                        dev_out);
     check_launch("slq final");
     return res;
@@ -1433,6 +1658,11 @@ LogdetResult slq_logdet(gp_ctx* c, const gp_matrix* m, uint64_t seed, int n_prob
 void slq_logdet_device(gp_ctx* c, const gp_matrix* m, uint64_t seed, int n_probes, int n_steps, bool reorth,
                        DeviceLogdet* out) {
   slq_impl<double>(c, m, seed, n_probes, n_steps, 1e-10, reorth, out);
+}
+
+void slq_logdet_batch(gp_ctx* c, const gp_matrix* m, uint64_t seed, int n_probes, int n_steps, const SlqBatch& b,
+                      DeviceLogdet* out) {
+  slq_impl<double>(c, m, seed, n_probes, n_steps, 1e-10, false, out, &b);
 }
 
 // Exact log det: Lanczos on the Jacobi-scaled matrix to dimension n with full
