@@ -212,10 +212,13 @@ def cpu_baseline(p):
 def serving_legs(args, ctx, ds, p, alpha):
     """Continuous batching: (1) the MCMC-proposal stream (Poisson, 50 req/s,
     mixture data sets with n log-uniform in [5k, 300k], mixed precision,
-    SLQ 30 x 50, PCG rtol 1e-10) -> p50/p99 latency and evals/s; (2) posterior
-    means on the resident space-time training set, requests of 1k-50k test
-    points: all queued at once (points/s), then Poisson at half that rate
-    (p50/p99)."""
+    SLQ 30 x 50, PCG rtol 1e-10; problems of at most 50k points batched by
+    gp_loglik_batch) -> p50/p99 latency and evals/s, then the first
+    --serve-saturation requests all queued at once on 1 slot, on 4 slots and
+    on 4 slots with batching (evals/s: the slots' overlap and the batching's
+    gain); (2) posterior means on the resident space-time training set,
+    requests of 1k-50k test points: all queued at once (points/s), then
+    Poisson at half that rate (p50/p99)."""
     import numpy as np
 
     from paper_2411_05869_amd.serve import GpuBackend, LoglikRequest, PredictRequest, Server, latency_stats
@@ -225,22 +228,50 @@ def serving_legs(args, ctx, ds, p, alpha):
     pool, reqs = config4_requests(n_requests=args.serve_requests, rate=50.0)
     # point Jacobi: on the 2-D mixture sets, whose dense clusters fill cells with
     # many points, the cell-block preconditioner takes more CG iterations
-    be = GpuBackend(n_slots=4, solve_opts=dict(precond=PRECOND_JACOBI))
-    for k, q in enumerate(pool):
-        be.add_dataset(f"d{k}", q.x, q.y, cell=q.cell, row_estimate=60.0)
-    requests = [LoglikRequest(f"d{k}", th, 1, arrival=t) for (t, k, th) in reqs]
-    log(f"serving: {len(requests)} log-likelihood requests at 50 req/s on 4 slots")
-    srv = Server(be, hbm_budget=64 << 30)
-    comps = srv.run(requests)
-    st = latency_stats(comps)
-    st.update(requests=len(requests), rate_per_s=50.0, slots=4, precond="jacobi",
-              peak_reserved_gb=round(srv.peak_reserved / 2 ** 30, 3),
+    backends = {}
+
+    def backend(slots, batch_max_n):
+        key = (slots, batch_max_n)
+        if key not in backends:
+            be = GpuBackend(n_slots=slots, solve_opts=dict(precond=PRECOND_JACOBI), batch_max_n=batch_max_n)
+            for k, q in enumerate(pool):
+                be.add_dataset(f"d{k}", q.x, q.y, cell=q.cell, row_estimate=60.0)
+            backends[key] = be
+        return backends[key]
+
+    def stream(be, rs, zero_arrival=False):
+        requests = [LoglikRequest(f"d{k}", th, 1, arrival=0.0 if zero_arrival else t) for (t, k, th) in rs]
+        srv = Server(be, hbm_budget=64 << 30)
+        comps = srv.run(requests)
+        st = latency_stats(comps)
+        bad = [c.result["status"] for c in comps if c.error is None and c.result["status"] != 0]
+        over = [ex / est for est, ex in srv.corrections if est > 0]
+        st.update(requests=len(requests), nonzero_status=len(bad),
+                  batches=int(sum(1 for c in comps if c.batch > 1)),
+                  mean_batch=round(float(np.mean([c.batch for c in comps])), 2),
+                  peak_reserved_gb=round(srv.peak_reserved / 2 ** 30, 3),
+                  exact_over_estimate=[round(min(over), 3), round(max(over), 3)] if over else None)
+        if zero_arrival:
+            span = max(c.done for c in comps)
+            st["saturation_evals_per_s"] = round(len(requests) / span, 2)
+        return st
+
+    log(f"serving: {len(reqs)} log-likelihood requests at 50 req/s on 4 slots")
+    st = stream(backend(4, 50_000), reqs)
+    st.update(rate_per_s=50.0, slots=4, precond="jacobi", batch_max_n=50_000,
               workload="mixture data sets n in [5k, 300k] (16 in the pool), log-normal proposals, mixed precision")
     res["loglik_stream"] = st
+    sat = reqs[:args.serve_saturation]
+    res["loglik_saturation"] = {}
+    for label, slots, bmax in (("1slot", 1, 0), ("4slot", 4, 0), ("4slot_batched", 4, 50_000)):
+        log(f"serving saturation: {len(sat)} requests at once, {label}")
+        res["loglik_saturation"][label] = stream(backend(slots, bmax), sat, zero_arrival=True)
     # predictions on the resident training set (alpha from the last mixed step)
+    be = backend(4, 50_000)
     be.datasets["train"] = (ds, None)
     be.predictors["train"] = (ctx.predictor(ds, p.theta, alpha), p.d, 0)
-    xs = config5_requests(n_requests=200, seed=5)
+    xs = config5_requests(n_requests=args.predict_requests, seed=5)
+    log(f"serving: {len(xs)} prediction requests")
     sat = [PredictRequest("train", x, 1, 0.0) for x in xs]
     comps = Server(be, hbm_budget=64 << 30).run(sat)
     span = max(c.done for c in comps)
@@ -377,7 +408,9 @@ def main():
     ap.add_argument("--lanczos", type=int, default=100, help="Lanczos steps of the timed log det (30 probes)")
     ap.add_argument("--stations", type=int, default=3000)
     ap.add_argument("--no-serve", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=128)
+    ap.add_argument("--serve-requests", type=int, default=512)
+    ap.add_argument("--serve-saturation", type=int, default=128)
+    ap.add_argument("--predict-requests", type=int, default=1000)
     ap.add_argument("--no-core", action="store_true")
     ap.add_argument("--no-var", action="store_true")
     ap.add_argument("--no-mcmc", action="store_true")

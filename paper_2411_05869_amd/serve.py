@@ -10,11 +10,18 @@ library calls release the GIL, so the slots' work overlaps on the GPU.
 Admission is first-in first-out under an HBM budget: the request at the head
 of the queue starts as soon as a slot is free and its footprint estimate fits
 in the budget not reserved by running requests.  A request whose footprint
-exceeds the whole budget is rejected with GP_ENOMEM.  Prediction requests
-that are waiting together are batched into one launch (gp_predict_batch: the
-rows of all requests back to back with a row-offset table, each request with
-its own predictor) when the backend can run them together, and split
-afterwards.
+exceeds the whole budget is rejected with GP_ENOMEM.  The estimate is made
+before the matrix exists (n times a per-data-set row-length estimate); once
+the slot has assembled the matrix the backend reports the footprint computed
+from the exact entry count and the reservation is corrected to it (the slot
+then also runs under a hard per-context budget of that size).
+
+Requests that are waiting together are batched when the backend can run them
+in shared launches: log-likelihoods of small problems (gp_loglik_batch: the
+matrices stacked block-diagonally, each problem with its own scalars and
+stopping test) and predictions (gp_predict_batch: the rows of all requests
+back to back with a row-offset table, each request with its own predictor);
+the results are split afterwards.
 
 The scheduling logic is independent of the device: a ``Backend`` runs one
 request (or batch) and estimates footprints.  ``GpuBackend`` uses the HIP
@@ -71,6 +78,9 @@ class Backend:
     """Runs requests; must be safe to call from one thread per slot."""
 
     n_slots: int = 1
+    # set by the Server while it runs: on_exact_footprint(slot, nbytes) corrects
+    # the reservation of the slot's running request to nbytes
+    on_exact_footprint = None
 
     def footprint(self, req) -> int:
         raise NotImplementedError
@@ -85,16 +95,26 @@ class Backend:
         """Whether b may join a's prediction launch (default: same predictor)."""
         return a.predictor == b.predictor and a.precision == b.precision
 
+    def can_batch_loglik(self, a: LoglikRequest, b: LoglikRequest) -> bool:
+        """Whether b may join a's likelihood launches (default: never)."""
+        return False
+
+    def run_loglik_batch(self, slot: int, reqs: List[LoglikRequest]):
+        raise NotImplementedError
+
 
 class Server:
     """FIFO admission by footprint over ``backend.n_slots`` slots."""
 
-    def __init__(self, backend: Backend, hbm_budget: int, max_predict_batch_points: int = 1 << 20):
+    def __init__(self, backend: Backend, hbm_budget: int, max_predict_batch_points: int = 1 << 20,
+                 max_loglik_batch: int = 16):
         self.backend = backend
         self.n_slots = backend.n_slots
         self.budget = int(hbm_budget)
         self.max_batch_points = max_predict_batch_points
+        self.max_loglik_batch = max_loglik_batch
         self.peak_reserved = 0
+        self.corrections = []      # (estimate, exact) per reported footprint
 
     def run(self, requests: List[Any], timeout: float = 3600.0) -> List[Completion]:
         """Serves ``requests`` (each with an ``arrival`` offset in seconds from
@@ -110,7 +130,18 @@ class Server:
         work = [queue.Queue() for _ in range(self.n_slots)]
         free = list(range(self.n_slots))
         reserved = 0
+        slot_fp = [0] * self.n_slots     # reservation of each slot's running request
         t0 = time.perf_counter()
+
+        def on_exact(slot, nbytes):
+            nonlocal reserved
+            with cv:
+                self.corrections.append((slot_fp[slot], int(nbytes)))
+                reserved += int(nbytes) - slot_fp[slot]
+                slot_fp[slot] = int(nbytes)
+                self.peak_reserved = max(self.peak_reserved, reserved)
+
+        self.backend.on_exact_footprint = on_exact
 
         def now():
             return time.perf_counter() - t0
@@ -125,7 +156,10 @@ class Server:
                 err = None
                 try:
                     if isinstance(batch[0], LoglikRequest):
-                        res = [self.backend.run_loglik(slot, batch[0])]
+                        if len(batch) == 1:
+                            res = [self.backend.run_loglik(slot, batch[0])]
+                        else:
+                            res = self.backend.run_loglik_batch(slot, batch)
                     else:
                         res = self.backend.run_predict(slot, batch)
                 except Exception as e:  # reported per request, the slot stays usable
@@ -155,10 +189,11 @@ class Server:
                     while finished:
                         item = finished.popleft()
                         if isinstance(item, tuple):
-                            _, slot, fp = item
+                            _, slot, _fp = item
                             free.append(slot)
                             free.sort()
-                            reserved -= fp
+                            reserved -= slot_fp[slot]
+                            slot_fp[slot] = 0
                         else:
                             done[item.rid] = item
                     # admit from the head while a slot is free and the footprint fits
@@ -189,9 +224,25 @@ class Server:
                                 else:
                                     keep.append(r)
                             waiting.extend(keep)
+                        elif self.max_loglik_batch > 1 and _can_batch_loglik(self.backend, head, head):
+                            # merge waiting likelihoods of small problems
+                            keep = collections.deque()
+                            while waiting:
+                                r = waiting.popleft()
+                                fr = self.backend.footprint(r)
+                                if (len(batch) < self.max_loglik_batch and isinstance(r, LoglikRequest)
+                                        and _can_batch_loglik(self.backend, head, r)
+                                        and reserved + fp + fr <= self.budget):
+                                    batch.append(r)
+                                    fp += fr
+                                else:
+                                    keep.append(r)
+                            waiting.extend(keep)
                         reserved += fp
                         self.peak_reserved = max(self.peak_reserved, reserved)
-                        work[free.pop(0)].put((batch, fp))
+                        slot = free.pop(0)
+                        slot_fp[slot] = fp
+                        work[slot].put((batch, fp))
                     if len(done) >= total:
                         break
                     wait = 0.05
@@ -204,6 +255,7 @@ class Server:
                 q.put(None)
             for th in threads:
                 th.join(timeout=60)
+            self.backend.on_exact_footprint = None
         return [done[r.rid] for r in sorted(requests, key=lambda r: r.rid)]
 
 
@@ -214,6 +266,11 @@ def _npts(xs) -> int:
 def _can_batch(backend, a: PredictRequest, b: PredictRequest) -> bool:
     f = getattr(backend, "can_batch", None)
     return f(a, b) if f is not None else Backend.can_batch(backend, a, b)
+
+
+def _can_batch_loglik(backend, a: LoglikRequest, b: LoglikRequest) -> bool:
+    f = getattr(backend, "can_batch_loglik", None)
+    return bool(f(a, b)) if f is not None else False
 
 
 def latency_stats(comps: List[Completion]) -> dict:
@@ -230,9 +287,13 @@ def latency_stats(comps: List[Completion]) -> dict:
 # ------------------------------------------------------------------ GPU backend
 
 class GpuBackend(Backend):
-    """Runs requests through the HIP library, one context and stream per slot."""
+    """Runs requests through the HIP library, one context and stream per slot.
 
-    def __init__(self, n_slots: int = 4, device: int = 0, solve_opts: Optional[dict] = None):
+    Likelihoods of problems with at most ``batch_max_n`` points are batched
+    (gp_loglik_batch); larger ones run alone."""
+
+    def __init__(self, n_slots: int = 4, device: int = 0, solve_opts: Optional[dict] = None,
+                 batch_max_n: int = 50_000, hard_budget: bool = True):
         import torch
 
         from . import Context
@@ -248,6 +309,8 @@ class GpuBackend(Backend):
         self.opts = dict(seed=2411, n_probes=30, n_lanczos=50)
         self.opts.update(solve_opts or {})
         self.row_estimate: Dict[str, float] = {}
+        self.batch_max_n = batch_max_n
+        self.hard_budget = hard_budget
 
     def add_dataset(self, name: str, x, y, cell=None, row_estimate: float = 100.0):
         torch = self.torch
@@ -277,32 +340,76 @@ class GpuBackend(Backend):
         pa, pb = self.predictors[a.predictor], self.predictors[b.predictor]
         return a.precision == b.precision and pa[1:] == pb[1:]
 
+    def can_batch_loglik(self, a: LoglikRequest, b: LoglikRequest) -> bool:
+        na, nb = self.datasets[a.dataset][0].n, self.datasets[b.dataset][0].n
+        return a.precision == b.precision and max(na, nb) <= self.batch_max_n
+
+    def _loglik_bytes(self, n: int, nnz: float, precision: int, batched: bool) -> int:
+        """Device bytes of one likelihood: the matrix (CSR, int16 column
+        offsets, row quads of the 32-column products at one union entry of a
+        column id and four values per 1.5 nonzeros or fewer, block-Jacobi
+        blocks), the solver's vectors and Lanczos blocks with the work space's
+        growth margin, and for a batch the stacked copy of the matrix."""
+        vb = 4 if precision == 1 else 8
+        csr = nnz * (4 + vb) + 24 * n
+        col16 = 2 * (nnz + 64)
+        quads = nnz / 1.5 * (4 + 4 * vb) + 6 * n
+        bjac = 48 * n
+        mat = csr + col16 + quads + bjac
+        work = 1.25 * n * (3 * 32 * 8 + 10 * 8) + 16 * n + (1 << 20)
+        return int(mat * (2 if batched else 1) + work)
+
     def footprint(self, req) -> int:
         if isinstance(req, LoglikRequest):
-            ds, _ = self.datasets[req.dataset]
-            n = ds.n
-            vb = 4 if req.precision == 1 else 8
-            nnz = n * self.row_estimate[req.dataset]
-            csr = nnz * (4 + vb) + 24 * n
-            # row quads of the 32-column products: one union entry (a column id
-            # and four values) per 1.5 nonzeros or fewer
-            quads = nnz / 1.5 * (4 + 4 * vb)
-            work = n * (3 * 32 * 8 + 8 * 8 + 16)   # Lanczos blocks + CG vectors + binning scratch
-            return int(csr + quads + work)
+            n = self.datasets[req.dataset][0].n
+            return self._loglik_bytes(n, n * self.row_estimate[req.dataset], req.precision,
+                                      n <= self.batch_max_n)
         return int(_npts(req.xs) * (8 * 3 + 8) + (1 << 16))
 
-    def run_loglik(self, slot: int, req: LoglikRequest):
+    def _assembled(self, slot: int, reqs: List[LoglikRequest], Ks) -> None:
+        """Reports (and returns) the footprint computed from the exact entry
+        counts of the assembled matrices; also raises the data sets' row-length
+        estimates to what the matrices hold."""
+        exact = 0
+        for r, K in zip(reqs, Ks):
+            self.row_estimate[r.dataset] = max(self.row_estimate[r.dataset], K.nnz / K.n * 1.1)
+            exact += self._loglik_bytes(K.n, K.nnz, r.precision, len(reqs) > 1)
+        if self.on_exact_footprint is not None:
+            self.on_exact_footprint(slot, exact)
+        return exact
+
+    def _run(self, slot: int, reqs: List[LoglikRequest]):
         ctx = self.ctxs[slot]
-        ds, yd = self.datasets[req.dataset]
         with self.torch.cuda.stream(self.streams[slot]):
-            K = ctx.assemble(ds, req.theta, req.precision)
+            base = ctx.memory()[0]
+            Ks = []
             try:
-                self.row_estimate[req.dataset] = max(self.row_estimate[req.dataset], K.nnz / K.n * 1.1)
-                r = ctx.loglik(K, yd, raise_on_error=False, **self.opts)
-                r["nnz"] = K.nnz
+                for r in reqs:
+                    ds, _ = self.datasets[r.dataset]
+                    Ks.append(ctx.assemble(ds, r.theta, r.precision))
+                exact = self._assembled(slot, reqs, Ks)
+                if self.hard_budget:
+                    ctx.set_hbm_budget(base + exact)
+                ys = [self.datasets[r.dataset][1] for r in reqs]
+                if len(reqs) == 1:
+                    res = [ctx.loglik(Ks[0], ys[0], raise_on_error=False, **self.opts)]
+                else:
+                    res = ctx.loglik_batch(Ks, ys, raise_on_error=False, **self.opts)
+                for r, K in zip(res, Ks):
+                    r["nnz"] = K.nnz
+                    r["batch"] = len(reqs)
             finally:
-                K.close()
-        return r
+                for K in Ks:
+                    K.close()
+                if self.hard_budget:
+                    ctx.set_hbm_budget(0)
+        return res
+
+    def run_loglik(self, slot: int, req: LoglikRequest):
+        return self._run(slot, [req])[0]
+
+    def run_loglik_batch(self, slot: int, reqs: List[LoglikRequest]):
+        return self._run(slot, reqs)
 
     def run_predict(self, slot: int, reqs: List[PredictRequest]):
         torch = self.torch

@@ -45,3 +45,30 @@ def test_predict_batched_equals_single():
     assert max(c.batch for c in comps) > 1
     for s, c in zip(single, comps):
         assert np.array_equal(s, c.result)
+
+
+def test_small_likelihoods_batched_equal_alone():
+    """On one slot, requests that wait together run as gp_loglik_batch; every
+    result equals the request run alone, bitwise, and the slot's hard budget
+    (from the exact entry count) is never hit."""
+    from paper_2411_05869_amd.serve import GpuBackend, LoglikRequest, Server
+    be = GpuBackend(n_slots=1)
+    base = []
+    for k, n in enumerate([4000, 12000]):
+        s = math.sqrt(1e5 / n)
+        p = gmm_problem(n, 720 + k, 0.0078 * s, 0.02 * s)
+        be.add_dataset(f"d{k}", p.x, p.y, cell=p.cell)
+        base.append(p.theta)
+    rng = np.random.default_rng(10)
+    reqs = [LoglikRequest(f"d{i % 2}", perturb_theta(rng, base[i % 2]), precision=1) for i in range(9)]
+    alone = [be.run_loglik(0, r) for r in reqs]
+    srv = Server(be, hbm_budget=8 << 30, max_loglik_batch=4)
+    comps = srv.run([LoglikRequest(r.dataset, r.theta, r.precision, 0.0) for r in reqs])
+    assert [c.batch for c in comps] == [4] * 8 + [1]
+    assert len(srv.corrections) == 3
+    for a, c in zip(alone, comps):
+        assert c.error is None, c.error
+        assert c.result["status"] == 0, c.result
+        for key in ("loglik", "logdet", "quad", "logdet_se", "cg_iters", "status"):
+            assert a[key] == c.result[key], (key, a[key], c.result[key])
+    print(f"[serve] batches {[c.batch for c in comps]}, corrections {srv.corrections[:3]}, identical to alone")

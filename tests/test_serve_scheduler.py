@@ -1,7 +1,8 @@
 """Scheduling logic of the serving loop, driven by a CPU fake backend:
 completion of every request, FIFO admission, the HBM budget never exceeded,
 rejection of requests that can never fit, overlap across slots, batching of
-prediction requests, and per-request error reporting."""
+prediction requests and of small likelihoods, the exact footprint replacing
+the estimate, and per-request error reporting."""
 import threading
 import time
 
@@ -124,3 +125,74 @@ def test_backend_failure_is_reported_per_request():
     comps = Server(be, 10_000).run([ll(10, 0.0) for _ in range(6)])
     assert "injected failure" in comps[3].error
     assert all(c.error is None for i, c in enumerate(comps) if i != 3)
+
+
+class BatchingBackend(FakeBackend):
+    """Fake backend that batches likelihoods marked small and reports an exact
+    footprint (factor x the estimate) once a request has started."""
+
+    def __init__(self, n_slots, work_s=0.02, exact_factor=1.0):
+        super().__init__(n_slots, work_s)
+        self.exact_factor = exact_factor
+        self.loglik_batches = []
+
+    def can_batch_loglik(self, a, b):
+        return a.theta.get("small", False) and b.theta.get("small", False)
+
+    def _report(self, slot, reqs):
+        if self.on_exact_footprint is not None:
+            self.on_exact_footprint(slot, int(sum(self.footprint(r) for r in reqs) * self.exact_factor))
+
+    def run_loglik(self, slot, req):
+        self._report(slot, [req])
+        return super().run_loglik(slot, req)
+
+    def run_loglik_batch(self, slot, reqs):
+        self._report(slot, reqs)
+        fp = sum(self.footprint(r) for r in reqs)
+        self._enter(fp, tuple(r.rid for r in reqs))
+        self.loglik_batches.append([r.rid for r in reqs])
+        try:
+            time.sleep(self.work_s)
+            return [{"loglik": -float(r.rid), "slot": slot} for r in reqs]
+        finally:
+            self._leave(fp)
+
+
+def test_small_likelihoods_are_batched_and_split():
+    be = BatchingBackend(1, work_s=0.03)
+    big = LoglikRequest("d", {"bytes": 100}, 1, 0.0)
+    small = [LoglikRequest("d", {"bytes": 10, "small": True}, 1, 0.0) for _ in range(6)]
+    srv = Server(be, 1 << 20, max_loglik_batch=4)
+    comps = srv.run([big] + small)
+    assert all(c.error is None for c in comps)
+    assert [c.result["loglik"] for c in comps] == [-float(i) for i in range(7)]
+    assert be.loglik_batches[0] == [1, 2, 3, 4] and be.loglik_batches[1] == [5, 6]
+    assert [c.batch for c in comps] == [1, 4, 4, 4, 4, 2, 2]
+
+
+def _concurrency(comps):
+    ev = sorted([(c.start, 1) for c in comps] + [(c.done, -1) for c in comps], key=lambda e: (e[0], e[1]))
+    cur = best = 0
+    for _, d in ev:
+        cur += d
+        best = max(best, cur)
+    return best
+
+
+def test_exact_footprint_replaces_the_estimate():
+    # estimates of 300 bytes against a budget of 1000 admit three requests at
+    # once; the exact footprint reported after assembly replaces each estimate
+    big = BatchingBackend(4, work_s=0.03, exact_factor=2.0)
+    srv = Server(big, 1000)
+    comps = srv.run([ll(300, 0.0) for _ in range(8)])
+    assert all(c.error is None for c in comps)
+    assert len(srv.corrections) == 8 and all(exact == 2 * est for est, exact in srv.corrections)
+    assert srv.peak_reserved >= 1200 and _concurrency(comps) <= 3
+    # smaller than estimated: the freed reservation admits a fourth request
+    small = BatchingBackend(4, work_s=0.05, exact_factor=0.5)
+    srv = Server(small, 1000)
+    comps = srv.run([ll(300, 0.0) for _ in range(8)])
+    assert all(c.error is None for c in comps)
+    assert all(exact * 2 == est for est, exact in srv.corrections)
+    assert _concurrency(comps) == 4
