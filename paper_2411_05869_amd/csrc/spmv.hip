@@ -525,7 +525,15 @@ static void build_col16(gp_ctx* c, gp_matrix* m) {
   if (m->col16_tried) return;
   m->col16_tried = true;
   ProfScope ps(c, "col16_build");
-  m->col16 = dev_new<int16_t>(c, m->nnz + kCsrPad);
+  // the offsets are a cache: without room for them (allocator or context
+  // budget) the products keep reading the int32 column ids
+  try {
+    m->col16 = dev_new<int16_t>(c, m->nnz + kCsrPad);
+  } catch (const Error& e) {
+    if (e.st != GP_ENOMEM) throw;
+    m->col16 = nullptr;
+    return;
+  }
   GPS_HIP(hipMemsetAsync(c->err_flag, 0, sizeof(int), c->stream));
   hipLaunchKernelGGL(k_col16, dim3(grid_for(m->n * kG, kThreads)), dim3(kThreads), 0, c->stream, m->n, m->row_ptr,
                      m->gskip, m->col, m->col16, c->err_flag);

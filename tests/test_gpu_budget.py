@@ -85,3 +85,22 @@ def test_predictor_over_budget():
     assert torch.equal(a.predict(pa, xs), b.predict(pb, xs))
     print(f"[budget predictor] in use {a.memory()[0]} vs fresh {b.memory()[0]}")
     assert a.memory()[0] == b.memory()[0]
+
+
+def test_int16_offsets_skipped_without_room():
+    """The int16 column offsets are a cache of the one-column product: when
+    the budget leaves no room for them the product reads the int32 column ids
+    (same sums, bitwise) instead of failing."""
+    p = config1()
+    a, b = _ctx(), _ctx()
+    ds_a, ds_b = a.dataset(dev(p.x), cell=p.cell), b.dataset(dev(p.x), cell=p.cell)
+    Kw, Ka, Kb = a.assemble(ds_a, p.theta, 1), a.assemble(ds_a, p.theta, 1), b.assemble(ds_b, p.theta, 1)
+    x = dev(np.random.default_rng(2).standard_normal(p.n))
+    a.matvec(Kw, x)                                  # grows the product's work space
+    a.set_hbm_budget(a.memory()[0] + (8 << 10))     # less than the 2 (nnz + 64) bytes of offsets
+    ya = a.matvec(Ka, x)
+    a.set_hbm_budget(0)
+    yb = b.matvec(Kb, x)
+    assert Ka.layout()["col16"] == 0 and Kb.layout()["col16"] == 1
+    assert np.array_equal(ya.cpu().numpy(), yb.cpu().numpy())
+    print("[budget col16] product without the offsets equals the product with them")
