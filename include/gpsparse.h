@@ -419,7 +419,9 @@ GP_API gp_status gp_predictor_destroy(gp_ctx* ctx, gp_predictor* p);
 /* gp_predict: posterior mean m(x*) = sum_q C_y(x*, x_q) alpha_q (no nugget)
  * for m test points (xstar_dev: m x d row-major float64) into mean_dev (m
  * float64).  The cross-covariance is evaluated and applied in one pass and
- * never stored.  GP_MIXED evaluates the cross-covariance in float32.  Test
+ * never stored.  GP_MIXED evaluates each cross-covariance value in float64
+ * (as the matrix's values are), rounds it to float32 and multiplies it by a
+ * float32 copy of alpha in float32; the sum is float64.  Test
  * coordinates are device data and are not checked: a non-finite test point
  * passes no support test and gets mean 0.
  * Errors: GP_EINVAL (m < 0, NULL buffers, unknown precision), GP_EDEVICE. */
