@@ -415,6 +415,8 @@ def main():
     ap.add_argument("--no-var", action="store_true")
     ap.add_argument("--no-mcmc", action="store_true")
     ap.add_argument("--var-points", type=int, default=64)
+    ap.add_argument("--isolated-steps", type=int, default=2,
+                    help="mixed steps with the log det after the solve (per-kernel rooflines without overlap)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="copy 1 GiB device-to-device first (reference dispatch for HBM counters)")
     ap.add_argument("--summarize-pmc", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "COMMAND"),
@@ -504,6 +506,13 @@ def main():
     # the same mixed step with 50 Lanczos steps, for comparison with the converged depth
     o50 = dict(opts, n_lanczos=50)
     dt_50, res_50, _ = timed(MIXED, 2, 0, o50)
+    # the same mixed step with the log det after the solve on one stream: each
+    # kernel then runs alone, and its launch times give its own roofline
+    prof_ser, dt_ser = None, None
+    if args.isolated_steps > 0:
+        ctx.set_concurrency(False)
+        dt_ser, _, prof_ser = timed(MIXED, args.isolated_steps, 0)
+        ctx.set_concurrency(True)
     asm_wall_m = assemble_wall(MIXED)
     asm_wall_d = assemble_wall(FP64)
     r_m, info_m = res_m[-1]
@@ -523,8 +532,8 @@ def main():
     models = {"spmv_f32val_f64": (spmv_format_bytes(n, lo, 4), spmv_bytes(n, nnz, 4, 8)),
               "spmm": (spmm_format_bytes(n, lo, 4), spmm_bytes(n, nnz, 4, 32, 8))}
 
-    def roofline(name):
-        cnt, tot = prof_m[name]
+    def roofline(name, prof=None):
+        cnt, tot = (prof or prof_m)[name]
         avg_s = tot / cnt / 1e3
         b, bcsr = models[name]
         achieved = b / avg_s / 1e9
@@ -539,6 +548,11 @@ def main():
     dom = max(present, key=lambda k: prof_m[k][1])
     roof = roofline(dom)
     others = {k: roofline(k) for k in present if k != dom}
+    isolated = None
+    if prof_ser is not None:
+        isolated = dict(ms_per_step=round(1e3 * dt_ser / args.isolated_steps, 2),
+                        note="log det after the solve on one stream, kernels alone",
+                        **{k: roofline(k, prof_ser) for k in models if k in prof_ser})
     asm_b = nnz * 8.1
     others["assembly"] = dict(bound="hbm", achieved=round(asm_b / (asm_ms_m / 1e3) / 1e9, 1), peak=HBM_PEAK_GBS,
                               unit="GB/s", frac=round(asm_b / (asm_ms_m / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
@@ -567,6 +581,7 @@ def main():
                binning_ms=round(1e3 * t_bin, 2),
                roofline=roof,
                roofline_other=others,
+               roofline_isolated=isolated,
                hbm_copy_gbs=round(copy_gbs, 1),
                matrix_layout=lo,
                kernels_ms_per_step={k: round(v[1] / args.steps, 3) for k, v in sorted(prof_m.items(),

@@ -101,6 +101,14 @@ GP_API gp_status gp_ctx_memory(const gp_ctx* ctx, size_t* bytes_in_use, size_t* 
  * what it had allocated.  0 = no budget (the default).  Memory already held
  * is kept even if it exceeds a new, smaller budget. */
 GP_API gp_status gp_ctx_set_hbm_budget(gp_ctx* ctx, size_t bytes);
+/* Concurrency of one likelihood (Sec. 3.3: the log det and the solve are
+ * independent tasks): with on = 1 (the default) gp_loglik, gp_loglik_async
+ * and gp_loglik_batch enqueue the SLQ log det on a second stream of the
+ * context, ordered after the call's earlier work and joined before its
+ * result, so its launches run beside the solver's; with on = 0 the log det
+ * runs after the solve on the context's stream.  The results are the same
+ * bitwise either way (the same kernels in the same order per task). */
+GP_API gp_status gp_ctx_set_concurrency(gp_ctx* ctx, int32_t on);
 
 /* Per-kernel timing: while enabled, the library brackets its kernel launches
  * with HIP events on the context's stream.  gp_profile_enable clears the

@@ -83,7 +83,7 @@ class CVarResult(C.Structure):
 
 EXPORTS = [
     "gp_ctx_create", "gp_ctx_destroy", "gp_ctx_set_stream", "gp_last_error", "gp_ctx_memory",
-    "gp_ctx_set_hbm_budget",
+    "gp_ctx_set_hbm_budget", "gp_ctx_set_concurrency",
     "gp_dataset_create", "gp_dataset_destroy", "gp_dataset_info", "gp_dataset_permutation",
     "gp_assemble", "gp_matrix_destroy", "gp_matrix_info", "gp_matrix_export_csr", "gp_matvec",
     "gp_matvec_noalloc", "gp_matrix_layout", "gp_predict_batch", "gp_loglik_async",
@@ -114,6 +114,7 @@ def lib():
     L.gp_last_error.restype = C.c_char_p
     L.gp_ctx_memory.argtypes = [P, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]
     L.gp_ctx_set_hbm_budget.argtypes = [P, C.c_size_t]
+    L.gp_ctx_set_concurrency.argtypes = [P, C.c_int32]
     L.gp_dataset_create.argtypes = [P, I64, I32, P, C.POINTER(D), C.POINTER(P)]
     L.gp_dataset_destroy.argtypes = [P, P]
     L.gp_dataset_info.argtypes = [P, C.POINTER(I64), C.POINTER(I32), C.POINTER(I64), C.POINTER(D)]
@@ -297,6 +298,10 @@ class Context:
         a, b = C.c_size_t(), C.c_size_t()
         self._L.gp_ctx_memory(self._h, C.byref(a), C.byref(b))
         return a.value, b.value
+
+    def set_concurrency(self, on: bool = True):
+        """Whether a likelihood's log det runs on a second stream beside the solve."""
+        self._check(self._L.gp_ctx_set_concurrency(self._h, 1 if on else 0), "gp_ctx_set_concurrency")
 
     def set_hbm_budget(self, nbytes: int = 0):
         """Cap the device bytes this context may hold (0: no cap); allocations past

@@ -16,6 +16,7 @@ void predict_batch(gp_ctx* c, int32_t nreq, const gp_predictor* const* preds, co
 
 // ------------------------------------------------------------------ memory
 void* dev_alloc(gp_ctx* c, size_t bytes) {
+  if (c->alloc_locked) throw Error{GP_EDEVICE, "internal: device allocation while enqueueing on the side stream"};
   if (bytes == 0) bytes = 16;
   if (c->budget && bytes > c->budget - std::min(c->budget, c->in_use))
     throw Error{GP_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes exceeds the context's HBM budget (" +
@@ -87,6 +88,24 @@ void record_aux(gp_ctx* c) {
 }
 
 void wait_aux(gp_ctx* c) { GPS_HIP(hipEventSynchronize(c->ev_aux)); }
+
+void fork_side(gp_ctx* c) {
+  if (!c->side) {
+    GPS_HIP(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
+    GPS_HIP(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+    GPS_HIP(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
+  }
+  GPS_HIP(hipEventRecord(c->ev_fork, c->stream));
+  GPS_HIP(hipStreamWaitEvent(c->side, c->ev_fork, 0));
+  c->side_pending = true;
+}
+
+void join_side(gp_ctx* c) {
+  if (!c->side_pending) return;
+  GPS_HIP(hipEventRecord(c->ev_join, c->side));
+  GPS_HIP(hipStreamWaitEvent(c->stream, c->ev_join, 0));
+  c->side_pending = false;
+}
 
 void h2d_async(gp_ctx* c, void* dst, const void* src, size_t bytes) {
   GPS_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, c->stream));
@@ -252,6 +271,12 @@ gp_status gp_ctx_destroy(gp_ctx* c) {
     for (hipEvent_t e : c->evpool) (void)hipEventDestroy(e);
     if (c->ev_aux) (void)hipEventDestroy(c->ev_aux);
     c->evpool.clear();
+    if (c->side) {
+      (void)hipStreamSynchronize(c->side);
+      (void)hipStreamDestroy(c->side);
+      (void)hipEventDestroy(c->ev_fork);
+      (void)hipEventDestroy(c->ev_join);
+    }
   });
   delete c;
   return st;
@@ -300,6 +325,12 @@ gp_status gp_profile_read(gp_ctx* c, int32_t max_entries, gp_profile_entry* out,
 }
 
 const char* gp_last_error(const gp_ctx* c) { return c ? c->err.c_str() : "context is NULL"; }
+
+gp_status gp_ctx_set_concurrency(gp_ctx* c, int32_t on) {
+  if (!c || (on != 0 && on != 1)) return GP_EINVAL;
+  c->concurrent = on == 1;
+  return GP_OK;
+}
 
 gp_status gp_ctx_set_hbm_budget(gp_ctx* c, size_t bytes) {
   if (!c) return GP_EINVAL;
@@ -457,6 +488,24 @@ static gp_status loglik_common(gp_ctx* c, const gp_matrix* m, const double* y, c
     gps::permute_to_binned<double>(c, m->ds, 1, y, yb);
     // the preconditioner is cached in the matrix object on first use
     gp_matrix* mm = const_cast<gp_matrix*>(m);
+    // The SLQ log det does not depend on the solve: it is enqueued first on
+    // the side stream (its device-driven form, nothing read back until the
+    // end) and runs beside the solver's launches; the solve's host checks
+    // wait on the main stream only.
+    const bool slq = with_logdet && (o.logdet_mode == GP_LOGDET_SLQ || o.logdet_mode == GP_LOGDET_SLQ_REORTH);
+    const bool reorth = o.logdet_mode == GP_LOGDET_SLQ_REORTH;
+    gps::JoinGuard join{c};
+    gps::DeviceLogdet* dld = nullptr;
+    if (slq) {
+      gps::build_product_caches(c, mm);
+      gps::slq_reserve(c, m, o.n_probes, o.n_lanczos, reorth);
+      dld = static_cast<gps::DeviceLogdet*>(gps::workspace(c, 126, sizeof(gps::DeviceLogdet)));
+      if (c->concurrent) {
+        gps::fork_side(c);
+        gps::SideScope side(c);
+        gps::slq_logdet_device(c, m, o.seed, o.n_probes, o.n_lanczos, reorth, dld);
+      }
+    }
     gps::SolveResult sr;
     if (o.solver != GP_SOLVER_MINRES) {
       sr = gps::pcg_solve(c, mm, yb, xb, o.rtol, o.max_iter, o.precond);
@@ -475,11 +524,20 @@ static gp_status loglik_common(gp_ctx* c, const gp_matrix* m, const double* y, c
     GPS_REQUIRE(std::isfinite(sr.quad), GP_EINVAL, "y holds non-finite values");
     solve_status = sr.st;
     if (alpha) gps::permute_to_orig<double>(c, m->ds, 1, xb, alpha);
-    if (with_logdet && o.logdet_mode != GP_LOGDET_NONE) {
-      const gps::LogdetResult lr =
-          o.logdet_mode == GP_LOGDET_EXACT
-              ? gps::exact_logdet(c, m, o.seed)
-              : gps::slq_logdet(c, m, o.seed, o.n_probes, o.n_lanczos, o.logdet_mode == GP_LOGDET_SLQ_REORTH);
+    if (slq) {
+      if (c->concurrent)
+        gps::join_side(c);
+      else
+        gps::slq_logdet_device(c, m, o.seed, o.n_probes, o.n_lanczos, reorth, dld);
+      gps::DeviceLogdet* h = static_cast<gps::DeviceLogdet*>(gps::pinned(c, sizeof(gps::DeviceLogdet)));
+      GPS_HIP(hipMemcpyAsync(h, dld, sizeof(gps::DeviceLogdet), hipMemcpyDeviceToHost, c->stream));
+      gps::sync(c);
+      out->logdet = h->logdet;
+      out->logdet_se = h->se;
+      out->lanczos_steps = h->steps;
+      if (solve_status == GP_OK) solve_status = static_cast<gp_status>(h->status);
+    } else if (with_logdet && o.logdet_mode == GP_LOGDET_EXACT) {
+      const gps::LogdetResult lr = gps::exact_logdet(c, m, o.seed);
       out->logdet = lr.logdet;
       out->logdet_se = lr.se;
       out->lanczos_steps = lr.steps;
@@ -556,13 +614,23 @@ gp_status gp_loglik_async(gp_ctx* c, const gp_matrix* m, const double* y, const 
     double* yb = static_cast<double*>(gps::workspace(c, 44, sizeof(double) * n));
     double* xb = static_cast<double*>(gps::workspace(c, 45, sizeof(double) * n));
     gps::permute_to_binned<double>(c, m->ds, 1, y, yb);
+    // the log det on the side stream beside the solve (joined before the result)
+    const bool with_logdet = o.logdet_mode != GP_LOGDET_NONE;
+    const bool reorth = o.logdet_mode == GP_LOGDET_SLQ_REORTH;
+    gps::DeviceLogdet* ld = static_cast<gps::DeviceLogdet*>(gps::workspace(c, 124, sizeof(gps::DeviceLogdet)));
+    gps::JoinGuard join{c};
+    if (with_logdet && c->concurrent) {
+      gps::slq_reserve(c, m, o.n_probes, o.n_lanczos, reorth);
+      gps::fork_side(c);
+      gps::SideScope side(c);
+      gps::slq_logdet_device(c, m, o.seed, o.n_probes, o.n_lanczos, reorth, ld);
+    }
     gps::DeviceSolve sv{};
     gps::pcg_solve_device(c, mm, yb, xb, o.rtol, o.max_iter, o.precond, &sv);
     if (alpha) gps::permute_to_orig<double>(c, m->ds, 1, xb, alpha);
-    const bool with_logdet = o.logdet_mode != GP_LOGDET_NONE;
-    gps::DeviceLogdet* ld = static_cast<gps::DeviceLogdet*>(gps::workspace(c, 124, sizeof(gps::DeviceLogdet)));
-    if (with_logdet)
-      gps::slq_logdet_device(c, m, o.seed, o.n_probes, o.n_lanczos, o.logdet_mode == GP_LOGDET_SLQ_REORTH, ld);
+    if (with_logdet && !c->concurrent)
+      gps::slq_logdet_device(c, m, o.seed, o.n_probes, o.n_lanczos, reorth, ld);
+    gps::join_side(c);
     // (n/2) log(2 pi) formed on the host as gp_loglik forms it
     const double half_n_log2pi = 0.5 * static_cast<double>(n) * std::log(2.0 * M_PI);
     hipLaunchKernelGGL(k_loglik_result, dim3(1), dim3(64), 0, c->stream, sv, ld, with_logdet ? 1 : 0, nullptr,
@@ -625,22 +693,29 @@ gp_status gp_loglik_batch(gp_ctx* c, int32_t nreq, const gp_matrix* const* K, co
       GPS_HIP(hipMemcpyAsync(perm + off[r], K[r]->ds->perm, sizeof(int32_t) * K[r]->n, hipMemcpyDeviceToDevice,
                              c->stream));
     }
+    // the log dets on the side stream beside the solves
+    const bool with_logdet = o.logdet_mode == GP_LOGDET_SLQ;
+    gps::DeviceLogdet* ld = static_cast<gps::DeviceLogdet*>(gps::workspace(c, 133, sizeof(gps::DeviceLogdet) * R));
+    gps::JoinGuard join{c};
+    gps::SlqBatch b;
+    b.R = R;
+    b.off = doff;
+    b.inv0 = dinv;
+    b.perm = perm;
+    b.nmax = nmax;
+    if (with_logdet && c->concurrent) {
+      gps::slq_reserve(c, S.get(), o.n_probes, o.n_lanczos, false, R);
+      gps::fork_side(c);
+      gps::SideScope side(c);
+      gps::slq_logdet_batch(c, S.get(), o.seed, o.n_probes, o.n_lanczos, b, ld);
+    }
     gps::DeviceSolve sv{};
     gps::pcg_solve_batch(c, S.get(), yb, xb, o.rtol, o.max_iter, o.precond, R, doff, nmax, &sv);
     if (alpha)
       for (int r = 0; r < R; ++r)
         if (alpha[r]) gps::permute_to_orig<double>(c, K[r]->ds, 1, xb + off[r], alpha[r]);
-    const bool with_logdet = o.logdet_mode == GP_LOGDET_SLQ;
-    gps::DeviceLogdet* ld = static_cast<gps::DeviceLogdet*>(gps::workspace(c, 133, sizeof(gps::DeviceLogdet) * R));
-    if (with_logdet) {
-      gps::SlqBatch b;
-      b.R = R;
-      b.off = doff;
-      b.inv0 = dinv;
-      b.perm = perm;
-      b.nmax = nmax;
-      gps::slq_logdet_batch(c, S.get(), o.seed, o.n_probes, o.n_lanczos, b, ld);
-    }
+    if (with_logdet && !c->concurrent) gps::slq_logdet_batch(c, S.get(), o.seed, o.n_probes, o.n_lanczos, b, ld);
+    gps::join_side(c);
     gp_loglik_result* dres = static_cast<gp_loglik_result*>(gps::workspace(c, 134, sizeof(gp_loglik_result) * R));
     hipLaunchKernelGGL(k_loglik_result, dim3(1), dim3(64), 0, c->stream, sv, ld, with_logdet ? 1 : 0, dhalf, 0.0, R,
                        dres);

@@ -83,6 +83,13 @@ struct gp_ctx {
   std::vector<ProfRec> prof;
   std::vector<hipEvent_t> evpool;
   size_t evnext = 0;
+  // second stream for independent work of one call (the log det beside the
+  // solve), created on first use; ordered against the main stream by events
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  bool side_pending = false;  // work was forked to the side stream and not joined yet
+  bool alloc_locked = false;  // set while work is enqueued on the side stream
+  bool concurrent = true;     // the log det of a likelihood on the side stream
 };
 
 struct gp_dataset {
@@ -232,6 +239,38 @@ void h2d_async(gp_ctx* c, void* dst, const void* src, size_t bytes);
 void record_aux(gp_ctx* c);
 void wait_aux(gp_ctx* c);
 void sync(gp_ctx* c);
+// Side stream: fork_side() orders the side stream after everything enqueued
+// on the main stream so far; while a SideScope lives, the context's stream is
+// the side stream and device allocations are refused (memory the side stream
+// uses must be allocated before the fork, in the main stream's order);
+// join_side() orders the main stream after the side stream's work.
+void fork_side(gp_ctx* c);
+void join_side(gp_ctx* c);
+struct SideScope {
+  gp_ctx* c;
+  hipStream_t main;
+  explicit SideScope(gp_ctx* c_) : c(c_), main(c_->stream) {
+    c->stream = c->side;
+    c->alloc_locked = true;
+  }
+  ~SideScope() {
+    c->stream = main;
+    c->alloc_locked = false;
+  }
+  SideScope(const SideScope&) = delete;
+  SideScope& operator=(const SideScope&) = delete;
+};
+// joins the side stream when it goes out of scope (also on an exception)
+struct JoinGuard {
+  gp_ctx* c;
+  ~JoinGuard() {
+    if (c->side_pending) {
+      (void)hipEventRecord(c->ev_join, c->side);
+      (void)hipStreamWaitEvent(c->stream, c->ev_join, 0);
+      c->side_pending = false;
+    }
+  }
+};
 
 template <typename T>
 T* dev_new(gp_ctx* c, size_t count) {
@@ -307,6 +346,8 @@ void spmv_f64(gp_ctx* c, const gp_matrix* m, const double* x, double* y, const i
 // builds the caches the products read (int16 offsets, row quads) now, with
 // host synchronisations, so that later products need none
 void build_product_caches(gp_ctx* c, gp_matrix* m);
+// allocates the work space of a 32-column product of m
+void spmm_reserve(gp_ctx* c, const gp_matrix* m);
 // Block-diagonal stack of R assembled matrices of one precision, whose product
 // caches (and block-Jacobi blocks, when block_jacobi) are built: a new matrix
 // with no dataset, row r of problem q at stacked row (rows of problems < q) + r.
@@ -414,6 +455,10 @@ struct DeviceLogdet {
 // writes the SLQ estimate into out (device memory)
 void slq_logdet_device(gp_ctx* c, const gp_matrix* m, uint64_t seed, int n_probes, int n_steps, bool reorth,
                        DeviceLogdet* out);
+// allocates (in the main stream's order) the work space slq_logdet_device and
+// slq_logdet_batch (R problems of n stacked rows) will use, so that they can
+// be enqueued on the side stream without allocating
+void slq_reserve(gp_ctx* c, const gp_matrix* m, int n_probes, int n_steps, bool reorth, int R = 1);
 // R problems stacked along the rows of m, each estimated as slq_logdet_device
 // would estimate it alone (same probes, keyed by the problem's own original
 // indices); out[r] per problem

@@ -1490,6 +1490,51 @@ __global__ void __launch_bounds__(kThreads) k_lz_colscale(int64_t n, int k, int 
 
 }  // namespace
 
+// The work space of an SLQ estimate (R problems stacked in n rows); the
+// device-driven form also keeps its Jacobi sums and per-probe results there.
+constexpr int kRoBlocks = 256;
+
+template <typename T>
+struct SlqBufs {
+  double *Qall = nullptr, *ropart = nullptr, *H = nullptr;
+  T *V, *Vp, *W, *sc;
+  double *part, *Ta, *Tb, *gam;
+  LzState* st;
+  int* bad;
+  double *djac = nullptr, *jpart = nullptr, *gam_all = nullptr;
+  int* steps_all = nullptr;
+};
+
+template <typename T>
+static SlqBufs<T> slq_bufs(gp_ctx* c, int64_t n, int n_probes, int n_steps, bool reorth, int R, bool dev) {
+  const int ld = 32;
+  const int64_t tstride = static_cast<int64_t>(32) * n_steps;
+  SlqBufs<T> b;
+  if (reorth) {
+    // full re-orthogonalisation keeps every normalised Lanczos block
+    b.Qall = static_cast<double*>(workspace(c, 57, sizeof(double) * n * ld * n_steps));
+    b.ropart = static_cast<double*>(workspace(c, 58, sizeof(double) * 32 * kRoBlocks * n_steps));
+    b.H = static_cast<double*>(workspace(c, 59, sizeof(double) * 32 * n_steps));
+  }
+  b.V = static_cast<T*>(workspace(c, 30, sizeof(T) * n * ld));
+  b.Vp = static_cast<T*>(workspace(c, 31, sizeof(T) * n * ld));
+  b.W = static_cast<T*>(workspace(c, 32, sizeof(T) * n * ld));
+  b.sc = static_cast<T*>(workspace(c, 33, sizeof(T) * n));
+  b.part = static_cast<double*>(workspace(c, 34, sizeof(double) * 32 * kRedBlocks * R));
+  b.st = static_cast<LzState*>(workspace(c, 35, sizeof(LzState) * R));
+  b.Ta = static_cast<double*>(workspace(c, 36, sizeof(double) * tstride * R));
+  b.Tb = static_cast<double*>(workspace(c, 37, sizeof(double) * tstride * R));
+  b.gam = static_cast<double*>(workspace(c, 38, sizeof(double) * 32 * R));
+  b.bad = static_cast<int*>(workspace(c, 39, sizeof(int) * std::max(R, 2)));
+  if (dev) {
+    b.djac = static_cast<double*>(workspace(c, 46, sizeof(double) * std::max(R, 2)));
+    b.jpart = static_cast<double*>(workspace(c, 47, sizeof(double) * kRedBlocks * R));
+    b.gam_all = static_cast<double*>(workspace(c, 48, sizeof(double) * n_probes * R));
+    b.steps_all = static_cast<int*>(workspace(c, 49, sizeof(int) * n_probes * R));
+  }
+  return b;
+}
+
 template <typename T>
 static LogdetResult slq_impl(gp_ctx* c, const gp_matrix* m, uint64_t seed, int n_probes, int n_steps, double tol,
                              bool reorth, DeviceLogdet* dev_out = nullptr, const SlqBatch* bt = nullptr) {
@@ -1508,24 +1553,15 @@ static LogdetResult slq_impl(gp_ctx* c, const gp_matrix* m, uint64_t seed, int n
   }
   const int64_t tstride = static_cast<int64_t>(32) * n_steps;
   const int32_t* perm = bt ? bt->perm : m->ds->perm;
-  // full re-orthogonalisation keeps every normalised Lanczos block
-  double* Qall = reorth ? static_cast<double*>(workspace(c, 57, sizeof(double) * n * ld * n_steps)) : nullptr;
-  constexpr int kRoBlocks = 256;
-  double* ropart = reorth ? static_cast<double*>(workspace(c, 58, sizeof(double) * 32 * kRoBlocks * n_steps)) : nullptr;
-  double* H = reorth ? static_cast<double*>(workspace(c, 59, sizeof(double) * 32 * n_steps)) : nullptr;
-  T* V = static_cast<T*>(workspace(c, 30, sizeof(T) * n * ld));
-  T* Vp = static_cast<T*>(workspace(c, 31, sizeof(T) * n * ld));
-  T* W = static_cast<T*>(workspace(c, 32, sizeof(T) * n * ld));
-  T* sc = static_cast<T*>(workspace(c, 33, sizeof(T) * n));
-  double* part = static_cast<double*>(workspace(c, 34, sizeof(double) * 32 * kRedBlocks * R));
-  LzState* st = static_cast<LzState*>(workspace(c, 35, sizeof(LzState) * R));
-  double* Ta = static_cast<double*>(workspace(c, 36, sizeof(double) * tstride * R));
-  double* Tb = static_cast<double*>(workspace(c, 37, sizeof(double) * tstride * R));
-  double* gam = static_cast<double*>(workspace(c, 38, sizeof(double) * 32 * R));
-  int* bad = static_cast<int*>(workspace(c, 39, sizeof(int) * std::max(R, 2)));
+  const bool dev = dev_out != nullptr;
+  const SlqBufs<T> bf = slq_bufs<T>(c, n, n_probes, n_steps, reorth, R, dev);
+  double *Qall = bf.Qall, *ropart = bf.ropart, *H = bf.H;
+  T *V = bf.V, *Vp = bf.Vp, *W = bf.W, *sc = bf.sc;
+  double *part = bf.part, *Ta = bf.Ta, *Tb = bf.Tb, *gam = bf.gam;
+  LzState* st = bf.st;
+  int* bad = bf.bad;
   hipLaunchKernelGGL((k_scale_vec<T>), dim3(grid_for(n, kThreads)), dim3(kThreads), 0, c->stream, n, m->diag, sc);
   check_launch("slq scale");
-  const bool dev = dev_out != nullptr;
   double jac = 0.0;
   double* djac = nullptr;
   double* gam_all = nullptr;
@@ -1533,12 +1569,12 @@ static LogdetResult slq_impl(gp_ctx* c, const gp_matrix* m, uint64_t seed, int n
   int* bad_all = nullptr;
   if (dev) {
     // Jacobi part, probe results and failure flags stay on the device
-    djac = static_cast<double*>(workspace(c, 46, sizeof(double) * std::max(R, 2)));
-    double* jpart = static_cast<double*>(workspace(c, 47, sizeof(double) * kRedBlocks * R));
-    hipLaunchKernelGGL(k_logsum_part, dim3(kRedBlocks, Ry), dim3(kThreads), 0, c->stream, nrow, m->diag, jpart, gj);
-    hipLaunchKernelGGL(k_sum_part, dim3(1, Ry), dim3(kThreads), 0, c->stream, jpart, kRedBlocks, djac, gj);
-    gam_all = static_cast<double*>(workspace(c, 48, sizeof(double) * n_probes * R));
-    steps_all = static_cast<int*>(workspace(c, 49, sizeof(int) * n_probes * R));
+    djac = bf.djac;
+    hipLaunchKernelGGL(k_logsum_part, dim3(kRedBlocks, Ry), dim3(kThreads), 0, c->stream, nrow, m->diag, bf.jpart,
+                       gj);
+    hipLaunchKernelGGL(k_sum_part, dim3(1, Ry), dim3(kThreads), 0, c->stream, bf.jpart, kRedBlocks, djac, gj);
+    gam_all = bf.gam_all;
+    steps_all = bf.steps_all;
     bad_all = bad;
     GPS_HIP(hipMemsetAsync(bad_all, 0, sizeof(int) * R, c->stream));
   } else {
@@ -1658,6 +1694,11 @@ LogdetResult slq_logdet(gp_ctx* c, const gp_matrix* m, uint64_t seed, int n_prob
 void slq_logdet_device(gp_ctx* c, const gp_matrix* m, uint64_t seed, int n_probes, int n_steps, bool reorth,
                        DeviceLogdet* out) {
   slq_impl<double>(c, m, seed, n_probes, n_steps, 1e-10, reorth, out);
+}
+
+void slq_reserve(gp_ctx* c, const gp_matrix* m, int n_probes, int n_steps, bool reorth, int R) {
+  (void)slq_bufs<double>(c, m->n, n_probes, n_steps, reorth, R, true);
+  spmm_reserve(c, m);
 }
 
 void slq_logdet_batch(gp_ctx* c, const gp_matrix* m, uint64_t seed, int n_probes, int n_steps, const SlqBatch& b,

@@ -1186,6 +1186,13 @@ static void build_quads(gp_ctx* c, gp_matrix* m) {
   }
 }
 
+// the work space of a 32-column product (partial blocks of multi-piece super-tiles)
+static size_t spmm_part_bytes(const gp_matrix* m) { return sizeof(double) * kSuperRows * 32 * m->npieces; }
+
+void spmm_reserve(gp_ctx* c, const gp_matrix* m) {
+  if (m->npieces > 0) (void)workspace(c, 55, spmm_part_bytes(m));
+}
+
 template <typename T>
 void spmm(gp_ctx* c, const gp_matrix* m, int k, int ld, const T* X, T* Y, const T* scale, const double* colscale) {
   static_assert(std::is_same<T, double>::value, "the products take float64 vectors");
@@ -1196,7 +1203,7 @@ void spmm(gp_ctx* c, const gp_matrix* m, int k, int ld, const T* X, T* Y, const 
   if (vec) build_quads(c, mm);
   ProfScope ps(c, "spmm");
   // partial blocks of the pieces of multi-piece super-tiles
-  T* part = m->npieces > 0 ? static_cast<T*>(workspace(c, 55, sizeof(T) * kSuperRows * 32 * m->npieces)) : nullptr;
+  T* part = m->npieces > 0 ? static_cast<T*>(workspace(c, 55, spmm_part_bytes(m))) : nullptr;
   const unsigned nb_short = round_up8(grid_for((m->n + kRowsPerWave - 1) / kRowsPerWave, kThreads / kWave));
   const unsigned nb = nb_short + static_cast<unsigned>(m->n_long);
   auto go = [&](auto vt, auto sc) {

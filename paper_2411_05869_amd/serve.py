@@ -140,6 +140,7 @@ class Server:
                 reserved += int(nbytes) - slot_fp[slot]
                 slot_fp[slot] = int(nbytes)
                 self.peak_reserved = max(self.peak_reserved, reserved)
+                cv.notify_all()   # a smaller reservation may admit the next request now
 
         self.backend.on_exact_footprint = on_exact
 
