@@ -398,6 +398,38 @@ def core_legs(ctx, ds, p, y, xs, opts, reps=2):
     return res
 
 
+def assembly_only(p, x, reps):
+    """Assembles the workload reps times in each precision (after one warm-up
+    call) with the library's per-kernel event timing; prints one JSON line."""
+    import torch
+
+    from paper_2411_05869_amd import FP64, MIXED, Context
+    ctx = Context()
+    ds = ctx.dataset(x, cell=p.cell)
+    out = dict(workload=p.name, n=p.n, reps=reps)
+    for name, prec in (("mixed", MIXED), ("fp64", FP64)):
+        ctx.assemble(ds, p.theta, prec).close()
+        torch.cuda.synchronize()
+        ctx.profile(True)
+        t0 = time.perf_counter()
+        for i in range(reps):
+            K = ctx.assemble(ds, p.theta, prec)
+            nnz = K.nnz
+            K.close()
+            log(f"assembly {i + 1}/{reps} {name} done")
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / reps
+        prof = ctx.profile_read()
+        ctx.profile(False)
+        kern = {k: round(v[1] / reps, 4) for k, v in sorted(prof.items(), key=lambda kv: -kv[1][1])}
+        kms = sum(kern.values())
+        vb = 4 if prec == MIXED else 8
+        b = nnz * (4 + vb) + (p.n + 1) * 8
+        out[name] = dict(nnz=nnz, wall_ms=round(1e3 * wall, 3), kernels_ms=round(kms, 3), kernels=kern,
+                         output_bytes=b, frac_of_8tbs=round(b / (kms / 1e3) / 1e9 / HBM_PEAK_GBS, 4))
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -419,6 +451,8 @@ def main():
                     help="mixed steps with the log det after the solve (per-kernel rooflines without overlap)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="copy 1 GiB device-to-device first (reference dispatch for HBM counters)")
+    ap.add_argument("--assembly-only", type=int, default=0, metavar="REPS",
+                    help="only assemble the workload REPS times per precision (profiling runs) and print the times")
     ap.add_argument("--summarize-pmc", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "COMMAND"),
                     help="write the SpMV traffic summary from two rocprofv3 --pmc output folders and exit")
     args = ap.parse_args()
@@ -449,6 +483,9 @@ def main():
     log(f"measured 1 GiB device copy: {copy_gbs:.0f} GB/s (read + write)")
     x = torch.tensor(p.x, device=dev)
     y = torch.tensor(p.y, device=dev)
+    if args.assembly_only:
+        assembly_only(p, x, args.assembly_only)
+        return
     xs_np = config5_requests(1, seed=5, m_lo=10000, m_hi=10000)[0]
     xs = torch.tensor(xs_np, device=dev)
     ctx = Context()

@@ -9,12 +9,12 @@
 //     columns in ascending order;
 //   * group pairs: rows with a group mask M take every point of
 //     U_M = {q : M(q) & M != 0}, a sorted list shared by all rows with mask M.
-// Rows with no group bit (most rows) hold only local entries and are done one
-// row per lane.  Rows with a group bit are done one row per wave: their
-// local-only entries L'(p) = local hits with no shared group are merged with
-// U_M by rank (binary search), so each row's columns come out sorted and
-// unique.  Count and fill run the same candidate loops; the fill checks that
-// it wrote exactly the counted number of entries.
+// A row with group mask M (M = 0 for most rows) holds first the |U_M| group
+// entries (ascending), then its local-only entries L'(p) = {q : u0^2 < 1,
+// M(q) & M = 0} (ascending; all local entries when M = 0).  The local parts
+// are found one row per lane; the group parts are written tile by tile for
+// the rows sharing a mask.  Count and fill run the same candidate loops; the
+// fill checks that it wrote exactly the counted number of entries.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -51,9 +51,6 @@ struct AsmArgs {
   // counts / outputs
   int32_t* counts;          // n
   int32_t* gskip;           // n: leading group entries of each row (|U_M| or 0)
-  int32_t* lcnt;            // nm
-  const int64_t* loff;      // nm + 1
-  int32_t* lscratch;        // L' lists
   const int64_t* row_ptr;   // n + 1
   int32_t* col;
   void* val;
@@ -87,16 +84,49 @@ __device__ __forceinline__ Window make_window(const AsmArgs& a, const int* c) {
 }
 
 // ---------------------------------------------------------------- features
+// Group mask of every point (the support tests of point_features, bump j of
+// group i is bump i * n2 + j): the bumps are staged in LDS kThreads at a
+// time and every thread tests its point against the staged ones.
 template <int D>
 __global__ void __launch_bounds__(kThreads) k_mask(KernelTheta kt, int64_t n, const double* __restrict__ xb,
                                                    uint64_t* __restrict__ mask, int32_t* __restrict__ flag) {
+  __shared__ double sh[3][kThreads], si[3][kThreads];
+  __shared__ int32_t sact[kThreads];
   const int64_t p = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x;
-  if (p >= n) return;
-  double x[3];
-  load_point<D>(xb, n, p, x);
-  const uint64_t m = point_features<D, false>(kt, x, nullptr);
-  mask[p] = m;
-  flag[p] = m != 0 ? 1 : 0;
+  double x[3] = {0, 0, 0};
+  if (p < n) load_point<D>(xb, n, p, x);
+  uint64_t m = 0;
+  const int nb = kt.n1 * kt.n2;
+  for (int b0 = 0; b0 < nb; b0 += kThreads) {
+    __syncthreads();  // the previous chunk has been read
+    const int b = b0 + static_cast<int>(threadIdx.x);
+    if (b < nb) {
+      const Bump& bp = kt.bumps[b];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        sh[k][threadIdx.x] = bp.h[k];
+        si[k][threadIdx.x] = bp.inv[k];
+      }
+      sact[threadIdx.x] = bp.a > 0.0 ? 1 : 0;
+    }
+    __syncthreads();
+    const int cnt = min(kThreads, nb - b0);
+    int gi = b0 / kt.n2, jj = b0 % kt.n2;
+    for (int j = 0; j < cnt; ++j) {
+      const double h[3] = {sh[0][j], sh[1][j], sh[2][j]};
+      const double inv[3] = {si[0][j], si[1][j], si[2][j]};
+      const double ub2 = scaled_sq<D>(x, h, inv);
+      if (sact[j] && ub2 < 1.0) m |= 1ull << gi;
+      if (++jj == kt.n2) {
+        jj = 0;
+        ++gi;
+      }
+    }
+  }
+  if (p < n) {
+    mask[p] = m;
+    flag[p] = m != 0 ? 1 : 0;
+  }
 }
 
 __global__ void __launch_bounds__(kThreads) k_compact_masked(int64_t n, const int32_t* __restrict__ flag,
@@ -175,15 +205,22 @@ __global__ void __launch_bounds__(kThreads) k_check_tau2(int64_t n, const double
   if (i < n && !(t[i] >= 0.0 && t[i] <= 1.7976931348623157e308)) atomicOr(err, 1);
 }
 
-// ------------------------------------------------------- rows without groups
+// ------------------------------------------------------------- local entries
+// Every row's local entries: for a row without a group bit all pairs with
+// u0^2 < 1; for a row with group mask M(p) only the local-only ones L'(p)
+// (u0^2 < 1 and M(q) & M(p) = 0), which follow the row's |U_M| group entries
+// (written by k_group_tile_fill).  One row per lane.
+//
+// A row's window is a set of pencils (cell rows along x within R rings),
+// each a contiguous range of binned points; visited in key order they give
+// the candidate columns in ascending order.  The wave's rows (consecutive in
+// binned order, so mostly in neighbouring cells) need, per pencil, one
+// contiguous range of points, the union of their own ranges.  When it holds
+// at most kStage points the wave stages their coordinates in its LDS slice
+// with coalesced loads and every lane scans its own range there; otherwise
+// the lanes read the points from global memory.  A row with a group bit reads
+// its candidates' masks from global memory (few rows have one).
 constexpr int kBuf = 4;
-
-// Candidate points are read through LDS: for each pencil of the window the
-// wave's rows (consecutive in binned order, so mostly neighbouring cells) need
-// one contiguous range of points, the union of their own ranges.  When the
-// union holds at most kStage points the wave stages its coordinates in its LDS
-// slice with coalesced loads and every lane scans its own range from LDS;
-// otherwise the lanes read the points from global memory.
 constexpr int kStage = 256;
 constexpr int kCu = 2;  // candidates whose global loads are in flight together
 
@@ -193,22 +230,31 @@ __device__ __forceinline__ void wave_sync_lds() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// COUNT (FILL = false): counts[p] = number of local (local-only) entries of
+// row p; gskip[p] = 0 for a row without a group bit (set for the others once
+// the group lists are known).  FILL: writes them at row_ptr[p] + gskip[p] and
+// checks that they are exactly the rest of the row.
 template <int D, bool FILL, typename VT, int CK = 0>
 __global__ void __launch_bounds__(kThreads) k_local_rows(AsmArgs a) {
   __shared__ double stage[kThreads / kWave][D][kStage];
   const int64_t p = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x;
   const int lane = lane_id();
   double (*st)[kStage] = stage[threadIdx.x / kWave];
-  // lanes without a local-only row take part in the staging with an empty window
-  const bool row = p < a.n && a.mask[p] == 0;
+  const uint64_t mp = p < a.n ? a.mask[p] : 0;
+  const int64_t out = (FILL && p < a.n) ? a.row_ptr[p] + (mp ? a.gskip[p] : 0) : 0;
+  const int64_t len = (FILL && p < a.n) ? a.row_ptr[p + 1] - out : 0;
+  const bool row = p < a.n;
   if (__ballot(row) == 0) return;  // uniform
   double xp[3] = {0, 0, 0};
   Window w{0, -1, 0, 0, 0, 0};
+  int cy = 0, cz = 0;
   if (row) {
     load_point<D>(a.xb, a.n, p, xp);
     int c[3];
     decode_key(a.key[p], a.g, c);
     w = make_window<D>(a, c);
+    cy = c[1];
+    cz = c[2];
   }
   // nonstationary core: fields of the row's point
   double sp = 0.0, Sp = 0.0;
@@ -218,18 +264,7 @@ __global__ void __launch_bounds__(kThreads) k_local_rows(AsmArgs a) {
       Sp = a.kt.core.Sig[p];
     }
   }
-  // the pencils of every row's window have the same (dy, dz) offsets; rows on
-  // a grid edge have fewer, and take the ones that exist
-  int cy = 0, cz = 0;
-  if (row) {
-    int c[3];
-    decode_key(a.key[p], a.g, c);
-    cy = c[1];
-    cz = c[2];
-  }
   int32_t cnt = 0;
-  const int64_t out = (FILL && row) ? a.row_ptr[p] : 0;
-  const int64_t len = (FILL && row) ? a.row_ptr[p + 1] - out : 0;
   VT* val = static_cast<VT*>(a.val);
   // fill: hits are buffered kBuf at a time and written with vector stores
   int32_t bc[kBuf];
@@ -259,6 +294,8 @@ __global__ void __launch_bounds__(kThreads) k_local_rows(AsmArgs a) {
     }
     ++cnt;
   };
+  // a local candidate of this row: u0^2 < 1, and no group shared with a row that has one
+  auto local = [&](int32_t q, double u2) { return u2 < 1.0 && (mp == 0 || (a.mask[q] & mp) == 0); };
   const int Ry = D >= 2 ? a.R[1] : 0, Rz = D >= 3 ? a.R[2] : 0;
   for (int dz = -Rz; dz <= Rz; ++dz)
     for (int dy = -Ry; dy <= Ry; ++dy) {
@@ -286,12 +323,26 @@ __global__ void __launch_bounds__(kThreads) k_local_rows(AsmArgs a) {
           for (int k = 0; k < D; ++k) st[k][j] = xq[k];
         }
         wave_sync_lds();
-        for (int32_t q = s; q < e; ++q) {
+        // two candidates per step (independent chains); an odd last one alone
+        int32_t q = s;
+        for (; q + 1 < e; q += 2) {
+          double xa[3], xb2[3];
+#pragma unroll
+          for (int k = 0; k < D; ++k) {
+            xa[k] = st[k][q - lo];
+            xb2[k] = st[k][q + 1 - lo];
+          }
+          const double ua = scaled_sq<D>(xp, xa, a.kt.inv0);
+          const double ub = scaled_sq<D>(xp, xb2, a.kt.inv0);
+          if (local(q, ua)) hit_at(q, ua, xa);
+          if (local(q + 1, ub)) hit_at(q + 1, ub, xb2);
+        }
+        if (q < e) {
           double xq[3];
 #pragma unroll
           for (int k = 0; k < D; ++k) xq[k] = st[k][q - lo];
           const double u2 = scaled_sq<D>(xp, xq, a.kt.inv0);
-          if (u2 < 1.0) hit_at(q, u2, xq);
+          if (local(q, u2)) hit_at(q, u2, xq);
         }
       } else {
         for (int32_t q0 = s; q0 < e; q0 += kCu) {
@@ -301,7 +352,7 @@ __global__ void __launch_bounds__(kThreads) k_local_rows(AsmArgs a) {
 #pragma unroll
           for (int u = 0; u < kCu; ++u) {
             const double u2 = scaled_sq<D>(xp, xq[u], a.kt.inv0);
-            if (q0 + u < e && u2 < 1.0) hit_at(q0 + u, u2, xq[u]);
+            if (q0 + u < e && local(q0 + u, u2)) hit_at(q0 + u, u2, xq[u]);
           }
         }
       }
@@ -309,7 +360,7 @@ __global__ void __launch_bounds__(kThreads) k_local_rows(AsmArgs a) {
   if (!row) return;
   if constexpr (!FILL) {
     a.counts[p] = cnt;
-    a.gskip[p] = 0;
+    if (mp == 0) a.gskip[p] = 0;
   } else {
     // the last nb % kBuf hits are still buffered, in bc[kBuf - rem ...]
     const int rem = nb % kBuf;
@@ -324,116 +375,127 @@ __global__ void __launch_bounds__(kThreads) k_local_rows(AsmArgs a) {
   }
 }
 
-// ------------------------------------------------------- rows with groups
-// PASS 0: count L'(p) and the row; PASS 1: write L'(p) to scratch.
-template <int D, int PASS>
-__global__ void __launch_bounds__(kThreads) k_group_rows_scan(AsmArgs a) {
-  const int64_t k = (blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x) / kWave;
-  if (k >= a.nm) return;
-  const int32_t p = a.mlist[k];
-  const uint64_t mp = a.mask[p];
-  double xp[3];
-  load_point<D>(a.xb, a.n, p, xp);
-  int c[3];
-  decode_key(a.key[p], a.g, c);
-  const Window w = make_window<D>(a, c);
-  int64_t running = 0;
-  const int64_t lbase = PASS == 1 ? a.loff[k] : 0;
-  const int64_t llen = PASS == 1 ? a.loff[k + 1] - lbase : 0;
-  const int lane = lane_id();
-  for (int z = w.z0; z <= w.z1; ++z)
-    for (int y = w.y0; y <= w.y1; ++y) {
-      const int64_t base = (static_cast<int64_t>(z) * a.g[1] + y) * a.g[0];
-      const int32_t s = a.cell_start[base + w.x0];
-      const int32_t e = a.cell_start[base + w.x1 + 1];
-      for (int32_t b = s; b < e; b += kWave) {
-        const int32_t q = b + lane;
-        bool hit = false;
-        if (q < e) {
-          double xq[3];
-          load_point<D>(a.xb, a.n, q, xq);
-          const double u2 = scaled_sq<D>(xp, xq, a.kt.inv0);
-          hit = (u2 < 1.0) && ((a.mask[q] & mp) == 0);
-        }
-        const uint64_t bal = __ballot(hit);
-        if constexpr (PASS == 1) {
-          const int64_t slot = running + __popcll(bal & lanes_below());
-          if (hit && slot < llen) a.lscratch[lbase + slot] = q;
-        }
-        running += __popcll(bal);
-      }
-    }
-  if (lane == 0) {
-    const int32_t D_id = a.did[k];
-    const int64_t nu = a.uoff[D_id + 1] - a.uoff[D_id];
-    if constexpr (PASS == 0) {
-      a.lcnt[k] = static_cast<int32_t>(running);
-      a.counts[p] = static_cast<int32_t>(nu + running);
-      a.gskip[p] = static_cast<int32_t>(nu);
-    } else {
-      if (running != a.loff[k + 1] - a.loff[k]) atomicOr(a.err, 2);
-    }
-  }
+// Rows with a group bit: |U_M| group entries come first in the row.
+__global__ void __launch_bounds__(kThreads) k_group_counts(int64_t nm, const int32_t* __restrict__ mlist,
+                                                           const int32_t* __restrict__ did,
+                                                           const int64_t* __restrict__ uoff,
+                                                           int32_t* __restrict__ counts, int32_t* __restrict__ gskip) {
+  const int64_t k = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x;
+  if (k >= nm) return;
+  const int32_t p = mlist[k];
+  const int32_t nu = static_cast<int32_t>(uoff[did[k] + 1] - uoff[did[k]]);
+  counts[p] += nu;
+  gskip[p] = nu;
 }
 
 // Row layout of a row with group mask M: first the |U_M| group entries in U_M
 // order (ascending column ids; every row with mask M shares this column list,
 // which the group-block products exploit), then the local-only entries L'(p)
 // in ascending order.
-template <int D, typename VT, int CK = 0>
-__global__ void __launch_bounds__(kThreads) k_group_rows_fill(AsmArgs a) {
-  const int64_t k = (blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x) / kWave;
-  if (k >= a.nm) return;
-  const int lane = lane_id();
-  const int32_t p = a.mlist[k];
-  const uint64_t mp = a.mask[p];
-  double xp[3];
-  load_point<D>(a.xb, a.n, p, xp);
-  const double* Fp = a.F + k * a.kt.n1;
-  const int32_t* L = a.lscratch + a.loff[k];
-  const int64_t nL = a.loff[k + 1] - a.loff[k];
-  const int32_t D_id = a.did[k];
-  const int32_t* U = a.ulist + a.uoff[D_id];
-  const int64_t nU = a.uoff[D_id + 1] - a.uoff[D_id];
-  const int64_t out = a.row_ptr[p];
-  const int64_t len = a.row_ptr[p + 1] - out;
+//
+// The rows are written tile by tile: block (x, y) takes tile x of the group
+// blocks (at most kTileRows rows, all with the mask M and so all with the
+// column list U_M) and the chunk y of kUChunk entries of U_M.  Thread t takes
+// the chunk's entries t, t + kThreads, ...: its point data (coordinates, mask
+// and the f_i of its groups shared with M) are loaded once and serve every
+// row of the tile, and each row's entries are written by consecutive threads
+// to consecutive positions.  The rows' f_i are staged in LDS.  Every value
+// is formed by the steps of entry_value with the row point first, as in the
+// local rows, so K_pq and K_qp are bitwise equal.  The rows' local-only
+// entries L'(p) after the group entries are written by k_local_rows.
+constexpr int kUChunk = 1024;
+constexpr int kFqRegs = 4;  // shared groups whose f_i(q) an entry keeps in registers
+
+template <int D, typename VT, int CK>
+__global__ void __launch_bounds__(kThreads) k_group_tile_fill(AsmArgs a, const int32_t* __restrict__ tiles,
+                                                              const int32_t* __restrict__ grows) {
+  __shared__ double sx[kTileRows][3];
+  __shared__ double sF[kTileRows][kMaxGroups];
+  __shared__ int32_t srow[kTileRows], sk[kTileRows];
+  __shared__ int64_t sout[kTileRows];
+  __shared__ double ssig[kTileRows], sSig[kTileRows];
+  const int32_t* t = tiles + 4 * static_cast<int64_t>(blockIdx.x);
+  const int32_t dm = t[0], i0 = t[1], rows = t[2];
+  const int64_t u0 = a.uoff[dm];
+  const int64_t nU = a.uoff[dm + 1] - u0;
+  const int64_t c0 = static_cast<int64_t>(blockIdx.y) * kUChunk;
+  if (c0 >= nU && blockIdx.y > 0) return;  // uniform: this tile has fewer chunks
+  const int n1 = a.kt.n1;
+  if (threadIdx.x < static_cast<unsigned>(rows)) {
+    const int r = threadIdx.x;
+    const int32_t p = grows[i0 + r];
+    const int32_t k = a.midx[p];
+    const int64_t out = a.row_ptr[p];
+    const int64_t len = a.row_ptr[p + 1] - out;
+    double xp[3] = {0, 0, 0};
+    load_point<D>(a.xb, a.n, p, xp);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) sx[r][c] = xp[c];
+    srow[r] = p;
+    sk[r] = k;
+    // counts disagree: the row is left unwritten and the error reported
+    const bool ok = a.gskip[p] == nU && len >= nU;
+    sout[r] = ok ? out : -1;
+    if (!ok && blockIdx.y == 0) atomicOr(a.err, 4);
+    ssig[r] = CK == 2 ? a.kt.core.sig[p] : 0.0;
+    sSig[r] = CK == 2 ? a.kt.core.Sig[p] : 0.0;
+  }
+  for (int e = threadIdx.x; e < rows * n1; e += kThreads) {
+    const int r = e / n1, i = e % n1;
+    sF[r][i] = a.F[static_cast<int64_t>(a.midx[grows[i0 + r]]) * n1 + i];
+  }
+  __syncthreads();
+  const uint64_t M = a.mask[srow[0]];
   VT* val = static_cast<VT*>(a.val);
-  if (nL + nU != len) {  // counts disagree: write nothing, report
-    if (lane == 0) atomicOr(a.err, 4);
-    return;
-  }
-  const int64_t u0 = a.uoff[D_id];
-  double sp = 0.0, Sp = 0.0;
-  if constexpr (CK == 2) {
-    sp = a.kt.core.sig[p];
-    Sp = a.kt.core.Sig[p];
-  }
-  auto core_at = [&](int32_t q, const double* xq) {
-    if constexpr (CK == 1) return core_value<D, 1>(a.kt.core, xp, xq, 0.0, 0.0, 0.0, 0.0);
-    if constexpr (CK == 2) return core_value<D, 2>(a.kt.core, xp, xq, sp, Sp, a.kt.core.sig[q], a.kt.core.Sig[q]);
-    return 1.0;
-  };
-  for (int64_t kk = lane; kk < nU; kk += kWave) {
-    const int32_t u = U[kk];
-    double xq[3];
+  const int64_t c1 = min(nU, c0 + kUChunk);
+  for (int64_t kk = c0 + threadIdx.x; kk < c1; kk += kThreads) {
+    const int32_t u = a.ulist[u0 + kk];
+    double xq[3] = {0, 0, 0};
 #pragma unroll
     for (int k = 0; k < D; ++k) xq[k] = a.ux[k * a.utotal + u0 + kk];
-    const double u2 = scaled_sq<D>(xp, xq, a.kt.inv0);
-    const uint64_t shared = a.umask[u0 + kk] & mp;
-    const double v = entry_value(a.kt, u2, shared, Fp, a.uF + u0 + kk, u == p, 1, a.utotal, core_at(u, xq), p);
-    const VT vs = static_cast<VT>(v);
-    a.col[out + kk] = u;
-    val[out + kk] = vs;
-    if (u == p) a.diag[p] = static_cast<double>(vs);
-  }
-  for (int64_t j = lane; j < nL; j += kWave) {
-    const int32_t q = L[j];
-    double xq[3];
-    load_point<D>(a.xb, a.n, q, xq);
-    const double u2 = scaled_sq<D>(xp, xq, a.kt.inv0);
-    const double v = entry_value(a.kt, u2, 0, nullptr, nullptr, false, 1, 1, core_at(q, xq));
-    a.col[out + nU + j] = q;
-    val[out + nU + j] = static_cast<VT>(v);
+    const uint64_t shared = a.umask[u0 + kk] & M;
+    // f_i(q) of the first kFqRegs shared groups, increasing i
+    double fq[kFqRegs];
+    int gi[kFqRegs];
+    uint64_t rest = shared;
+#pragma unroll
+    for (int j = 0; j < kFqRegs; ++j) {
+      gi[j] = rest ? __builtin_ctzll(rest) : 0;
+      fq[j] = rest ? a.uF[gi[j] * a.utotal + u0 + kk] : 0.0;
+      rest &= rest - 1;
+    }
+    const int ng = __popcll(shared);
+    double sq = 0.0, Sq = 0.0;
+    if constexpr (CK == 2) {
+      sq = a.kt.core.sig[u];
+      Sq = a.kt.core.Sig[u];
+    }
+    for (int r = 0; r < rows; ++r) {
+      const int64_t out = sout[r];
+      if (out < 0) continue;
+      const int32_t p = srow[r];
+      const double xp[3] = {sx[r][0], sx[r][1], sx[r][2]};
+      const double u2 = scaled_sq<D>(xp, xq, a.kt.inv0);
+      double cv = 1.0;
+      if constexpr (CK == 1) cv = core_value<D, 1>(a.kt.core, xp, xq, 0.0, 0.0, 0.0, 0.0);
+      if constexpr (CK == 2) cv = core_value<D, 2>(a.kt.core, xp, xq, ssig[r], sSig[r], sq, Sq);
+      double acc = entry_local(a.kt, u2);
+#pragma unroll
+      for (int j = 0; j < kFqRegs; ++j)
+        if (j < ng) acc = entry_add_group(acc, sF[r][gi[j]], fq[j]);
+      if (ng > kFqRegs) {  // rare: the remaining groups from memory, increasing i
+        uint64_t more = rest;
+        while (more) {
+          const int i = __builtin_ctzll(more);
+          more &= more - 1;
+          acc = entry_add_group(acc, sF[r][i], a.uF[i * a.utotal + u0 + kk]);
+        }
+      }
+      const VT vs = static_cast<VT>(entry_finish(a.kt, acc, cv, u == p, p));
+      a.col[out + kk] = u;
+      val[out + kk] = vs;
+      if (u == p) a.diag[p] = static_cast<double>(vs);
+    }
   }
 }
 
@@ -642,7 +704,10 @@ void compute_features(gp_ctx* c, const gp_dataset* ds, const KernelTheta& kt, Fe
                        f->mask, flag);
   });
   check_launch("mask");
-  scan_i32_to_i32(c, flag, pos, n);
+  {
+    ProfScope ps(c, "asm_scan");
+    scan_i32_to_i32(c, flag, pos, n);
+  }
   int32_t* h = static_cast<int32_t*>(pinned(c, sizeof(int32_t)));
   GPS_HIP(hipMemcpyAsync(h, pos + n, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
   sync(c);
@@ -650,8 +715,11 @@ void compute_features(gp_ctx* c, const gp_dataset* ds, const KernelTheta& kt, Fe
   f->mlist = static_cast<int32_t*>(workspace(c, ws_base + 4, sizeof(int32_t) * std::max<int64_t>(f->nm, 1)));
   uint64_t* mmask = static_cast<uint64_t*>(workspace(c, ws_base + 5, sizeof(uint64_t) * std::max<int64_t>(f->nm, 1)));
   f->mmask = mmask;
-  hipLaunchKernelGGL(k_compact_masked, dim3(grid_for(n, kThreads)), dim3(kThreads), 0, c->stream, n, flag, pos,
-                     f->mask, f->midx, f->mlist, mmask);
+  {
+    ProfScope ps(c, "asm_compact");
+    hipLaunchKernelGGL(k_compact_masked, dim3(grid_for(n, kThreads)), dim3(kThreads), 0, c->stream, n, flag, pos,
+                       f->mask, f->midx, f->mlist, mmask);
+  }
   check_launch("compact masked");
   f->F = static_cast<double*>(workspace(c, ws_base + 6, sizeof(double) * std::max<int64_t>(f->nm * kt.n1, 1)));
   if (f->nm > 0) {
@@ -811,6 +879,8 @@ gp_matrix* assemble(gp_ctx* c, const gp_dataset* ds, const gp_theta* th, int pre
   }
   const int64_t nD = static_cast<int64_t>(dmask.size());
   const int64_t utotal = uoff.back();
+  int64_t max_nu = 1;
+  for (int64_t x = 0; x < nD; ++x) max_nu = std::max(max_nu, uoff[x + 1] - uoff[x]);
   // rows grouped by their mask (stable, so ascending within a mask) and cut into
   // tiles of at most kTileRows rows for the group-block products
   std::vector<int32_t> goff(nD + 1, 0), grows(nm);
@@ -905,42 +975,36 @@ gp_matrix* assemble(gp_ctx* c, const gp_dataset* ds, const gp_theta* th, int pre
   a.uoff = d_uoff;
   a.ulist = d_ulist;
   a.utotal = utotal;
-  a.lcnt = static_cast<int32_t*>(workspace(c, 13, sizeof(int32_t) * std::max<int64_t>(nm, 1)));
-  int64_t* loff = static_cast<int64_t*>(workspace(c, 14, sizeof(int64_t) * (nm + 1)));
-  a.loff = loff;
   GPS_HIP(hipMemsetAsync(c->err_flag, 0, sizeof(int), c->stream));
-
-  // count pass of the rows with a group bit
-  dispatch_d(d, [&](auto DD) {
-    constexpr int D = decltype(DD)::value;
-    if (nm > 0) {
-      ProfScope ps(c, "asm_count_group");
-      hipLaunchKernelGGL((k_group_rows_scan<D, 0>), dim3(grid_for(nm * kWave, kThreads)), dim3(kThreads), 0,
-                         c->stream, a);
-    }
-  });
-  check_launch("count");
+  // rows with a group bit: their |U_M| group entries come first
+  if (nm > 0) {
+    ProfScope ps(c, "asm_compact");
+    hipLaunchKernelGGL(k_group_counts, dim3(grid_for(nm, kThreads)), dim3(kThreads), 0, c->stream, nm, f.mlist, d_did,
+                       d_uoff, a.counts, m->gskip);
+    check_launch("group counts");
+  }
 
   m->row_ptr = dev_new<int64_t>(c, n + 1);
   m->bytes += sizeof(int64_t) * (n + 1);
-  scan_i32_to_i64(c, a.counts, m->row_ptr, n);
-  scan_i32_to_i64(c, a.lcnt, loff, nm);
   int32_t* lflag = static_cast<int32_t*>(workspace(c, 15, sizeof(int32_t) * n));
   int32_t* lpos = static_cast<int32_t*>(workspace(c, 16, sizeof(int32_t) * (n + 1)));
   int32_t* maxrow = static_cast<int32_t*>(workspace(c, 17, sizeof(int32_t) * 2));
-  GPS_HIP(hipMemsetAsync(maxrow, 0, sizeof(int32_t), c->stream));
-  hipLaunchKernelGGL(k_long_flags, dim3(grid_for(n, kThreads)), dim3(kThreads), 0, c->stream, n, a.counts,
-                     m->gskip, lflag, maxrow);
-  check_launch("long flags");
-  scan_i32_to_i32(c, lflag, lpos, n);
-  // one synchronisation: nnz, |L'| total, number of long rows, longest row
+  {
+    ProfScope ps(c, "asm_scan");
+    scan_i32_to_i64(c, a.counts, m->row_ptr, n);
+    GPS_HIP(hipMemsetAsync(maxrow, 0, sizeof(int32_t), c->stream));
+    hipLaunchKernelGGL(k_long_flags, dim3(grid_for(n, kThreads)), dim3(kThreads), 0, c->stream, n, a.counts,
+                       m->gskip, lflag, maxrow);
+    check_launch("long flags");
+    scan_i32_to_i32(c, lflag, lpos, n);
+  }
+  // one synchronisation: nnz, number of long rows, longest row
   struct Sizes {
-    int64_t nnz, ltot;
+    int64_t nnz;
     int32_t nlong, maxrow;
   };
   Sizes* hs = static_cast<Sizes*>(pinned(c, sizeof(Sizes)));
   GPS_HIP(hipMemcpyAsync(&hs->nnz, m->row_ptr + n, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
-  GPS_HIP(hipMemcpyAsync(&hs->ltot, loff + nm, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
   GPS_HIP(hipMemcpyAsync(&hs->nlong, lpos + n, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
   GPS_HIP(hipMemcpyAsync(&hs->maxrow, maxrow, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
   sync(c);
@@ -961,11 +1025,13 @@ gp_matrix* assemble(gp_ctx* c, const gp_dataset* ds, const gp_theta* th, int pre
   m->diag = dev_new<double>(c, n);
   m->long_rows = dev_new<int32_t>(c, std::max<int64_t>(m->n_long, 1));
   m->bytes += (sizeof(int32_t) + vbytes) * m->nnz + sizeof(double) * n + sizeof(int32_t) * m->n_long;
-  hipLaunchKernelGGL(k_long_compact, dim3(grid_for(n, kThreads)), dim3(kThreads), 0, c->stream, n, lflag, lpos,
-                     m->long_rows);
+  {
+    ProfScope ps(c, "asm_compact");
+    hipLaunchKernelGGL(k_long_compact, dim3(grid_for(n, kThreads)), dim3(kThreads), 0, c->stream, n, lflag, lpos,
+                       m->long_rows);
+  }
   check_launch("long rows");
 
-  a.lscratch = static_cast<int32_t*>(workspace(c, 18, sizeof(int32_t) * std::max<int64_t>(sz.ltot, 1)));
   {
     const int64_t ut = std::max<int64_t>(utotal, 1);
     double* ux = static_cast<double*>(workspace(c, 19, sizeof(double) * 3 * ut));
@@ -977,6 +1043,7 @@ gp_matrix* assemble(gp_ctx* c, const gp_dataset* ds, const gp_theta* th, int pre
     if (utotal > 0)
       dispatch_d(ds->d, [&](auto DD) {
         constexpr int D = decltype(DD)::value;
+        ProfScope ps(c, "asm_group_lists");
         hipLaunchKernelGGL((k_ugather<D>), dim3(grid_for(utotal, kThreads)), dim3(kThreads), 0, c->stream, a, ux,
                            umask, uF);
       });
@@ -988,11 +1055,6 @@ gp_matrix* assemble(gp_ctx* c, const gp_dataset* ds, const gp_theta* th, int pre
   a.diag = m->diag;
   dispatch_d(d, [&](auto DD) {
     constexpr int D = decltype(DD)::value;
-    if (nm > 0) {
-      ProfScope ps(c, "asm_list_group");
-      hipLaunchKernelGGL((k_group_rows_scan<D, 1>), dim3(grid_for(nm * kWave, kThreads)), dim3(kThreads), 0,
-                         c->stream, a);
-    }
     auto fill = [&](auto VTv) {
       using VT = decltype(VTv);
       dispatch_core(kt.core.kind, [&](auto CC) {
@@ -1002,10 +1064,11 @@ gp_matrix* assemble(gp_ctx* c, const gp_dataset* ds, const gp_theta* th, int pre
           hipLaunchKernelGGL((k_local_rows<D, true, VT, CK>), dim3(grid_for(n, kThreads)), dim3(kThreads), 0,
                              c->stream, a);
         }
-        if (nm > 0) {
+        if (ntiles > 0) {
           ProfScope ps(c, "asm_fill_group");
-          hipLaunchKernelGGL((k_group_rows_fill<D, VT, CK>), dim3(grid_for(nm * kWave, kThreads)), dim3(kThreads),
-                             0, c->stream, a);
+          hipLaunchKernelGGL((k_group_tile_fill<D, VT, CK>),
+                             dim3(static_cast<unsigned>(ntiles), static_cast<unsigned>((max_nu + kUChunk - 1) / kUChunk)),
+                             dim3(kThreads), 0, c->stream, a, m->g_tiles, m->g_rows);
         }
       });
     };

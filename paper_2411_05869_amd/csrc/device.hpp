@@ -50,6 +50,27 @@ __device__ __forceinline__ double wendland(double u2, int variant) {
   return t8 * poly;
 }
 
+// The three steps of an entry (entry_value below): the local term, one group
+// term added (the caller adds them in increasing i), the core and diagonal.
+__device__ __forceinline__ double entry_local(const KernelTheta& kt, double u2) {
+#pragma clang fp contract(off)
+  return (u2 < 1.0) ? kt.s0 * wendland(u2, kt.variant) : 0.0;
+}
+__device__ __forceinline__ double entry_add_group(double acc, double fp, double fq) {
+#pragma clang fp contract(off)
+  return acc + fp * fq;
+}
+__device__ __forceinline__ double entry_finish(const KernelTheta& kt, double acc, double core, bool diag,
+                                               int64_t row) {
+#pragma clang fp contract(off)
+  acc = core * acc;
+  if (diag) {
+    acc = acc + kt.nugget;
+    if (kt.tau2) acc = acc + kt.tau2[row];  // Delta_pp = sigma^2 + tau2[p] (Eq. Zcov)
+  }
+  return acc;
+}
+
 // Entry K_pq (Eq. sparseCov, Eq. C_sparse, Eq. Zcov): core x (s0 f0 [local] +
 // sum over shared groups in increasing i of f_i(p) f_i(q)) + sigma^2 [p = q].
 // f_i(p) = Fp[i * sp], f_i(q) = Fq[i * sq]; core = C_core(x_p, x_q), 1 without
@@ -57,19 +78,13 @@ __device__ __forceinline__ double wendland(double u2, int variant) {
 __device__ __forceinline__ double entry_value(const KernelTheta& kt, double u2, uint64_t shared,
                                               const double* Fp, const double* Fq, bool diag, int64_t sp = 1,
                                               int64_t sq = 1, double core = 1.0, int64_t row = 0) {
-#pragma clang fp contract(off)
-  double acc = (u2 < 1.0) ? kt.s0 * wendland(u2, kt.variant) : 0.0;
+  double acc = entry_local(kt, u2);
   while (shared) {
     const int i = __builtin_ctzll(shared);
     shared &= shared - 1;
-    acc = acc + Fp[i * sp] * Fq[i * sq];
+    acc = entry_add_group(acc, Fp[i * sp], Fq[i * sq]);
   }
-  acc = core * acc;
-  if (diag) {
-    acc = acc + kt.nugget;
-    if (kt.tau2) acc = acc + kt.tau2[row];  // Delta_pp = sigma^2 + tau2[p] (Eq. Zcov)
-  }
-  return acc;
+  return entry_finish(kt, acc, core, diag, row);
 }
 
 // Matern correlation M_nu(t) (Rasmussen-Williams scaling sqrt(2 nu) t) at
