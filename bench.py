@@ -89,11 +89,22 @@ def copy_peak_gbs(torch, dev, nbytes=1 << 30, reps=5):
 EXACT_LOGLIK = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests", "golden",
                             "spacetime_n1095000_exact.json")
 TRAFFIC_PROFILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
-                               "traffic_spmv_f32val_f64_spacetime_n1095000.md")
-SPMV_SOURCE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2411_05869_amd", "csrc", "spmv.hip")
-# the conjugate-gradient product of the mixed form: float32 values, float64 vectors
-SPMV_KERNELS = ("k_group_spmv<float, double, double, double>", "k_spmv<float, double, double, double>")
-SPMV_PROFILE_NAME = "spmv_f32val_f64"
+                               "traffic_spacetime_n1095000.md")
+CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2411_05869_amd", "csrc")
+# kernel groups whose HBM traffic the counter summary records: (source file, the
+# kernels of one launch of the group, mixed form on the space-time workload)
+TRAFFIC_GROUPS = {
+    # the conjugate-gradient product: float32 values, float64 vectors
+    "spmv_f32val_f64": ("spmv.hip", ("k_group_spmv<float, double, double, double>(",
+                                     "k_spmv<float, double, double, double>(")),
+    # the 32-column SLQ product: MFMA group blocks, their piece sums, the row quads
+    "spmm": ("spmv.hip", ("k_group_spmm_mfma<float, double, true>(", "k_group_reduce<double>(",
+                          "k_spmm_quad<float, true>(")),
+    # the assembly's main kernels (float32 values)
+    "assembly": ("assemble.hip", ("k_mask<3>(", "k_fvals<3>(", "k_local_rows<3, false, double, 0>(",
+                                  "k_ulists(", "k_ugather<3>(", "k_local_rows<3, true, float, 0>(",
+                                  "k_group_tile_fill<3, float, 0>(")),
+}
 CALIB_BYTES = 1 << 30
 
 
@@ -121,25 +132,26 @@ def source_sha256(path):
         return hashlib.sha256(f.read()).hexdigest()
 
 
-def stored_traffic():
-    """HBM bytes per mixed-form SpMV (both kernels) from the committed counter summary,
-    or None when it is missing or the SpMV source changed since it was taken."""
+def stored_traffic(group):
+    """HBM bytes per launch of a kernel group from the committed counter summary,
+    or None when it is missing or the group's source changed since it was taken."""
     try:
         fields = {}
         for line in open(TRAFFIC_PROFILE):
             if line.startswith("- ") and ": " in line:
                 k, v = line[2:].split(": ", 1)
                 fields[k.strip()] = v.strip().strip("`")
-        if fields.get("spmv_source_sha256") != source_sha256(SPMV_SOURCE):
+        src = os.path.join(CSRC, TRAFFIC_GROUPS[group][0])
+        if fields.get(f"{group}.source_sha256") != source_sha256(src):
             return None
-        return int(fields["traffic_bytes_per_launch"])
+        return int(fields[f"{group}.traffic_bytes_per_launch"])
     except (OSError, KeyError, ValueError):
         return None
 
 
 def summarize_pmc(fetch_dir, write_dir, command):
-    """Per-dispatch FETCH_SIZE / WRITE_SIZE (KiB) of the mixed-form SpMV kernels, scaled
-    by what the same counters read for a copy of CALIB_BYTES bytes."""
+    """Per-dispatch FETCH_SIZE / WRITE_SIZE (KiB) of the kernel groups, scaled by
+    what the same counters read for a copy of CALIB_BYTES bytes in the same run."""
     import csv
     import glob
 
@@ -148,30 +160,70 @@ def summarize_pmc(fetch_dir, write_dir, command):
         rows = [r for r in csv.DictReader(open(f[0])) if r["Counter_Name"] == counter]
         copy = max(float(r["Counter_Value"]) for r in rows if "copy" in r["Kernel_Name"].lower())
         per = {}
-        for k in SPMV_KERNELS:
-            v = [float(r["Counter_Value"]) for r in rows if k in r["Kernel_Name"]]
-            per[k] = (sum(v) / len(v), len(v))
+        for g, (_, kernels) in TRAFFIC_GROUPS.items():
+            for k in kernels:
+                v = [float(r["Counter_Value"]) for r in rows if k in r["Kernel_Name"]]
+                per[(g, k)] = (sum(v) / len(v), len(v)) if v else (0.0, 0)
         return copy, per
 
     cf, pf = load(fetch_dir, "FETCH_SIZE")
     cw, pw = load(write_dir, "WRITE_SIZE")
     sf, sw = CALIB_BYTES / (cf * 1024.0), CALIB_BYTES / (cw * 1024.0)
-    fetch = sum(v for v, _ in pf.values()) * 1024.0 * sf
-    write = sum(v for v, _ in pw.values()) * 1024.0 * sw
-    lines = ["# HBM traffic of the mixed-form SpMV (float32 values, float64 vectors; the conjugate-gradient "
-             "product) on the space-time workload, n = 1,095,000",
-             "", "Two counter runs of the same command (run from /tmp with TMPDIR=/tmp on one MI355X), "
+    lines = ["# HBM traffic of the main kernels on the space-time workload (n = 1,095,000), mixed form",
+             "", "Two counter runs of the same command on one MI355X (run from /tmp with TMPDIR=/tmp), "
              "one with `--pmc FETCH_SIZE`, one with `--pmc WRITE_SIZE`:", "", "```", command, "```", "",
              f"Calibration: a device-to-device copy of {CALIB_BYTES} bytes (bench.py --copy-calibration) read "
              f"FETCH_SIZE {cf:.0f} KiB and WRITE_SIZE {cw:.0f} KiB; scale factors {sf:.4f} (fetch), {sw:.4f} (write).",
-             "", "| kernel | dispatches | FETCH_SIZE KiB/dispatch | WRITE_SIZE KiB/dispatch |", "|---|---:|---:|---:|"]
-    for k in SPMV_KERNELS:
-        lines.append(f"| `{k}` | {pf[k][1]} | {pf[k][0]:.0f} | {pw[k][0]:.0f} |")
-    lines += ["", "Figures read by bench.py (traffic of one SpMV = both kernels, scaled):", "",
-              f"- fetch_bytes_per_launch: {int(fetch)}", f"- write_bytes_per_launch: {int(write)}",
-              f"- traffic_bytes_per_launch: {int(fetch + write)}",
-              f"- spmv_source_sha256: `{source_sha256(SPMV_SOURCE)}`", ""]
+             "", "| group | kernel | dispatches | FETCH_SIZE KiB/dispatch | WRITE_SIZE KiB/dispatch | scaled MB/dispatch |",
+             "|---|---|---:|---:|---:|---:|"]
+    tail = ["", "Figures read by bench.py (one launch of a group = one dispatch of each of its kernels, scaled):", ""]
+    for g, (src, kernels) in TRAFFIC_GROUPS.items():
+        fetch = write = 0.0
+        for k in kernels:
+            (fv, fn), (wv, _) = pf[(g, k)], pw[(g, k)]
+            fetch += fv * 1024.0 * sf
+            write += wv * 1024.0 * sw
+            lines.append(f"| {g} | `{k[:-1]}` | {fn} | {fv:.0f} | {wv:.0f} | {(fv * sf + wv * sw) * 1024 / 1e6:.1f} |")
+        tail += [f"- {g}.fetch_bytes_per_launch: {int(fetch)}", f"- {g}.write_bytes_per_launch: {int(write)}",
+                 f"- {g}.traffic_bytes_per_launch: {int(fetch + write)}",
+                 f"- {g}.source_sha256: `{source_sha256(os.path.join(CSRC, src))}`"]
+    lines += tail + [""]
     with open(TRAFFIC_PROFILE, "w") as f:
+        f.write("\n".join(lines))
+    print("\n".join(lines))
+
+
+STATS_PROFILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                             "loglik_step_spacetime_n1095000_kernel_stats.md")
+
+
+def summarize_stats(stats_csv, bench_json, command, top=40):
+    """Writes the kernel-statistics summary of a `rocprofv3 --kernel-trace --stats`
+    run of bench.py (its kernel_stats.csv and the JSON line the same run printed)."""
+    import csv
+    rows = list(csv.DictReader(open(stats_csv)))
+    tot = sum(float(r["TotalDurationNs"]) for r in rows)
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    b = json.load(open(bench_json))
+    lines = ["# Kernel statistics of bench.py on the space-time workload (n = 1,095,000, 87.35M nonzeros)", "",
+             "`rocprofv3 --kernel-trace --stats` of the command below on one MI355X (run from /tmp with TMPDIR=/tmp); "
+             "the bench line it printed is summarised after the table.", "", "```", command, "```", "",
+             "| kernel | calls | total ms | avg us | min us | max us | % |", "|---|---:|---:|---:|---:|---:|---:|"]
+    for r in rows[:top]:
+        name = r["Name"].replace("gps::(anonymous namespace)::", "")
+        name = name.split("(")[0] if "(" in name else name
+        lines.append(f"| `{name}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.2f} | "
+                     f"{float(r['AverageNs']) / 1e3:.2f} | {float(r['MinNs']) / 1e3:.2f} | "
+                     f"{float(r['MaxNs']) / 1e3:.2f} | {100 * float(r['TotalDurationNs']) / tot:.2f} |")
+    ro = b["roofline"]
+    lines += ["", "Bench line of the same run (library event timing on the library's streams):", "",
+              f"- value {b['value']} loglik evals/s ({b['ms_per_step']} ms per step), fp64 {b['fp64']['value']}",
+              f"- roofline: kernel {ro['kernel']}, {ro['avg_us']} us per launch, {ro['achieved']} GB/s, frac {ro['frac']}",
+              f"- isolated steps (log det after the solve, one stream): "
+              + ", ".join(f"{k} {v['avg_us']} us" for k, v in (b.get("roofline_isolated") or {}).items()
+                          if isinstance(v, dict)),
+              f"- assembly kernels {b['assemble_kernels_ms']} ms, wall {b['assemble_ms']} ms", ""]
+    with open(STATS_PROFILE, "w") as f:
         f.write("\n".join(lines))
     print("\n".join(lines))
 
@@ -453,11 +505,16 @@ def main():
                     help="copy 1 GiB device-to-device first (reference dispatch for HBM counters)")
     ap.add_argument("--assembly-only", type=int, default=0, metavar="REPS",
                     help="only assemble the workload REPS times per precision (profiling runs) and print the times")
+    ap.add_argument("--summarize-stats", nargs=3, metavar=("STATS_CSV", "BENCH_JSON", "COMMAND"),
+                    help="write the kernel-statistics summary from a rocprofv3 --stats run and exit")
     ap.add_argument("--summarize-pmc", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "COMMAND"),
                     help="write the SpMV traffic summary from two rocprofv3 --pmc output folders and exit")
     args = ap.parse_args()
     if args.summarize_pmc:
         summarize_pmc(*args.summarize_pmc)
+        return
+    if args.summarize_stats:
+        summarize_stats(*args.summarize_stats)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the library runs on one GPU; "
@@ -576,7 +633,7 @@ def main():
         achieved = b / avg_s / 1e9
         return dict(bound="hbm", kernel=name, achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 4),
-                    traffic=stored_traffic() if name == SPMV_PROFILE_NAME else None, avg_us=round(avg_s * 1e6, 2),
+                    traffic=stored_traffic(name), avg_us=round(avg_s * 1e6, 2),
                     launches=cnt, bytes_per_launch=int(b), bytes_model="stored format (gp_matrix_layout)",
                     effective_plain_csr=dict(bytes_per_launch=int(bcsr), achieved=round(bcsr / avg_s / 1e9, 1),
                                              frac=round(bcsr / avg_s / 1e9 / HBM_PEAK_GBS, 4)))
@@ -594,7 +651,8 @@ def main():
     others["assembly"] = dict(bound="hbm", achieved=round(asm_b / (asm_ms_m / 1e3) / 1e9, 1), peak=HBM_PEAK_GBS,
                               unit="GB/s", frac=round(asm_b / (asm_ms_m / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
                               bytes_per_launch=int(asm_b), bytes_model="8.1 B per stored entry (int32 column id, "
-                              "float32 value, row pointer and point data)", kernels_ms=round(asm_ms_m, 3))
+                              "float32 value, row pointer and point data)", kernels_ms=round(asm_ms_m, 3),
+                              traffic=stored_traffic("assembly"))
     r50 = res_50[-1][0]
 
     out = dict(metric=METRIC, value=round(evals_m, 4), unit="loglik evals/s", n_gpus=1, steps=args.steps,

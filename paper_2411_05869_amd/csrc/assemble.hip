@@ -237,7 +237,9 @@ __device__ __forceinline__ void wave_sync_lds() {
 template <int D, bool FILL, typename VT, int CK = 0>
 __global__ void __launch_bounds__(kThreads) k_local_rows(AsmArgs a) {
   __shared__ double stage[kThreads / kWave][D][kStage];
-  const int64_t p = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x;
+  // each XCD takes a contiguous range of rows: their candidates and output
+  // cache lines stay within its L2
+  const int64_t p = xcd_remap(blockIdx.x, gridDim.x) * static_cast<int64_t>(kThreads) + threadIdx.x;
   const int lane = lane_id();
   double (*st)[kStage] = stage[threadIdx.x / kWave];
   const uint64_t mp = p < a.n ? a.mask[p] : 0;

@@ -125,10 +125,12 @@ struct gp_matrix {
   int16_t* col16 = nullptr;
   bool col16_tried = false;
   // row quads of the multi-column product, built on first use.  The rows
-  // are listed line by line along the grid axis with the most cells (a line:
-  // the cells with every other cell coordinate fixed, one after another,
-  // binned order within a cell), each line padded to a multiple of four
-  // rows; quad q (listed rows 4q .. 4q+3) holds the ascending union of its
+  // are listed along the grid axis with the most cells (a line: the cells
+  // with every other cell coordinate fixed, one after another, binned order
+  // within a cell) in segments of a few consecutive cells of a line, each
+  // segment padded to a multiple of four rows (segments ordered by region of
+  // lines, then position along the line, then line); quad q (listed rows
+  // 4q .. 4q+3) holds the ascending union of its
   // rows' CSR-part columns (rows with more than kLongRow such entries left
   // out) with the four rows' values per column (0 where a row has none).
   int64_t ntrow = 0;             // listed rows (padded)

@@ -778,14 +778,16 @@ namespace {
 // The CSR part of the 32-column product reads one 256-byte row of X per
 // stored entry.  Rows next to each other along the grid axis with the most
 // cells (at the space-time workload: one station on consecutive days) share
-// most of their columns, so the rows are listed line by line along that axis
-// (a line: the cells with all other cell coordinates fixed, binned order
-// within a cell) and every four consecutive listed rows form a quad that
-// stores the ascending union of its rows' columns once, with the four rows'
-// values per entry: one gather of an X row serves four rows.  Consecutive
-// quads of a line share many X rows, which then come from the caches.
+// most of their columns, so the rows are listed along that axis (a line: the
+// cells with all other cell coordinates fixed, binned order within a cell),
+// in segments of kSlabCells cells of a line, and every four consecutive
+// listed rows of a segment form a quad that stores the ascending union of its
+// rows' columns once, with the four rows' values per entry: one gather of an
+// X row serves four rows.  Consecutive quads share many X rows, which then
+// come from the caches (k_line_rows gives the order of the segments).
 constexpr int kQuad = 4;
 constexpr int kLineThreads = 256;
+constexpr int kSlabCells = 16;  // cells of a line per listed segment
 
 struct LineGeom {
   int a;            // axis along which a line runs
@@ -793,6 +795,10 @@ struct LineGeom {
   int o[2];         // the other axes, fastest first
   int32_t g[3];     // cells per axis
   int64_t stride[3];
+  int64_t nlines;   // lines of the grid
+  int64_t lpr;      // lines per region (the lines are cut into kXcds contiguous regions)
+  int32_t slab;     // cells of a line per segment
+  int32_t nslab;    // segments per line
 };
 
 // exclusive prefix sum over the block of v (kLineThreads threads); *total
@@ -819,43 +825,54 @@ __device__ __forceinline__ int32_t block_excl_scan(int32_t v, int32_t* total) {
   return before + x - v;
 }
 
-// Block per line.  PASS 0: the line's row count padded to a multiple of four
-// (lpad).  PASS 1: the line's rows in order of their cells along the line
-// (binned order within a cell), then the padding (-1).
+// The rows are listed segment by segment: a segment is the rows of lg.slab
+// consecutive cells of one line (binned order within a cell), padded to a
+// multiple of four.  Segments are ordered by region (kXcds contiguous ranges
+// of lines), then slab, then line: the 32-column product gives each XCD a
+// contiguous range of quads, so an XCD sweeps its region slab by slab and the
+// X rows that neighbouring lines share are read while they are in its L2.
+// Block per segment.  PASS 0: the segment's row count padded to a multiple of
+// four (lpad).  PASS 1: its rows, then the padding (-1).
 template <int PASS>
 __global__ void __launch_bounds__(kLineThreads) k_line_rows(LineGeom lg, const int32_t* __restrict__ cell_start,
                                                              int32_t* __restrict__ lpad, const int64_t* __restrict__ loff,
                                                              int32_t* __restrict__ trow) {
-  const int64_t L = blockIdx.x;
-  int64_t base = 0, r = L;
-  for (int j = 0; j < lg.nother; ++j) {
-    const int ax = lg.o[j];
-    base += (r % lg.g[ax]) * lg.stride[ax];
-    r /= lg.g[ax];
-  }
-  const int64_t sa = lg.stride[lg.a];
-  const int ga = lg.g[lg.a];
-  const int64_t out0 = PASS == 1 ? loff[L] : 0;
+  const int64_t S = blockIdx.x;
+  const int64_t j = S % lg.lpr, rs = S / lg.lpr;
+  const int64_t region = rs / lg.nslab;
+  const int slab = static_cast<int>(rs % lg.nslab);
+  const int64_t L = region * lg.lpr + j;
   int64_t running = 0;
-  for (int i0 = 0; i0 < ga; i0 += kLineThreads) {
-    const int i = i0 + static_cast<int>(threadIdx.x);
-    int32_t cs = 0, cnt = 0;
-    if (i < ga) {
-      const int64_t key = base + i * sa;
-      cs = cell_start[key];
-      cnt = cell_start[key + 1] - cs;
+  const int64_t out0 = PASS == 1 ? loff[S] : 0;
+  if (L < lg.nlines) {
+    int64_t base = 0, r = L;
+    for (int k = 0; k < lg.nother; ++k) {
+      const int ax = lg.o[k];
+      base += (r % lg.g[ax]) * lg.stride[ax];
+      r /= lg.g[ax];
     }
-    int32_t total;
-    const int32_t ex = block_excl_scan(cnt, &total);
-    if constexpr (PASS == 1)
-      for (int32_t j = 0; j < cnt; ++j) trow[out0 + running + ex + j] = cs + j;
-    running += total;
+    const int64_t sa = lg.stride[lg.a];
+    const int c0 = slab * lg.slab, c1 = min(c0 + lg.slab, lg.g[lg.a]);
+    for (int i0 = c0; i0 < c1; i0 += kLineThreads) {
+      const int i = i0 + static_cast<int>(threadIdx.x);
+      int32_t cs = 0, cnt = 0;
+      if (i < c1) {
+        const int64_t key = base + i * sa;
+        cs = cell_start[key];
+        cnt = cell_start[key + 1] - cs;
+      }
+      int32_t total;
+      const int32_t ex = block_excl_scan(cnt, &total);
+      if constexpr (PASS == 1)
+        for (int32_t t = 0; t < cnt; ++t) trow[out0 + running + ex + t] = cs + t;
+      running += total;
+    }
   }
   const int64_t pad = (running + kQuad - 1) / kQuad * kQuad;
   if constexpr (PASS == 0) {
-    if (threadIdx.x == 0) lpad[L] = static_cast<int32_t>(pad);
+    if (threadIdx.x == 0) lpad[S] = static_cast<int32_t>(pad);
   } else {
-    for (int64_t j = running + threadIdx.x; j < pad; j += kLineThreads) trow[out0 + j] = -1;
+    for (int64_t t = running + threadIdx.x; t < pad; t += kLineThreads) trow[out0 + t] = -1;
   }
 }
 
@@ -1141,16 +1158,22 @@ static void build_quads(gp_ctx* c, gp_matrix* m) {
       if (k != lg.a) lg.o[lg.nother++] = k;
     const int64_t nlines = ds->ncells / lg.g[lg.a];
     GPS_REQUIRE(nlines * lg.g[lg.a] == ds->ncells, GP_EDEVICE, "quad build: grid does not match the dataset's cells");
-    TmpBuf lpad(c, sizeof(int32_t) * nlines), loff(c, sizeof(int64_t) * (nlines + 1));
-    hipLaunchKernelGGL((k_line_rows<0>), dim3(static_cast<unsigned>(nlines)), dim3(kLineThreads), 0, c->stream, lg,
+    lg.nlines = nlines;
+    lg.lpr = (nlines + kXcds - 1) / kXcds;
+    lg.slab = kSlabCells;
+    lg.nslab = (lg.g[lg.a] + kSlabCells - 1) / kSlabCells;
+    const int64_t nseg = static_cast<int64_t>(kXcds) * lg.nslab * lg.lpr;
+    GPS_REQUIRE(nseg < (int64_t(1) << 31), GP_ENOMEM, "quad build: too many segments");
+    TmpBuf lpad(c, sizeof(int32_t) * nseg), loff(c, sizeof(int64_t) * (nseg + 1));
+    hipLaunchKernelGGL((k_line_rows<0>), dim3(static_cast<unsigned>(nseg)), dim3(kLineThreads), 0, c->stream, lg,
                        ds->cell_start, lpad.as<int32_t>(), nullptr, nullptr);
     check_launch("line rows");
-    scan_i32_to_i64(c, lpad.as<int32_t>(), loff.as<int64_t>(), nlines);
-    m->ntrow = read_i64(c, loff.as<int64_t>() + nlines);
+    scan_i32_to_i64(c, lpad.as<int32_t>(), loff.as<int64_t>(), nseg);
+    m->ntrow = read_i64(c, loff.as<int64_t>() + nseg);
     GPS_REQUIRE(m->ntrow < (int64_t(1) << 31), GP_ENOMEM, "quad build: too many rows");
     m->trow = dev_new<int32_t>(c, std::max<int64_t>(m->ntrow, 1));
     TmpBuf trow(c, sizeof(int32_t) * std::max<int64_t>(m->ntrow, 1));
-    hipLaunchKernelGGL((k_line_rows<1>), dim3(static_cast<unsigned>(nlines)), dim3(kLineThreads), 0, c->stream, lg,
+    hipLaunchKernelGGL((k_line_rows<1>), dim3(static_cast<unsigned>(nseg)), dim3(kLineThreads), 0, c->stream, lg,
                        ds->cell_start, nullptr, loff.as<int64_t>(), trow.as<int32_t>());
     check_launch("line rows");
     const int64_t ng = m->ntrow / kQuad;
