@@ -157,23 +157,24 @@ __global__ void __launch_bounds__(kThreads) k_fvals(KernelTheta kt, int64_t n, i
 }
 
 // One block per distinct mask M: U_M = masked points q (ascending) with M(q) & M != 0.
-__global__ void __launch_bounds__(kThreads) k_ulists(int64_t nm, const uint64_t* __restrict__ mmask,
-                                                     const int32_t* __restrict__ mlist,
-                                                     const uint64_t* __restrict__ dmask,
-                                                     const int64_t* __restrict__ uoff, int32_t* __restrict__ ulist) {
-  __shared__ int32_t wcount[kThreads / kWave];
+constexpr int kUlThreads = 1024;
+__global__ void __launch_bounds__(kUlThreads) k_ulists(int64_t nm, const uint64_t* __restrict__ mmask,
+                                                       const int32_t* __restrict__ mlist,
+                                                       const uint64_t* __restrict__ dmask,
+                                                       const int64_t* __restrict__ uoff, int32_t* __restrict__ ulist) {
+  __shared__ int32_t wcount[kUlThreads / kWave];
   const uint64_t M = dmask[blockIdx.x];
   int32_t* out = ulist + uoff[blockIdx.x];
   const int w = threadIdx.x / kWave;
   int64_t running = 0;
-  for (int64_t b = 0; b < nm; b += kThreads) {
+  for (int64_t b = 0; b < nm; b += kUlThreads) {
     const int64_t k = b + threadIdx.x;
     const bool hit = k < nm && (mmask[k] & M) != 0;
     const uint64_t bal = __ballot(hit);
     if (lane_id() == 0) wcount[w] = __popcll(bal);
     __syncthreads();
     int64_t before = 0, total = 0;
-    for (int i = 0; i < kThreads / kWave; ++i) {
+    for (int i = 0; i < kUlThreads / kWave; ++i) {
       if (i < w) before += wcount[i];
       total += wcount[i];
     }
@@ -967,7 +968,7 @@ gp_matrix* assemble(gp_ctx* c, const gp_dataset* ds, const gp_theta* th, int pre
     put(tiles.data(), b_ti, m->g_tiles);
     if (nD) {
       ProfScope ps(c, "asm_group_lists");
-      hipLaunchKernelGGL(k_ulists, dim3(static_cast<unsigned>(nD)), dim3(kThreads), 0, c->stream, nm, mmask, f.mlist,
+      hipLaunchKernelGGL(k_ulists, dim3(static_cast<unsigned>(nD)), dim3(kUlThreads), 0, c->stream, nm, mmask, f.mlist,
                          d_dmask, d_uoff, d_ulist);
       check_launch("group lists");
     }

@@ -1,6 +1,6 @@
-// Deterministic device-wide exclusive scan (three passes, fixed order).
-// Wave64 inclusive scan by shuffles, then an LDS scan of wave totals per block,
-// then a single-block scan of block totals.
+// Deterministic device-wide exclusive scan of integers (two passes): per-tile
+// sums, then per tile a wave64 inclusive scan by shuffles and an LDS scan of
+// wave totals, offset by the sum of the earlier tiles' sums.
 #include "internal.hpp"
 
 namespace gps {
@@ -56,25 +56,28 @@ __global__ void __launch_bounds__(kScanThreads) k_tile_sums(const TI* __restrict
   if (threadIdx.x == 0) tile_sum[blockIdx.x] = tot;
 }
 
-// Exclusive scan of the tile sums in place by one block; writes the total to *total.
+// Sum of the tile sums before this block's tile (integers: exact in any order).
 template <typename TO>
-__global__ void __launch_bounds__(kScanThreads) k_scan_tiles(TO* __restrict__ tile_sum, int64_t ntiles,
-                                                             TO* __restrict__ total) {
-  TO carry = 0;
-  for (int64_t b = 0; b < ntiles; b += kScanThreads) {
-    const int64_t i = b + threadIdx.x;
-    TO v = i < ntiles ? tile_sum[i] : 0;
-    TO ex;
-    TO tot = block_exclusive_scan<TO>(v, &ex);
-    if (i < ntiles) tile_sum[i] = carry + ex;
-    carry += tot;
-  }
-  if (threadIdx.x == 0) *total = carry;
+__device__ __forceinline__ TO tiles_before(const TO* __restrict__ tile_sum) {
+  __shared__ TO red[kScanThreads / kWave];
+  TO v = 0;
+  for (unsigned t = threadIdx.x; t < blockIdx.x; t += kScanThreads) v += tile_sum[t];
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = v;
+  __syncthreads();
+  TO s = 0;
+#pragma unroll
+  for (int i = 0; i < kScanThreads / kWave; ++i) s += red[i];
+  __syncthreads();
+  return s;
 }
 
+// Each block adds the tile sums before its tile itself, so no pass scans the
+// tile sums; the last block also writes the total to out[n].
 template <typename TI, typename TO>
 __global__ void __launch_bounds__(kScanThreads) k_scan_apply(const TI* __restrict__ in, int64_t n,
-                                                             const TO* __restrict__ tile_off,
+                                                             const TO* __restrict__ tile_sum,
                                                              TO* __restrict__ out) {
   // each thread owns kScanItems consecutive elements of the tile
   __shared__ TI stage[kScanTile];
@@ -93,8 +96,10 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_apply(const TI* __restric
     s += static_cast<TO>(stage[threadIdx.x * kScanItems + i]);
   }
   TO ex;
-  block_exclusive_scan<TO>(s, &ex);
-  const TO off = tile_off[blockIdx.x] + ex;
+  const TO tile = block_exclusive_scan<TO>(s, &ex);
+  const TO before = tiles_before<TO>(tile_sum);
+  const TO off = before + ex;
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[n] = before + tile;
 #pragma unroll
   for (int i = 0; i < kScanItems; ++i) {
     const int64_t idx = base + static_cast<int64_t>(threadIdx.x) * kScanItems + i;
@@ -102,22 +107,27 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_apply(const TI* __restric
   }
 }
 
+template <typename TO>
+__global__ void k_scan_zero(TO* __restrict__ out) { out[0] = 0; }
+
 template <typename TI, typename TO>
 void scan_impl(gp_ctx* c, const TI* in, TO* out, int64_t n) {
   const int64_t ntiles = (n + kScanTile - 1) / kScanTile;
-  TmpBuf tiles(c, sizeof(TO) * (ntiles > 0 ? ntiles : 1));
+  // the tile sums live in a work-space slot of the context: scans run one after
+  // another on its stream, and no allocation call sits between the launches
+  TO* tiles = static_cast<TO*>(workspace(c, 13, sizeof(TO) * (ntiles > 0 ? ntiles : 1)));
   if (n > 0) {
     hipLaunchKernelGGL((k_tile_sums<TI, TO>), dim3(static_cast<unsigned>(ntiles)), dim3(kScanThreads), 0,
-                       c->stream, in, n, tiles.as<TO>());
+                       c->stream, in, n, tiles);
     check_launch("scan tile sums");
   }
-  hipLaunchKernelGGL((k_scan_tiles<TO>), dim3(1), dim3(kScanThreads), 0, c->stream, tiles.as<TO>(), ntiles,
-                     out + n);
-  check_launch("scan tiles");
   if (n > 0) {
     hipLaunchKernelGGL((k_scan_apply<TI, TO>), dim3(static_cast<unsigned>(ntiles)), dim3(kScanThreads), 0,
-                       c->stream, in, n, tiles.as<TO>(), out);
+                       c->stream, in, n, tiles, out);
     check_launch("scan apply");
+  } else {
+    hipLaunchKernelGGL((k_scan_zero<TO>), dim3(1), dim3(1), 0, c->stream, out);
+    check_launch("scan empty");
   }
 }
 
