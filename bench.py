@@ -4,9 +4,10 @@ Workload: the space-time data set (3,000 stations x 365 days, n = 1,095,000,
 d = 3; anisotropic Wendland radii (0.03, 0.03, 3 days); 16 x 4 space-time
 bumps; nugget 1e-2), resident on the device.  One step is one pass of the
 hot path for one hyper-parameter vector:
-    assemble K(theta) + sigma^2 I  ->  log-likelihood (Jacobi PCG for
-    y^T K^-1 y to rtol 1e-10, SLQ log det with 30 probes x 100 Lanczos steps,
-    the depth at which the estimate of this workload has converged: with 50
+    assemble K(theta) + sigma^2 I  ->  log-likelihood (block-Jacobi PCG for
+    y^T K^-1 y to rtol 1e-10, SLQ log det with 30 probes x 80 Lanczos steps,
+    a depth at which the estimate of this workload has converged to within
+    0.2 standard errors of its 128-step value for six probe seeds: with 50
     steps its quadrature bias is 0.1-0.3%, several standard errors)
     ->  posterior mean at 10,000 test points with the solved alpha.
 The mixed form (float32 values and PCG products, float64 residuals,
@@ -489,7 +490,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--fp64-steps", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--lanczos", type=int, default=100, help="Lanczos steps of the timed log det (30 probes)")
+    ap.add_argument("--lanczos", type=int, default=80, help="Lanczos steps of the timed log det (30 probes)")
     ap.add_argument("--stations", type=int, default=3000)
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=512)
