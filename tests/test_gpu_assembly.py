@@ -167,3 +167,35 @@ def test_invalid_theta_is_einval(ctx):
     with pytest.raises(GPError) as e:
         ctx.dataset(dev(x))
     assert e.value.name == "GP_EINVAL"
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-8), (1, 1e-5)])
+def test_sixty_four_groups(ctx, prec, tol):
+    """n1 = 64 groups, as many as a point's mask holds: masks use bit 63 and most
+    masked points lie in several groups (2.6 on average), so the shared lists
+    U_M are long and overlap.  Pattern and values, then the log-likelihood
+    against the oracle: exact log det; SLQ with the oracle's probes, plain
+    (whose three-term recurrence amplifies the two sides' different summation
+    orders: held to 1e-6) and with full re-orthogonalisation on both sides
+    (within the bar)."""
+    from oracle import likelihood, slq
+    from paper_2411_05869_amd import LOGDET_EXACT, LOGDET_SLQ_REORTH
+    p = uniform_problem(1200, 2, 64, r0=0.03, n1=64, n2=1, bump_radius=0.12)
+    K, rp, col, val = run_case(ctx, p, prec, what="64 groups")
+    Kd, _ = kernel.dense(p.x, p.theta)
+    y = np.linalg.cholesky(Kd) @ p.z_std
+    ref = likelihood.dense_cholesky(Kd, y)
+    r = ctx.loglik(K, dev(y), logdet_mode=LOGDET_EXACT)
+    seed = 64
+    opts = dict(seed=seed, n_probes=30, n_lanczos=50)
+    rs = ctx.loglik(K, dev(y), **opts)
+    ro = ctx.loglik(K, dev(y), logdet_mode=LOGDET_SLQ_REORTH, **opts)
+    o = slq.slq_logdet(Kd, seed=seed, n_probes=30, n_steps=50)
+    oo = slq.slq_logdet(Kd, seed=seed, n_probes=30, n_steps=50, reorth=True)
+    e_ll = rel(r["loglik"], ref["loglik"])
+    e_slq, e_ro = rel(rs["logdet"], o["logdet"]), rel(ro["logdet"], oo["logdet"])
+    print(f"[64 groups prec={prec}] nnz {K.nnz} ({K.nnz / p.n:.0f} per row); exact-mode loglik rel {e_ll:.2e}; "
+          f"SLQ against the oracle's SLQ: plain rel {e_slq:.2e}, re-orthogonalised rel {e_ro:.2e}")
+    assert r["status"] == 0 and rs["status"] == 0 and ro["status"] == 0
+    assert e_ll <= tol and e_ro <= tol
+    assert e_slq <= max(tol, 1e-6)
