@@ -275,14 +275,22 @@ def _can_batch_loglik(backend, a: LoglikRequest, b: LoglikRequest) -> bool:
 
 
 def latency_stats(comps: List[Completion]) -> dict:
+    """p50/p99/mean latency and throughput; ``mean_slots_busy`` is the time-average
+    number of slots running a request (or batch) between the first start and the
+    last completion."""
     ok = [c for c in comps if c.error is None]
     lat = np.array([c.latency for c in ok]) if ok else np.zeros(0)
     span = (max(c.done for c in ok) - min(c.arrival for c in ok)) if ok else float("nan")
+    # one interval per slot run (a batch's requests share it)
+    runs = {(c.slot, c.start, c.done) for c in ok}
+    busy_span = (max(c.done for c in ok) - min(c.start for c in ok)) if ok else float("nan")
+    busy = sum(e - s for _, s, e in runs) / busy_span if ok and busy_span > 0 else float("nan")
     return dict(completed=len(ok), failed=len(comps) - len(ok),
                 p50_ms=float(np.percentile(lat, 50) * 1e3) if lat.size else float("nan"),
                 p99_ms=float(np.percentile(lat, 99) * 1e3) if lat.size else float("nan"),
                 mean_ms=float(lat.mean() * 1e3) if lat.size else float("nan"),
-                throughput_per_s=len(ok) / span if ok and span > 0 else float("nan"))
+                throughput_per_s=len(ok) / span if ok and span > 0 else float("nan"),
+                mean_slots_busy=round(float(busy), 3))
 
 
 # ------------------------------------------------------------------ GPU backend

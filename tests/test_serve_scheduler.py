@@ -104,9 +104,13 @@ def test_slots_overlap():
     be = FakeBackend(4, work_s=0.05)
     reqs = [ll(10, 0.0) for _ in range(8)]
     t = time.perf_counter()
-    Server(be, 10_000).run(reqs)
+    comps = Server(be, 10_000).run(reqs)
     elapsed = time.perf_counter() - t
     assert elapsed < 0.05 * 8 * 0.6      # 8 x 50 ms of work on 4 slots
+    # the time-average number of busy slots: about 4 here, 1 on one slot
+    assert latency_stats(comps)["mean_slots_busy"] > 2.5
+    one = latency_stats(Server(FakeBackend(1, work_s=0.02), 10_000).run([ll(10, 0.0) for _ in range(4)]))
+    assert 0.9 <= one["mean_slots_busy"] <= 1.0 + 1e-9
 
 
 def test_prediction_requests_are_batched_and_split():
