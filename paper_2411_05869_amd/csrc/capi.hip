@@ -100,8 +100,54 @@ void fork_side(gp_ctx* c) {
   c->side_pending = true;
 }
 
+// units of side-stream work in flight at most; a unit of the SLQ log det is
+// one Lanczos step (about a millisecond at n = 10^6), so this covers the
+// main stream's host waits between its pumps
+constexpr int kSideAhead = 6;
+
+void side_install(gp_ctx* c, std::unique_ptr<SideFeed> f) {
+  GPS_REQUIRE(c->side_pending && !c->feed, GP_EDEVICE, "internal: side work installed twice");
+  c->feed = std::move(f);
+  c->feed_issued = c->feed_done = 0;
+  side_pump(c);
+}
+
+void side_pump(gp_ctx* c) {
+  if (!c->feed) return;
+  if (c->feed_ev.empty()) {
+    c->feed_ev.resize(kSideAhead + 1, nullptr);
+    for (hipEvent_t& e : c->feed_ev) GPS_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  }
+  const int64_t ring = static_cast<int64_t>(c->feed_ev.size());
+  while (c->feed_done < c->feed_issued) {
+    const hipError_t q = hipEventQuery(c->feed_ev[c->feed_done % ring]);
+    if (q == hipErrorNotReady) break;
+    GPS_HIP(q);
+    ++c->feed_done;
+  }
+  // an event slot is recorded again only after its previous unit has completed
+  while (c->feed && c->feed_issued - c->feed_done < kSideAhead) {
+    bool more;
+    {
+      SideScope side(c);
+      more = c->feed->unit(c);
+      GPS_HIP(hipEventRecord(c->feed_ev[c->feed_issued % ring], c->stream));
+    }
+    ++c->feed_issued;
+    if (!more) c->feed.reset();
+  }
+}
+
 void join_side(gp_ctx* c) {
   if (!c->side_pending) return;
+  while (c->feed) {  // the units not enqueued yet
+    bool more;
+    {
+      SideScope side(c);
+      more = c->feed->unit(c);
+    }
+    if (!more) c->feed.reset();
+  }
   GPS_HIP(hipEventRecord(c->ev_join, c->side));
   GPS_HIP(hipStreamWaitEvent(c->stream, c->ev_join, 0));
   c->side_pending = false;
@@ -271,12 +317,15 @@ gp_status gp_ctx_destroy(gp_ctx* c) {
     for (hipEvent_t e : c->evpool) (void)hipEventDestroy(e);
     if (c->ev_aux) (void)hipEventDestroy(c->ev_aux);
     c->evpool.clear();
+    c->feed.reset();
     if (c->side) {
       (void)hipStreamSynchronize(c->side);
       (void)hipStreamDestroy(c->side);
       (void)hipEventDestroy(c->ev_fork);
       (void)hipEventDestroy(c->ev_join);
     }
+    for (hipEvent_t e : c->feed_ev) (void)hipEventDestroy(e);
+    c->feed_ev.clear();
   });
   delete c;
   return st;
@@ -298,6 +347,26 @@ gp_status gp_profile_enable(gp_ctx* c, int32_t on) {
     c->evnext = 0;
     c->prof_on = on != 0;
   });
+}
+
+gp_status gp_profile_only(gp_ctx* c, const char* names) {
+  if (!c) return GP_EINVAL;
+  std::vector<std::string> v;
+  if (names) {
+    std::string cur;
+    for (const char* q = names;; ++q) {
+      if (*q == ',' || *q == '\0') {
+        if (cur.size() > 31) return GP_EINVAL;
+        if (!cur.empty()) v.push_back(cur);
+        cur.clear();
+        if (*q == '\0') break;
+      } else {
+        cur.push_back(*q);
+      }
+    }
+  }
+  c->prof_only = std::move(v);
+  return GP_OK;
 }
 
 gp_status gp_profile_read(gp_ctx* c, int32_t max_entries, gp_profile_entry* out, int32_t* n_out) {
@@ -500,11 +569,7 @@ static gp_status loglik_common(gp_ctx* c, const gp_matrix* m, const double* y, c
       gps::build_product_caches(c, mm);
       gps::slq_reserve(c, m, o.n_probes, o.n_lanczos, reorth);
       dld = static_cast<gps::DeviceLogdet*>(gps::workspace(c, 126, sizeof(gps::DeviceLogdet)));
-      if (c->concurrent) {
-        gps::fork_side(c);
-        gps::SideScope side(c);
-        gps::slq_logdet_device(c, m, o.seed, o.n_probes, o.n_lanczos, reorth, dld);
-      }
+      if (c->concurrent) gps::slq_logdet_side(c, m, o.seed, o.n_probes, o.n_lanczos, reorth, dld);
     }
     gps::SolveResult sr;
     if (o.solver != GP_SOLVER_MINRES) {
@@ -621,9 +686,7 @@ gp_status gp_loglik_async(gp_ctx* c, const gp_matrix* m, const double* y, const 
     gps::JoinGuard join{c};
     if (with_logdet && c->concurrent) {
       gps::slq_reserve(c, m, o.n_probes, o.n_lanczos, reorth);
-      gps::fork_side(c);
-      gps::SideScope side(c);
-      gps::slq_logdet_device(c, m, o.seed, o.n_probes, o.n_lanczos, reorth, ld);
+      gps::slq_logdet_side(c, m, o.seed, o.n_probes, o.n_lanczos, reorth, ld);
     }
     gps::DeviceSolve sv{};
     gps::pcg_solve_device(c, mm, yb, xb, o.rtol, o.max_iter, o.precond, &sv);
@@ -705,9 +768,7 @@ gp_status gp_loglik_batch(gp_ctx* c, int32_t nreq, const gp_matrix* const* K, co
     b.nmax = nmax;
     if (with_logdet && c->concurrent) {
       gps::slq_reserve(c, S.get(), o.n_probes, o.n_lanczos, false, R);
-      gps::fork_side(c);
-      gps::SideScope side(c);
-      gps::slq_logdet_batch(c, S.get(), o.seed, o.n_probes, o.n_lanczos, b, ld);
+      gps::slq_batch_side(c, S.get(), o.seed, o.n_probes, o.n_lanczos, b, ld);
     }
     gps::DeviceSolve sv{};
     gps::pcg_solve_batch(c, S.get(), yb, xb, o.rtol, o.max_iter, o.precond, R, doff, nmax, &sv);

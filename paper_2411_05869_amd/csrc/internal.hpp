@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <cstdio>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -50,6 +51,14 @@ inline unsigned grid_for(int64_t items, int per_block) {
   return static_cast<unsigned>(g < 1 ? 1 : g);
 }
 
+// Work for the side stream handed over one unit at a time (see side_pump).
+struct SideFeed {
+  virtual ~SideFeed() = default;
+  // enqueues the next unit on c->stream (the side stream while it runs);
+  // false once the last unit has been enqueued
+  virtual bool unit(gp_ctx* c) = 0;
+};
+
 }  // namespace gps
 
 // ---------------------------------------------------------------- objects
@@ -81,6 +90,7 @@ struct gp_ctx {
     hipEvent_t a, b;
   };
   std::vector<ProfRec> prof;
+  std::vector<std::string> prof_only;  // names timed (empty: all)
   std::vector<hipEvent_t> evpool;
   size_t evnext = 0;
   // second stream for independent work of one call (the log det beside the
@@ -90,6 +100,11 @@ struct gp_ctx {
   bool side_pending = false;  // work was forked to the side stream and not joined yet
   bool alloc_locked = false;  // set while work is enqueued on the side stream
   bool concurrent = true;     // the log det of a likelihood on the side stream
+  // side-stream work not enqueued yet, and a ring of events marking the
+  // completion of its latest units (side_pump)
+  std::unique_ptr<gps::SideFeed> feed;
+  std::vector<hipEvent_t> feed_ev;
+  int64_t feed_issued = 0, feed_done = 0;
 };
 
 struct gp_dataset {
@@ -248,6 +263,16 @@ void sync(gp_ctx* c);
 // join_side() orders the main stream after the side stream's work.
 void fork_side(gp_ctx* c);
 void join_side(gp_ctx* c);
+// A long side-stream sequence (the SLQ log det: several hundred launches) is
+// not enqueued in one go: once the device queue is full the host blocks in
+// the launch until the side stream has drained part of it, and the main
+// stream's launches, issued after it, start late.  side_install() takes such
+// work after fork_side() (its set-up already enqueued on the side stream);
+// side_pump() keeps a few of its units in flight and is called from the main
+// stream's host loops; join_side() enqueues the units still left before it
+// joins.
+void side_install(gp_ctx* c, std::unique_ptr<SideFeed> f);
+void side_pump(gp_ctx* c);
 struct SideScope {
   gp_ctx* c;
   hipStream_t main;
@@ -266,6 +291,7 @@ struct SideScope {
 struct JoinGuard {
   gp_ctx* c;
   ~JoinGuard() {
+    c->feed.reset();  // after an error: units not yet enqueued are dropped
     if (c->side_pending) {
       (void)hipEventRecord(c->ev_join, c->side);
       (void)hipStreamWaitEvent(c->stream, c->ev_join, 0);
@@ -305,7 +331,7 @@ struct ProfScope {
   const char* name;
   hipEvent_t a = nullptr;
   ProfScope(gp_ctx* c_, const char* n) : c(c_), name(n) {
-    if (c->prof_on) {
+    if (c->prof_on && timed(n)) {
       a = prof_event(c);
       (void)hipEventRecord(a, c->stream);
     }
@@ -316,6 +342,12 @@ struct ProfScope {
       (void)hipEventRecord(b, c->stream);
       c->prof.push_back({name, a, b});
     }
+  }
+  bool timed(const char* n) const {
+    if (c->prof_only.empty()) return true;
+    for (const std::string& o : c->prof_only)
+      if (o == n) return true;
+    return false;
   }
 };
 
@@ -457,6 +489,10 @@ struct DeviceLogdet {
 // writes the SLQ estimate into out (device memory)
 void slq_logdet_device(gp_ctx* c, const gp_matrix* m, uint64_t seed, int n_probes, int n_steps, bool reorth,
                        DeviceLogdet* out);
+// the same on the side stream beside the main stream's work: forks, enqueues
+// the set-up and hands the Lanczos steps to side_install (one unit per step)
+void slq_logdet_side(gp_ctx* c, const gp_matrix* m, uint64_t seed, int n_probes, int n_steps, bool reorth,
+                     DeviceLogdet* out);
 // allocates (in the main stream's order) the work space slq_logdet_device and
 // slq_logdet_batch (R problems of n stacked rows) will use, so that they can
 // be enqueued on the side stream without allocating
@@ -473,6 +509,10 @@ struct SlqBatch {
 };
 void slq_logdet_batch(gp_ctx* c, const gp_matrix* m, uint64_t seed, int n_probes, int n_steps, const SlqBatch& b,
                       DeviceLogdet* out);
+// the batch estimate on the side stream (as slq_logdet_side; b is copied, the
+// device arrays it points to must live until the join)
+void slq_batch_side(gp_ctx* c, const gp_matrix* m, uint64_t seed, int n_probes, int n_steps, const SlqBatch& b,
+                    DeviceLogdet* out);
 
 // deterministic reductions
 double dot_f64(gp_ctx* c, const double* a, const double* b, int64_t n);   // synchronising

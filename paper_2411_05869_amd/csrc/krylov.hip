@@ -873,6 +873,7 @@ SolveResult pcg_solve(gp_ctx* c, gp_matrix* m, const double* y, double* x, doubl
   const dim3 G(kRedBlocks), B(kThreads);
   auto read = [&]() {
     GPS_HIP(hipMemcpyAsync(hs, s, sizeof(CgScalars), hipMemcpyDeviceToHost, c->stream));
+    side_pump(c);  // the side stream's queue topped up before the host waits
     sync(c);
     return *hs;
   };
@@ -928,6 +929,7 @@ SolveResult pcg_solve(gp_ctx* c, gp_matrix* m, const double* y, double* x, doubl
           hipLaunchKernelGGL(k_beta_fin, dim3(1), B, 0, c->stream, spart, static_cast<int>(nbs), s, 3);
       }
       check_launch("pcg iteration");
+      side_pump(c);
     }
     it += steps;
     sc = read();
@@ -1140,6 +1142,7 @@ static void pcg_device_impl(gp_ctx* c, gp_matrix* m, const double* y, double* x,
       else
         hipLaunchKernelGGL(k_beta_fin, G1, B, 0, c->stream, spart, static_cast<int>(nbs), s, 3, skip_iter, g,
                            kThreads * kStepRows);
+      side_pump(c);
     }
     hipLaunchKernelGGL(k_ctl_check, dim3(1), C, 0, c->stream, s, ctl, steps, R, all);
     true_residual(skip_true, &all->skip_true);
@@ -1148,6 +1151,7 @@ static void pcg_device_impl(gp_ctx* c, gp_matrix* m, const double* y, double* x,
     check_launch("pcg iteration block");
     if (poll) {
       GPS_HIP(hipMemcpyAsync(hflag, &all->skip_iter, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+      side_pump(c);
       sync(c);
       if (*hflag) break;
     }
@@ -1341,6 +1345,7 @@ SolveResult minres_solve(gp_ctx* c, gp_matrix* m, const double* y, double* x, bo
   const dim3 G(kRedBlocks), B(kThreads);
   auto read = [&]() {
     GPS_HIP(hipMemcpyAsync(hs, s, sizeof(MrScalars), hipMemcpyDeviceToHost, c->stream));
+    side_pump(c);
     sync(c);
     return *hs;
   };
@@ -1393,6 +1398,7 @@ SolveResult minres_solve(gp_ctx* c, gp_matrix* m, const double* y, double* x, bo
       hipLaunchKernelGGL(k_mr_rotate, dim3(1), B, 0, c->stream, part, static_cast<int>(nbp), s);
       hipLaunchKernelGGL(k_mr_update, G, B, 0, c->stream, n, s, wa, wb, x, v, z);
       check_launch("minres step");
+      side_pump(c);
       // rotate: r1 <- r2, r2 <- rn; w1 <- w2, w2 <- the new w (written over w1)
       double* t1 = r1;
       r1 = r2;
@@ -1535,151 +1541,211 @@ static SlqBufs<T> slq_bufs(gp_ctx* c, int64_t n, int n_probes, int n_steps, bool
   return b;
 }
 
+// One SLQ estimate as a sequence of units, each one Lanczos step of the
+// current block of (at most 32) probes: the block's start before its first
+// step, its quadrature after its last, the estimate after the last block.
+// The constructor enqueues the set-up (column scale, Jacobi part).  With
+// dev_out every result stays on the device; without, the host reads each
+// block's quadratures (a synchronisation per block) and result() forms the
+// estimate.
+template <typename T>
+class SlqRun final : public SideFeed {
+ public:
+  SlqRun(gp_ctx* c, const gp_matrix* m, uint64_t seed, int n_probes, int n_steps, double tol, bool reorth,
+         DeviceLogdet* dev_out, const SlqBatch* bt)
+      : m_(m), n_(m->n), seed_(seed), n_probes_(n_probes), n_steps_(n_steps), tol_(tol), reorth_(reorth),
+        dev_out_(dev_out) {
+    // a batch: R problems stacked along the rows, each with its own Lanczos
+    // state, coefficients, partial sums and estimate (dev_out[r])
+    if (bt) {
+      batch_ = true;
+      bt_ = *bt;
+      R_ = bt->R;
+      gl_.off = gj_.off = bt->off;
+      gl_.pstride = 32 * kRedBlocks;
+      gj_.pstride = kRedBlocks;
+    }
+    nrow_ = batch_ ? bt_.nmax : n_;
+    tstride_ = static_cast<int64_t>(32) * n_steps;
+    perm_ = batch_ ? bt_.perm : m->ds->perm;
+    const bool dev = dev_out != nullptr;
+    bf_ = slq_bufs<T>(c, n_, n_probes, n_steps, reorth, R_, dev);
+    V_ = bf_.V;
+    Vp_ = bf_.Vp;
+    W_ = bf_.W;
+    const unsigned Ry = static_cast<unsigned>(R_);
+    hipLaunchKernelGGL((k_scale_vec<T>), dim3(grid_for(n_, kThreads)), dim3(kThreads), 0, c->stream, n_, m->diag,
+                       bf_.sc);
+    check_launch("slq scale");
+    if (dev) {
+      // Jacobi part, probe results and failure flags stay on the device
+      hipLaunchKernelGGL(k_logsum_part, dim3(kRedBlocks, Ry), dim3(kThreads), 0, c->stream, nrow_, m->diag, bf_.jpart,
+                         gj_);
+      hipLaunchKernelGGL(k_sum_part, dim3(1, Ry), dim3(kThreads), 0, c->stream, bf_.jpart, kRedBlocks, bf_.djac, gj_);
+      GPS_HIP(hipMemsetAsync(bf_.bad, 0, sizeof(int) * R_, c->stream));
+    } else {
+      jac_ = logsum_f64(c, m->diag, n_);
+    }
+  }
+
+  bool unit(gp_ctx* c) override {
+    if (p0_ >= n_probes_) return finish(c);
+    const int ld = 32;
+    const unsigned Ry = static_cast<unsigned>(R_);
+    const bool dev = dev_out_ != nullptr;
+    LzState* st = bf_.st;
+    if (j_ == 0) {
+      k_ = std::min(32, n_probes_ - p0_);
+      const double inv0 = 1.0 / std::sqrt(static_cast<double>(n_));  // v_1 = +-1 / sqrt(n)
+      if (dev) {
+        hipLaunchKernelGGL(k_lz_state_init, dim3(1, Ry), dim3(32), 0, c->stream, st, k_, inv0,
+                           batch_ ? bt_.inv0 : nullptr);
+      } else {
+        LzState init{};
+        for (int l = 0; l < 32; ++l) {
+          init.active[l] = l < k_ ? 1 : 0;
+          init.inv_cur[l] = l < k_ ? inv0 : 0.0;
+        }
+        LzState* hst = static_cast<LzState*>(pinned_for_write(c, sizeof(LzState)));
+        *hst = init;
+        h2d_async(c, st, hst, sizeof(LzState));
+        GPS_HIP(hipMemsetAsync(bf_.bad, 0, sizeof(int), c->stream));
+      }
+      hipLaunchKernelGGL((k_lz_init<T>), dim3(grid_for(n_ * ld, kThreads)), dim3(kThreads), 0, c->stream, n_, k_, ld,
+                         p0_, seed_, perm_, V_, Vp_);
+      check_launch("lanczos init");
+    }
+    if (j_ < n_steps_) {
+      step(c, j_);
+      if (++j_ < n_steps_) return true;
+    }
+    hipLaunchKernelGGL(k_quadrature, dim3((k_ + kQuadProbes - 1) / kQuadProbes, Ry), dim3(kQuadProbes), 0,
+                       c->stream, k_, bf_.Ta, bf_.Tb, st, static_cast<double>(n_), bf_.gam, bf_.bad, gl_, tstride_);
+    check_launch("quadrature");
+    if (dev) {
+      hipLaunchKernelGGL(k_slq_collect, dim3(1, Ry), dim3(32), 0, c->stream, st, bf_.gam, k_, p0_, bf_.gam_all,
+                         bf_.steps_all, n_probes_);
+      check_launch("slq collect");
+    } else {
+      double* hg = static_cast<double*>(pinned(c, sizeof(double) * 32 + sizeof(LzState) + 16));
+      GPS_HIP(hipMemcpyAsync(hg, bf_.gam, sizeof(double) * 32, hipMemcpyDeviceToHost, c->stream));
+      LzState* hs2 = reinterpret_cast<LzState*>(hg + 32);
+      GPS_HIP(hipMemcpyAsync(hs2, st, sizeof(LzState), hipMemcpyDeviceToHost, c->stream));
+      int* hb = reinterpret_cast<int*>(reinterpret_cast<char*>(hs2) + sizeof(LzState));
+      GPS_HIP(hipMemcpyAsync(hb, bf_.bad, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+      sync(c);
+      for (int l = 0; l < k_; ++l) {
+        gammas_.push_back(hg[l]);
+        max_steps_ = std::max(max_steps_, hs2->steps[l]);
+      }
+      nbad_ |= *hb;
+    }
+    j_ = 0;
+    p0_ += 32;
+    if (p0_ < n_probes_) return true;
+    return finish(c);
+  }
+
+  // the host-driven form's estimate, after the last unit
+  LogdetResult result() const {
+    LogdetResult res;
+    if (dev_out_) return res;
+    double mean = 0;
+    for (double g : gammas_) mean += g;
+    mean /= static_cast<double>(gammas_.size());
+    double var = 0;
+    for (double g : gammas_) var += (g - mean) * (g - mean);
+    res.se = gammas_.size() > 1 ? std::sqrt(var / static_cast<double>(gammas_.size() - 1) / gammas_.size()) : 0.0;
+    res.logdet = jac_ + mean;
+    res.steps = max_steps_;
+    if (nbad_ & 2) res.st = GP_ENOTPD;
+    if (nbad_ & 1) res.st = GP_EDEVICE;
+    return res;
+  }
+
+ private:
+  // the estimate from the per-probe results (device-driven form); no units left
+  bool finish(gp_ctx* c) {
+    if (dev_out_ && !finished_) {
+      hipLaunchKernelGGL(k_slq_final, dim3(1, static_cast<unsigned>(R_)), dim3(1), 0, c->stream, bf_.gam_all,
+                         bf_.steps_all, n_probes_, bf_.djac, bf_.bad, dev_out_);
+      check_launch("slq final");
+    }
+    finished_ = true;
+    return false;
+  }
+
+  // Lanczos step j of the current block
+  void step(gp_ctx* c, int j) {
+    const int ld = 32;
+    const unsigned Ry = static_cast<unsigned>(R_);
+    const int last = j == n_steps_ - 1;
+    LzState* st = bf_.st;
+    double* part = bf_.part;
+    // W = A v_j (a batch applies each problem's column factors afterwards)
+    spmm<T>(c, m_, ld, ld, V_, W_, bf_.sc, batch_ ? nullptr : st->inv_cur);
+    if (batch_)
+      hipLaunchKernelGGL(k_lz_colscale, dim3(grid_for(nrow_ * 32, kThreads), Ry), dim3(kThreads), 0, c->stream,
+                         nrow_, k_, ld, st, W_, gl_);
+    ProfScope ps(c, "lanczos_vector_ops");
+    hipLaunchKernelGGL((k_lz_beta_dot<T>), dim3(kRedBlocks, Ry), dim3(kThreads), 0, c->stream, nrow_, ld, st, V_, Vp_,
+                       W_, part, gl_);
+    hipLaunchKernelGGL(k_lz_fin, dim3(1, Ry), dim3(kFinGroups * 32), 0, c->stream, part, kRedBlocks, k_, 0, j, last,
+                       tol_, st, bf_.Ta, bf_.Tb, gl_, tstride_);
+    hipLaunchKernelGGL((k_lz_alpha_norm<T>), dim3(kRedBlocks, Ry), dim3(kThreads), 0, c->stream, nrow_, ld, st, V_,
+                       W_, part, gl_);
+    if (reorth_) {
+      // W -= Q Q^T W twice over q_0 .. q_j, then |W|^2 afresh
+      double* Qj = bf_.Qall + static_cast<int64_t>(j) * n_ * ld;
+      hipLaunchKernelGGL(k_lz_store_q, dim3(grid_for(n_ * ld, kThreads)), dim3(kThreads), 0, c->stream, n_, V_, st,
+                         Qj);
+      for (int pass = 0; pass < 2; ++pass) {
+        hipLaunchKernelGGL(k_ro_dot, dim3(kRoBlocks, j + 1), dim3(kThreads), 0, c->stream, n_, bf_.Qall, W_,
+                           bf_.ropart);
+        hipLaunchKernelGGL(k_ro_fin, dim3(j + 1), dim3(32), 0, c->stream, bf_.ropart, kRoBlocks, bf_.H);
+        hipLaunchKernelGGL(k_ro_update, dim3(grid_for(n_ * ld, kThreads)), dim3(kThreads), 0, c->stream, n_, j + 1,
+                           bf_.Qall, bf_.H, W_);
+      }
+      hipLaunchKernelGGL(k_lz_norm, dim3(kRedBlocks), dim3(kThreads), 0, c->stream, n_, W_, part);
+      check_launch("lanczos reorthogonalisation");
+    }
+    hipLaunchKernelGGL(k_lz_fin, dim3(1, Ry), dim3(kFinGroups * 32), 0, c->stream, part, kRedBlocks, k_, 1, j, last,
+                       tol_, st, bf_.Ta, bf_.Tb, gl_, tstride_);
+    if (!last) {
+      // rotate: the residual block W holds the next (unnormalised) v
+      T* old_prev = Vp_;
+      Vp_ = V_;
+      V_ = W_;
+      W_ = old_prev;
+    }
+    check_launch("lanczos step");
+  }
+
+  const gp_matrix* m_;
+  int64_t n_, nrow_ = 0, tstride_ = 0;
+  uint64_t seed_;
+  int n_probes_, n_steps_, R_ = 1;
+  double tol_;
+  bool reorth_, batch_ = false, finished_ = false;
+  DeviceLogdet* dev_out_;
+  SlqBatch bt_;
+  Seg gl_, gj_;
+  const int32_t* perm_ = nullptr;
+  SlqBufs<T> bf_;
+  T *V_ = nullptr, *Vp_ = nullptr, *W_ = nullptr;
+  double jac_ = 0.0;
+  std::vector<double> gammas_;
+  int max_steps_ = 0, nbad_ = 0;
+  int p0_ = 0, j_ = 0, k_ = 0;  // current probe block and step
+};
+
 template <typename T>
 static LogdetResult slq_impl(gp_ctx* c, const gp_matrix* m, uint64_t seed, int n_probes, int n_steps, double tol,
                              bool reorth, DeviceLogdet* dev_out = nullptr, const SlqBatch* bt = nullptr) {
-  const int64_t n = m->n;
-  const int ld = 32;
-  // a batch: R problems stacked along the rows, each with its own Lanczos
-  // state, coefficients, partial sums and estimate (dev_out[r])
-  const int R = bt ? bt->R : 1;
-  const unsigned Ry = static_cast<unsigned>(R);
-  const int64_t nrow = bt ? bt->nmax : n;
-  Seg gl, gj;
-  if (bt) {
-    gl.off = gj.off = bt->off;
-    gl.pstride = 32 * kRedBlocks;
-    gj.pstride = kRedBlocks;
+  SlqRun<T> run(c, m, seed, n_probes, n_steps, tol, reorth, dev_out, bt);
+  while (run.unit(c)) {
   }
-  const int64_t tstride = static_cast<int64_t>(32) * n_steps;
-  const int32_t* perm = bt ? bt->perm : m->ds->perm;
-  const bool dev = dev_out != nullptr;
-  const SlqBufs<T> bf = slq_bufs<T>(c, n, n_probes, n_steps, reorth, R, dev);
-  double *Qall = bf.Qall, *ropart = bf.ropart, *H = bf.H;
-  T *V = bf.V, *Vp = bf.Vp, *W = bf.W, *sc = bf.sc;
-  double *part = bf.part, *Ta = bf.Ta, *Tb = bf.Tb, *gam = bf.gam;
-  LzState* st = bf.st;
-  int* bad = bf.bad;
-  hipLaunchKernelGGL((k_scale_vec<T>), dim3(grid_for(n, kThreads)), dim3(kThreads), 0, c->stream, n, m->diag, sc);
-  check_launch("slq scale");
-  double jac = 0.0;
-  double* djac = nullptr;
-  double* gam_all = nullptr;
-  int* steps_all = nullptr;
-  int* bad_all = nullptr;
-  if (dev) {
-    // Jacobi part, probe results and failure flags stay on the device
-    djac = bf.djac;
-    hipLaunchKernelGGL(k_logsum_part, dim3(kRedBlocks, Ry), dim3(kThreads), 0, c->stream, nrow, m->diag, bf.jpart,
-                       gj);
-    hipLaunchKernelGGL(k_sum_part, dim3(1, Ry), dim3(kThreads), 0, c->stream, bf.jpart, kRedBlocks, djac, gj);
-    gam_all = bf.gam_all;
-    steps_all = bf.steps_all;
-    bad_all = bad;
-    GPS_HIP(hipMemsetAsync(bad_all, 0, sizeof(int) * R, c->stream));
-  } else {
-    jac = logsum_f64(c, m->diag, n);
-  }
-  std::vector<double> gammas;
-  int max_steps = 0;
-  int nbad = 0;
-  for (int p0 = 0; p0 < n_probes; p0 += 32) {
-    const int k = std::min(32, n_probes - p0);
-    const double inv0 = 1.0 / std::sqrt(static_cast<double>(n));  // v_1 = +-1 / sqrt(n)
-    if (dev) {
-      hipLaunchKernelGGL(k_lz_state_init, dim3(1, Ry), dim3(32), 0, c->stream, st, k, inv0, bt ? bt->inv0 : nullptr);
-    } else {
-      LzState init{};
-      for (int l = 0; l < 32; ++l) {
-        init.active[l] = l < k ? 1 : 0;
-        init.inv_cur[l] = l < k ? inv0 : 0.0;
-      }
-      LzState* hst = static_cast<LzState*>(pinned_for_write(c, sizeof(LzState)));
-      *hst = init;
-      h2d_async(c, st, hst, sizeof(LzState));
-      GPS_HIP(hipMemsetAsync(bad, 0, sizeof(int), c->stream));
-    }
-    hipLaunchKernelGGL((k_lz_init<T>), dim3(grid_for(n * ld, kThreads)), dim3(kThreads), 0, c->stream, n, k, ld, p0,
-                       seed, perm, V, Vp);
-    check_launch("lanczos init");
-    for (int j = 0; j < n_steps; ++j) {
-      const int last = j == n_steps - 1;
-      // W = A v_j (a batch applies each problem's column factors afterwards)
-      spmm<T>(c, m, ld, ld, V, W, sc, bt ? nullptr : st->inv_cur);
-      if (bt)
-        hipLaunchKernelGGL(k_lz_colscale, dim3(grid_for(nrow * 32, kThreads), Ry), dim3(kThreads), 0, c->stream,
-                           nrow, k, ld, st, W, gl);
-      ProfScope ps(c, "lanczos_vector_ops");
-      hipLaunchKernelGGL((k_lz_beta_dot<T>), dim3(kRedBlocks, Ry), dim3(kThreads), 0, c->stream, nrow, ld, st, V, Vp,
-                         W, part, gl);
-      hipLaunchKernelGGL(k_lz_fin, dim3(1, Ry), dim3(kFinGroups * 32), 0, c->stream, part, kRedBlocks, k, 0, j, last,
-                         tol, st, Ta, Tb, gl, tstride);
-      hipLaunchKernelGGL((k_lz_alpha_norm<T>), dim3(kRedBlocks, Ry), dim3(kThreads), 0, c->stream, nrow, ld, st, V, W,
-                         part, gl);
-      if (reorth) {
-        // W -= Q Q^T W twice over q_0 .. q_j, then |W|^2 afresh
-        double* Qj = Qall + static_cast<int64_t>(j) * n * ld;
-        hipLaunchKernelGGL(k_lz_store_q, dim3(grid_for(n * ld, kThreads)), dim3(kThreads), 0, c->stream, n, V, st, Qj);
-        for (int pass = 0; pass < 2; ++pass) {
-          hipLaunchKernelGGL(k_ro_dot, dim3(kRoBlocks, j + 1), dim3(kThreads), 0, c->stream, n, Qall, W, ropart);
-          hipLaunchKernelGGL(k_ro_fin, dim3(j + 1), dim3(32), 0, c->stream, ropart, kRoBlocks, H);
-          hipLaunchKernelGGL(k_ro_update, dim3(grid_for(n * ld, kThreads)), dim3(kThreads), 0, c->stream, n, j + 1,
-                             Qall, H, W);
-        }
-        hipLaunchKernelGGL(k_lz_norm, dim3(kRedBlocks), dim3(kThreads), 0, c->stream, n, W, part);
-        check_launch("lanczos reorthogonalisation");
-      }
-      hipLaunchKernelGGL(k_lz_fin, dim3(1, Ry), dim3(kFinGroups * 32), 0, c->stream, part, kRedBlocks, k, 1, j, last,
-                         tol, st, Ta, Tb, gl, tstride);
-      if (!last) {
-        // rotate: the residual block W holds the next (unnormalised) v
-        T* old_prev = Vp;
-        Vp = V;
-        V = W;
-        W = old_prev;
-      }
-      check_launch("lanczos step");
-    }
-    hipLaunchKernelGGL(k_quadrature, dim3((k + kQuadProbes - 1) / kQuadProbes, Ry), dim3(kQuadProbes), 0, c->stream, k,
-                       Ta, Tb, st, static_cast<double>(n), gam, bad, gl, tstride);
-    check_launch("quadrature");
-    if (dev) {
-      hipLaunchKernelGGL(k_slq_collect, dim3(1, Ry), dim3(32), 0, c->stream, st, gam, k, p0, gam_all, steps_all,
-                         n_probes);
-      check_launch("slq collect");
-      continue;
-    }
-    double* hg = static_cast<double*>(pinned(c, sizeof(double) * 32 + sizeof(LzState) + 16));
-    GPS_HIP(hipMemcpyAsync(hg, gam, sizeof(double) * 32, hipMemcpyDeviceToHost, c->stream));
-    LzState* hs2 = reinterpret_cast<LzState*>(hg + 32);
-    GPS_HIP(hipMemcpyAsync(hs2, st, sizeof(LzState), hipMemcpyDeviceToHost, c->stream));
-    int* hb = reinterpret_cast<int*>(reinterpret_cast<char*>(hs2) + sizeof(LzState));
-    GPS_HIP(hipMemcpyAsync(hb, bad, sizeof(int), hipMemcpyDeviceToHost, c->stream));
-    sync(c);
-    for (int l = 0; l < k; ++l) {
-      gammas.push_back(hg[l]);
-      max_steps = std::max(max_steps, hs2->steps[l]);
-    }
-    nbad |= *hb;
-  }
-  LogdetResult res;
-  if (dev) {
-    hipLaunchKernelGGL(k_slq_final, dim3(1, Ry), dim3(1), 0, c->stream, gam_all, steps_all, n_probes, djac, bad_all,
-                       dev_out);
-    check_launch("slq final");
-    return res;
-  }
-  double mean = 0;
-  for (double g : gammas) mean += g;
-  mean /= static_cast<double>(gammas.size());
-  double var = 0;
-  for (double g : gammas) var += (g - mean) * (g - mean);
-  res.se = gammas.size() > 1 ? std::sqrt(var / static_cast<double>(gammas.size() - 1) / gammas.size()) : 0.0;
-  res.logdet = jac + mean;
-  res.steps = max_steps;
-  if (nbad & 2) res.st = GP_ENOTPD;
-  if (nbad & 1) res.st = GP_EDEVICE;
-  return res;
+  return run.result();
 }
 
 // Lanczos vectors, products and reductions are float64 for both forms; the
@@ -1694,6 +1760,28 @@ LogdetResult slq_logdet(gp_ctx* c, const gp_matrix* m, uint64_t seed, int n_prob
 void slq_logdet_device(gp_ctx* c, const gp_matrix* m, uint64_t seed, int n_probes, int n_steps, bool reorth,
                        DeviceLogdet* out) {
   slq_impl<double>(c, m, seed, n_probes, n_steps, 1e-10, reorth, out);
+}
+
+void slq_logdet_side(gp_ctx* c, const gp_matrix* m, uint64_t seed, int n_probes, int n_steps, bool reorth,
+                     DeviceLogdet* out) {
+  fork_side(c);
+  std::unique_ptr<SideFeed> run;
+  {
+    SideScope side(c);
+    run = std::make_unique<SlqRun<double>>(c, m, seed, n_probes, n_steps, 1e-10, reorth, out, nullptr);
+  }
+  side_install(c, std::move(run));
+}
+
+void slq_batch_side(gp_ctx* c, const gp_matrix* m, uint64_t seed, int n_probes, int n_steps, const SlqBatch& b,
+                    DeviceLogdet* out) {
+  fork_side(c);
+  std::unique_ptr<SideFeed> run;
+  {
+    SideScope side(c);
+    run = std::make_unique<SlqRun<double>>(c, m, seed, n_probes, n_steps, 1e-10, false, out, &b);
+  }
+  side_install(c, std::move(run));
 }
 
 void slq_reserve(gp_ctx* c, const gp_matrix* m, int n_probes, int n_steps, bool reorth, int R) {
