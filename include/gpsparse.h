@@ -122,6 +122,12 @@ typedef struct gp_profile_entry {
 } gp_profile_entry;
 GP_API gp_status gp_profile_enable(gp_ctx* ctx, int32_t on);
 GP_API gp_status gp_profile_read(gp_ctx* ctx, int32_t max_entries, gp_profile_entry* out, int32_t* n_out);
+/* Restricts the timing to the names in `names`, a comma-separated list as
+ * gp_profile_read reports them (NULL or "" times every name again).  Each
+ * timed launch group adds two events to its stream, so a caller timing one
+ * product in a measured region can leave the others untimed.  Kept until the
+ * next call; GP_EINVAL for a name longer than 31 characters. */
+GP_API gp_status gp_profile_only(gp_ctx* ctx, const char* names);
 
 /* ------------------------------------------------------------------ dataset
  * gp_dataset_create: copies and spatially bins n points (x_dev, n x d

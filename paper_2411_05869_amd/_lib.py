@@ -90,6 +90,7 @@ EXPORTS = [
     "gp_loglik_batch",
     "gp_solve_opts_default", "gp_loglik", "gp_solve", "gp_predictor_create", "gp_predictor_destroy",
     "gp_predict", "gp_predict_var", "gp_mean_residual", "gp_profile_enable", "gp_profile_read",
+    "gp_profile_only",
 ]
 
 
@@ -142,6 +143,7 @@ def lib():
     L.gp_predict_var.argtypes = [P, P, C.POINTER(CTheta), I64, P, C.POINTER(CSolveOpts), P, C.POINTER(CVarResult)]
     L.gp_profile_enable.argtypes = [P, I32]
     L.gp_profile_read.argtypes = [P, I32, C.POINTER(CProfileEntry), C.POINTER(I32)]
+    L.gp_profile_only.argtypes = [P, C.c_char_p]
     for name in EXPORTS:
         getattr(L, name).restype = st
     L.gp_last_error.restype = C.c_char_p
@@ -308,8 +310,11 @@ class Context:
         it fail with GPError status GP_ENOMEM."""
         self._check(self._L.gp_ctx_set_hbm_budget(self._h, int(nbytes)), "gp_ctx_set_hbm_budget")
 
-    def profile(self, on: bool = True):
-        """Start (and clear) or stop per-kernel event timing inside the library."""
+    def profile(self, on: bool = True, only=None):
+        """Start (and clear) or stop per-kernel event timing inside the library;
+        only: names to time (None: all of them)."""
+        names = ",".join(only) if only else None
+        self._check(self._L.gp_profile_only(self._h, names.encode() if names else None), "gp_profile_only")
         self._check(self._L.gp_profile_enable(self._h, 1 if on else 0), "gp_profile_enable")
 
     def profile_read(self) -> dict:

@@ -56,3 +56,26 @@ def test_concurrency_on_off_equal(prec):
         _same(b1, b0, f"gp_loglik_batch problem {i}")
     print(f"[concurrency prec={prec}] on and off equal: loglik {res[True][0][0]['loglik']:.12g}, "
           f"{res[True][1][0]['loglik']:.12g}")
+
+
+def test_profile_only_times_the_named_groups():
+    """gp_profile_only: with a list of names only those launch groups are timed
+    (two events each on their stream); what is timed does not change a result."""
+    from paper_2411_05869_amd import Context, GPError
+    ctx = Context()
+    p = config1()
+    y = dev(np.random.default_rng(5).standard_normal(p.n))
+    K = ctx.assemble(ctx.dataset(dev(p.x), cell=p.cell), p.theta, 1)
+    ctx.profile(True, only=["spmm", "spmv_f32val_f64"])
+    r1 = ctx.loglik(K, y, n_lanczos=20)
+    some = ctx.profile_read()
+    ctx.profile(True)
+    r2 = ctx.loglik(K, y, n_lanczos=20)
+    every = ctx.profile_read()
+    ctx.profile(False)
+    assert set(some) == {"spmm", "spmv_f32val_f64"}
+    assert some["spmm"][0] == 20 and some["spmv_f32val_f64"][0] >= r1["cg_iters"]
+    assert {"spmm", "spmv_f32val_f64", "pcg_vector_ops", "lanczos_vector_ops"} <= set(every)
+    _same(r1, r2, "timed subsets")
+    with pytest.raises(GPError):
+        ctx.profile(True, only=["x" * 32])
