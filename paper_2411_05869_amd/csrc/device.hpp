@@ -173,6 +173,11 @@ __device__ __forceinline__ uint64_t point_features(const KernelTheta& kt, const 
   return mask;
 }
 
+// Raises the issue priority of the calling wave over other waves on its SIMD.
+// The solver's kernels call it: with the log det's launches on a second
+// stream sharing the CUs, the solve is the longer chain of the two.
+__device__ __forceinline__ void solve_wave_priority() { __builtin_amdgcn_s_setprio(3); }
+
 // Workgroup b of a launch runs on XCD b % 8 (each XCD has its own L2).  This
 // maps b to a logical block index such that every XCD receives one contiguous
 // range of logical blocks; it is a bijection on [0, nb).

@@ -137,6 +137,7 @@ __global__ void __launch_bounds__(kThreads) k_pcg_step(int64_t n, Precond M, CgS
                                                        double* __restrict__ part, const int* __restrict__ skip,
                                                        Seg g = {}) {
   if (seg_skip(skip)) return;
+  solve_wave_priority();
   const int64_t o = seg_begin(g, n);
   if (g.off && static_cast<int>(blockIdx.x) >= seg_blocks(n, kThreads * kStepRows)) return;
   const int64_t e = o + n;  // rows o .. e of the stacked vectors (the preconditioner is indexed by stacked rows)
@@ -230,6 +231,7 @@ __global__ void __launch_bounds__(kThreads) k_pcg_direction(int64_t n, CgScalars
                                                             const double* __restrict__ z, double* __restrict__ p,
                                                             const int* __restrict__ skip, Seg g = {}) {
   if (seg_skip(skip)) return;
+  solve_wave_priority();
   const int64_t o = seg_begin(g, n);
   if (g.off) nb = seg_blocks(n, kThreads * kStepRows);  // the step's partials of this problem
   z += o;
@@ -328,6 +330,7 @@ __global__ void __launch_bounds__(kThreads) k_pq_part(int64_t n, const double* _
                                                       const QT* __restrict__ q, double* __restrict__ part,
                                                       const int* __restrict__ skip, Seg g = {}) {
   if (seg_skip(skip)) return;
+  solve_wave_priority();
   const int64_t o = seg_begin(g, n);
   p += o;
   q += o;

@@ -86,6 +86,7 @@ __global__ void __launch_bounds__(kThreads) k_spmv(int64_t n, unsigned nb_long, 
                                                    const XT* __restrict__ x, YT* __restrict__ y,
                                                    const int16_t* __restrict__ off16, const int* __restrict__ skip) {
   if (skip && *skip) return;  // a device-side decision cancelled this product
+  solve_wave_priority();
   if (blockIdx.x >= nb_long) {
     const unsigned b = xcd_remap(blockIdx.x - nb_long, gridDim.x - nb_long);
     const int64_t row = (b * static_cast<int64_t>(kThreads) + threadIdx.x) / kG;
@@ -396,6 +397,7 @@ __global__ void __launch_bounds__(kThreads) k_group_spmv(const int32_t* __restri
                                                          const XT* __restrict__ x, YT* __restrict__ y,
                                                          const int* __restrict__ skip) {
   if (skip && *skip) return;  // uniform over the launch
+  solve_wave_priority();
   __shared__ AT xs[kGChunk];
   constexpr int kRows = kTileRows / (kThreads / kWave);
   // tiles come largest first; block b runs on XCD b % 8, so every XCD gets an
