@@ -79,3 +79,37 @@ def test_profile_only_times_the_named_groups():
     _same(r1, r2, "timed subsets")
     with pytest.raises(GPError):
         ctx.profile(True, only=["x" * 32])
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_side_work_after_an_error_and_across_probe_blocks(prec):
+    """The log det is handed to the side stream a Lanczos step at a time.  A
+    likelihood that fails inside the solve (y holds a NaN: GP_EINVAL after the
+    log det has started) drops the steps not yet enqueued; the next call on the
+    same context is unaffected.  With 40 probes (two blocks of at most 32: the
+    first block's quadrature and the second block's start fall between units)
+    the estimate is bitwise the same beside the solve, after it, and on a fresh
+    context."""
+    import torch
+    from paper_2411_05869_amd import Context, GPError
+    p = config1()
+    y = np.random.default_rng(8).standard_normal(p.n)
+    bad = y.copy()
+    bad[17] = np.nan
+    ctx = Context()
+    K = ctx.assemble(ctx.dataset(dev(p.x), cell=p.cell), p.theta, prec)
+    opts = dict(n_probes=40, n_lanczos=30)
+    with pytest.raises(GPError) as e:
+        ctx.loglik(K, dev(bad), **opts)
+    assert e.value.name == "GP_EINVAL"
+    r_on = ctx.loglik(K, dev(y), **opts)
+    ctx.set_concurrency(False)
+    r_off = ctx.loglik(K, dev(y), **opts)
+    fresh = Context()
+    Kf = fresh.assemble(fresh.dataset(dev(p.x), cell=p.cell), p.theta, prec)
+    r_fresh = fresh.loglik(Kf, dev(y), **opts)
+    assert r_on["status"] == 0 and r_on["lanczos_steps"] > 0
+    _same(r_on, r_off, "beside vs after the solve")
+    _same(r_on, r_fresh, "after an error vs a fresh context")
+    print(f"[side work prec={prec}] loglik {r_on['loglik']:.12g} logdet {r_on['logdet']:.12g} "
+          f"+- {r_on['logdet_se']:.3g} (40 probes)")
