@@ -229,6 +229,80 @@ def summarize_stats(stats_csv, bench_json, command, top=40):
     print("\n".join(lines))
 
 
+OVERLAP_PROFILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                               "serving_overlap_mixture_4slots.md")
+
+
+def serve_overlap(n_requests):
+    """The first n_requests of the config-4 likelihood stream queued at once on 4
+    slots without batching (the run a kernel trace of the slots' overlap is
+    taken from); prints the host-side statistics as one JSON line."""
+    from paper_2411_05869_amd import PRECOND_JACOBI
+    from paper_2411_05869_amd.serve import GpuBackend, LoglikRequest, Server, latency_stats
+    from workloads import config4_requests
+    pool, reqs = config4_requests(n_requests=n_requests, rate=50.0)
+    be = GpuBackend(n_slots=4, solve_opts=dict(precond=PRECOND_JACOBI), batch_max_n=0)
+    for k, q in enumerate(pool):
+        be.add_dataset(f"d{k}", q.x, q.y, cell=q.cell, row_estimate=60.0)
+    requests = [LoglikRequest(f"d{k}", th, 1, arrival=0.0) for (_, k, th) in reqs]
+    comps = Server(be, hbm_budget=64 << 30).run(requests)
+    st = latency_stats(comps)
+    st.update(requests=len(requests), slots=4, saturation_evals_per_s=round(len(requests) / max(c.done for c in comps), 2))
+    print(json.dumps(st), flush=True)
+
+
+def summarize_overlap(trace_csv, bench_json, command):
+    """Writes the summary of a `rocprofv3 --kernel-trace` run of
+    `bench.py --serve-overlap`: from the first assembly kernel to the last
+    kernel, how long kernels of one, two, three or more HIP streams ran at
+    the same time (each slot has a main stream and a side stream for the log
+    det), and each stream's busy time."""
+    import csv
+    rows = list(csv.DictReader(open(trace_csv)))
+    t0 = min(int(r["Start_Timestamp"]) for r in rows if "k_mask" in r["Kernel_Name"])
+    ks = [(int(r["Start_Timestamp"]), int(r["End_Timestamp"]), r["Stream_Id"]) for r in rows
+          if int(r["Start_Timestamp"]) >= t0]
+    t1 = max(e for _, e, _ in ks)
+    ev = sorted([(s_, 1, st) for s_, _, st in ks] + [(e, -1, st) for _, e, st in ks], key=lambda v: (v[0], v[1]))
+    active = {}
+    at_least = {1: 0, 2: 0, 3: 0, 4: 0}
+    weighted = 0
+    last = t0
+    for t, d, st in ev:
+        nbusy = sum(1 for v in active.values() if v > 0)
+        for k in at_least:
+            if nbusy >= k:
+                at_least[k] += t - last
+        weighted += nbusy * (t - last)
+        last = t
+        active[st] = active.get(st, 0) + d
+    busy = {}
+    for s_, e, st in ks:
+        b = busy.setdefault(st, [0, 0])
+        b[0] += 1
+        b[1] += e - s_
+    span = t1 - t0
+    host = json.load(open(bench_json))
+    lines = ["# Overlap of the serving slots' kernels (config-4 mixture likelihoods, 4 slots)", "",
+             "`rocprofv3 --kernel-trace` of the command below on one MI355X (run from /tmp with TMPDIR=/tmp): "
+             f"the first {host['requests']} likelihood requests of the config-4 stream queued at once on 4 slots, "
+             "no batching. Each slot has its own HIP stream and context, and each context a second stream for the "
+             "log det. Times from the first assembly kernel to the end of the last kernel.", "", "```", command,
+             "```", "",
+             f"- span {span / 1e6:.1f} ms; kernels of at least 1 / 2 / 3 / 4 streams running: "
+             + " / ".join(f"{at_least[k] / 1e6:.1f} ms ({100 * at_least[k] / span:.0f}%)" for k in (1, 2, 3, 4)),
+             f"- streams with a kernel running, averaged over the time any runs: {weighted / max(at_least[1], 1):.2f}",
+             f"- host side (the same run): {host['saturation_evals_per_s']} evals/s, mean slots busy "
+             f"{host['mean_slots_busy']}, p50 {host['p50_ms']:.0f} ms, p99 {host['p99_ms']:.0f} ms", "",
+             "| stream | kernels | busy ms | busy % of span |", "|---|---:|---:|---:|"]
+    for st, (cnt, b) in sorted(busy.items(), key=lambda kv: -kv[1][1]):
+        lines.append(f"| {st} | {cnt} | {b / 1e6:.1f} | {100 * b / span:.0f} |")
+    lines.append("")
+    with open(OVERLAP_PROFILE, "w") as f:
+        f.write("\n".join(lines))
+    print("\n".join(lines))
+
+
 def cpu_baseline(p):
     """The oracle on a bounded sample of the same workload (same point density):
     stations in [0, 0.5]^2, days 0..72 -> about 55k points, 2.3M nonzeros."""
@@ -510,9 +584,19 @@ def main():
                     help="write the kernel-statistics summary from a rocprofv3 --stats run and exit")
     ap.add_argument("--summarize-pmc", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "COMMAND"),
                     help="write the SpMV traffic summary from two rocprofv3 --pmc output folders and exit")
+    ap.add_argument("--serve-overlap", type=int, default=0, metavar="REQUESTS",
+                    help="only queue the first REQUESTS config-4 likelihoods at once on 4 slots (trace runs)")
+    ap.add_argument("--summarize-overlap", nargs=3, metavar=("TRACE_CSV", "BENCH_JSON", "COMMAND"),
+                    help="write the slots' overlap summary from a rocprofv3 --kernel-trace run and exit")
     args = ap.parse_args()
     if args.summarize_pmc:
         summarize_pmc(*args.summarize_pmc)
+        return
+    if args.summarize_overlap:
+        summarize_overlap(*args.summarize_overlap)
+        return
+    if args.serve_overlap:
+        serve_overlap(args.serve_overlap)
         return
     if args.summarize_stats:
         summarize_stats(*args.summarize_stats)
