@@ -127,6 +127,25 @@ def vs_exact(r, workload):
                 loglik_rel=abs(r["loglik"] - g["loglik"]) / abs(g["loglik"]), exact_loglik=g["loglik"])
 
 
+ORACLE_SLQ = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests", "golden",
+                          "spacetime_n1095000_slq.json")
+
+
+def vs_oracle_slq(r, workload, seed, probes, steps):
+    """The GPU's SLQ log det against the oracle's with the same probes and step
+    count (plain Lanczos on both sides; tests/golden/make_spacetime_slq.py);
+    None when no stored estimate matches."""
+    try:
+        with open(ORACLE_SLQ) as f:
+            g = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if (g.get("workload"), g.get("seed"), g.get("probes"), g.get("steps")) != (workload, seed, probes, steps):
+        return None
+    return dict(logdet_rel=abs(r["logdet"] - g["logdet"]) / abs(g["logdet"]), oracle_logdet=g["logdet"],
+                seed=seed, probes=probes, steps=steps)
+
+
 def source_sha256(path):
     import hashlib
     with open(path, "rb") as f:
@@ -301,6 +320,46 @@ def summarize_overlap(trace_csv, bench_json, command):
     with open(OVERLAP_PROFILE, "w") as f:
         f.write("\n".join(lines))
     print("\n".join(lines))
+
+
+def cpu_serving(n_sample):
+    """The oracle on sampled serving requests, on this host (single-threaded
+    KD-tree, SuperLU and NumPy elementwise work): config 4, n_sample requests
+    of the 512-request stream (a seeded choice), each the exact log-likelihood
+    of its proposal on its data set (KD-tree pattern, float64 entries, SuperLU);
+    config 5, the posterior mean at 64 test points of the first request by the
+    oracle's cross-covariance rows over the 1,095,000 training points (any
+    fixed weight vector: the time does not depend on it).  Prints one JSON line."""
+    import numpy as np
+
+    from oracle import kernel, likelihood
+    from workloads import config3, config4_requests, config5_requests
+    pool, reqs = config4_requests(n_requests=512, rate=50.0)
+    pick = np.random.default_rng(44).choice(len(reqs), size=n_sample, replace=False)
+    lat, ns = [], []
+    for i in sorted(pick):
+        _, k, th = reqs[i]
+        q = pool[k]
+        t0 = time.perf_counter()
+        likelihood.sparse_lu(kernel.to_scipy(*kernel.sparse(q.x, th), q.n), q.y)
+        lat.append(time.perf_counter() - t0)
+        ns.append(q.n)
+        log(f"cpu serving: request {i} n={q.n} {lat[-1]:.2f} s")
+    p = config3()
+    xs = config5_requests(1)[0][:64]
+    w = np.random.default_rng(55).standard_normal(p.n)
+    t0 = time.perf_counter()
+    rp, cols, vals = kernel.cross_entries(xs, p.x, p.theta)
+    _ = np.array([vals[rp[s]:rp[s + 1]] @ w[cols[rp[s]:rp[s + 1]]] for s in range(xs.shape[0])])
+    tp = time.perf_counter() - t0
+    lat_s = sorted(lat)
+    out = dict(kind="oracle", host_cpus=os.cpu_count(),
+               loglik=dict(requests=n_sample, n=[int(v) for v in ns], mean_s=round(float(np.mean(lat)), 3),
+                           p50_s=round(lat_s[len(lat_s) // 2], 3), max_s=round(lat_s[-1], 3),
+                           evals_per_s=round(n_sample / float(np.sum(lat)), 3)),
+               predict=dict(points=int(xs.shape[0]), seconds=round(tp, 2), points_per_s=round(xs.shape[0] / tp, 2),
+                            training_points=int(p.n)))
+    print(json.dumps(out), flush=True)
 
 
 def cpu_baseline(p):
@@ -588,7 +647,12 @@ def main():
                     help="only queue the first REQUESTS config-4 likelihoods at once on 4 slots (trace runs)")
     ap.add_argument("--summarize-overlap", nargs=3, metavar=("TRACE_CSV", "BENCH_JSON", "COMMAND"),
                     help="write the slots' overlap summary from a rocprofv3 --kernel-trace run and exit")
+    ap.add_argument("--cpu-serving", type=int, default=0, metavar="REQUESTS",
+                    help="only time the oracle on REQUESTS sampled config-4 requests and 64 config-5 test points")
     args = ap.parse_args()
+    if args.cpu_serving:
+        cpu_serving(args.cpu_serving)
+        return
     if args.summarize_pmc:
         summarize_pmc(*args.summarize_pmc)
         return
@@ -771,11 +835,14 @@ def main():
                fp64=dict(value=round(evals_d, 4), unit="loglik evals/s", ms_per_step=round(1e3 * dt_d / args.fp64_steps, 2),
                          nnz_per_s=round(nnz / asm_wall_d, 1), assemble_ms=round(1e3 * asm_wall_d, 3),
                          assemble_kernels_ms=round(asm_ms_d, 3),
-                         loglik=r_d["loglik"], cg_iters=r_d["cg_iters"], vs_exact=vs_exact(r_d, p.name)),
+                         loglik=r_d["loglik"], cg_iters=r_d["cg_iters"], vs_exact=vs_exact(r_d, p.name),
+                         vs_oracle_slq=vs_oracle_slq(r_d, p.name, opts["seed"], opts["n_probes"],
+                                                     opts["n_lanczos"])),
                mixed=dict(loglik=r_m["loglik"], logdet=r_m["logdet"], quad=r_m["quad"], logdet_se=r_m["logdet_se"],
                           cg_iters=r_m["cg_iters"], refreshes=r_m["refreshes"], relres=r_m["relres"],
                           rel_vs_fp64=abs(r_m["loglik"] - r_d["loglik"]) / abs(r_d["loglik"]),
-                          vs_exact=vs_exact(r_m, p.name)),
+                          vs_exact=vs_exact(r_m, p.name),
+                          vs_oracle_slq=vs_oracle_slq(r_m, p.name, opts["seed"], opts["n_probes"], opts["n_lanczos"])),
                mixed_30x50=dict(value=round(2 / dt_50, 4), unit="loglik evals/s", ms_per_step=round(1e3 * dt_50 / 2, 2),
                                 logdet=r50["logdet"], logdet_se=r50["logdet_se"], vs_exact=vs_exact(r50, p.name)),
                binning_ms=round(1e3 * t_bin, 2),
