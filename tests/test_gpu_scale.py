@@ -49,6 +49,9 @@ from gpu_util import dev, host, rel
 pytestmark = pytest.mark.gpu
 
 N_ROWS = 100
+# plain Lanczos on both sides, different summation orders: held to this
+# relative bound (the recurrence amplifies rounding; see the SLQ tests)
+PLAIN_BOUND = 1e-6
 
 
 @pytest.fixture(scope="module")
@@ -263,6 +266,35 @@ def test_config3_loglik_against_exact(ctx, cfg3, prec, tol):
     assert r["status"] == 0 and all(d["status"] == 0 for d in deep) and e_quad <= tol
     assert all(abs(g) <= 3.0 for g in gaps)
     assert abs(gap) <= 5e-3 * abs(gold["logdet"])
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-8), (1, 1e-5)])
+def test_config3_slq_identical_probes(ctx, cfg3, prec, tol):
+    # The benchmark's log det (seed 2411, 30 probes x 80 Lanczos steps) against
+    # the oracle's SLQ with the same probes (tests/golden/spacetime_n1095000_slq.json):
+    # with full re-orthogonalisation on both sides within 1e-8 / 1e-5; plain
+    # Lanczos, whose recurrence amplifies the two sides' different summation
+    # orders, within PLAIN_BOUND.
+    from paper_2411_05869_amd import LOGDET_SLQ_REORTH
+    with open(os.path.join(os.path.dirname(__file__), "golden", "spacetime_n1095000_slq.json")) as f:
+        gold = json.load(f)
+    p, ds, _ = cfg3
+    assert gold["n"] == p.n and gold["workload"] == p.name
+    K = ctx.assemble(ds, p.theta, prec)
+    y = dev(p.y)
+    opts = dict(seed=gold["seed"], n_probes=gold["probes"], n_lanczos=gold["steps"])
+    r = ctx.loglik(K, y, **opts)
+    ro = ctx.loglik(K, y, logdet_mode=LOGDET_SLQ_REORTH, **opts)
+    K.close()
+    e = rel(r["logdet"], gold["logdet"])
+    eo = rel(ro["logdet"], gold["reorth"]["logdet"])
+    print(f"[cfg3 SLQ identical probes prec={prec}] plain: GPU {r['logdet']:.12g} oracle {gold['logdet']:.12g} "
+          f"rel {e:.2e}; re-orthogonalised: GPU {ro['logdet']:.12g} oracle {gold['reorth']['logdet']:.12g} "
+          f"rel {eo:.2e}")
+    assert r["status"] == 0 and r["lanczos_steps"] == max(gold["probe_steps"])
+    assert ro["status"] == 0 and ro["lanczos_steps"] == max(gold["reorth"]["probe_steps"])
+    assert e <= max(tol, PLAIN_BOUND)
+    assert eo <= tol
 
 
 @pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 2.0 ** -24 + 1e-12)])
