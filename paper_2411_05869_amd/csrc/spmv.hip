@@ -1063,21 +1063,33 @@ __global__ void __launch_bounds__(kThreads) k_spmm_quad(int64_t ngroups, const i
     for (int64_t j0 = s; j0 < e; j0 += kWave) {
       const int m = static_cast<int>(min<int64_t>(kWave, e - j0));
       wave_sync_lds();  // the previous chunk has been read
-      {
-        int32_t q = 0;
-        double v[kQuad] = {};
-        if (lane < m) {
-          q = qcol[j0 + lane];
-          const double sc = SCALE ? scale[q] : 1.0;
+      // Column ids are staged first and the first X rows requested while the
+      // column scales are still on their way; the weights (value times the
+      // column's scale) follow through the second stage.
+      int32_t q = 0;
+      VT raw[kQuad];
+      double sc = 1.0;
 #pragma unroll
-          for (int r = 0; r < kQuad; ++r) v[r] = static_cast<double>(qval[(j0 + lane) * kQuad + r]) * sc;
-        }
-        sq[w][lane] = q;
+      for (int r = 0; r < kQuad; ++r) raw[r] = VT(0);
+      if (lane < m) {
+        q = qcol[j0 + lane];
 #pragma unroll
-        for (int r = 0; r < kQuad; ++r) sv[w][lane][r] = v[r];
+        for (int r = 0; r < kQuad; ++r) raw[r] = qval[(j0 + lane) * kQuad + r];
       }
+      sq[w][lane] = q;
+      if (SCALE && lane < m) sc = scale[q];
       wave_sync_lds();
       const int nq = (m + V::kEpi - 1) / V::kEpi;
+      int32_t qn[kQuadUq];
+      V xn[kQuadUq];
+#pragma unroll
+      for (int u = 0; u < kQuadUq; ++u) {
+        qn[u] = sq[w][(V::kEpi * u + gs_lane) & (kWave - 1)];
+        __builtin_memcpy(xn[u].v, X + static_cast<int64_t>(qn[u]) * ld + cp * V::kCpl, 16);
+      }
+#pragma unroll
+      for (int r = 0; r < kQuad; ++r) sv[w][lane][r] = static_cast<double>(raw[r]) * sc;
+      wave_sync_lds();
       for (int i0 = 0; i0 < nq; i0 += kQuadUq) {
         int32_t qq[kQuadUq];
         double vv[kQuadUq][kQuad];
@@ -1089,9 +1101,14 @@ __global__ void __launch_bounds__(kThreads) k_spmm_quad(int64_t ngroups, const i
           for (int r = 0; r < kQuad; ++r) vv[u][r] = (i0 + u < nq) ? sv[w][idx][r] : 0.0;
         }
         V xv[kQuadUq];
+        if (i0 == 0) {
 #pragma unroll
-        for (int u = 0; u < kQuadUq; ++u)
-          __builtin_memcpy(xv[u].v, X + static_cast<int64_t>(qq[u]) * ld + cp * V::kCpl, 16);
+          for (int u = 0; u < kQuadUq; ++u) xv[u] = xn[u];
+        } else {
+#pragma unroll
+          for (int u = 0; u < kQuadUq; ++u)
+            __builtin_memcpy(xv[u].v, X + static_cast<int64_t>(qq[u]) * ld + cp * V::kCpl, 16);
+        }
 #pragma unroll
         for (int u = 0; u < kQuadUq; ++u)
 #pragma unroll
