@@ -113,3 +113,28 @@ def test_side_work_after_an_error_and_across_probe_blocks(prec):
     _same(r_on, r_fresh, "after an error vs a fresh context")
     print(f"[side work prec={prec}] loglik {r_on['loglik']:.12g} logdet {r_on['logdet']:.12g} "
           f"+- {r_on['logdet_se']:.3g} (40 probes)")
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_side_work_through_the_minres_fallback(prec):
+    """CG capped below convergence hands over to MINRES (GP_SOLVER_AUTO) while
+    the log det's Lanczos steps are handed to the side stream from both
+    solvers' loops: every result is bitwise the same with the log det beside
+    the solve and after it."""
+    from paper_2411_05869_amd import LOGDET_NONE, SOLVER_AUTO, SOLVER_CG, Context
+    ctx = Context()
+    p = config1()
+    y = dev(np.random.default_rng(9).standard_normal(p.n))
+    K = ctx.assemble(ctx.dataset(dev(p.x), cell=p.cell), p.theta, prec)
+    full = ctx.loglik(K, y, logdet_mode=LOGDET_NONE, solver=SOLVER_CG)
+    cap = max(8, int(0.75 * full["cg_iters"]))
+    res = {}
+    for on in (True, False):
+        ctx.set_concurrency(on)
+        res[on] = ctx.loglik(K, y, solver=SOLVER_AUTO, max_iter=cap, n_lanczos=40)
+    r = res[True]
+    print(f"[side work, MINRES fallback prec={prec}] cg {r['cg_iters']} + minres {r['minres_iters']}, "
+          f"loglik {r['loglik']:.12g}")
+    assert r["status"] == 0 and r["cg_iters"] == cap and r["minres_iters"] > 0
+    _same(res[True], res[False], "MINRES fallback beside vs after the solve")
+    assert res[True]["minres_iters"] == res[False]["minres_iters"]
