@@ -199,3 +199,52 @@ def test_sixty_four_groups(ctx, prec, tol):
     assert r["status"] == 0 and rs["status"] == 0 and ro["status"] == 0
     assert e_ll <= tol and e_ro <= tol
     assert e_slq <= max(tol, 1e-6)
+
+
+def _group_layout(x, theta):
+    """The grouping of the masked rows recomputed from the oracle's group
+    membership: distinct masks, list sizes |U_M| = sum of the rows of every
+    distinct mask sharing a group, entries in group blocks, and the list
+    entries the one- and multi-column products stage (per tile of 16 and per
+    super-tile of 64 rows of a mask)."""
+    M, _ = kernel.features(x, theta)
+    bits = (M.astype(np.uint64) << np.arange(M.shape[1], dtype=np.uint64)).sum(axis=1) if M.shape[1] else \
+        np.zeros(len(x), np.uint64)
+    masked = bits[bits != 0]
+    dm, mult = np.unique(masked, return_counts=True)
+    share = (dm[:, None] & dm[None, :]) != 0
+    nu = share.astype(np.int64) @ mult.astype(np.int64)
+    tiles = (mult + 15) // 16
+    stiles = (mult + 63) // 64
+    return dict(group_rows=int(len(masked)), group_masks=int(len(dm)), group_list_entries=int(nu.sum()),
+                nnz_group=int((mult * nu).sum()), gemv_stage_entries=int((tiles * nu).sum()),
+                gemm_stage_entries=int((stiles * nu).sum()))
+
+
+@pytest.mark.parametrize("case", ["64 groups", "config 1", "config 2", "one dense group", "no bumps"])
+def test_group_layout_against_oracle_membership(ctx, case):
+    """The grouping of the masked rows (distinct masks, their lists, the
+    tiles of the group-block products) against the same counts recomputed from
+    the oracle's group membership."""
+    from workloads import Problem
+    if case == "64 groups":
+        p = uniform_problem(1200, 2, 64, r0=0.03, n1=64, n2=1, bump_radius=0.12)
+    elif case == "config 1":
+        p = config1()
+    elif case == "config 2":
+        p = config2()
+    elif case == "one dense group":
+        th1 = Theta(1.0, np.array([0.05, 0.05]), np.array([[[0.5, 0.5]]]), np.full((1, 1, 2), 5.0), np.ones((1, 1)),
+                    np.ones((1, 1)), 0.1)
+        p = Problem("dense", np.random.default_rng(6).random((700, 2)), th1)
+    else:
+        th0 = Theta(2.0, np.array([0.1, 0.1]), np.zeros((0, 0, 2)), np.zeros((0, 0, 2)), np.zeros((0, 0)),
+                    np.zeros((0, 0)), 0.1)
+        p = Problem("nobumps", np.random.default_rng(5).random((300, 2)), th0)
+    want = _group_layout(p.x, p.theta)
+    K = ctx.assemble(ctx.dataset(dev(p.x), cell=p.cell), p.theta, 1)
+    lo = K.layout()
+    K.close()
+    got = {k: lo[k] for k in want}
+    print(f"[group layout {case}] {got}")
+    assert got == want
