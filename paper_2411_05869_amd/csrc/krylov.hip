@@ -454,27 +454,76 @@ struct LzState {
   double beta_prev[32];  // used by the next step
   double inv_cur[32];    // v_j = Vcur * inv_cur (0 for finished probes)
   double inv_prev[32];   // v_{j-1} = Vprev * inv_prev
+  double dcorr[32];      // w_{j-1} . v_{j-1} of the previous step
   int active[32];
   int steps[32];
 };
 
-// W[:, l] -= beta_prev[l] * v_{j-1}[:, l]; partial sums of v_j[:, l] . W[:, l] (float64)
+// A Lanczos step makes two passes over the blocks after the product.  The
+// product W = S K S V (v_j = V inv_cur) is not scaled by inv_cur;
+// k_lz_vw_part forms partial sums of V[:, l] . W[:, l], and
+// alpha_j = v_j . (A v_j - beta_j v_{j-1}) is then inv_cur^2 times their
+// total minus w_{j-1} . v_{j-1}, the term kept from the previous step
+// (v_j = w_{j-1} / beta_j), so that the second pass applies inv_cur and both
+// subtractions at once (in exact arithmetic the same alpha as subtracting
+// beta_j v_{j-1} before the dot product).
 template <typename T>
-__global__ void __launch_bounds__(kThreads) k_lz_beta_dot(int64_t n, int ld, const LzState* __restrict__ st,
-                                                          const T* __restrict__ V, const T* __restrict__ Vprev,
-                                                          T* __restrict__ W, double* __restrict__ part, Seg g = {}) {
+__global__ void __launch_bounds__(kThreads) k_lz_vw_part(int64_t n, int ld, const T* __restrict__ V,
+                                                         const T* __restrict__ W, double* __restrict__ part,
+                                                         Seg g = {}) {
+  const int64_t o = seg_begin(g, n) * ld;
+  V += o;
+  W += o;
+  part += blockIdx.y * g.pstride;
+  const int l = threadIdx.x & 31;
+  const int rl = threadIdx.x >> 5;
+  double acc = 0;
+  const int64_t S = static_cast<int64_t>(gridDim.x) * 8;
+  int64_t p = blockIdx.x * 8ll + rl;
+  for (; p + 3 * S < n; p += 4 * S) {
+    T wv[4], vv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t i = (p + u * S) * ld + l;
+      wv[u] = W[i];
+      vv[u] = V[i];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc += static_cast<double>(vv[u]) * static_cast<double>(wv[u]);
+  }
+  for (; p < n; p += S) {
+    const int64_t i = p * ld + l;
+    acc += static_cast<double>(V[i]) * static_cast<double>(W[i]);
+  }
+  __shared__ double sh[8][32];
+  sh[rl][l] = acc;
+  __syncthreads();
+  if (rl == 0) {
+    double t = 0;
+    for (int j = 0; j < 8; ++j) t += sh[j][l];
+    part[blockIdx.x * 32 + l] = t;
+  }
+}
+
+// W holds S K S V without the factor inv_cur of v_j:
+// W[:, l] = (W inv_cur - beta_prev v_{j-1}) - alpha v_j; partial sums of
+// |W[:, l]|^2 at part[b * 64 + l] and of W[:, l] . V[:, l] (unnormalised v_j)
+// at part[b * 64 + 32 + l]
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_lz_update(int64_t n, int ld, const LzState* __restrict__ st,
+                                                        const T* __restrict__ V, const T* __restrict__ Vprev,
+                                                        T* __restrict__ W, double* __restrict__ part, Seg g = {}) {
   const int64_t o = seg_begin(g, n) * ld;
   V += o;
   Vprev += o;
   W += o;
   st += blockIdx.y;
   part += blockIdx.y * g.pstride;
-  // thread layout: 32 columns x 8 row-lanes per block
   const int l = threadIdx.x & 31;
   const int rl = threadIdx.x >> 5;
-  const T bp = static_cast<T>(st->beta_prev[l]);
+  const T a = static_cast<T>(st->alpha[l]), bp = static_cast<T>(st->beta_prev[l]);
   const T ic = static_cast<T>(st->inv_cur[l]), ip = static_cast<T>(st->inv_prev[l]);
-  double acc = 0;
+  double an = 0, ad = 0;
   const int64_t S = static_cast<int64_t>(gridDim.x) * 8;
   int64_t p = blockIdx.x * 8ll + rl;
   for (; p + 3 * S < n; p += 4 * S) {
@@ -488,75 +537,35 @@ __global__ void __launch_bounds__(kThreads) k_lz_beta_dot(int64_t n, int ld, con
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const T w = wv[u] - bp * (pv[u] * ip);
+      const T w1 = wv[u] * ic - bp * (pv[u] * ip);
+      const T w = w1 - a * (vv[u] * ic);
       W[(p + u * S) * ld + l] = w;
-      acc += static_cast<double>(vv[u] * ic) * static_cast<double>(w);
+      an += static_cast<double>(w) * static_cast<double>(w);
+      ad += static_cast<double>(w) * static_cast<double>(vv[u]);
     }
   }
   for (; p < n; p += S) {
     const int64_t i = p * ld + l;
-    const T w = W[i] - bp * (Vprev[i] * ip);
+    const T w1 = W[i] * ic - bp * (Vprev[i] * ip);
+    const T w = w1 - a * (V[i] * ic);
     W[i] = w;
-    acc += static_cast<double>(V[i] * ic) * static_cast<double>(w);
+    an += static_cast<double>(w) * static_cast<double>(w);
+    ad += static_cast<double>(w) * static_cast<double>(V[i]);
   }
-  __shared__ double sh[8][32];
-  sh[rl][l] = acc;
+  __shared__ double sh[2][8][32];
+  sh[0][rl][l] = an;
+  sh[1][rl][l] = ad;
   __syncthreads();
   if (rl == 0) {
-    double s = 0;
-    for (int j = 0; j < 8; ++j) s += sh[j][l];
-    part[blockIdx.x * 32 + l] = s;
+    double t = 0, d = 0;
+    for (int j = 0; j < 8; ++j) {
+      t += sh[0][j][l];
+      d += sh[1][j][l];
+    }
+    part[blockIdx.x * 64 + l] = t;
+    part[blockIdx.x * 64 + 32 + l] = d;
   }
 }
-
-// W[:, l] -= alpha[l] * v_j[:, l]; partial sums of |W[:, l]|^2
-template <typename T>
-__global__ void __launch_bounds__(kThreads) k_lz_alpha_norm(int64_t n, int ld, const LzState* __restrict__ st,
-                                                            const T* __restrict__ V, T* __restrict__ W,
-                                                            double* __restrict__ part, Seg g = {}) {
-  const int64_t o = seg_begin(g, n) * ld;
-  V += o;
-  W += o;
-  st += blockIdx.y;
-  part += blockIdx.y * g.pstride;
-  const int l = threadIdx.x & 31;
-  const int rl = threadIdx.x >> 5;
-  const T a = static_cast<T>(st->alpha[l]);
-  const T ic = static_cast<T>(st->inv_cur[l]);
-  double acc = 0;
-  const int64_t S = static_cast<int64_t>(gridDim.x) * 8;
-  int64_t p = blockIdx.x * 8ll + rl;
-  for (; p + 3 * S < n; p += 4 * S) {
-    T wv[4], vv[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int64_t i = (p + u * S) * ld + l;
-      wv[u] = W[i];
-      vv[u] = V[i];
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const T w = wv[u] - a * (vv[u] * ic);
-      W[(p + u * S) * ld + l] = w;
-      acc += static_cast<double>(w) * static_cast<double>(w);
-    }
-  }
-  for (; p < n; p += S) {
-    const int64_t i = p * ld + l;
-    const T w = W[i] - a * (V[i] * ic);
-    W[i] = w;
-    acc += static_cast<double>(w) * static_cast<double>(w);
-  }
-  __shared__ double sh[8][32];
-  sh[rl][l] = acc;
-  __syncthreads();
-  if (rl == 0) {
-    double s = 0;
-    for (int j = 0; j < 8; ++j) s += sh[j][l];
-    part[blockIdx.x * 32 + l] = s;
-  }
-}
-
 
 // Full re-orthogonalisation (classical Gram-Schmidt, applied twice by the
 // driver) of the residual block W against the normalised Lanczos vectors
@@ -606,27 +615,37 @@ __global__ void __launch_bounds__(kThreads) k_ro_update(int64_t n, int nv, const
   W[i] = w;
 }
 
-// partial sums of |W[:, l]|^2 (after re-orthogonalisation)
-__global__ void __launch_bounds__(kThreads) k_lz_norm(int64_t n, const double* __restrict__ W,
-                                                      double* __restrict__ part) {
+// after re-orthogonalisation: partial sums of |W[:, l]|^2 at part[b * 64 + l]
+// and of W[:, l] . V[:, l] at part[b * 64 + 32 + l]
+__global__ void __launch_bounds__(kThreads) k_lz_norm_dot(int64_t n, const double* __restrict__ V,
+                                                          const double* __restrict__ W, double* __restrict__ part) {
   const int l = threadIdx.x & 31;
   const int rl = threadIdx.x >> 5;
-  double acc = 0;
+  double an = 0, ad = 0;
   for (int64_t p = blockIdx.x * 8ll + rl; p < n; p += static_cast<int64_t>(gridDim.x) * 8) {
     const double w = W[p * 32 + l];
-    acc += w * w;
+    an += w * w;
+    ad += w * V[p * 32 + l];
   }
-  __shared__ double sh[8][32];
-  sh[rl][l] = acc;
+  __shared__ double sh[2][8][32];
+  sh[0][rl][l] = an;
+  sh[1][rl][l] = ad;
   __syncthreads();
   if (rl == 0) {
-    double t = 0;
-    for (int j = 0; j < 8; ++j) t += sh[j][l];
-    part[blockIdx.x * 32 + l] = t;
+    double t = 0, d = 0;
+    for (int q = 0; q < 8; ++q) {
+      t += sh[0][q][l];
+      d += sh[1][q][l];
+    }
+    part[blockIdx.x * 64 + l] = t;
+    part[blockIdx.x * 64 + 32 + l] = d;
   }
 }
 
-// mode 0: alpha; mode 1: beta + breakdown (j = step index, last = final step).
+// mode 0: alpha = inv_cur^2 x (sum of V . S K S V) - dcorr; mode 1: beta +
+// breakdown (j = step index, last = final step) from the partials of |w|^2,
+// and dcorr = inv_cur x the sum of w . V (those partials 32 after the first,
+// 64 per block).
 // 32 columns; each of kFinGroups groups of 32 threads sums the partials b = g,
 // g + kFinGroups, ... of its column (four interleaved accumulators, so several
 // loads are in flight), then the groups are added in order.
@@ -642,21 +661,37 @@ __global__ void __launch_bounds__(kFinGroups * 32) k_lz_fin(const double* __rest
   Ta += blockIdx.y * tstride;
   Tb += blockIdx.y * tstride;
   __shared__ double sh[kFinGroups][32];
+  __shared__ double sh2[kFinGroups][32];
   const int l = threadIdx.x & 31;
   const int g = threadIdx.x >> 5;
-  double a4[4] = {0, 0, 0, 0};
+  const int ps = mode == 1 ? 64 : 32;
+  double a4[4] = {0, 0, 0, 0}, d4[4] = {0, 0, 0, 0};
   int b = g;
   for (; b + 3 * kFinGroups < nb; b += 4 * kFinGroups)
 #pragma unroll
-    for (int u = 0; u < 4; ++u) a4[u] += part[(b + u * kFinGroups) * 32 + l];
+    for (int u = 0; u < 4; ++u) {
+      a4[u] += part[(b + u * kFinGroups) * ps + l];
+      if (mode == 1) d4[u] += part[(b + u * kFinGroups) * ps + 32 + l];
+    }
 #pragma unroll
   for (int u = 0; u < 3; ++u)
-    if (b + u * kFinGroups < nb) a4[u] += part[(b + u * kFinGroups) * 32 + l];
+    if (b + u * kFinGroups < nb) {
+      a4[u] += part[(b + u * kFinGroups) * ps + l];
+      if (mode == 1) d4[u] += part[(b + u * kFinGroups) * ps + 32 + l];
+    }
   sh[g][l] = (a4[0] + a4[1]) + (a4[2] + a4[3]);
+  sh2[g][l] = (d4[0] + d4[1]) + (d4[2] + d4[3]);
   __syncthreads();
   if (g == 0 && l < k) {
     double t = 0;
     for (int q = 0; q < kFinGroups; ++q) t += sh[q][l];
+    if (mode == 1) {
+      double d = 0;
+      for (int q = 0; q < kFinGroups; ++q) d += sh2[q][l];
+      st->dcorr[l] = d * st->inv_cur[l];  // read before the rotation below
+    } else {
+      t = t * st->inv_cur[l] * st->inv_cur[l] - st->dcorr[l];
+    }
     if (mode == 0) {
       st->alpha[l] = t;
       if (st->active[l]) Ta[j * 32 + l] = t;
@@ -1440,7 +1475,7 @@ __global__ void k_lz_state_init(LzState* __restrict__ st, int k, double inv0, co
   if (l >= 32) return;
   st += blockIdx.y;
   if (inv0s) inv0 = inv0s[blockIdx.y];
-  st->alpha[l] = st->beta[l] = st->beta_prev[l] = st->inv_prev[l] = 0.0;
+  st->alpha[l] = st->beta[l] = st->beta_prev[l] = st->inv_prev[l] = st->dcorr[l] = 0.0;
   st->active[l] = l < k ? 1 : 0;
   st->inv_cur[l] = l < k ? inv0 : 0.0;
   st->steps[l] = 0;
@@ -1484,19 +1519,6 @@ __global__ void k_slq_final(const double* __restrict__ gam_all, const int* __res
   out->status = (bad[0] & 1) ? GP_EDEVICE : ((bad[0] & 2) ? GP_ENOTPD : GP_OK);
 }
 
-// W[:, l] *= inv_cur[l] of the row's problem (l < k): the column factor a
-// single problem's product applies as its last multiplication
-__global__ void __launch_bounds__(kThreads) k_lz_colscale(int64_t n, int k, int ld, const LzState* __restrict__ st,
-                                                          double* __restrict__ W, Seg g) {
-  const int64_t o = seg_begin(g, n);
-  const double* f = st[blockIdx.y].inv_cur;
-  for (int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; i < n * 32;
-       i += static_cast<int64_t>(gridDim.x) * kThreads) {
-    const int l = static_cast<int>(i & 31);
-    if (l < k) W[(o + (i >> 5)) * ld + l] *= f[l];
-  }
-}
-
 }  // namespace
 
 // The work space of an SLQ estimate (R problems stacked in n rows); the
@@ -1529,7 +1551,7 @@ static SlqBufs<T> slq_bufs(gp_ctx* c, int64_t n, int n_probes, int n_steps, bool
   b.Vp = static_cast<T*>(workspace(c, 31, sizeof(T) * n * ld));
   b.W = static_cast<T*>(workspace(c, 32, sizeof(T) * n * ld));
   b.sc = static_cast<T*>(workspace(c, 33, sizeof(T) * n));
-  b.part = static_cast<double*>(workspace(c, 34, sizeof(double) * 32 * kRedBlocks * R));
+  b.part = static_cast<double*>(workspace(c, 34, sizeof(double) * 64 * kRedBlocks * R));
   b.st = static_cast<LzState*>(workspace(c, 35, sizeof(LzState) * R));
   b.Ta = static_cast<double*>(workspace(c, 36, sizeof(double) * tstride * R));
   b.Tb = static_cast<double*>(workspace(c, 37, sizeof(double) * tstride * R));
@@ -1570,6 +1592,8 @@ class SlqRun final : public SideFeed {
     }
     nrow_ = batch_ ? bt_.nmax : n_;
     tstride_ = static_cast<int64_t>(32) * n_steps;
+    // the step's kernels: per-problem partial sums 64 x kRedBlocks apart
+    if (batch_) gf_ = Seg{bt_.off, 64 * kRedBlocks};
     perm_ = batch_ ? bt_.perm : m->ds->perm;
     const bool dev = dev_out != nullptr;
     bf_ = slq_bufs<T>(c, n_, n_probes, n_steps, reorth, R_, dev);
@@ -1685,20 +1709,18 @@ class SlqRun final : public SideFeed {
     const int last = j == n_steps_ - 1;
     LzState* st = bf_.st;
     double* part = bf_.part;
-    // W = A v_j (a batch applies each problem's column factors afterwards)
-    spmm<T>(c, m_, ld, ld, V_, W_, bf_.sc, batch_ ? nullptr : st->inv_cur);
-    if (batch_)
-      hipLaunchKernelGGL(k_lz_colscale, dim3(grid_for(nrow_ * 32, kThreads), Ry), dim3(kThreads), 0, c->stream,
-                         nrow_, k_, ld, st, W_, gl_);
+    // W = S K S V; the sums of V W and alpha; one pass applies inv_cur and
+    // both subtractions
+    spmm<T>(c, m_, ld, ld, V_, W_, bf_.sc, nullptr);
     ProfScope ps(c, "lanczos_vector_ops");
-    hipLaunchKernelGGL((k_lz_beta_dot<T>), dim3(kRedBlocks, Ry), dim3(kThreads), 0, c->stream, nrow_, ld, st, V_, Vp_,
-                       W_, part, gl_);
+    hipLaunchKernelGGL((k_lz_vw_part<T>), dim3(kRedBlocks, Ry), dim3(kThreads), 0, c->stream, nrow_, ld, V_, W_, part,
+                       gf_);
     hipLaunchKernelGGL(k_lz_fin, dim3(1, Ry), dim3(kFinGroups * 32), 0, c->stream, part, kRedBlocks, k_, 0, j, last,
-                       tol_, st, bf_.Ta, bf_.Tb, gl_, tstride_);
-    hipLaunchKernelGGL((k_lz_alpha_norm<T>), dim3(kRedBlocks, Ry), dim3(kThreads), 0, c->stream, nrow_, ld, st, V_,
-                       W_, part, gl_);
+                       tol_, st, bf_.Ta, bf_.Tb, gf_, tstride_);
+    hipLaunchKernelGGL((k_lz_update<T>), dim3(kRedBlocks, Ry), dim3(kThreads), 0, c->stream, nrow_, ld, st, V_, Vp_,
+                       W_, part, gf_);
     if (reorth_) {
-      // W -= Q Q^T W twice over q_0 .. q_j, then |W|^2 afresh
+      // W -= Q Q^T W twice over q_0 .. q_j, then |W|^2 and W . V afresh
       double* Qj = bf_.Qall + static_cast<int64_t>(j) * n_ * ld;
       hipLaunchKernelGGL(k_lz_store_q, dim3(grid_for(n_ * ld, kThreads)), dim3(kThreads), 0, c->stream, n_, V_, st,
                          Qj);
@@ -1709,11 +1731,11 @@ class SlqRun final : public SideFeed {
         hipLaunchKernelGGL(k_ro_update, dim3(grid_for(n_ * ld, kThreads)), dim3(kThreads), 0, c->stream, n_, j + 1,
                            bf_.Qall, bf_.H, W_);
       }
-      hipLaunchKernelGGL(k_lz_norm, dim3(kRedBlocks), dim3(kThreads), 0, c->stream, n_, W_, part);
+      hipLaunchKernelGGL(k_lz_norm_dot, dim3(kRedBlocks), dim3(kThreads), 0, c->stream, n_, V_, W_, part);
       check_launch("lanczos reorthogonalisation");
     }
     hipLaunchKernelGGL(k_lz_fin, dim3(1, Ry), dim3(kFinGroups * 32), 0, c->stream, part, kRedBlocks, k_, 1, j, last,
-                       tol_, st, bf_.Ta, bf_.Tb, gl_, tstride_);
+                       tol_, st, bf_.Ta, bf_.Tb, gf_, tstride_);
     if (!last) {
       // rotate: the residual block W holds the next (unnormalised) v
       T* old_prev = Vp_;
@@ -1730,6 +1752,7 @@ class SlqRun final : public SideFeed {
   int n_probes_, n_steps_, R_ = 1;
   double tol_;
   bool reorth_, batch_ = false, finished_ = false;
+  Seg gf_;  // problems of the step's kernels
   DeviceLogdet* dev_out_;
   SlqBatch bt_;
   Seg gl_, gj_;

@@ -2,6 +2,14 @@
 import numpy as np
 import scipy.sparse as sp
 
+# SLQ with plain three-term Lanczos on both sides, identical probes: the
+# recurrence amplifies the two sides' rounding (other summation orders, and
+# alpha formed as v.Av minus the previous step's w.v instead of v.(Av - beta
+# v_prev), equal in exact arithmetic), so the plain estimates are held to this
+# relative bound; with full re-orthogonalisation on both sides the estimates
+# are held to the parity bar (1e-8 float64, 1e-5 mixed).
+PLAIN_BOUND = 2e-6
+
 
 def dev(a):
     import torch

@@ -15,7 +15,7 @@
   1e-8 (float64) / 1e-5 (mixed); the SLQ log det against the exact one within
   3 standard errors, and against the oracle's SLQ with the same probes
   (tests/golden/mixture_n100000_slq.json): with full re-orthogonalisation on
-  both sides within 1e-8 / 1e-5, plain Lanczos within 1e-6 (rounding
+  both sides within 1e-8 / 1e-5, plain Lanczos within 2e-6 (rounding
   amplified by the plain recurrence); the same quadratic form by MINRES.
 * Space-time workload with the nonstationary core kernel: sampled rows against
   the oracle (pattern bit-exact, values within 1e-12 relative).
@@ -44,14 +44,11 @@ import pytest
 
 from oracle import kernel, likelihood, predict
 from workloads import config2, config3, config5_requests
-from gpu_util import dev, host, rel
+from gpu_util import PLAIN_BOUND, dev, host, rel
 
 pytestmark = pytest.mark.gpu
 
 N_ROWS = 100
-# plain Lanczos on both sides, different summation orders: held to this
-# relative bound (the recurrence amplifies rounding; see the SLQ tests)
-PLAIN_BOUND = 1e-6
 
 
 @pytest.fixture(scope="module")
@@ -183,8 +180,8 @@ def test_config2_slq_identical_probes(ctx, prec, tol):
     # the oracle's SLQ with the same probes (default seed), 30 x 50, written by
     # tests/golden/make_mixture_slq.py.  Plain three-term Lanczos amplifies the
     # rounding differences of the two implementations (other summation
-    # orders) over 50 steps: the plain estimates agree to about 5e-8 here and
-    # are held to 1e-6.  With full re-orthogonalisation on both sides the
+    # orders) over 50 steps: the plain estimates agree to about 1e-7 here and
+    # are held to PLAIN_BOUND.  With full re-orthogonalisation on both sides the
     # basis stays orthonormal to rounding and the estimates agree within the
     # bar: 1e-8 (float64) / 1e-5 (mixed).
     from paper_2411_05869_amd import LOGDET_SLQ_REORTH
@@ -206,7 +203,7 @@ def test_config2_slq_identical_probes(ctx, prec, tol):
           f"rel {eo:.2e}")
     assert r["status"] == 0 and r["lanczos_steps"] == max(gold["probe_steps"])
     assert ro["status"] == 0 and ro["lanczos_steps"] == max(gold["reorth"]["probe_steps"])
-    assert e <= max(tol, 1e-6)
+    assert e <= max(tol, PLAIN_BOUND)
     assert eo <= tol
 
 
