@@ -390,10 +390,12 @@ gp_matrix* stack_matrices(gp_ctx* c, int R, const gp_matrix* const* ms, bool blo
 // synchronisation, no profiling events)
 void spmv_f64_enqueue(gp_ctx* c, const gp_matrix* m, const double* x, double* y);
 // Y = S K S X D for k columns, X/Y n x ld row-major (S = diag(scale) or identity
-// if null; D = diag(colscale), a device array of k values, or identity if null)
+// if null; D = diag(colscale), a device array of k values, or identity if null).
+// share: the product runs beside another stream's kernels and holds fewer
+// wave slots per CU, so that they find room (same results).
 template <typename T>
 void spmm(gp_ctx* c, const gp_matrix* m, int k, int ld, const T* X, T* Y, const T* scale,
-          const double* colscale = nullptr);
+          const double* colscale = nullptr, bool share = false);
 
 // original <-> binned order for n x k row-major blocks
 template <typename T>

@@ -1673,6 +1673,10 @@ class SlqRun final : public SideFeed {
     return finish(c);
   }
 
+  // the steps run beside a solve on the other stream: their products leave
+  // wave slots to it
+  void beside_solve() { beside_ = true; }
+
   // the host-driven form's estimate, after the last unit
   LogdetResult result() const {
     LogdetResult res;
@@ -1711,7 +1715,7 @@ class SlqRun final : public SideFeed {
     double* part = bf_.part;
     // W = S K S V; the sums of V W and alpha; one pass applies inv_cur and
     // both subtractions
-    spmm<T>(c, m_, ld, ld, V_, W_, bf_.sc, nullptr);
+    spmm<T>(c, m_, ld, ld, V_, W_, bf_.sc, nullptr, beside_);
     ProfScope ps(c, "lanczos_vector_ops");
     hipLaunchKernelGGL((k_lz_vw_part<T>), dim3(kRedBlocks, Ry), dim3(kThreads), 0, c->stream, nrow_, ld, V_, W_, part,
                        gf_);
@@ -1751,7 +1755,7 @@ class SlqRun final : public SideFeed {
   uint64_t seed_;
   int n_probes_, n_steps_, R_ = 1;
   double tol_;
-  bool reorth_, batch_ = false, finished_ = false;
+  bool reorth_, batch_ = false, finished_ = false, beside_ = false;
   Seg gf_;  // problems of the step's kernels
   DeviceLogdet* dev_out_;
   SlqBatch bt_;
@@ -1794,7 +1798,9 @@ void slq_logdet_side(gp_ctx* c, const gp_matrix* m, uint64_t seed, int n_probes,
   std::unique_ptr<SideFeed> run;
   {
     SideScope side(c);
-    run = std::make_unique<SlqRun<double>>(c, m, seed, n_probes, n_steps, 1e-10, reorth, out, nullptr);
+    auto r = std::make_unique<SlqRun<double>>(c, m, seed, n_probes, n_steps, 1e-10, reorth, out, nullptr);
+    r->beside_solve();
+    run = std::move(r);
   }
   side_install(c, std::move(run));
 }
@@ -1805,7 +1811,9 @@ void slq_batch_side(gp_ctx* c, const gp_matrix* m, uint64_t seed, int n_probes, 
   std::unique_ptr<SideFeed> run;
   {
     SideScope side(c);
-    run = std::make_unique<SlqRun<double>>(c, m, seed, n_probes, n_steps, 1e-10, false, out, &b);
+    auto r = std::make_unique<SlqRun<double>>(c, m, seed, n_probes, n_steps, 1e-10, false, out, &b);
+    r->beside_solve();
+    run = std::move(r);
   }
   side_install(c, std::move(run));
 }
